@@ -1,0 +1,212 @@
+"""FP64 CPU oracle for the mass-spring cloth step -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg import this package.
+The product path (the HIP library and its binding) never imports it and shares no code with
+it.  The arithmetic lives in ``cloth_oracle.c`` (plain C, FP64, single-threaded); this file
+only builds that library, marshals numpy arrays into it, and adds a complex-step tangent
+(``substep_jvp_cs``) written independently in numpy for checking the hand-written adjoint.
+
+Every function takes plain arrays (positions [N,3], spring ends [S,2], ...); FP32 inputs are
+upcast exactly to FP64.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "cloth_oracle.c")
+_LIB = os.path.join(_HERE, "libcloth_oracle.so")
+_lib = None
+
+
+def build() -> str:
+    """Compile cloth_oracle.c with gcc (always recompiles)."""
+    tmp = _LIB + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared",
+                           "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build()
+    lib = C.CDLL(_LIB)
+    P = C.c_void_p
+    dp = C.POINTER(C.c_double)
+    ip = C.POINTER(C.c_int)
+    fp = C.POINTER(C.c_float)
+    lib.orc_model_new.restype = P
+    lib.orc_model_new.argtypes = [C.c_int, dp, C.c_int, ip, dp, dp, dp, dp, C.c_int, dp, C.c_int,
+                                  ip, C.c_double, C.c_double, C.c_double]
+    lib.orc_model_free.argtypes = [P]
+    lib.orc_model_set_params.argtypes = [P, dp, dp]
+    lib.orc_forces.argtypes = [P, dp, dp, dp]
+    lib.orc_substep.argtypes = [P, dp, dp, C.c_double, ip, dp]
+    lib.orc_run.argtypes = [P, dp, dp, C.c_double, C.c_int]
+    lib.orc_contacts.restype = C.c_int
+    lib.orc_contacts.argtypes = [P, dp, ip, C.c_int]
+    lib.orc_point_tri_dist2.restype = C.c_double
+    lib.orc_point_tri_dist2.argtypes = [dp, dp, dp, dp]
+    lib.orc_candidates_f32.restype = C.c_longlong
+    lib.orc_candidates_f32.argtypes = [C.c_int, fp, C.c_int, fp, ip, C.c_float, ip, C.c_longlong]
+    lib.orc_substep_vjp.argtypes = [P, dp, dp, C.c_double, dp, dp, dp, dp, dp, dp]
+    lib.orc_rollout_grad.argtypes = [P, dp, dp, C.c_double, C.c_int, C.c_int, ip, dp, C.c_int,
+                                     dp, dp, dp, dp, dp]
+    lib.orc_model_triangle.argtypes = [P, C.c_int, dp, dp, dp, dp]
+    _lib = lib
+    return lib
+
+
+def _d(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_int))
+
+
+class Model:
+    """A cloth plus its static surface, held by the C oracle.
+
+    inv_mass: [N] (0 marks a pinned node); ends [S,2]; rest/k/c [S]; verts [V,3];
+    tris [T,3]; thickness (0 disables collision); cell: bucket size of the oracle's own
+    acceleration grid (any positive value gives the same results).
+    """
+
+    def __init__(self, inv_mass, ends, rest, k, c, gravity=(0.0, -9.81, 0.0), verts=None,
+                 tris=None, thickness=0.0, restitution=0.5, cell=0.0):
+        self._lib = _load()
+        self.w = _d(inv_mass)
+        self.N = int(self.w.shape[0])
+        self.ends = _i(ends).reshape(-1, 2)
+        self.S = int(self.ends.shape[0])
+        self.rest, self.k, self.c = _d(rest), _d(k), _d(c)
+        self.g = _d(gravity)
+        self.verts = _d(np.zeros((0, 3)) if verts is None else verts).reshape(-1, 3)
+        self.tris = _i(np.zeros((0, 3)) if tris is None else tris).reshape(-1, 3)
+        self.thickness = float(thickness)
+        self.restitution = float(restitution)
+        self._h = self._lib.orc_model_new(
+            self.N, _dp(self.w), self.S, _ip(self.ends), _dp(self.rest), _dp(self.k),
+            _dp(self.c), _dp(self.g), self.verts.shape[0], _dp(self.verts), self.tris.shape[0],
+            _ip(self.tris), self.thickness, self.restitution, float(cell))
+
+    @classmethod
+    def from_inputs(cls, inp, k=None, c=None):
+        """Build from any object with the ClothInputs fields."""
+        m = np.asarray(inp.mass, dtype=np.float64)
+        pinned = np.asarray(inp.pinned).astype(bool)
+        w = np.where(pinned, 0.0, 1.0 / m)
+        return cls(w, inp.ends, inp.rest, inp.k if k is None else k, inp.c if c is None else c,
+                   inp.gravity, inp.verts, inp.tris, inp.thickness, inp.restitution,
+                   inp.cell_size)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.orc_model_free(h)
+            self._h = None
+
+    def set_params(self, k=None, c=None):
+        if k is not None:
+            self.k = _d(k)
+        if c is not None:
+            self.c = _d(c)
+        self._lib.orc_model_set_params(self._h, _dp(self.k), _dp(self.c))
+
+    def forces(self, x, v):
+        x, v = _d(x).reshape(-1, 3), _d(v).reshape(-1, 3)
+        F = np.zeros((self.N, 3))
+        self._lib.orc_forces(self._h, _dp(x), _dp(v), _dp(F))
+        return F
+
+    def substep(self, x, v, h):
+        """One substep; returns (x, v, contact_count [N], margin [N])."""
+        x, v = _d(x).reshape(-1, 3).copy(), _d(v).reshape(-1, 3).copy()
+        cnt = np.zeros(self.N, dtype=np.int32)
+        mg = np.zeros(self.N)
+        self._lib.orc_substep(self._h, _dp(x), _dp(v), float(h), _ip(cnt), _dp(mg))
+        return x, v, cnt, mg
+
+    def run(self, x, v, h, n_sub):
+        x, v = _d(x).reshape(-1, 3).copy(), _d(v).reshape(-1, 3).copy()
+        self._lib.orc_run(self._h, _dp(x), _dp(v), float(h), int(n_sub))
+        return x, v
+
+    def contacts(self, p):
+        out = np.zeros(512, dtype=np.int32)
+        n = self._lib.orc_contacts(self._h, _dp(_d(p)), _ip(out), 512)
+        return out[:min(n, 512)].copy()
+
+    def triangle(self, t):
+        A, n, lo, hi = (np.zeros(3) for _ in range(4))
+        self._lib.orc_model_triangle(self._h, int(t), _dp(A), _dp(n), _dp(lo), _dp(hi))
+        return A, n, lo, hi
+
+    def substep_vjp(self, x, v, h, xb_out, vb_out):
+        """Adjoint of one substep at (x, v): returns (xb_in, vb_in, kb, cb)."""
+        x, v = _d(x).reshape(-1, 3), _d(v).reshape(-1, 3)
+        xbo, vbo = _d(xb_out).reshape(-1, 3), _d(vb_out).reshape(-1, 3)
+        xbi, vbi = np.zeros((self.N, 3)), np.zeros((self.N, 3))
+        kb, cb = np.zeros(self.S), np.zeros(self.S)
+        self._lib.orc_substep_vjp(self._h, _dp(x), _dp(v), float(h), _dp(xbo), _dp(vbo),
+                                  _dp(xbi), _dp(vbi), _dp(kb), _dp(cb))
+        return xbi, vbi, kb, cb
+
+    def rollout_grad(self, x0, v0, h, n_sub, out_sub, xbar, ckpt=1):
+        """Checkpointed rollout gradient.
+
+        out_sub: ascending substep counts at which the loss reads positions; xbar:
+        [len(out_sub), N, 3] = dL/dx there.  Returns dict(x_out, gk, gc, gv0, gx0)."""
+        x0, v0 = _d(x0).reshape(-1, 3), _d(v0).reshape(-1, 3)
+        out_sub = _i(out_sub)
+        n_out = int(out_sub.shape[0])
+        xbar = _d(xbar).reshape(n_out, self.N, 3)
+        x_out = np.zeros((n_out, self.N, 3))
+        gk, gc = np.zeros(self.S), np.zeros(self.S)
+        gv0, gx0 = np.zeros((self.N, 3)), np.zeros((self.N, 3))
+        self._lib.orc_rollout_grad(self._h, _dp(x0), _dp(v0), float(h), int(n_sub), n_out,
+                                   _ip(out_sub), _dp(xbar), int(ckpt), _dp(x_out), _dp(gk),
+                                   _dp(gc), _dp(gv0), _dp(gx0))
+        return dict(x_out=x_out, gk=gk, gc=gc, gv0=gv0, gx0=gx0)
+
+
+def point_tri_dist2(p, A, B, Cc):
+    lib = _load()
+    return lib.orc_point_tri_dist2(_dp(_d(p)), _dp(_d(A)), _dp(_d(B)), _dp(_d(Cc)))
+
+
+def candidates_f32(x, verts, tris, thickness, cap=None):
+    """FP32 brute-force broad-phase pairs (node, tri), sorted by node then triangle."""
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, 3)
+    verts = np.ascontiguousarray(verts, dtype=np.float32).reshape(-1, 3)
+    tris = _i(tris).reshape(-1, 3)
+    fp = C.POINTER(C.c_float)
+    n = lib.orc_candidates_f32(x.shape[0], x.ctypes.data_as(fp), tris.shape[0],
+                               verts.ctypes.data_as(fp), _ip(tris), float(np.float32(thickness)),
+                               None, 0)
+    pairs = np.zeros((max(n, 1), 2), dtype=np.int32)
+    lib.orc_candidates_f32(x.shape[0], x.ctypes.data_as(fp), tris.shape[0],
+                           verts.ctypes.data_as(fp), _ip(tris), float(np.float32(thickness)),
+                           _ip(pairs), n)
+    return pairs[:n].copy()
+
+
+from .cstep import substep_jvp_cs  # noqa: E402,F401

@@ -1,0 +1,578 @@
+/*
+ * FP64 CPU oracle for the mass-spring cloth step -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg load this
+ * library.  The product (the HIP library) never calls, links or includes it, and it shares
+ * no code with the product: no headers, helpers or tables.  It is deliberately plain and
+ * slow: loops written in the order of the method's definition, FP64 throughout, single
+ * threaded, no blocking or fusion beyond what the definition states.
+ *
+ * What one substep computes (h = frame dt / substeps):
+ *   1. Spring forces, spring-centric, as in Alg. 1 of the paper's appendix: for a spring
+ *      (a, b) with rest length L0, stiffness k and damping c,
+ *          dir = normalize(x_b - x_a)
+ *          f   = (k (|x_b - x_a| - L0) + c (v_b . dir - v_a . dir)) dir
+ *      added to node a and subtracted from node b (action and reaction).
+ *   2. Explicit integration (Sec. 3 names an Euler method; read here as semi-implicit
+ *      Euler): v* = v + h (w F + g), x* = x + h v*, with w = 1/m.  Pinned nodes (w = 0)
+ *      keep x and get v* = 0.
+ *   3. Collision against a static triangle surface.  The paper averages a per-collision
+ *      direction over all hits of a node (Sec. 3, collision paragraph) and applies it in
+ *      Alg. 2: if the node has at least one hit, v <- -0.5 v and pos <- pos + direction.
+ *      Here a hit is a triangle t with point-triangle distance dist(x*, t) < th, the
+ *      direction of a hit is (th - (x* - A_t) . n_t) n_t with n_t the unit outward normal
+ *      (it puts x* at distance th in front of the triangle's plane), the directions are
+ *      averaged over the hits, and the restitution factor (0.5 in Alg. 2) is a parameter.
+ *   The candidate set is defined by brute force over all triangles; a bucket grid is used
+ *   only to skip triangles whose thickness-inflated bounding box cannot contain x*, which
+ *   is implied by dist < th, so it never changes the result.
+ *
+ * Also here: the FP32 brute-force broad-phase predicate (the exact candidate set a
+ * uniform grid must reproduce), the reverse-mode adjoint of one substep with the contact
+ * set held fixed, and a checkpointed rollout gradient.
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fPIC -shared -o libcloth_oracle.so
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ small vector helpers */
+
+static void sub3(const double *a, const double *b, double *o) { o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2]; }
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static void cross3(const double *a, const double *b, double *o)
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* ------------------------------------------------------------------ model */
+
+typedef struct {
+    int N, S, V, T;
+    double *w;          /* [N] inverse mass, 0 = pinned */
+    int *ends;          /* [S][2] */
+    double *rest, *k, *c;
+    double g[3];
+    double *verts;      /* [V][3] */
+    int *tris;          /* [T][3] */
+    double th;          /* collision thickness (0 disables collision) */
+    double restitution; /* v <- -restitution v on contact */
+    /* per triangle: first vertex, unit outward normal, inflated bounding box */
+    double *tA, *tn, *tlo, *thi;
+    /* bucket grid over the inflated boxes (acceleration only) */
+    double org[3], cell;
+    int dim[3];
+    int *cell_start, *cell_tris;
+} orc_model;
+
+
+static int cell_coord(const orc_model *m, double p, int axis)
+{
+    double f = floor((p - m->org[axis]) / m->cell);
+    if (!(f >= 0.0)) return 0; /* also catches NaN */
+    if (f > (double)(m->dim[axis] - 1)) return m->dim[axis] - 1;
+    return (int)f;
+}
+
+static void build_surface(orc_model *m, double cell)
+{
+    int T = m->T;
+    m->tA = calloc((size_t)T * 3 + 1, sizeof(double));
+    m->tn = calloc((size_t)T * 3 + 1, sizeof(double));
+    m->tlo = calloc((size_t)T * 3 + 1, sizeof(double));
+    m->thi = calloc((size_t)T * 3 + 1, sizeof(double));
+    double bmin[3] = {INFINITY, INFINITY, INFINITY}, bmax[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int t = 0; t < T; ++t) {
+        const double *A = m->verts + 3 * m->tris[3 * t + 0];
+        const double *B = m->verts + 3 * m->tris[3 * t + 1];
+        const double *C = m->verts + 3 * m->tris[3 * t + 2];
+        double e1[3], e2[3], n[3];
+        sub3(B, A, e1);
+        sub3(C, A, e2);
+        cross3(e1, e2, n);
+        double ln = sqrt(dot3(n, n));
+        for (int a = 0; a < 3; ++a) {
+            m->tA[3 * t + a] = A[a];
+            m->tn[3 * t + a] = n[a] / ln;
+            double lo = fmin(A[a], fmin(B[a], C[a])) - m->th;
+            double hi = fmax(A[a], fmax(B[a], C[a])) + m->th;
+            m->tlo[3 * t + a] = lo;
+            m->thi[3 * t + a] = hi;
+            if (lo < bmin[a]) bmin[a] = lo;
+            if (hi > bmax[a]) bmax[a] = hi;
+        }
+    }
+    if (T == 0) {
+        m->cell = 1.0;
+        for (int a = 0; a < 3; ++a) { m->org[a] = 0; m->dim[a] = 1; }
+    } else {
+        if (!(cell > 0)) cell = 0.05;
+        /* keep the bucket count modest: grow the cell until it holds */
+        for (;;) {
+            long long tot = 1;
+            for (int a = 0; a < 3; ++a) {
+                long long d = (long long)floor((bmax[a] - bmin[a]) / cell) + 1;
+                tot *= d;
+            }
+            if (tot <= (1LL << 23)) break;
+            cell *= 2.0;
+        }
+        m->cell = cell;
+        for (int a = 0; a < 3; ++a) {
+            m->org[a] = bmin[a];
+            m->dim[a] = (int)floor((bmax[a] - bmin[a]) / cell) + 1;
+        }
+    }
+    long long ncell = (long long)m->dim[0] * m->dim[1] * m->dim[2];
+    m->cell_start = calloc((size_t)ncell + 1, sizeof(int));
+    /* count, prefix, fill -- plain counting sort by cell, triangles in ascending id */
+    for (int pass = 0; pass < 2; ++pass) {
+        int *fill = NULL;
+        if (pass == 1) {
+            for (long long i = 0; i < ncell; ++i) m->cell_start[i + 1] += m->cell_start[i];
+            m->cell_tris = malloc(sizeof(int) * ((size_t)m->cell_start[ncell] + 1));
+            fill = calloc((size_t)ncell + 1, sizeof(int));
+        }
+        for (int t = 0; t < T; ++t) {
+            int lo[3], hi[3];
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = cell_coord(m, m->tlo[3 * t + a], a);
+                hi[a] = cell_coord(m, m->thi[3 * t + a], a);
+            }
+            for (int i = lo[0]; i <= hi[0]; ++i)
+                for (int j = lo[1]; j <= hi[1]; ++j)
+                    for (int q = lo[2]; q <= hi[2]; ++q) {
+                        long long id = ((long long)q * m->dim[1] + j) * m->dim[0] + i;
+                        if (pass == 0) m->cell_start[id + 1] += 1;
+                        else m->cell_tris[m->cell_start[id] + fill[id]++] = t;
+                    }
+        }
+        free(fill);
+    }
+}
+
+orc_model *orc_model_new(int N, const double *w, int S, const int *ends, const double *rest,
+                         const double *k, const double *c, const double *g, int V,
+                         const double *verts, int T, const int *tris, double th,
+                         double restitution, double cell)
+{
+    orc_model *m = calloc(1, sizeof(orc_model));
+    m->N = N; m->S = S; m->V = V; m->T = T;
+    m->w = malloc(sizeof(double) * (size_t)(N + 1));
+    memcpy(m->w, w, sizeof(double) * (size_t)N);
+    m->ends = malloc(sizeof(int) * (size_t)(2 * S + 1));
+    memcpy(m->ends, ends, sizeof(int) * (size_t)(2 * S));
+    m->rest = malloc(sizeof(double) * (size_t)(S + 1));
+    m->k = malloc(sizeof(double) * (size_t)(S + 1));
+    m->c = malloc(sizeof(double) * (size_t)(S + 1));
+    memcpy(m->rest, rest, sizeof(double) * (size_t)S);
+    memcpy(m->k, k, sizeof(double) * (size_t)S);
+    memcpy(m->c, c, sizeof(double) * (size_t)S);
+    for (int a = 0; a < 3; ++a) m->g[a] = g[a];
+    m->verts = malloc(sizeof(double) * (size_t)(3 * V + 1));
+    if (V) memcpy(m->verts, verts, sizeof(double) * (size_t)(3 * V));
+    m->tris = malloc(sizeof(int) * (size_t)(3 * T + 1));
+    if (T) memcpy(m->tris, tris, sizeof(int) * (size_t)(3 * T));
+    m->th = th;
+    m->restitution = restitution;
+    if (th <= 0) m->T = T = 0; /* collision disabled */
+    build_surface(m, cell);
+    return m;
+}
+
+void orc_model_set_params(orc_model *m, const double *k, const double *c)
+{
+    if (k) memcpy(m->k, k, sizeof(double) * (size_t)m->S);
+    if (c) memcpy(m->c, c, sizeof(double) * (size_t)m->S);
+}
+
+void orc_model_free(orc_model *m)
+{
+    if (!m) return;
+    free(m->w); free(m->ends); free(m->rest); free(m->k); free(m->c);
+    free(m->verts); free(m->tris); free(m->tA); free(m->tn); free(m->tlo); free(m->thi);
+    free(m->cell_start); free(m->cell_tris);
+    free(m);
+}
+
+/* ------------------------------------------------------------------ 1. spring forces */
+
+/* F[N][3] = sum of Alg. 1 spring forces at state (x, v). */
+void orc_forces(const orc_model *m, const double *x, const double *v, double *F)
+{
+    memset(F, 0, sizeof(double) * 3 * (size_t)m->N);
+    for (int s = 0; s < m->S; ++s) {
+        int a = m->ends[2 * s], b = m->ends[2 * s + 1];
+        double d[3], dir[3];
+        sub3(x + 3 * b, x + 3 * a, d);
+        double len = sqrt(dot3(d, d));
+        for (int q = 0; q < 3; ++q) dir[q] = d[q] / len;
+        double spring = m->k[s] * (len - m->rest[s]);
+        double damp = m->c[s] * (dot3(v + 3 * b, dir) - dot3(v + 3 * a, dir));
+        for (int q = 0; q < 3; ++q) {
+            double f = (spring + damp) * dir[q];
+            F[3 * a + q] += f;
+            F[3 * b + q] -= f;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ point-triangle distance */
+
+/* Squared distance from p to the closed segment [a, b]. */
+static double seg_dist2(const double *p, const double *a, const double *b)
+{
+    double ab[3], ap[3];
+    sub3(b, a, ab);
+    sub3(p, a, ap);
+    double L2 = dot3(ab, ab);
+    double t = L2 > 0 ? dot3(ap, ab) / L2 : 0.0;
+    if (t < 0) t = 0;
+    if (t > 1) t = 1;
+    double r[3];
+    for (int q = 0; q < 3; ++q) r[q] = ap[q] - t * ab[q];
+    return dot3(r, r);
+}
+
+/* Squared distance from p to the closed triangle (A, B, C): the distance to the plane if
+ * p's orthogonal projection lies inside the triangle, otherwise the distance to the
+ * nearest of the three edges. */
+double orc_point_tri_dist2(const double *p, const double *A, const double *B, const double *C)
+{
+    double e1[3], e2[3], n[3], ap[3];
+    sub3(B, A, e1);
+    sub3(C, A, e2);
+    cross3(e1, e2, n);
+    double nn = dot3(n, n);
+    sub3(p, A, ap);
+    double sd = dot3(ap, n);
+    /* projection q = p - (sd/nn) n; barycentric signs from sub-triangle orientations */
+    double q[3];
+    for (int i = 0; i < 3; ++i) q[i] = p[i] - sd / nn * n[i];
+    double t0[3], t1[3], c0[3], c1[3], c2[3];
+    sub3(B, q, t0); sub3(C, q, t1); cross3(t0, t1, c0); /* opposite A */
+    sub3(C, q, t0); sub3(A, q, t1); cross3(t0, t1, c1); /* opposite B */
+    sub3(A, q, t0); sub3(B, q, t1); cross3(t0, t1, c2); /* opposite C */
+    if (dot3(c0, n) >= 0 && dot3(c1, n) >= 0 && dot3(c2, n) >= 0) return sd * sd / nn;
+    double d0 = seg_dist2(p, A, B), d1 = seg_dist2(p, B, C), d2 = seg_dist2(p, C, A);
+    double d = d0 < d1 ? d0 : d1;
+    return d < d2 ? d : d2;
+}
+
+/* ------------------------------------------------------------------ one substep */
+
+static int in_box(const orc_model *m, int t, const double *p)
+{
+    for (int a = 0; a < 3; ++a)
+        if (p[a] < m->tlo[3 * t + a] || p[a] > m->thi[3 * t + a]) return 0;
+    return 1;
+}
+
+/* Contacts of point p: triangles with dist(p, t) < th, in ascending triangle id.
+ * Writes up to cap ids into out and returns the count; *margin (if given) receives the
+ * smallest |dist - th| over every triangle whose inflated box holds p. */
+static int contacts_of(const orc_model *m, const double *p, int *out, int cap, double *margin)
+{
+    if (m->T == 0) { if (margin) *margin = INFINITY; return 0; }
+    int ci = cell_coord(m, p[0], 0), cj = cell_coord(m, p[1], 1), ck = cell_coord(m, p[2], 2);
+    long long id = ((long long)ck * m->dim[1] + cj) * m->dim[0] + ci;
+    int n = 0;
+    double mg = INFINITY;
+    for (int r = m->cell_start[id]; r < m->cell_start[id + 1]; ++r) {
+        int t = m->cell_tris[r];
+        if (!in_box(m, t, p)) continue;
+        const double *A = m->verts + 3 * m->tris[3 * t];
+        const double *B = m->verts + 3 * m->tris[3 * t + 1];
+        const double *C = m->verts + 3 * m->tris[3 * t + 2];
+        double d = sqrt(orc_point_tri_dist2(p, A, B, C));
+        double gap = fabs(d - m->th);
+        if (gap < mg) mg = gap;
+        if (d < m->th) {
+            if (n < cap) out[n] = t;
+            ++n;
+        }
+    }
+    if (margin) *margin = mg;
+    return n;
+}
+
+#define ORC_MAX_CONTACTS 512
+
+/* Advance (x, v) [N][3] by one substep of length h, in place.
+ * count (optional, [N]) receives each node's number of contacts; margin (optional, [N])
+ * the smallest |dist - th| over its box candidates (INFINITY if none). */
+void orc_substep(const orc_model *m, double *x, double *v, double h, int *count, double *margin)
+{
+    int N = m->N;
+    double *F = malloc(sizeof(double) * 3 * (size_t)N);
+    orc_forces(m, x, v, F);
+    /* 2. integrate */
+    for (int i = 0; i < N; ++i) {
+        if (m->w[i] == 0.0) {
+            for (int q = 0; q < 3; ++q) v[3 * i + q] = 0.0;
+            continue;
+        }
+        for (int q = 0; q < 3; ++q) {
+            v[3 * i + q] = v[3 * i + q] + h * (m->w[i] * F[3 * i + q] + m->g[q]);
+            x[3 * i + q] = x[3 * i + q] + h * v[3 * i + q];
+        }
+    }
+    /* 3. collision response on the predicted positions */
+    int ids[ORC_MAX_CONTACTS];
+    for (int i = 0; i < N; ++i) {
+        if (count) count[i] = 0;
+        if (margin) margin[i] = INFINITY;
+        if (m->w[i] == 0.0) continue;
+        double *p = x + 3 * i;
+        int n = contacts_of(m, p, ids, ORC_MAX_CONTACTS, margin ? margin + i : NULL);
+        if (count) count[i] = n;
+        if (n == 0) continue;
+        if (n > ORC_MAX_CONTACTS) n = ORC_MAX_CONTACTS;
+        double sum[3] = {0, 0, 0};
+        for (int r = 0; r < n; ++r) {
+            int t = ids[r];
+            const double *nt = m->tn + 3 * t;
+            double ap[3];
+            sub3(p, m->tA + 3 * t, ap);
+            double push = m->th - dot3(ap, nt);
+            for (int q = 0; q < 3; ++q) sum[q] += push * nt[q];
+        }
+        for (int q = 0; q < 3; ++q) {
+            p[q] = p[q] + sum[q] / n;
+            v[3 * i + q] = -m->restitution * v[3 * i + q];
+        }
+    }
+    free(F);
+}
+
+/* n_sub substeps in sequence. */
+void orc_run(const orc_model *m, double *x, double *v, double h, int n_sub)
+{
+    for (int s = 0; s < n_sub; ++s) orc_substep(m, x, v, h, NULL, NULL);
+}
+
+/* Number of contacts a node at p would get, and the contact triangle ids (ascending). */
+int orc_contacts(const orc_model *m, const double *p, int *out, int cap)
+{
+    return contacts_of(m, p, out, cap, NULL);
+}
+
+/* ------------------------------------------------------------------ FP32 broad-phase predicate */
+
+/* Brute force over all (node, triangle) pairs in FP32: node i is a candidate of triangle t
+ * iff lo_t <= x_i <= hi_t on every axis, where lo_t = fl32(min of t's vertex coordinates -
+ * th) and hi_t = fl32(max + th).  Pinned-ness is ignored here.  Pairs are written as
+ * (node, tri) in ascending node, then triangle, order; returns the total pair count (pairs
+ * beyond cap are counted but not written). */
+long long orc_candidates_f32(int N, const float *x, int T, const float *verts, const int *tris,
+                             float th, int *pairs, long long cap)
+{
+    float *lo = malloc(sizeof(float) * 3 * (size_t)(T + 1));
+    float *hi = malloc(sizeof(float) * 3 * (size_t)(T + 1));
+    for (int t = 0; t < T; ++t) {
+        for (int a = 0; a < 3; ++a) {
+            float va = verts[3 * tris[3 * t] + a], vb = verts[3 * tris[3 * t + 1] + a],
+                  vc = verts[3 * tris[3 * t + 2] + a];
+            float mn = va < vb ? va : vb;
+            mn = mn < vc ? mn : vc;
+            float mx = va > vb ? va : vb;
+            mx = mx > vc ? mx : vc;
+            lo[3 * t + a] = mn - th;
+            hi[3 * t + a] = mx + th;
+        }
+    }
+    long long n = 0;
+    for (int i = 0; i < N; ++i) {
+        const float *p = x + 3 * i;
+        for (int t = 0; t < T; ++t) {
+            int in = 1;
+            for (int a = 0; a < 3; ++a)
+                if (!(lo[3 * t + a] <= p[a] && p[a] <= hi[3 * t + a])) { in = 0; break; }
+            if (in) {
+                if (n < cap) { pairs[2 * n] = i; pairs[2 * n + 1] = t; }
+                ++n;
+            }
+        }
+    }
+    free(lo);
+    free(hi);
+    return n;
+}
+
+/* ------------------------------------------------------------------ adjoint of one substep */
+
+/* Reverse-mode derivative of orc_substep at state (x, v) with the contact set held fixed.
+ * Given xb_out, vb_out = dL/d(x, v) after the substep, writes xb_in, vb_in = dL/d(x, v)
+ * before it and ADDS dL/dk, dL/dc into kb, cb (either may be NULL). */
+void orc_substep_vjp(const orc_model *m, const double *x, const double *v, double h,
+                     const double *xb_out, const double *vb_out, double *xb_in, double *vb_in,
+                     double *kb, double *cb)
+{
+    int N = m->N;
+    double *F = malloc(sizeof(double) * 3 * (size_t)N);
+    double *Fb = calloc(3 * (size_t)N, sizeof(double));
+    orc_forces(m, x, v, F);
+    int ids[ORC_MAX_CONTACTS];
+    for (int i = 0; i < N; ++i) {
+        if (m->w[i] == 0.0) {
+            /* pinned: x* = x, v* = 0, and no contact */
+            for (int q = 0; q < 3; ++q) { xb_in[3 * i + q] = xb_out[3 * i + q]; vb_in[3 * i + q] = 0.0; }
+            continue;
+        }
+        double vs[3], xs[3];
+        for (int q = 0; q < 3; ++q) {
+            vs[q] = v[3 * i + q] + h * (m->w[i] * F[3 * i + q] + m->g[q]);
+            xs[q] = x[3 * i + q] + h * vs[q];
+        }
+        int n = contacts_of(m, xs, ids, ORC_MAX_CONTACTS, NULL);
+        if (n > ORC_MAX_CONTACTS) n = ORC_MAX_CONTACTS;
+        double xbs[3], vbs[3];
+        for (int q = 0; q < 3; ++q) { xbs[q] = xb_out[3 * i + q]; vbs[q] = vb_out[3 * i + q]; }
+        if (n > 0) {
+            /* x' = x* + mean_t (th - (x* - A_t).n_t) n_t  ->  dx'/dx* = I - mean_t n_t n_t^T
+             * v' = -r v*                                  ->  dv'/dv* = -r I */
+            double acc[3] = {0, 0, 0};
+            for (int r = 0; r < n; ++r) {
+                const double *nt = m->tn + 3 * ids[r];
+                double s = dot3(nt, xbs);
+                for (int q = 0; q < 3; ++q) acc[q] += s * nt[q];
+            }
+            for (int q = 0; q < 3; ++q) {
+                xbs[q] = xbs[q] - acc[q] / n;
+                vbs[q] = -m->restitution * vbs[q];
+            }
+        }
+        /* x* = x + h v*,  v* = v + h (w F + g) */
+        for (int q = 0; q < 3; ++q) {
+            double vtot = vbs[q] + h * xbs[q];
+            xb_in[3 * i + q] = xbs[q];
+            vb_in[3 * i + q] = vtot;
+            Fb[3 * i + q] = h * m->w[i] * vtot;
+        }
+    }
+    /* spring forces, transposed spring by spring */
+    for (int s = 0; s < m->S; ++s) {
+        int a = m->ends[2 * s], b = m->ends[2 * s + 1];
+        double d[3], u[3], dv[3], lam[3];
+        sub3(x + 3 * b, x + 3 * a, d);
+        sub3(v + 3 * b, v + 3 * a, dv);
+        sub3(Fb + 3 * a, Fb + 3 * b, lam); /* f enters F_a with +, F_b with - */
+        double len = sqrt(dot3(d, d));
+        for (int q = 0; q < 3; ++q) u[q] = d[q] / len;
+        double dvu = dot3(dv, u);
+        double phi = m->k[s] * (len - m->rest[s]) + m->c[s] * dvu;
+        double ul = dot3(u, lam);
+        /* f = phi u(d) with phi = k (|d| - L0) + c (dv . u):
+         *   df = phi (I - u u^T)/|d| dd + u (k u + c (I - u u^T) dv/|d|)^T dd + c u u^T ddv */
+        double db[3], dvb[3];
+        for (int q = 0; q < 3; ++q) {
+            double perp_l = lam[q] - u[q] * ul;
+            double perp_dv = dv[q] - u[q] * dvu;
+            db[q] = phi / len * perp_l + m->k[s] * u[q] * ul + m->c[s] / len * perp_dv * ul;
+            dvb[q] = m->c[s] * u[q] * ul;
+        }
+        for (int q = 0; q < 3; ++q) {
+            xb_in[3 * b + q] += db[q];
+            xb_in[3 * a + q] -= db[q];
+            vb_in[3 * b + q] += dvb[q];
+            vb_in[3 * a + q] -= dvb[q];
+        }
+        if (kb) kb[s] += (len - m->rest[s]) * ul;
+        if (cb) cb[s] += dvu * ul;
+    }
+    free(F);
+    free(Fb);
+}
+
+/* ------------------------------------------------------------------ rollout gradient */
+
+/* Run n_sub substeps from (x0, v0) and back-propagate.
+ *   out_sub[j] (ascending, 1..n_sub): substep counts after which the loss reads x;
+ *   xbar[j][N][3]: dL/dx at those states.
+ * Writes x_out[j][N][3] (the states themselves, if x_out is not NULL) and the gradients
+ * gk[S], gc[S], gv0[N][3], gx0[N][3] (any may be NULL).  States are checkpointed every
+ * ckpt substeps (ckpt >= 1) and each segment is recomputed from its checkpoint on the way
+ * back; the values do not depend on ckpt. */
+void orc_rollout_grad(const orc_model *m, const double *x0, const double *v0, double h,
+                      int n_sub, int n_out, const int *out_sub, const double *xbar,
+                      int ckpt, double *x_out, double *gk, double *gc, double *gv0,
+                      double *gx0)
+{
+    int N = m->N, S = m->S;
+    size_t n3 = 3 * (size_t)N;
+    if (ckpt < 1) ckpt = 1;
+    int n_ck = n_sub / ckpt + 1;
+    double *ck_x = malloc(sizeof(double) * n3 * (size_t)n_ck);
+    double *ck_v = malloc(sizeof(double) * n3 * (size_t)n_ck);
+    double *x = malloc(sizeof(double) * n3), *v = malloc(sizeof(double) * n3);
+    memcpy(x, x0, sizeof(double) * n3);
+    memcpy(v, v0, sizeof(double) * n3);
+    int j = 0;
+    for (int s = 0; s <= n_sub; ++s) {
+        if (s % ckpt == 0) {
+            memcpy(ck_x + n3 * (size_t)(s / ckpt), x, sizeof(double) * n3);
+            memcpy(ck_v + n3 * (size_t)(s / ckpt), v, sizeof(double) * n3);
+        }
+        while (j < n_out && out_sub[j] == s) {
+            if (x_out) memcpy(x_out + n3 * (size_t)j, x, sizeof(double) * n3);
+            ++j;
+        }
+        if (s < n_sub) orc_substep(m, x, v, h, NULL, NULL);
+    }
+    double *kb = calloc((size_t)S + 1, sizeof(double)), *cb = calloc((size_t)S + 1, sizeof(double));
+    double *xb = calloc(n3, sizeof(double)), *vb = calloc(n3, sizeof(double));
+    double *xb2 = malloc(sizeof(double) * n3), *vb2 = malloc(sizeof(double) * n3);
+    double *seg_x = malloc(sizeof(double) * n3 * (size_t)ckpt);
+    double *seg_v = malloc(sizeof(double) * n3 * (size_t)ckpt);
+    /* backward, one checkpoint segment at a time: recompute the segment's states from its
+     * checkpoint, then apply the substep adjoints in reverse order */
+    j = n_out - 1;
+    while (j >= 0 && out_sub[j] == n_sub) {
+        for (size_t q = 0; q < n3; ++q) xb[q] += xbar[n3 * (size_t)j + q];
+        --j;
+    }
+    for (int seg = (n_sub - 1) / ckpt; seg >= 0 && n_sub > 0; --seg) {
+        int base = seg * ckpt;
+        int top = base + ckpt < n_sub ? base + ckpt : n_sub; /* substeps base..top-1 */
+        memcpy(seg_x, ck_x + n3 * (size_t)seg, sizeof(double) * n3);
+        memcpy(seg_v, ck_v + n3 * (size_t)seg, sizeof(double) * n3);
+        for (int r = 1; r < top - base; ++r) {
+            memcpy(seg_x + n3 * (size_t)r, seg_x + n3 * (size_t)(r - 1), sizeof(double) * n3);
+            memcpy(seg_v + n3 * (size_t)r, seg_v + n3 * (size_t)(r - 1), sizeof(double) * n3);
+            orc_substep(m, seg_x + n3 * (size_t)r, seg_v + n3 * (size_t)r, h, NULL, NULL);
+        }
+        for (int s = top; s > base; --s) {
+            int slot = s - 1 - base; /* state before substep s-1 -> s */
+            orc_substep_vjp(m, seg_x + n3 * (size_t)slot, seg_v + n3 * (size_t)slot, h, xb, vb,
+                            xb2, vb2, kb, cb);
+            memcpy(xb, xb2, sizeof(double) * n3);
+            memcpy(vb, vb2, sizeof(double) * n3);
+            while (j >= 0 && out_sub[j] == s - 1) {
+                for (size_t q = 0; q < n3; ++q) xb[q] += xbar[n3 * (size_t)j + q];
+                --j;
+            }
+        }
+    }
+    if (gk) memcpy(gk, kb, sizeof(double) * (size_t)S);
+    if (gc) memcpy(gc, cb, sizeof(double) * (size_t)S);
+    if (gv0) memcpy(gv0, vb, sizeof(double) * n3);
+    if (gx0) memcpy(gx0, xb, sizeof(double) * n3);
+    free(ck_x); free(ck_v); free(x); free(v); free(kb); free(cb);
+    free(xb); free(vb); free(xb2); free(vb2); free(seg_x); free(seg_v);
+}
+
+/* ------------------------------------------------------------------ accessors */
+
+void orc_model_triangle(const orc_model *m, int t, double *A, double *n, double *lo, double *hi)
+{
+    for (int a = 0; a < 3; ++a) {
+        if (A) A[a] = m->tA[3 * t + a];
+        if (n) n[a] = m->tn[3 * t + a];
+        if (lo) lo[a] = m->tlo[3 * t + a];
+        if (hi) hi[a] = m->thi[3 * t + a];
+    }
+}
