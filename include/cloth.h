@@ -1,0 +1,165 @@
+/*
+ * cloth.h -- C ABI of the MI355X (gfx950) mass-spring cloth library.
+ *
+ * The library advances a mass-spring cloth (Sec. 3 of the paper: nodes joined by springs
+ * with rest length, stiffness and damping) through the per-frame path of Sec. 3 and Fig. 2:
+ *   1. spring forces of Alg. 1, gathered per node over a CSR incidence list;
+ *   2. explicit (semi-implicit Euler) integration with gravity and pinned nodes;
+ *   3. a uniform-grid broad phase over the triangles of a static collision surface;
+ *   4. point-triangle proximity with a thickness and the averaged response of Alg. 2
+ *      (velocity reversed and scaled by the restitution, 0.5 in Alg. 2; position pushed
+ *      by the mean of the per-hit directions, Sec. 3 collision paragraph).
+ *
+ * Conventions (every entry point):
+ *   - Return value: CLOTH_OK (0) or a negative CLOTH_E* status.  No call aborts or throws;
+ *     cloth_last_error() gives a message for the calling thread's last failure.
+ *   - Ownership: the caller owns every array it passes; the library copies inputs at create
+ *     time and owns its device memory until the matching destroy.  Host pointers are
+ *     marked [host], device pointers [device].
+ *   - Layout: host arrays of 3-vectors are AoS, element (i, k) at [i*3 + k], as Alg. 2
+ *     writes positions and velocities.  Device state views are SoA, [k*N + i] in the
+ *     library's internal node order (see cloth_device_state).
+ *   - Streams: every call enqueues on the HIP stream given at create (NULL = the null
+ *     stream); calls that return host data synchronise that stream.  A handle is used from
+ *     one thread at a time; distinct handles are independent.
+ *   - Determinism: for identical inputs the results are bit-identical across runs and
+ *     across launch configurations (forces are gathered in a fixed order, no float
+ *     atomics; contact sums run in ascending triangle id).
+ */
+#ifndef CLOTH_H
+#define CLOTH_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cloth_sim cloth_sim;     /* opaque, library-owned */
+typedef struct cloth_batch cloth_batch; /* opaque, library-owned */
+
+enum cloth_status {
+    CLOTH_OK = 0,
+    CLOTH_EINVAL = -1,    /* invalid argument or input data */
+    CLOTH_ENOMEM = -2,    /* device or host allocation failed, or a size limit was hit */
+    CLOTH_EDEVICE = -3,   /* a HIP runtime call or kernel failed */
+    CLOTH_EUNSTABLE = -4, /* substep too long for the explicit scheme (see cloth_step) */
+    CLOTH_ESTATE = -5,    /* call out of order (e.g. backward without forward) */
+    CLOTH_ENAN = -6       /* a non-finite value appeared in the state (CLOTH_F_CHECK_NAN) */
+};
+
+/* cloth_params.flags */
+#define CLOTH_F_CHECK_NAN 0x1u          /* flag non-finite state values; cloth_read_state
+                                           then returns CLOTH_ENAN */
+#define CLOTH_F_NO_STABILITY_CHECK 0x2u /* skip the substep-length check of cloth_step */
+
+typedef struct cloth_params {
+    float gravity[3];  /* m/s^2, e.g. {0, -9.81, 0} */
+    float thickness;   /* m; contact when point-triangle distance < thickness; 0 disables
+                          collision */
+    float cell_size;   /* m; broad-phase grid cell edge; <= 0 selects 2 x mean surface edge */
+    float restitution; /* on contact v <- -restitution * v (0.5 in Alg. 2) */
+    unsigned flags;    /* CLOTH_F_* */
+} cloth_params;
+
+/*
+ * cloth_create -- build a simulation from a cloth grid, its springs and a surface mesh.
+ *   nx, ny      grid shape; N = nx*ny nodes, node id i*nx + j for row i, column j (used to
+ *               order nodes in memory; any spring graph over the N nodes is accepted).
+ *   x0, v0      [host] [N*3] initial positions / velocities (v0 NULL = zero).
+ *   mass        [host] [N] node masses, > 0 for unpinned nodes.
+ *   pinned      [host] [N] nonzero = pinned node (never moves, zero velocity, no
+ *               collision); NULL = none.
+ *   n_springs, ends  [host] [S*2] node ids (a, b), a != b; Alg. 1's indexA / indexB.
+ *   rest, k, c  [host] [S] rest length > 0, stiffness >= 0, damping >= 0 (Alg. 1).
+ *   n_verts, verts   [host] [V*3] surface vertices (may be 0 / NULL).
+ *   n_tris, tris     [host] [T*3] vertex ids, wound counter-clockwise seen from outside
+ *               (the unit outward normal is normalize((B-A) x (C-A))); no zero-area triangle.
+ *   p           [host] parameters, copied.
+ *   hip_stream  hipStream_t to run on, or NULL.
+ *   out         receives the handle.
+ * Errors: CLOTH_EINVAL for N <= 0, S < 0, an index out of range, a == b, rest <= 0,
+ *   k < 0, c < 0, mass <= 0 on an unpinned node, any non-finite input, a degenerate
+ *   triangle, thickness < 0, restitution outside [0, 1]; CLOTH_ENOMEM; CLOTH_EDEVICE.
+ */
+int cloth_create(int nx, int ny, const float* x0, const float* v0, const float* mass,
+                 const unsigned char* pinned, int n_springs, const int* ends, const float* rest,
+                 const float* k, const float* c, int n_verts, const float* verts, int n_tris,
+                 const int* tris, const cloth_params* p, void* hip_stream, cloth_sim** out);
+
+/*
+ * cloth_step -- advance n_steps frames of length dt, each split into n_substeps substeps
+ * of h = dt / n_substeps (forces -> integrate -> broad phase -> narrow phase -> response
+ * per substep).  Asynchronous on the handle's stream.
+ * Errors: CLOTH_EINVAL (dt <= 0 or non-finite, n_substeps < 1, n_steps < 0);
+ *   CLOTH_EUNSTABLE when (w h)^2 + 2 g h >= 4, where w^2 and g bound the largest
+ *   eigenvalues of M^-1 K and M^-1 C (Gershgorin row sums of the spring stiffness and
+ *   damping matrices at the initial configuration) -- the stability limit of the damped
+ *   semi-implicit Euler scheme; skipped with CLOTH_F_NO_STABILITY_CHECK.
+ */
+int cloth_step(cloth_sim* sim, float dt, int n_substeps, int n_steps);
+
+/*
+ * cloth_read_state -- copy the current state to the host, AoS [N*3] in node-id order
+ * (Alg. 2's output: updated positions and velocities).  v_out may be NULL.  Synchronises.
+ * Returns CLOTH_ENAN if CLOTH_F_CHECK_NAN is set and a non-finite value was produced.
+ */
+int cloth_read_state(const cloth_sim* sim, float* x_out, float* v_out);
+
+/* cloth_write_state -- overwrite the state from host AoS arrays [N*3] (v may be NULL = 0);
+ * with cloth_read_state this gives bit-exact save / resume. */
+int cloth_write_state(cloth_sim* sim, const float* x, const float* v);
+
+/*
+ * cloth_device_state -- borrowed [device] views of the current state, SoA [3][N] in the
+ * library's internal node order, valid until the next cloth_step / cloth_write_state /
+ * cloth_destroy.  Either pointer may be NULL.  cloth_node_order gives the order.
+ */
+int cloth_device_state(cloth_sim* sim, float** x_soa, float** v_soa);
+
+/* cloth_node_order -- [host] [N] out: order[p] = node id stored at internal slot p. */
+int cloth_node_order(const cloth_sim* sim, int* order);
+
+/* cloth_info -- sizes: out[0] = N, out[1] = S, out[2] = T, out[3] = grid cells,
+ * out[4] = grid references, out[5..7] = grid dims (x, y, z).  [host] out[8]. */
+int cloth_info(const cloth_sim* sim, long long* out);
+
+/* cloth_destroy -- release everything; NULL is accepted. */
+int cloth_destroy(cloth_sim* sim);
+
+/*
+ * cloth_debug_candidates -- broad-phase candidate pairs of arbitrary query points against
+ * the handle's surface grid.  A point P is a candidate of triangle t iff
+ * lo_t <= P <= hi_t on every axis, lo_t = fl32(min of t's vertex coordinates - thickness),
+ * hi_t = fl32(max + thickness) -- the exact set an O(points x triangles) FP32 brute force
+ * gives, found through the uniform grid.
+ *   points     [host] [n_points*3] AoS.
+ *   pairs_out  [host] [cap*2] receives (point index, triangle id) sorted by point, then
+ *              triangle; at most cap pairs are written.
+ *   n_out      [host] receives the total number of pairs (may exceed cap).
+ * Errors: CLOTH_EINVAL (n_points < 0, NULL pointers with cap > 0, collision disabled).
+ */
+int cloth_debug_candidates(cloth_sim* sim, int n_points, const float* points, int* pairs_out,
+                           long long cap, long long* n_out);
+
+/*
+ * cloth_stability_bound -- host-only (no GPU) stability bounds of a spring network at
+ * configuration x0: *omega2 and *gamma are the largest Gershgorin row sums of M^-1 K and
+ * M^-1 C (K, C assembled from k u u^T and c u u^T per spring, u the unit spring direction);
+ * pinned nodes' rows are skipped.  cloth_step rejects h with omega2 h^2 + 2 gamma h >= 4.
+ *   x0 [host] [n_nodes*3]; mass [host] [n_nodes]; pinned [host] [n_nodes] or NULL;
+ *   ends [host] [S*2]; k, c [host] [S].  Errors: CLOTH_EINVAL as for cloth_create.
+ */
+int cloth_stability_bound(int n_nodes, const float* x0, const float* mass,
+                          const unsigned char* pinned, int n_springs, const int* ends,
+                          const float* k, const float* c, double* omega2, double* gamma);
+
+/* cloth_status_str -- static text for a status code. */
+const char* cloth_status_str(int status);
+
+/* cloth_last_error -- message for the calling thread's last failed call ("" if none). */
+const char* cloth_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CLOTH_H */

@@ -51,6 +51,10 @@ def _load():
     lib.orc_forces.argtypes = [P, dp, dp, dp]
     lib.orc_substep.argtypes = [P, dp, dp, C.c_double, ip, dp]
     lib.orc_run.argtypes = [P, dp, dp, C.c_double, C.c_int]
+    lib.orc_predict.argtypes = [P, dp, dp, C.c_double]
+    lib.orc_respond.argtypes = [P, dp, dp, ip, C.c_int]
+    lib.orc_box_candidates.restype = C.c_int
+    lib.orc_box_candidates.argtypes = [P, dp, ip, dp, C.c_int]
     lib.orc_contacts.restype = C.c_int
     lib.orc_contacts.argtypes = [P, dp, ip, C.c_int]
     lib.orc_point_tri_dist2.restype = C.c_double
@@ -148,6 +152,28 @@ class Model:
         x, v = _d(x).reshape(-1, 3).copy(), _d(v).reshape(-1, 3).copy()
         self._lib.orc_run(self._h, _dp(x), _dp(v), float(h), int(n_sub))
         return x, v
+
+    def predict(self, x, v, h):
+        """Forces and integration only: returns (x*, v*)."""
+        x, v = _d(x).reshape(-1, 3).copy(), _d(v).reshape(-1, 3).copy()
+        self._lib.orc_predict(self._h, _dp(x), _dp(v), float(h))
+        return x, v
+
+    def respond(self, p, v, ids):
+        """Response of one node at predicted (p, v) to the contact triangles ids."""
+        p, v = _d(p).reshape(3).copy(), _d(v).reshape(3).copy()
+        ids = _i(np.sort(np.asarray(ids, dtype=np.int64)))
+        self._lib.orc_respond(self._h, _dp(p), _dp(v), _ip(ids), int(ids.shape[0]))
+        return p, v
+
+    def box_candidates(self, p):
+        """(ids, exact distances) of every triangle whose inflated box holds p."""
+        ids = np.zeros(1024, dtype=np.int32)
+        dist = np.zeros(1024)
+        n = self._lib.orc_box_candidates(self._h, _dp(_d(p).reshape(3)), _ip(ids), _dp(dist),
+                                         1024)
+        n = min(n, 1024)
+        return ids[:n].copy(), dist[:n].copy()
 
     def contacts(self, p):
         out = np.zeros(512, dtype=np.int32)

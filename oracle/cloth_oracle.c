@@ -24,8 +24,9 @@
  *      (it puts x* at distance th in front of the triangle's plane), the directions are
  *      averaged over the hits, and the restitution factor (0.5 in Alg. 2) is a parameter.
  *   The candidate set is defined by brute force over all triangles; a bucket grid is used
- *   only to skip triangles whose thickness-inflated bounding box cannot contain x*, which
- *   is implied by dist < th, so it never changes the result.
+ *   only to skip triangles whose bounding box, inflated by th plus a slack of ORC_BOX_SLACK,
+ *   cannot contain x*.  dist < th implies x* lies in that box, so the filter never changes
+ *   the result; the slack lets the near-threshold margin see triangles just beyond th.
  *
  * Also here: the FP32 brute-force broad-phase predicate (the exact candidate set a
  * uniform grid must reproduce), the reverse-mode adjoint of one substep with the contact
@@ -50,6 +51,8 @@ static void cross3(const double *a, const double *b, double *o)
 }
 
 /* ------------------------------------------------------------------ model */
+
+#define ORC_BOX_SLACK 1e-5 /* m: extra inflation of the acceleration boxes */
 
 typedef struct {
     int N, S, V, T;
@@ -98,8 +101,8 @@ static void build_surface(orc_model *m, double cell)
         for (int a = 0; a < 3; ++a) {
             m->tA[3 * t + a] = A[a];
             m->tn[3 * t + a] = n[a] / ln;
-            double lo = fmin(A[a], fmin(B[a], C[a])) - m->th;
-            double hi = fmax(A[a], fmax(B[a], C[a])) + m->th;
+            double lo = fmin(A[a], fmin(B[a], C[a])) - m->th - ORC_BOX_SLACK;
+            double hi = fmax(A[a], fmax(B[a], C[a])) + m->th + ORC_BOX_SLACK;
             m->tlo[3 * t + a] = lo;
             m->thi[3 * t + a] = hi;
             if (lo < bmin[a]) bmin[a] = lo;
@@ -274,7 +277,7 @@ static int in_box(const orc_model *m, int t, const double *p)
 
 /* Contacts of point p: triangles with dist(p, t) < th, in ascending triangle id.
  * Writes up to cap ids into out and returns the count; *margin (if given) receives the
- * smallest |dist - th| over every triangle whose inflated box holds p. */
+ * smallest |dist - th| over every triangle whose (slack-inflated) box holds p. */
 static int contacts_of(const orc_model *m, const double *p, int *out, int cap, double *margin)
 {
     if (m->T == 0) { if (margin) *margin = INFINITY; return 0; }
@@ -302,15 +305,12 @@ static int contacts_of(const orc_model *m, const double *p, int *out, int cap, d
 
 #define ORC_MAX_CONTACTS 512
 
-/* Advance (x, v) [N][3] by one substep of length h, in place.
- * count (optional, [N]) receives each node's number of contacts; margin (optional, [N])
- * the smallest |dist - th| over its box candidates (INFINITY if none). */
-void orc_substep(const orc_model *m, double *x, double *v, double h, int *count, double *margin)
+/* Forces and integration of one substep without collision: (x, v) -> (x*, v*) in place. */
+void orc_predict(const orc_model *m, double *x, double *v, double h)
 {
     int N = m->N;
     double *F = malloc(sizeof(double) * 3 * (size_t)N);
     orc_forces(m, x, v, F);
-    /* 2. integrate */
     for (int i = 0; i < N; ++i) {
         if (m->w[i] == 0.0) {
             for (int q = 0; q < 3; ++q) v[3 * i + q] = 0.0;
@@ -321,32 +321,68 @@ void orc_substep(const orc_model *m, double *x, double *v, double h, int *count,
             x[3 * i + q] = x[3 * i + q] + h * v[3 * i + q];
         }
     }
-    /* 3. collision response on the predicted positions */
+    free(F);
+}
+
+/* Response of one node at predicted (p, v) to the contact triangles ids[0..n) (ascending):
+ * p <- p + mean_t (th - (p - A_t).n_t) n_t, v <- -restitution v; unchanged if n == 0. */
+void orc_respond(const orc_model *m, double *p, double *v, const int *ids, int n)
+{
+    if (n <= 0) return;
+    double sum[3] = {0, 0, 0};
+    for (int r = 0; r < n; ++r) {
+        int t = ids[r];
+        const double *nt = m->tn + 3 * t;
+        double ap[3];
+        sub3(p, m->tA + 3 * t, ap);
+        double push = m->th - dot3(ap, nt);
+        for (int q = 0; q < 3; ++q) sum[q] += push * nt[q];
+    }
+    for (int q = 0; q < 3; ++q) {
+        p[q] = p[q] + sum[q] / n;
+        v[q] = -m->restitution * v[q];
+    }
+}
+
+/* Every triangle whose slack-inflated box holds p, ascending, with its exact distance to p.
+ * Returns the count (entries beyond cap are counted, not written). */
+int orc_box_candidates(const orc_model *m, const double *p, int *ids, double *dist, int cap)
+{
+    if (m->T == 0) return 0;
+    int ci = cell_coord(m, p[0], 0), cj = cell_coord(m, p[1], 1), ck = cell_coord(m, p[2], 2);
+    long long id = ((long long)ck * m->dim[1] + cj) * m->dim[0] + ci;
+    int n = 0;
+    for (int r = m->cell_start[id]; r < m->cell_start[id + 1]; ++r) {
+        int t = m->cell_tris[r];
+        if (!in_box(m, t, p)) continue;
+        if (n < cap) {
+            ids[n] = t;
+            dist[n] = sqrt(orc_point_tri_dist2(p, m->verts + 3 * m->tris[3 * t],
+                                               m->verts + 3 * m->tris[3 * t + 1],
+                                               m->verts + 3 * m->tris[3 * t + 2]));
+        }
+        ++n;
+    }
+    return n;
+}
+
+/* Advance (x, v) [N][3] by one substep of length h, in place.
+ * count (optional, [N]) receives each node's number of contacts; margin (optional, [N])
+ * the smallest |dist - th| over its box candidates (INFINITY if none). */
+void orc_substep(const orc_model *m, double *x, double *v, double h, int *count, double *margin)
+{
+    int N = m->N;
+    orc_predict(m, x, v, h);
     int ids[ORC_MAX_CONTACTS];
     for (int i = 0; i < N; ++i) {
         if (count) count[i] = 0;
         if (margin) margin[i] = INFINITY;
         if (m->w[i] == 0.0) continue;
-        double *p = x + 3 * i;
-        int n = contacts_of(m, p, ids, ORC_MAX_CONTACTS, margin ? margin + i : NULL);
+        int n = contacts_of(m, x + 3 * i, ids, ORC_MAX_CONTACTS, margin ? margin + i : NULL);
         if (count) count[i] = n;
-        if (n == 0) continue;
         if (n > ORC_MAX_CONTACTS) n = ORC_MAX_CONTACTS;
-        double sum[3] = {0, 0, 0};
-        for (int r = 0; r < n; ++r) {
-            int t = ids[r];
-            const double *nt = m->tn + 3 * t;
-            double ap[3];
-            sub3(p, m->tA + 3 * t, ap);
-            double push = m->th - dot3(ap, nt);
-            for (int q = 0; q < 3; ++q) sum[q] += push * nt[q];
-        }
-        for (int q = 0; q < 3; ++q) {
-            p[q] = p[q] + sum[q] / n;
-            v[3 * i + q] = -m->restitution * v[3 * i + q];
-        }
+        orc_respond(m, x + 3 * i, v + 3 * i, ids, n);
     }
-    free(F);
 }
 
 /* n_sub substeps in sequence. */

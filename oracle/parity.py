@@ -1,0 +1,57 @@
+"""One-substep parity check of a device result against the oracle -- TEST INFRASTRUCTURE.
+
+A contact is decided by comparing a point-triangle distance with the thickness.  When the
+FP64 distance lies within ``border`` of the thickness, FP32 arithmetic may legitimately take
+either decision, and after a push the node sits at exactly the thickness from the pushing
+triangle's plane, so such near-threshold decisions are common.  Nodes with such a triangle
+are therefore checked against every valid resolution: the oracle's response with the sure
+contacts plus any subset of the ambiguous ones must reproduce the device result.
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+
+def substep_parity(model, x, v, h, x1, v1, L, border=1e-6, xtol=2e-6, vtol_abs=2e-3,
+                   vtol_rel=1e-4, tag=""):
+    """Raises AssertionError on a mismatch; returns summary statistics.
+
+    x, v: the state the device started from (FP32 arrays, [N,3]); x1, v1: the device's state
+    one substep of length h later; L: length scale for the position tolerance xtol * L."""
+    x64, v64 = np.asarray(x, np.float64), np.asarray(v, np.float64)
+    xr, vr, cnt, margin = model.substep(x64, v64, h)
+    X1, V1 = np.asarray(x1, np.float64), np.asarray(v1, np.float64)
+    ex = np.abs(X1 - xr).max(axis=1)
+    ev = np.abs(V1 - vr).max(axis=1)
+    vtol = vtol_abs + vtol_rel * float(np.abs(vr).max())
+    amb = margin < border
+    bad = np.nonzero(~amb & ((ex > xtol * L) | (ev > vtol)))[0]
+    assert bad.size == 0, (tag, "mismatch", bad[:8].tolist(), ex[bad[:8]].tolist(),
+                           ev[bad[:8]].tolist())
+    resolved = 0
+    if amb.any():
+        xs, vs = model.predict(x64, v64, h)
+        th = model.thickness
+        for i in np.nonzero(amb)[0]:
+            ids, dist = model.box_candidates(xs[i])
+            sure = [int(t) for t, d in zip(ids, dist) if d < th - border]
+            maybe = [int(t) for t, d in zip(ids, dist) if abs(d - th) <= border]
+            assert len(maybe) <= 10, (tag, "too many ambiguous contacts", i, len(maybe))
+            ok = False
+            for r in range(len(maybe) + 1):
+                for sub in itertools.combinations(maybe, r):
+                    p, q = model.respond(xs[i], vs[i], sorted(sure + list(sub)))
+                    if (np.abs(p - X1[i]).max() <= xtol * L and np.abs(q - V1[i]).max() <= vtol):
+                        ok = True
+                        break
+                if ok:
+                    break
+            assert ok, (tag, "ambiguous node matches no valid resolution", int(i), sure, maybe,
+                        X1[i].tolist(), xr[i].tolist())
+            resolved += 1
+    clean = ~amb
+    return dict(contacts=int(np.count_nonzero(cnt)), ambiguous=int(amb.sum()),
+                resolved=resolved, ex=float(ex[clean].max() / L) if clean.any() else 0.0,
+                ev=float(ev[clean].max()) if clean.any() else 0.0)

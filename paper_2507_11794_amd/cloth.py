@@ -1,0 +1,264 @@
+"""ctypes binding of the HIP cloth library (include/cloth.h).
+
+Argument marshalling only: every step of the simulation runs in the library's HIP kernels.
+The functions keep the C names (cloth_create, cloth_step, ...); ``Cloth`` wraps a handle.
+Loading fails loudly if libcloth.so cannot be built or loaded -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcloth.so")
+
+CLOTH_OK, CLOTH_EINVAL, CLOTH_ENOMEM, CLOTH_EDEVICE = 0, -1, -2, -3
+CLOTH_EUNSTABLE, CLOTH_ESTATE, CLOTH_ENAN = -4, -5, -6
+CLOTH_F_CHECK_NAN, CLOTH_F_NO_STABILITY_CHECK = 0x1, 0x2
+
+_lib = None
+_lock = threading.Lock()
+
+
+class ClothError(RuntimeError):
+    def __init__(self, status: int, text: str, detail: str):
+        super().__init__(f"{text} ({status}): {detail}")
+        self.status = status
+        self.detail = detail
+
+
+class cloth_params(C.Structure):
+    _fields_ = [("gravity", C.c_float * 3), ("thickness", C.c_float), ("cell_size", C.c_float),
+                ("restitution", C.c_float), ("flags", C.c_uint)]
+
+
+_fp = C.POINTER(C.c_float)
+_ip = C.POINTER(C.c_int)
+_u8p = C.POINTER(C.c_ubyte)
+_llp = C.POINTER(C.c_longlong)
+_vp = C.c_void_p
+
+# (name, restype, argtypes)
+_SIGNATURES = [
+    ("cloth_create", C.c_int, [C.c_int, C.c_int, _fp, _fp, _fp, _u8p, C.c_int, _ip, _fp, _fp, _fp,
+                               C.c_int, _fp, C.c_int, _ip, C.POINTER(cloth_params), _vp,
+                               C.POINTER(_vp)]),
+    ("cloth_step", C.c_int, [_vp, C.c_float, C.c_int, C.c_int]),
+    ("cloth_read_state", C.c_int, [_vp, _fp, _fp]),
+    ("cloth_write_state", C.c_int, [_vp, _fp, _fp]),
+    ("cloth_device_state", C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp)]),
+    ("cloth_node_order", C.c_int, [_vp, _ip]),
+    ("cloth_info", C.c_int, [_vp, _llp]),
+    ("cloth_destroy", C.c_int, [_vp]),
+    ("cloth_debug_candidates", C.c_int, [_vp, C.c_int, _fp, _ip, C.c_longlong, _llp]),
+    ("cloth_stability_bound", C.c_int, [C.c_int, _fp, _fp, _u8p, C.c_int, _ip, _fp, _fp,
+                                        C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    ("cloth_status_str", C.c_char_p, [C.c_int]),
+    ("cloth_last_error", C.c_char_p, []),
+]
+
+
+def load(path: str = LIB_PATH):
+    """Load libcloth.so, building it first only if it does not exist."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            from . import build as _build
+            _build.build()
+        lib = C.CDLL(path)
+        for name, res, args in _SIGNATURES:
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+        return lib
+
+
+def _check(status: int):
+    if status != CLOTH_OK:
+        lib = load()
+        raise ClothError(status, lib.cloth_status_str(status).decode(),
+                         lib.cloth_last_error().decode())
+
+
+def _f32(a, n=None):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a
+
+
+def _ptr(a, t):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+def default_stream() -> int:
+    """HIP stream handle of torch's current stream (0 if torch or a GPU is unavailable)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return int(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return 0
+
+
+def make_params(gravity=(0.0, -9.81, 0.0), thickness=0.0, cell_size=0.0, restitution=0.5,
+                flags=0) -> cloth_params:
+    p = cloth_params()
+    for q in range(3):
+        p.gravity[q] = float(gravity[q])
+    p.thickness = float(thickness)
+    p.cell_size = float(cell_size)
+    p.restitution = float(restitution)
+    p.flags = int(flags)
+    return p
+
+
+def cloth_create(nx, ny, x0, v0, mass, pinned, ends, rest, k, c, verts, tris, params,
+                 stream=None):
+    """Returns an opaque handle (int)."""
+    lib = load()
+    N = int(nx) * int(ny)
+    x0 = _f32(x0).reshape(N, 3)
+    v0 = None if v0 is None else _f32(v0).reshape(N, 3)
+    mass = _f32(mass).reshape(N)
+    pinned = None if pinned is None else np.ascontiguousarray(pinned, dtype=np.uint8).reshape(N)
+    ends = np.ascontiguousarray(ends, dtype=np.int32).reshape(-1, 2)
+    S = ends.shape[0]
+    rest, k, c = _f32(rest).reshape(S), _f32(k).reshape(S), _f32(c).reshape(S)
+    verts = _f32(np.zeros((0, 3)) if verts is None else verts).reshape(-1, 3)
+    tris = np.ascontiguousarray(np.zeros((0, 3)) if tris is None else tris,
+                                dtype=np.int32).reshape(-1, 3)
+    out = _vp()
+    st = lib.cloth_create(int(nx), int(ny), _ptr(x0, _fp), _ptr(v0, _fp), _ptr(mass, _fp),
+                          _ptr(pinned, _u8p), S, _ptr(ends, _ip), _ptr(rest, _fp), _ptr(k, _fp),
+                          _ptr(c, _fp), verts.shape[0], _ptr(verts, _fp), tris.shape[0],
+                          _ptr(tris, _ip), C.byref(params),
+                          _vp(default_stream() if stream is None else int(stream)), C.byref(out))
+    _check(st)
+    return out.value
+
+
+def cloth_step(h, dt, n_substeps, n_steps):
+    _check(load().cloth_step(_vp(h), float(dt), int(n_substeps), int(n_steps)))
+
+
+def cloth_read_state(h, n):
+    x = np.zeros((n, 3), dtype=np.float32)
+    v = np.zeros((n, 3), dtype=np.float32)
+    _check(load().cloth_read_state(_vp(h), _ptr(x, _fp), _ptr(v, _fp)))
+    return x, v
+
+
+def cloth_write_state(h, x, v=None):
+    x = _f32(x)
+    v = None if v is None else _f32(v)
+    _check(load().cloth_write_state(_vp(h), _ptr(x, _fp), _ptr(v, _fp)))
+
+
+def cloth_device_state(h):
+    xp, vp = _vp(), _vp()
+    _check(load().cloth_device_state(_vp(h), C.byref(xp), C.byref(vp)))
+    return xp.value, vp.value
+
+
+def cloth_node_order(h, n):
+    order = np.zeros(n, dtype=np.int32)
+    _check(load().cloth_node_order(_vp(h), _ptr(order, _ip)))
+    return order
+
+
+def cloth_info(h):
+    out = np.zeros(8, dtype=np.int64)
+    _check(load().cloth_info(_vp(h), _ptr(out, _llp)))
+    keys = ("nodes", "springs", "tris", "cells", "refs", "dim_x", "dim_y", "dim_z")
+    return dict(zip(keys, (int(x) for x in out)))
+
+
+def cloth_destroy(h):
+    if h:
+        _check(load().cloth_destroy(_vp(h)))
+
+
+def cloth_debug_candidates(h, points):
+    lib = load()
+    P = _f32(points).reshape(-1, 3)
+    n = C.c_longlong(0)
+    _check(lib.cloth_debug_candidates(_vp(h), P.shape[0], _ptr(P, _fp), None, 0, C.byref(n)))
+    pairs = np.zeros((max(n.value, 1), 2), dtype=np.int32)
+    n2 = C.c_longlong(0)
+    _check(lib.cloth_debug_candidates(_vp(h), P.shape[0], _ptr(P, _fp), _ptr(pairs, _ip),
+                                      n.value, C.byref(n2)))
+    return pairs[:n.value].copy()
+
+
+def cloth_stability_bound(x0, mass, pinned, ends, k, c):
+    """Host-only (omega2, gamma) bounds; see include/cloth.h."""
+    lib = load()
+    x0 = _f32(x0).reshape(-1, 3)
+    n = x0.shape[0]
+    mass = _f32(mass).reshape(n)
+    pinned = None if pinned is None else np.ascontiguousarray(pinned, dtype=np.uint8).reshape(n)
+    ends = np.ascontiguousarray(ends, dtype=np.int32).reshape(-1, 2)
+    S = ends.shape[0]
+    k, c = _f32(k).reshape(S), _f32(c).reshape(S)
+    w2, g = C.c_double(0), C.c_double(0)
+    _check(lib.cloth_stability_bound(n, _ptr(x0, _fp), _ptr(mass, _fp), _ptr(pinned, _u8p), S,
+                                     _ptr(ends, _ip), _ptr(k, _fp), _ptr(c, _fp), C.byref(w2),
+                                     C.byref(g)))
+    return w2.value, g.value
+
+
+class Cloth:
+    """One simulation handle built from a ClothInputs-like object."""
+
+    def __init__(self, inp, flags=0, stream=None):
+        self.inp = inp
+        self.n = int(inp.nx * inp.ny)
+        self.params = make_params(inp.gravity, inp.thickness, inp.cell_size, inp.restitution,
+                                  flags)
+        self.h = cloth_create(inp.nx, inp.ny, inp.x0, inp.v0, inp.mass, inp.pinned, inp.ends,
+                              inp.rest, inp.k, inp.c, inp.verts, inp.tris, self.params, stream)
+
+    def step(self, dt=None, n_substeps=None, n_steps=1):
+        cloth_step(self.h, self.inp.dt if dt is None else dt,
+                   self.inp.n_substeps if n_substeps is None else n_substeps, n_steps)
+
+    def read_state(self):
+        return cloth_read_state(self.h, self.n)
+
+    def write_state(self, x, v=None):
+        cloth_write_state(self.h, x, v)
+
+    def device_state(self):
+        return cloth_device_state(self.h)
+
+    def node_order(self):
+        return cloth_node_order(self.h, self.n)
+
+    def info(self):
+        return cloth_info(self.h)
+
+    def debug_candidates(self, points):
+        return cloth_debug_candidates(self.h, points)
+
+    def close(self):
+        if getattr(self, "h", None):
+            cloth_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,93 @@
+// Internal declarations shared by the host API (api.cpp) and the HIP kernel sources.
+// Not part of the public ABI (include/cloth.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cloth {
+
+// Static collision surface and its uniform grid, as the kernels see them.
+//   cell of a point p: c_a = clamp(floor((p_a - org_a) * inv_cell), 0, dim_a - 1) per axis,
+//   linear id (c_z * dim_y + c_y) * dim_x + c_x; refs[cell_start[c] .. cell_start[c+1]) are
+//   the triangles whose inflated box overlaps cell c, in ascending triangle id.
+struct SurfaceView {
+    int n_tris;                  // 0 = collision disabled
+    float org[3];
+    float inv_cell;
+    int dim[3];
+    float thickness;
+    float thickness2;            // thickness^2
+    const uint32_t* cell_start;  // [cells + 1]
+    const uint32_t* refs;        // [refs]
+    const float4* box_lo;        // [T] inflated box, .w unused
+    const float4* box_hi;        // [T]
+    const float4* geo;           // [T*4]: A, B-A, C-A, unit outward normal (.w unused)
+};
+
+// One cloth's node and spring arrays on the device (internal node order).
+//   State is SoA: x[k*ld + i].
+//   Incidences use a sliced CSR layout: nodes are grouped in slices of 64 (one wavefront),
+//   and the r-th incidence of node i (r < deg[i]) sits at slice_ptr[i/64] + r*64 + i%64, so
+//   the 64 lanes of a wavefront read incidence r with one coalesced access.  Per incidence:
+//   nbr (neighbour node), ik/ic/il (the spring's stiffness, damping, rest length) and
+//   inc_spring (spring id, bitwise-negated (~s) when node i is the spring's second end b).
+//   Each node's incidences are in ascending (neighbour, spring) order.
+struct ClothView {
+    int n;
+    int ld;  // SoA leading dimension (>= n)
+    const float* w;  // [n] inverse mass, 0 = pinned
+    const int* deg;        // [n]
+    const int* slice_ptr;  // [ceil(n/64) + 1]
+    const int* nbr;
+    const float* ik;
+    const float* ic;
+    const float* il;
+    const int* inc_spring;
+};
+
+struct StepParams {
+    float h;
+    float g[3];
+    float restitution;
+    int check_nan;
+    int* nan_flag;
+};
+
+// a1-a4: one substep for every node (one thread per node).
+hipError_t launch_substep(const ClothView& cv, const SurfaceView& sv, const StepParams& sp,
+                          const float* xs, const float* vs, float* xd, float* vd, int block,
+                          hipStream_t stream);
+
+// --- a3 grid build ---------------------------------------------------------------------
+// Per triangle: inflated box, geometry, and the number of grid cells its box overlaps
+// (clamped to 2^31-1); total_refs accumulates the sum (64-bit).
+hipError_t launch_tri_prep(int n_tris, const float* verts, const int* tris, float thickness,
+                           const float org[3], float inv_cell, const int dim[3], float4* box_lo,
+                           float4* box_hi, float4* geo, unsigned long long* total_refs,
+                           hipStream_t stream);
+hipError_t launch_grid_count(int n_tris, const float4* box_lo, const float4* box_hi,
+                             const float org[3], float inv_cell, const int dim[3],
+                             uint32_t* counts, hipStream_t stream);
+hipError_t launch_grid_fill(int n_tris, const float4* box_lo, const float4* box_hi,
+                            const float org[3], float inv_cell, const int dim[3],
+                            const uint32_t* cell_start, uint32_t* fill, uint32_t* refs,
+                            hipStream_t stream);
+hipError_t launch_grid_sort(int n_cells, const uint32_t* cell_start, uint32_t* refs,
+                            hipStream_t stream);
+
+// Exclusive prefix sum of in[0..n) into out[0..n] (out[n] = total) with wavefront scans.
+// tmp must hold scan_tmp_words(n) words.
+size_t scan_tmp_words(size_t n);
+hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, size_t n, uint32_t* tmp,
+                              hipStream_t stream);
+
+// Broad-phase query for arbitrary points (SoA [3][ld]): per-point candidate counts, then
+// the (point, triangle) pairs at the given offsets.
+hipError_t launch_candidates_count(int n, int ld, const float* p, const SurfaceView& sv,
+                                   uint32_t* counts, hipStream_t stream);
+hipError_t launch_candidates_write(int n, int ld, const float* p, const SurfaceView& sv,
+                                   const uint32_t* offsets, int* pairs, hipStream_t stream);
+
+}  // namespace cloth

@@ -1,0 +1,297 @@
+// a3: uniform-grid broad phase over the static surface triangles.
+//
+// Build (once per surface): per-triangle thickness-inflated boxes and geometry; per-cell
+// reference counts by integer atomics; an exclusive prefix sum of the counts built from
+// wavefront (64-lane) scans; a scatter of triangle ids into their cells; and a per-cell sort
+// so every cell lists its triangles in ascending id (the atomic scatter order is not
+// deterministic, the sorted order is).
+// Query: a point's cell and an inclusive box test against each triangle listed there; this
+// yields exactly the set an all-pairs FP32 box test gives (see cell_axis).
+#include "cloth_device.h"
+#include "cloth_internal.h"
+
+namespace cloth {
+
+namespace {
+
+struct Dims {
+    float org[3];
+    float inv_cell;
+    int dim[3];
+};
+
+__device__ __forceinline__ void cell_range(const Dims& g, const float4& lo, const float4& hi,
+                                           int c0[3], int c1[3]) {
+    c0[0] = cell_axis(lo.x, g.org[0], g.inv_cell, g.dim[0]);
+    c0[1] = cell_axis(lo.y, g.org[1], g.inv_cell, g.dim[1]);
+    c0[2] = cell_axis(lo.z, g.org[2], g.inv_cell, g.dim[2]);
+    c1[0] = cell_axis(hi.x, g.org[0], g.inv_cell, g.dim[0]);
+    c1[1] = cell_axis(hi.y, g.org[1], g.inv_cell, g.dim[1]);
+    c1[2] = cell_axis(hi.z, g.org[2], g.inv_cell, g.dim[2]);
+}
+
+Dims make_dims(const float org[3], float inv_cell, const int dim[3]) {
+    Dims g;
+    for (int a = 0; a < 3; ++a) {
+        g.org[a] = org[a];
+        g.dim[a] = dim[a];
+    }
+    g.inv_cell = inv_cell;
+    return g;
+}
+
+__global__ void k_tri_prep(int T, const float* __restrict__ verts, const int* __restrict__ tris,
+                           float th, Dims g, float4* box_lo, float4* box_hi, float4* geo,
+                           unsigned long long* total_refs) {
+#pragma clang fp contract(off)
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    const int ia = tris[3 * t], ib = tris[3 * t + 1], ic = tris[3 * t + 2];
+    const float ax = verts[3 * ia], ay = verts[3 * ia + 1], az = verts[3 * ia + 2];
+    const float bx = verts[3 * ib], by = verts[3 * ib + 1], bz = verts[3 * ib + 2];
+    const float cx = verts[3 * ic], cy = verts[3 * ic + 1], cz = verts[3 * ic + 2];
+    float4 lo, hi;
+    lo.x = fminf(fminf(ax, bx), cx) - th;
+    lo.y = fminf(fminf(ay, by), cy) - th;
+    lo.z = fminf(fminf(az, bz), cz) - th;
+    lo.w = 0.0f;
+    hi.x = fmaxf(fmaxf(ax, bx), cx) + th;
+    hi.y = fmaxf(fmaxf(ay, by), cy) + th;
+    hi.z = fmaxf(fmaxf(az, bz), cz) + th;
+    hi.w = 0.0f;
+    box_lo[t] = lo;
+    box_hi[t] = hi;
+    const float e1x = bx - ax, e1y = by - ay, e1z = bz - az;
+    const float e2x = cx - ax, e2y = cy - ay, e2z = cz - az;
+    float nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+    const float len = sqrtf(nx * nx + ny * ny + nz * nz);
+    nx /= len;
+    ny /= len;
+    nz /= len;
+    geo[4 * t] = make_float4(ax, ay, az, 0.0f);
+    geo[4 * t + 1] = make_float4(e1x, e1y, e1z, 0.0f);
+    geo[4 * t + 2] = make_float4(e2x, e2y, e2z, 0.0f);
+    geo[4 * t + 3] = make_float4(nx, ny, nz, 0.0f);
+    int c0[3], c1[3];
+    cell_range(g, lo, hi, c0, c1);
+    const unsigned long long n = (unsigned long long)(c1[0] - c0[0] + 1) *
+                                 (unsigned long long)(c1[1] - c0[1] + 1) *
+                                 (unsigned long long)(c1[2] - c0[2] + 1);
+    atomicAdd(total_refs, n);
+}
+
+__global__ void k_grid_count(int T, const float4* __restrict__ box_lo,
+                             const float4* __restrict__ box_hi, Dims g, uint32_t* counts) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    int c0[3], c1[3];
+    cell_range(g, box_lo[t], box_hi[t], c0, c1);
+    for (int z = c0[2]; z <= c1[2]; ++z)
+        for (int y = c0[1]; y <= c1[1]; ++y)
+            for (int x = c0[0]; x <= c1[0]; ++x)
+                atomicAdd(&counts[(z * g.dim[1] + y) * g.dim[0] + x], 1u);
+}
+
+__global__ void k_grid_fill(int T, const float4* __restrict__ box_lo,
+                            const float4* __restrict__ box_hi, Dims g,
+                            const uint32_t* __restrict__ cell_start, uint32_t* fill,
+                            uint32_t* refs) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    int c0[3], c1[3];
+    cell_range(g, box_lo[t], box_hi[t], c0, c1);
+    for (int z = c0[2]; z <= c1[2]; ++z)
+        for (int y = c0[1]; y <= c1[1]; ++y)
+            for (int x = c0[0]; x <= c1[0]; ++x) {
+                const int c = (z * g.dim[1] + y) * g.dim[0] + x;
+                const uint32_t slot = atomicAdd(&fill[c], 1u);
+                refs[cell_start[c] + slot] = (uint32_t)t;
+            }
+}
+
+// Insertion sort of each cell's (short) reference list.
+__global__ void k_grid_sort(int C, const uint32_t* __restrict__ cell_start, uint32_t* refs) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    const uint32_t b = cell_start[c], e = cell_start[c + 1];
+    for (uint32_t i = b + 1; i < e; ++i) {
+        const uint32_t v = refs[i];
+        uint32_t j = i;
+        while (j > b && refs[j - 1] > v) {
+            refs[j] = refs[j - 1];
+            --j;
+        }
+        refs[j] = v;
+    }
+}
+
+// ------------------------------------------------------------------ prefix sum
+constexpr int kScanThreads = 1024;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+// Inclusive scan across the 64 lanes of a wavefront.
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// Tile-local exclusive scan of m entries of in (in[n..m) read as 0); sums[tile] = tile total.
+__global__ void __launch_bounds__(kScanThreads)
+    k_scan_tile(const uint32_t* __restrict__ in, size_t n, size_t m, uint32_t* __restrict__ out,
+                uint32_t* __restrict__ sums) {
+    __shared__ uint32_t wave_tot[kScanThreads / 64];
+    const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t tot = 0;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        const size_t idx = base + q;
+        v[q] = (idx < n) ? in[idx] : 0u;
+        tot += v[q];
+    }
+    const uint32_t incl = wave_inclusive_scan(tot);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 63) wave_tot[wave] = incl;
+    __syncthreads();
+    if (wave == 0) {
+        uint32_t wt = lane < kScanThreads / 64 ? wave_tot[lane] : 0u;
+        const uint32_t wi = wave_inclusive_scan(wt);
+        if (lane < kScanThreads / 64) wave_tot[lane] = wi - wt;  // exclusive wave offsets
+        if (lane == kScanThreads / 64 - 1 && sums) sums[blockIdx.x] = wi;
+    }
+    __syncthreads();
+    uint32_t run = wave_tot[wave] + incl - tot;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        const size_t idx = base + q;
+        if (idx < m) out[idx] = run;
+        run += v[q];
+    }
+}
+
+__global__ void __launch_bounds__(kScanThreads)
+    k_scan_add(uint32_t* out, size_t m, const uint32_t* __restrict__ offs) {
+    const uint32_t add = offs[blockIdx.x];
+    const size_t base = (size_t)blockIdx.x * kScanTile;
+    for (int q = threadIdx.x; q < kScanTile; q += kScanThreads) {
+        const size_t idx = base + q;
+        if (idx < m) out[idx] += add;
+    }
+}
+
+// ------------------------------------------------------------------ point queries
+__global__ void k_cand_count(int n, int ld, const float* __restrict__ p, SurfaceView sv,
+                             uint32_t* counts) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float px = p[i], py = p[ld + i], pz = p[2 * ld + i];
+    const int c = cell_of(sv, px, py, pz);
+    uint32_t cnt = 0;
+    for (uint32_t r = sv.cell_start[c]; r < sv.cell_start[c + 1]; ++r) {
+        const uint32_t t = sv.refs[r];
+        if (in_box(sv.box_lo[t], sv.box_hi[t], px, py, pz)) ++cnt;
+    }
+    counts[i] = cnt;
+}
+
+__global__ void k_cand_write(int n, int ld, const float* __restrict__ p, SurfaceView sv,
+                             const uint32_t* __restrict__ offsets, int* pairs) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float px = p[i], py = p[ld + i], pz = p[2 * ld + i];
+    const int c = cell_of(sv, px, py, pz);
+    uint32_t o = offsets[i];
+    for (uint32_t r = sv.cell_start[c]; r < sv.cell_start[c + 1]; ++r) {
+        const uint32_t t = sv.refs[r];
+        if (in_box(sv.box_lo[t], sv.box_hi[t], px, py, pz)) {
+            pairs[2 * (size_t)o] = i;
+            pairs[2 * (size_t)o + 1] = (int)t;
+            ++o;
+        }
+    }
+}
+
+inline int blocks_for(long long n, int b) { return (int)((n + b - 1) / b); }
+
+}  // namespace
+
+hipError_t launch_tri_prep(int n_tris, const float* verts, const int* tris, float thickness,
+                           const float org[3], float inv_cell, const int dim[3], float4* box_lo,
+                           float4* box_hi, float4* geo, unsigned long long* total_refs,
+                           hipStream_t stream) {
+    if (n_tris <= 0) return hipSuccess;
+    k_tri_prep<<<blocks_for(n_tris, 256), 256, 0, stream>>>(
+        n_tris, verts, tris, thickness, make_dims(org, inv_cell, dim), box_lo, box_hi, geo,
+        total_refs);
+    return hipGetLastError();
+}
+
+hipError_t launch_grid_count(int n_tris, const float4* box_lo, const float4* box_hi,
+                             const float org[3], float inv_cell, const int dim[3],
+                             uint32_t* counts, hipStream_t stream) {
+    if (n_tris <= 0) return hipSuccess;
+    k_grid_count<<<blocks_for(n_tris, 256), 256, 0, stream>>>(
+        n_tris, box_lo, box_hi, make_dims(org, inv_cell, dim), counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_grid_fill(int n_tris, const float4* box_lo, const float4* box_hi,
+                            const float org[3], float inv_cell, const int dim[3],
+                            const uint32_t* cell_start, uint32_t* fill, uint32_t* refs,
+                            hipStream_t stream) {
+    if (n_tris <= 0) return hipSuccess;
+    k_grid_fill<<<blocks_for(n_tris, 256), 256, 0, stream>>>(
+        n_tris, box_lo, box_hi, make_dims(org, inv_cell, dim), cell_start, fill, refs);
+    return hipGetLastError();
+}
+
+hipError_t launch_grid_sort(int n_cells, const uint32_t* cell_start, uint32_t* refs,
+                            hipStream_t stream) {
+    if (n_cells <= 0) return hipSuccess;
+    k_grid_sort<<<blocks_for(n_cells, 256), 256, 0, stream>>>(n_cells, cell_start, refs);
+    return hipGetLastError();
+}
+
+size_t scan_tmp_words(size_t n) {
+    const size_t m = n + 1;
+    const size_t nb = (m + kScanTile - 1) / kScanTile;
+    if (nb <= 1) return 1;
+    return nb + (nb + 1) + scan_tmp_words(nb);
+}
+
+hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, size_t n, uint32_t* tmp,
+                              hipStream_t stream) {
+    const size_t m = n + 1;
+    const size_t nb = (m + kScanTile - 1) / kScanTile;
+    uint32_t* sums = tmp;
+    k_scan_tile<<<(unsigned)nb, kScanThreads, 0, stream>>>(in, n, m, out, sums);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nb <= 1) return e;
+    uint32_t* offs = tmp + nb;
+    e = scan_exclusive_u32(sums, offs, nb, tmp + nb + (nb + 1), stream);
+    if (e != hipSuccess) return e;
+    k_scan_add<<<(unsigned)nb, kScanThreads, 0, stream>>>(out, m, offs);
+    return hipGetLastError();
+}
+
+hipError_t launch_candidates_count(int n, int ld, const float* p, const SurfaceView& sv,
+                                   uint32_t* counts, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    k_cand_count<<<blocks_for(n, 256), 256, 0, stream>>>(n, ld, p, sv, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_candidates_write(int n, int ld, const float* p, const SurfaceView& sv,
+                                   const uint32_t* offsets, int* pairs, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    k_cand_write<<<blocks_for(n, 256), 256, 0, stream>>>(n, ld, p, sv, offsets, pairs);
+    return hipGetLastError();
+}
+
+}  // namespace cloth

@@ -1,0 +1,109 @@
+// Host-side building blocks shared by the plain, batched and rollout entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/cloth.h"
+#include "cloth_internal.h"
+
+namespace cloth {
+
+// Sets the calling thread's last-error message and returns code.
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+extern thread_local std::string g_last_error;
+
+// Device allocations owned by one handle, released together.
+struct DeviceArena {
+    std::vector<void*> ptrs;
+    DeviceArena() = default;
+    DeviceArena(const DeviceArena&) = delete;
+    DeviceArena& operator=(const DeviceArena&) = delete;
+    ~DeviceArena();
+    void release();
+    hipError_t alloc_bytes(void** p, size_t bytes);
+    template <class T>
+    hipError_t alloc(T** p, size_t n) {
+        void* q = nullptr;
+        hipError_t e = alloc_bytes(&q, n * sizeof(T));
+        *p = static_cast<T*>(q);
+        return e;
+    }
+    void free_one(void* p);
+};
+
+// The cloth_create arguments of one cloth (borrowed host pointers).
+struct ClothHostInput {
+    int nx, ny;
+    const float* x0;
+    const float* v0;
+    const float* mass;
+    const unsigned char* pinned;
+    int n_springs;
+    const int* ends;
+    const float* rest;
+    const float* k;
+    const float* c;
+    int n_verts;
+    const float* verts;
+    int n_tris;
+    const int* tris;
+};
+
+// Host copies of one cloth in internal node order (see ClothView for the layout).
+struct ClothHost {
+    int n = 0, ld = 0;
+    std::vector<int> order, slot;  // order[slot] = node id; slot[node id] = internal slot
+    std::vector<float> x, v, w;
+    std::vector<int> deg, slice_ptr, nbr, inc_spring;
+    std::vector<float> ik, ic, il;
+    void release_arrays() {
+        std::vector<float>().swap(x);
+        std::vector<float>().swap(v);
+        std::vector<float>().swap(w);
+        std::vector<int>().swap(deg);
+        std::vector<int>().swap(slice_ptr);
+        std::vector<int>().swap(nbr);
+        std::vector<int>().swap(inc_spring);
+        std::vector<float>().swap(ik);
+        std::vector<float>().swap(ic);
+        std::vector<float>().swap(il);
+    }
+};
+
+struct ClothDevice {
+    int n = 0, ld = 0;
+    float* x[2] = {nullptr, nullptr};
+    float* v[2] = {nullptr, nullptr};
+    int cur = 0;
+    float* w = nullptr;
+    int* deg = nullptr;
+    int* slice_ptr = nullptr;
+    int* nbr = nullptr;
+    float* ik = nullptr;
+    float* ic = nullptr;
+    float* il = nullptr;
+    int* inc_spring = nullptr;
+    ClothView view() const;
+};
+
+struct SurfaceDevice {
+    SurfaceView view{};
+    double cell = 0.0;
+    long long n_cells = 0, n_refs = 0;
+};
+
+std::vector<int> tile_order(int nx, int ny);
+int validate_cloth(const ClothHostInput& in);
+int validate_params(const cloth_params* p);
+void stability_bounds(const ClothHostInput& in, double* omega2, double* gamma);
+bool unstable(double omega2, double gamma, double h);
+int build_cloth_host(const ClothHostInput& in, ClothHost* out);
+int upload_cloth(const ClothHost& h, DeviceArena& arena, hipStream_t stream, ClothDevice* d);
+int build_surface(const ClothHostInput& in, const cloth_params& p, DeviceArena& arena,
+                  hipStream_t stream, SurfaceDevice* sd);
+
+}  // namespace cloth

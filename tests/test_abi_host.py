@@ -1,0 +1,144 @@
+"""The C ABI on the host: every declared symbol is exported, invalid inputs are rejected
+before any device work, and the host-only stability bound is a true upper bound."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2507_11794_amd import cloth as B
+from paper_2507_11794_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"^\s*(?:const\s+)?\w[\w\s\*]*?\b(cloth_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.load()
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_every_declared_symbol():
+    bound = {name for name, _, _ in B._SIGNATURES}
+    assert set(declared_functions()) <= bound
+
+
+def test_status_strings():
+    lib = B.load()
+    for code in range(0, -7, -1):
+        s = lib.cloth_status_str(code).decode()
+        assert s.startswith("CLOTH_")
+    assert b"unknown" in lib.cloth_status_str(42)
+
+
+def _create(inp, **over):
+    args = dict(nx=inp.nx, ny=inp.ny, x0=inp.x0, v0=inp.v0, mass=inp.mass, pinned=inp.pinned,
+                ends=inp.ends, rest=inp.rest, k=inp.k, c=inp.c, verts=inp.verts, tris=inp.tris)
+    params = over.pop("params", B.make_params(inp.gravity, inp.thickness, inp.cell_size,
+                                              inp.restitution))
+    args.update(over)
+    return B.cloth_create(params=params, **args)
+
+
+@pytest.mark.parametrize("case", [
+    "bad_end", "self_spring", "zero_rest", "neg_k", "neg_mass", "nan_x", "degenerate_tri",
+    "tri_index", "restitution", "neg_thickness", "nan_v0",
+])
+def test_create_rejects_invalid_input_before_device_work(case):
+    inp = W.small_collision_scene(n=6, freq=2)
+    ends, rest, k = inp.ends.copy(), inp.rest.copy(), inp.k.copy()
+    mass, x0, v0 = inp.mass.copy(), inp.x0.copy(), inp.v0.copy()
+    verts, tris = inp.verts.copy(), inp.tris.copy()
+    params = B.make_params(inp.gravity, inp.thickness, inp.cell_size, inp.restitution)
+    over = {}
+    if case == "bad_end":
+        ends[3, 1] = inp.n_nodes
+    elif case == "self_spring":
+        ends[3, 1] = ends[3, 0]
+    elif case == "zero_rest":
+        rest[0] = 0.0
+    elif case == "neg_k":
+        k[5] = -1.0
+    elif case == "neg_mass":
+        mass[2] = -1e-3
+    elif case == "nan_x":
+        x0[4, 1] = np.nan
+    elif case == "nan_v0":
+        v0[1, 2] = np.inf
+    elif case == "degenerate_tri":
+        tris[7] = [tris[7, 0], tris[7, 0], tris[7, 1]]
+    elif case == "tri_index":
+        tris[0, 2] = verts.shape[0]
+    elif case == "restitution":
+        params = B.make_params(inp.gravity, inp.thickness, inp.cell_size, 1.5)
+    elif case == "neg_thickness":
+        params = B.make_params(inp.gravity, -0.1, inp.cell_size, 0.5)
+    over.update(ends=ends, rest=rest, k=k, mass=mass, x0=x0, v0=v0, verts=verts, tris=tris,
+                params=params)
+    with pytest.raises(B.ClothError) as ei:
+        _create(inp, **over)
+    assert ei.value.status == B.CLOTH_EINVAL
+    assert ei.value.detail
+
+
+def test_create_rejects_null_out_and_destroy_accepts_null():
+    lib = B.load()
+    p = B.make_params()
+    assert lib.cloth_create(1, 1, None, None, None, None, 0, None, None, None, None, 0, None, 0,
+                            None, C.byref(p), None, None) == B.CLOTH_EINVAL
+    assert lib.cloth_destroy(None) == B.CLOTH_OK
+    assert lib.cloth_step(None, 0.01, 1, 1) == B.CLOTH_EINVAL
+    assert b"NULL" in lib.cloth_last_error()
+
+
+def _dense_stiffness(x, ends, k):
+    N = x.shape[0]
+    K = np.zeros((3 * N, 3 * N))
+    for (a, b), ks in zip(ends, k):
+        d = x[b] - x[a]
+        u = d / np.linalg.norm(d)
+        blk = ks * np.outer(u, u)
+        for (i, j, sg) in ((a, a, 1), (b, b, 1), (a, b, -1), (b, a, -1)):
+            K[3 * i:3 * i + 3, 3 * j:3 * j + 3] += sg * blk
+    return K
+
+
+def test_stability_bound_is_an_upper_bound_and_selects_substeps():
+    inp = W.config0(n=12)
+    w2, g = B.cloth_stability_bound(inp.x0, inp.mass, inp.pinned, inp.ends, inp.k, inp.c)
+    x = inp.x0.astype(np.float64)
+    free = np.repeat(inp.pinned == 0, 3)
+    minv = np.repeat(1.0 / inp.mass.astype(np.float64), 3)
+    K = _dense_stiffness(x, inp.ends, inp.k.astype(np.float64))
+    Cm = _dense_stiffness(x, inp.ends, inp.c.astype(np.float64))
+    A = (minv[:, None] * K)[np.ix_(free, free)]
+    lam = np.max(np.abs(np.linalg.eigvals(A)))
+    Dm = (minv[:, None] * Cm)[np.ix_(free, free)]
+    lam_c = np.max(np.abs(np.linalg.eigvals(Dm)))
+    assert lam <= w2 * (1 + 1e-9) and w2 <= 6 * lam
+    assert lam_c <= g * (1 + 1e-9)
+
+
+def test_config0_needs_substeps():
+    inp = W.config0()
+    w2, g = B.cloth_stability_bound(inp.x0, inp.mass, inp.pinned, inp.ends, inp.k, inp.c)
+    unstable = lambda h: w2 * h * h + 2 * g * h >= 4
+    assert unstable(1 / 600) and not unstable(1 / 2400)
+    assert unstable(1 / 600) == (w2 * (1 / 600) ** 2 + 2 * g / 600 >= 4)
+    for cfg in W.config3(n_cloths=8):
+        w2b, gb = B.cloth_stability_bound(cfg.x0, cfg.mass, cfg.pinned, cfg.ends, cfg.k, cfg.c)
+        assert w2b * cfg.h ** 2 + 2 * gb * cfg.h < 4
