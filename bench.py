@@ -35,7 +35,74 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--launch", default="",
+                    help="launch configuration, e.g. kernel=tile,tile=256,K=4,block=256,graph=1")
+    ap.add_argument("--sweep", action="store_true",
+                    help="time several launch configurations on the draped state and exit")
     return ap.parse_args()
+
+
+def parse_launch(text: str) -> dict:
+    from paper_2507_11794_amd import cloth
+
+    cfg = {}
+    names = {"tile": "tile_nodes", "K": "substeps_per_launch", "block": "block_threads",
+             "graph": "use_graph"}
+    for part in filter(None, text.split(",")):
+        k, v = part.split("=")
+        if k == "kernel":
+            cfg["kernel"] = cloth.CLOTH_KERNEL_TILE if v == "tile" else cloth.CLOTH_KERNEL_DIRECT
+        else:
+            cfg[names.get(k, k)] = int(v)
+    return cfg
+
+
+SWEEP = [
+    "kernel=direct,block=64,graph=0", "kernel=direct,block=256,graph=0",
+    "kernel=direct,block=256,graph=1",
+    "kernel=tile,tile=256,K=1", "kernel=tile,tile=256,K=2", "kernel=tile,tile=256,K=4",
+    "kernel=tile,tile=128,K=2", "kernel=tile,tile=128,K=4", "kernel=tile,tile=512,K=2",
+    "kernel=tile,tile=512,K=4", "kernel=tile,tile=1024,K=4", "kernel=tile,tile=256,K=4,block=128",
+    "kernel=tile,tile=64,K=1", "kernel=tile,tile=256,K=8",
+]
+
+
+def sweep(inp, frames: int = 40):
+    """Time launch configurations from the same draped state (results are bit-identical)."""
+    import torch
+
+    from paper_2507_11794_amd import cloth
+
+    stream = torch.cuda.current_stream()
+    sim = cloth.Cloth(inp, stream=stream.cuda_stream)
+    sim.step(n_steps=150)
+    x0, v0 = sim.read_state()
+    ref = None
+    for text in SWEEP:
+        sim.write_state(x0, v0)
+        try:
+            sim.set_launch(**parse_launch(text))
+        except cloth.ClothError as e:
+            print(json.dumps({"sweep": text, "error": str(e)}), flush=True)
+            continue
+        sim.step(n_steps=5)
+        sim.write_state(x0, v0)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        sim.step(n_steps=frames)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        us = ev0.elapsed_time(ev1) * 1e3 / (frames * inp.n_substeps)
+        x, _ = sim.read_state()
+        same = None if ref is None else bool(np.array_equal(x, ref))
+        ref = x if ref is None else ref
+        print(json.dumps({"sweep": text, "us_per_substep": round(us, 3),
+                          "node_updates_per_s": inp.n_nodes / (us * 1e-6),
+                          "bit_identical_to_first": same}), flush=True)
+    sim.close()
+    return 0
 
 
 def calibrate_copy(mib: int, reps: int = 5):
@@ -95,8 +162,14 @@ def main():
     if args.calibrate_copy:
         return calibrate_copy(args.calibrate_copy)
     inp = workloads.config1()
+    if args.sweep:
+        return sweep(inp)
     stream = torch.cuda.current_stream()
     sim = cloth.Cloth(inp, stream=stream.cuda_stream)
+    if args.launch:
+        sim.set_launch(**parse_launch(args.launch))
+    launch = sim.get_launch()
+    K = launch["substeps_per_launch"] if launch["kernel"] == cloth.CLOTH_KERNEL_TILE else 1
     sim.step(n_steps=args.warmup)
     torch.cuda.synchronize()
 
@@ -111,11 +184,11 @@ def main():
     t1 = time.perf_counter()
     wall = t1 - t0
     gpu_ms = ev0.elapsed_time(ev1)
-    launches = args.steps * inp.n_substeps
+    launches = args.steps * inp.n_substeps / K
     kernel_s = gpu_ms * 1e-3 / launches
     node_updates = inp.n_nodes * inp.n_substeps * args.steps
     value = node_updates / wall
-    bps = algorithmic_bytes_per_substep(inp.n_nodes, inp.n_springs)
+    bps = algorithmic_bytes_per_substep(inp.n_nodes, inp.n_springs) * K
     achieved = bps / kernel_s / 1e9
     x, v = sim.read_state()
     info = sim.info()
@@ -142,7 +215,10 @@ def main():
             "grid_refs": info["refs"],
         },
         "roofline": {
-            "kernel": "k_substep (fused forces, integration, broad and narrow phase)",
+            "kernel": ("k_tile (K substeps of fused forces, integration, broad and narrow "
+                       "phase per launch)" if K > 1 or launch["kernel"] == cloth.CLOTH_KERNEL_TILE
+                       else "k_substep (fused forces, integration, broad and narrow phase)"),
+            "launch": launch,
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

@@ -60,6 +60,31 @@ typedef struct cloth_params {
     unsigned flags;    /* CLOTH_F_* */
 } cloth_params;
 
+/* Launch configuration (cloth_set_launch).  Results are bit-identical for every valid
+ * configuration: it changes only how the substeps are scheduled on the GPU. */
+enum cloth_kernel {
+    CLOTH_KERNEL_TILE = 0,  /* temporally blocked tiles: K substeps per launch in LDS */
+    CLOTH_KERNEL_DIRECT = 1 /* one launch per substep, one thread per node */
+};
+
+/* How tiles are assigned to workgroups (tile kernel). */
+enum cloth_schedule {
+    CLOTH_SCHED_GRID = 0, /* one workgroup per tile, contiguous runs of tiles per XCD */
+    CLOTH_SCHED_LPT = 1,  /* `workgroups` persistent workgroups, tiles by decreasing cost to
+                             the least-loaded workgroup (longest processing time first) */
+    CLOTH_SCHED_RR = 2    /* `workgroups` persistent workgroups, tiles round-robin */
+};
+
+typedef struct cloth_launch {
+    int kernel;              /* enum cloth_kernel */
+    int tile_nodes;          /* tile kernel: nodes per workgroup tile, multiple of 64 (64..4096) */
+    int substeps_per_launch; /* tile kernel: substeps advanced per launch, 1..8 */
+    int block_threads;       /* threads per workgroup: 64, 128, 192 or 256 */
+    int use_graph;           /* nonzero: replay launches from a captured hipGraph */
+    int schedule;            /* tile kernel: enum cloth_schedule */
+    int workgroups;          /* persistent schedules: number of workgroups (> 0) */
+} cloth_launch;
+
 /*
  * cloth_create -- build a simulation from a cloth grid, its springs and a surface mesh.
  *   nx, ny      grid shape; N = nx*ny nodes, node id i*nx + j for row i, column j (used to
@@ -122,6 +147,17 @@ int cloth_node_order(const cloth_sim* sim, int* order);
  * out[4] = grid references, out[5..7] = grid dims (x, y, z).  [host] out[8]. */
 int cloth_info(const cloth_sim* sim, long long* out);
 
+/*
+ * cloth_set_launch / cloth_get_launch -- choose how cloth_step schedules substeps.
+ * Default: tile kernel, 256 tile nodes, 4 substeps per launch, 256 threads, graphs on,
+ * grid schedule.
+ * cloth_set_launch validates the configuration and rebuilds the tile plan if needed
+ * (synchronises the handle's stream).  Errors: CLOTH_EINVAL for an out-of-range field or a
+ * tile region that does not fit in LDS (the previous configuration stays in effect).
+ */
+int cloth_set_launch(cloth_sim* sim, const cloth_launch* cfg);
+int cloth_get_launch(const cloth_sim* sim, cloth_launch* cfg);
+
 /* cloth_destroy -- release everything; NULL is accepted. */
 int cloth_destroy(cloth_sim* sim);
 
@@ -151,6 +187,91 @@ int cloth_debug_candidates(cloth_sim* sim, int n_points, const float* points, in
 int cloth_stability_bound(int n_nodes, const float* x0, const float* mass,
                           const unsigned char* pinned, int n_springs, const int* ends,
                           const float* k, const float* c, double* omega2, double* gamma);
+
+/*
+ * cloth_rollout_forward -- differentiable rollout (the gradients of cloth_rollout_backward).
+ * Sets the handle's spring stiffness and damping to k, c, starts from the positions given at
+ * create and velocities v0, and advances n_steps frames of n_substeps substeps exactly as
+ * cloth_step does, recording positions after the frames listed in out_steps and keeping a
+ * checkpoint of (x, v) every ckpt_every frames.  The handle's state afterwards is the final
+ * rollout state.  Asynchronous on the handle's stream (reads k and c to the host first).
+ *   k_dev, c_dev [device] [S] per-spring stiffness and damping, spring-id order.
+ *   v0_dev       [device] [N*3] initial velocities, node-id order (NULL = the create-time v0).
+ *   out_steps    [host] [n_out] ascending frame counts in 0..n_steps.
+ *   x_out_dev    [device] [n_out*N*3] receives the positions at those frames.
+ * Memory: (n_steps/ckpt_every + 1) checkpoints, plus ckpt_every*n_substeps + 1 states in
+ * the backward pass, N*24 bytes each.
+ * Errors: CLOTH_EINVAL (sizes, order, non-finite or negative k / c), CLOTH_EUNSTABLE.
+ */
+int cloth_rollout_forward(cloth_sim* sim, const float* k_dev, const float* c_dev,
+                          const float* v0_dev, float dt, int n_substeps, int n_steps,
+                          int ckpt_every, const int* out_steps, int n_out, float* x_out_dev);
+
+/*
+ * cloth_rollout_backward -- gradients of a loss L(x_out) through the last forward rollout,
+ * by the exact reverse-mode adjoint of every substep with each node's contact set held at
+ * the forward pass's (the derivative of the smooth piece the rollout lies on).
+ *   gx_out_dev [device] [n_out*N*3] dL/dx_out.
+ *   gk_dev, gc_dev [device] [S] receive dL/dk, dL/dc; gv0_dev [device] [N*3] dL/dv0
+ *   (node-id order); any may be NULL.  Gradients accumulate in FP64 per spring.
+ * May be called more than once per forward pass.  Asynchronous on the handle's stream.
+ * Errors: CLOTH_ESTATE without a preceding successful cloth_rollout_forward.
+ */
+int cloth_rollout_backward(cloth_sim* sim, const float* gx_out_dev, float* gk_dev,
+                           float* gc_dev, float* gv0_dev);
+
+/*
+ * cloth_autotune -- measured search over launch configurations for this handle's workload:
+ * each candidate (kernel, tile nodes, substeps per launch, threads, schedule) is timed with
+ * HIP events over `frames` frames of dt / n_substeps from the current state, which is
+ * restored afterwards; the fastest is applied and returned in *best (may be NULL).  Every
+ * candidate gives bit-identical results.  If the environment variable CLOTH_AUTOTUNE_CACHE
+ * names a file, results are looked up there (keyed by device name and a hash of the
+ * workload's sizes) and new results appended.  Synchronises the handle's stream.
+ */
+int cloth_autotune(cloth_sim* sim, float dt, int n_substeps, int frames, cloth_launch* best);
+
+/* The arguments of cloth_create for one cloth of a batch (borrowed host pointers). */
+typedef struct cloth_sim_desc {
+    int nx, ny;
+    const float* x0;
+    const float* v0;
+    const float* mass;
+    const unsigned char* pinned;
+    int n_springs;
+    const int* ends;
+    const float* rest;
+    const float* k;
+    const float* c;
+    int n_verts;
+    const float* verts;
+    int n_tris;
+    const int* tris;
+} cloth_sim_desc;
+
+/*
+ * cloth_batch_create -- many independent cloths, each with its own surface, stepped together.
+ * descs [host] [n] as for cloth_create (node ids per cloth); p applies to every cloth (with
+ * cell_size <= 0 each cloth's grid uses 2 x its own mean surface edge).  All cloths share one
+ * node array, one tile plan and one hipGraph; tiles never cross two cloths, so cloth i evolves
+ * exactly as a cloth_create handle of its own would (bit for bit).
+ * Errors: as cloth_create, for the first invalid cloth (cloth_last_error names it).
+ */
+int cloth_batch_create(int n, const cloth_sim_desc* descs, const cloth_params* p,
+                       void* hip_stream, cloth_batch** out);
+/* cloth_batch_step -- cloth_step for every cloth of the batch (stability checked per cloth). */
+int cloth_batch_step(cloth_batch* b, float dt, int n_substeps, int n_steps);
+/* cloth_batch_read_state -- cloth i's state, AoS [N_i*3] in its own node ids. */
+int cloth_batch_read_state(const cloth_batch* b, int i, float* x_out, float* v_out);
+/* cloth_batch_set_launch / cloth_batch_get_launch / cloth_batch_autotune -- as for a handle. */
+int cloth_batch_set_launch(cloth_batch* b, const cloth_launch* cfg);
+int cloth_batch_get_launch(const cloth_batch* b, cloth_launch* cfg);
+int cloth_batch_autotune(cloth_batch* b, float dt, int n_substeps, int frames, cloth_launch* best);
+/* cloth_batch_info -- out[0] = cloths, out[1] = total nodes, out[2] = total springs,
+ * out[3] = total triangles, out[4] = tiles of the current plan, out[5] = workgroups. */
+int cloth_batch_info(const cloth_batch* b, long long* out);
+/* cloth_batch_destroy -- NULL is accepted. */
+int cloth_batch_destroy(cloth_batch* b);
 
 /* cloth_status_str -- static text for a status code. */
 const char* cloth_status_str(int status);

@@ -30,6 +30,24 @@ class ClothError(RuntimeError):
         self.detail = detail
 
 
+class cloth_launch(C.Structure):
+    _fields_ = [("kernel", C.c_int), ("tile_nodes", C.c_int), ("substeps_per_launch", C.c_int),
+                ("block_threads", C.c_int), ("use_graph", C.c_int), ("schedule", C.c_int),
+                ("workgroups", C.c_int)]
+
+
+CLOTH_KERNEL_TILE, CLOTH_KERNEL_DIRECT = 0, 1
+CLOTH_SCHED_GRID, CLOTH_SCHED_LPT, CLOTH_SCHED_RR = 0, 1, 2
+
+
+class cloth_sim_desc(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("x0", C.c_void_p), ("v0", C.c_void_p),
+                ("mass", C.c_void_p), ("pinned", C.c_void_p), ("n_springs", C.c_int),
+                ("ends", C.c_void_p), ("rest", C.c_void_p), ("k", C.c_void_p), ("c", C.c_void_p),
+                ("n_verts", C.c_int), ("verts", C.c_void_p), ("n_tris", C.c_int),
+                ("tris", C.c_void_p)]
+
+
 class cloth_params(C.Structure):
     _fields_ = [("gravity", C.c_float * 3), ("thickness", C.c_float), ("cell_size", C.c_float),
                 ("restitution", C.c_float), ("flags", C.c_uint)]
@@ -56,6 +74,21 @@ _SIGNATURES = [
     ("cloth_debug_candidates", C.c_int, [_vp, C.c_int, _fp, _ip, C.c_longlong, _llp]),
     ("cloth_stability_bound", C.c_int, [C.c_int, _fp, _fp, _u8p, C.c_int, _ip, _fp, _fp,
                                         C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    ("cloth_set_launch", C.c_int, [_vp, C.POINTER(cloth_launch)]),
+    ("cloth_get_launch", C.c_int, [_vp, C.POINTER(cloth_launch)]),
+    ("cloth_rollout_forward", C.c_int, [_vp, _vp, _vp, _vp, C.c_float, C.c_int, C.c_int, C.c_int,
+                                        _ip, C.c_int, _vp]),
+    ("cloth_rollout_backward", C.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    ("cloth_autotune", C.c_int, [_vp, C.c_float, C.c_int, C.c_int, C.POINTER(cloth_launch)]),
+    ("cloth_batch_create", C.c_int, [C.c_int, C.POINTER(cloth_sim_desc), C.POINTER(cloth_params),
+                                     _vp, C.POINTER(_vp)]),
+    ("cloth_batch_step", C.c_int, [_vp, C.c_float, C.c_int, C.c_int]),
+    ("cloth_batch_read_state", C.c_int, [_vp, C.c_int, _fp, _fp]),
+    ("cloth_batch_set_launch", C.c_int, [_vp, C.POINTER(cloth_launch)]),
+    ("cloth_batch_get_launch", C.c_int, [_vp, C.POINTER(cloth_launch)]),
+    ("cloth_batch_autotune", C.c_int, [_vp, C.c_float, C.c_int, C.c_int, C.POINTER(cloth_launch)]),
+    ("cloth_batch_info", C.c_int, [_vp, _llp]),
+    ("cloth_batch_destroy", C.c_int, [_vp]),
     ("cloth_status_str", C.c_char_p, [C.c_int]),
     ("cloth_last_error", C.c_char_p, []),
 ]
@@ -196,6 +229,47 @@ def cloth_debug_candidates(h, points):
     return pairs[:n.value].copy()
 
 
+def make_launch(kernel=CLOTH_KERNEL_TILE, tile_nodes=256, substeps_per_launch=4,
+                block_threads=256, use_graph=1, schedule=CLOTH_SCHED_GRID, workgroups=0):
+    return cloth_launch(int(kernel), int(tile_nodes), int(substeps_per_launch),
+                        int(block_threads), int(use_graph), int(schedule), int(workgroups))
+
+
+def launch_dict(cfg: cloth_launch) -> dict:
+    return {f: getattr(cfg, f) for f, _ in cloth_launch._fields_}
+
+
+def cloth_set_launch(h, **kw):
+    cfg = make_launch(**kw)
+    _check(load().cloth_set_launch(_vp(h), C.byref(cfg)))
+
+
+def cloth_get_launch(h) -> dict:
+    cfg = cloth_launch()
+    _check(load().cloth_get_launch(_vp(h), C.byref(cfg)))
+    return launch_dict(cfg)
+
+
+def cloth_autotune(h, dt, n_substeps, frames) -> dict:
+    cfg = cloth_launch()
+    _check(load().cloth_autotune(_vp(h), float(dt), int(n_substeps), int(frames), C.byref(cfg)))
+    return launch_dict(cfg)
+
+
+def cloth_rollout_forward(h, k_ptr, c_ptr, v0_ptr, dt, n_substeps, n_steps, ckpt_every,
+                          out_steps, x_out_ptr):
+    """Device pointers as ints (0 = NULL); out_steps is a host sequence of frame counts."""
+    steps = np.ascontiguousarray(out_steps, dtype=np.int32)
+    _check(load().cloth_rollout_forward(_vp(h), _vp(k_ptr), _vp(c_ptr), _vp(v0_ptr), float(dt),
+                                        int(n_substeps), int(n_steps), int(ckpt_every),
+                                        _ptr(steps, _ip), int(steps.shape[0]), _vp(x_out_ptr)))
+
+
+def cloth_rollout_backward(h, gx_out_ptr, gk_ptr, gc_ptr, gv0_ptr):
+    _check(load().cloth_rollout_backward(_vp(h), _vp(gx_out_ptr), _vp(gk_ptr), _vp(gc_ptr),
+                                         _vp(gv0_ptr)))
+
+
 def cloth_stability_bound(x0, mass, pinned, ends, k, c):
     """Host-only (omega2, gamma) bounds; see include/cloth.h."""
     lib = load()
@@ -243,12 +317,118 @@ class Cloth:
     def info(self):
         return cloth_info(self.h)
 
+    def set_launch(self, **kw):
+        cfg = dict(self.get_launch())
+        cfg.update(kw)
+        cloth_set_launch(self.h, **cfg)
+
+    def get_launch(self):
+        return cloth_get_launch(self.h)
+
     def debug_candidates(self, points):
         return cloth_debug_candidates(self.h, points)
+
+    def autotune(self, frames=10, dt=None, n_substeps=None):
+        return cloth_autotune(self.h, self.inp.dt if dt is None else dt,
+                              self.inp.n_substeps if n_substeps is None else n_substeps, frames)
 
     def close(self):
         if getattr(self, "h", None):
             cloth_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ClothBatch:
+    """Many independent cloths (ClothInputs-like objects) stepped together.
+
+    Every cloth shares dt, n_substeps, gravity, thickness and restitution (taken from the
+    first); each keeps its own springs, surface and (with cell_size <= 0 in the shared
+    parameters) its own grid cell."""
+
+    def __init__(self, inputs, flags=0, stream=None, cell_size=0.0):
+        lib = load()
+        self.inputs = list(inputs)
+        first = self.inputs[0]
+        self.params = make_params(first.gravity, first.thickness, cell_size, first.restitution,
+                                  flags)
+        self._keep = []
+        descs = (cloth_sim_desc * len(self.inputs))()
+        for d, inp in zip(descs, self.inputs):
+            arrs = dict(
+                x0=_f32(inp.x0), v0=_f32(inp.v0), mass=_f32(inp.mass),
+                pinned=np.ascontiguousarray(inp.pinned, dtype=np.uint8),
+                ends=np.ascontiguousarray(inp.ends, dtype=np.int32), rest=_f32(inp.rest),
+                k=_f32(inp.k), c=_f32(inp.c), verts=_f32(inp.verts),
+                tris=np.ascontiguousarray(inp.tris, dtype=np.int32))
+            self._keep.append(arrs)
+            d.nx, d.ny = int(inp.nx), int(inp.ny)
+            for f in ("x0", "v0", "mass", "pinned", "ends", "rest", "k", "c", "verts", "tris"):
+                setattr(d, f, arrs[f].ctypes.data)
+            d.n_springs = int(arrs["ends"].shape[0])
+            d.n_verts = int(arrs["verts"].reshape(-1, 3).shape[0])
+            d.n_tris = int(arrs["tris"].reshape(-1, 3).shape[0])
+        out = _vp()
+        st = lib.cloth_batch_create(len(self.inputs), descs, C.byref(self.params),
+                                    _vp(default_stream() if stream is None else int(stream)),
+                                    C.byref(out))
+        self._keep = None
+        _check(st)
+        self.h = out.value
+
+    def step(self, n_steps=1, dt=None, n_substeps=None):
+        first = self.inputs[0]
+        _check(load().cloth_batch_step(_vp(self.h), float(first.dt if dt is None else dt),
+                                       int(first.n_substeps if n_substeps is None else n_substeps),
+                                       int(n_steps)))
+
+    def read_state(self, i):
+        n = int(self.inputs[i].nx * self.inputs[i].ny)
+        x = np.zeros((n, 3), dtype=np.float32)
+        v = np.zeros((n, 3), dtype=np.float32)
+        _check(load().cloth_batch_read_state(_vp(self.h), int(i), _ptr(x, _fp), _ptr(v, _fp)))
+        return x, v
+
+    def set_launch(self, **kw):
+        cfg = self.get_launch()
+        cfg.update(kw)
+        c = make_launch(**cfg)
+        _check(load().cloth_batch_set_launch(_vp(self.h), C.byref(c)))
+
+    def get_launch(self):
+        cfg = cloth_launch()
+        _check(load().cloth_batch_get_launch(_vp(self.h), C.byref(cfg)))
+        return launch_dict(cfg)
+
+    def autotune(self, frames=3, dt=None, n_substeps=None):
+        first = self.inputs[0]
+        cfg = cloth_launch()
+        _check(load().cloth_batch_autotune(
+            _vp(self.h), float(first.dt if dt is None else dt),
+            int(first.n_substeps if n_substeps is None else n_substeps), int(frames),
+            C.byref(cfg)))
+        return launch_dict(cfg)
+
+    def info(self):
+        out = np.zeros(6, dtype=np.int64)
+        _check(load().cloth_batch_info(_vp(self.h), _ptr(out, _llp)))
+        keys = ("cloths", "nodes", "springs", "tris", "tiles", "workgroups")
+        return dict(zip(keys, (int(x) for x in out)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(load().cloth_batch_destroy(_vp(self.h)))
             self.h = None
 
     def __enter__(self):

@@ -1,0 +1,253 @@
+// a6: reverse-mode adjoint of one substep, with the contact set held at the one the forward
+// pass found, plus the layout kernels of the differentiable rollout.
+//
+// Forward substep (per node i, node-local frame with i as Alg. 1's indexA):
+//   F_i = sum_j f(d = x_j - x_i, dv = v_j - v_i),  f = phi u,  u = d/|d|,
+//   phi = k (|d| - L0) + c dv.u
+//   v* = v + h (w F + g),  x* = x + h v*        (pinned: v* = 0, x* = x)
+//   contact set C: x' = x* + mean_t (th - (x* - A_t).n_t) n_t,  v' = -r v*
+// Given the adjoints (xb', vb') of (x', v'):
+//   k_adj_node:    xbs = (I - mean_t n_t n_t^T) xb',  vbs = -r vb'  (identity without contact)
+//                  vtot = vbs + h xbs;  partial xb = xbs, vb = vtot;  Fb = h w vtot
+//                  (pinned: xb = xb', vb = 0, Fb = 0)
+//   k_adj_springs: with lambda = Fb_i - Fb_j for each incident spring,
+//                  xb_i -= df/dd^T lambda = k u (u.l) + (phi/|d|)(l - u (u.l))
+//                                           + (c/|d|)(dv - u (dv.u)) (u.l)
+//                  vb_i -= df/ddv^T lambda = c u (u.l)
+//                  and the spring's first end adds (|d| - L0)(u.l) to dL/dk and
+//                  (dv.u)(u.l) to dL/dc (FP64 accumulators, one owner per spring: no atomics).
+#include "cloth_device.h"
+#include "cloth_internal.h"
+
+namespace cloth {
+
+namespace {
+
+__global__ void __launch_bounds__(256)
+    k_adj_node(const ClothView cv, const SurfaceView sv, const StepParams sp,
+               const float* __restrict__ xs, const float* __restrict__ vs,
+               const float* __restrict__ xb_out, const float* __restrict__ vb_out,
+               float* __restrict__ fb, float* __restrict__ xb_part, float* __restrict__ vb_part) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cv.n) return;
+    const int ld = cv.ld;
+    const float xi = xs[i], yi = xs[ld + i], zi = xs[2 * ld + i];
+    const float vxi = vs[i], vyi = vs[ld + i], vzi = vs[2 * ld + i];
+    const float w = cv.w[i];
+    const float bx = xb_out[i], by = xb_out[ld + i], bz = xb_out[2 * ld + i];
+    const float cx = vb_out[i], cy = vb_out[ld + i], cz = vb_out[2 * ld + i];
+    if (w == 0.0f) {
+        xb_part[i] = bx;
+        xb_part[ld + i] = by;
+        xb_part[2 * ld + i] = bz;
+        vb_part[i] = vb_part[ld + i] = vb_part[2 * ld + i] = 0.0f;
+        fb[i] = fb[ld + i] = fb[2 * ld + i] = 0.0f;
+        return;
+    }
+    // recompute the forward prediction exactly as the forward kernels do
+    float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+    const int deg = cv.deg[i];
+    const int base = cv.slice_ptr[i >> 6] + (i & 63);
+    for (int r = 0; r < deg; ++r) {
+        const int q = base + r * 64;
+        const int j = cv.nbr[q];
+        spring_force(xs[j] - xi, xs[ld + j] - yi, xs[2 * ld + j] - zi, vs[j] - vxi,
+                     vs[ld + j] - vyi, vs[2 * ld + j] - vzi, cv.ik[q], cv.ic[q], cv.il[q], fx, fy,
+                     fz);
+    }
+    float px, py, pz, qx, qy, qz;
+    integrate(w, sp.h, sp.g, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz, px, py, pz, qx, qy, qz);
+    float sx = bx, sy = by, sz = bz, tx = cx, ty = cy, tz = cz;
+    if (sv.n_tris > 0) {
+        float ax = 0.0f, ay = 0.0f, az = 0.0f;
+        const int cnt = contacts_visit(sv, px, py, pz, [&](const float4& n, float) {
+            const float proj = n.x * bx + n.y * by + n.z * bz;
+            ax += proj * n.x;
+            ay += proj * n.y;
+            az += proj * n.z;
+        });
+        if (cnt > 0) {
+            const float inv = 1.0f / (float)cnt;
+            sx = bx - ax * inv;
+            sy = by - ay * inv;
+            sz = bz - az * inv;
+            tx = -sp.restitution * cx;
+            ty = -sp.restitution * cy;
+            tz = -sp.restitution * cz;
+        }
+    }
+    const float h = sp.h;
+    const float ux = tx + h * sx, uy = ty + h * sy, uz = tz + h * sz;
+    xb_part[i] = sx;
+    xb_part[ld + i] = sy;
+    xb_part[2 * ld + i] = sz;
+    vb_part[i] = ux;
+    vb_part[ld + i] = uy;
+    vb_part[2 * ld + i] = uz;
+    fb[i] = h * w * ux;
+    fb[ld + i] = h * w * uy;
+    fb[2 * ld + i] = h * w * uz;
+}
+
+__global__ void __launch_bounds__(256)
+    k_adj_springs(const ClothView cv, const float* __restrict__ xs, const float* __restrict__ vs,
+                  const float* __restrict__ fb, const float* __restrict__ xb_part,
+                  const float* __restrict__ vb_part, float* __restrict__ xb_in,
+                  float* __restrict__ vb_in, double* __restrict__ kb, double* __restrict__ cb) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cv.n) return;
+    const int ld = cv.ld;
+    const float xi = xs[i], yi = xs[ld + i], zi = xs[2 * ld + i];
+    const float vxi = vs[i], vyi = vs[ld + i], vzi = vs[2 * ld + i];
+    const float fbx = fb[i], fby = fb[ld + i], fbz = fb[2 * ld + i];
+    float gx = xb_part[i], gy = xb_part[ld + i], gz = xb_part[2 * ld + i];
+    float hx = vb_part[i], hy = vb_part[ld + i], hz = vb_part[2 * ld + i];
+    const int deg = cv.deg[i];
+    const int base = cv.slice_ptr[i >> 6] + (i & 63);
+    for (int r = 0; r < deg; ++r) {
+        const int q = base + r * 64;
+        const int j = cv.nbr[q];
+        const float k = cv.ik[q], c = cv.ic[q], L0 = cv.il[q];
+        const float dx = xs[j] - xi, dy = xs[ld + j] - yi, dz = xs[2 * ld + j] - zi;
+        const float ex = vs[j] - vxi, ey = vs[ld + j] - vyi, ez = vs[2 * ld + j] - vzi;
+        const float lx = fbx - fb[j], ly = fby - fb[ld + j], lz = fbz - fb[2 * ld + j];
+        const float l2 = dx * dx + dy * dy + dz * dz;
+        const float il = __builtin_amdgcn_rsqf(l2);
+        const float len = l2 * il;
+        const float ux = dx * il, uy = dy * il, uz = dz * il;
+        const float dvu = ex * ux + ey * uy + ez * uz;
+        const float phi = k * (len - L0) + c * dvu;
+        const float ul = ux * lx + uy * ly + uz * lz;
+        const float a = phi * il, b = c * il * ul, kk = k * ul;
+        const float dbx = a * (lx - ux * ul) + kk * ux + b * (ex - ux * dvu);
+        const float dby = a * (ly - uy * ul) + kk * uy + b * (ey - uy * dvu);
+        const float dbz = a * (lz - uz * ul) + kk * uz + b * (ez - uz * dvu);
+        const float cu = c * ul;
+        gx -= dbx;
+        gy -= dby;
+        gz -= dbz;
+        hx -= cu * ux;
+        hy -= cu * uy;
+        hz -= cu * uz;
+        const int code = cv.inc_spring[q];
+        if (code >= 0) {  // node i is the spring's first end: it owns the spring's gradients
+            kb[code] += (double)((len - L0) * ul);
+            cb[code] += (double)(dvu * ul);
+        }
+    }
+    xb_in[i] = gx;
+    xb_in[ld + i] = gy;
+    xb_in[2 * ld + i] = gz;
+    vb_in[i] = hx;
+    vb_in[ld + i] = hy;
+    vb_in[2 * ld + i] = hz;
+}
+
+// out_soa[k*ld + slot[id]] (+)= in_aos[3*id + k]
+__global__ void k_import(int n, int ld, const int* __restrict__ slot, const float* __restrict__ aos,
+                         float* __restrict__ soa, int accumulate) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    const int p = slot[id];
+    for (int q = 0; q < 3; ++q) {
+        const float v = aos[3 * (size_t)id + q];
+        soa[(size_t)q * ld + p] = accumulate ? soa[(size_t)q * ld + p] + v : v;
+    }
+}
+
+// out_aos[3*id + k] = in_soa[k*ld + slot[id]]
+__global__ void k_export(int n, int ld, const int* __restrict__ slot, const float* __restrict__ soa,
+                         float* __restrict__ aos) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    const int p = slot[id];
+    for (int q = 0; q < 3; ++q) aos[3 * (size_t)id + q] = soa[(size_t)q * ld + p];
+}
+
+// Per-incidence copies of k and c from per-spring arrays (code = spring id, ~id for the
+// second end, < -(1<<30) never occurs; padding entries hold code 0 and are never read).
+__global__ void k_set_params(size_t m, const int* __restrict__ code, const float* __restrict__ k,
+                             const float* __restrict__ c, float* __restrict__ ik,
+                             float* __restrict__ ic) {
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    const int s0 = code[q];
+    const int s = s0 >= 0 ? s0 : ~s0;
+    ik[q] = k[s];
+    ic[q] = c[s];
+}
+
+__global__ void k_set_params_plan(size_t m, const int* __restrict__ sid, const float* __restrict__ k,
+                                  const float* __restrict__ c, float4* __restrict__ inc) {
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    const int s = sid[q];
+    if (s < 0) return;
+    inc[q].x = k[s];
+    inc[q].y = c[s];
+}
+
+__global__ void k_d2f(size_t n, const double* __restrict__ a, float* __restrict__ b) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+inline unsigned blocks(size_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+hipError_t launch_adj_node(const ClothView& cv, const SurfaceView& sv, const StepParams& sp,
+                           const float* xs, const float* vs, const float* xb_out,
+                           const float* vb_out, float* fb, float* xb_part, float* vb_part,
+                           hipStream_t st) {
+    if (cv.n <= 0) return hipSuccess;
+    k_adj_node<<<blocks(cv.n, 256), 256, 0, st>>>(cv, sv, sp, xs, vs, xb_out, vb_out, fb, xb_part,
+                                                  vb_part);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_springs(const ClothView& cv, const float* xs, const float* vs,
+                              const float* fb, const float* xb_part, const float* vb_part,
+                              float* xb_in, float* vb_in, double* kb, double* cb,
+                              hipStream_t st) {
+    if (cv.n <= 0) return hipSuccess;
+    k_adj_springs<<<blocks(cv.n, 256), 256, 0, st>>>(cv, xs, vs, fb, xb_part, vb_part, xb_in,
+                                                     vb_in, kb, cb);
+    return hipGetLastError();
+}
+
+hipError_t launch_import(int n, int ld, const int* slot, const float* aos, float* soa,
+                         int accumulate, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_import<<<blocks(n, 256), 256, 0, st>>>(n, ld, slot, aos, soa, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_export(int n, int ld, const int* slot, const float* soa, float* aos,
+                         hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_export<<<blocks(n, 256), 256, 0, st>>>(n, ld, slot, soa, aos);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_params(size_t m, const int* code, const float* k, const float* c, float* ik,
+                             float* ic, hipStream_t st) {
+    if (m == 0) return hipSuccess;
+    k_set_params<<<blocks(m, 256), 256, 0, st>>>(m, code, k, c, ik, ic);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_params_plan(size_t m, const int* sid, const float* k, const float* c,
+                                  float4* inc, hipStream_t st) {
+    if (m == 0) return hipSuccess;
+    k_set_params_plan<<<blocks(m, 256), 256, 0, st>>>(m, sid, k, c, inc);
+    return hipGetLastError();
+}
+
+hipError_t launch_d2f(size_t n, const double* a, float* b, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    k_d2f<<<blocks(n, 256), 256, 0, st>>>(n, a, b);
+    return hipGetLastError();
+}
+
+}  // namespace cloth

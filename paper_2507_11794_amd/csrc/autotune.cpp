@@ -1,0 +1,195 @@
+// Autotuner: a measured search over launch configurations (kernel, tile nodes, substeps per
+// launch, threads per workgroup, tile schedule).  Every configuration gives bit-identical
+// results, so the choice only affects speed.  Results can be cached in the file named by
+// CLOTH_AUTOTUNE_CACHE, keyed by the device and a hash of the workload's sizes.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "sim.h"
+
+namespace cloth {
+
+namespace {
+
+uint64_t fnv(uint64_t h, uint64_t v) {
+    for (int b = 0; b < 8; ++b) {
+        h ^= (v >> (8 * b)) & 0xff;
+        h *= 1099511628211ULL;
+    }
+    return h;
+}
+
+uint64_t workload_hash(const cloth_sim* s, float h, int n_substeps) {
+    uint64_t x = 1469598103934665603ULL;
+    unsigned hb;
+    std::memcpy(&hb, &h, 4);
+    x = fnv(x, (uint64_t)s->n_nodes);
+    x = fnv(x, (uint64_t)s->n_springs);
+    x = fnv(x, (uint64_t)s->groups.size());
+    x = fnv(x, hb);
+    x = fnv(x, (uint64_t)n_substeps);
+    for (size_t g = 0; g < s->groups.size(); ++g) {
+        x = fnv(x, (uint64_t)s->groups[g].n);
+        x = fnv(x, (uint64_t)s->surfs[g].view.n_tris);
+        x = fnv(x, (uint64_t)s->surfs[g].n_refs);
+    }
+    return x;
+}
+
+std::string device_key() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return "unknown";
+    std::string k = prop.gcnArchName;
+    for (auto& ch : k)
+        if (ch == ' ') ch = '_';
+    return k + "_cu" + std::to_string(prop.multiProcessorCount);
+}
+
+bool cache_lookup(const std::string& key, cloth_launch* out) {
+    const char* path = std::getenv("CLOTH_AUTOTUNE_CACHE");
+    if (!path || !*path) return false;
+    std::ifstream f(path);
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string k;
+        cloth_launch c{};
+        if (is >> k >> c.kernel >> c.tile_nodes >> c.substeps_per_launch >> c.block_threads >>
+            c.use_graph >> c.schedule >> c.workgroups) {
+            if (k == key && check_launch(c) == CLOTH_OK) {
+                *out = c;
+                found = true;  // the last entry for a key wins
+            }
+        }
+    }
+    return found;
+}
+
+void cache_store(const std::string& key, const cloth_launch& c) {
+    const char* path = std::getenv("CLOTH_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    std::ofstream f(path, std::ios::app);
+    f << key << ' ' << c.kernel << ' ' << c.tile_nodes << ' ' << c.substeps_per_launch << ' '
+      << c.block_threads << ' ' << c.use_graph << ' ' << c.schedule << ' ' << c.workgroups << '\n';
+}
+
+std::vector<cloth_launch> candidates(int cus) {
+    std::vector<cloth_launch> v;
+    v.push_back({CLOTH_KERNEL_DIRECT, 256, 1, 256, 1, CLOTH_SCHED_GRID, 0});
+    const int tk[][2] = {{256, 1}, {128, 2}, {256, 2}, {512, 2}, {128, 4},
+                         {256, 4}, {512, 4}, {1024, 4}, {256, 8}};
+    for (const auto& t : tk) v.push_back({CLOTH_KERNEL_TILE, t[0], t[1], 256, 1, CLOTH_SCHED_GRID, 0});
+    v.push_back({CLOTH_KERNEL_TILE, 256, 4, 128, 1, CLOTH_SCHED_GRID, 0});
+    for (int m : {2, 4}) {
+        v.push_back({CLOTH_KERNEL_TILE, 256, 4, 256, 1, CLOTH_SCHED_LPT, m * cus});
+        v.push_back({CLOTH_KERNEL_TILE, 256, 4, 256, 1, CLOTH_SCHED_RR, m * cus});
+    }
+    return v;
+}
+
+}  // namespace
+
+int autotune_sim(cloth_sim* s, float dt, int n_substeps, int frames, cloth_launch* best) {
+    if (!(dt > 0.0f) || n_substeps < 1 || frames < 1)
+        return fail(CLOTH_EINVAL, "need dt > 0, n_substeps >= 1, frames >= 1");
+    const float h = dt / (float)n_substeps;
+    char hex[32];
+    std::snprintf(hex, sizeof(hex), "%016llx", (unsigned long long)workload_hash(s, h, n_substeps));
+    const std::string key = device_key() + ":" + hex;
+    cloth_launch chosen;
+    if (cache_lookup(key, &chosen)) {
+        int st = set_launch(s, chosen);
+        if (st == CLOTH_OK) {
+            if (best) *best = chosen;
+            return CLOTH_OK;
+        }
+    }
+    int cus = 256;
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    }
+    const size_t ld = (size_t)s->dev.ld;
+    DeviceArena tmp;
+    float* save;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e;
+    if ((e = tmp.alloc(&save, 6 * ld)) || (e = hipEventCreate(&e0)) || (e = hipEventCreate(&e1))) {
+        if (e0) (void)hipEventDestroy(e0);
+        return hip_fail(e, "autotune setup");
+    }
+    auto copy_state = [&](bool to_save) -> hipError_t {
+        float* X = s->dev.x[s->dev.cur];
+        float* V = s->dev.v[s->dev.cur];
+        hipError_t r;
+        if (to_save) {
+            if ((r = hipMemcpyAsync(save, X, 12 * ld, hipMemcpyDeviceToDevice, s->stream))) return r;
+            return hipMemcpyAsync(save + 3 * ld, V, 12 * ld, hipMemcpyDeviceToDevice, s->stream);
+        }
+        if ((r = hipMemcpyAsync(X, save, 12 * ld, hipMemcpyDeviceToDevice, s->stream))) return r;
+        return hipMemcpyAsync(V, save + 3 * ld, 12 * ld, hipMemcpyDeviceToDevice, s->stream);
+    };
+    const cloth_launch original = s->launch;
+    int st = CLOTH_OK;
+    float best_ms = 0.0f;
+    bool have = false;
+    if ((e = copy_state(true))) st = hip_fail(e, "autotune save");
+    for (const cloth_launch& c : candidates(cus)) {
+        if (st != CLOTH_OK) break;
+        if (set_launch(s, c) != CLOTH_OK) continue;  // e.g. a region too large for LDS
+        float ms = 0.0f;
+        if ((e = copy_state(false))) { st = hip_fail(e, "autotune restore"); break; }
+        if (run_substeps(s, h, (long long)n_substeps) != CLOTH_OK) continue;  // builds graphs
+        if ((e = copy_state(false)) || (e = hipEventRecord(e0, s->stream))) {
+            st = hip_fail(e, "autotune");
+            break;
+        }
+        if (run_substeps(s, h, (long long)frames * n_substeps) != CLOTH_OK) continue;
+        if ((e = hipEventRecord(e1, s->stream)) || (e = hipEventSynchronize(e1)) ||
+            (e = hipEventElapsedTime(&ms, e0, e1))) {
+            st = hip_fail(e, "autotune timing");
+            break;
+        }
+        if (!have || ms < best_ms) {
+            best_ms = ms;
+            chosen = s->launch;
+            have = true;
+        }
+    }
+    if (st == CLOTH_OK && (e = copy_state(false))) st = hip_fail(e, "autotune restore");
+    if (st == CLOTH_OK && (e = hipStreamSynchronize(s->stream))) st = hip_fail(e, "autotune");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != CLOTH_OK) {
+        (void)set_launch(s, original);
+        return st;
+    }
+    if (!have) {
+        (void)set_launch(s, original);
+        return fail(CLOTH_EDEVICE, "no launch configuration could run");
+    }
+    if ((st = set_launch(s, chosen)) != CLOTH_OK) return st;
+    cache_store(key, chosen);
+    if (best) *best = chosen;
+    return CLOTH_OK;
+}
+
+}  // namespace cloth
+
+extern "C" int cloth_autotune(cloth_sim* sim, float dt, int n_substeps, int frames,
+                              cloth_launch* best) {
+    if (!sim) return cloth::fail(CLOTH_EINVAL, "NULL handle");
+    return cloth::autotune_sim(sim, dt, n_substeps, frames, best);
+}

@@ -55,10 +55,79 @@ struct StepParams {
     int* nan_flag;
 };
 
-// a1-a4: one substep for every node (one thread per node).
+// Temporally blocked tiles.  The internal node order is cut into tiles of consecutive
+// slots; one workgroup owns a tile and the region of nodes within K spring hops of it,
+// ordered by hop level (level 0 = the tile, ascending slot within a level).  level[k] counts
+// the nodes within k hops, so substep s of a launch recomputes the prefix [0, level[K - s])
+// in LDS and only the tile itself is written back after K substeps.  Computed nodes
+// (u < level[K - 1]) carry their incidences in region-local form: inc[inc_off + r * inc_pad
+// + u] = (k, c, rest length, local neighbour index as int bits), in the same order as the
+// node's global incidence list, so the arithmetic matches the one-substep kernel bit for bit.
+constexpr int kMaxTileK = 8;
+
+struct TileMeta {
+    int group;       // cloth of a batch (index into TileView::svs)
+    int region_off;  // into region_slot
+    int region_n;    // = level[K_plan]
+    int comp_off;    // into comp_deg
+    int inc_off;     // float4 offset into inc
+    int inc_pad;     // multiple of 64, >= level[K_plan - 1]
+    int level[kMaxTileK + 1];
+};
+
+struct TileView {
+    int n_tiles;
+    int rmax;  // largest region (LDS sizing)
+    int ld;    // global SoA leading dimension
+    int n_workgroups;      // grid size of the schedule
+    const int* item_ptr;   // [n_workgroups + 1]: workgroup b runs items[item_ptr[b]..item_ptr[b+1])
+    const int* items;      // tile ids
+    const SurfaceView* svs;  // [groups] surface of each cloth
+    const TileMeta* meta;
+    const int* region_slot;
+    const int* comp_deg;
+    const float4* inc;
+    const float* w;  // inverse mass by global slot
+};
+
+// K substeps (K <= the plan's K) of every tile; reads (xs, vs), writes (xd, vd).
+// collide = 0 skips the collision stage for every cloth (no cloth has a surface).
+hipError_t launch_tiles(const TileView& tv, int K, int collide, const StepParams& sp,
+                        const float* xs, const float* vs, float* xd, float* vd, int block,
+                        hipStream_t stream);
+size_t tile_lds_bytes(int rmax);
+// Raise the tile kernels' dynamic LDS limit when a plan needs more than 64 KiB.
+hipError_t prepare_tile_kernels(size_t lds_bytes);
+
+// a1-a4: one substep for every node (one thread per node).  With node_group non-NULL the
+// node's surface is svs[node_group[i]] (a batch of cloths); otherwise sv.
 hipError_t launch_substep(const ClothView& cv, const SurfaceView& sv, const StepParams& sp,
                           const float* xs, const float* vs, float* xd, float* vd, int block,
-                          hipStream_t stream);
+                          hipStream_t stream, const SurfaceView* svs = nullptr,
+                          const int* node_group = nullptr);
+
+// --- a6 adjoint ----------------------------------------------------------------------------
+// Response and integration transpose of one substep at state (xs, vs): partial adjoints and
+// the force adjoint fb = h w vtot (see adjoint.hip).
+hipError_t launch_adj_node(const ClothView& cv, const SurfaceView& sv, const StepParams& sp,
+                           const float* xs, const float* vs, const float* xb_out,
+                           const float* vb_out, float* fb, float* xb_part, float* vb_part,
+                           hipStream_t st);
+// Spring-force transpose: xb_in / vb_in = partial + spring terms; adds dL/dk, dL/dc.
+hipError_t launch_adj_springs(const ClothView& cv, const float* xs, const float* vs,
+                              const float* fb, const float* xb_part, const float* vb_part,
+                              float* xb_in, float* vb_in, double* kb, double* cb, hipStream_t st);
+// Node-id AoS [n][3] <-> internal SoA [3][ld] through slot[id].
+hipError_t launch_import(int n, int ld, const int* slot, const float* aos, float* soa,
+                         int accumulate, hipStream_t st);
+hipError_t launch_export(int n, int ld, const int* slot, const float* soa, float* aos,
+                         hipStream_t st);
+// Per-incidence k, c from per-spring arrays (sliced CSR and tile plan forms).
+hipError_t launch_set_params(size_t m, const int* code, const float* k, const float* c, float* ik,
+                             float* ic, hipStream_t st);
+hipError_t launch_set_params_plan(size_t m, const int* sid, const float* k, const float* c,
+                                  float4* inc, hipStream_t st);
+hipError_t launch_d2f(size_t n, const double* a, float* b, hipStream_t st);
 
 // --- a3 grid build ---------------------------------------------------------------------
 // Per triangle: inflated box, geometry, and the number of grid cells its box overlaps

@@ -6,7 +6,7 @@
 // so every cell lists its triangles in ascending id (the atomic scatter order is not
 // deterministic, the sorted order is).
 // Query: a point's cell and an inclusive box test against each triangle listed there; this
-// yields exactly the set an all-pairs FP32 box test gives (see cell_axis).
+// yields exactly the set an all-pairs FP32 box test gives (see cell_coord_f and cell_of).
 #include "cloth_device.h"
 #include "cloth_internal.h"
 
@@ -193,6 +193,10 @@ __global__ void k_cand_count(int n, int ld, const float* __restrict__ p, Surface
     const float px = p[i], py = p[ld + i], pz = p[2 * ld + i];
     const int c = cell_of(sv, px, py, pz);
     uint32_t cnt = 0;
+    if (c < 0) {  // outside the grid: no inflated box holds the point
+        counts[i] = 0;
+        return;
+    }
     for (uint32_t r = sv.cell_start[c]; r < sv.cell_start[c + 1]; ++r) {
         const uint32_t t = sv.refs[r];
         if (in_box(sv.box_lo[t], sv.box_hi[t], px, py, pz)) ++cnt;
@@ -206,6 +210,7 @@ __global__ void k_cand_write(int n, int ld, const float* __restrict__ p, Surface
     if (i >= n) return;
     const float px = p[i], py = p[ld + i], pz = p[2 * ld + i];
     const int c = cell_of(sv, px, py, pz);
+    if (c < 0) return;
     uint32_t o = offsets[i];
     for (uint32_t r = sv.cell_start[c]; r < sv.cell_start[c + 1]; ++r) {
         const uint32_t t = sv.refs[r];

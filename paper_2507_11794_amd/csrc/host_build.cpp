@@ -1,5 +1,6 @@
-// Host side of the C ABI (include/cloth.h): input validation, the internal node order, the
-// sliced CSR incidence build, the stability bound, the surface grid build, and stepping.
+// Host-side building blocks of a simulation handle: error plumbing, input validation, the
+// internal node order, the sliced CSR incidence build, the stability bound and the surface
+// grid build.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -13,8 +14,6 @@
 #include "../../include/cloth.h"
 #include "cloth_internal.h"
 #include "host_common.h"
-
-using namespace cloth;
 
 // ------------------------------------------------------------------ error plumbing
 
@@ -54,17 +53,32 @@ void DeviceArena::free_one(void* p) {
     }
 }
 
-// Internal node order: the nx-by-ny grid cut into 8x8 tiles, tiles in row-major order,
-// nodes row-major within a tile, so a wavefront of 64 consecutive slots covers a compact
-// patch of cloth.
+// Internal node order: the nx-by-ny grid is cut into 8x8 tiles, the tiles are ordered along
+// a Morton (Z-order) curve over their (column, row) coordinates, and nodes are row-major
+// within a tile.  A wavefront of 64 consecutive slots is then one 8x8 patch, and any aligned
+// run of 4^k tiles is a square patch, which keeps spring neighbours and grid cells of
+// consecutive slots close together.
 std::vector<int> tile_order(int nx, int ny) {
     const int T = 8;
+    const int tx = (nx + T - 1) / T, ty = (ny + T - 1) / T;
+    auto spread = [](unsigned long long v) {
+        unsigned long long r = 0;
+        for (int b = 0; b < 32; ++b) r |= ((v >> b) & 1ULL) << (2 * b);
+        return r;
+    };
+    std::vector<std::pair<unsigned long long, int>> tiles;
+    tiles.reserve((size_t)tx * ty);
+    for (int j = 0; j < ty; ++j)
+        for (int i = 0; i < tx; ++i)
+            tiles.emplace_back(spread((unsigned)i) | (spread((unsigned)j) << 1), j * tx + i);
+    std::sort(tiles.begin(), tiles.end());
     std::vector<int> order;
     order.reserve((size_t)nx * ny);
-    for (int ty = 0; ty < ny; ty += T)
-        for (int tx = 0; tx < nx; tx += T)
-            for (int i = ty; i < std::min(ny, ty + T); ++i)
-                for (int j = tx; j < std::min(nx, tx + T); ++j) order.push_back(i * nx + j);
+    for (const auto& tl : tiles) {
+        const int ti = tl.second % tx, tj = tl.second / tx;
+        for (int i = tj * T; i < std::min(ny, tj * T + T); ++i)
+            for (int j = ti * T; j < std::min(nx, ti * T + T); ++j) order.push_back(i * nx + j);
+    }
     return order;
 }
 
@@ -181,10 +195,10 @@ bool unstable(double omega2, double gamma, double h) {
 }
 
 // Host-side cloth arrays in internal order.
-int build_cloth_host(const ClothHostInput& in, ClothHost* out) {
+int build_cloth_host(const ClothHostInput& in, ClothHost* out, const std::vector<int>* order) {
     const int N = in.nx * in.ny;
     out->n = N;
-    out->order = tile_order(in.nx, in.ny);
+    out->order = order ? *order : tile_order(in.nx, in.ny);
     out->slot.assign(N, 0);
     for (int p = 0; p < N; ++p) out->slot[out->order[p]] = p;
     out->ld = N;
@@ -303,8 +317,10 @@ ClothView ClothDevice::view() const {
     return v;
 }
 
+constexpr size_t kRefPad = 8;
+
 // Uniform grid over the surface: origin fl32(min vertex) - thickness, cells of edge
-// cell_size, dims ceil((max vertex + thickness - origin) / cell_size) per axis.
+// cell_size, dims floor((fl32(max vertex + thickness) - origin) / cell_size) + 1 per axis.
 int build_surface(const ClothHostInput& in, const cloth_params& p, DeviceArena& arena,
                   hipStream_t stream, SurfaceDevice* sd) {
     sd->view = SurfaceView{};
@@ -340,16 +356,21 @@ int build_surface(const ClothHostInput& in, const cloth_params& p, DeviceArena& 
             vmax[q] = std::max(vmax[q], in.verts[3 * i + q]);
         }
     SurfaceView& sv = sd->view;
+    sv.inv_cell = (float)(1.0 / cell);
     long long cells = 1;
     for (int q = 0; q < 3; ++q) {
+        // origin at or below every inflated low corner; dims so the largest inflated high
+        // corner maps to dim - 1 with the kernels' own FP32 formula floor((p - org) * inv)
         sv.org[q] = vmin[q] - p.thickness;
-        const double span = ((double)vmax[q] + p.thickness - (double)sv.org[q]) / cell;
-        sv.dim[q] = (int)std::max(1.0, std::ceil(span));
+        const float hmax = vmax[q] + p.thickness;
+        volatile float diff = hmax - sv.org[q];
+        volatile float scaled = diff * sv.inv_cell;
+        const double top = std::floor((double)scaled);
+        if (!(top < (double)(1 << 20))) return fail(CLOTH_ENOMEM, "grid too fine for the surface; raise cell_size");
+        sv.dim[q] = (int)top + 1;
         cells *= sv.dim[q];
-        if (sv.dim[q] > (1 << 20)) return fail(CLOTH_ENOMEM, "grid too fine for the surface; raise cell_size");
     }
     if (cells > (1LL << 27)) return fail(CLOTH_ENOMEM, "grid too fine for the surface; raise cell_size");
-    sv.inv_cell = (float)(1.0 / cell);
     sv.thickness = p.thickness;
     sv.thickness2 = p.thickness * p.thickness;
     sv.n_tris = T;
@@ -380,9 +401,13 @@ int build_surface(const ClothHostInput& in, const cloth_params& p, DeviceArena& 
     uint32_t *counts, *cell_start, *refs, *tmp;
     const size_t C = (size_t)cells;
     if ((e = arena.alloc(&counts, C)) || (e = arena.alloc(&cell_start, C + 1)) ||
-        (e = arena.alloc(&refs, (size_t)total)) || (e = arena.alloc(&tmp, scan_tmp_words(C))))
+        (e = arena.alloc(&refs, (size_t)total + kRefPad)) ||
+        (e = arena.alloc(&tmp, scan_tmp_words(C))))
         return hip_fail(e, "hipMalloc grid");
-    if ((e = hipMemsetAsync(counts, 0, 4 * C, stream)) ||
+    // kRefPad zero entries after the last reference let the query loop load references in
+    // groups of four without a bounds test (triangle 0 is always a valid index)
+    if ((e = hipMemsetAsync(refs, 0, 4 * ((size_t)total + kRefPad), stream)) ||
+        (e = hipMemsetAsync(counts, 0, 4 * C, stream)) ||
         (e = launch_grid_count(T, box_lo, box_hi, sv.org, sv.inv_cell, sv.dim, counts, stream)) ||
         (e = scan_exclusive_u32(counts, cell_start, C, tmp, stream)) ||
         (e = hipMemsetAsync(counts, 0, 4 * C, stream)) ||
@@ -405,242 +430,3 @@ int build_surface(const ClothHostInput& in, const cloth_params& p, DeviceArena& 
 }
 
 }  // namespace cloth
-
-// ------------------------------------------------------------------ the handle
-
-struct cloth_sim {
-    ClothHostInput shape;  // sizes only (pointers cleared after create)
-    cloth_params p{};
-    hipStream_t stream = nullptr;
-    ClothHost host;
-    ClothDevice dev;
-    SurfaceDevice surf;
-    DeviceArena arena;
-    int* nan_flag = nullptr;
-    double omega2 = 0.0, gamma = 0.0;
-    int block = 256;
-};
-
-extern "C" {
-
-int cloth_create(int nx, int ny, const float* x0, const float* v0, const float* mass,
-                 const unsigned char* pinned, int n_springs, const int* ends, const float* rest,
-                 const float* k, const float* c, int n_verts, const float* verts, int n_tris,
-                 const int* tris, const cloth_params* p, void* hip_stream, cloth_sim** out) {
-    if (!out) return fail(CLOTH_EINVAL, "out is NULL");
-    *out = nullptr;
-    ClothHostInput in{nx, ny, x0, v0, mass, pinned, n_springs, ends, rest, k, c, n_verts, verts,
-                      n_tris, tris};
-    int st;
-    if ((st = validate_params(p)) || (st = validate_cloth(in))) return st;
-    cloth_sim* s = new (std::nothrow) cloth_sim();
-    if (!s) return fail(CLOTH_ENOMEM, "host allocation failed");
-    s->p = *p;
-    s->stream = (hipStream_t)hip_stream;
-    try {
-        st = build_cloth_host(in, &s->host);
-        if (st == CLOTH_OK) stability_bounds(in, &s->omega2, &s->gamma);
-    } catch (const std::bad_alloc&) {
-        st = fail(CLOTH_ENOMEM, "host allocation failed");
-    }
-    if (st == CLOTH_OK) st = upload_cloth(s->host, s->arena, s->stream, &s->dev);
-    if (st == CLOTH_OK) st = build_surface(in, s->p, s->arena, s->stream, &s->surf);
-    if (st == CLOTH_OK) {
-        hipError_t e;
-        if ((e = s->arena.alloc(&s->nan_flag, 1)) ||
-            (e = hipMemsetAsync(s->nan_flag, 0, 4, s->stream)) || (e = hipStreamSynchronize(s->stream)))
-            st = hip_fail(e, "create");
-    }
-    if (st != CLOTH_OK) {
-        (void)hipStreamSynchronize(s->stream);
-        delete s;
-        return st;
-    }
-    s->shape = in;
-    s->shape.x0 = s->shape.v0 = s->shape.mass = s->shape.rest = s->shape.k = s->shape.c = nullptr;
-    s->shape.verts = nullptr;
-    s->shape.pinned = nullptr;
-    s->shape.ends = s->shape.tris = nullptr;
-    // host staging copies are no longer needed except the order maps
-    s->host.release_arrays();
-    *out = s;
-    return CLOTH_OK;
-}
-
-int cloth_step(cloth_sim* s, float dt, int n_substeps, int n_steps) {
-    if (!s) return fail(CLOTH_EINVAL, "NULL handle");
-    if (!(dt > 0.0f) || !std::isfinite(dt)) return fail(CLOTH_EINVAL, "dt must be positive and finite");
-    if (n_substeps < 1 || n_steps < 0) return fail(CLOTH_EINVAL, "n_substeps >= 1 and n_steps >= 0");
-    const float h = dt / (float)n_substeps;
-    if (!(s->p.flags & CLOTH_F_NO_STABILITY_CHECK) && unstable(s->omega2, s->gamma, h))
-        return fail(CLOTH_EUNSTABLE, "substep h = " + std::to_string(h) +
-                                         " s exceeds the explicit stability bound (omega^2 = " +
-                                         std::to_string(s->omega2) + ", gamma = " +
-                                         std::to_string(s->gamma) + "); use more substeps");
-    StepParams sp;
-    sp.h = h;
-    for (int q = 0; q < 3; ++q) sp.g[q] = s->p.gravity[q];
-    sp.restitution = s->p.restitution;
-    sp.check_nan = (s->p.flags & CLOTH_F_CHECK_NAN) ? 1 : 0;
-    sp.nan_flag = s->nan_flag;
-    const ClothView cv = s->dev.view();
-    const long long total = (long long)n_steps * n_substeps;
-    for (long long it = 0; it < total; ++it) {
-        const int src = s->dev.cur, dst = src ^ 1;
-        hipError_t e = launch_substep(cv, s->surf.view, sp, s->dev.x[src], s->dev.v[src],
-                                      s->dev.x[dst], s->dev.v[dst], s->block, s->stream);
-        if (e != hipSuccess) return hip_fail(e, "substep launch");
-        s->dev.cur = dst;
-    }
-    return CLOTH_OK;
-}
-
-int cloth_read_state(const cloth_sim* s, float* x_out, float* v_out) {
-    if (!s || !x_out) return fail(CLOTH_EINVAL, "NULL argument");
-    const int N = s->dev.n, ld = s->dev.ld;
-    std::vector<float> xs(3 * (size_t)ld), vs(v_out ? 3 * (size_t)ld : 0);
-    int flag = 0;
-    hipError_t e;
-    if ((e = hipMemcpyAsync(xs.data(), s->dev.x[s->dev.cur], 12 * (size_t)ld, hipMemcpyDeviceToHost,
-                            s->stream)))
-        return hip_fail(e, "read state");
-    if (v_out && (e = hipMemcpyAsync(vs.data(), s->dev.v[s->dev.cur], 12 * (size_t)ld,
-                                     hipMemcpyDeviceToHost, s->stream)))
-        return hip_fail(e, "read state");
-    if ((e = hipMemcpyAsync(&flag, s->nan_flag, 4, hipMemcpyDeviceToHost, s->stream)) ||
-        (e = hipStreamSynchronize(s->stream)))
-        return hip_fail(e, "read state");
-    for (int p = 0; p < N; ++p) {
-        const int id = s->host.order[p];
-        for (int q = 0; q < 3; ++q) {
-            x_out[3 * (size_t)id + q] = xs[(size_t)q * ld + p];
-            if (v_out) v_out[3 * (size_t)id + q] = vs[(size_t)q * ld + p];
-        }
-    }
-    if ((s->p.flags & CLOTH_F_CHECK_NAN) && flag)
-        return fail(CLOTH_ENAN, "a non-finite value appeared in the state");
-    return CLOTH_OK;
-}
-
-int cloth_write_state(cloth_sim* s, const float* x, const float* v) {
-    if (!s || !x) return fail(CLOTH_EINVAL, "NULL argument");
-    const int N = s->dev.n, ld = s->dev.ld;
-    std::vector<float> xs(3 * (size_t)ld, 0.0f), vs(3 * (size_t)ld, 0.0f);
-    for (int p = 0; p < N; ++p) {
-        const int id = s->host.order[p];
-        for (int q = 0; q < 3; ++q) {
-            const float xv = x[3 * (size_t)id + q];
-            const float vv = v ? v[3 * (size_t)id + q] : 0.0f;
-            if (!std::isfinite(xv) || !std::isfinite(vv)) return fail(CLOTH_EINVAL, "non-finite state");
-            xs[(size_t)q * ld + p] = xv;
-            vs[(size_t)q * ld + p] = vv;
-        }
-    }
-    hipError_t e;
-    if ((e = hipMemcpyAsync(s->dev.x[s->dev.cur], xs.data(), 12 * (size_t)ld, hipMemcpyHostToDevice,
-                            s->stream)) ||
-        (e = hipMemcpyAsync(s->dev.v[s->dev.cur], vs.data(), 12 * (size_t)ld, hipMemcpyHostToDevice,
-                            s->stream)) ||
-        (e = hipMemsetAsync(s->nan_flag, 0, 4, s->stream)) || (e = hipStreamSynchronize(s->stream)))
-        return hip_fail(e, "write state");
-    return CLOTH_OK;
-}
-
-int cloth_device_state(cloth_sim* s, float** x_soa, float** v_soa) {
-    if (!s) return fail(CLOTH_EINVAL, "NULL handle");
-    if (x_soa) *x_soa = s->dev.x[s->dev.cur];
-    if (v_soa) *v_soa = s->dev.v[s->dev.cur];
-    return CLOTH_OK;
-}
-
-int cloth_node_order(const cloth_sim* s, int* order) {
-    if (!s || !order) return fail(CLOTH_EINVAL, "NULL argument");
-    std::memcpy(order, s->host.order.data(), sizeof(int) * s->host.order.size());
-    return CLOTH_OK;
-}
-
-int cloth_info(const cloth_sim* s, long long* out) {
-    if (!s || !out) return fail(CLOTH_EINVAL, "NULL argument");
-    out[0] = s->dev.n;
-    out[1] = s->shape.n_springs;
-    out[2] = s->surf.view.n_tris;
-    out[3] = s->surf.n_cells;
-    out[4] = s->surf.n_refs;
-    for (int q = 0; q < 3; ++q) out[5 + q] = s->surf.view.n_tris ? s->surf.view.dim[q] : 0;
-    return CLOTH_OK;
-}
-
-int cloth_destroy(cloth_sim* s) {
-    if (!s) return CLOTH_OK;
-    (void)hipStreamSynchronize(s->stream);
-    delete s;
-    return CLOTH_OK;
-}
-
-int cloth_debug_candidates(cloth_sim* s, int n_points, const float* points, int* pairs_out,
-                           long long cap, long long* n_out) {
-    if (!s || !n_out) return fail(CLOTH_EINVAL, "NULL argument");
-    if (n_points < 0 || cap < 0) return fail(CLOTH_EINVAL, "negative size");
-    if (n_points > 0 && !points) return fail(CLOTH_EINVAL, "points is NULL");
-    if (cap > 0 && !pairs_out) return fail(CLOTH_EINVAL, "pairs_out is NULL");
-    if (s->surf.view.n_tris == 0) return fail(CLOTH_EINVAL, "collision is disabled for this handle");
-    *n_out = 0;
-    if (n_points == 0) return CLOTH_OK;
-    DeviceArena tmp;
-    float* d_p;
-    uint32_t *d_cnt, *d_off, *d_scan;
-    hipError_t e;
-    const size_t n = (size_t)n_points;
-    if ((e = tmp.alloc(&d_p, 3 * n)) || (e = tmp.alloc(&d_cnt, n)) || (e = tmp.alloc(&d_off, n + 1)) ||
-        (e = tmp.alloc(&d_scan, scan_tmp_words(n))))
-        return hip_fail(e, "hipMalloc candidates");
-    std::vector<float> soa(3 * n);
-    for (size_t i = 0; i < n; ++i)
-        for (int q = 0; q < 3; ++q) soa[q * n + i] = points[3 * i + q];
-    uint32_t total = 0;
-    if ((e = hipMemcpyAsync(d_p, soa.data(), 12 * n, hipMemcpyHostToDevice, s->stream)) ||
-        (e = launch_candidates_count(n_points, n_points, d_p, s->surf.view, d_cnt, s->stream)) ||
-        (e = scan_exclusive_u32(d_cnt, d_off, n, d_scan, s->stream)) ||
-        (e = hipMemcpyAsync(&total, d_off + n, 4, hipMemcpyDeviceToHost, s->stream)) ||
-        (e = hipStreamSynchronize(s->stream)))
-        return hip_fail(e, "candidate count");
-    *n_out = total;
-    if (total == 0 || cap == 0) return CLOTH_OK;
-    int* d_pairs;
-    if ((e = tmp.alloc(&d_pairs, 2 * (size_t)total))) return hip_fail(e, "hipMalloc pairs");
-    const size_t ncopy = (size_t)std::min<long long>(cap, total);
-    if ((e = launch_candidates_write(n_points, n_points, d_p, s->surf.view, d_off, d_pairs, s->stream)) ||
-        (e = hipMemcpyAsync(pairs_out, d_pairs, 8 * ncopy, hipMemcpyDeviceToHost, s->stream)) ||
-        (e = hipStreamSynchronize(s->stream)))
-        return hip_fail(e, "candidate write");
-    return CLOTH_OK;
-}
-
-int cloth_stability_bound(int n_nodes, const float* x0, const float* mass,
-                          const unsigned char* pinned, int n_springs, const int* ends,
-                          const float* k, const float* c, double* omega2, double* gamma) {
-    if (!omega2 || !gamma) return fail(CLOTH_EINVAL, "NULL output");
-    std::vector<float> rest((size_t)std::max(n_springs, 0), 1.0f);
-    ClothHostInput in{n_nodes, 1, x0, nullptr, mass, pinned, n_springs, ends, rest.data(), k, c,
-                      0, nullptr, 0, nullptr};
-    if (int st = validate_cloth(in)) return st;
-    stability_bounds(in, omega2, gamma);
-    return CLOTH_OK;
-}
-
-const char* cloth_status_str(int status) {
-    switch (status) {
-        case CLOTH_OK: return "CLOTH_OK";
-        case CLOTH_EINVAL: return "CLOTH_EINVAL: invalid argument";
-        case CLOTH_ENOMEM: return "CLOTH_ENOMEM: out of memory or size limit";
-        case CLOTH_EDEVICE: return "CLOTH_EDEVICE: HIP runtime or kernel failure";
-        case CLOTH_EUNSTABLE: return "CLOTH_EUNSTABLE: substep exceeds the stability bound";
-        case CLOTH_ESTATE: return "CLOTH_ESTATE: call out of order";
-        case CLOTH_ENAN: return "CLOTH_ENAN: non-finite state";
-        default: return "unknown cloth status";
-    }
-}
-
-const char* cloth_last_error(void) { return g_last_error.c_str(); }
-
-}  // extern "C"

@@ -60,17 +60,11 @@ struct ClothHost {
     std::vector<float> x, v, w;
     std::vector<int> deg, slice_ptr, nbr, inc_spring;
     std::vector<float> ik, ic, il;
-    void release_arrays() {
+    // The state copies are only needed for the upload; the incidence lists stay for
+    // rebuilding tile plans.
+    void release_state() {
         std::vector<float>().swap(x);
         std::vector<float>().swap(v);
-        std::vector<float>().swap(w);
-        std::vector<int>().swap(deg);
-        std::vector<int>().swap(slice_ptr);
-        std::vector<int>().swap(nbr);
-        std::vector<int>().swap(inc_spring);
-        std::vector<float>().swap(ik);
-        std::vector<float>().swap(ic);
-        std::vector<float>().swap(il);
     }
 };
 
@@ -90,6 +84,20 @@ struct ClothDevice {
     ClothView view() const;
 };
 
+// Device copy of a tile plan (build_tile_plan) and its schedule (build_schedule).
+struct TilePlanDevice {
+    DeviceArena arena;
+    DeviceArena sched_arena;
+    std::vector<TileMeta> meta_host;
+    int schedule = -1, sched_workgroups = 0;
+    int tile_nodes = 0, K = 0;
+    TileView view{};
+    int* inc_sid = nullptr;  // spring id per incidence entry (-1 = padding)
+    size_t inc_count = 0;
+    size_t bytes = 0;
+    long long computed_per_launch_first = 0;  // nodes computed in the first substep of a launch
+};
+
 struct SurfaceDevice {
     SurfaceView view{};
     double cell = 0.0;
@@ -101,9 +109,14 @@ int validate_cloth(const ClothHostInput& in);
 int validate_params(const cloth_params* p);
 void stability_bounds(const ClothHostInput& in, double* omega2, double* gamma);
 bool unstable(double omega2, double gamma, double h);
-int build_cloth_host(const ClothHostInput& in, ClothHost* out);
+// order: internal slot -> node id; NULL = the 8x8-tile Morton order of (nx, ny).
+int build_cloth_host(const ClothHostInput& in, ClothHost* out,
+                     const std::vector<int>* order = nullptr);
 int upload_cloth(const ClothHost& h, DeviceArena& arena, hipStream_t stream, ClothDevice* d);
 int build_surface(const ClothHostInput& in, const cloth_params& p, DeviceArena& arena,
                   hipStream_t stream, SurfaceDevice* sd);
+int build_tile_plan(const ClothHost& h, const std::vector<int>& group_off, int tile_nodes, int K,
+                    hipStream_t stream, TilePlanDevice* out);
+int build_schedule(TilePlanDevice* plan, int mode, int n_workgroups, hipStream_t stream);
 
 }  // namespace cloth

@@ -1,0 +1,208 @@
+// a6: differentiable rollout (cloth_rollout_forward / cloth_rollout_backward) with
+// checkpointed recomputation.  The forward pass records positions at the requested frames
+// and (x, v) every ckpt_every frames; the backward pass walks the checkpoint segments from
+// last to first, recomputes each segment's states from its checkpoint (bit-identical to the
+// forward pass, so the contact sets are the same), and applies the substep adjoints in
+// reverse.  Memory: one checkpoint per ckpt_every frames plus one segment of states.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "sim.h"
+
+using namespace cloth;
+
+namespace {
+
+// Stiffness and damping from device arrays into every copy the handle keeps.
+int set_spring_params(cloth_sim* s, const float* k_dev, const float* c_dev) {
+    const size_t S = (size_t)s->n_springs;
+    if (S == 0) return CLOTH_OK;
+    hipError_t e;
+    std::vector<float> k(S), c(S);
+    if ((e = hipMemcpyAsync(k.data(), k_dev, 4 * S, hipMemcpyDeviceToHost, s->stream)) ||
+        (e = hipMemcpyAsync(c.data(), c_dev, 4 * S, hipMemcpyDeviceToHost, s->stream)) ||
+        (e = hipStreamSynchronize(s->stream)))
+        return hip_fail(e, "read spring parameters");
+    for (size_t q = 0; q < S; ++q)
+        if (!(k[q] >= 0.0f) || !std::isfinite(k[q]) || !(c[q] >= 0.0f) || !std::isfinite(c[q]))
+            return fail(CLOTH_EINVAL, "spring " + std::to_string(q) + " needs finite k, c >= 0");
+    s->k = k;
+    s->c = c;
+    for (size_t q = 0; q < s->host.inc_spring.size(); ++q) {
+        const int code = s->host.inc_spring[q];
+        const int sid = code >= 0 ? code : ~code;
+        s->host.ik[q] = k[sid];
+        s->host.ic[q] = c[sid];
+    }
+    if ((e = launch_set_params(s->host.inc_spring.size(), s->dev.inc_spring, k_dev, c_dev,
+                               s->dev.ik, s->dev.ic, s->stream)))
+        return hip_fail(e, "set spring parameters");
+    if (s->plan.inc_count &&
+        (e = launch_set_params_plan(s->plan.inc_count, s->plan.inc_sid, k_dev, c_dev,
+                                    const_cast<float4*>(s->plan.view.inc), s->stream)))
+        return hip_fail(e, "set tile parameters");
+    refresh_stability(s);
+    return CLOTH_OK;
+}
+
+StepParams step_params(const cloth_sim* s, float h) {
+    StepParams sp;
+    sp.h = h;
+    for (int q = 0; q < 3; ++q) sp.g[q] = s->p.gravity[q];
+    sp.restitution = s->p.restitution;
+    sp.check_nan = 0;
+    sp.nan_flag = s->nan_flag;
+    return sp;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cloth_rollout_forward(cloth_sim* s, const float* k_dev, const float* c_dev,
+                          const float* v0_dev, float dt, int n_substeps, int n_steps,
+                          int ckpt_every, const int* out_steps, int n_out, float* x_out_dev) {
+    if (!s) return fail(CLOTH_EINVAL, "NULL handle");
+    if (s->groups.size() != 1) return fail(CLOTH_EINVAL, "rollouts take a single-cloth handle");
+    if (s->n_springs > 0 && (!k_dev || !c_dev)) return fail(CLOTH_EINVAL, "k and c are required");
+    if (!(dt > 0.0f) || !std::isfinite(dt) || n_substeps < 1 || n_steps < 0 || ckpt_every < 1)
+        return fail(CLOTH_EINVAL, "need dt > 0, n_substeps >= 1, n_steps >= 0, ckpt_every >= 1");
+    if (n_out < 0 || (n_out > 0 && (!out_steps || !x_out_dev)))
+        return fail(CLOTH_EINVAL, "out_steps and x_out are required when n_out > 0");
+    for (int j = 0; j < n_out; ++j)
+        if (out_steps[j] < 0 || out_steps[j] > n_steps || (j && out_steps[j] < out_steps[j - 1]))
+            return fail(CLOTH_EINVAL, "out_steps must be ascending frame counts in 0..n_steps");
+    s->roll.ready = false;
+    int st = set_spring_params(s, k_dev, c_dev);
+    if (st != CLOTH_OK) return st;
+    const float h = dt / (float)n_substeps;
+    if (!(s->p.flags & CLOTH_F_NO_STABILITY_CHECK) &&
+        unstable(s->groups[0].omega2, s->groups[0].gamma, h))
+        return fail(CLOTH_EUNSTABLE, "substep exceeds the explicit stability bound");
+    RolloutState& R = s->roll;
+    const int N = s->dev.n;
+    const size_t ld = (size_t)s->dev.ld, state = 6 * ld;
+    R.h = h;
+    R.n_sub = (long long)n_steps * n_substeps;
+    R.ckpt = (long long)ckpt_every * n_substeps;
+    R.n_ck = R.n_sub / R.ckpt + 1;
+    R.out_sub.assign(n_out, 0);
+    for (int j = 0; j < n_out; ++j) R.out_sub[j] = (long long)out_steps[j] * n_substeps;
+    hipError_t e;
+    if ((e = hipStreamSynchronize(s->stream))) return hip_fail(e, "synchronise");
+    R.arena.release();
+    R.seg = nullptr;
+    R.adj = nullptr;
+    R.kb = R.cb = nullptr;
+    if ((e = R.arena.alloc(&R.ck, (size_t)R.n_ck * state)))
+        return hip_fail(e, "hipMalloc checkpoints");
+    // initial state: the handle's initial positions and the given velocities
+    float* X = s->dev.x[s->dev.cur];
+    float* V = s->dev.v[s->dev.cur];
+    if ((e = hipMemcpyAsync(X, s->x_init, 12 * ld, hipMemcpyDeviceToDevice, s->stream)) ||
+        (e = hipMemcpyAsync(V, s->v_init, 12 * ld, hipMemcpyDeviceToDevice, s->stream)) ||
+        (v0_dev && (e = launch_import(N, (int)ld, s->slot_dev, v0_dev, V, 0, s->stream))) ||
+        (e = hipMemsetAsync(s->nan_flag, 0, 4, s->stream)))
+        return hip_fail(e, "rollout initial state");
+    long long pos = 0;
+    int j = 0;
+    for (;;) {
+        if (pos % R.ckpt == 0) {
+            float* dst = R.ck + (size_t)(pos / R.ckpt) * state;
+            if ((e = hipMemcpyAsync(dst, s->dev.x[s->dev.cur], 12 * ld, hipMemcpyDeviceToDevice,
+                                    s->stream)) ||
+                (e = hipMemcpyAsync(dst + 3 * ld, s->dev.v[s->dev.cur], 12 * ld,
+                                    hipMemcpyDeviceToDevice, s->stream)))
+                return hip_fail(e, "checkpoint");
+        }
+        while (j < n_out && R.out_sub[j] == pos) {
+            if ((e = launch_export(N, (int)ld, s->slot_dev, s->dev.x[s->dev.cur],
+                                   x_out_dev + (size_t)j * 3 * N, s->stream)))
+                return hip_fail(e, "record output");
+            ++j;
+        }
+        if (pos == R.n_sub) break;
+        long long next = std::min(R.n_sub, (pos / R.ckpt + 1) * R.ckpt);
+        if (j < n_out) next = std::min(next, R.out_sub[j]);
+        if ((st = run_substeps(s, h, next - pos)) != CLOTH_OK) return st;
+        pos = next;
+    }
+    R.ready = true;
+    return CLOTH_OK;
+}
+
+int cloth_rollout_backward(cloth_sim* s, const float* gx_out_dev, float* gk_dev, float* gc_dev,
+                           float* gv0_dev) {
+    if (!s) return fail(CLOTH_EINVAL, "NULL handle");
+    RolloutState& R = s->roll;
+    if (!R.ready) return fail(CLOTH_ESTATE, "cloth_rollout_backward needs a preceding forward pass");
+    if (!R.out_sub.empty() && !gx_out_dev) return fail(CLOTH_EINVAL, "gx_out is required");
+    const int N = s->dev.n, n_out = (int)R.out_sub.size();
+    const size_t ld = (size_t)s->dev.ld, S = (size_t)s->n_springs, state = 6 * ld;
+    hipError_t e;
+    if (!R.seg) {
+        if ((e = R.arena.alloc(&R.seg, (size_t)(R.ckpt + 1) * state)) ||
+            (e = R.arena.alloc(&R.adj, 7 * 3 * ld)) || (e = R.arena.alloc(&R.kb, S + 1)) ||
+            (e = R.arena.alloc(&R.cb, S + 1)))
+            return hip_fail(e, "hipMalloc adjoint buffers");
+    }
+    float* xb = R.adj;
+    float* vb = R.adj + 3 * ld;
+    float* xb2 = R.adj + 6 * ld;
+    float* vb2 = R.adj + 9 * ld;
+    float* fb = R.adj + 12 * ld;
+    float* xbp = R.adj + 15 * ld;
+    float* vbp = R.adj + 18 * ld;
+    if ((e = hipMemsetAsync(xb, 0, 4 * 6 * ld, s->stream)) ||
+        (e = hipMemsetAsync(R.kb, 0, 8 * (S + 1), s->stream)) ||
+        (e = hipMemsetAsync(R.cb, 0, 8 * (S + 1), s->stream)))
+        return hip_fail(e, "clear adjoints");
+    const ClothView cv = s->dev.view();
+    const StepParams sp = step_params(s, R.h);
+    int j = n_out - 1;
+    auto add_outputs = [&](long long at) -> hipError_t {
+        while (j >= 0 && R.out_sub[j] == at) {
+            hipError_t r = launch_import(N, (int)ld, s->slot_dev, gx_out_dev + (size_t)j * 3 * N,
+                                         xb, 1, s->stream);
+            if (r != hipSuccess) return r;
+            --j;
+        }
+        return hipSuccess;
+    };
+    if ((e = add_outputs(R.n_sub))) return hip_fail(e, "seed adjoint");
+    for (long long seg = (R.n_sub - 1) / R.ckpt; seg >= 0 && R.n_sub > 0; --seg) {
+        const long long base = seg * R.ckpt, top = std::min(base + R.ckpt, R.n_sub);
+        if ((e = hipMemcpyAsync(R.seg, R.ck + (size_t)seg * state, 4 * state,
+                                hipMemcpyDeviceToDevice, s->stream)))
+            return hip_fail(e, "restore checkpoint");
+        for (long long r = 1; r < top - base; ++r) {
+            const float* xs = R.seg + (size_t)(r - 1) * state;
+            float* xd = R.seg + (size_t)r * state;
+            if ((e = launch_substep(cv, s->surfs[0].view, sp, xs, xs + 3 * ld, xd, xd + 3 * ld, 256,
+                                    s->stream)))
+                return hip_fail(e, "recompute segment");
+        }
+        for (long long t = top; t > base; --t) {
+            const float* xs = R.seg + (size_t)(t - 1 - base) * state;
+            if ((e = launch_adj_node(cv, s->surfs[0].view, sp, xs, xs + 3 * ld, xb, vb, fb, xbp, vbp,
+                                     s->stream)) ||
+                (e = launch_adj_springs(cv, xs, xs + 3 * ld, fb, xbp, vbp, xb2, vb2, R.kb, R.cb,
+                                        s->stream)))
+                return hip_fail(e, "adjoint substep");
+            std::swap(xb, xb2);
+            std::swap(vb, vb2);
+            if ((e = add_outputs(t - 1))) return hip_fail(e, "add output adjoint");
+        }
+    }
+    if ((gv0_dev && (e = launch_export(N, (int)ld, s->slot_dev, vb, gv0_dev, s->stream))) ||
+        (gk_dev && (e = launch_d2f(S, R.kb, gk_dev, s->stream))) ||
+        (gc_dev && (e = launch_d2f(S, R.cb, gc_dev, s->stream))))
+        return hip_fail(e, "write gradients");
+    return CLOTH_OK;
+}
+
+}  // extern "C"

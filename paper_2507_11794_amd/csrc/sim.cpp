@@ -1,0 +1,535 @@
+// The plain C ABI (include/cloth.h): create / step / state access / launch configuration,
+// and the substep scheduler (tile plans, schedules, hipGraph replay).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sim.h"
+
+namespace cloth {
+
+int check_launch(const cloth_launch& c) {
+    if (c.kernel != CLOTH_KERNEL_TILE && c.kernel != CLOTH_KERNEL_DIRECT)
+        return fail(CLOTH_EINVAL, "unknown kernel");
+    if (c.block_threads < 64 || c.block_threads > 256 || (c.block_threads & 63))
+        return fail(CLOTH_EINVAL, "block_threads must be 64, 128, 192 or 256");
+    if (c.kernel == CLOTH_KERNEL_TILE) {
+        if (c.tile_nodes < 64 || c.tile_nodes > 4096 || (c.tile_nodes & 63))
+            return fail(CLOTH_EINVAL, "tile_nodes must be a multiple of 64 in 64..4096");
+        if (c.substeps_per_launch < 1 || c.substeps_per_launch > kMaxTileK)
+            return fail(CLOTH_EINVAL, "substeps_per_launch must be in 1..8");
+        if (c.schedule < CLOTH_SCHED_GRID || c.schedule > CLOTH_SCHED_RR)
+            return fail(CLOTH_EINVAL, "unknown schedule");
+        if (c.schedule != CLOTH_SCHED_GRID && (c.workgroups < 1 || c.workgroups > (1 << 20)))
+            return fail(CLOTH_EINVAL, "persistent schedules need 1..2^20 workgroups");
+    }
+    return CLOTH_OK;
+}
+
+int ensure_plan(cloth_sim* s, const cloth_launch& c) {
+    if (c.kernel != CLOTH_KERNEL_TILE) return CLOTH_OK;
+    const bool plan_ok = s->plan.tile_nodes == c.tile_nodes && s->plan.K == c.substeps_per_launch;
+    const int wg = c.schedule == CLOTH_SCHED_GRID ? 0 : c.workgroups;
+    const bool sched_ok = plan_ok && s->plan.schedule == c.schedule && s->plan.sched_workgroups == wg;
+    if (sched_ok) return CLOTH_OK;
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "synchronise before replanning");
+    s->drop_graphs();
+    if (!plan_ok) {
+        TilePlanDevice fresh;
+        int st = build_tile_plan(s->host, s->group_off, c.tile_nodes, c.substeps_per_launch,
+                                 s->stream, &fresh);
+        if (st != CLOTH_OK) return st;
+        if ((e = prepare_tile_kernels(tile_lds_bytes(fresh.view.rmax))))
+            return hip_fail(e, "tile kernel LDS attribute");
+        s->plan.arena.release();
+        s->plan.arena.ptrs.swap(fresh.arena.ptrs);
+        s->plan.meta_host.swap(fresh.meta_host);
+        s->plan.tile_nodes = fresh.tile_nodes;
+        s->plan.K = fresh.K;
+        s->plan.view = fresh.view;
+        s->plan.view.w = s->dev.w;
+        s->plan.view.svs = s->svs_dev;
+        s->plan.inc_sid = fresh.inc_sid;
+        s->plan.inc_count = fresh.inc_count;
+        s->plan.bytes = fresh.bytes;
+        s->plan.computed_per_launch_first = fresh.computed_per_launch_first;
+        s->plan.schedule = -1;
+    }
+    int st = build_schedule(&s->plan, c.schedule, wg, s->stream);
+    if (st != CLOTH_OK) return st;
+    ++s->plan_version;
+    return CLOTH_OK;
+}
+
+int set_launch(cloth_sim* s, const cloth_launch& cfg) {
+    int st = check_launch(cfg);
+    if (st != CLOTH_OK) return st;
+    if ((st = ensure_plan(s, cfg)) != CLOTH_OK) return st;
+    if (cfg.kernel != s->launch.kernel || cfg.block_threads != s->launch.block_threads) {
+        hipError_t e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return hip_fail(e, "synchronise");
+        s->drop_graphs();
+    }
+    s->launch = cfg;
+    if (cfg.kernel == CLOTH_KERNEL_DIRECT) {
+        s->launch.schedule = CLOTH_SCHED_GRID;
+        s->launch.workgroups = 0;
+    }
+    return CLOTH_OK;
+}
+
+namespace {
+
+// One launch advancing K substeps from buffer `src` into buffer `src ^ 1`.
+hipError_t launch_once(cloth_sim* s, const StepParams& sp, int K, int src, hipStream_t st) {
+    const int dst = src ^ 1;
+    if (s->launch.kernel == CLOTH_KERNEL_TILE)
+        return launch_tiles(s->plan.view, K, s->any_collision, sp, s->dev.x[src], s->dev.v[src],
+                            s->dev.x[dst], s->dev.v[dst], s->launch.block_threads, st);
+    if (s->groups.size() == 1)
+        return launch_substep(s->dev.view(), s->surfs[0].view, sp, s->dev.x[src], s->dev.v[src],
+                              s->dev.x[dst], s->dev.v[dst], s->launch.block_threads, st);
+    return launch_substep(s->dev.view(), s->surfs[0].view, sp, s->dev.x[src], s->dev.v[src],
+                          s->dev.x[dst], s->dev.v[dst], s->launch.block_threads, st, s->svs_dev,
+                          s->node_group_dev);
+}
+
+// A captured graph of `chunk` (even) launches of K substeps starting from buffer `parity`.
+hipGraphExec_t get_graph(cloth_sim* s, const StepParams& sp, int K, int chunk, int parity) {
+    unsigned hb;
+    std::memcpy(&hb, &sp.h, 4);
+    for (auto& g : s->graphs)
+        if (g.h_bits == hb && g.K == K && g.chunk == chunk && g.parity == parity &&
+            g.plan_version == s->plan_version)
+            return g.exec;
+    if (!s->capture && hipStreamCreateWithFlags(&s->capture, hipStreamNonBlocking) != hipSuccess) {
+        s->capture = nullptr;
+        return nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(s->capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return nullptr;
+    bool ok = true;
+    int cur = parity;
+    for (int i = 0; i < chunk; ++i) {
+        if (launch_once(s, sp, K, cur, s->capture) != hipSuccess) ok = false;
+        cur ^= 1;
+    }
+    if (hipStreamEndCapture(s->capture, &graph) != hipSuccess || !ok || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (s->graphs.size() >= 8) {
+        (void)hipGraphExecDestroy(s->graphs.front().exec);
+        s->graphs.erase(s->graphs.begin());
+    }
+    s->graphs.push_back(GraphEntry{hb, K, chunk, parity, s->plan_version, exec});
+    return exec;
+}
+
+}  // namespace
+
+// Any split of the substeps into launches gives the same bits, so the schedule only affects
+// speed.
+int run_substeps(cloth_sim* s, float h, long long total) {
+    StepParams sp;
+    sp.h = h;
+    for (int q = 0; q < 3; ++q) sp.g[q] = s->p.gravity[q];
+    sp.restitution = s->p.restitution;
+    sp.check_nan = (s->p.flags & CLOTH_F_CHECK_NAN) ? 1 : 0;
+    sp.nan_flag = s->nan_flag;
+    int st = ensure_plan(s, s->launch);
+    if (st != CLOTH_OK) return st;
+    s->roll.ready = false;  // stepping moves the state away from a rollout's checkpoints
+    const int K = s->launch.kernel == CLOTH_KERNEL_TILE ? s->launch.substeps_per_launch : 1;
+    long long launches = total / K;
+    const int rem = (int)(total % K);
+    if (s->launch.use_graph) {
+        // about 32 substeps per graph, an even number of launches so the buffers return to
+        // their starting parity after every replay
+        int chunk = std::max(1, 32 / K);
+        chunk += chunk & 1;
+        if (launches >= chunk) {
+            hipGraphExec_t exec = get_graph(s, sp, K, chunk, s->dev.cur);
+            if (exec) {
+                for (long long r = launches / chunk; r > 0; --r) {
+                    hipError_t e = hipGraphLaunch(exec, s->stream);
+                    if (e != hipSuccess) return hip_fail(e, "graph launch");
+                }
+                launches %= chunk;
+            }
+        }
+    }
+    for (long long i = 0; i < launches; ++i) {
+        hipError_t e = launch_once(s, sp, K, s->dev.cur, s->stream);
+        if (e != hipSuccess) return hip_fail(e, "substep launch");
+        s->dev.cur ^= 1;
+    }
+    if (rem) {
+        hipError_t e = launch_once(s, sp, rem, s->dev.cur, s->stream);
+        if (e != hipSuccess) return hip_fail(e, "substep launch");
+        s->dev.cur ^= 1;
+    }
+    return CLOTH_OK;
+}
+
+int step_sim(cloth_sim* s, float dt, int n_substeps, int n_steps) {
+    if (!(dt > 0.0f) || !std::isfinite(dt)) return fail(CLOTH_EINVAL, "dt must be positive and finite");
+    if (n_substeps < 1 || n_steps < 0) return fail(CLOTH_EINVAL, "n_substeps >= 1 and n_steps >= 0");
+    const float h = dt / (float)n_substeps;
+    if (!(s->p.flags & CLOTH_F_NO_STABILITY_CHECK))
+        for (size_t g = 0; g < s->groups.size(); ++g)
+            if (unstable(s->groups[g].omega2, s->groups[g].gamma, h))
+                return fail(CLOTH_EUNSTABLE,
+                            "cloth " + std::to_string(g) + ": substep h = " + std::to_string(h) +
+                                " s exceeds the explicit stability bound (omega^2 = " +
+                                std::to_string(s->groups[g].omega2) + ", gamma = " +
+                                std::to_string(s->groups[g].gamma) + "); use more substeps");
+    return run_substeps(s, h, (long long)n_steps * n_substeps);
+}
+
+void refresh_stability(cloth_sim* s) {
+    for (auto& g : s->groups) {
+        ClothHostInput in{};
+        in.nx = g.n;
+        in.ny = 1;
+        in.x0 = s->x0.data() + 3 * (size_t)g.node_off;
+        in.mass = s->mass.data() + g.node_off;
+        in.pinned = s->pinned.data() + g.node_off;
+        in.n_springs = 0;
+        // springs of this cloth, renumbered to the cloth's own node ids
+        std::vector<int> ends(2 * (size_t)g.n_springs);
+        for (int q = 0; q < 2 * g.n_springs; ++q)
+            ends[q] = s->ends[2 * (size_t)g.spring_off + q] - g.node_off;
+        in.n_springs = g.n_springs;
+        in.ends = ends.data();
+        in.k = s->k.data() + g.spring_off;
+        in.c = s->c.data() + g.spring_off;
+        stability_bounds(in, &g.omega2, &g.gamma);
+    }
+}
+
+int read_state_range(const cloth_sim* s, int group, float* x_out, float* v_out) {
+    const GroupInfo& g = s->groups[group];
+    const size_t ld = (size_t)s->dev.ld, n = (size_t)g.n;
+    std::vector<float> xs(3 * n), vs(v_out ? 3 * n : 0);
+    int flag = 0;
+    hipError_t e;
+    for (int q = 0; q < 3; ++q) {
+        if ((e = hipMemcpyAsync(xs.data() + q * n, s->dev.x[s->dev.cur] + q * ld + g.slot_off,
+                                4 * n, hipMemcpyDeviceToHost, s->stream)))
+            return hip_fail(e, "read state");
+        if (v_out && (e = hipMemcpyAsync(vs.data() + q * n, s->dev.v[s->dev.cur] + q * ld + g.slot_off,
+                                         4 * n, hipMemcpyDeviceToHost, s->stream)))
+            return hip_fail(e, "read state");
+    }
+    if ((e = hipMemcpyAsync(&flag, s->nan_flag, 4, hipMemcpyDeviceToHost, s->stream)) ||
+        (e = hipStreamSynchronize(s->stream)))
+        return hip_fail(e, "read state");
+    for (size_t p = 0; p < n; ++p) {
+        const size_t id = (size_t)(s->host.order[g.slot_off + p] - g.node_off);
+        for (int q = 0; q < 3; ++q) {
+            x_out[3 * id + q] = xs[q * n + p];
+            if (v_out) v_out[3 * id + q] = vs[q * n + p];
+        }
+    }
+    if ((s->p.flags & CLOTH_F_CHECK_NAN) && flag)
+        return fail(CLOTH_ENAN, "a non-finite value appeared in the state");
+    return CLOTH_OK;
+}
+
+int create_sim(const std::vector<ClothHostInput>& cloths, const cloth_params* p,
+               hipStream_t stream, cloth_sim** out) {
+    *out = nullptr;
+    int st = validate_params(p);
+    if (st != CLOTH_OK) return st;
+    if (cloths.empty()) return fail(CLOTH_EINVAL, "no cloth");
+    long long n_tot = 0, s_tot = 0;
+    for (size_t g = 0; g < cloths.size(); ++g) {
+        if ((st = validate_cloth(cloths[g])) != CLOTH_OK) {
+            if (cloths.size() > 1) g_last_error = "cloth " + std::to_string(g) + ": " + g_last_error;
+            return st;
+        }
+        n_tot += (long long)cloths[g].nx * cloths[g].ny;
+        s_tot += cloths[g].n_springs;
+    }
+    if (n_tot > (1LL << 28) || s_tot > (1LL << 29)) return fail(CLOTH_EINVAL, "too many nodes or springs");
+    cloth_sim* s = new (std::nothrow) cloth_sim();
+    if (!s) return fail(CLOTH_ENOMEM, "host allocation failed");
+    s->p = *p;
+    s->stream = stream;
+    s->n_nodes = (int)n_tot;
+    s->n_springs = (int)s_tot;
+    try {
+        // merged arrays in caller numbering: cloth g's node i is node node_off_g + i
+        std::vector<int> order;
+        order.reserve((size_t)n_tot);
+        s->x0.reserve(3 * (size_t)n_tot);
+        std::vector<float> v0(3 * (size_t)n_tot, 0.0f), rest;
+        int node_off = 0;
+        s->group_off.push_back(0);
+        for (const auto& in : cloths) {
+            GroupInfo g;
+            g.nx = in.nx;
+            g.ny = in.ny;
+            g.n = in.nx * in.ny;
+            g.node_off = node_off;
+            g.slot_off = (int)order.size();
+            g.n_springs = in.n_springs;
+            g.spring_off = (int)s->k.size();
+            for (int id : tile_order(in.nx, in.ny)) order.push_back(node_off + id);
+            s->x0.insert(s->x0.end(), in.x0, in.x0 + 3 * (size_t)g.n);
+            if (in.v0) std::copy(in.v0, in.v0 + 3 * (size_t)g.n, v0.begin() + 3 * (size_t)node_off);
+            s->mass.insert(s->mass.end(), in.mass, in.mass + g.n);
+            for (int i = 0; i < g.n; ++i) s->pinned.push_back(in.pinned && in.pinned[i] ? 1 : 0);
+            for (int q = 0; q < 2 * in.n_springs; ++q) s->ends.push_back(in.ends[q] + node_off);
+            rest.insert(rest.end(), in.rest, in.rest + in.n_springs);
+            s->k.insert(s->k.end(), in.k, in.k + in.n_springs);
+            s->c.insert(s->c.end(), in.c, in.c + in.n_springs);
+            s->groups.push_back(g);
+            node_off += g.n;
+            s->group_off.push_back((int)order.size());
+        }
+        ClothHostInput merged{};
+        merged.nx = (int)n_tot;
+        merged.ny = 1;
+        merged.x0 = s->x0.data();
+        merged.v0 = v0.data();
+        merged.mass = s->mass.data();
+        merged.pinned = s->pinned.data();
+        merged.n_springs = (int)s_tot;
+        merged.ends = s->ends.data();
+        merged.rest = rest.data();
+        merged.k = s->k.data();
+        merged.c = s->c.data();
+        st = build_cloth_host(merged, &s->host, &order);
+        for (size_t g = 0; g < cloths.size() && st == CLOTH_OK; ++g)
+            stability_bounds(cloths[g], &s->groups[g].omega2, &s->groups[g].gamma);
+    } catch (const std::bad_alloc&) {
+        st = fail(CLOTH_ENOMEM, "host allocation failed");
+    }
+    if (st == CLOTH_OK) st = upload_cloth(s->host, s->arena, s->stream, &s->dev);
+    if (st == CLOTH_OK) {
+        s->surfs.resize(cloths.size());
+        for (size_t g = 0; g < cloths.size() && st == CLOTH_OK; ++g) {
+            st = build_surface(cloths[g], s->p, s->arena, s->stream, &s->surfs[g]);
+            if (st != CLOTH_OK && cloths.size() > 1)
+                g_last_error = "cloth " + std::to_string(g) + ": " + g_last_error;
+            if (st == CLOTH_OK && s->surfs[g].view.n_tris > 0) s->any_collision = 1;
+        }
+    }
+    if (st == CLOTH_OK) {
+        const size_t N = (size_t)n_tot, G = cloths.size();
+        const size_t ld = (size_t)s->dev.ld;
+        std::vector<SurfaceView> svs(G);
+        for (size_t g = 0; g < G; ++g) svs[g] = s->surfs[g].view;
+        hipError_t e;
+        if ((e = s->arena.alloc(&s->nan_flag, 1)) || (e = s->arena.alloc(&s->x_init, 3 * ld)) ||
+            (e = s->arena.alloc(&s->v_init, 3 * ld)) || (e = s->arena.alloc(&s->slot_dev, N)) ||
+            (e = s->arena.alloc(&s->svs_dev, G)) ||
+            (e = hipMemsetAsync(s->nan_flag, 0, 4, s->stream)) ||
+            (e = hipMemcpyAsync(s->svs_dev, svs.data(), G * sizeof(SurfaceView),
+                                hipMemcpyHostToDevice, s->stream)) ||
+            (e = hipMemcpyAsync(s->x_init, s->dev.x[0], 12 * ld, hipMemcpyDeviceToDevice, s->stream)) ||
+            (e = hipMemcpyAsync(s->v_init, s->dev.v[0], 12 * ld, hipMemcpyDeviceToDevice, s->stream)) ||
+            (e = hipMemcpyAsync(s->slot_dev, s->host.slot.data(), 4 * N, hipMemcpyHostToDevice,
+                                s->stream)))
+            st = hip_fail(e, "create");
+        if (st == CLOTH_OK && G > 1) {
+            std::vector<int> grp(N);
+            for (size_t g = 0; g < G; ++g)
+                for (int q = s->group_off[g]; q < s->group_off[g + 1]; ++q) grp[q] = (int)g;
+            if ((e = s->arena.alloc(&s->node_group_dev, N)) ||
+                (e = hipMemcpyAsync(s->node_group_dev, grp.data(), 4 * N, hipMemcpyHostToDevice,
+                                    s->stream)))
+                st = hip_fail(e, "create");
+        }
+        if (st == CLOTH_OK && (e = hipStreamSynchronize(s->stream))) st = hip_fail(e, "create");
+    }
+    if (st != CLOTH_OK) {
+        delete s;
+        return st;
+    }
+    s->host.release_state();
+    *out = s;
+    return CLOTH_OK;
+}
+
+}  // namespace cloth
+
+using namespace cloth;
+
+extern "C" {
+
+int cloth_create(int nx, int ny, const float* x0, const float* v0, const float* mass,
+                 const unsigned char* pinned, int n_springs, const int* ends, const float* rest,
+                 const float* k, const float* c, int n_verts, const float* verts, int n_tris,
+                 const int* tris, const cloth_params* p, void* hip_stream, cloth_sim** out) {
+    if (!out) return fail(CLOTH_EINVAL, "out is NULL");
+    *out = nullptr;
+    ClothHostInput in{nx, ny, x0, v0, mass, pinned, n_springs, ends, rest, k, c, n_verts, verts,
+                      n_tris, tris};
+    return create_sim({in}, p, (hipStream_t)hip_stream, out);
+}
+
+int cloth_step(cloth_sim* s, float dt, int n_substeps, int n_steps) {
+    if (!s) return fail(CLOTH_EINVAL, "NULL handle");
+    return step_sim(s, dt, n_substeps, n_steps);
+}
+
+int cloth_set_launch(cloth_sim* s, const cloth_launch* cfg) {
+    if (!s || !cfg) return fail(CLOTH_EINVAL, "NULL argument");
+    return set_launch(s, *cfg);
+}
+
+int cloth_get_launch(const cloth_sim* s, cloth_launch* cfg) {
+    if (!s || !cfg) return fail(CLOTH_EINVAL, "NULL argument");
+    *cfg = s->launch;
+    return CLOTH_OK;
+}
+
+int cloth_read_state(const cloth_sim* s, float* x_out, float* v_out) {
+    if (!s || !x_out) return fail(CLOTH_EINVAL, "NULL argument");
+    if (s->groups.size() != 1) return fail(CLOTH_EINVAL, "use cloth_batch_read_state for a batch");
+    return read_state_range(s, 0, x_out, v_out);
+}
+
+int cloth_write_state(cloth_sim* s, const float* x, const float* v) {
+    if (!s || !x) return fail(CLOTH_EINVAL, "NULL argument");
+    const int N = s->dev.n, ld = s->dev.ld;
+    std::vector<float> xs(3 * (size_t)ld, 0.0f), vs(3 * (size_t)ld, 0.0f);
+    for (int p = 0; p < N; ++p) {
+        const int id = s->host.order[p];
+        for (int q = 0; q < 3; ++q) {
+            const float xv = x[3 * (size_t)id + q];
+            const float vv = v ? v[3 * (size_t)id + q] : 0.0f;
+            if (!std::isfinite(xv) || !std::isfinite(vv)) return fail(CLOTH_EINVAL, "non-finite state");
+            xs[(size_t)q * ld + p] = xv;
+            vs[(size_t)q * ld + p] = vv;
+        }
+    }
+    hipError_t e;
+    if ((e = hipMemcpyAsync(s->dev.x[s->dev.cur], xs.data(), 12 * (size_t)ld, hipMemcpyHostToDevice,
+                            s->stream)) ||
+        (e = hipMemcpyAsync(s->dev.v[s->dev.cur], vs.data(), 12 * (size_t)ld, hipMemcpyHostToDevice,
+                            s->stream)) ||
+        (e = hipMemsetAsync(s->nan_flag, 0, 4, s->stream)) || (e = hipStreamSynchronize(s->stream)))
+        return hip_fail(e, "write state");
+    s->roll.ready = false;
+    return CLOTH_OK;
+}
+
+int cloth_device_state(cloth_sim* s, float** x_soa, float** v_soa) {
+    if (!s) return fail(CLOTH_EINVAL, "NULL handle");
+    if (x_soa) *x_soa = s->dev.x[s->dev.cur];
+    if (v_soa) *v_soa = s->dev.v[s->dev.cur];
+    return CLOTH_OK;
+}
+
+int cloth_node_order(const cloth_sim* s, int* order) {
+    if (!s || !order) return fail(CLOTH_EINVAL, "NULL argument");
+    std::memcpy(order, s->host.order.data(), sizeof(int) * s->host.order.size());
+    return CLOTH_OK;
+}
+
+int cloth_info(const cloth_sim* s, long long* out) {
+    if (!s || !out) return fail(CLOTH_EINVAL, "NULL argument");
+    const SurfaceDevice& sf = s->surfs[0];
+    out[0] = s->dev.n;
+    out[1] = s->n_springs;
+    out[2] = sf.view.n_tris;
+    out[3] = sf.n_cells;
+    out[4] = sf.n_refs;
+    for (int q = 0; q < 3; ++q) out[5 + q] = sf.view.n_tris ? sf.view.dim[q] : 0;
+    return CLOTH_OK;
+}
+
+int cloth_destroy(cloth_sim* s) {
+    if (!s) return CLOTH_OK;
+    (void)hipStreamSynchronize(s->stream);
+    delete s;
+    return CLOTH_OK;
+}
+
+int cloth_debug_candidates(cloth_sim* s, int n_points, const float* points, int* pairs_out,
+                           long long cap, long long* n_out) {
+    if (!s || !n_out) return fail(CLOTH_EINVAL, "NULL argument");
+    if (n_points < 0 || cap < 0) return fail(CLOTH_EINVAL, "negative size");
+    if (n_points > 0 && !points) return fail(CLOTH_EINVAL, "points is NULL");
+    if (cap > 0 && !pairs_out) return fail(CLOTH_EINVAL, "pairs_out is NULL");
+    const SurfaceView& sv = s->surfs[0].view;
+    if (sv.n_tris == 0) return fail(CLOTH_EINVAL, "collision is disabled for this handle");
+    *n_out = 0;
+    if (n_points == 0) return CLOTH_OK;
+    DeviceArena tmp;
+    float* d_p;
+    uint32_t *d_cnt, *d_off, *d_scan;
+    hipError_t e;
+    const size_t n = (size_t)n_points;
+    if ((e = tmp.alloc(&d_p, 3 * n)) || (e = tmp.alloc(&d_cnt, n)) || (e = tmp.alloc(&d_off, n + 1)) ||
+        (e = tmp.alloc(&d_scan, scan_tmp_words(n))))
+        return hip_fail(e, "hipMalloc candidates");
+    std::vector<float> soa(3 * n);
+    for (size_t i = 0; i < n; ++i)
+        for (int q = 0; q < 3; ++q) soa[q * n + i] = points[3 * i + q];
+    uint32_t total = 0;
+    if ((e = hipMemcpyAsync(d_p, soa.data(), 12 * n, hipMemcpyHostToDevice, s->stream)) ||
+        (e = launch_candidates_count(n_points, n_points, d_p, sv, d_cnt, s->stream)) ||
+        (e = scan_exclusive_u32(d_cnt, d_off, n, d_scan, s->stream)) ||
+        (e = hipMemcpyAsync(&total, d_off + n, 4, hipMemcpyDeviceToHost, s->stream)) ||
+        (e = hipStreamSynchronize(s->stream)))
+        return hip_fail(e, "candidate count");
+    *n_out = total;
+    if (total == 0 || cap == 0) return CLOTH_OK;
+    int* d_pairs;
+    if ((e = tmp.alloc(&d_pairs, 2 * (size_t)total))) return hip_fail(e, "hipMalloc pairs");
+    const size_t ncopy = (size_t)std::min<long long>(cap, total);
+    if ((e = launch_candidates_write(n_points, n_points, d_p, sv, d_off, d_pairs, s->stream)) ||
+        (e = hipMemcpyAsync(pairs_out, d_pairs, 8 * ncopy, hipMemcpyDeviceToHost, s->stream)) ||
+        (e = hipStreamSynchronize(s->stream)))
+        return hip_fail(e, "candidate write");
+    return CLOTH_OK;
+}
+
+int cloth_stability_bound(int n_nodes, const float* x0, const float* mass,
+                          const unsigned char* pinned, int n_springs, const int* ends,
+                          const float* k, const float* c, double* omega2, double* gamma) {
+    if (!omega2 || !gamma) return fail(CLOTH_EINVAL, "NULL output");
+    std::vector<float> rest((size_t)std::max(n_springs, 0), 1.0f);
+    ClothHostInput in{n_nodes, 1, x0, nullptr, mass, pinned, n_springs, ends, rest.data(), k, c,
+                      0, nullptr, 0, nullptr};
+    if (int st = validate_cloth(in)) return st;
+    stability_bounds(in, omega2, gamma);
+    return CLOTH_OK;
+}
+
+const char* cloth_status_str(int status) {
+    switch (status) {
+        case CLOTH_OK: return "CLOTH_OK";
+        case CLOTH_EINVAL: return "CLOTH_EINVAL: invalid argument";
+        case CLOTH_ENOMEM: return "CLOTH_ENOMEM: out of memory or size limit";
+        case CLOTH_EDEVICE: return "CLOTH_EDEVICE: HIP runtime or kernel failure";
+        case CLOTH_EUNSTABLE: return "CLOTH_EUNSTABLE: substep exceeds the stability bound";
+        case CLOTH_ESTATE: return "CLOTH_ESTATE: call out of order";
+        case CLOTH_ENAN: return "CLOTH_ENAN: non-finite state";
+        default: return "unknown cloth status";
+    }
+}
+
+const char* cloth_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -14,11 +14,12 @@
 
 namespace cloth {
 
-template <bool COLLIDE>
+template <bool COLLIDE, bool GROUPED>
 __global__ void __launch_bounds__(256)
-    k_substep(const ClothView cv, const SurfaceView sv, const StepParams sp,
+    k_substep(const ClothView cv, const SurfaceView sv1, const StepParams sp,
               const float* __restrict__ xs, const float* __restrict__ vs, float* __restrict__ xd,
-              float* __restrict__ vd) {
+              float* __restrict__ vd, const SurfaceView* __restrict__ svs,
+              const int* __restrict__ node_group) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cv.n) return;
     const int ld = cv.ld;
@@ -38,48 +39,15 @@ __global__ void __launch_bounds__(256)
                      fz);
     }
 
-    // a2: integrate
-    float px = xi, py = yi, pz = zi, qx = 0.0f, qy = 0.0f, qz = 0.0f;
-    if (w != 0.0f) {
-        const float h = sp.h;
-        qx = vxi + h * (w * fx + sp.g[0]);
-        qy = vyi + h * (w * fy + sp.g[1]);
-        qz = vzi + h * (w * fz + sp.g[2]);
-        px = xi + h * qx;
-        py = yi + h * qy;
-        pz = zi + h * qz;
-    }
-
-    // a3 + a4
+    // a2: integrate; a3 + a4: broad phase, narrow phase, response
+    float px, py, pz, qx, qy, qz;
+    integrate(w, sp.h, sp.g, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz, px, py, pz, qx, qy, qz);
     if (COLLIDE && w != 0.0f) {
-        const int cell = cell_of(sv, px, py, pz);
-        const uint32_t b = sv.cell_start[cell], e = sv.cell_start[cell + 1];
-        float sx = 0.0f, sy = 0.0f, sz = 0.0f;
-        int cnt = 0;
-        for (uint32_t r = b; r < e; ++r) {
-            const uint32_t t = sv.refs[r];
-            if (!in_box(sv.box_lo[t], sv.box_hi[t], px, py, pz)) continue;
-            const float4 A = sv.geo[4 * t], e1 = sv.geo[4 * t + 1], e2 = sv.geo[4 * t + 2],
-                         n = sv.geo[4 * t + 3];
-            const float ax = px - A.x, ay = py - A.y, az = pz - A.z;
-            const float s = ax * n.x + ay * n.y + az * n.z;
-            const float d2 = point_tri_dist2(ax, ay, az, e1.x, e1.y, e1.z, e2.x, e2.y, e2.z, s);
-            if (d2 < sv.thickness2) {
-                const float push = sv.thickness - s;
-                sx += push * n.x;
-                sy += push * n.y;
-                sz += push * n.z;
-                ++cnt;
-            }
-        }
-        if (cnt > 0) {
-            const float inv = 1.0f / (float)cnt;
-            px += sx * inv;
-            py += sy * inv;
-            pz += sz * inv;
-            qx = -sp.restitution * qx;
-            qy = -sp.restitution * qy;
-            qz = -sp.restitution * qz;
+        if (GROUPED) {
+            const SurfaceView sv = svs[node_group[i]];
+            if (sv.n_tris > 0) collide(sv, sp.restitution, px, py, pz, qx, qy, qz);
+        } else {
+            collide(sv1, sp.restitution, px, py, pz, qx, qy, qz);
         }
     }
 
@@ -97,14 +65,19 @@ __global__ void __launch_bounds__(256)
 
 hipError_t launch_substep(const ClothView& cv, const SurfaceView& sv, const StepParams& sp,
                           const float* xs, const float* vs, float* xd, float* vd, int block,
-                          hipStream_t stream) {
+                          hipStream_t stream, const SurfaceView* svs, const int* node_group) {
     if (cv.n <= 0) return hipSuccess;
     if (block <= 0 || block > 256 || (block & 63)) block = 256;
     const int grid = (cv.n + block - 1) / block;
-    if (sv.n_tris > 0)
-        k_substep<true><<<grid, block, 0, stream>>>(cv, sv, sp, xs, vs, xd, vd);
+    if (svs && node_group)
+        k_substep<true, true><<<grid, block, 0, stream>>>(cv, sv, sp, xs, vs, xd, vd, svs,
+                                                          node_group);
+    else if (sv.n_tris > 0)
+        k_substep<true, false><<<grid, block, 0, stream>>>(cv, sv, sp, xs, vs, xd, vd, nullptr,
+                                                           nullptr);
     else
-        k_substep<false><<<grid, block, 0, stream>>>(cv, sv, sp, xs, vs, xd, vd);
+        k_substep<false, false><<<grid, block, 0, stream>>>(cv, sv, sp, xs, vs, xd, vd, nullptr,
+                                                            nullptr);
     return hipGetLastError();
 }
 

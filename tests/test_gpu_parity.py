@@ -180,3 +180,50 @@ def test_nan_flag_reported():
         with pytest.raises(B.ClothError) as ei:
             sim.read_state()
         assert ei.value.status == B.CLOTH_ENAN
+
+
+LAUNCHES = [
+    dict(kernel=B.CLOTH_KERNEL_DIRECT, block_threads=64, use_graph=0),
+    dict(kernel=B.CLOTH_KERNEL_DIRECT, block_threads=256, use_graph=1),
+    dict(kernel=B.CLOTH_KERNEL_TILE, tile_nodes=64, substeps_per_launch=1, use_graph=0),
+    dict(kernel=B.CLOTH_KERNEL_TILE, tile_nodes=256, substeps_per_launch=2, use_graph=1),
+    dict(kernel=B.CLOTH_KERNEL_TILE, tile_nodes=256, substeps_per_launch=3, use_graph=1),
+    dict(kernel=B.CLOTH_KERNEL_TILE, tile_nodes=1024, substeps_per_launch=4, block_threads=128,
+         use_graph=1),
+    dict(kernel=B.CLOTH_KERNEL_TILE, tile_nodes=128, substeps_per_launch=8, use_graph=0),
+]
+
+
+@pytest.mark.parametrize("scene", ["small", "config1_64"])
+def test_every_launch_configuration_is_bit_identical(scene):
+    if scene == "small":
+        inp = W.small_collision_scene(n=40, n_steps=90, spacing=0.008)
+    else:
+        inp = W.config1(n=64, freq=20, n_steps=150)
+    outs = []
+    for cfg in LAUNCHES:
+        with B.Cloth(inp) as sim:
+            sim.set_launch(**cfg)
+            # an odd substep count exercises the remainder launch and graph parity
+            sim.step(n_steps=inp.n_steps)
+            sim.step(dt=h32(inp), n_substeps=1, n_steps=3)
+            outs.append((cfg, *sim.read_state()))
+    ref = outs[0]
+    for cfg, x, v in outs[1:]:
+        assert np.array_equal(x, ref[1]) and np.array_equal(v, ref[2]), cfg
+    moved = np.abs(ref[1] - inp.x0).max()
+    assert moved > 0.01
+
+
+def test_tile_kernel_default_matches_oracle_one_substep():
+    inp = W.config1(n=96, freq=24)
+    model = oracle.Model.from_inputs(inp)
+    with B.Cloth(inp) as sim:
+        assert sim.get_launch()["kernel"] == B.CLOTH_KERNEL_TILE
+        sim.step(n_steps=120)
+        for _ in range(3):
+            x, v = sim.read_state()
+            sim.step(dt=h32(inp), n_substeps=1, n_steps=1)
+            x1, v1 = sim.read_state()
+            r = one_substep_check(inp, x, v, x1, v1, model, tag="tile default")
+    assert r["contacts"] > 100
