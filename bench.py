@@ -39,7 +39,97 @@ def parse():
                     help="launch configuration, e.g. kernel=tile,tile=256,K=4,block=256,graph=1")
     ap.add_argument("--sweep", action="store_true",
                     help="time several launch configurations on the draped state and exit")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched comparison")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint comparison")
+    ap.add_argument("--batch-cloths", type=int, default=512)
     return ap.parse_args()
+
+
+def bench_batched(n_cloths: int, frames: int):
+    """512 cloths of side U{16..128}, each over its own 5,120-triangle sphere: one batch handle
+    (autotuned launch configuration) against plain per-cloth handles stepped one after another,
+    both on this GPU.  Returns node-updates/s of each and the final-state bit identity."""
+    import torch
+
+    from paper_2507_11794_amd import cloth, workloads
+
+    cl = workloads.config3(n_cloths=n_cloths)
+    n_nodes = sum(c.n_nodes for c in cl)
+    sub = cl[0].n_substeps
+    stream = torch.cuda.current_stream()
+    b = cloth.ClothBatch(cl, stream=stream.cuda_stream)
+    tuned = b.autotune(frames=2)
+    b.step(n_steps=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(n_steps=frames)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    xb = [b.read_state(i)[0] for i in (0, n_cloths // 2, n_cloths - 1)]
+    b.close()
+    sims = [cloth.Cloth(c, stream=stream.cuda_stream) for c in cl]
+    for s_ in sims:
+        s_.step(n_steps=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s_ in sims:
+        s_.step(n_steps=frames)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    same = all(np.array_equal(sims[i].read_state()[0], x)
+               for i, x in zip((0, n_cloths // 2, n_cloths - 1), xb))
+    for s_ in sims:
+        s_.close()
+    upd = n_nodes * sub * frames
+    return {"cloths": n_cloths, "nodes": n_nodes, "frames": frames,
+            "batched_node_updates_per_s": upd / t_batch,
+            "plain_per_cloth_node_updates_per_s": upd / t_plain,
+            "speedup": t_plain / t_batch, "launch": tuned,
+            "bit_identical_sampled_cloths": bool(same)}
+
+
+def bench_adjoint(frames: int = 200):
+    """64x64 cloth over a 2,000-triangle sphere, trajectory loss on the final frame, gradients
+    for per-spring k, c and v0 with checkpoints every 20 frames: forward + recompute + backward
+    against plain forward stepping of the same frames on this GPU."""
+    import torch
+
+    from paper_2507_11794_amd import cloth, workloads
+    from paper_2507_11794_amd.rollout import ClothRollout
+
+    inp, k_hat = workloads.config4(n_steps=frames)
+    dev = torch.device("cuda")
+    stream = torch.cuda.current_stream()
+    sim = cloth.Cloth(inp, stream=stream.cuda_stream)
+    sim.step(n_steps=frames)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim2 = cloth.Cloth(inp, stream=stream.cuda_stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim2.step(n_steps=frames)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    k = torch.tensor(inp.k, device=dev, requires_grad=True)
+    c = torch.tensor(inp.c, device=dev, requires_grad=True)
+    v0 = torch.zeros((inp.n_nodes, 3), device=dev, requires_grad=True)
+    target = torch.zeros((inp.n_nodes, 3), device=dev)
+    for rep in range(2):  # the first pass allocates the checkpoint buffers
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = ClothRollout.apply(sim, k, c, v0, inp.dt, inp.n_substeps, frames, 20, [frames])
+        loss = ((x[0] - target) ** 2).sum(dim=1).mean()
+        loss.backward()
+        torch.cuda.synchronize()
+        t_grad = time.perf_counter() - t0
+        k.grad = c.grad = v0.grad = None
+    sim.close()
+    sim2.close()
+    upd = inp.n_nodes * inp.n_substeps * frames
+    return {"nodes": inp.n_nodes, "frames": frames, "checkpoint_frames": 20,
+            "plain_forward_node_updates_per_s": upd / t_plain,
+            "forward_backward_node_updates_per_s": upd / t_grad,
+            "gradient_cost_vs_plain": t_grad / t_plain}
 
 
 def parse_launch(text: str) -> dict:
@@ -47,7 +137,7 @@ def parse_launch(text: str) -> dict:
 
     cfg = {}
     names = {"tile": "tile_nodes", "K": "substeps_per_launch", "block": "block_threads",
-             "graph": "use_graph"}
+             "graph": "use_graph", "stage": "stage_refs", "sched": "schedule", "wg": "workgroups"}
     for part in filter(None, text.split(",")):
         k, v = part.split("=")
         if k == "kernel":
@@ -58,12 +148,12 @@ def parse_launch(text: str) -> dict:
 
 
 SWEEP = [
-    "kernel=direct,block=64,graph=0", "kernel=direct,block=256,graph=0",
-    "kernel=direct,block=256,graph=1",
-    "kernel=tile,tile=256,K=1", "kernel=tile,tile=256,K=2", "kernel=tile,tile=256,K=4",
-    "kernel=tile,tile=128,K=2", "kernel=tile,tile=128,K=4", "kernel=tile,tile=512,K=2",
-    "kernel=tile,tile=512,K=4", "kernel=tile,tile=1024,K=4", "kernel=tile,tile=256,K=4,block=128",
-    "kernel=tile,tile=64,K=1", "kernel=tile,tile=256,K=8",
+    "kernel=direct,stage=0", "kernel=direct,stage=256", "kernel=direct,stage=512",
+    "kernel=direct,stage=1024", "kernel=direct,block=128,stage=512",
+    "kernel=tile,tile=64,K=1,stage=384", "kernel=tile,tile=256,K=1,stage=0",
+    "kernel=tile,tile=256,K=1,stage=384", "kernel=tile,tile=256,K=2,stage=256",
+    "kernel=tile,tile=128,K=2,stage=384", "kernel=tile,tile=256,K=4,stage=256",
+    "kernel=tile,tile=512,K=2,stage=256",
 ]
 
 
@@ -229,6 +319,10 @@ def main():
             "avg_launch_us": kernel_s * 1e6,
         },
     }
+    if not args.no_batch:
+        out["batched"] = bench_batched(args.batch_cloths, 200)
+    if not args.no_adjoint:
+        out["adjoint"] = bench_adjoint(200)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inp, x, v, args.cpu_seconds)
     print(json.dumps(out))

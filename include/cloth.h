@@ -83,6 +83,8 @@ typedef struct cloth_launch {
     int use_graph;           /* nonzero: replay launches from a captured hipGraph */
     int schedule;            /* tile kernel: enum cloth_schedule */
     int workgroups;          /* persistent schedules: number of workgroups (> 0) */
+    int stage_refs;          /* grid references staged in LDS per wavefront for the
+                                collision query, 0..1024 (0 = read them from memory) */
 } cloth_launch;
 
 /*
@@ -149,8 +151,8 @@ int cloth_info(const cloth_sim* sim, long long* out);
 
 /*
  * cloth_set_launch / cloth_get_launch -- choose how cloth_step schedules substeps.
- * Default: tile kernel, 256 tile nodes, 4 substeps per launch, 256 threads, graphs on,
- * grid schedule.
+ * Default: tile kernel, 256 tile nodes, 1 substep per launch, 256 threads, graphs on,
+ * grid schedule, 384 staged references.
  * cloth_set_launch validates the configuration and rebuilds the tile plan if needed
  * (synchronises the handle's stream).  Errors: CLOTH_EINVAL for an out-of-range field or a
  * tile region that does not fit in LDS (the previous configuration stays in effect).
@@ -272,6 +274,14 @@ int cloth_batch_autotune(cloth_batch* b, float dt, int n_substeps, int frames, c
 int cloth_batch_info(const cloth_batch* b, long long* out);
 /* cloth_batch_destroy -- NULL is accepted. */
 int cloth_batch_destroy(cloth_batch* b);
+
+/*
+ * cloth_debug_contacts -- the contact set every node would get in a substep of length h
+ * from the current state, with the step's own arithmetic: counts[i] triangles, the first
+ * min(counts[i], cap) of them (ascending id) at ids[i*cap ...].  counts, ids [host] in node-id
+ * order ([N], [N*cap]).  Single-cloth handles.  Synchronises.
+ */
+int cloth_debug_contacts(cloth_sim* sim, float h, int* counts, int* ids, int cap);
 
 /* cloth_status_str -- static text for a status code. */
 const char* cloth_status_str(int status);

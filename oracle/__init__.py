@@ -62,6 +62,7 @@ def _load():
     lib.orc_candidates_f32.restype = C.c_longlong
     lib.orc_candidates_f32.argtypes = [C.c_int, fp, C.c_int, fp, ip, C.c_float, ip, C.c_longlong]
     lib.orc_substep_vjp.argtypes = [P, dp, dp, C.c_double, dp, dp, dp, dp, dp, dp]
+    lib.orc_substep_vjp_given.argtypes = [P, dp, dp, C.c_double, ip, ip, dp, dp, dp, dp, dp, dp]
     lib.orc_rollout_grad.argtypes = [P, dp, dp, C.c_double, C.c_int, C.c_int, ip, dp, C.c_int,
                                      dp, dp, dp, dp, dp]
     lib.orc_model_triangle.argtypes = [P, C.c_int, dp, dp, dp, dp]
@@ -193,6 +194,22 @@ class Model:
         kb, cb = np.zeros(self.S), np.zeros(self.S)
         self._lib.orc_substep_vjp(self._h, _dp(x), _dp(v), float(h), _dp(xbo), _dp(vbo),
                                   _dp(xbi), _dp(vbi), _dp(kb), _dp(cb))
+        return xbi, vbi, kb, cb
+
+    def substep_vjp_given(self, x, v, h, contacts, xb_out, vb_out):
+        """Adjoint of one substep at (x, v) with node i's contact triangles given as
+        contacts[i] (a sequence of ids); returns (xb_in, vb_in, kb, cb)."""
+        x, v = _d(x).reshape(-1, 3), _d(v).reshape(-1, 3)
+        off = np.zeros(self.N + 1, dtype=np.int32)
+        off[1:] = np.cumsum([len(c) for c in contacts])
+        ids = _i(np.concatenate([np.sort(np.asarray(c, dtype=np.int64)) for c in contacts])
+                 if off[-1] else np.zeros(1))
+        xbo, vbo = _d(xb_out).reshape(-1, 3), _d(vb_out).reshape(-1, 3)
+        xbi, vbi = np.zeros((self.N, 3)), np.zeros((self.N, 3))
+        kb, cb = np.zeros(self.S), np.zeros(self.S)
+        self._lib.orc_substep_vjp_given(self._h, _dp(x), _dp(v), float(h), _ip(off), _ip(ids),
+                                        _dp(xbo), _dp(vbo), _dp(xbi), _dp(vbi), _dp(kb),
+                                        _dp(cb))
         return xbi, vbi, kb, cb
 
     def rollout_grad(self, x0, v0, h, n_sub, out_sub, xbar, ckpt=1):

@@ -524,6 +524,76 @@ void orc_substep_vjp(const orc_model *m, const double *x, const double *v, doubl
     free(Fb);
 }
 
+/* The same adjoint with the contact set given explicitly instead of recomputed: node i's
+ * contact triangles are ids[off[i] .. off[i+1]) (ascending).  Used to evaluate the adjoint
+ * on another implementation's trajectory and contact decisions. */
+void orc_substep_vjp_given(const orc_model *m, const double *x, const double *v, double h,
+                           const int *off, const int *ids, const double *xb_out,
+                           const double *vb_out, double *xb_in, double *vb_in, double *kb,
+                           double *cb)
+{
+    int N = m->N;
+    double *F = malloc(sizeof(double) * 3 * (size_t)N);
+    double *Fb = calloc(3 * (size_t)N, sizeof(double));
+    orc_forces(m, x, v, F);
+    for (int i = 0; i < N; ++i) {
+        if (m->w[i] == 0.0) {
+            for (int q = 0; q < 3; ++q) { xb_in[3 * i + q] = xb_out[3 * i + q]; vb_in[3 * i + q] = 0.0; }
+            continue;
+        }
+        int n = off[i + 1] - off[i];
+        double xbs[3], vbs[3];
+        for (int q = 0; q < 3; ++q) { xbs[q] = xb_out[3 * i + q]; vbs[q] = vb_out[3 * i + q]; }
+        if (n > 0) {
+            double acc[3] = {0, 0, 0};
+            for (int r = 0; r < n; ++r) {
+                const double *nt = m->tn + 3 * ids[off[i] + r];
+                double s = dot3(nt, xbs);
+                for (int q = 0; q < 3; ++q) acc[q] += s * nt[q];
+            }
+            for (int q = 0; q < 3; ++q) {
+                xbs[q] = xbs[q] - acc[q] / n;
+                vbs[q] = -m->restitution * vbs[q];
+            }
+        }
+        for (int q = 0; q < 3; ++q) {
+            double vtot = vbs[q] + h * xbs[q];
+            xb_in[3 * i + q] = xbs[q];
+            vb_in[3 * i + q] = vtot;
+            Fb[3 * i + q] = h * m->w[i] * vtot;
+        }
+    }
+    for (int s = 0; s < m->S; ++s) {
+        int a = m->ends[2 * s], b = m->ends[2 * s + 1];
+        double d[3], u[3], dv[3], lam[3];
+        sub3(x + 3 * b, x + 3 * a, d);
+        sub3(v + 3 * b, v + 3 * a, dv);
+        sub3(Fb + 3 * a, Fb + 3 * b, lam);
+        double len = sqrt(dot3(d, d));
+        for (int q = 0; q < 3; ++q) u[q] = d[q] / len;
+        double dvu = dot3(dv, u);
+        double phi = m->k[s] * (len - m->rest[s]) + m->c[s] * dvu;
+        double ul = dot3(u, lam);
+        double db[3], dvb[3];
+        for (int q = 0; q < 3; ++q) {
+            double perp_l = lam[q] - u[q] * ul;
+            double perp_dv = dv[q] - u[q] * dvu;
+            db[q] = phi / len * perp_l + m->k[s] * u[q] * ul + m->c[s] / len * perp_dv * ul;
+            dvb[q] = m->c[s] * u[q] * ul;
+        }
+        for (int q = 0; q < 3; ++q) {
+            xb_in[3 * b + q] += db[q];
+            xb_in[3 * a + q] -= db[q];
+            vb_in[3 * b + q] += dvb[q];
+            vb_in[3 * a + q] -= dvb[q];
+        }
+        if (kb) kb[s] += (len - m->rest[s]) * ul;
+        if (cb) cb[s] += dvu * ul;
+    }
+    free(F);
+    free(Fb);
+}
+
 /* ------------------------------------------------------------------ rollout gradient */
 
 /* Run n_sub substeps from (x0, v0) and back-propagate.

@@ -55,3 +55,36 @@ def substep_parity(model, x, v, h, x1, v1, L, border=1e-6, xtol=2e-6, vtol_abs=2
     return dict(contacts=int(np.count_nonzero(cnt)), ambiguous=int(amb.sum()),
                 resolved=resolved, ex=float(ex[clean].max() / L) if clean.any() else 0.0,
                 ev=float(ev[clean].max()) if clean.any() else 0.0)
+
+
+def resolve_contacts(model, x, v, h, x1, v1, L, border=1e-6, xtol=2e-6, vtol_abs=2e-3,
+                     vtol_rel=1e-4):
+    """The contact set another implementation used in one substep from (x, v) to (x1, v1):
+    per node, the oracle's sure contacts plus the subset of near-threshold triangles whose
+    response reproduces (x1, v1).  Raises AssertionError if no valid set does."""
+    x64, v64 = np.asarray(x, np.float64), np.asarray(v, np.float64)
+    X1, V1 = np.asarray(x1, np.float64), np.asarray(v1, np.float64)
+    xs, vs = model.predict(x64, v64, h)
+    th = model.thickness
+    vtol = vtol_abs + vtol_rel * float(np.abs(vs).max())
+    out = []
+    for i in range(x64.shape[0]):
+        if model.w[i] == 0.0 or th <= 0:
+            out.append([])
+            continue
+        ids, dist = model.box_candidates(xs[i])
+        sure = [int(t) for t, d in zip(ids, dist) if d < th - border]
+        maybe = [int(t) for t, d in zip(ids, dist) if abs(d - th) <= border]
+        found = None
+        for r in range(len(maybe) + 1):
+            for sub in itertools.combinations(maybe, r):
+                cs = sorted(sure + list(sub))
+                p, q = model.respond(xs[i], vs[i], cs)
+                if np.abs(p - X1[i]).max() <= xtol * L and np.abs(q - V1[i]).max() <= vtol:
+                    found = cs
+                    break
+            if found is not None:
+                break
+        assert found is not None, ("no contact set reproduces node", i)
+        out.append(found)
+    return out

@@ -33,7 +33,7 @@ class ClothError(RuntimeError):
 class cloth_launch(C.Structure):
     _fields_ = [("kernel", C.c_int), ("tile_nodes", C.c_int), ("substeps_per_launch", C.c_int),
                 ("block_threads", C.c_int), ("use_graph", C.c_int), ("schedule", C.c_int),
-                ("workgroups", C.c_int)]
+                ("workgroups", C.c_int), ("stage_refs", C.c_int)]
 
 
 CLOTH_KERNEL_TILE, CLOTH_KERNEL_DIRECT = 0, 1
@@ -89,6 +89,7 @@ _SIGNATURES = [
     ("cloth_batch_autotune", C.c_int, [_vp, C.c_float, C.c_int, C.c_int, C.POINTER(cloth_launch)]),
     ("cloth_batch_info", C.c_int, [_vp, _llp]),
     ("cloth_batch_destroy", C.c_int, [_vp]),
+    ("cloth_debug_contacts", C.c_int, [_vp, C.c_float, _ip, _ip, C.c_int]),
     ("cloth_status_str", C.c_char_p, [C.c_int]),
     ("cloth_last_error", C.c_char_p, []),
 ]
@@ -229,10 +230,12 @@ def cloth_debug_candidates(h, points):
     return pairs[:n.value].copy()
 
 
-def make_launch(kernel=CLOTH_KERNEL_TILE, tile_nodes=256, substeps_per_launch=4,
-                block_threads=256, use_graph=1, schedule=CLOTH_SCHED_GRID, workgroups=0):
+def make_launch(kernel=CLOTH_KERNEL_TILE, tile_nodes=256, substeps_per_launch=1,
+                block_threads=256, use_graph=1, schedule=CLOTH_SCHED_GRID, workgroups=0,
+                stage_refs=384):
     return cloth_launch(int(kernel), int(tile_nodes), int(substeps_per_launch),
-                        int(block_threads), int(use_graph), int(schedule), int(workgroups))
+                        int(block_threads), int(use_graph), int(schedule), int(workgroups),
+                        int(stage_refs))
 
 
 def launch_dict(cfg: cloth_launch) -> dict:
@@ -327,6 +330,15 @@ class Cloth:
 
     def debug_candidates(self, points):
         return cloth_debug_candidates(self.h, points)
+
+    def debug_contacts(self, h, cap=16):
+        """Per node, the ascending triangle ids of its contacts in a substep of length h."""
+        counts = np.zeros(self.n, dtype=np.int32)
+        ids = np.zeros(self.n * cap, dtype=np.int32)
+        _check(load().cloth_debug_contacts(_vp(self.h), float(h), _ptr(counts, _ip),
+                                           _ptr(ids, _ip), int(cap)))
+        assert counts.max(initial=0) <= cap, "raise cap"
+        return [ids[i * cap:i * cap + counts[i]].tolist() for i in range(self.n)]
 
     def autotune(self, frames=10, dt=None, n_substeps=None):
         return cloth_autotune(self.h, self.inp.dt if dt is None else dt,

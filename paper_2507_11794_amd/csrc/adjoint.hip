@@ -46,21 +46,13 @@ __global__ void __launch_bounds__(256)
     }
     // recompute the forward prediction exactly as the forward kernels do
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-    const int deg = cv.deg[i];
-    const int base = cv.slice_ptr[i >> 6] + (i & 63);
-    for (int r = 0; r < deg; ++r) {
-        const int q = base + r * 64;
-        const int j = cv.nbr[q];
-        spring_force(xs[j] - xi, xs[ld + j] - yi, xs[2 * ld + j] - zi, vs[j] - vxi,
-                     vs[ld + j] - vyi, vs[2 * ld + j] - vzi, cv.ik[q], cv.ic[q], cv.il[q], fx, fy,
-                     fz);
-    }
+    gather_global(cv, xs, vs, i, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz);
     float px, py, pz, qx, qy, qz;
     integrate(w, sp.h, sp.g, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz, px, py, pz, qx, qy, qz);
     float sx = bx, sy = by, sz = bz, tx = cx, ty = cy, tz = cz;
     if (sv.n_tris > 0) {
         float ax = 0.0f, ay = 0.0f, az = 0.0f;
-        const int cnt = contacts_visit(sv, px, py, pz, [&](const float4& n, float) {
+        const int cnt = contacts_visit(sv, px, py, pz, [&](const float4& n, float, uint32_t) {
             const float proj = n.x * bx + n.y * by + n.z * bz;
             ax += proj * n.x;
             ay += proj * n.y;
@@ -143,6 +135,34 @@ __global__ void __launch_bounds__(256)
     vb_in[2 * ld + i] = hz;
 }
 
+// Contact set each node would get in a substep of length h from (xs, vs): counts[slot] and
+// up to cap triangle ids at ids[slot*cap ...] (ascending).  Same arithmetic as the step.
+__global__ void __launch_bounds__(256)
+    k_debug_contacts(const ClothView cv, const SurfaceView sv, const StepParams sp,
+                     const float* __restrict__ xs, const float* __restrict__ vs, int* counts,
+                     int* ids, int cap) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cv.n) return;
+    const int ld = cv.ld;
+    const float w = cv.w[i];
+    if (w == 0.0f || sv.n_tris == 0) {
+        counts[i] = 0;
+        return;
+    }
+    const float xi = xs[i], yi = xs[ld + i], zi = xs[2 * ld + i];
+    const float vxi = vs[i], vyi = vs[ld + i], vzi = vs[2 * ld + i];
+    float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+    gather_global(cv, xs, vs, i, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz);
+    float px, py, pz, qx, qy, qz;
+    integrate(w, sp.h, sp.g, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz, px, py, pz, qx, qy, qz);
+    int n = 0;
+    const int cnt = contacts_visit(sv, px, py, pz, [&](const float4&, float, uint32_t t) {
+        if (n < cap) ids[(size_t)i * cap + n] = (int)t;
+        ++n;
+    });
+    counts[i] = cnt;
+}
+
 // out_soa[k*ld + slot[id]] (+)= in_aos[3*id + k]
 __global__ void k_import(int n, int ld, const int* __restrict__ slot, const float* __restrict__ aos,
                          float* __restrict__ soa, int accumulate) {
@@ -213,6 +233,14 @@ hipError_t launch_adj_springs(const ClothView& cv, const float* xs, const float*
     if (cv.n <= 0) return hipSuccess;
     k_adj_springs<<<blocks(cv.n, 256), 256, 0, st>>>(cv, xs, vs, fb, xb_part, vb_part, xb_in,
                                                      vb_in, kb, cb);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_contacts(const ClothView& cv, const SurfaceView& sv, const StepParams& sp,
+                                const float* xs, const float* vs, int* counts, int* ids, int cap,
+                                hipStream_t st) {
+    if (cv.n <= 0) return hipSuccess;
+    k_debug_contacts<<<blocks(cv.n, 256), 256, 0, st>>>(cv, sv, sp, xs, vs, counts, ids, cap);
     return hipGetLastError();
 }
 

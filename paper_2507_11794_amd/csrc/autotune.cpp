@@ -66,7 +66,7 @@ bool cache_lookup(const std::string& key, cloth_launch* out) {
         std::string k;
         cloth_launch c{};
         if (is >> k >> c.kernel >> c.tile_nodes >> c.substeps_per_launch >> c.block_threads >>
-            c.use_graph >> c.schedule >> c.workgroups) {
+            c.use_graph >> c.schedule >> c.workgroups >> c.stage_refs) {
             if (k == key && check_launch(c) == CLOTH_OK) {
                 *out = c;
                 found = true;  // the last entry for a key wins
@@ -81,19 +81,27 @@ void cache_store(const std::string& key, const cloth_launch& c) {
     if (!path || !*path) return;
     std::ofstream f(path, std::ios::app);
     f << key << ' ' << c.kernel << ' ' << c.tile_nodes << ' ' << c.substeps_per_launch << ' '
-      << c.block_threads << ' ' << c.use_graph << ' ' << c.schedule << ' ' << c.workgroups << '\n';
+      << c.block_threads << ' ' << c.use_graph << ' ' << c.schedule << ' ' << c.workgroups << ' '
+      << c.stage_refs << '\n';
 }
 
-std::vector<cloth_launch> candidates(int cus) {
+std::vector<cloth_launch> candidates(int cus, bool collide) {
     std::vector<cloth_launch> v;
-    v.push_back({CLOTH_KERNEL_DIRECT, 256, 1, 256, 1, CLOTH_SCHED_GRID, 0});
-    const int tk[][2] = {{256, 1}, {128, 2}, {256, 2}, {512, 2}, {128, 4},
-                         {256, 4}, {512, 4}, {1024, 4}, {256, 8}};
-    for (const auto& t : tk) v.push_back({CLOTH_KERNEL_TILE, t[0], t[1], 256, 1, CLOTH_SCHED_GRID, 0});
-    v.push_back({CLOTH_KERNEL_TILE, 256, 4, 128, 1, CLOTH_SCHED_GRID, 0});
+    const int stages[] = {0, 256, 512};
+    for (int st : stages) {
+        if (!collide && st) continue;
+        v.push_back({CLOTH_KERNEL_DIRECT, 256, 1, 256, 1, CLOTH_SCHED_GRID, 0, st});
+        v.push_back({CLOTH_KERNEL_DIRECT, 256, 1, 128, 1, CLOTH_SCHED_GRID, 0, st});
+    }
+    const int tk[][2] = {{64, 1}, {256, 1}, {128, 2}, {256, 2}, {128, 4}, {256, 4}, {512, 4}};
+    for (const auto& t : tk)
+        for (int st : stages) {
+            if (!collide && st) continue;
+            v.push_back({CLOTH_KERNEL_TILE, t[0], t[1], 256, 1, CLOTH_SCHED_GRID, 0, st});
+        }
     for (int m : {2, 4}) {
-        v.push_back({CLOTH_KERNEL_TILE, 256, 4, 256, 1, CLOTH_SCHED_LPT, m * cus});
-        v.push_back({CLOTH_KERNEL_TILE, 256, 4, 256, 1, CLOTH_SCHED_RR, m * cus});
+        v.push_back({CLOTH_KERNEL_TILE, 256, 2, 256, 1, CLOTH_SCHED_LPT, m * cus, collide ? 256 : 0});
+        v.push_back({CLOTH_KERNEL_TILE, 256, 2, 256, 1, CLOTH_SCHED_RR, m * cus, collide ? 256 : 0});
     }
     return v;
 }
@@ -146,7 +154,7 @@ int autotune_sim(cloth_sim* s, float dt, int n_substeps, int frames, cloth_launc
     float best_ms = 0.0f;
     bool have = false;
     if ((e = copy_state(true))) st = hip_fail(e, "autotune save");
-    for (const cloth_launch& c : candidates(cus)) {
+    for (const cloth_launch& c : candidates(cus, s->any_collision != 0)) {
         if (st != CLOTH_OK) break;
         if (set_launch(s, c) != CLOTH_OK) continue;  // e.g. a region too large for LDS
         float ms = 0.0f;

@@ -59,6 +59,46 @@ __device__ __forceinline__ void spring_force(float dx, float dy, float dz, float
     fz += s * dz;
 }
 
+// a1 gather of one node over a sliced-CSR incidence list in global memory, four incidences
+// at a time: their records, then their neighbours' states, are loaded together before the
+// forces are summed in incidence order (so the sum is the same as a one-by-one loop).
+__device__ __forceinline__ void gather_global(const ClothView& cv, const float* __restrict__ xs,
+                                              const float* __restrict__ vs, int i, float xi,
+                                              float yi, float zi, float vxi, float vyi,
+                                              float vzi, float& fx, float& fy, float& fz) {
+    const int ld = cv.ld;
+    const int deg = cv.deg[i];
+    const int base = cv.slice_ptr[i >> 6] + (i & 63);
+    for (int r0 = 0; r0 < deg; r0 += 4) {
+        int j[4];
+        float k[4], c[4], L0[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int qq = base + (r0 + q) * 64;
+            const bool ok = r0 + q < deg;
+            j[q] = ok ? cv.nbr[qq] : i;
+            k[q] = ok ? cv.ik[qq] : 0.0f;
+            c[q] = ok ? cv.ic[qq] : 0.0f;
+            L0[q] = ok ? cv.il[qq] : 0.0f;
+        }
+        float nx[4], ny[4], nz[4], mx[4], my[4], mz[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            nx[q] = xs[j[q]];
+            ny[q] = xs[ld + j[q]];
+            nz[q] = xs[2 * ld + j[q]];
+            mx[q] = vs[j[q]];
+            my[q] = vs[ld + j[q]];
+            mz[q] = vs[2 * ld + j[q]];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (r0 + q < deg)
+                spring_force(nx[q] - xi, ny[q] - yi, nz[q] - zi, mx[q] - vxi, my[q] - vyi,
+                             mz[q] - vzi, k[q], c[q], L0[q], fx, fy, fz);
+    }
+}
+
 // Squared distance from p to triangle (A, A+e1, A+e2) by Voronoi regions (Ericson,
 // Real-Time Collision Detection, Sec. 5.1.5).  ap = p - A; s = ap . n (signed plane
 // distance along the unit normal n), used for the face region.
@@ -117,12 +157,50 @@ __device__ __forceinline__ void integrate(float w, float h, const float g[3], fl
     }
 }
 
+// Narrow phase against one broad-phase candidate whose packed geometry (A, n.x), (B-A, n.y),
+// (C-A, n.z) is g0, g1, g2: contact iff the point-triangle distance is < thickness; then
+// visit(n, s, t).  Returns 1 for a contact.
+template <class Visit>
+__device__ __forceinline__ int narrow_visit(const SurfaceView& sv, uint32_t t, const float4& g0,
+                                            const float4& g1, const float4& g2, float px,
+                                            float py, float pz, Visit&& visit) {
+    const float4 n = make_float4(g0.w, g1.w, g2.w, 0.0f);
+    const float ax = px - g0.x, ay = py - g0.y, az = pz - g0.z;
+    const float s = ax * n.x + ay * n.y + az * n.z;
+    const float d2 = point_tri_dist2(ax, ay, az, g1.x, g1.y, g1.z, g2.x, g2.y, g2.z, s);
+    if (d2 < sv.thickness2) {
+        visit(n, s, t);
+        return 1;
+    }
+    return 0;
+}
+
+// Narrow phase for up to 4 box hits at once: their geometry loads are issued together, then
+// the hits are visited in the given (ascending) order.
+template <class Visit>
+__device__ __forceinline__ int narrow_batch(const SurfaceView& sv, const uint32_t* t, int n,
+                                            float px, float py, float pz, Visit&& visit) {
+    float4 g[4][3];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (q < n) {
+            g[q][0] = sv.geo[3 * t[q]];
+            g[q][1] = sv.geo[3 * t[q] + 1];
+            g[q][2] = sv.geo[3 * t[q] + 2];
+        }
+    int cnt = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (q < n) cnt += narrow_visit(sv, t[q], g[q][0], g[q][1], g[q][2], px, py, pz, visit);
+    return cnt;
+}
+
 // a3 + a4 contact search for a node at predicted position p: candidates are the triangles
 // listed in p's cell whose inflated box holds p (ascending id); a candidate is a contact iff
-// the point-triangle distance is < thickness, and visit(n, s) is then called with the
-// triangle's unit normal n and the signed plane distance s = (p - A).n.  References are
-// loaded four at a time (refs has at least four entries of padding) so the ref -> box load
-// chains overlap.  Returns the contact count.
+// the point-triangle distance is < thickness, and visit(n, s, t) is then called with the
+// triangle's unit normal n, the signed plane distance s = (p - A).n and the triangle id t.  References are
+// read from the inline reference boxes four at a time (the arrays carry at least four
+// entries of padding).  Returns the contact count.
 template <class Visit>
 __device__ __forceinline__ int contacts_visit(const SurfaceView& sv, float px, float py, float pz,
                                               Visit&& visit) {
@@ -130,32 +208,26 @@ __device__ __forceinline__ int contacts_visit(const SurfaceView& sv, float px, f
     if (cell < 0) return 0;
     const uint32_t b = sv.cell_start[cell], e = sv.cell_start[cell + 1];
     int cnt = 0;
+    uint32_t hit[4];
+    int nh = 0;
     for (uint32_t r = b; r < e; r += 4) {
-        uint32_t t[4];
         float4 lo[4], hi[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) t[q] = sv.refs[r + q];
-#pragma unroll
         for (int q = 0; q < 4; ++q) {
-            lo[q] = sv.box_lo[t[q]];
-            hi[q] = sv.box_hi[t[q]];
+            lo[q] = sv.ref_lo[r + q];
+            hi[q] = sv.ref_hi[r + q];
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 4; ++q)
             if (r + q < e && in_box(lo[q], hi[q], px, py, pz)) {
-                const float4 A = sv.geo[4 * t[q]], e1 = sv.geo[4 * t[q] + 1],
-                             e2 = sv.geo[4 * t[q] + 2], n = sv.geo[4 * t[q] + 3];
-                const float ax = px - A.x, ay = py - A.y, az = pz - A.z;
-                const float s = ax * n.x + ay * n.y + az * n.z;
-                const float d2 =
-                    point_tri_dist2(ax, ay, az, e1.x, e1.y, e1.z, e2.x, e2.y, e2.z, s);
-                if (d2 < sv.thickness2) {
-                    visit(n, s);
-                    ++cnt;
+                hit[nh++] = (uint32_t)__float_as_int(lo[q].w);
+                if (nh == 4) {
+                    cnt += narrow_batch(sv, hit, 4, px, py, pz, visit);
+                    nh = 0;
                 }
             }
-        }
     }
+    if (nh) cnt += narrow_batch(sv, hit, nh, px, py, pz, visit);
     return cnt;
 }
 
@@ -165,7 +237,7 @@ __device__ __forceinline__ int collide(const SurfaceView& sv, float restitution,
                                        float& py, float& pz, float& qx, float& qy, float& qz) {
     float sx = 0.0f, sy = 0.0f, sz = 0.0f;
     const float th = sv.thickness;
-    const int cnt = contacts_visit(sv, px, py, pz, [&](const float4& n, float s) {
+    const int cnt = contacts_visit(sv, px, py, pz, [&](const float4& n, float s, uint32_t) {
         const float push = th - s;
         sx += push * n.x;
         sy += push * n.y;
@@ -181,6 +253,121 @@ __device__ __forceinline__ int collide(const SurfaceView& sv, float restitution,
         qz = -restitution * qz;
     }
     return cnt;
+}
+
+// Orders LDS writes of some lanes of a wavefront before later LDS reads of other lanes.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// a3 + a4 for the 64 nodes of a wavefront, cooperatively; every lane of the wavefront must
+// call it (active = the lane holds an unpinned node).  The lanes' distinct grid cells are
+// found by leader election, their reference boxes (stage_cap at most) are staged into this
+// wavefront's LDS area with independent loads, and each lane then tests its own cell's range
+// from LDS.  Hits are visited in ascending triangle id, exactly as contacts_visit does, so
+// both give the same contacts and the same sums.  More than stage_cap references fall back to
+// contacts_visit.  Returns the lane's contact count after applying the response.
+__device__ __forceinline__ int collide_wave(const SurfaceView& sv, float4* stage_lo,
+                                            float4* stage_hi, int stage_cap, bool active,
+                                            float restitution, float& px, float& py, float& pz,
+                                            float& qx, float& qy, float& qz) {
+    const int lane = threadIdx.x & 63;
+    const int cell = active ? cell_of(sv, px, py, pz) : -1;
+    unsigned long long pending = __ballot(cell >= 0);
+    if (pending == 0ULL) return 0;
+    int my_u = 0, n_u = 0, ucell = 0;
+    while (pending) {
+        const int leader = __builtin_ctzll(pending);
+        const int c = __shfl(cell, leader);
+        const unsigned long long same = __ballot(cell == c);
+        if (cell == c) my_u = n_u;
+        if (lane == n_u) ucell = c;
+        ++n_u;
+        pending &= ~same;
+    }
+    uint32_t b = 0, cnt = 0;
+    if (lane < n_u) {
+        b = sv.cell_start[ucell];
+        cnt = sv.cell_start[ucell + 1] - b;
+    }
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += t;
+    }
+    const uint32_t off = incl - cnt;
+    const uint32_t M = __shfl(incl, 63);
+    const uint32_t my_off = __shfl(off, my_u), my_cnt = __shfl(cnt, my_u);
+    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+    int contacts = 0;
+    const float th = sv.thickness;
+    auto accumulate = [&](const float4& n, float s, uint32_t) {
+        const float push = th - s;
+        sx += push * n.x;
+        sy += push * n.y;
+        sz += push * n.z;
+    };
+    if (M <= (uint32_t)stage_cap) {
+        for (uint32_t j0 = 0; j0 < M; j0 += 256) {
+            float4 lo[4], hi[4];
+            uint32_t jj[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t j = j0 + q * 64 + lane;
+                int k = 0;  // the unique cell whose range holds entry j
+#pragma unroll
+                for (int step = 32; step >= 1; step >>= 1) {
+                    const int cand = k + step;
+                    const uint32_t oc = __shfl(off, cand < 64 ? cand : 63);
+                    if (cand < n_u && oc <= j) k = cand;
+                }
+                const uint32_t r = __shfl(b, k) + (j - __shfl(off, k));
+                jj[q] = j;
+                if (j < M) {
+                    lo[q] = sv.ref_lo[r];
+                    hi[q] = sv.ref_hi[r];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (jj[q] < M) {
+                    stage_lo[jj[q]] = lo[q];
+                    stage_hi[jj[q]] = hi[q];
+                }
+        }
+        wave_sync();
+        if (cell >= 0) {
+            uint32_t hit[4];
+            int nh = 0;
+            for (uint32_t r = my_off; r < my_off + my_cnt; ++r) {
+                const float4 lo = stage_lo[r], hi = stage_hi[r];
+                if (in_box(lo, hi, px, py, pz)) {
+                    hit[nh++] = (uint32_t)__float_as_int(lo.w);
+                    if (nh == 4) {
+                        contacts += narrow_batch(sv, hit, 4, px, py, pz, accumulate);
+                        nh = 0;
+                    }
+                }
+            }
+            if (nh) contacts += narrow_batch(sv, hit, nh, px, py, pz, accumulate);
+        }
+        wave_sync();  // the stage is reused by the next call
+    } else if (cell >= 0) {
+        contacts = contacts_visit(sv, px, py, pz, accumulate);
+    }
+    if (contacts > 0) {
+        const float inv = 1.0f / (float)contacts;
+        px += sx * inv;
+        py += sy * inv;
+        pz += sz * inv;
+        qx = -restitution * qx;
+        qy = -restitution * qy;
+        qz = -restitution * qz;
+    }
+    return contacts;
 }
 
 }  // namespace cloth

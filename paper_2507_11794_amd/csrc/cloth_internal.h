@@ -21,9 +21,11 @@ struct SurfaceView {
     float thickness2;            // thickness^2
     const uint32_t* cell_start;  // [cells + 1]
     const uint32_t* refs;        // [refs]
+    const float4* ref_lo;        // [refs]: inflated box of refs[r]; .w = triangle id (int bits)
+    const float4* ref_hi;        // [refs]: .w unused
     const float4* box_lo;        // [T] inflated box, .w unused
     const float4* box_hi;        // [T]
-    const float4* geo;           // [T*4]: A, B-A, C-A, unit outward normal (.w unused)
+    const float4* geo;           // [T*3]: (A, n.x), (B-A, n.y), (C-A, n.z); n = unit outward normal
 };
 
 // One cloth's node and spring arrays on the device (internal node order).
@@ -94,17 +96,23 @@ struct TileView {
 // collide = 0 skips the collision stage for every cloth (no cloth has a surface).
 hipError_t launch_tiles(const TileView& tv, int K, int collide, const StepParams& sp,
                         const float* xs, const float* vs, float* xd, float* vd, int block,
-                        hipStream_t stream);
-size_t tile_lds_bytes(int rmax);
+                        int stage_cap, hipStream_t stream);
+// LDS of one tile workgroup: the region state plus the collision stage of its wavefronts.
+size_t tile_lds_bytes(int rmax, int block = 256, int stage_cap = 0);
 // Raise the tile kernels' dynamic LDS limit when a plan needs more than 64 KiB.
 hipError_t prepare_tile_kernels(size_t lds_bytes);
 
 // a1-a4: one substep for every node (one thread per node).  With node_group non-NULL the
 // node's surface is svs[node_group[i]] (a batch of cloths); otherwise sv.
+// stage_cap: reference boxes staged in LDS per wavefront for the collision query (0 = none;
+// at most kMaxStage).
+constexpr int kMaxStage = 1024;
 hipError_t launch_substep(const ClothView& cv, const SurfaceView& sv, const StepParams& sp,
                           const float* xs, const float* vs, float* xd, float* vd, int block,
                           hipStream_t stream, const SurfaceView* svs = nullptr,
-                          const int* node_group = nullptr);
+                          const int* node_group = nullptr, int stage_cap = 0);
+// Raise the one-substep kernel's dynamic LDS limit when its stage needs more than 64 KiB.
+hipError_t prepare_substep_kernels(size_t lds_bytes);
 
 // --- a6 adjoint ----------------------------------------------------------------------------
 // Response and integration transpose of one substep at state (xs, vs): partial adjoints and
@@ -117,6 +125,10 @@ hipError_t launch_adj_node(const ClothView& cv, const SurfaceView& sv, const Ste
 hipError_t launch_adj_springs(const ClothView& cv, const float* xs, const float* vs,
                               const float* fb, const float* xb_part, const float* vb_part,
                               float* xb_in, float* vb_in, double* kb, double* cb, hipStream_t st);
+// Contact sets of the next substep (internal slot order): counts[slot], ids[slot*cap ...].
+hipError_t launch_debug_contacts(const ClothView& cv, const SurfaceView& sv, const StepParams& sp,
+                                const float* xs, const float* vs, int* counts, int* ids, int cap,
+                                hipStream_t st);
 // Node-id AoS [n][3] <-> internal SoA [3][ld] through slot[id].
 hipError_t launch_import(int n, int ld, const int* slot, const float* aos, float* soa,
                          int accumulate, hipStream_t st);
@@ -144,6 +156,10 @@ hipError_t launch_grid_fill(int n_tris, const float4* box_lo, const float4* box_
                             const uint32_t* cell_start, uint32_t* fill, uint32_t* refs,
                             hipStream_t stream);
 hipError_t launch_grid_sort(int n_cells, const uint32_t* cell_start, uint32_t* refs,
+                            hipStream_t stream);
+// ref_lo[r] = (box_lo[refs[r]].xyz, refs[r] as int bits), ref_hi[r] = box_hi[refs[r]] for r < n.
+hipError_t launch_ref_boxes(size_t n, const uint32_t* refs, const float4* box_lo,
+                            const float4* box_hi, float4* ref_lo, float4* ref_hi,
                             hipStream_t stream);
 
 // Exclusive prefix sum of in[0..n) into out[0..n] (out[n] = total) with wavefront scans.

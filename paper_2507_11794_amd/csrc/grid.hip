@@ -68,10 +68,9 @@ __global__ void k_tri_prep(int T, const float* __restrict__ verts, const int* __
     nx /= len;
     ny /= len;
     nz /= len;
-    geo[4 * t] = make_float4(ax, ay, az, 0.0f);
-    geo[4 * t + 1] = make_float4(e1x, e1y, e1z, 0.0f);
-    geo[4 * t + 2] = make_float4(e2x, e2y, e2z, 0.0f);
-    geo[4 * t + 3] = make_float4(nx, ny, nz, 0.0f);
+    geo[3 * t] = make_float4(ax, ay, az, nx);
+    geo[3 * t + 1] = make_float4(e1x, e1y, e1z, ny);
+    geo[3 * t + 2] = make_float4(e2x, e2y, e2z, nz);
     int c0[3], c1[3];
     cell_range(g, lo, hi, c0, c1);
     const unsigned long long n = (unsigned long long)(c1[0] - c0[0] + 1) *
@@ -123,6 +122,18 @@ __global__ void k_grid_sort(int C, const uint32_t* __restrict__ cell_start, uint
         }
         refs[j] = v;
     }
+}
+
+__global__ void k_ref_boxes(size_t n, const uint32_t* __restrict__ refs,
+                            const float4* __restrict__ box_lo, const float4* __restrict__ box_hi,
+                            float4* ref_lo, float4* ref_hi) {
+    const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const uint32_t t = refs[r];
+    float4 lo = box_lo[t];
+    lo.w = __int_as_float((int)t);
+    ref_lo[r] = lo;
+    ref_hi[r] = box_hi[t];
 }
 
 // ------------------------------------------------------------------ prefix sum
@@ -260,6 +271,15 @@ hipError_t launch_grid_sort(int n_cells, const uint32_t* cell_start, uint32_t* r
                             hipStream_t stream) {
     if (n_cells <= 0) return hipSuccess;
     k_grid_sort<<<blocks_for(n_cells, 256), 256, 0, stream>>>(n_cells, cell_start, refs);
+    return hipGetLastError();
+}
+
+hipError_t launch_ref_boxes(size_t n, const uint32_t* refs, const float4* box_lo,
+                            const float4* box_hi, float4* ref_lo, float4* ref_hi,
+                            hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    k_ref_boxes<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(n, refs, box_lo, box_hi, ref_lo,
+                                                               ref_hi);
     return hipGetLastError();
 }
 

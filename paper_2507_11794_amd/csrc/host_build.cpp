@@ -384,7 +384,7 @@ int build_surface(const ClothHostInput& in, const cloth_params& p, DeviceArena& 
     float4 *box_lo, *box_hi, *geo;
     if ((e = arena.alloc(&d_verts, 3 * (size_t)Vn)) || (e = arena.alloc(&d_tris, 3 * (size_t)T)) ||
         (e = arena.alloc(&d_total, 1)) || (e = arena.alloc(&box_lo, (size_t)T)) ||
-        (e = arena.alloc(&box_hi, (size_t)T)) || (e = arena.alloc(&geo, 4 * (size_t)T)))
+        (e = arena.alloc(&box_hi, (size_t)T)) || (e = arena.alloc(&geo, 3 * (size_t)T)))
         return hip_fail(e, "hipMalloc surface");
     if ((e = hipMemcpyAsync(d_verts, in.verts, 12 * (size_t)Vn, hipMemcpyHostToDevice, stream)) ||
         (e = hipMemcpyAsync(d_tris, in.tris, 12 * (size_t)T, hipMemcpyHostToDevice, stream)) ||
@@ -415,6 +415,15 @@ int build_surface(const ClothHostInput& in, const cloth_params& p, DeviceArena& 
                               refs, stream)) ||
         (e = launch_grid_sort((int)C, cell_start, refs, stream)) || (e = hipStreamSynchronize(stream)))
         return hip_fail(e, "grid build");
+    float4 *ref_lo, *ref_hi;
+    if ((e = arena.alloc(&ref_lo, (size_t)total + kRefPad)) ||
+        (e = arena.alloc(&ref_hi, (size_t)total + kRefPad)) ||
+        (e = launch_ref_boxes((size_t)total + kRefPad, refs, box_lo, box_hi, ref_lo, ref_hi,
+                              stream)) ||
+        (e = hipStreamSynchronize(stream)))
+        return hip_fail(e, "reference boxes");
+    sv.ref_lo = ref_lo;
+    sv.ref_hi = ref_hi;
     arena.free_one(counts);
     arena.free_one(tmp);
     arena.free_one(d_verts);

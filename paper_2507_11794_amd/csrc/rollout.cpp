@@ -205,4 +205,32 @@ int cloth_rollout_backward(cloth_sim* s, const float* gx_out_dev, float* gk_dev,
     return CLOTH_OK;
 }
 
+int cloth_debug_contacts(cloth_sim* s, float h, int* counts, int* ids, int cap) {
+    if (!s || !counts) return fail(CLOTH_EINVAL, "NULL argument");
+    if (s->groups.size() != 1) return fail(CLOTH_EINVAL, "single-cloth handles only");
+    if (!(h > 0.0f) || !std::isfinite(h) || cap < 0 || (cap > 0 && !ids))
+        return fail(CLOTH_EINVAL, "need h > 0 and ids when cap > 0");
+    const int N = s->dev.n;
+    DeviceArena tmp;
+    int *d_cnt, *d_ids;
+    hipError_t e;
+    if ((e = tmp.alloc(&d_cnt, (size_t)N)) || (e = tmp.alloc(&d_ids, (size_t)N * cap + 1)))
+        return hip_fail(e, "hipMalloc contacts");
+    std::vector<int> cnt(N), id((size_t)N * cap + 1);
+    if ((e = launch_debug_contacts(s->dev.view(), s->surfs[0].view, step_params(s, h),
+                                   s->dev.x[s->dev.cur], s->dev.v[s->dev.cur], d_cnt, d_ids, cap,
+                                   s->stream)) ||
+        (e = hipMemcpyAsync(cnt.data(), d_cnt, 4 * (size_t)N, hipMemcpyDeviceToHost, s->stream)) ||
+        (cap > 0 && (e = hipMemcpyAsync(id.data(), d_ids, 4 * (size_t)N * cap,
+                                        hipMemcpyDeviceToHost, s->stream))) ||
+        (e = hipStreamSynchronize(s->stream)))
+        return hip_fail(e, "debug contacts");
+    for (int p = 0; p < N; ++p) {
+        const int node = s->host.order[p];
+        counts[node] = cnt[p];
+        for (int r = 0; r < cap; ++r) ids[(size_t)node * cap + r] = id[(size_t)p * cap + r];
+    }
+    return CLOTH_OK;
+}
+
 }  // extern "C"

@@ -18,6 +18,8 @@ int check_launch(const cloth_launch& c) {
         return fail(CLOTH_EINVAL, "unknown kernel");
     if (c.block_threads < 64 || c.block_threads > 256 || (c.block_threads & 63))
         return fail(CLOTH_EINVAL, "block_threads must be 64, 128, 192 or 256");
+    if (c.stage_refs < 0 || c.stage_refs > kMaxStage)
+        return fail(CLOTH_EINVAL, "stage_refs must be in 0..1024");
     if (c.kernel == CLOTH_KERNEL_TILE) {
         if (c.tile_nodes < 64 || c.tile_nodes > 4096 || (c.tile_nodes & 63))
             return fail(CLOTH_EINVAL, "tile_nodes must be a multiple of 64 in 64..4096");
@@ -45,8 +47,6 @@ int ensure_plan(cloth_sim* s, const cloth_launch& c) {
         int st = build_tile_plan(s->host, s->group_off, c.tile_nodes, c.substeps_per_launch,
                                  s->stream, &fresh);
         if (st != CLOTH_OK) return st;
-        if ((e = prepare_tile_kernels(tile_lds_bytes(fresh.view.rmax))))
-            return hip_fail(e, "tile kernel LDS attribute");
         s->plan.arena.release();
         s->plan.arena.ptrs.swap(fresh.arena.ptrs);
         s->plan.meta_host.swap(fresh.meta_host);
@@ -70,13 +70,26 @@ int ensure_plan(cloth_sim* s, const cloth_launch& c) {
 int set_launch(cloth_sim* s, const cloth_launch& cfg) {
     int st = check_launch(cfg);
     if (st != CLOTH_OK) return st;
+    // until this call succeeds the plan may not match s->launch; the next run re-applies it
+    s->launch_ready = false;
     if ((st = ensure_plan(s, cfg)) != CLOTH_OK) return st;
+    // dynamic LDS of the chosen kernel: check it fits and raise the kernels' limit
+    const int stage = s->any_collision ? cfg.stage_refs : 0;
+    const size_t lds = cfg.kernel == CLOTH_KERNEL_TILE
+                           ? tile_lds_bytes(s->plan.view.rmax, cfg.block_threads, stage)
+                           : (size_t)(cfg.block_threads / 64) * 2 * stage * sizeof(float4);
+    if (lds > 160 * 1024)
+        return fail(CLOTH_EINVAL, "tile region plus collision stage exceed 160 KiB of LDS");
+    hipError_t pe = cfg.kernel == CLOTH_KERNEL_TILE ? prepare_tile_kernels(lds)
+                                                     : prepare_substep_kernels(lds);
+    if (pe != hipSuccess) return hip_fail(pe, "kernel LDS attribute");
     if (cfg.kernel != s->launch.kernel || cfg.block_threads != s->launch.block_threads) {
         hipError_t e = hipStreamSynchronize(s->stream);
         if (e != hipSuccess) return hip_fail(e, "synchronise");
         s->drop_graphs();
     }
     s->launch = cfg;
+    s->launch_ready = true;
     if (cfg.kernel == CLOTH_KERNEL_DIRECT) {
         s->launch.schedule = CLOTH_SCHED_GRID;
         s->launch.workgroups = 0;
@@ -89,12 +102,16 @@ namespace {
 // One launch advancing K substeps from buffer `src` into buffer `src ^ 1`.
 hipError_t launch_once(cloth_sim* s, const StepParams& sp, int K, int src, hipStream_t st) {
     const int dst = src ^ 1;
+    if (s->launch.kernel == CLOTH_KERNEL_TILE && (K < 1 || K > s->plan.K))
+        return hipErrorInvalidValue;  // the plan covers at most plan.K substeps per launch
     if (s->launch.kernel == CLOTH_KERNEL_TILE)
         return launch_tiles(s->plan.view, K, s->any_collision, sp, s->dev.x[src], s->dev.v[src],
-                            s->dev.x[dst], s->dev.v[dst], s->launch.block_threads, st);
+                            s->dev.x[dst], s->dev.v[dst], s->launch.block_threads,
+                            s->launch.stage_refs, st);
     if (s->groups.size() == 1)
         return launch_substep(s->dev.view(), s->surfs[0].view, sp, s->dev.x[src], s->dev.v[src],
-                              s->dev.x[dst], s->dev.v[dst], s->launch.block_threads, st);
+                              s->dev.x[dst], s->dev.v[dst], s->launch.block_threads, st, nullptr,
+                              nullptr, s->launch.stage_refs);
     return launch_substep(s->dev.view(), s->surfs[0].view, sp, s->dev.x[src], s->dev.v[src],
                           s->dev.x[dst], s->dev.v[dst], s->launch.block_threads, st, s->svs_dev,
                           s->node_group_dev);
@@ -152,8 +169,11 @@ int run_substeps(cloth_sim* s, float h, long long total) {
     sp.restitution = s->p.restitution;
     sp.check_nan = (s->p.flags & CLOTH_F_CHECK_NAN) ? 1 : 0;
     sp.nan_flag = s->nan_flag;
-    int st = ensure_plan(s, s->launch);
-    if (st != CLOTH_OK) return st;
+    int st = CLOTH_OK;
+    if (!s->launch_ready) {
+        if ((st = set_launch(s, s->launch)) != CLOTH_OK) return st;
+        s->launch_ready = true;
+    }
     s->roll.ready = false;  // stepping moves the state away from a rollout's checkpoints
     const int K = s->launch.kernel == CLOTH_KERNEL_TILE ? s->launch.substeps_per_launch : 1;
     long long launches = total / K;

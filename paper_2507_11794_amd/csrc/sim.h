@@ -67,7 +67,8 @@ struct cloth_sim {
     cloth::TilePlanDevice plan;
     long long plan_version = 0;
     std::vector<cloth::GraphEntry> graphs;
-    cloth_launch launch{CLOTH_KERNEL_TILE, 256, 4, 256, 1, CLOTH_SCHED_GRID, 0};
+    cloth_launch launch{CLOTH_KERNEL_TILE, 256, 1, 256, 1, CLOTH_SCHED_GRID, 0, 384};
+    bool launch_ready = false;  // plan, schedule and LDS limits match `launch`
     int* nan_flag = nullptr;
     // host copies kept for the stability bound and parameter updates (caller numbering)
     std::vector<float> x0, mass, k, c;

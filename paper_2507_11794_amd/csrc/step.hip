@@ -19,38 +19,41 @@ __global__ void __launch_bounds__(256)
     k_substep(const ClothView cv, const SurfaceView sv1, const StepParams sp,
               const float* __restrict__ xs, const float* __restrict__ vs, float* __restrict__ xd,
               float* __restrict__ vd, const SurfaceView* __restrict__ svs,
-              const int* __restrict__ node_group) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cv.n) return;
+              const int* __restrict__ node_group, const int stage_cap) {
+    extern __shared__ float4 stage[];  // [wavefronts][2][stage_cap]
+    // workgroups are dealt round-robin to the 8 XCDs: give each XCD a contiguous node range
+    const int nb = gridDim.x, q8 = nb >> 3, rem = nb & 7, x8 = blockIdx.x & 7;
+    const int blk = x8 * q8 + (x8 < rem ? x8 : rem) + (blockIdx.x >> 3);
+    const int i = blk * blockDim.x + threadIdx.x;
+    const bool valid = i < cv.n;
     const int ld = cv.ld;
-    const float xi = xs[i], yi = xs[ld + i], zi = xs[2 * ld + i];
-    const float vxi = vs[i], vyi = vs[ld + i], vzi = vs[2 * ld + i];
-    const float w = cv.w[i];
-
-    // a1: gather
-    float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-    const int deg = cv.deg[i];
-    const int base = cv.slice_ptr[i >> 6] + (i & 63);
-    for (int r = 0; r < deg; ++r) {
-        const int q = base + r * 64;
-        const int j = cv.nbr[q];
-        spring_force(xs[j] - xi, xs[ld + j] - yi, xs[2 * ld + j] - zi, vs[j] - vxi,
-                     vs[ld + j] - vyi, vs[2 * ld + j] - vzi, cv.ik[q], cv.ic[q], cv.il[q], fx, fy,
-                     fz);
+    float px = 0.0f, py = 0.0f, pz = 0.0f, qx = 0.0f, qy = 0.0f, qz = 0.0f, w = 0.0f;
+    if (valid) {
+        const float xi = xs[i], yi = xs[ld + i], zi = xs[2 * ld + i];
+        const float vxi = vs[i], vyi = vs[ld + i], vzi = vs[2 * ld + i];
+        w = cv.w[i];
+        // a1: gather
+        float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+        gather_global(cv, xs, vs, i, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz);
+        // a2: integrate
+        integrate(w, sp.h, sp.g, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz, px, py, pz, qx, qy, qz);
     }
-
-    // a2: integrate; a3 + a4: broad phase, narrow phase, response
-    float px, py, pz, qx, qy, qz;
-    integrate(w, sp.h, sp.g, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz, px, py, pz, qx, qy, qz);
-    if (COLLIDE && w != 0.0f) {
+    // a3 + a4: broad phase, narrow phase, response
+    if (COLLIDE) {
         if (GROUPED) {
-            const SurfaceView sv = svs[node_group[i]];
-            if (sv.n_tris > 0) collide(sv, sp.restitution, px, py, pz, qx, qy, qz);
-        } else {
+            if (valid && w != 0.0f) {
+                const SurfaceView sv = svs[node_group[i]];
+                if (sv.n_tris > 0) collide(sv, sp.restitution, px, py, pz, qx, qy, qz);
+            }
+        } else if (stage_cap > 0) {
+            float4* lo = stage + (size_t)(threadIdx.x >> 6) * 2 * stage_cap;
+            collide_wave(sv1, lo, lo + stage_cap, stage_cap, valid && w != 0.0f, sp.restitution,
+                         px, py, pz, qx, qy, qz);
+        } else if (valid && w != 0.0f) {
             collide(sv1, sp.restitution, px, py, pz, qx, qy, qz);
         }
     }
-
+    if (!valid) return;
     xd[i] = px;
     xd[ld + i] = py;
     xd[2 * ld + i] = pz;
@@ -63,21 +66,30 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+hipError_t prepare_substep_kernels(size_t lds_bytes) {
+    if (lds_bytes <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute((const void*)k_substep<true, false>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+}
+
 hipError_t launch_substep(const ClothView& cv, const SurfaceView& sv, const StepParams& sp,
                           const float* xs, const float* vs, float* xd, float* vd, int block,
-                          hipStream_t stream, const SurfaceView* svs, const int* node_group) {
+                          hipStream_t stream, const SurfaceView* svs, const int* node_group,
+                          int stage_cap) {
     if (cv.n <= 0) return hipSuccess;
     if (block <= 0 || block > 256 || (block & 63)) block = 256;
     const int grid = (cv.n + block - 1) / block;
-    if (svs && node_group)
+    if (svs && node_group) {
         k_substep<true, true><<<grid, block, 0, stream>>>(cv, sv, sp, xs, vs, xd, vd, svs,
-                                                          node_group);
-    else if (sv.n_tris > 0)
-        k_substep<true, false><<<grid, block, 0, stream>>>(cv, sv, sp, xs, vs, xd, vd, nullptr,
-                                                           nullptr);
-    else
+                                                          node_group, 0);
+    } else if (sv.n_tris > 0) {
+        const size_t lds = (size_t)(block / 64) * 2 * stage_cap * sizeof(float4);
+        k_substep<true, false><<<grid, block, lds, stream>>>(cv, sv, sp, xs, vs, xd, vd, nullptr,
+                                                             nullptr, stage_cap);
+    } else {
         k_substep<false, false><<<grid, block, 0, stream>>>(cv, sv, sp, xs, vs, xd, vd, nullptr,
-                                                            nullptr);
+                                                            nullptr, 0);
+    }
     return hipGetLastError();
 }
 

@@ -17,7 +17,8 @@ template <bool COLLIDE>
 __device__ __forceinline__ void run_tile(const TileView& tv, const TileMeta& m, const int K,
                                          const StepParams& sp, const float* __restrict__ xs,
                                          const float* __restrict__ vs, float* __restrict__ xd,
-                                         float* __restrict__ vd, float* lds) {
+                                         float* __restrict__ vd, float* lds, float4* stage,
+                                         int stage_cap) {
     const int rmax = tv.rmax, ld = tv.ld;
     float* X0 = lds;
     float* X1 = lds + 3 * rmax;
@@ -44,34 +45,58 @@ __device__ __forceinline__ void run_tile(const TileView& tv, const TileMeta& m, 
         float* Xd = (s & 1) ? X1 : X0;
         float* Vd = (s & 1) ? V1 : V0;
         const int ncomp = m.level[K - s];
-        for (int u = threadIdx.x; u < ncomp; u += blockDim.x) {
-            const float xi = Xs[u], yi = Xs[rmax + u], zi = Xs[2 * rmax + u];
-            const float vxi = Vs[u], vyi = Vs[rmax + u], vzi = Vs[2 * rmax + u];
-            const float w = tv.w[rs[u]];
-            const int deg = tv.comp_deg[m.comp_off + u];
-            const float4* inc = tv.inc + m.inc_off + u;
-            float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-#pragma unroll 4
-            for (int r = 0; r < deg; ++r) {
-                const float4 e = inc[r * m.inc_pad];
-                const int j = __float_as_int(e.w);
-                spring_force(Xs[j] - xi, Xs[rmax + j] - yi, Xs[2 * rmax + j] - zi, Vs[j] - vxi,
-                             Vs[rmax + j] - vyi, Vs[2 * rmax + j] - vzi, e.x, e.y, e.z, fx, fy,
-                             fz);
+        // wavefront-uniform chunks of 64 nodes, so the collision query can run per wavefront
+        for (int u0 = threadIdx.x & ~63; u0 < ncomp; u0 += blockDim.x) {
+            const int u = u0 + (threadIdx.x & 63);
+            const bool valid = u < ncomp;
+            float px = 0.0f, py = 0.0f, pz = 0.0f, qx = 0.0f, qy = 0.0f, qz = 0.0f, w = 0.0f;
+            if (valid) {
+                const float xi = Xs[u], yi = Xs[rmax + u], zi = Xs[2 * rmax + u];
+                const float vxi = Vs[u], vyi = Vs[rmax + u], vzi = Vs[2 * rmax + u];
+                w = tv.w[rs[u]];
+                const int deg = tv.comp_deg[m.comp_off + u];
+                const float4* inc = tv.inc + m.inc_off + u;
+                float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+                // records of four incidences are loaded together, then summed in order
+                for (int r0 = 0; r0 < deg; r0 += 4) {
+                    float4 e[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        e[q] = r0 + q < deg ? inc[(r0 + q) * m.inc_pad]
+                                            : make_float4(0.0f, 0.0f, 0.0f, __int_as_float(u));
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (r0 + q < deg) {
+                            const int j = __float_as_int(e[q].w);
+                            spring_force(Xs[j] - xi, Xs[rmax + j] - yi, Xs[2 * rmax + j] - zi,
+                                         Vs[j] - vxi, Vs[rmax + j] - vyi,
+                                         Vs[2 * rmax + j] - vzi, e[q].x, e[q].y, e[q].z, fx,
+                                         fy, fz);
+                        }
+                }
+                integrate(w, sp.h, sp.g, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz, px, py, pz, qx,
+                          qy, qz);
             }
-            float px, py, pz, qx, qy, qz;
-            integrate(w, sp.h, sp.g, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz, px, py, pz, qx, qy,
-                      qz);
-            if (collide_here && w != 0.0f) collide(sv, sp.restitution, px, py, pz, qx, qy, qz);
-            Xd[u] = px;
-            Xd[rmax + u] = py;
-            Xd[2 * rmax + u] = pz;
-            Vd[u] = qx;
-            Vd[rmax + u] = qy;
-            Vd[2 * rmax + u] = qz;
-            if (sp.check_nan) {
-                const float sum = px + py + pz + qx + qy + qz;
-                if (!__builtin_isfinite(sum)) atomicOr(sp.nan_flag, 1);
+            if (collide_here) {
+                if (stage_cap > 0) {
+                    float4* lo = stage + (size_t)(threadIdx.x >> 6) * 2 * stage_cap;
+                    collide_wave(sv, lo, lo + stage_cap, stage_cap, valid && w != 0.0f,
+                                 sp.restitution, px, py, pz, qx, qy, qz);
+                } else if (valid && w != 0.0f) {
+                    collide(sv, sp.restitution, px, py, pz, qx, qy, qz);
+                }
+            }
+            if (valid) {
+                Xd[u] = px;
+                Xd[rmax + u] = py;
+                Xd[2 * rmax + u] = pz;
+                Vd[u] = qx;
+                Vd[rmax + u] = qy;
+                Vd[2 * rmax + u] = qz;
+                if (sp.check_nan) {
+                    const float sum = px + py + pz + qx + qy + qz;
+                    if (!__builtin_isfinite(sum)) atomicOr(sp.nan_flag, 1);
+                }
             }
         }
         __syncthreads();
@@ -94,19 +119,25 @@ __device__ __forceinline__ void run_tile(const TileView& tv, const TileMeta& m, 
 template <bool COLLIDE>
 __global__ void __launch_bounds__(256)
     k_tile(const TileView tv, const int K, const StepParams sp, const float* __restrict__ xs,
-           const float* __restrict__ vs, float* __restrict__ xd, float* __restrict__ vd) {
-    extern __shared__ float lds[];
+           const float* __restrict__ vs, float* __restrict__ xd, float* __restrict__ vd,
+           const int stage_cap) {
+    extern __shared__ float4 lds4[];
+    float* lds = reinterpret_cast<float*>(lds4);
+    float4* stage = lds4 + 3 * (size_t)tv.rmax;  // after 12 * rmax floats of state
     const int b0 = tv.item_ptr[blockIdx.x], b1 = tv.item_ptr[blockIdx.x + 1];
     for (int it = b0; it < b1; ++it) {
         const TileMeta& m = tv.meta[tv.items[it]];
-        run_tile<COLLIDE>(tv, m, K, sp, xs, vs, xd, vd, lds);
+        run_tile<COLLIDE>(tv, m, K, sp, xs, vs, xd, vd, lds, stage, stage_cap);
         __syncthreads();  // LDS is reused by the next tile
     }
 }
 
 }  // namespace
 
-size_t tile_lds_bytes(int rmax) { return (size_t)12 * sizeof(float) * (size_t)rmax; }
+size_t tile_lds_bytes(int rmax, int block, int stage_cap) {
+    return (size_t)12 * sizeof(float) * (size_t)rmax +
+           (size_t)(block / 64) * 2 * (size_t)stage_cap * sizeof(float4);
+}
 
 hipError_t prepare_tile_kernels(size_t lds_bytes) {
     if (lds_bytes <= 64 * 1024) return hipSuccess;
@@ -119,14 +150,16 @@ hipError_t prepare_tile_kernels(size_t lds_bytes) {
 
 hipError_t launch_tiles(const TileView& tv, int K, int collide, const StepParams& sp,
                         const float* xs, const float* vs, float* xd, float* vd, int block,
-                        hipStream_t stream) {
+                        int stage_cap, hipStream_t stream) {
     if (tv.n_tiles <= 0 || tv.n_workgroups <= 0) return hipSuccess;
     if (block <= 0 || block > 256 || (block & 63)) block = 256;
-    const size_t lds = tile_lds_bytes(tv.rmax);
+    if (!collide) stage_cap = 0;
+    const size_t lds = tile_lds_bytes(tv.rmax, block, stage_cap);
     if (collide)
-        k_tile<true><<<tv.n_workgroups, block, lds, stream>>>(tv, K, sp, xs, vs, xd, vd);
+        k_tile<true><<<tv.n_workgroups, block, lds, stream>>>(tv, K, sp, xs, vs, xd, vd,
+                                                              stage_cap);
     else
-        k_tile<false><<<tv.n_workgroups, block, lds, stream>>>(tv, K, sp, xs, vs, xd, vd);
+        k_tile<false><<<tv.n_workgroups, block, lds, stream>>>(tv, K, sp, xs, vs, xd, vd, 0);
     return hipGetLastError();
 }
 

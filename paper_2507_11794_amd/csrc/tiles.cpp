@@ -103,7 +103,7 @@ int build_tile_plan(const ClothHost& h, const std::vector<int>& group_off, int t
             }
         }
     }
-    if (tile_lds_bytes(rmax) > 160 * 1024)
+    if (tile_lds_bytes(rmax, 64, 0) > 160 * 1024)
         return fail(CLOTH_EINVAL, "tile region too large for LDS; use fewer tile nodes or substeps");
     out->arena.release();
     hipError_t e;

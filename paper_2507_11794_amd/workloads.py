@@ -19,6 +19,7 @@ are cast once to FP32.
 from __future__ import annotations
 
 import dataclasses
+import functools
 import math
 from typing import List, Optional
 
@@ -169,6 +170,12 @@ def _icosahedron():
 
 
 def geodesic_sphere(freq: int):
+    P, F = _geodesic_sphere_cached(int(freq))
+    return P.copy(), F.copy()
+
+
+@functools.lru_cache(maxsize=8)
+def _geodesic_sphere_cached(freq: int):
     """Class-I geodesic subdivision of the icosahedron at frequency ``freq``.
 
     Each face (A, B, C) is cut into freq^2 triangles on the lattice
