@@ -66,6 +66,7 @@ def _load():
     lib.orc_rollout_grad.argtypes = [P, dp, dp, C.c_double, C.c_int, C.c_int, ip, dp, C.c_int,
                                      dp, dp, dp, dp, dp]
     lib.orc_model_triangle.argtypes = [P, C.c_int, dp, dp, dp, dp]
+    lib.orc_vertex_normals.argtypes = [C.c_int, C.c_int, dp, dp]
     _lib = lib
     return lib
 
@@ -233,6 +234,15 @@ class Model:
 def point_tri_dist2(p, A, B, Cc):
     lib = _load()
     return lib.orc_point_tri_dist2(_dp(_d(p)), _dp(_d(A)), _dp(_d(B)), _dp(_d(Cc)))
+
+
+def vertex_normals(nx, ny, x):
+    """Per-vertex normals of an nx-by-ny cloth grid (area-weighted, normalised)."""
+    lib = _load()
+    x = _d(x).reshape(-1, 3)
+    n = np.zeros_like(x)
+    lib.orc_vertex_normals(int(nx), int(ny), _dp(x), _dp(n))
+    return n
 
 
 def candidates_f32(x, verts, tris, thickness, cap=None):

@@ -671,6 +671,36 @@ void orc_rollout_grad(const orc_model *m, const double *x0, const double *v0, do
     free(xb); free(vb); free(xb2); free(vb2); free(seg_x); free(seg_v);
 }
 
+/* ------------------------------------------------------------------ vertex normals */
+
+/* Per-vertex normals of an nx-by-ny cloth grid (node (i, j) = i*nx + j, Sec. 3's normal
+ * update before rendering): each quad (i, j)-(i+1, j)-(i+1, j+1)-(i, j+1) is split into the
+ * triangles (a, b, c) and (a, c, d) along its (i, j)-(i+1, j+1) diagonal; every triangle adds
+ * its cross product (B - A) x (C - A) -- twice its area times its unit normal -- to its three
+ * vertices, and each vertex sum is normalised (a zero sum stays zero). */
+void orc_vertex_normals(int nx, int ny, const double *x, double *n)
+{
+    memset(n, 0, sizeof(double) * 3 * (size_t)nx * (size_t)ny);
+    for (int i = 0; i + 1 < ny; ++i)
+        for (int j = 0; j + 1 < nx; ++j) {
+            int a = i * nx + j, b = (i + 1) * nx + j, c = (i + 1) * nx + j + 1, d = i * nx + j + 1;
+            int tri[2][3] = {{a, b, c}, {a, c, d}};
+            for (int t = 0; t < 2; ++t) {
+                double e1[3], e2[3], cr[3];
+                sub3(x + 3 * tri[t][1], x + 3 * tri[t][0], e1);
+                sub3(x + 3 * tri[t][2], x + 3 * tri[t][0], e2);
+                cross3(e1, e2, cr);
+                for (int k = 0; k < 3; ++k)
+                    for (int q = 0; q < 3; ++q) n[3 * tri[t][k] + q] += cr[q];
+            }
+        }
+    for (long long v = 0; v < (long long)nx * ny; ++v) {
+        double len = sqrt(dot3(n + 3 * v, n + 3 * v));
+        if (len > 0)
+            for (int q = 0; q < 3; ++q) n[3 * v + q] /= len;
+    }
+}
+
 /* ------------------------------------------------------------------ accessors */
 
 void orc_model_triangle(const orc_model *m, int t, double *A, double *n, double *lo, double *hi)
