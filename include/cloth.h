@@ -283,6 +283,21 @@ int cloth_batch_destroy(cloth_batch* b);
  */
 int cloth_debug_contacts(cloth_sim* sim, float h, int* counts, int* ids, int cap);
 
+/*
+ * cloth_vertex_normals / cloth_batch_vertex_normals -- per-vertex normals of the current
+ * cloth state (the normal update before shading, Sec. 3).  Each quad (i,j), (i+1,j),
+ * (i+1,j+1), (i,j+1) of the nx-by-ny grid (node (i,j) = i*nx + j) is split along its
+ * (i,j)-(i+1,j+1) diagonal into triangles (a,b,c) and (a,c,d); a vertex's normal is the
+ * normalised sum of (B-A) x (C-A) over the triangles that contain it (area weighting), or 0
+ * if that sum is 0 (e.g. a 1-wide strip).
+ * n_out [device] float[3 * N] (N = all nodes of the handle; for a batch, cloth i's nodes
+ * follow cloth i-1's), AoS in node-id order; caller-owned, written asynchronously on the
+ * handle's stream.  The first call allocates the node-order table (synchronises once).
+ * Errors: CLOTH_EINVAL for NULL arguments, CLOTH_EDEVICE for a HIP failure.
+ */
+int cloth_vertex_normals(cloth_sim* sim, float* n_out);
+int cloth_batch_vertex_normals(cloth_batch* b, float* n_out);
+
 /* cloth_status_str -- static text for a status code. */
 const char* cloth_status_str(int status);
 

@@ -90,6 +90,8 @@ _SIGNATURES = [
     ("cloth_batch_info", C.c_int, [_vp, _llp]),
     ("cloth_batch_destroy", C.c_int, [_vp]),
     ("cloth_debug_contacts", C.c_int, [_vp, C.c_float, _ip, _ip, C.c_int]),
+    ("cloth_vertex_normals", C.c_int, [_vp, _vp]),
+    ("cloth_batch_vertex_normals", C.c_int, [_vp, _vp]),
     ("cloth_status_str", C.c_char_p, [C.c_int]),
     ("cloth_last_error", C.c_char_p, []),
 ]
@@ -273,6 +275,24 @@ def cloth_rollout_backward(h, gx_out_ptr, gk_ptr, gc_ptr, gv0_ptr):
                                          _vp(gv0_ptr)))
 
 
+def cloth_vertex_normals(h, n_out_ptr):
+    """n_out_ptr: device pointer (int) to float[3 * N]; written on the handle's stream."""
+    _check(load().cloth_vertex_normals(_vp(h), _vp(n_out_ptr)))
+
+
+def cloth_batch_vertex_normals(h, n_out_ptr):
+    _check(load().cloth_batch_vertex_normals(_vp(h), _vp(n_out_ptr)))
+
+
+def _normals_tensor(n, out):
+    import torch
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    if out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous() or out.numel() != 3 * n:
+        raise ValueError("out must be a contiguous float32 CUDA tensor of 3*N elements")
+    return out
+
+
 def cloth_stability_bound(x0, mass, pinned, ends, k, c):
     """Host-only (omega2, gamma) bounds; see include/cloth.h."""
     lib = load()
@@ -330,6 +350,13 @@ class Cloth:
 
     def debug_candidates(self, points):
         return cloth_debug_candidates(self.h, points)
+
+    def vertex_normals(self, out=None):
+        """Per-vertex normals [N, 3] of the current state as a CUDA tensor, written on the
+        handle's stream (torch's current stream when the handle was made)."""
+        out = _normals_tensor(self.n, out)
+        cloth_vertex_normals(self.h, out.data_ptr())
+        return out
 
     def debug_contacts(self, h, cap=16):
         """Per node, the ascending triangle ids of its contacts in a substep of length h."""
@@ -411,6 +438,12 @@ class ClothBatch:
         v = np.zeros((n, 3), dtype=np.float32)
         _check(load().cloth_batch_read_state(_vp(self.h), int(i), _ptr(x, _fp), _ptr(v, _fp)))
         return x, v
+
+    def vertex_normals(self, out=None):
+        """Per-vertex normals [sum N_i, 3] of every cloth, cloth after cloth (CUDA tensor)."""
+        out = _normals_tensor(sum(int(i.nx * i.ny) for i in self.inputs), out)
+        cloth_batch_vertex_normals(self.h, out.data_ptr())
+        return out
 
     def set_launch(self, **kw):
         cfg = self.get_launch()

@@ -46,6 +46,11 @@ int cloth_batch_read_state(const cloth_batch* b, int i, float* x_out, float* v_o
     return read_state_range(b->sim, i, x_out, v_out);
 }
 
+int cloth_batch_vertex_normals(cloth_batch* b, float* n_out) {
+    if (!b) return fail(CLOTH_EINVAL, "NULL handle");
+    return vertex_normals(b->sim, n_out);
+}
+
 int cloth_batch_set_launch(cloth_batch* b, const cloth_launch* cfg) {
     if (!b || !cfg) return fail(CLOTH_EINVAL, "NULL argument");
     return set_launch(b->sim, *cfg);

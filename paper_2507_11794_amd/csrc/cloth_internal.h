@@ -140,6 +140,12 @@ hipError_t launch_set_params(size_t m, const int* code, const float* k, const fl
 hipError_t launch_set_params_plan(size_t m, const int* sid, const float* k, const float* c,
                                   float4* inc, hipStream_t st);
 hipError_t launch_d2f(size_t n, const double* a, float* b, hipStream_t st);
+// Per-vertex normals of the state x (SoA [3][ld], internal slots) into out (AoS, caller
+// numbering); order[slot] = node id, groups[g] = (node_off, nx, ny, 0), node_group[slot]
+// (NULL for one cloth).
+hipError_t launch_vertex_normals(int n, int ld, const float* x, const int* order, const int* slot,
+                                 const int* node_group, const int4* groups, float* out,
+                                 hipStream_t st);
 
 // --- a3 grid build ---------------------------------------------------------------------
 // Per triangle: inflated box, geometry, and the number of grid cells its box overlaps

@@ -389,6 +389,33 @@ int create_sim(const std::vector<ClothHostInput>& cloths, const cloth_params* p,
     return CLOTH_OK;
 }
 
+int vertex_normals(cloth_sim* s, float* n_out) {
+    if (!n_out) return fail(CLOTH_EINVAL, "n_out is NULL");
+    hipError_t e;
+    if (!s->order_dev) {
+        const size_t G = s->groups.size();
+        std::vector<int4> desc(G);
+        for (size_t g = 0; g < G; ++g)
+            desc[g] = make_int4(s->groups[g].node_off, s->groups[g].nx, s->groups[g].ny, 0);
+        int* order = nullptr;
+        int4* gd = nullptr;
+        if ((e = s->arena.alloc(&order, (size_t)s->n_nodes)) || (e = s->arena.alloc(&gd, G)) ||
+            (e = hipMemcpyAsync(order, s->host.order.data(), 4 * (size_t)s->n_nodes,
+                                hipMemcpyHostToDevice, s->stream)) ||
+            (e = hipMemcpyAsync(gd, desc.data(), G * sizeof(int4), hipMemcpyHostToDevice,
+                                s->stream)) ||
+            (e = hipStreamSynchronize(s->stream)))
+            return hip_fail(e, "normals set-up");
+        s->order_dev = order;
+        s->group_desc_dev = gd;
+    }
+    if ((e = launch_vertex_normals(s->n_nodes, s->dev.ld, s->dev.x[s->dev.cur], s->order_dev,
+                                   s->slot_dev, s->node_group_dev, s->group_desc_dev, n_out,
+                                   s->stream)))
+        return hip_fail(e, "normals");
+    return CLOTH_OK;
+}
+
 }  // namespace cloth
 
 using namespace cloth;
@@ -409,6 +436,11 @@ int cloth_create(int nx, int ny, const float* x0, const float* v0, const float* 
 int cloth_step(cloth_sim* s, float dt, int n_substeps, int n_steps) {
     if (!s) return fail(CLOTH_EINVAL, "NULL handle");
     return step_sim(s, dt, n_substeps, n_steps);
+}
+
+int cloth_vertex_normals(cloth_sim* s, float* n_out) {
+    if (!s) return fail(CLOTH_EINVAL, "NULL handle");
+    return vertex_normals(s, n_out);
 }
 
 int cloth_set_launch(cloth_sim* s, const cloth_launch* cfg) {

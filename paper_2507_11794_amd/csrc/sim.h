@@ -78,6 +78,9 @@ struct cloth_sim {
     float* x_init = nullptr;
     float* v_init = nullptr;
     int* slot_dev = nullptr;
+    // allocated by the first normals call: slot -> node id, per-cloth (node_off, nx, ny, 0)
+    int* order_dev = nullptr;
+    int4* group_desc_dev = nullptr;
     cloth::RolloutState roll;
 
     void drop_graphs() {
@@ -115,6 +118,9 @@ void refresh_stability(cloth_sim* s);
 // Copy the state of slots [slot_off, slot_off + n) to the host in caller numbering
 // (node id - node_off).
 int read_state_range(const cloth_sim* s, int group, float* x_out, float* v_out);
+// Per-vertex normals of the current state of every cloth into n_out (device, AoS, caller
+// numbering), on the handle's stream.
+int vertex_normals(cloth_sim* s, float* n_out);
 // Measured search over launch configurations (autotune.cpp).
 int autotune_sim(cloth_sim* s, float dt, int n_substeps, int frames, cloth_launch* best);
 
