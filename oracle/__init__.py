@@ -67,6 +67,8 @@ def _load():
                                      dp, dp, dp, dp, dp]
     lib.orc_model_triangle.argtypes = [P, C.c_int, dp, dp, dp, dp]
     lib.orc_vertex_normals.argtypes = [C.c_int, C.c_int, dp, dp]
+    lib.orc_model_set_surface.argtypes = [P, dp]
+    lib.orc_model_set_external.argtypes = [P, dp]
     _lib = lib
     return lib
 
@@ -135,6 +137,18 @@ class Model:
         if c is not None:
             self.c = _d(c)
         self._lib.orc_model_set_params(self._h, _dp(self.k), _dp(self.c))
+
+    def set_surface(self, verts):
+        """Move the surface: new vertex positions [V,3] for the same triangles."""
+        v = _d(verts).reshape(-1, 3)
+        assert v.shape == self.verts.shape
+        self.verts = v
+        self._lib.orc_model_set_surface(self._h, _dp(self.verts))
+
+    def set_external_force(self, f=None):
+        """Per-node external forces [N,3] added before integration (None removes them)."""
+        self.fext = None if f is None else _d(f).reshape(self.N, 3)
+        self._lib.orc_model_set_external(self._h, None if f is None else _dp(self.fext))
 
     def forces(self, x, v):
         x, v = _d(x).reshape(-1, 3), _d(v).reshape(-1, 3)

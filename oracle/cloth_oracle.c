@@ -14,7 +14,8 @@
  *          f   = (k (|x_b - x_a| - L0) + c (v_b . dir - v_a . dir)) dir
  *      added to node a and subtracted from node b (action and reaction).
  *   2. Explicit integration (Sec. 3 names an Euler method; read here as semi-implicit
- *      Euler): v* = v + h (w F + g), x* = x + h v*, with w = 1/m.  Pinned nodes (w = 0)
+ *      Euler): v* = v + h (w (F + f_ext) + g), x* = x + h v*, with w = 1/m and f_ext an
+ *      optional per-node external force (zero unless set).  Pinned nodes (w = 0)
  *      keep x and get v* = 0.
  *   3. Collision against a static triangle surface.  The paper averages a per-collision
  *      direction over all hits of a node (Sec. 3, collision paragraph) and applies it in
@@ -27,6 +28,9 @@
  *   only to skip triangles whose bounding box, inflated by th plus a slack of ORC_BOX_SLACK,
  *   cannot contain x*.  dist < th implies x* lies in that box, so the filter never changes
  *   the result; the slack lets the near-threshold margin see triangles just beyond th.
+ *
+ * The surface may be moved between substeps (orc_model_set_surface): each substep sees the
+ * surface as it was last set.
  *
  * Also here: the FP32 brute-force broad-phase predicate (the exact candidate set a
  * uniform grid must reproduce), the reverse-mode adjoint of one substep with the contact
@@ -62,12 +66,13 @@ typedef struct {
     double g[3];
     double *verts;      /* [V][3] */
     int *tris;          /* [T][3] */
+    double *fext;       /* [N][3] external forces (NULL = none) */
     double th;          /* collision thickness (0 disables collision) */
     double restitution; /* v <- -restitution v on contact */
     /* per triangle: first vertex, unit outward normal, inflated bounding box */
     double *tA, *tn, *tlo, *thi;
     /* bucket grid over the inflated boxes (acceleration only) */
-    double org[3], cell;
+    double org[3], cell, cell_req;
     int dim[3];
     int *cell_start, *cell_tris;
 } orc_model;
@@ -183,9 +188,36 @@ orc_model *orc_model_new(int N, const double *w, int S, const int *ends, const d
     m->th = th;
     m->restitution = restitution;
     if (th <= 0) m->T = T = 0; /* collision disabled */
+    m->cell_req = cell;
     build_surface(m, cell);
     return m;
 }
+
+/* Replace the surface's vertex positions (same triangles) and rebuild everything derived
+ * from them: a moving or deforming collision surface is a static one between two calls. */
+void orc_model_set_surface(orc_model *m, const double *verts)
+{
+    if (m->V) memcpy(m->verts, verts, sizeof(double) * (size_t)(3 * m->V));
+    free(m->tA); free(m->tn); free(m->tlo); free(m->thi);
+    free(m->cell_start); free(m->cell_tris);
+    m->cell_tris = NULL;
+    build_surface(m, m->cell_req);
+}
+
+/* External per-node forces f[N][3] (a pull on part of the cloth, Sec. 4's pulled-cloth
+ * scenes), added to the spring forces of every node before integration; NULL removes them.
+ * Pinned nodes ignore them like any force. */
+void orc_model_set_external(orc_model *m, const double *f)
+{
+    free(m->fext);
+    m->fext = NULL;
+    if (f) {
+        m->fext = malloc(sizeof(double) * 3 * (size_t)(m->N + 1));
+        memcpy(m->fext, f, sizeof(double) * 3 * (size_t)m->N);
+    }
+}
+
+static double fext_of(const orc_model *m, int i, int q) { return m->fext ? m->fext[3 * i + q] : 0.0; }
 
 void orc_model_set_params(orc_model *m, const double *k, const double *c)
 {
@@ -198,7 +230,7 @@ void orc_model_free(orc_model *m)
     if (!m) return;
     free(m->w); free(m->ends); free(m->rest); free(m->k); free(m->c);
     free(m->verts); free(m->tris); free(m->tA); free(m->tn); free(m->tlo); free(m->thi);
-    free(m->cell_start); free(m->cell_tris);
+    free(m->cell_start); free(m->cell_tris); free(m->fext);
     free(m);
 }
 
@@ -317,7 +349,7 @@ void orc_predict(const orc_model *m, double *x, double *v, double h)
             continue;
         }
         for (int q = 0; q < 3; ++q) {
-            v[3 * i + q] = v[3 * i + q] + h * (m->w[i] * F[3 * i + q] + m->g[q]);
+            v[3 * i + q] = v[3 * i + q] + h * (m->w[i] * (F[3 * i + q] + fext_of(m, i, q)) + m->g[q]);
             x[3 * i + q] = x[3 * i + q] + h * v[3 * i + q];
         }
     }
@@ -461,7 +493,7 @@ void orc_substep_vjp(const orc_model *m, const double *x, const double *v, doubl
         }
         double vs[3], xs[3];
         for (int q = 0; q < 3; ++q) {
-            vs[q] = v[3 * i + q] + h * (m->w[i] * F[3 * i + q] + m->g[q]);
+            vs[q] = v[3 * i + q] + h * (m->w[i] * (F[3 * i + q] + fext_of(m, i, q)) + m->g[q]);
             xs[q] = x[3 * i + q] + h * vs[q];
         }
         int n = contacts_of(m, xs, ids, ORC_MAX_CONTACTS, NULL);
