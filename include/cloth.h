@@ -284,6 +284,34 @@ int cloth_batch_destroy(cloth_batch* b);
 int cloth_debug_contacts(cloth_sim* sim, float h, int* counts, int* ids, int cap);
 
 /*
+ * cloth_update_surface / cloth_batch_update_surface -- move or deform a collision surface:
+ * new positions [host] float[n_verts * 3] for the same triangles (n_verts must equal the
+ * count given at creation; for a batch, cloth i's surface).  The grid is rebuilt on the
+ * device with the cell size fixed at creation; its origin and dims follow the new bounds.
+ * Substeps after the call see the new surface (the surface is static between two updates;
+ * the response stays v <- -restitution v, not relative to the surface's motion).  Buffers
+ * are reused while large enough.  Synchronises the handle's stream (the reference count is
+ * read back).  Ends a rollout's validity (CLOTH_ESTATE for a later backward).
+ * Errors: CLOTH_EINVAL (NULL, wrong n_verts, non-finite vertex, no collision surface),
+ * CLOTH_ENOMEM (grid too fine or too many references; raise cell_size), CLOTH_EDEVICE.
+ * A failure after the device arrays started changing leaves the handle refusing to step
+ * (CLOTH_ESTATE) until an update of that surface succeeds.
+ */
+int cloth_update_surface(cloth_sim* sim, const float* verts, int n_verts);
+int cloth_batch_update_surface(cloth_batch* b, int i, const float* verts, int n_verts);
+
+/*
+ * cloth_set_external_force / cloth_batch_set_external_force -- constant per-node external
+ * forces in newtons, f [host] float[N * 3] in node-id order (a batch: all cloths, cloth after
+ * cloth), added to the spring forces before integration: v* = v + h (w (F + f) + g) (the
+ * pulled-cloth scenes of Sec. 4).  Pinned nodes ignore it.  f = NULL removes the forces.
+ * The forces persist until the next call.  Synchronises the handle's stream.
+ * Errors: CLOTH_EINVAL (non-finite entry), CLOTH_ENOMEM, CLOTH_EDEVICE.
+ */
+int cloth_set_external_force(cloth_sim* sim, const float* f);
+int cloth_batch_set_external_force(cloth_batch* b, const float* f);
+
+/*
  * cloth_vertex_normals / cloth_batch_vertex_normals -- per-vertex normals of the current
  * cloth state (the normal update before shading, Sec. 3).  Each quad (i,j), (i+1,j),
  * (i+1,j+1), (i,j+1) of the nx-by-ny grid (node (i,j) = i*nx + j) is split along its

@@ -91,6 +91,10 @@ _SIGNATURES = [
     ("cloth_batch_destroy", C.c_int, [_vp]),
     ("cloth_debug_contacts", C.c_int, [_vp, C.c_float, _ip, _ip, C.c_int]),
     ("cloth_vertex_normals", C.c_int, [_vp, _vp]),
+    ("cloth_update_surface", C.c_int, [_vp, _fp, C.c_int]),
+    ("cloth_batch_update_surface", C.c_int, [_vp, C.c_int, _fp, C.c_int]),
+    ("cloth_set_external_force", C.c_int, [_vp, _fp]),
+    ("cloth_batch_set_external_force", C.c_int, [_vp, _fp]),
     ("cloth_batch_vertex_normals", C.c_int, [_vp, _vp]),
     ("cloth_status_str", C.c_char_p, [C.c_int]),
     ("cloth_last_error", C.c_char_p, []),
@@ -275,6 +279,18 @@ def cloth_rollout_backward(h, gx_out_ptr, gk_ptr, gc_ptr, gv0_ptr):
                                          _vp(gv0_ptr)))
 
 
+def cloth_update_surface(h, verts):
+    v = _f32(verts).reshape(-1, 3)
+    _check(load().cloth_update_surface(_vp(h), _ptr(v, _fp), int(v.shape[0])))
+
+
+def cloth_set_external_force(h, f):
+    if f is None:
+        _check(load().cloth_set_external_force(_vp(h), None))
+    else:
+        _check(load().cloth_set_external_force(_vp(h), _ptr(_f32(f).reshape(-1), _fp)))
+
+
 def cloth_vertex_normals(h, n_out_ptr):
     """n_out_ptr: device pointer (int) to float[3 * N]; written on the handle's stream."""
     _check(load().cloth_vertex_normals(_vp(h), _vp(n_out_ptr)))
@@ -350,6 +366,16 @@ class Cloth:
 
     def debug_candidates(self, points):
         return cloth_debug_candidates(self.h, points)
+
+    def update_surface(self, verts):
+        """Move the collision surface: new vertex positions [V, 3], same triangles."""
+        cloth_update_surface(self.h, verts)
+
+    def set_external_force(self, f=None):
+        """Per-node external forces [N, 3] in newtons (None removes them)."""
+        if f is not None and np.asarray(f).size != 3 * self.n:
+            raise ValueError("f must hold N x 3 values")
+        cloth_set_external_force(self.h, f)
 
     def vertex_normals(self, out=None):
         """Per-vertex normals [N, 3] of the current state as a CUDA tensor, written on the
@@ -438,6 +464,22 @@ class ClothBatch:
         v = np.zeros((n, 3), dtype=np.float32)
         _check(load().cloth_batch_read_state(_vp(self.h), int(i), _ptr(x, _fp), _ptr(v, _fp)))
         return x, v
+
+    def update_surface(self, i, verts):
+        v = _f32(verts).reshape(-1, 3)
+        _check(load().cloth_batch_update_surface(_vp(self.h), int(i), _ptr(v, _fp),
+                                                 int(v.shape[0])))
+
+    def set_external_force(self, f=None):
+        """Per-node external forces [sum N_i, 3] (cloth after cloth; None removes them)."""
+        n = sum(int(i.nx * i.ny) for i in self.inputs)
+        if f is None:
+            _check(load().cloth_batch_set_external_force(_vp(self.h), None))
+            return
+        f = _f32(f).reshape(-1)
+        if f.size != 3 * n:
+            raise ValueError("f must hold sum(N_i) x 3 values")
+        _check(load().cloth_batch_set_external_force(_vp(self.h), _ptr(f, _fp)))
 
     def vertex_normals(self, out=None):
         """Per-vertex normals [sum N_i, 3] of every cloth, cloth after cloth (CUDA tensor)."""

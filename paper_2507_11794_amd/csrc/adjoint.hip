@@ -47,6 +47,7 @@ __global__ void __launch_bounds__(256)
     // recompute the forward prediction exactly as the forward kernels do
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
     gather_global(cv, xs, vs, i, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz);
+    add_external(sp, i, fx, fy, fz);
     float px, py, pz, qx, qy, qz;
     integrate(w, sp.h, sp.g, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz, px, py, pz, qx, qy, qz);
     float sx = bx, sy = by, sz = bz, tx = cx, ty = cy, tz = cz;
@@ -153,6 +154,7 @@ __global__ void __launch_bounds__(256)
     const float vxi = vs[i], vyi = vs[ld + i], vzi = vs[2 * ld + i];
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
     gather_global(cv, xs, vs, i, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz);
+    add_external(sp, i, fx, fy, fz);
     float px, py, pz, qx, qy, qz;
     integrate(w, sp.h, sp.g, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz, px, py, pz, qx, qy, qz);
     int n = 0;

@@ -46,6 +46,17 @@ int cloth_batch_read_state(const cloth_batch* b, int i, float* x_out, float* v_o
     return read_state_range(b->sim, i, x_out, v_out);
 }
 
+int cloth_batch_update_surface(cloth_batch* b, int i, const float* verts, int n_verts) {
+    if (!b) return fail(CLOTH_EINVAL, "NULL handle");
+    if (i < 0 || i >= (int)b->sim->groups.size()) return fail(CLOTH_EINVAL, "cloth index out of range");
+    return update_surface(b->sim, i, verts, n_verts);
+}
+
+int cloth_batch_set_external_force(cloth_batch* b, const float* f) {
+    if (!b) return fail(CLOTH_EINVAL, "NULL handle");
+    return set_external_force(b->sim, f);
+}
+
 int cloth_batch_vertex_normals(cloth_batch* b, float* n_out) {
     if (!b) return fail(CLOTH_EINVAL, "NULL handle");
     return vertex_normals(b->sim, n_out);

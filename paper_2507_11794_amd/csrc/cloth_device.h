@@ -138,6 +138,16 @@ __device__ __forceinline__ float point_tri_dist2(float apx, float apy, float apz
     return s * s;  // face region: distance to the plane
 }
 
+// External force of the node in internal slot `slot`, added to its spring-force sum.
+__device__ __forceinline__ void add_external(const StepParams& sp, int slot, float& fx, float& fy,
+                                             float& fz) {
+    if (sp.fext) {
+        fx += sp.fext[slot];
+        fy += sp.fext[sp.fext_ld + slot];
+        fz += sp.fext[2 * sp.fext_ld + slot];
+    }
+}
+
 // a2: semi-implicit Euler for one node; pinned nodes (w = 0) keep x and get v* = 0.
 __device__ __forceinline__ void integrate(float w, float h, const float g[3], float xi, float yi,
                                           float zi, float vxi, float vyi, float vzi, float fx,

@@ -55,6 +55,8 @@ struct StepParams {
     float restitution;
     int check_nan;
     int* nan_flag;
+    const float* fext;  // external forces, SoA [3][fext_ld] by internal slot; NULL = none
+    int fext_ld;
 };
 
 // Temporally blocked tiles.  The internal node order is cut into tiles of consecutive
@@ -102,15 +104,15 @@ size_t tile_lds_bytes(int rmax, int block = 256, int stage_cap = 0);
 // Raise the tile kernels' dynamic LDS limit when a plan needs more than 64 KiB.
 hipError_t prepare_tile_kernels(size_t lds_bytes);
 
-// a1-a4: one substep for every node (one thread per node).  With node_group non-NULL the
-// node's surface is svs[node_group[i]] (a batch of cloths); otherwise sv.
-// stage_cap: reference boxes staged in LDS per wavefront for the collision query (0 = none;
-// at most kMaxStage).
+// a1-a4: one substep for every node (one thread per node).  collide = 0 skips a3/a4.  The
+// surfaces are read on the device: node i's is svs[node_group[i]] with node_group non-NULL
+// (a batch of cloths), otherwise svs[0].  stage_cap: reference boxes staged in LDS per
+// wavefront for the collision query (0 = none; at most kMaxStage).
 constexpr int kMaxStage = 1024;
-hipError_t launch_substep(const ClothView& cv, const SurfaceView& sv, const StepParams& sp,
-                          const float* xs, const float* vs, float* xd, float* vd, int block,
-                          hipStream_t stream, const SurfaceView* svs = nullptr,
-                          const int* node_group = nullptr, int stage_cap = 0);
+hipError_t launch_substep(const ClothView& cv, int collide, const StepParams& sp, const float* xs,
+                          const float* vs, float* xd, float* vd, int block, hipStream_t stream,
+                          const SurfaceView* svs, const int* node_group = nullptr,
+                          int stage_cap = 0);
 // Raise the one-substep kernel's dynamic LDS limit when its stage needs more than 64 KiB.
 hipError_t prepare_substep_kernels(size_t lds_bytes);
 

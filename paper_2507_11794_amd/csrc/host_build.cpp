@@ -321,6 +321,8 @@ constexpr size_t kRefPad = 8;
 
 // Uniform grid over the surface: origin fl32(min vertex) - thickness, cells of edge
 // cell_size, dims floor((fl32(max vertex + thickness) - origin) / cell_size) + 1 per axis.
+// The cell size is fixed when the surface is first built; origin, dims and every derived
+// array are recomputed by each rebuild.
 int build_surface(const ClothHostInput& in, const cloth_params& p, DeviceArena& arena,
                   hipStream_t stream, SurfaceDevice* sd) {
     sd->view = SurfaceView{};
@@ -349,92 +351,121 @@ int build_surface(const ClothHostInput& in, const cloth_params& p, DeviceArena& 
         }
         cell = (double)(float)(2.0 * sum / (double)edges.size());
     }
-    float vmin[3] = {INFINITY, INFINITY, INFINITY}, vmax[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int i = 0; i < Vn; ++i)
-        for (int q = 0; q < 3; ++q) {
-            vmin[q] = std::min(vmin[q], in.verts[3 * i + q]);
-            vmax[q] = std::max(vmax[q], in.verts[3 * i + q]);
-        }
     SurfaceView& sv = sd->view;
     sv.inv_cell = (float)(1.0 / cell);
-    long long cells = 1;
-    for (int q = 0; q < 3; ++q) {
-        // origin at or below every inflated low corner; dims so the largest inflated high
-        // corner maps to dim - 1 with the kernels' own FP32 formula floor((p - org) * inv)
-        sv.org[q] = vmin[q] - p.thickness;
-        const float hmax = vmax[q] + p.thickness;
-        volatile float diff = hmax - sv.org[q];
-        volatile float scaled = diff * sv.inv_cell;
-        const double top = std::floor((double)scaled);
-        if (!(top < (double)(1 << 20))) return fail(CLOTH_ENOMEM, "grid too fine for the surface; raise cell_size");
-        sv.dim[q] = (int)top + 1;
-        cells *= sv.dim[q];
-    }
-    if (cells > (1LL << 27)) return fail(CLOTH_ENOMEM, "grid too fine for the surface; raise cell_size");
     sv.thickness = p.thickness;
     sv.thickness2 = p.thickness * p.thickness;
     sv.n_tris = T;
     sd->cell = cell;
-    sd->n_cells = cells;
-
+    sd->n_verts = Vn;
     hipError_t e;
-    float* d_verts = nullptr;
-    int* d_tris = nullptr;
-    unsigned long long* d_total = nullptr;
-    float4 *box_lo, *box_hi, *geo;
-    if ((e = arena.alloc(&d_verts, 3 * (size_t)Vn)) || (e = arena.alloc(&d_tris, 3 * (size_t)T)) ||
-        (e = arena.alloc(&d_total, 1)) || (e = arena.alloc(&box_lo, (size_t)T)) ||
-        (e = arena.alloc(&box_hi, (size_t)T)) || (e = arena.alloc(&geo, 3 * (size_t)T)))
+    if ((e = arena.alloc(&sd->verts, 3 * (size_t)Vn)) || (e = arena.alloc(&sd->tris, 3 * (size_t)T)) ||
+        (e = arena.alloc(&sd->total, 1)) || (e = arena.alloc(&sd->box_lo, (size_t)T)) ||
+        (e = arena.alloc(&sd->box_hi, (size_t)T)) || (e = arena.alloc(&sd->geo, 3 * (size_t)T)))
         return hip_fail(e, "hipMalloc surface");
-    if ((e = hipMemcpyAsync(d_verts, in.verts, 12 * (size_t)Vn, hipMemcpyHostToDevice, stream)) ||
-        (e = hipMemcpyAsync(d_tris, in.tris, 12 * (size_t)T, hipMemcpyHostToDevice, stream)) ||
-        (e = hipMemsetAsync(d_total, 0, 8, stream)))
+    if ((e = hipMemcpyAsync(sd->tris, in.tris, 12 * (size_t)T, hipMemcpyHostToDevice, stream)))
         return hip_fail(e, "upload surface");
-    if ((e = launch_tri_prep(T, d_verts, d_tris, sv.thickness, sv.org, sv.inv_cell, sv.dim, box_lo,
-                             box_hi, geo, d_total, stream)))
+    return rebuild_surface(sd, in.verts, arena, stream);
+}
+
+int rebuild_surface(SurfaceDevice* sd, const float* verts, DeviceArena& arena,
+                    hipStream_t stream) {
+    SurfaceView& sv = sd->view;
+    const int T = sv.n_tris, Vn = sd->n_verts;
+    float vmin[3] = {INFINITY, INFINITY, INFINITY}, vmax[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = 0; i < Vn; ++i)
+        for (int q = 0; q < 3; ++q) {
+            const float c = verts[3 * i + q];
+            if (!std::isfinite(c)) return fail(CLOTH_EINVAL, "non-finite surface vertex");
+            vmin[q] = std::min(vmin[q], c);
+            vmax[q] = std::max(vmax[q], c);
+        }
+    float org[3];
+    int dim[3];
+    long long cells = 1;
+    for (int q = 0; q < 3; ++q) {
+        // origin at or below every inflated low corner; dims so the largest inflated high
+        // corner maps to dim - 1 with the kernels' own FP32 formula floor((p - org) * inv)
+        org[q] = vmin[q] - sv.thickness;
+        const float hmax = vmax[q] + sv.thickness;
+        volatile float diff = hmax - org[q];
+        volatile float scaled = diff * sv.inv_cell;
+        const double top = std::floor((double)scaled);
+        if (!(top < (double)(1 << 20))) return fail(CLOTH_ENOMEM, "grid too fine for the surface; raise cell_size");
+        dim[q] = (int)top + 1;
+        cells *= dim[q];
+    }
+    if (cells > (1LL << 27)) return fail(CLOTH_ENOMEM, "grid too fine for the surface; raise cell_size");
+    const size_t C = (size_t)cells;
+    hipError_t e;
+    sd->dirty = true;
+    // every buffer is reused while it is large enough, so a moving surface reallocates only
+    // when its grid or reference count grows
+    if (C > sd->cap_cells) {
+        if ((e = hipStreamSynchronize(stream))) return hip_fail(e, "grid resize");
+        arena.free_one(sd->counts);
+        arena.free_one(sd->cell_start);
+        arena.free_one(sd->tmp);
+        sd->counts = sd->cell_start = sd->tmp = nullptr;
+        sd->cap_cells = 0;
+        const size_t cap = C + C / 4;
+        if ((e = arena.alloc(&sd->counts, cap)) || (e = arena.alloc(&sd->cell_start, cap + 1)) ||
+            (e = arena.alloc(&sd->tmp, scan_tmp_words(cap))))
+            return hip_fail(e, "hipMalloc grid");
+        sd->cap_cells = cap;
+    }
+    for (int q = 0; q < 3; ++q) {
+        sv.org[q] = org[q];
+        sv.dim[q] = dim[q];
+    }
+    sd->n_cells = cells;
+    if ((e = hipMemcpyAsync(sd->verts, verts, 12 * (size_t)Vn, hipMemcpyHostToDevice, stream)) ||
+        (e = hipMemsetAsync(sd->total, 0, 8, stream)))
+        return hip_fail(e, "upload surface");
+    if ((e = launch_tri_prep(T, sd->verts, sd->tris, sv.thickness, sv.org, sv.inv_cell, sv.dim,
+                             sd->box_lo, sd->box_hi, sd->geo, sd->total, stream)))
         return hip_fail(e, "triangle prep");
     unsigned long long total = 0;
-    if ((e = hipMemcpyAsync(&total, d_total, 8, hipMemcpyDeviceToHost, stream)) ||
+    if ((e = hipMemcpyAsync(&total, sd->total, 8, hipMemcpyDeviceToHost, stream)) ||
         (e = hipStreamSynchronize(stream)))
         return hip_fail(e, "read reference count");
     if (total > (1ULL << 30)) return fail(CLOTH_ENOMEM, "too many grid references; raise cell_size");
-    uint32_t *counts, *cell_start, *refs, *tmp;
-    const size_t C = (size_t)cells;
-    if ((e = arena.alloc(&counts, C)) || (e = arena.alloc(&cell_start, C + 1)) ||
-        (e = arena.alloc(&refs, (size_t)total + kRefPad)) ||
-        (e = arena.alloc(&tmp, scan_tmp_words(C))))
-        return hip_fail(e, "hipMalloc grid");
+    if ((size_t)total + kRefPad > sd->cap_refs) {
+        arena.free_one(sd->refs);
+        arena.free_one(sd->ref_lo);
+        arena.free_one(sd->ref_hi);
+        sd->refs = nullptr;
+        sd->ref_lo = sd->ref_hi = nullptr;
+        sd->cap_refs = 0;
+        const size_t cap = (size_t)total + (size_t)total / 4 + kRefPad;
+        if ((e = arena.alloc(&sd->refs, cap)) || (e = arena.alloc(&sd->ref_lo, cap)) ||
+            (e = arena.alloc(&sd->ref_hi, cap)))
+            return hip_fail(e, "hipMalloc grid");
+        sd->cap_refs = cap;
+    }
     // kRefPad zero entries after the last reference let the query loop load references in
     // groups of four without a bounds test (triangle 0 is always a valid index)
-    if ((e = hipMemsetAsync(refs, 0, 4 * ((size_t)total + kRefPad), stream)) ||
-        (e = hipMemsetAsync(counts, 0, 4 * C, stream)) ||
-        (e = launch_grid_count(T, box_lo, box_hi, sv.org, sv.inv_cell, sv.dim, counts, stream)) ||
-        (e = scan_exclusive_u32(counts, cell_start, C, tmp, stream)) ||
-        (e = hipMemsetAsync(counts, 0, 4 * C, stream)) ||
-        (e = launch_grid_fill(T, box_lo, box_hi, sv.org, sv.inv_cell, sv.dim, cell_start, counts,
-                              refs, stream)) ||
-        (e = launch_grid_sort((int)C, cell_start, refs, stream)) || (e = hipStreamSynchronize(stream)))
+    if ((e = hipMemsetAsync(sd->refs + total, 0, 4 * kRefPad, stream)) ||
+        (e = hipMemsetAsync(sd->counts, 0, 4 * C, stream)) ||
+        (e = launch_grid_count(T, sd->box_lo, sd->box_hi, sv.org, sv.inv_cell, sv.dim, sd->counts,
+                               stream)) ||
+        (e = scan_exclusive_u32(sd->counts, sd->cell_start, C, sd->tmp, stream)) ||
+        (e = hipMemsetAsync(sd->counts, 0, 4 * C, stream)) ||
+        (e = launch_grid_fill(T, sd->box_lo, sd->box_hi, sv.org, sv.inv_cell, sv.dim,
+                              sd->cell_start, sd->counts, sd->refs, stream)) ||
+        (e = launch_grid_sort((int)C, sd->cell_start, sd->refs, stream)) ||
+        (e = launch_ref_boxes((size_t)total + kRefPad, sd->refs, sd->box_lo, sd->box_hi,
+                              sd->ref_lo, sd->ref_hi, stream)))
         return hip_fail(e, "grid build");
-    float4 *ref_lo, *ref_hi;
-    if ((e = arena.alloc(&ref_lo, (size_t)total + kRefPad)) ||
-        (e = arena.alloc(&ref_hi, (size_t)total + kRefPad)) ||
-        (e = launch_ref_boxes((size_t)total + kRefPad, refs, box_lo, box_hi, ref_lo, ref_hi,
-                              stream)) ||
-        (e = hipStreamSynchronize(stream)))
-        return hip_fail(e, "reference boxes");
-    sv.ref_lo = ref_lo;
-    sv.ref_hi = ref_hi;
-    arena.free_one(counts);
-    arena.free_one(tmp);
-    arena.free_one(d_verts);
-    arena.free_one(d_tris);
-    arena.free_one(d_total);
-    sv.cell_start = cell_start;
-    sv.refs = refs;
-    sv.box_lo = box_lo;
-    sv.box_hi = box_hi;
-    sv.geo = geo;
+    sv.cell_start = sd->cell_start;
+    sv.refs = sd->refs;
+    sv.ref_lo = sd->ref_lo;
+    sv.ref_hi = sd->ref_hi;
+    sv.box_lo = sd->box_lo;
+    sv.box_hi = sd->box_hi;
+    sv.geo = sd->geo;
     sd->n_refs = (long long)total;
+    sd->dirty = false;
     return CLOTH_OK;
 }
 

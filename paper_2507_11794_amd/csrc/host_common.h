@@ -102,6 +102,16 @@ struct SurfaceDevice {
     SurfaceView view{};
     double cell = 0.0;
     long long n_cells = 0, n_refs = 0;
+    int n_verts = 0;
+    // build buffers, kept for rebuilds (capacities in elements)
+    float* verts = nullptr;
+    int* tris = nullptr;
+    unsigned long long* total = nullptr;
+    float4 *box_lo = nullptr, *box_hi = nullptr, *geo = nullptr;
+    uint32_t *counts = nullptr, *cell_start = nullptr, *tmp = nullptr, *refs = nullptr;
+    float4 *ref_lo = nullptr, *ref_hi = nullptr;
+    size_t cap_cells = 0, cap_refs = 0;
+    bool dirty = false;  // a rebuild started rewriting the arrays and has not completed
 };
 
 std::vector<int> tile_order(int nx, int ny);
@@ -115,6 +125,10 @@ int build_cloth_host(const ClothHostInput& in, ClothHost* out,
 int upload_cloth(const ClothHost& h, DeviceArena& arena, hipStream_t stream, ClothDevice* d);
 int build_surface(const ClothHostInput& in, const cloth_params& p, DeviceArena& arena,
                   hipStream_t stream, SurfaceDevice* sd);
+// Rebuild the grid and every per-triangle array for new vertex positions [n_verts][3] (host)
+// of the same triangles; synchronises the stream once (to size the reference array).
+int rebuild_surface(SurfaceDevice* sd, const float* verts, DeviceArena& arena,
+                    hipStream_t stream);
 int build_tile_plan(const ClothHost& h, const std::vector<int>& group_off, int tile_nodes, int K,
                     hipStream_t stream, TilePlanDevice* out);
 int build_schedule(TilePlanDevice* plan, int mode, int n_workgroups, hipStream_t stream);

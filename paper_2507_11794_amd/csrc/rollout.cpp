@@ -56,6 +56,8 @@ StepParams step_params(const cloth_sim* s, float h) {
     sp.restitution = s->p.restitution;
     sp.check_nan = 0;
     sp.nan_flag = s->nan_flag;
+    sp.fext = s->fext_on ? s->fext_dev : nullptr;
+    sp.fext_ld = s->dev.ld;
     return sp;
 }
 
@@ -68,6 +70,7 @@ int cloth_rollout_forward(cloth_sim* s, const float* k_dev, const float* c_dev,
                           int ckpt_every, const int* out_steps, int n_out, float* x_out_dev) {
     if (!s) return fail(CLOTH_EINVAL, "NULL handle");
     if (s->groups.size() != 1) return fail(CLOTH_EINVAL, "rollouts take a single-cloth handle");
+    if (s->surface_broken) return fail(CLOTH_ESTATE, "a surface update failed; update it again first");
     if (s->n_springs > 0 && (!k_dev || !c_dev)) return fail(CLOTH_EINVAL, "k and c are required");
     if (!(dt > 0.0f) || !std::isfinite(dt) || n_substeps < 1 || n_steps < 0 || ckpt_every < 1)
         return fail(CLOTH_EINVAL, "need dt > 0, n_substeps >= 1, n_steps >= 0, ckpt_every >= 1");
@@ -182,8 +185,8 @@ int cloth_rollout_backward(cloth_sim* s, const float* gx_out_dev, float* gk_dev,
         for (long long r = 1; r < top - base; ++r) {
             const float* xs = R.seg + (size_t)(r - 1) * state;
             float* xd = R.seg + (size_t)r * state;
-            if ((e = launch_substep(cv, s->surfs[0].view, sp, xs, xs + 3 * ld, xd, xd + 3 * ld, 256,
-                                    s->stream)))
+            if ((e = launch_substep(cv, s->surfs[0].view.n_tris > 0, sp, xs, xs + 3 * ld, xd,
+                                    xd + 3 * ld, 256, s->stream, s->svs_dev)))
                 return hip_fail(e, "recompute segment");
         }
         for (long long t = top; t > base; --t) {
@@ -208,6 +211,7 @@ int cloth_rollout_backward(cloth_sim* s, const float* gx_out_dev, float* gk_dev,
 int cloth_debug_contacts(cloth_sim* s, float h, int* counts, int* ids, int cap) {
     if (!s || !counts) return fail(CLOTH_EINVAL, "NULL argument");
     if (s->groups.size() != 1) return fail(CLOTH_EINVAL, "single-cloth handles only");
+    if (s->surface_broken) return fail(CLOTH_ESTATE, "a surface update failed; update it again first");
     if (!(h > 0.0f) || !std::isfinite(h) || cap < 0 || (cap > 0 && !ids))
         return fail(CLOTH_EINVAL, "need h > 0 and ids when cap > 0");
     const int N = s->dev.n;

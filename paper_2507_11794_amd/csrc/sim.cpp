@@ -109,10 +109,10 @@ hipError_t launch_once(cloth_sim* s, const StepParams& sp, int K, int src, hipSt
                             s->dev.x[dst], s->dev.v[dst], s->launch.block_threads,
                             s->launch.stage_refs, st);
     if (s->groups.size() == 1)
-        return launch_substep(s->dev.view(), s->surfs[0].view, sp, s->dev.x[src], s->dev.v[src],
-                              s->dev.x[dst], s->dev.v[dst], s->launch.block_threads, st, nullptr,
-                              nullptr, s->launch.stage_refs);
-    return launch_substep(s->dev.view(), s->surfs[0].view, sp, s->dev.x[src], s->dev.v[src],
+        return launch_substep(s->dev.view(), s->surfs[0].view.n_tris > 0, sp, s->dev.x[src],
+                              s->dev.v[src], s->dev.x[dst], s->dev.v[dst], s->launch.block_threads,
+                              st, s->svs_dev, nullptr, s->launch.stage_refs);
+    return launch_substep(s->dev.view(), s->any_collision, sp, s->dev.x[src], s->dev.v[src],
                           s->dev.x[dst], s->dev.v[dst], s->launch.block_threads, st, s->svs_dev,
                           s->node_group_dev);
 }
@@ -169,6 +169,8 @@ int run_substeps(cloth_sim* s, float h, long long total) {
     sp.restitution = s->p.restitution;
     sp.check_nan = (s->p.flags & CLOTH_F_CHECK_NAN) ? 1 : 0;
     sp.nan_flag = s->nan_flag;
+    sp.fext = s->fext_on ? s->fext_dev : nullptr;
+    sp.fext_ld = s->dev.ld;
     int st = CLOTH_OK;
     if (!s->launch_ready) {
         if ((st = set_launch(s, s->launch)) != CLOTH_OK) return st;
@@ -208,6 +210,8 @@ int run_substeps(cloth_sim* s, float h, long long total) {
 }
 
 int step_sim(cloth_sim* s, float dt, int n_substeps, int n_steps) {
+    if (s->surface_broken)
+        return fail(CLOTH_ESTATE, "a surface update failed; the handle cannot step until one succeeds");
     if (!(dt > 0.0f) || !std::isfinite(dt)) return fail(CLOTH_EINVAL, "dt must be positive and finite");
     if (n_substeps < 1 || n_steps < 0) return fail(CLOTH_EINVAL, "n_substeps >= 1 and n_steps >= 0");
     const float h = dt / (float)n_substeps;
@@ -389,6 +393,55 @@ int create_sim(const std::vector<ClothHostInput>& cloths, const cloth_params* p,
     return CLOTH_OK;
 }
 
+int update_surface(cloth_sim* s, int group, const float* verts, int n_verts) {
+    if (!verts) return fail(CLOTH_EINVAL, "verts is NULL");
+    SurfaceDevice& sd = s->surfs[group];
+    if (sd.view.n_tris == 0) return fail(CLOTH_EINVAL, "the cloth has no collision surface");
+    if (n_verts != sd.n_verts)
+        return fail(CLOTH_EINVAL, "n_verts must equal the surface's vertex count (" +
+                                      std::to_string(sd.n_verts) + ")");
+    const int st = rebuild_surface(&sd, verts, s->arena, s->stream);
+    // a rebuild that failed after it started rewriting device arrays leaves that surface
+    // inconsistent: the handle refuses to step until a rebuild of it succeeds
+    s->surface_broken = false;
+    for (const auto& other : s->surfs) s->surface_broken |= other.dirty;
+    if (st != CLOTH_OK) return st;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(s->svs_dev + group, &sd.view, sizeof(SurfaceView),
+                            hipMemcpyHostToDevice, s->stream)) ||
+        (e = hipStreamSynchronize(s->stream)))
+        return hip_fail(e, "surface update");
+    s->roll.ready = false;  // a rollout's contact sets were taken against the old surface
+    return CLOTH_OK;
+}
+
+int set_external_force(cloth_sim* s, const float* f) {
+    s->roll.ready = false;
+    if (!f) {
+        if (s->fext_on) s->drop_graphs();  // captured launches hold the force pointer
+        s->fext_on = false;
+        return CLOTH_OK;
+    }
+    const size_t N = (size_t)s->n_nodes, ld = (size_t)s->dev.ld;
+    std::vector<float> soa(3 * ld, 0.0f);
+    for (size_t p = 0; p < N; ++p) {
+        const size_t id = (size_t)s->host.order[p];
+        for (int q = 0; q < 3; ++q) {
+            const float v = f[3 * id + q];
+            if (!std::isfinite(v)) return fail(CLOTH_EINVAL, "non-finite external force");
+            soa[q * ld + p] = v;
+        }
+    }
+    hipError_t e;
+    if (!s->fext_dev && (e = s->arena.alloc(&s->fext_dev, 3 * ld))) return hip_fail(e, "hipMalloc force");
+    if ((e = hipMemcpyAsync(s->fext_dev, soa.data(), 12 * ld, hipMemcpyHostToDevice, s->stream)) ||
+        (e = hipStreamSynchronize(s->stream)))
+        return hip_fail(e, "upload force");
+    if (!s->fext_on) s->drop_graphs();
+    s->fext_on = true;
+    return CLOTH_OK;
+}
+
 int vertex_normals(cloth_sim* s, float* n_out) {
     if (!n_out) return fail(CLOTH_EINVAL, "n_out is NULL");
     hipError_t e;
@@ -436,6 +489,17 @@ int cloth_create(int nx, int ny, const float* x0, const float* v0, const float* 
 int cloth_step(cloth_sim* s, float dt, int n_substeps, int n_steps) {
     if (!s) return fail(CLOTH_EINVAL, "NULL handle");
     return step_sim(s, dt, n_substeps, n_steps);
+}
+
+int cloth_update_surface(cloth_sim* s, const float* verts, int n_verts) {
+    if (!s) return fail(CLOTH_EINVAL, "NULL handle");
+    if (s->groups.size() != 1) return fail(CLOTH_EINVAL, "use cloth_batch_update_surface for a batch");
+    return update_surface(s, 0, verts, n_verts);
+}
+
+int cloth_set_external_force(cloth_sim* s, const float* f) {
+    if (!s) return fail(CLOTH_EINVAL, "NULL handle");
+    return set_external_force(s, f);
 }
 
 int cloth_vertex_normals(cloth_sim* s, float* n_out) {
@@ -525,6 +589,7 @@ int cloth_debug_candidates(cloth_sim* s, int n_points, const float* points, int*
     if (cap > 0 && !pairs_out) return fail(CLOTH_EINVAL, "pairs_out is NULL");
     const SurfaceView& sv = s->surfs[0].view;
     if (sv.n_tris == 0) return fail(CLOTH_EINVAL, "collision is disabled for this handle");
+    if (s->surface_broken) return fail(CLOTH_ESTATE, "a surface update failed; update it again first");
     *n_out = 0;
     if (n_points == 0) return CLOTH_OK;
     DeviceArena tmp;

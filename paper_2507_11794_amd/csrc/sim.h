@@ -81,6 +81,10 @@ struct cloth_sim {
     // allocated by the first normals call: slot -> node id, per-cloth (node_off, nx, ny, 0)
     int* order_dev = nullptr;
     int4* group_desc_dev = nullptr;
+    // external forces (SoA [3][ld], internal slots), allocated by the first set call
+    float* fext_dev = nullptr;
+    bool fext_on = false;
+    bool surface_broken = false;  // a surface rebuild failed part-way: stepping is refused
     cloth::RolloutState roll;
 
     void drop_graphs() {
@@ -118,6 +122,10 @@ void refresh_stability(cloth_sim* s);
 // Copy the state of slots [slot_off, slot_off + n) to the host in caller numbering
 // (node id - node_off).
 int read_state_range(const cloth_sim* s, int group, float* x_out, float* v_out);
+// New vertex positions for cloth `group`'s surface (same triangles): rebuilds its grid.
+int update_surface(cloth_sim* s, int group, const float* verts, int n_verts);
+// Per-node external forces [n_nodes][3] in caller numbering (NULL removes them).
+int set_external_force(cloth_sim* s, const float* f);
 // Per-vertex normals of the current state of every cloth into n_out (device, AoS, caller
 // numbering), on the handle's stream.
 int vertex_normals(cloth_sim* s, float* n_out);

@@ -16,10 +16,10 @@ namespace cloth {
 
 template <bool COLLIDE, bool GROUPED>
 __global__ void __launch_bounds__(256)
-    k_substep(const ClothView cv, const SurfaceView sv1, const StepParams sp,
-              const float* __restrict__ xs, const float* __restrict__ vs, float* __restrict__ xd,
-              float* __restrict__ vd, const SurfaceView* __restrict__ svs,
-              const int* __restrict__ node_group, const int stage_cap) {
+    k_substep(const ClothView cv, const StepParams sp, const float* __restrict__ xs,
+              const float* __restrict__ vs, float* __restrict__ xd, float* __restrict__ vd,
+              const SurfaceView* __restrict__ svs, const int* __restrict__ node_group,
+              const int stage_cap) {
     extern __shared__ float4 stage[];  // [wavefronts][2][stage_cap]
     // workgroups are dealt round-robin to the 8 XCDs: give each XCD a contiguous node range
     const int nb = gridDim.x, q8 = nb >> 3, rem = nb & 7, x8 = blockIdx.x & 7;
@@ -35,6 +35,7 @@ __global__ void __launch_bounds__(256)
         // a1: gather
         float fx = 0.0f, fy = 0.0f, fz = 0.0f;
         gather_global(cv, xs, vs, i, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz);
+        add_external(sp, i, fx, fy, fz);
         // a2: integrate
         integrate(w, sp.h, sp.g, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz, px, py, pz, qx, qy, qz);
     }
@@ -45,12 +46,17 @@ __global__ void __launch_bounds__(256)
                 const SurfaceView sv = svs[node_group[i]];
                 if (sv.n_tris > 0) collide(sv, sp.restitution, px, py, pz, qx, qy, qz);
             }
-        } else if (stage_cap > 0) {
-            float4* lo = stage + (size_t)(threadIdx.x >> 6) * 2 * stage_cap;
-            collide_wave(sv1, lo, lo + stage_cap, stage_cap, valid && w != 0.0f, sp.restitution,
-                         px, py, pz, qx, qy, qz);
-        } else if (valid && w != 0.0f) {
-            collide(sv1, sp.restitution, px, py, pz, qx, qy, qz);
+        } else {
+            // the surface is read from device memory, so captured graphs stay valid when it
+            // is rebuilt
+            const SurfaceView sv1 = svs[0];
+            if (stage_cap > 0) {
+                float4* lo = stage + (size_t)(threadIdx.x >> 6) * 2 * stage_cap;
+                collide_wave(sv1, lo, lo + stage_cap, stage_cap, valid && w != 0.0f,
+                             sp.restitution, px, py, pz, qx, qy, qz);
+            } else if (valid && w != 0.0f) {
+                collide(sv1, sp.restitution, px, py, pz, qx, qy, qz);
+            }
         }
     }
     if (!valid) return;
@@ -72,23 +78,22 @@ hipError_t prepare_substep_kernels(size_t lds_bytes) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
 }
 
-hipError_t launch_substep(const ClothView& cv, const SurfaceView& sv, const StepParams& sp,
-                          const float* xs, const float* vs, float* xd, float* vd, int block,
-                          hipStream_t stream, const SurfaceView* svs, const int* node_group,
-                          int stage_cap) {
+hipError_t launch_substep(const ClothView& cv, int collide, const StepParams& sp, const float* xs,
+                          const float* vs, float* xd, float* vd, int block, hipStream_t stream,
+                          const SurfaceView* svs, const int* node_group, int stage_cap) {
     if (cv.n <= 0) return hipSuccess;
     if (block <= 0 || block > 256 || (block & 63)) block = 256;
     const int grid = (cv.n + block - 1) / block;
-    if (svs && node_group) {
-        k_substep<true, true><<<grid, block, 0, stream>>>(cv, sv, sp, xs, vs, xd, vd, svs,
-                                                          node_group, 0);
-    } else if (sv.n_tris > 0) {
+    if (collide && node_group) {
+        k_substep<true, true><<<grid, block, 0, stream>>>(cv, sp, xs, vs, xd, vd, svs, node_group,
+                                                          0);
+    } else if (collide) {
         const size_t lds = (size_t)(block / 64) * 2 * stage_cap * sizeof(float4);
-        k_substep<true, false><<<grid, block, lds, stream>>>(cv, sv, sp, xs, vs, xd, vd, nullptr,
-                                                             nullptr, stage_cap);
+        k_substep<true, false><<<grid, block, lds, stream>>>(cv, sp, xs, vs, xd, vd, svs, nullptr,
+                                                             stage_cap);
     } else {
-        k_substep<false, false><<<grid, block, 0, stream>>>(cv, sv, sp, xs, vs, xd, vd, nullptr,
-                                                            nullptr, 0);
+        k_substep<false, false><<<grid, block, 0, stream>>>(cv, sp, xs, vs, xd, vd, svs, nullptr,
+                                                            0);
     }
     return hipGetLastError();
 }

@@ -74,6 +74,7 @@ __device__ __forceinline__ void run_tile(const TileView& tv, const TileMeta& m, 
                                          fy, fz);
                         }
                 }
+                add_external(sp, rs[u], fx, fy, fz);
                 integrate(w, sp.h, sp.g, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz, px, py, pz, qx,
                           qy, qz);
             }

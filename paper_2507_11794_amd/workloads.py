@@ -407,5 +407,31 @@ def small_collision_scene(n: int = 24, freq: int = 6, seed: int = 7, drop: float
                    name=f"small cloth {n}x{n} vs sphere {tris.shape[0]} tris")
 
 
+def pulled_cloth_scene(n: int = 24, freq: int = 6, seed: int = 9, spacing: float = 0.015,
+                       drop: float = 0.165, pull: float = 0.004, n_steps: int = 120):
+    """A cloth dropped onto a sphere whose last row is pulled along +x (the pulled-cloth
+    scenes of Sec. 4): returns (inputs, f_ext [N,3] float32 in newtons)."""
+    inp = small_collision_scene(n=n, freq=freq, seed=seed, drop=drop, spacing=spacing,
+                                n_steps=n_steps)
+    f = np.zeros((inp.n_nodes, 3), dtype=np.float32)
+    f[(n - 1) * n:, 0] = pull
+    inp.name = f"pulled cloth {n}x{n} vs sphere {inp.n_tris} tris"
+    return inp, f
+
+
+def moving_surface(verts: np.ndarray, frame: int, dt: float, velocity=(0.0, 0.04, 0.0),
+                   omega: float = 0.6) -> np.ndarray:
+    """Surface vertices at the start of `frame`: the input mesh rotated about the vertical
+    axis through its centroid by omega t and translated by velocity t (t = frame dt), as
+    float32 (a rigidly moving collision surface)."""
+    v = np.asarray(verts, dtype=np.float64)
+    t = frame * dt
+    c = v.mean(axis=0)
+    a = omega * t
+    R = np.array([[math.cos(a), 0.0, math.sin(a)], [0.0, 1.0, 0.0],
+                  [-math.sin(a), 0.0, math.cos(a)]])
+    return ((v - c) @ R.T + c + np.asarray(velocity) * t).astype(np.float32)
+
+
 def config(i: int, **kw):
     return [config0, config1, config2, config3, config4][i](**kw)

@@ -1,0 +1,185 @@
+"""GPU moving surface (cloth_update_surface: per-frame grid rebuild) and external pull forces
+(cloth_set_external_force) against the FP64 oracle, plus bitwise identity of every launch
+configuration (graphs included) across surface updates, and batch == plain handles.
+Tolerances as in the other parity tests (one substep: 2e-6 of the cloth side, 2e-3 m/s plus
+1e-4 relative; near-threshold contacts resolved)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.parity import substep_parity
+from paper_2507_11794_amd import cloth as B
+from paper_2507_11794_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def h32(inp):
+    return float(np.float32(np.float32(inp.dt) / np.float32(inp.n_substeps)))
+
+
+def side(inp):
+    return float(np.max(np.ptp(inp.x0.astype(np.float64), axis=0)))
+
+
+def _probe_points(verts, tris, th, rng, n=1200):
+    V = verts.astype(np.float64)
+    pts = [V[rng.integers(0, V.shape[0], n)] + rng.normal(0, 0.008, size=(n, 3)),
+           rng.uniform(-2, 2, size=(100, 3))]
+    lo = np.min(verts[tris], axis=1) - np.float32(th)
+    hi = np.max(verts[tris], axis=1) + np.float32(th)
+    pick = rng.integers(0, tris.shape[0], 100)
+    for bound in (lo[pick], hi[pick]):
+        base = (lo[pick] + hi[pick]) * np.float32(0.5)
+        for axis in range(3):
+            for d in (-1, 0, 1):
+                q = base.copy()
+                q[:, axis] = bound[:, axis]
+                if d:
+                    q[:, axis] = np.nextafter(q[:, axis], np.float32(d * np.inf))
+                pts.append(q.astype(np.float64))
+    return np.concatenate(pts).astype(np.float32)
+
+
+def test_broadphase_after_surface_updates_equals_fp32_brute_force():
+    inp = W.small_collision_scene(n=8, freq=6)
+    rng = np.random.default_rng(5)
+    V0 = inp.verts.astype(np.float64)
+    c = V0.mean(axis=0)
+    moves = [
+        W.moving_surface(inp.verts, 30, inp.dt),             # small rigid motion
+        (V0 + [1.7, -0.4, 0.25]).astype(np.float32),         # far translation: new origin
+        ((V0 - c) * 2.5 + c).astype(np.float32),             # grown: more cells and refs
+        ((V0 - c) * 0.6 + c).astype(np.float32),             # shrunk: buffers reused
+        (V0 + rng.normal(0, 0.004, V0.shape)).astype(np.float32),  # deformed
+    ]
+    with B.Cloth(inp) as sim:
+        grids = []
+        for V in moves:
+            sim.update_surface(V)
+            info = sim.info()
+            grids.append((info["cells"], info["refs"]))
+            P = _probe_points(V, inp.tris, inp.thickness, rng)
+            got = sim.debug_candidates(P)
+            want = oracle.candidates_f32(P, V, inp.tris, inp.thickness)
+            assert got.shape == want.shape and np.array_equal(got, want)
+    print("grids (cells, refs):", grids)
+    assert grids[2][0] > grids[0][0] and grids[2][1] > grids[0][1]
+
+
+def _pulled_run(sim, inp, f, frames, per_frame=None):
+    sim.set_external_force(f)
+    for fr in range(frames):
+        sim.update_surface(W.moving_surface(inp.verts, fr, inp.dt))
+        if per_frame:
+            per_frame(fr)
+        sim.step(n_steps=1)
+    return sim.read_state()
+
+
+def test_pulled_cloth_on_moving_surface_one_substep_parity():
+    inp, f = W.pulled_cloth_scene(n_steps=120)
+    model = oracle.Model.from_inputs(inp)
+    model.set_external_force(f)
+    h = h32(inp)
+    contacts = 0
+    with B.Cloth(inp) as sim:
+        sim.set_external_force(f)
+        for fr in range(inp.n_steps):
+            V = W.moving_surface(inp.verts, fr, inp.dt)
+            sim.update_surface(V)
+            model.set_surface(V)
+            if fr % 4 == 0 or fr > 80:
+                x, v = sim.read_state()
+                sim.step(dt=h, n_substeps=1, n_steps=1)
+                x1, v1 = sim.read_state()
+                r = substep_parity(model, x, v, h, x1, v1, side(inp), tag=f"frame {fr}")
+                contacts += r["contacts"]
+                sim.step(dt=h, n_substeps=1, n_steps=inp.n_substeps - 1)
+            else:
+                sim.step(n_steps=1)
+        xT, _ = sim.read_state()
+    print(f"contacts checked: {contacts}")
+    assert contacts > 1000
+    # the pull moved the last row along +x relative to the first
+    n = inp.nx
+    assert xT[(n - 1) * n:, 0].mean() > inp.x0[(n - 1) * n:, 0].mean()
+
+
+LAUNCHES = [
+    dict(kernel=B.CLOTH_KERNEL_TILE, use_graph=1),
+    dict(kernel=B.CLOTH_KERNEL_TILE, use_graph=1, substeps_per_launch=2, tile_nodes=128),
+    dict(kernel=B.CLOTH_KERNEL_DIRECT, use_graph=0),
+    dict(kernel=B.CLOTH_KERNEL_DIRECT, use_graph=1, stage_refs=0),
+    dict(kernel=B.CLOTH_KERNEL_DIRECT, use_graph=1, stage_refs=256),
+]
+
+
+def test_every_launch_configuration_bit_identical_across_surface_updates():
+    inp, f = W.pulled_cloth_scene(n=20, n_steps=90)
+    outs = []
+    for cfg in LAUNCHES:
+        with B.Cloth(inp) as sim:
+            sim.set_launch(**cfg)
+            outs.append(_pulled_run(sim, inp, f, 90))
+    for (x, v), cfg in zip(outs[1:], LAUNCHES[1:]):
+        assert np.array_equal(x, outs[0][0]) and np.array_equal(v, outs[0][1]), cfg
+
+
+def test_force_removed_and_zero_force_equal_no_force():
+    inp, f = W.pulled_cloth_scene(n=16, n_steps=40)
+    with B.Cloth(inp) as a:
+        a.step(n_steps=40)
+        xa, va = a.read_state()
+    with B.Cloth(inp) as b:
+        b.set_external_force(f)
+        b.step(n_steps=1)
+        b.set_external_force(None)
+        b.write_state(inp.x0, inp.v0)
+        b.step(n_steps=40)
+        xb, vb = b.read_state()
+    with B.Cloth(inp) as c:
+        c.set_external_force(np.zeros_like(f))
+        c.step(n_steps=40)
+        xc, vc = c.read_state()
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+    assert np.array_equal(xa, xc) and np.array_equal(va, vc)
+
+
+def test_batch_surface_updates_and_forces_equal_plain_handles():
+    cl = W.config3(n_cloths=3, seed=21, side_lo=12, side_hi=30, freq=6, n_steps=40)
+    rng = np.random.default_rng(6)
+    forces = [rng.normal(0, 2e-3, size=(c.n_nodes, 3)).astype(np.float32) for c in cl]
+    frames = 40
+    with B.ClothBatch(cl) as b:
+        b.set_external_force(np.concatenate(forces))
+        for fr in range(frames):
+            b.update_surface(1, W.moving_surface(cl[1].verts, fr, cl[1].dt))
+            b.step(n_steps=1)
+        got = [b.read_state(i) for i in range(len(cl))]
+    for i, c in enumerate(cl):
+        with B.Cloth(c) as s:
+            s.set_external_force(forces[i])
+            for fr in range(frames):
+                if i == 1:
+                    s.update_surface(W.moving_surface(c.verts, fr, c.dt))
+                s.step(n_steps=1)
+            xp, vp = s.read_state()
+        assert np.array_equal(got[i][0], xp) and np.array_equal(got[i][1], vp), i
+
+
+def test_update_surface_argument_errors():
+    inp = W.small_collision_scene(n=8, freq=3)
+    with B.Cloth(inp) as sim:
+        for bad in (inp.verts[:-1], np.full_like(inp.verts, np.nan)):
+            with pytest.raises(B.ClothError) as ei:
+                sim.update_surface(bad)
+            assert ei.value.status == B.CLOTH_EINVAL
+        sim.step(n_steps=2)  # still usable: nothing was rewritten
+        with pytest.raises(B.ClothError) as ei:
+            sim.set_external_force(np.full((inp.n_nodes, 3), np.inf, np.float32))
+        assert ei.value.status == B.CLOTH_EINVAL
+    with B.Cloth(W.config0(n=8)) as sim:
+        with pytest.raises(B.ClothError) as ei:
+            sim.update_surface(np.zeros((3, 3), np.float32))
+        assert ei.value.status == B.CLOTH_EINVAL
