@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint comparison")
     ap.add_argument("--batch-cloths", type=int, default=512)
+    ap.add_argument("--no-normals", action="store_true", help="skip the vertex-normal timing")
+    ap.add_argument("--no-moving", action="store_true",
+                    help="skip the moving-surface / pulled-cloth timing")
     return ap.parse_args()
 
 
@@ -130,6 +133,62 @@ def bench_adjoint(frames: int = 200):
             "plain_forward_node_updates_per_s": upd / t_plain,
             "forward_backward_node_updates_per_s": upd / t_grad,
             "gradient_cost_vs_plain": t_grad / t_plain}
+
+
+def bench_normals(sim, n_nodes: int, reps: int = 200):
+    """Per-vertex normals of the current state: average kernel time over reps calls, timed
+    with HIP events on the handle's stream, against 24 B/node (state read, normal written)."""
+    import torch
+
+    stream = torch.cuda.current_stream()
+    out = sim.vertex_normals()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        sim.vertex_normals(out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    us = ev0.elapsed_time(ev1) * 1e3 / reps
+    gbs = 24.0 * n_nodes / (us * 1e-6) / 1e9
+    return {"nodes": n_nodes, "us_per_call": us, "algorithmic_bytes_per_call": 24 * n_nodes,
+            "achieved_gbs": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+
+
+def bench_moving(frames: int = 60):
+    """The 316x316 cloth over the 100,820-triangle sphere while the sphere moves every frame
+    (its grid rebuilt on the device before each frame) and the cloth's last row is pulled
+    along +x: frame throughput, and the surface update's own cost."""
+    import torch
+
+    from paper_2507_11794_amd import cloth, workloads
+
+    inp = workloads.config1()
+    n = inp.nx
+    f = np.zeros((inp.n_nodes, 3), dtype=np.float32)
+    f[(n - 1) * n:, 0] = 0.002
+    stream = torch.cuda.current_stream()
+    sim = cloth.Cloth(inp, stream=stream.cuda_stream)
+    sim.set_external_force(f)
+    sim.step(n_steps=100)
+    verts = [workloads.moving_surface(inp.verts, 100 + i, inp.dt) for i in range(frames)]
+    torch.cuda.synchronize()
+    t_upd = 0.0
+    t0 = time.perf_counter()
+    for V in verts:
+        ta = time.perf_counter()
+        sim.update_surface(V)
+        t_upd += time.perf_counter() - ta
+        sim.step(n_steps=1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    info = sim.info()
+    sim.close()
+    return {"frames": frames, "nodes": inp.n_nodes, "tris": inp.n_tris, "grid_refs": info["refs"],
+            "node_updates_per_s": inp.n_nodes * inp.n_substeps * frames / wall,
+            "ms_per_frame": wall * 1e3 / frames,
+            "surface_update_ms": t_upd * 1e3 / frames}
 
 
 def parse_launch(text: str) -> dict:
@@ -282,6 +341,7 @@ def main():
     achieved = bps / kernel_s / 1e9
     x, v = sim.read_state()
     info = sim.info()
+    normals = None if args.no_normals else bench_normals(sim, inp.n_nodes)
     sim.close()
     out = {
         "metric": "node-updates/s w/ collision, 100K nodes vs 100K tris; batched+adjoint vs plain",
@@ -319,6 +379,10 @@ def main():
             "avg_launch_us": kernel_s * 1e6,
         },
     }
+    if normals:
+        out["normals"] = normals
+    if not args.no_moving:
+        out["moving_surface"] = bench_moving()
     if not args.no_batch:
         out["batched"] = bench_batched(args.batch_cloths, 200)
     if not args.no_adjoint:

@@ -63,8 +63,14 @@ typedef struct cloth_params {
 /* Launch configuration (cloth_set_launch).  Results are bit-identical for every valid
  * configuration: it changes only how the substeps are scheduled on the GPU. */
 enum cloth_kernel {
-    CLOTH_KERNEL_TILE = 0,  /* temporally blocked tiles: K substeps per launch in LDS */
-    CLOTH_KERNEL_DIRECT = 1 /* one launch per substep, one thread per node */
+    CLOTH_KERNEL_TILE = 0,        /* temporally blocked tiles: K substeps per launch in LDS */
+    CLOTH_KERNEL_DIRECT = 1,      /* one launch per substep, one thread per node */
+    /* spring-centric force accumulation as in Alg. 1 (one thread per spring adding +f / -f
+     * to its ends), then a node pass; for measuring the paper's design against the gather */
+    CLOTH_KERNEL_SCATTER_F32 = 2, /* FP32 atomic adds: rounding varies from run to run */
+    CLOTH_KERNEL_SCATTER_FIX = 3  /* int32 atomics at 2^-24 N (WGSL's integer atomics):
+                                     deterministic; |f| < 8 N per spring component, else
+                                     cloth_read_state reports CLOTH_ENAN */
 };
 
 /* How tiles are assigned to workgroups (tile kernel). */
@@ -203,7 +209,8 @@ int cloth_stability_bound(int n_nodes, const float* x0, const float* mass,
  *   x_out_dev    [device] [n_out*N*3] receives the positions at those frames.
  * Memory: (n_steps/ckpt_every + 1) checkpoints, plus ckpt_every*n_substeps + 1 states in
  * the backward pass, N*24 bytes each.
- * Errors: CLOTH_EINVAL (sizes, order, non-finite or negative k / c), CLOTH_EUNSTABLE.
+ * Errors: CLOTH_EINVAL (sizes, order, non-finite or negative k / c, a scatter kernel
+ * selected: rollouts recompute with the gather kernels), CLOTH_EUNSTABLE.
  */
 int cloth_rollout_forward(cloth_sim* sim, const float* k_dev, const float* c_dev,
                           const float* v0_dev, float dt, int n_substeps, int n_steps,

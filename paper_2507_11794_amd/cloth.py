@@ -37,6 +37,7 @@ class cloth_launch(C.Structure):
 
 
 CLOTH_KERNEL_TILE, CLOTH_KERNEL_DIRECT = 0, 1
+CLOTH_KERNEL_SCATTER_F32, CLOTH_KERNEL_SCATTER_FIX = 2, 3
 CLOTH_SCHED_GRID, CLOTH_SCHED_LPT, CLOTH_SCHED_RR = 0, 1, 2
 
 

@@ -49,6 +49,17 @@ struct ClothView {
     const int* inc_spring;
 };
 
+// Springs for the spring-centric (scatter) force pass: ends as internal slots, parameters
+// per spring, ordered by (min slot, max slot) for locality.
+struct SpringList {
+    int n;
+    const int* a;
+    const int* b;
+    const float* k;
+    const float* c;
+    const float* L0;
+};
+
 struct StepParams {
     float h;
     float g[3];
@@ -115,6 +126,16 @@ hipError_t launch_substep(const ClothView& cv, int collide, const StepParams& sp
                           int stage_cap = 0);
 // Raise the one-substep kernel's dynamic LDS limit when its stage needs more than 64 KiB.
 hipError_t prepare_substep_kernels(size_t lds_bytes);
+// One substep with spring-centric forces: the spring pass accumulates into F (SoA [3][ld],
+// FP32 or, with fix, int32 at 2^-24 N; all zero on entry), then the node pass integrates,
+// collides (as launch_substep) and zeroes F.  Fixed-point overflow sets bit 2 of
+// sp.nan_flag.
+hipError_t launch_scatter_substep(const ClothView& cv, const SpringList& sl, int fix, int collide,
+                                  const StepParams& sp, float* F, const float* xs,
+                                  const float* vs, float* xd, float* vd, int block,
+                                  hipStream_t st, const SurfaceView* svs, const int* node_group,
+                                  int stage_cap);
+hipError_t prepare_scatter_kernels(size_t lds_bytes);
 
 // --- a6 adjoint ----------------------------------------------------------------------------
 // Response and integration transpose of one substep at state (xs, vs): partial adjoints and

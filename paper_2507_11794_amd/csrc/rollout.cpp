@@ -45,6 +45,10 @@ int set_spring_params(cloth_sim* s, const float* k_dev, const float* c_dev) {
         (e = launch_set_params_plan(s->plan.inc_count, s->plan.inc_sid, k_dev, c_dev,
                                     const_cast<float4*>(s->plan.view.inc), s->stream)))
         return hip_fail(e, "set tile parameters");
+    if (s->springs.ready &&
+        (e = launch_set_params(S, s->springs.sid, k_dev, c_dev, s->springs.k, s->springs.c,
+                               s->stream)))
+        return hip_fail(e, "set spring-list parameters");
     refresh_stability(s);
     return CLOTH_OK;
 }
@@ -71,6 +75,9 @@ int cloth_rollout_forward(cloth_sim* s, const float* k_dev, const float* c_dev,
     if (!s) return fail(CLOTH_EINVAL, "NULL handle");
     if (s->groups.size() != 1) return fail(CLOTH_EINVAL, "rollouts take a single-cloth handle");
     if (s->surface_broken) return fail(CLOTH_ESTATE, "a surface update failed; update it again first");
+    if (s->launch.kernel != CLOTH_KERNEL_TILE && s->launch.kernel != CLOTH_KERNEL_DIRECT)
+        return fail(CLOTH_EINVAL, "rollouts recompute with the gather kernels: select the tile "
+                                  "or direct kernel");
     if (s->n_springs > 0 && (!k_dev || !c_dev)) return fail(CLOTH_EINVAL, "k and c are required");
     if (!(dt > 0.0f) || !std::isfinite(dt) || n_substeps < 1 || n_steps < 0 || ckpt_every < 1)
         return fail(CLOTH_EINVAL, "need dt > 0, n_substeps >= 1, n_steps >= 0, ckpt_every >= 1");

@@ -14,7 +14,7 @@
 namespace cloth {
 
 int check_launch(const cloth_launch& c) {
-    if (c.kernel != CLOTH_KERNEL_TILE && c.kernel != CLOTH_KERNEL_DIRECT)
+    if (c.kernel < CLOTH_KERNEL_TILE || c.kernel > CLOTH_KERNEL_SCATTER_FIX)
         return fail(CLOTH_EINVAL, "unknown kernel");
     if (c.block_threads < 64 || c.block_threads > 256 || (c.block_threads & 63))
         return fail(CLOTH_EINVAL, "block_threads must be 64, 128, 192 or 256");
@@ -67,6 +67,61 @@ int ensure_plan(cloth_sim* s, const cloth_launch& c) {
     return CLOTH_OK;
 }
 
+int ensure_springs(cloth_sim* s) {
+    if (s->springs.ready) return CLOTH_OK;
+    const int S = s->n_springs;
+    const size_t ld = (size_t)s->dev.ld;
+    // per-spring rest lengths from the incidence lists; ends as internal slots
+    std::vector<float> rest(S, 0.0f);
+    for (size_t q = 0; q < s->host.inc_spring.size(); ++q) {
+        const int code = s->host.inc_spring[q];
+        rest[code >= 0 ? code : ~code] = s->host.il[q];
+    }
+    std::vector<int> perm(S);
+    for (int q = 0; q < S; ++q) perm[q] = q;
+    auto lo = [&](int q) { return std::min(s->host.slot[s->ends[2 * q]], s->host.slot[s->ends[2 * q + 1]]); };
+    auto hi = [&](int q) { return std::max(s->host.slot[s->ends[2 * q]], s->host.slot[s->ends[2 * q + 1]]); };
+    std::sort(perm.begin(), perm.end(), [&](int p, int q) {
+        return lo(p) != lo(q) ? lo(p) < lo(q) : (hi(p) != hi(q) ? hi(p) < hi(q) : p < q);
+    });
+    std::vector<int> a(S), b(S);
+    std::vector<float> k(S), c(S), L0(S);
+    for (int r = 0; r < S; ++r) {
+        const int q = perm[r];
+        a[r] = s->host.slot[s->ends[2 * q]];
+        b[r] = s->host.slot[s->ends[2 * q + 1]];
+        k[r] = s->k[q];
+        c[r] = s->c[q];
+        L0[r] = rest[q];
+    }
+    SpringDevice& d = s->springs;
+    d.arena.release();
+    int *da = nullptr, *db = nullptr, *sid = nullptr;
+    float *dk = nullptr, *dc = nullptr, *dl = nullptr, *F = nullptr;
+    hipError_t e;
+    if ((e = d.arena.alloc(&da, (size_t)S)) || (e = d.arena.alloc(&db, (size_t)S)) ||
+        (e = d.arena.alloc(&sid, (size_t)S)) || (e = d.arena.alloc(&dk, (size_t)S)) ||
+        (e = d.arena.alloc(&dc, (size_t)S)) || (e = d.arena.alloc(&dl, (size_t)S)) ||
+        (e = d.arena.alloc(&F, 3 * ld)) ||
+        (e = hipMemcpyAsync(da, a.data(), 4 * (size_t)S, hipMemcpyHostToDevice, s->stream)) ||
+        (e = hipMemcpyAsync(db, b.data(), 4 * (size_t)S, hipMemcpyHostToDevice, s->stream)) ||
+        (e = hipMemcpyAsync(sid, perm.data(), 4 * (size_t)S, hipMemcpyHostToDevice, s->stream)) ||
+        (e = hipMemcpyAsync(dk, k.data(), 4 * (size_t)S, hipMemcpyHostToDevice, s->stream)) ||
+        (e = hipMemcpyAsync(dc, c.data(), 4 * (size_t)S, hipMemcpyHostToDevice, s->stream)) ||
+        (e = hipMemcpyAsync(dl, L0.data(), 4 * (size_t)S, hipMemcpyHostToDevice, s->stream)) ||
+        (e = hipMemsetAsync(F, 0, 12 * ld, s->stream)) || (e = hipStreamSynchronize(s->stream))) {
+        d.arena.release();
+        return hip_fail(e, "spring list");
+    }
+    d.view = SpringList{S, da, db, dk, dc, dl};
+    d.sid = sid;
+    d.k = dk;
+    d.c = dc;
+    d.F = F;
+    d.ready = true;
+    return CLOTH_OK;
+}
+
 int set_launch(cloth_sim* s, const cloth_launch& cfg) {
     int st = check_launch(cfg);
     if (st != CLOTH_OK) return st;
@@ -80,20 +135,25 @@ int set_launch(cloth_sim* s, const cloth_launch& cfg) {
                            : (size_t)(cfg.block_threads / 64) * 2 * stage * sizeof(float4);
     if (lds > 160 * 1024)
         return fail(CLOTH_EINVAL, "tile region plus collision stage exceed 160 KiB of LDS");
+    const bool scatter = cfg.kernel == CLOTH_KERNEL_SCATTER_F32 || cfg.kernel == CLOTH_KERNEL_SCATTER_FIX;
+    if (scatter && (st = ensure_springs(s)) != CLOTH_OK) return st;
     hipError_t pe = cfg.kernel == CLOTH_KERNEL_TILE ? prepare_tile_kernels(lds)
-                                                     : prepare_substep_kernels(lds);
+                    : scatter                       ? prepare_scatter_kernels(lds)
+                                                    : prepare_substep_kernels(lds);
     if (pe != hipSuccess) return hip_fail(pe, "kernel LDS attribute");
-    if (cfg.kernel != s->launch.kernel || cfg.block_threads != s->launch.block_threads) {
+    cloth_launch norm = cfg;
+    if (cfg.kernel != CLOTH_KERNEL_TILE) {
+        norm.schedule = CLOTH_SCHED_GRID;
+        norm.workgroups = 0;
+    }
+    if (std::memcmp(&norm, &s->launch, sizeof(cloth_launch)) != 0) {
+        // captured graphs hold the old configuration's kernels and arguments
         hipError_t e = hipStreamSynchronize(s->stream);
         if (e != hipSuccess) return hip_fail(e, "synchronise");
         s->drop_graphs();
     }
-    s->launch = cfg;
+    s->launch = norm;
     s->launch_ready = true;
-    if (cfg.kernel == CLOTH_KERNEL_DIRECT) {
-        s->launch.schedule = CLOTH_SCHED_GRID;
-        s->launch.workgroups = 0;
-    }
     return CLOTH_OK;
 }
 
@@ -108,6 +168,14 @@ hipError_t launch_once(cloth_sim* s, const StepParams& sp, int K, int src, hipSt
         return launch_tiles(s->plan.view, K, s->any_collision, sp, s->dev.x[src], s->dev.v[src],
                             s->dev.x[dst], s->dev.v[dst], s->launch.block_threads,
                             s->launch.stage_refs, st);
+    if (s->launch.kernel == CLOTH_KERNEL_SCATTER_F32 || s->launch.kernel == CLOTH_KERNEL_SCATTER_FIX)
+        return launch_scatter_substep(s->dev.view(), s->springs.view,
+                                      s->launch.kernel == CLOTH_KERNEL_SCATTER_FIX,
+                                      s->any_collision, sp, s->springs.F, s->dev.x[src],
+                                      s->dev.v[src], s->dev.x[dst], s->dev.v[dst],
+                                      s->launch.block_threads, st, s->svs_dev,
+                                      s->groups.size() > 1 ? s->node_group_dev : nullptr,
+                                      s->launch.stage_refs);
     if (s->groups.size() == 1)
         return launch_substep(s->dev.view(), s->surfs[0].view.n_tris > 0, sp, s->dev.x[src],
                               s->dev.v[src], s->dev.x[dst], s->dev.v[dst], s->launch.block_threads,
@@ -271,7 +339,10 @@ int read_state_range(const cloth_sim* s, int group, float* x_out, float* v_out) 
             if (v_out) v_out[3 * id + q] = vs[q * n + p];
         }
     }
-    if ((s->p.flags & CLOTH_F_CHECK_NAN) && flag)
+    if (flag & 2)
+        return fail(CLOTH_ENAN, "a spring force exceeded the fixed-point accumulator's range "
+                                "(8 N per component); use another kernel");
+    if ((s->p.flags & CLOTH_F_CHECK_NAN) && (flag & 1))
         return fail(CLOTH_ENAN, "a non-finite value appeared in the state");
     return CLOTH_OK;
 }

@@ -14,6 +14,17 @@
 
 namespace cloth {
 
+// Spring list and force accumulator of the spring-centric (scatter) kernels.
+struct SpringDevice {
+    DeviceArena arena;
+    SpringList view{};
+    int* sid = nullptr;  // caller spring id of each list entry
+    float* k = nullptr;
+    float* c = nullptr;
+    float* F = nullptr;  // [3][ld], zero between substeps
+    bool ready = false;
+};
+
 struct GraphEntry {
     unsigned h_bits;
     int K, chunk, parity;
@@ -65,6 +76,7 @@ struct cloth_sim {
     int any_collision = 0;
     cloth::DeviceArena arena;
     cloth::TilePlanDevice plan;
+    cloth::SpringDevice springs;
     long long plan_version = 0;
     std::vector<cloth::GraphEntry> graphs;
     cloth_launch launch{CLOTH_KERNEL_TILE, 256, 1, 256, 1, CLOTH_SCHED_GRID, 0, 384};
@@ -111,6 +123,8 @@ int create_sim(const std::vector<ClothHostInput>& cloths, const cloth_params* p,
 int check_launch(const cloth_launch& c);
 // Make sure the tile plan and its schedule match the launch configuration.
 int ensure_plan(cloth_sim* s, const cloth_launch& c);
+// Build the spring list and force accumulator of the scatter kernels (once).
+int ensure_springs(cloth_sim* s);
 // Apply a launch configuration (validates, replans, drops stale graphs).
 int set_launch(cloth_sim* s, const cloth_launch& c);
 // Advance `total` substeps of length h with the handle's launch configuration.
