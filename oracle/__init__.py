@@ -68,6 +68,11 @@ def _load():
     lib.orc_model_triangle.argtypes = [P, C.c_int, dp, dp, dp, dp]
     lib.orc_vertex_normals.argtypes = [C.c_int, C.c_int, dp, dp]
     lib.orc_model_set_surface.argtypes = [P, dp]
+    lib.orc_mt.restype = C.c_int
+    lib.orc_mt.argtypes = [dp, dp, dp, dp, dp, C.c_double, dp, dp]
+    lib.orc_mt_contacts.restype = C.c_int
+    lib.orc_mt_contacts.argtypes = [P, C.c_int, C.c_int, dp, dp, C.c_int, ip, C.c_int, dp]
+    lib.orc_substep_mt.argtypes = [P, C.c_int, C.c_int, dp, dp, C.c_double, ip, dp]
     lib.orc_model_set_external.argtypes = [P, dp]
     _lib = lib
     return lib
@@ -149,6 +154,26 @@ class Model:
         """Per-node external forces [N,3] added before integration (None removes them)."""
         self.fext = None if f is None else _d(f).reshape(self.N, 3)
         self._lib.orc_model_set_external(self._h, None if f is None else _dp(self.fext))
+
+    def mt_contacts(self, nx, ny, xs, xp, i):
+        """Node i's contact set under the triangle-triangle narrow phase (ascending triangle
+        ids) and the smallest decision margin of its tests."""
+        xs, xp = _d(xs).reshape(-1, 3), _d(xp).reshape(-1, 3)
+        out = np.zeros(512, dtype=np.int32)
+        mg = np.zeros(1)
+        n = self._lib.orc_mt_contacts(self._h, int(nx), int(ny), _dp(xs), _dp(xp), int(i),
+                                      _ip(out), 512, _dp(mg))
+        return out[:min(n, 512)].tolist(), float(mg[0])
+
+    def substep_mt(self, nx, ny, x, v, h):
+        """One substep with the triangle-triangle narrow phase: (x1, v1, counts, margins)."""
+        x = _d(x).reshape(-1, 3).copy()
+        v = _d(v).reshape(-1, 3).copy()
+        cnt = np.zeros(self.N, dtype=np.int32)
+        mg = np.zeros(self.N)
+        self._lib.orc_substep_mt(self._h, int(nx), int(ny), _dp(x), _dp(v), float(h), _ip(cnt),
+                                 _dp(mg))
+        return x, v, cnt, mg
 
     def forces(self, x, v):
         x, v = _d(x).reshape(-1, 3), _d(v).reshape(-1, 3)
@@ -248,6 +273,19 @@ class Model:
 def point_tri_dist2(p, A, B, Cc):
     lib = _load()
     return lib.orc_point_tri_dist2(_dp(_d(p)), _dp(_d(A)), _dp(_d(B)), _dp(_d(Cc)))
+
+
+MT_EPS = 1e-7
+
+
+def mt(S, E, V0, V1, V2, eps=MT_EPS):
+    """Extended Moller-Trumbore segment-triangle test: (hit, t, margin)."""
+    lib = _load()
+    t = np.zeros(1)
+    mg = np.zeros(1)
+    hit = lib.orc_mt(_dp(_d(S)), _dp(_d(E)), _dp(_d(V0)), _dp(_d(V1)), _dp(_d(V2)), float(eps),
+                     _dp(t), _dp(mg))
+    return bool(hit), float(t[0]) if hit else None, float(mg[0])
 
 
 def vertex_normals(nx, ny, x):

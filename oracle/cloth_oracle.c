@@ -703,6 +703,198 @@ void orc_rollout_grad(const orc_model *m, const double *x0, const double *v0, do
     free(xb); free(vb); free(xb2); free(vb2); free(seg_x); free(seg_v);
 }
 
+/* ------------------------------------------------------------------ extended Moller-Trumbore narrow phase */
+
+/* Segment S -> E against triangle (V0, V1, V2), following the steps of Sec. 3's extended
+ * Moller-Trumbore process: with d = E - S and r = d / |d|, e1 = V1 - V0, e2 = V2 - V0,
+ * h = r x e2 and a = e1 . h, the segment is parallel when |a| < eps; otherwise with
+ * f = 1 / a, s = S - V0: u = f (s . h) must lie in [0, 1], and with q = s x e1,
+ * v = f (r . q) >= 0, u + v <= 1 and t = f (e2 . q) strictly inside (eps, |d|).  Returns 1
+ * for a crossing (then *t_out = t, the distance from S to the crossing point S + t r).
+ * A zero-length segment crosses nothing.  *margin (optional) receives the smallest distance,
+ * in metres, of the decision quantities from their bounds (u, 1 - u, v, 1 - u - v scaled by
+ * the longer triangle edge; t - eps and |d| - t), INFINITY when parallel or degenerate. */
+int orc_mt(const double *S, const double *E, const double *V0, const double *V1,
+           const double *V2, double eps, double *t_out, double *margin)
+{
+    if (margin) *margin = INFINITY;
+    double d[3], r[3], e1[3], e2[3], h[3], sv[3], q[3];
+    sub3(E, S, d);
+    double len = sqrt(dot3(d, d));
+    if (!(len > 0.0)) return 0;
+    for (int k = 0; k < 3; ++k) r[k] = d[k] / len;
+    sub3(V1, V0, e1);
+    sub3(V2, V0, e2);
+    cross3(r, e2, h);
+    double a = dot3(e1, h);
+    if (fabs(a) < eps) return 0;
+    double f = 1.0 / a;
+    sub3(S, V0, sv);
+    double u = f * dot3(sv, h);
+    cross3(sv, e1, q);
+    double v = f * dot3(r, q);
+    double t = f * dot3(e2, q);
+    if (margin) {
+        double L = fmax(sqrt(dot3(e1, e1)), sqrt(dot3(e2, e2)));
+        double m = fmin(fmin(fabs(u), fabs(1.0 - u)), fmin(fabs(v), fabs(1.0 - u - v))) * L;
+        m = fmin(m, fmin(fabs(t - eps), fabs(len - t)));
+        *margin = m;
+    }
+    if (u < 0.0 || u > 1.0) return 0;
+    if (v < 0.0 || u + v > 1.0) return 0;
+    if (!(eps < t && t < len)) return 0;
+    if (t_out) *t_out = t;
+    return 1;
+}
+
+/* Triangles of the cloth grid that contain node i = (row, col): each quad (r, c), (r+1, c),
+ * (r+1, c+1), (r, c+1) is split along its (r, c)-(r+1, c+1) diagonal into (a, b, c) and
+ * (a, c, d).  Writes up to 6 triangles (vertex triples) and returns their count. */
+static int cloth_tris_of(int nx, int ny, int i, int tri[6][3])
+{
+    int row = i / nx, col = i % nx, n = 0;
+    for (int qr = row - 1; qr <= row; ++qr)
+        for (int qc = col - 1; qc <= col; ++qc) {
+            if (qr < 0 || qc < 0 || qr + 1 >= ny || qc + 1 >= nx) continue;
+            int a = qr * nx + qc, b = (qr + 1) * nx + qc, c = (qr + 1) * nx + qc + 1, d = qr * nx + qc + 1;
+            int two[2][3] = {{a, b, c}, {a, c, d}};
+            for (int k = 0; k < 2; ++k)
+                if (two[k][0] == i || two[k][1] == i || two[k][2] == i) {
+                    for (int z = 0; z < 3; ++z) tri[n][z] = two[k][z];
+                    ++n;
+                }
+        }
+    return n;
+}
+
+/* Cloth-mesh edges at node i (the triangles' edges: grid neighbours along rows and columns
+ * and the split diagonal), as neighbour ids.  Returns their count (at most 6). */
+static int cloth_edges_of(int nx, int ny, int i, int nb[6])
+{
+    int row = i / nx, col = i % nx, n = 0;
+    int dr[6] = {0, 0, 1, -1, 1, -1}, dc[6] = {1, -1, 0, 0, 1, -1};
+    for (int k = 0; k < 6; ++k) {
+        int r2 = row + dr[k], c2 = col + dc[k];
+        if (r2 < 0 || c2 < 0 || r2 >= ny || c2 >= nx) continue;
+        nb[n++] = r2 * nx + c2;
+    }
+    return n;
+}
+
+static void aabb_add(double lo[3], double hi[3], const double *p)
+{
+    for (int a = 0; a < 3; ++a) {
+        if (p[a] < lo[a]) lo[a] = p[a];
+        if (p[a] > hi[a]) hi[a] = p[a];
+    }
+}
+
+static int box_overlaps(const orc_model *m, int t, const double lo[3], const double hi[3])
+{
+    for (int a = 0; a < 3; ++a)
+        if (hi[a] < m->tlo[3 * t + a] || lo[a] > m->thi[3 * t + a]) return 0;
+    return 1;
+}
+
+#define ORC_MT_EPS 1e-7
+
+/* The contact set of node i under the triangle-triangle narrow phase (Sec. 3): surface
+ * triangle t is a contact of i when
+ *   (A) a cloth edge at i, at predicted positions xp, crosses t (oriented from the lower
+ *       node id), or
+ *   (B) an edge of t (oriented from the lower vertex id) crosses a cloth triangle at i, at xp
+ *       (so every triangle next to a surface edge that pierces the cloth is a contact of
+ *       that cloth triangle's three nodes), or
+ *   (C) i's own path from xs to xp crosses t (the continuous test).
+ * Pinned nodes have no contacts.  Candidates are the triangles whose slack-inflated box
+ * overlaps the box of i's edges, cloth triangles and path; a crossing point lies in both
+ * boxes, so the filter never changes the result.  Writes up to cap ids in ascending order and
+ * returns the count; *margin receives the smallest decision margin over every test made. */
+int orc_mt_contacts(const orc_model *m, int nx, int ny, const double *xs, const double *xp,
+                    int i, int *out, int cap, double *margin)
+{
+    double mg = INFINITY;
+    int n = 0;
+    if (m->T == 0 || m->w[i] == 0.0) { if (margin) *margin = mg; return 0; }
+    int tri[6][3], nb[6];
+    int ntri = cloth_tris_of(nx, ny, i, tri), nnb = cloth_edges_of(nx, ny, i, nb);
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    aabb_add(lo, hi, xs + 3 * i);
+    aabb_add(lo, hi, xp + 3 * i);
+    for (int k = 0; k < nnb; ++k) aabb_add(lo, hi, xp + 3 * nb[k]);
+    int clo[3], chi[3];
+    for (int a = 0; a < 3; ++a) { clo[a] = cell_coord(m, lo[a], a); chi[a] = cell_coord(m, hi[a], a); }
+    char *seen = calloc((size_t)m->T, 1);
+    for (int ck = clo[2]; ck <= chi[2]; ++ck)
+        for (int cj = clo[1]; cj <= chi[1]; ++cj)
+            for (int ci = clo[0]; ci <= chi[0]; ++ci) {
+                long long id = ((long long)ck * m->dim[1] + cj) * m->dim[0] + ci;
+                for (int r = m->cell_start[id]; r < m->cell_start[id + 1]; ++r) {
+                    int t = m->cell_tris[r];
+                    if (seen[t] || !box_overlaps(m, t, lo, hi)) continue;
+                    seen[t] = 1;
+                    const int *tv = m->tris + 3 * t;
+                    const double *V0 = m->verts + 3 * tv[0], *V1 = m->verts + 3 * tv[1],
+                                 *V2 = m->verts + 3 * tv[2];
+                    int hit = 0;
+                    double g;
+                    for (int k = 0; k < nnb; ++k) {            /* (A) */
+                        int p0 = i < nb[k] ? i : nb[k], p1 = i < nb[k] ? nb[k] : i;
+                        hit |= orc_mt(xp + 3 * p0, xp + 3 * p1, V0, V1, V2, ORC_MT_EPS, NULL, &g);
+                        if (g < mg) mg = g;
+                    }
+                    for (int k = 0; k < ntri; ++k)             /* (B) */
+                        for (int z = 0; z < 3; ++z) {
+                            int u0 = tv[z], u1 = tv[(z + 1) % 3];
+                            int w0 = u0 < u1 ? u0 : u1, w1 = u0 < u1 ? u1 : u0;
+                            hit |= orc_mt(m->verts + 3 * w0, m->verts + 3 * w1, xp + 3 * tri[k][0],
+                                          xp + 3 * tri[k][1], xp + 3 * tri[k][2], ORC_MT_EPS, NULL, &g);
+                            if (g < mg) mg = g;
+                        }
+                    hit |= orc_mt(xs + 3 * i, xp + 3 * i, V0, V1, V2, ORC_MT_EPS, NULL, &g);  /* (C) */
+                    if (g < mg) mg = g;
+                    if (hit) {
+                        /* insert in ascending order */
+                        int pos = n < cap ? n : cap;
+                        while (pos > 0 && out[pos - 1] > t) {
+                            if (pos < cap) out[pos] = out[pos - 1];
+                            --pos;
+                        }
+                        if (pos < cap) out[pos] = t;
+                        ++n;
+                    }
+                }
+            }
+    free(seen);
+    if (margin) *margin = mg;
+    return n;
+}
+
+/* One substep with the triangle-triangle narrow phase: prediction as in orc_substep, every
+ * node's contact set from the start positions and the predictions of all nodes, then the
+ * averaged response of each node (x* + mean (th - s_t) n_t, v <- -restitution v*). */
+void orc_substep_mt(const orc_model *m, int nx, int ny, double *x, double *v, double h,
+                    int *count, double *margin)
+{
+    int N = m->N;
+    double *xs = malloc(sizeof(double) * 3 * (size_t)N);
+    memcpy(xs, x, sizeof(double) * 3 * (size_t)N);
+    orc_predict(m, x, v, h);
+    double *xp = malloc(sizeof(double) * 3 * (size_t)N);
+    memcpy(xp, x, sizeof(double) * 3 * (size_t)N);
+    int ids[ORC_MAX_CONTACTS];
+    for (int i = 0; i < N; ++i) {
+        double mg;
+        int n = orc_mt_contacts(m, nx, ny, xs, xp, i, ids, ORC_MAX_CONTACTS, &mg);
+        if (count) count[i] = n;
+        if (margin) margin[i] = mg;
+        if (n > ORC_MAX_CONTACTS) n = ORC_MAX_CONTACTS;
+        orc_respond(m, x + 3 * i, v + 3 * i, ids, n);
+    }
+    free(xs);
+    free(xp);
+}
+
 /* ------------------------------------------------------------------ vertex normals */
 
 /* Per-vertex normals of an nx-by-ny cloth grid (node (i, j) = i*nx + j, Sec. 3's normal
