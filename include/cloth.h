@@ -50,6 +50,15 @@ enum cloth_status {
 #define CLOTH_F_CHECK_NAN 0x1u          /* flag non-finite state values; cloth_read_state
                                            then returns CLOTH_ENAN */
 #define CLOTH_F_NO_STABILITY_CHECK 0x2u /* skip the substep-length check of cloth_step */
+/* Narrow phase by triangle-triangle intersection (Sec. 3's extended Moller-Trumbore
+ * process) instead of point-triangle proximity: surface triangle t is a contact of node i
+ * when a cloth edge at i crosses t, an edge of t crosses a cloth triangle at i, or i's path
+ * over the substep crosses t (segments oriented from the lower node / vertex id; eps 1e-7).
+ * The cloth mesh is the nx-by-ny grid with each quad split along its (i,j)-(i+1,j+1)
+ * diagonal.  The response is unchanged (averaged push to the thickness, v <- -r v).  Every
+ * substep is then a prediction launch plus a contact launch (the launch configuration's
+ * kernel choice does not apply); rollouts are not available on such handles. */
+#define CLOTH_F_NARROW_MT 0x4u
 
 typedef struct cloth_params {
     float gravity[3];  /* m/s^2, e.g. {0, -9.81, 0} */
@@ -286,7 +295,8 @@ int cloth_batch_destroy(cloth_batch* b);
  * cloth_debug_contacts -- the contact set every node would get in a substep of length h
  * from the current state, with the step's own arithmetic: counts[i] triangles, the first
  * min(counts[i], cap) of them (ascending id) at ids[i*cap ...].  counts, ids [host] in node-id
- * order ([N], [N*cap]).  Single-cloth handles.  Synchronises.
+ * order ([N], [N*cap]).  Single-cloth handles.  Synchronises.  With CLOTH_F_NARROW_MT the
+ * listed ids are sorted but, past cap, need not be the smallest.
  */
 int cloth_debug_contacts(cloth_sim* sim, float h, int* counts, int* ids, int cap);
 

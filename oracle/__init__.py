@@ -73,6 +73,8 @@ def _load():
     lib.orc_mt_contacts.restype = C.c_int
     lib.orc_mt_contacts.argtypes = [P, C.c_int, C.c_int, dp, dp, C.c_int, ip, C.c_int, dp]
     lib.orc_substep_mt.argtypes = [P, C.c_int, C.c_int, dp, dp, C.c_double, ip, dp]
+    lib.orc_mt_candidates.restype = C.c_int
+    lib.orc_mt_candidates.argtypes = [P, C.c_int, C.c_int, dp, dp, C.c_int, ip, ip, dp, C.c_int]
     lib.orc_model_set_external.argtypes = [P, dp]
     _lib = lib
     return lib
@@ -164,6 +166,18 @@ class Model:
         n = self._lib.orc_mt_contacts(self._h, int(nx), int(ny), _dp(xs), _dp(xp), int(i),
                                       _ip(out), 512, _dp(mg))
         return out[:min(n, 512)].tolist(), float(mg[0])
+
+    def mt_candidates(self, nx, ny, xs, xp, i):
+        """Node i's candidate triangles (ascending) with hit flags and decision margins."""
+        xs, xp = _d(xs).reshape(-1, 3), _d(xp).reshape(-1, 3)
+        n = self._lib.orc_mt_candidates(self._h, int(nx), int(ny), _dp(xs), _dp(xp), int(i),
+                                        None, None, None, 0)
+        ids = np.zeros(max(n, 1), dtype=np.int32)
+        hits = np.zeros(max(n, 1), dtype=np.int32)
+        mg = np.zeros(max(n, 1))
+        self._lib.orc_mt_candidates(self._h, int(nx), int(ny), _dp(xs), _dp(xp), int(i),
+                                    _ip(ids), _ip(hits), _dp(mg), n)
+        return ids[:n], hits[:n].astype(bool), mg[:n]
 
     def substep_mt(self, nx, ny, x, v, h):
         """One substep with the triangle-triangle narrow phase: (x1, v1, counts, margins)."""

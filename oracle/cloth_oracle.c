@@ -810,12 +810,42 @@ static int box_overlaps(const orc_model *m, int t, const double lo[3], const dou
  * overlaps the box of i's edges, cloth triangles and path; a crossing point lies in both
  * boxes, so the filter never changes the result.  Writes up to cap ids in ascending order and
  * returns the count; *margin receives the smallest decision margin over every test made. */
-int orc_mt_contacts(const orc_model *m, int nx, int ny, const double *xs, const double *xp,
-                    int i, int *out, int cap, double *margin)
+/* Whether node i's tests (A), (B), (C) find a crossing with triangle t; *mg receives the
+ * smallest decision margin over those tests. */
+static int mt_pair(const orc_model *m, const double *xs, const double *xp, int i, int t,
+                   const int *nb, int nnb, int tri[6][3], int ntri, double *mg)
 {
-    double mg = INFINITY;
-    int n = 0;
-    if (m->T == 0 || m->w[i] == 0.0) { if (margin) *margin = mg; return 0; }
+    const int *tv = m->tris + 3 * t;
+    const double *V0 = m->verts + 3 * tv[0], *V1 = m->verts + 3 * tv[1], *V2 = m->verts + 3 * tv[2];
+    int hit = 0;
+    double g, best = INFINITY;
+    for (int k = 0; k < nnb; ++k) {            /* (A) */
+        int p0 = i < nb[k] ? i : nb[k], p1 = i < nb[k] ? nb[k] : i;
+        hit |= orc_mt(xp + 3 * p0, xp + 3 * p1, V0, V1, V2, ORC_MT_EPS, NULL, &g);
+        if (g < best) best = g;
+    }
+    for (int k = 0; k < ntri; ++k)             /* (B) */
+        for (int z = 0; z < 3; ++z) {
+            int u0 = tv[z], u1 = tv[(z + 1) % 3];
+            int w0 = u0 < u1 ? u0 : u1, w1 = u0 < u1 ? u1 : u0;
+            hit |= orc_mt(m->verts + 3 * w0, m->verts + 3 * w1, xp + 3 * tri[k][0],
+                          xp + 3 * tri[k][1], xp + 3 * tri[k][2], ORC_MT_EPS, NULL, &g);
+            if (g < best) best = g;
+        }
+    hit |= orc_mt(xs + 3 * i, xp + 3 * i, V0, V1, V2, ORC_MT_EPS, NULL, &g);  /* (C) */
+    if (g < best) best = g;
+    *mg = best;
+    return hit;
+}
+
+/* Every candidate triangle of node i (ascending id) with whether it is a contact and the
+ * smallest decision margin of its tests.  Returns the candidate count (entries beyond cap
+ * are counted, not written).  Candidates are the triangles whose slack-inflated box
+ * overlaps the box of i's path, edges and cloth triangles. */
+int orc_mt_candidates(const orc_model *m, int nx, int ny, const double *xs, const double *xp,
+                      int i, int *ids, int *hits, double *margins, int cap)
+{
+    if (m->T == 0 || m->w[i] == 0.0) return 0;
     int tri[6][3], nb[6];
     int ntri = cloth_tris_of(nx, ny, i, tri), nnb = cloth_edges_of(nx, ny, i, nb);
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -831,41 +861,50 @@ int orc_mt_contacts(const orc_model *m, int nx, int ny, const double *xs, const 
                 long long id = ((long long)ck * m->dim[1] + cj) * m->dim[0] + ci;
                 for (int r = m->cell_start[id]; r < m->cell_start[id + 1]; ++r) {
                     int t = m->cell_tris[r];
-                    if (seen[t] || !box_overlaps(m, t, lo, hi)) continue;
-                    seen[t] = 1;
-                    const int *tv = m->tris + 3 * t;
-                    const double *V0 = m->verts + 3 * tv[0], *V1 = m->verts + 3 * tv[1],
-                                 *V2 = m->verts + 3 * tv[2];
-                    int hit = 0;
-                    double g;
-                    for (int k = 0; k < nnb; ++k) {            /* (A) */
-                        int p0 = i < nb[k] ? i : nb[k], p1 = i < nb[k] ? nb[k] : i;
-                        hit |= orc_mt(xp + 3 * p0, xp + 3 * p1, V0, V1, V2, ORC_MT_EPS, NULL, &g);
-                        if (g < mg) mg = g;
-                    }
-                    for (int k = 0; k < ntri; ++k)             /* (B) */
-                        for (int z = 0; z < 3; ++z) {
-                            int u0 = tv[z], u1 = tv[(z + 1) % 3];
-                            int w0 = u0 < u1 ? u0 : u1, w1 = u0 < u1 ? u1 : u0;
-                            hit |= orc_mt(m->verts + 3 * w0, m->verts + 3 * w1, xp + 3 * tri[k][0],
-                                          xp + 3 * tri[k][1], xp + 3 * tri[k][2], ORC_MT_EPS, NULL, &g);
-                            if (g < mg) mg = g;
-                        }
-                    hit |= orc_mt(xs + 3 * i, xp + 3 * i, V0, V1, V2, ORC_MT_EPS, NULL, &g);  /* (C) */
-                    if (g < mg) mg = g;
-                    if (hit) {
-                        /* insert in ascending order */
-                        int pos = n < cap ? n : cap;
-                        while (pos > 0 && out[pos - 1] > t) {
-                            if (pos < cap) out[pos] = out[pos - 1];
-                            --pos;
-                        }
-                        if (pos < cap) out[pos] = t;
-                        ++n;
-                    }
+                    if (!seen[t] && box_overlaps(m, t, lo, hi)) seen[t] = 1;
                 }
             }
+    int n = 0;
+    for (int t = 0; t < m->T; ++t) {
+        if (!seen[t]) continue;
+        double mg;
+        int hit = mt_pair(m, xs, xp, i, t, nb, nnb, tri, ntri, &mg);
+        if (n < cap) { ids[n] = t; hits[n] = hit; margins[n] = mg; }
+        ++n;
+    }
     free(seen);
+    return n;
+}
+
+/* The contact set of node i under the triangle-triangle narrow phase (Sec. 3): surface
+ * triangle t is a contact of i when
+ *   (A) a cloth edge at i, at predicted positions xp, crosses t (oriented from the lower
+ *       node id), or
+ *   (B) an edge of t (oriented from the lower vertex id) crosses a cloth triangle at i, at xp
+ *       (so every triangle next to a surface edge that pierces the cloth is a contact of
+ *       that cloth triangle's three nodes), or
+ *   (C) i's own path from xs to xp crosses t (the continuous test).
+ * Pinned nodes have no contacts.  Candidates are the triangles whose slack-inflated box
+ * overlaps the box of i's edges, cloth triangles and path; a crossing point lies in both
+ * boxes, so the filter never changes the result.  Writes up to cap ids in ascending order and
+ * returns the count; *margin receives the smallest decision margin over every test made. */
+int orc_mt_contacts(const orc_model *m, int nx, int ny, const double *xs, const double *xp,
+                    int i, int *out, int cap, double *margin)
+{
+    int ncand = orc_mt_candidates(m, nx, ny, xs, xp, i, NULL, NULL, NULL, 0);
+    int *ids = malloc(sizeof(int) * (size_t)(ncand + 1)), *hits = malloc(sizeof(int) * (size_t)(ncand + 1));
+    double *mgs = malloc(sizeof(double) * (size_t)(ncand + 1));
+    orc_mt_candidates(m, nx, ny, xs, xp, i, ids, hits, mgs, ncand);
+    double mg = INFINITY;
+    int n = 0;
+    for (int r = 0; r < ncand; ++r) {
+        if (mgs[r] < mg) mg = mgs[r];
+        if (hits[r]) {
+            if (n < cap) out[n] = ids[r];
+            ++n;
+        }
+    }
+    free(ids); free(hits); free(mgs);
     if (margin) *margin = mg;
     return n;
 }

@@ -88,3 +88,41 @@ def resolve_contacts(model, x, v, h, x1, v1, L, border=1e-6, xtol=2e-6, vtol_abs
         assert found is not None, ("no contact set reproduces node", i)
         out.append(found)
     return out
+
+
+def mt_substep_parity(model, nx, ny, x, v, h, x1, v1, L, border=2e-6, xtol=2e-6, vtol_abs=2e-3,
+                      vtol_rel=1e-4, tag=""):
+    """substep_parity for the triangle-triangle narrow phase: nodes whose tests all lie at
+    least ``border`` from a decision boundary must match the oracle's substep; the others
+    must match the response to the sure contacts plus some subset of the near-boundary
+    candidates."""
+    x64, v64 = np.asarray(x, np.float64), np.asarray(v, np.float64)
+    xr, vr, cnt, margin = model.substep_mt(nx, ny, x64, v64, h)
+    X1, V1 = np.asarray(x1, np.float64), np.asarray(v1, np.float64)
+    ex = np.abs(X1 - xr).max(axis=1)
+    ev = np.abs(V1 - vr).max(axis=1)
+    vtol = vtol_abs + vtol_rel * float(np.abs(vr).max())
+    amb = margin < border
+    bad = np.nonzero(~amb & ((ex > xtol * L) | (ev > vtol)))[0]
+    assert bad.size == 0, (tag, "mismatch", bad[:8].tolist(), ex[bad[:8]].tolist(),
+                           ev[bad[:8]].tolist(), cnt[bad[:8]].tolist())
+    if amb.any():
+        xs, vs = model.predict(x64, v64, h)
+        for i in np.nonzero(amb)[0]:
+            ids, hits, mg = model.mt_candidates(nx, ny, x64, xs, i)
+            sure = [int(t) for t, hh, g in zip(ids, hits, mg) if hh and g >= border]
+            maybe = [int(t) for t, g in zip(ids, mg) if g < border]
+            assert len(maybe) <= 10, (tag, "too many ambiguous candidates", int(i), len(maybe))
+            ok = False
+            for r in range(len(maybe) + 1):
+                for sub in itertools.combinations(maybe, r):
+                    p, q = model.respond(xs[i], vs[i], sorted(sure + list(sub)))
+                    if np.abs(p - X1[i]).max() <= xtol * L and np.abs(q - V1[i]).max() <= vtol:
+                        ok = True
+                        break
+                if ok:
+                    break
+            assert ok, (tag, "ambiguous node matches no valid resolution", int(i), sure, maybe)
+    clean = ~amb
+    return dict(contacts=int(np.count_nonzero(cnt)), ambiguous=int(amb.sum()),
+                ex=float(ex[clean].max() / L) if clean.any() else 0.0)

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libcloth.so")
 
 CLOTH_OK, CLOTH_EINVAL, CLOTH_ENOMEM, CLOTH_EDEVICE = 0, -1, -2, -3
 CLOTH_EUNSTABLE, CLOTH_ESTATE, CLOTH_ENAN = -4, -5, -6
-CLOTH_F_CHECK_NAN, CLOTH_F_NO_STABILITY_CHECK = 0x1, 0x2
+CLOTH_F_CHECK_NAN, CLOTH_F_NO_STABILITY_CHECK, CLOTH_F_NARROW_MT = 0x1, 0x2, 0x4
 
 _lib = None
 _lock = threading.Lock()

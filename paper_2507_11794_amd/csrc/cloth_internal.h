@@ -26,6 +26,7 @@ struct SurfaceView {
     const float4* box_lo;        // [T] inflated box, .w unused
     const float4* box_hi;        // [T]
     const float4* geo;           // [T*3]: (A, n.x), (B-A, n.y), (C-A, n.z); n = unit outward normal
+    const float4* tri_v;         // [T*3]: the vertices (x, y, z, vertex id as int bits)
 };
 
 // One cloth's node and spring arrays on the device (internal node order).
@@ -137,6 +138,26 @@ hipError_t launch_scatter_substep(const ClothView& cv, const SpringList& sl, int
                                   int stage_cap);
 hipError_t prepare_scatter_kernels(size_t lds_bytes);
 
+// Cloth-grid topology for the triangle-triangle narrow phase: order[slot] = node id,
+// slot[node id], node_group[slot] (NULL for one cloth), groups[g] = (node_off, nx, ny, 0).
+struct MtTopology {
+    const int* order;
+    const int* slot;
+    const int* node_group;
+    const int4* groups;
+};
+// One substep with the triangle-triangle narrow phase: prediction into P ([6][ld]: x*, v*),
+// then the contact search and the averaged response into xd, vd.
+hipError_t launch_mt_substep(const ClothView& cv, const StepParams& sp, const MtTopology& tp,
+                             const SurfaceView* svs, const float* xs, const float* vs, float* P,
+                             float* xd, float* vd, int block, hipStream_t st);
+// The contact sets that substep would use: counts[slot], up to cap ids per slot (in the
+// kernel's candidate order).
+hipError_t launch_mt_debug_contacts(const ClothView& cv, const StepParams& sp,
+                                    const MtTopology& tp, const SurfaceView* svs, const float* xs,
+                                    const float* vs, float* P, int* counts, int* ids, int cap,
+                                    hipStream_t st);
+
 // --- a6 adjoint ----------------------------------------------------------------------------
 // Response and integration transpose of one substep at state (xs, vs): partial adjoints and
 // the force adjoint fb = h w vtot (see adjoint.hip).
@@ -171,12 +192,12 @@ hipError_t launch_vertex_normals(int n, int ld, const float* x, const int* order
                                  hipStream_t st);
 
 // --- a3 grid build ---------------------------------------------------------------------
-// Per triangle: inflated box, geometry, and the number of grid cells its box overlaps
+// Per triangle: inflated box, geometry, vertices, and the number of grid cells its box overlaps
 // (clamped to 2^31-1); total_refs accumulates the sum (64-bit).
 hipError_t launch_tri_prep(int n_tris, const float* verts, const int* tris, float thickness,
                            const float org[3], float inv_cell, const int dim[3], float4* box_lo,
-                           float4* box_hi, float4* geo, unsigned long long* total_refs,
-                           hipStream_t stream);
+                           float4* box_hi, float4* geo, float4* tri_v,
+                           unsigned long long* total_refs, hipStream_t stream);
 hipError_t launch_grid_count(int n_tris, const float4* box_lo, const float4* box_hi,
                              const float org[3], float inv_cell, const int dim[3],
                              uint32_t* counts, hipStream_t stream);

@@ -42,7 +42,7 @@ Dims make_dims(const float org[3], float inv_cell, const int dim[3]) {
 
 __global__ void k_tri_prep(int T, const float* __restrict__ verts, const int* __restrict__ tris,
                            float th, Dims g, float4* box_lo, float4* box_hi, float4* geo,
-                           unsigned long long* total_refs) {
+                           float4* tri_v, unsigned long long* total_refs) {
 #pragma clang fp contract(off)
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= T) return;
@@ -71,6 +71,9 @@ __global__ void k_tri_prep(int T, const float* __restrict__ verts, const int* __
     geo[3 * t] = make_float4(ax, ay, az, nx);
     geo[3 * t + 1] = make_float4(e1x, e1y, e1z, ny);
     geo[3 * t + 2] = make_float4(e2x, e2y, e2z, nz);
+    tri_v[3 * t] = make_float4(ax, ay, az, __int_as_float(ia));
+    tri_v[3 * t + 1] = make_float4(bx, by, bz, __int_as_float(ib));
+    tri_v[3 * t + 2] = make_float4(cx, cy, cz, __int_as_float(ic));
     int c0[3], c1[3];
     cell_range(g, lo, hi, c0, c1);
     const unsigned long long n = (unsigned long long)(c1[0] - c0[0] + 1) *
@@ -239,11 +242,11 @@ inline int blocks_for(long long n, int b) { return (int)((n + b - 1) / b); }
 
 hipError_t launch_tri_prep(int n_tris, const float* verts, const int* tris, float thickness,
                            const float org[3], float inv_cell, const int dim[3], float4* box_lo,
-                           float4* box_hi, float4* geo, unsigned long long* total_refs,
-                           hipStream_t stream) {
+                           float4* box_hi, float4* geo, float4* tri_v,
+                           unsigned long long* total_refs, hipStream_t stream) {
     if (n_tris <= 0) return hipSuccess;
     k_tri_prep<<<blocks_for(n_tris, 256), 256, 0, stream>>>(
-        n_tris, verts, tris, thickness, make_dims(org, inv_cell, dim), box_lo, box_hi, geo,
+        n_tris, verts, tris, thickness, make_dims(org, inv_cell, dim), box_lo, box_hi, geo, tri_v,
         total_refs);
     return hipGetLastError();
 }

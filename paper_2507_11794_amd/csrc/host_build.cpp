@@ -145,6 +145,8 @@ int validate_params(const cloth_params* p) {
     if (!(p->restitution >= 0.0f && p->restitution <= 1.0f))
         return fail(CLOTH_EINVAL, "restitution must be in [0, 1]");
     if (!std::isfinite(p->cell_size)) return fail(CLOTH_EINVAL, "non-finite cell_size");
+    if (p->flags & ~(CLOTH_F_CHECK_NAN | CLOTH_F_NO_STABILITY_CHECK | CLOTH_F_NARROW_MT))
+        return fail(CLOTH_EINVAL, "unknown flag");
     return CLOTH_OK;
 }
 
@@ -361,7 +363,8 @@ int build_surface(const ClothHostInput& in, const cloth_params& p, DeviceArena& 
     hipError_t e;
     if ((e = arena.alloc(&sd->verts, 3 * (size_t)Vn)) || (e = arena.alloc(&sd->tris, 3 * (size_t)T)) ||
         (e = arena.alloc(&sd->total, 1)) || (e = arena.alloc(&sd->box_lo, (size_t)T)) ||
-        (e = arena.alloc(&sd->box_hi, (size_t)T)) || (e = arena.alloc(&sd->geo, 3 * (size_t)T)))
+        (e = arena.alloc(&sd->box_hi, (size_t)T)) || (e = arena.alloc(&sd->geo, 3 * (size_t)T)) ||
+        (e = arena.alloc(&sd->tri_v, 3 * (size_t)T)))
         return hip_fail(e, "hipMalloc surface");
     if ((e = hipMemcpyAsync(sd->tris, in.tris, 12 * (size_t)T, hipMemcpyHostToDevice, stream)))
         return hip_fail(e, "upload surface");
@@ -423,7 +426,7 @@ int rebuild_surface(SurfaceDevice* sd, const float* verts, DeviceArena& arena,
         (e = hipMemsetAsync(sd->total, 0, 8, stream)))
         return hip_fail(e, "upload surface");
     if ((e = launch_tri_prep(T, sd->verts, sd->tris, sv.thickness, sv.org, sv.inv_cell, sv.dim,
-                             sd->box_lo, sd->box_hi, sd->geo, sd->total, stream)))
+                             sd->box_lo, sd->box_hi, sd->geo, sd->tri_v, sd->total, stream)))
         return hip_fail(e, "triangle prep");
     unsigned long long total = 0;
     if ((e = hipMemcpyAsync(&total, sd->total, 8, hipMemcpyDeviceToHost, stream)) ||
@@ -464,6 +467,7 @@ int rebuild_surface(SurfaceDevice* sd, const float* verts, DeviceArena& arena,
     sv.box_lo = sd->box_lo;
     sv.box_hi = sd->box_hi;
     sv.geo = sd->geo;
+    sv.tri_v = sd->tri_v;
     sd->n_refs = (long long)total;
     sd->dirty = false;
     return CLOTH_OK;

@@ -107,7 +107,7 @@ struct SurfaceDevice {
     float* verts = nullptr;
     int* tris = nullptr;
     unsigned long long* total = nullptr;
-    float4 *box_lo = nullptr, *box_hi = nullptr, *geo = nullptr;
+    float4 *box_lo = nullptr, *box_hi = nullptr, *geo = nullptr, *tri_v = nullptr;
     uint32_t *counts = nullptr, *cell_start = nullptr, *tmp = nullptr, *refs = nullptr;
     float4 *ref_lo = nullptr, *ref_hi = nullptr;
     size_t cap_cells = 0, cap_refs = 0;

@@ -1,0 +1,247 @@
+// Triangle-triangle narrow phase (the extended Moller-Trumbore process of Sec. 3) as an
+// alternative to the point-triangle proximity test.  A substep is two launches: the
+// collision-free prediction of every node (forces and integration, into a scratch state),
+// then one thread per node that finds the node's contact set from the predictions of its
+// cloth neighbours and responds.  Surface triangle t is a contact of node i when
+//   (A) a cloth edge at i crosses t (oriented from the lower node id),
+//   (B) an edge of t (oriented from the lower vertex id) crosses a cloth triangle at i, or
+//   (C) i's path from its start position to its prediction crosses t.
+// The cloth mesh is the grid's quads split along their (r, c)-(r+1, c+1) diagonals.
+// Candidates come from the grid cells covering the box of i's path, edges and triangles; a
+// triangle listed in several of those cells is tested only in the first of them (the cell
+// whose coordinates are the maxima of its own and the query's low cells), so each
+// candidate is tested once, in a fixed order.  The response is the averaged push of Alg. 2:
+// x = x* + mean_t (th - (x* - A_t).n_t) n_t, v = -restitution v*.
+#include "cloth_device.h"
+#include "cloth_internal.h"
+
+namespace cloth {
+
+namespace {
+
+constexpr float kMtEps = 1e-7f;
+
+__device__ __forceinline__ float3 f3(const float4& a) { return make_float3(a.x, a.y, a.z); }
+__device__ __forceinline__ float3 sub3(float3 a, float3 b) {
+    return make_float3(a.x - b.x, a.y - b.y, a.z - b.z);
+}
+__device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ float3 cross3(float3 a, float3 b) {
+    return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+
+// Does segment S -> E cross triangle (V0, V1, V2)?  The six steps of the extended
+// Moller-Trumbore process: direction r = d / |d|, h = r x e2, a = e1 . h (parallel when
+// |a| < eps), u = (s . h) / a in [0, 1], v = (r . q) / a >= 0 with u + v <= 1, and the
+// crossing distance t = (e2 . q) / a strictly inside (eps, |d|).  Kept out of line: it is
+// called from 25 places per candidate.
+__device__ __noinline__ bool mt_cross(float3 S, float3 E, float3 V0, float3 V1, float3 V2) {
+    const float3 d = sub3(E, S);
+    const float len2 = dot3(d, d);
+    if (!(len2 > 0.0f)) return false;
+    const float len = sqrtf(len2);
+    const float3 r = make_float3(d.x / len, d.y / len, d.z / len);
+    const float3 e1 = sub3(V1, V0), e2 = sub3(V2, V0);
+    const float3 h = cross3(r, e2);
+    const float a = dot3(e1, h);
+    if (fabsf(a) < kMtEps) return false;
+    const float f = 1.0f / a;
+    const float3 s = sub3(S, V0);
+    const float u = f * dot3(s, h);
+    if (u < 0.0f || u > 1.0f) return false;
+    const float3 q = cross3(s, e1);
+    const float v = f * dot3(r, q);
+    if (v < 0.0f || u + v > 1.0f) return false;
+    const float t = f * dot3(e2, q);
+    return kMtEps < t && t < len;
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+template <bool DEBUG>
+__global__ void __launch_bounds__(256)
+    k_mt_collide(const ClothView cv, const StepParams sp, const int* __restrict__ order,
+                 const int* __restrict__ slot, const int* __restrict__ node_group,
+                 const int4* __restrict__ groups, const SurfaceView* __restrict__ svs,
+                 const float* __restrict__ xs, const float* __restrict__ P, float* __restrict__ xd,
+                 float* __restrict__ vd, int* __restrict__ counts, int* __restrict__ ids, int cap) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= cv.n) return;
+    const int ld = cv.ld;
+    const float* Pv = P + 3 * (size_t)ld;
+    float3 xp = make_float3(P[p], P[ld + p], P[2 * ld + p]);
+    float3 vp = make_float3(Pv[p], Pv[ld + p], Pv[2 * ld + p]);
+    const float w = cv.w[p];
+    const int g = node_group ? node_group[p] : 0;
+    const SurfaceView sv = svs[g];
+    int cnt = 0;
+    float3 acc = make_float3(0.0f, 0.0f, 0.0f);
+    if (w != 0.0f && sv.n_tris > 0) {
+        const int4 G = groups[g];  // node_off, nx, ny
+        const int id = order[p], loc = id - G.x, nx = G.y, ny = G.z;
+        const int row = loc / nx, col = loc - row * nx;
+        // cloth-edge neighbours in the order (0,+1) (0,-1) (+1,0) (-1,0) (+1,+1) (-1,-1);
+        // absent ones have ok = false
+        const int dr[6] = {0, 0, 1, -1, 1, -1}, dc[6] = {1, -1, 0, 0, 1, -1};
+        float3 q[6];
+        bool ok[6];
+        int nid[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const int r2 = row + dr[k], c2 = col + dc[k];
+            ok[k] = r2 >= 0 && c2 >= 0 && r2 < ny && c2 < nx;
+            nid[k] = id + dr[k] * nx + dc[k];
+            const int sk = ok[k] ? slot[nid[k]] : p;
+            q[k] = make_float3(P[sk], P[ld + sk], P[2 * ld + sk]);
+        }
+        const float3 x0 = make_float3(xs[p], xs[ld + p], xs[2 * ld + p]);
+        // query box: path and neighbours (every cloth triangle at i is spanned by them)
+        float3 lo = make_float3(fminf(x0.x, xp.x), fminf(x0.y, xp.y), fminf(x0.z, xp.z));
+        float3 hi = make_float3(fmaxf(x0.x, xp.x), fmaxf(x0.y, xp.y), fmaxf(x0.z, xp.z));
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            if (ok[k]) {
+                lo = make_float3(fminf(lo.x, q[k].x), fminf(lo.y, q[k].y), fminf(lo.z, q[k].z));
+                hi = make_float3(fmaxf(hi.x, q[k].x), fmaxf(hi.y, q[k].y), fmaxf(hi.z, q[k].z));
+            }
+        // cloth triangles at i (the split of the quads around it), vertices in (a, b, c) /
+        // (a, c, d) order; neighbour index 6 stands for i itself
+        //   quad (r-1, c-1): (ul, l, i), (ul, i, u)   quad (r-1, c): (u, i, r)
+        //   quad (r, c-1):   (l, d, i)                quad (r, c):   (i, d, dr), (i, dr, r)
+        // with r = 0, l = 1, d = 2, u = 3, dr = 4, ul = 5
+        const int T0[6] = {5, 5, 3, 1, 6, 6}, T1[6] = {1, 6, 6, 2, 2, 4}, T2[6] = {6, 3, 0, 6, 4, 0};
+        bool tok[6];
+        tok[0] = ok[5] && ok[1] && ok[3];
+        tok[1] = tok[0];
+        tok[2] = ok[3] && ok[0];
+        tok[3] = ok[1] && ok[2];
+        tok[4] = ok[2] && ok[4] && ok[0];
+        tok[5] = tok[4];
+        auto vert = [&](int k) { return k == 6 ? xp : q[k]; };
+        // cell range of the query box, clamped to the grid (boxes outside the grid hold no
+        // triangles)
+        const float fl0 = cell_coord_f(lo.x, sv.org[0], sv.inv_cell), fh0 = cell_coord_f(hi.x, sv.org[0], sv.inv_cell);
+        const float fl1 = cell_coord_f(lo.y, sv.org[1], sv.inv_cell), fh1 = cell_coord_f(hi.y, sv.org[1], sv.inv_cell);
+        const float fl2 = cell_coord_f(lo.z, sv.org[2], sv.inv_cell), fh2 = cell_coord_f(hi.z, sv.org[2], sv.inv_cell);
+        const bool inside = fh0 >= 0.0f && fh1 >= 0.0f && fh2 >= 0.0f &&
+                            fl0 <= (float)(sv.dim[0] - 1) && fl1 <= (float)(sv.dim[1] - 1) &&
+                            fl2 <= (float)(sv.dim[2] - 1);
+        if (inside) {
+            const int q0x = cell_axis(lo.x, sv.org[0], sv.inv_cell, sv.dim[0]);
+            const int q0y = cell_axis(lo.y, sv.org[1], sv.inv_cell, sv.dim[1]);
+            const int q0z = cell_axis(lo.z, sv.org[2], sv.inv_cell, sv.dim[2]);
+            const int q1x = cell_axis(hi.x, sv.org[0], sv.inv_cell, sv.dim[0]);
+            const int q1y = cell_axis(hi.y, sv.org[1], sv.inv_cell, sv.dim[1]);
+            const int q1z = cell_axis(hi.z, sv.org[2], sv.inv_cell, sv.dim[2]);
+            const float th = sv.thickness;
+            for (int cz = q0z; cz <= q1z; ++cz)
+                for (int cy = q0y; cy <= q1y; ++cy)
+                    for (int cx = q0x; cx <= q1x; ++cx) {
+                        const int cell = (cz * sv.dim[1] + cy) * sv.dim[0] + cx;
+                        const uint32_t b = sv.cell_start[cell], e = sv.cell_start[cell + 1];
+                        for (uint32_t rr = b; rr < e; ++rr) {
+                            const float4 blo = sv.ref_lo[rr], bhi = sv.ref_hi[rr];
+                            if (bhi.x < lo.x || blo.x > hi.x || bhi.y < lo.y || blo.y > hi.y ||
+                                bhi.z < lo.z || blo.z > hi.z)
+                                continue;
+                            // test each triangle in the first query cell that lists it
+                            if (max(cell_axis(blo.x, sv.org[0], sv.inv_cell, sv.dim[0]), q0x) != cx ||
+                                max(cell_axis(blo.y, sv.org[1], sv.inv_cell, sv.dim[1]), q0y) != cy ||
+                                max(cell_axis(blo.z, sv.org[2], sv.inv_cell, sv.dim[2]), q0z) != cz)
+                                continue;
+                            const uint32_t t = (uint32_t)__float_as_int(blo.w);
+                            const float4 a0 = sv.tri_v[3 * t], a1 = sv.tri_v[3 * t + 1],
+                                         a2 = sv.tri_v[3 * t + 2];
+                            const float3 V0 = f3(a0), V1 = f3(a1), V2 = f3(a2);
+                            bool hit = mt_cross(x0, xp, V0, V1, V2);  // (C)
+#pragma unroll
+                            for (int k = 0; k < 6; ++k)  // (A)
+                                if (!hit && ok[k])
+                                    hit = id < nid[k] ? mt_cross(xp, q[k], V0, V1, V2)
+                                                      : mt_cross(q[k], xp, V0, V1, V2);
+                            const float3 Vs[3] = {V0, V1, V2};
+                            const int vid[3] = {__float_as_int(a0.w), __float_as_int(a1.w),
+                                                __float_as_int(a2.w)};
+#pragma unroll
+                            for (int z = 0; z < 3; ++z) {  // (B)
+                                const int z1 = z == 2 ? 0 : z + 1;
+                                const bool fwd = vid[z] < vid[z1];
+                                const float3 S = fwd ? Vs[z] : Vs[z1], E = fwd ? Vs[z1] : Vs[z];
+#pragma unroll
+                                for (int k = 0; k < 6; ++k)
+                                    if (!hit && tok[k])
+                                        hit = mt_cross(S, E, vert(T0[k]), vert(T1[k]), vert(T2[k]));
+                            }
+                            if (hit) {
+                                if (DEBUG) {
+                                    if (cnt < cap) ids[(size_t)p * cap + cnt] = (int)t;
+                                } else {
+                                    const float4 g0 = sv.geo[3 * t], g1 = sv.geo[3 * t + 1],
+                                                 g2 = sv.geo[3 * t + 2];
+                                    const float3 n = make_float3(g0.w, g1.w, g2.w);
+                                    const float s = dot3(sub3(xp, f3(g0)), n);
+                                    const float push = th - s;
+                                    acc.x += push * n.x;
+                                    acc.y += push * n.y;
+                                    acc.z += push * n.z;
+                                }
+                                ++cnt;
+                            }
+                        }
+                    }
+        }
+    }
+    if (DEBUG) {
+        counts[p] = cnt;
+        return;
+    }
+    if (cnt > 0) {
+        const float inv = 1.0f / (float)cnt;
+        xp.x += acc.x * inv;
+        xp.y += acc.y * inv;
+        xp.z += acc.z * inv;
+        vp.x = -sp.restitution * vp.x;
+        vp.y = -sp.restitution * vp.y;
+        vp.z = -sp.restitution * vp.z;
+    }
+    xd[p] = xp.x;
+    xd[ld + p] = xp.y;
+    xd[2 * ld + p] = xp.z;
+    vd[p] = vp.x;
+    vd[ld + p] = vp.y;
+    vd[2 * ld + p] = vp.z;
+    if (sp.check_nan) {
+        const float sum = xp.x + xp.y + xp.z + vp.x + vp.y + vp.z;
+        if (!__builtin_isfinite(sum)) atomicOr(sp.nan_flag, 1);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_mt_substep(const ClothView& cv, const StepParams& sp, const MtTopology& tp,
+                             const SurfaceView* svs, const float* xs, const float* vs, float* P,
+                             float* xd, float* vd, int block, hipStream_t st) {
+    if (cv.n <= 0) return hipSuccess;
+    // prediction without collision into P, then the contact search and response
+    hipError_t e = launch_substep(cv, 0, sp, xs, vs, P, P + 3 * (size_t)cv.ld, block, st, svs);
+    if (e != hipSuccess) return e;
+    k_mt_collide<false><<<(cv.n + 255) / 256, 256, 0, st>>>(cv, sp, tp.order, tp.slot,
+                                                            tp.node_group, tp.groups, svs, xs, P,
+                                                            xd, vd, nullptr, nullptr, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_mt_debug_contacts(const ClothView& cv, const StepParams& sp,
+                                    const MtTopology& tp, const SurfaceView* svs, const float* xs,
+                                    const float* vs, float* P, int* counts, int* ids, int cap,
+                                    hipStream_t st) {
+    if (cv.n <= 0) return hipSuccess;
+    hipError_t e = launch_substep(cv, 0, sp, xs, vs, P, P + 3 * (size_t)cv.ld, 256, st, svs);
+    if (e != hipSuccess) return e;
+    k_mt_collide<true><<<(cv.n + 255) / 256, 256, 0, st>>>(cv, sp, tp.order, tp.slot,
+                                                           tp.node_group, tp.groups, svs, xs, P,
+                                                           nullptr, nullptr, counts, ids, cap);
+    return hipGetLastError();
+}
+
+}  // namespace cloth

@@ -75,6 +75,7 @@ int cloth_rollout_forward(cloth_sim* s, const float* k_dev, const float* c_dev,
     if (!s) return fail(CLOTH_EINVAL, "NULL handle");
     if (s->groups.size() != 1) return fail(CLOTH_EINVAL, "rollouts take a single-cloth handle");
     if (s->surface_broken) return fail(CLOTH_ESTATE, "a surface update failed; update it again first");
+    if (s->mt) return fail(CLOTH_EINVAL, "rollouts use the point-triangle narrow phase");
     if (s->launch.kernel != CLOTH_KERNEL_TILE && s->launch.kernel != CLOTH_KERNEL_DIRECT)
         return fail(CLOTH_EINVAL, "rollouts recompute with the gather kernels: select the tile "
                                   "or direct kernel");
@@ -228,9 +229,16 @@ int cloth_debug_contacts(cloth_sim* s, float h, int* counts, int* ids, int cap) 
     if ((e = tmp.alloc(&d_cnt, (size_t)N)) || (e = tmp.alloc(&d_ids, (size_t)N * cap + 1)))
         return hip_fail(e, "hipMalloc contacts");
     std::vector<int> cnt(N), id((size_t)N * cap + 1);
-    if ((e = launch_debug_contacts(s->dev.view(), s->surfs[0].view, step_params(s, h),
-                                   s->dev.x[s->dev.cur], s->dev.v[s->dev.cur], d_cnt, d_ids, cap,
-                                   s->stream)) ||
+    const hipError_t le =
+        s->mt ? launch_mt_debug_contacts(s->dev.view(), step_params(s, h),
+                                         MtTopology{s->order_dev, s->slot_dev, nullptr,
+                                                    s->group_desc_dev},
+                                         s->svs_dev, s->dev.x[s->dev.cur], s->dev.v[s->dev.cur],
+                                         s->mt_pred, d_cnt, d_ids, cap, s->stream)
+              : launch_debug_contacts(s->dev.view(), s->surfs[0].view, step_params(s, h),
+                                      s->dev.x[s->dev.cur], s->dev.v[s->dev.cur], d_cnt, d_ids,
+                                      cap, s->stream);
+    if ((e = le) ||
         (e = hipMemcpyAsync(cnt.data(), d_cnt, 4 * (size_t)N, hipMemcpyDeviceToHost, s->stream)) ||
         (cap > 0 && (e = hipMemcpyAsync(id.data(), d_ids, 4 * (size_t)N * cap,
                                         hipMemcpyDeviceToHost, s->stream))) ||
@@ -239,6 +247,8 @@ int cloth_debug_contacts(cloth_sim* s, float h, int* counts, int* ids, int cap) 
     for (int p = 0; p < N; ++p) {
         const int node = s->host.order[p];
         counts[node] = cnt[p];
+        // the triangle-triangle search lists contacts in its candidate order
+        if (s->mt) std::sort(id.begin() + (size_t)p * cap, id.begin() + (size_t)p * cap + std::min(cnt[p], cap));
         for (int r = 0; r < cap; ++r) ids[(size_t)node * cap + r] = id[(size_t)p * cap + r];
     }
     return CLOTH_OK;

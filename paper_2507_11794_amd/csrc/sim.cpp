@@ -162,6 +162,13 @@ namespace {
 // One launch advancing K substeps from buffer `src` into buffer `src ^ 1`.
 hipError_t launch_once(cloth_sim* s, const StepParams& sp, int K, int src, hipStream_t st) {
     const int dst = src ^ 1;
+    if (s->mt && s->any_collision)
+        return launch_mt_substep(s->dev.view(), sp,
+                                 MtTopology{s->order_dev, s->slot_dev,
+                                            s->groups.size() > 1 ? s->node_group_dev : nullptr,
+                                            s->group_desc_dev},
+                                 s->svs_dev, s->dev.x[src], s->dev.v[src], s->mt_pred,
+                                 s->dev.x[dst], s->dev.v[dst], s->launch.block_threads, st);
     if (s->launch.kernel == CLOTH_KERNEL_TILE && (K < 1 || K > s->plan.K))
         return hipErrorInvalidValue;  // the plan covers at most plan.K substeps per launch
     if (s->launch.kernel == CLOTH_KERNEL_TILE)
@@ -245,7 +252,7 @@ int run_substeps(cloth_sim* s, float h, long long total) {
         s->launch_ready = true;
     }
     s->roll.ready = false;  // stepping moves the state away from a rollout's checkpoints
-    const int K = s->launch.kernel == CLOTH_KERNEL_TILE ? s->launch.substeps_per_launch : 1;
+    const int K = substeps_per_launch(s);
     long long launches = total / K;
     const int rem = (int)(total % K);
     if (s->launch.use_graph) {
@@ -453,6 +460,11 @@ int create_sim(const std::vector<ClothHostInput>& cloths, const cloth_params* p,
                                     s->stream)))
                 st = hip_fail(e, "create");
         }
+        if (st == CLOTH_OK && (p->flags & CLOTH_F_NARROW_MT) && s->any_collision) {
+            s->mt = true;
+            if ((e = s->arena.alloc(&s->mt_pred, 6 * ld))) st = hip_fail(e, "create");
+            if (st == CLOTH_OK) st = ensure_topology(s);
+        }
         if (st == CLOTH_OK && (e = hipStreamSynchronize(s->stream))) st = hip_fail(e, "create");
     }
     if (st != CLOTH_OK) {
@@ -513,8 +525,12 @@ int set_external_force(cloth_sim* s, const float* f) {
     return CLOTH_OK;
 }
 
-int vertex_normals(cloth_sim* s, float* n_out) {
-    if (!n_out) return fail(CLOTH_EINVAL, "n_out is NULL");
+int substeps_per_launch(const cloth_sim* s) {
+    if (s->mt && s->any_collision) return 1;
+    return s->launch.kernel == CLOTH_KERNEL_TILE ? s->launch.substeps_per_launch : 1;
+}
+
+int ensure_topology(cloth_sim* s) {
     hipError_t e;
     if (!s->order_dev) {
         const size_t G = s->groups.size();
@@ -533,6 +549,14 @@ int vertex_normals(cloth_sim* s, float* n_out) {
         s->order_dev = order;
         s->group_desc_dev = gd;
     }
+    return CLOTH_OK;
+}
+
+int vertex_normals(cloth_sim* s, float* n_out) {
+    if (!n_out) return fail(CLOTH_EINVAL, "n_out is NULL");
+    int st = ensure_topology(s);
+    if (st != CLOTH_OK) return st;
+    hipError_t e;
     if ((e = launch_vertex_normals(s->n_nodes, s->dev.ld, s->dev.x[s->dev.cur], s->order_dev,
                                    s->slot_dev, s->node_group_dev, s->group_desc_dev, n_out,
                                    s->stream)))

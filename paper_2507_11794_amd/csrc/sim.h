@@ -96,7 +96,9 @@ struct cloth_sim {
     // external forces (SoA [3][ld], internal slots), allocated by the first set call
     float* fext_dev = nullptr;
     bool fext_on = false;
-    bool surface_broken = false;  // a surface rebuild failed part-way: stepping is refused
+    bool surface_broken = false;
+    bool mt = false;             // triangle-triangle narrow phase (CLOTH_F_NARROW_MT)
+    float* mt_pred = nullptr;    // its prediction scratch, [6][ld]  // a surface rebuild failed part-way: stepping is refused
     cloth::RolloutState roll;
 
     void drop_graphs() {
@@ -140,6 +142,10 @@ int read_state_range(const cloth_sim* s, int group, float* x_out, float* v_out);
 int update_surface(cloth_sim* s, int group, const float* verts, int n_verts);
 // Per-node external forces [n_nodes][3] in caller numbering (NULL removes them).
 int set_external_force(cloth_sim* s, const float* f);
+// Device tables of the cloth-grid topology (node order, per-cloth sizes), made once.
+int ensure_topology(cloth_sim* s);
+// Substeps one launch of the current configuration advances.
+int substeps_per_launch(const cloth_sim* s);
 // Per-vertex normals of the current state of every cloth into n_out (device, AoS, caller
 // numbering), on the handle's stream.
 int vertex_normals(cloth_sim* s, float* n_out);

@@ -1,0 +1,115 @@
+"""GPU triangle-triangle narrow phase (CLOTH_F_NARROW_MT, the extended Moller-Trumbore
+process of Sec. 3) against the FP64 oracle: one-substep parity through a drop, contact
+sets compared directly, the closed-form fall through a plane, batch == plain and graphs ==
+stream launches.  Decisions within 2e-6 m of a boundary (barycentric bounds scaled by the
+triangle edge, segment ends) may go either way in FP32 and are resolved as in the other
+parity tests."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.parity import mt_substep_parity
+from paper_2507_11794_amd import cloth as B
+from paper_2507_11794_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+MT = B.CLOTH_F_NARROW_MT
+BORDER = 2e-6
+
+
+def h32(inp):
+    return float(np.float32(np.float32(inp.dt) / np.float32(inp.n_substeps)))
+
+
+def side(inp):
+    return float(np.max(np.ptp(inp.x0.astype(np.float64), axis=0)))
+
+
+def test_mt_one_substep_parity_through_a_drop():
+    inp = W.small_collision_scene(n=24, n_steps=130)
+    model = oracle.Model.from_inputs(inp)
+    h = h32(inp)
+    contacts = amb = 0
+    with B.Cloth(inp, flags=MT) as sim:
+        for frame in range(inp.n_steps):
+            if frame % 5 == 0 or frame > 75:
+                x, v = sim.read_state()
+                sim.step(dt=h, n_substeps=1, n_steps=1)
+                x1, v1 = sim.read_state()
+                r = mt_substep_parity(model, inp.nx, inp.ny, x, v, h, x1, v1, side(inp),
+                                      border=BORDER, tag=f"frame {frame}")
+                contacts += r["contacts"]
+                amb += r["ambiguous"]
+                sim.step(dt=h, n_substeps=1, n_steps=inp.n_substeps - 1)
+            else:
+                sim.step(n_steps=1)
+    print(f"contacts {contacts}, resolved near-boundary nodes {amb}")
+    assert contacts > 300
+
+
+def test_mt_contact_sets_equal_the_oracle():
+    inp = W.small_collision_scene(n=24, n_steps=110)
+    model = oracle.Model.from_inputs(inp)
+    h = h32(inp)
+    with B.Cloth(inp, flags=MT) as sim:
+        sim.step(n_steps=inp.n_steps)
+        x, v = sim.read_state()
+        got = sim.debug_contacts(h, cap=32)
+    x64, v64 = x.astype(np.float64), v.astype(np.float64)
+    xp, _ = model.predict(x64, v64, h)
+    n_contact = 0
+    for i in range(inp.n_nodes):
+        ids, hits, mg = model.mt_candidates(inp.nx, inp.ny, x64, xp, i)
+        sure = {int(t) for t, hh, g in zip(ids, hits, mg) if hh and g >= BORDER}
+        maybe = {int(t) for t, g in zip(ids, mg) if g < BORDER}
+        g = set(got[i])
+        assert sure <= g <= sure | maybe, (i, sorted(g), sorted(sure), sorted(maybe))
+        n_contact += bool(g)
+    assert n_contact > 20
+
+
+def test_mt_fall_through_a_plane_lands_at_the_thickness():
+    n, th = 8, 0.005
+    x0 = W.flat_grid(n, n, 0.015, (0.0, 0.002, 0.0)).astype(np.float32)  # the rest spacing
+    base = W.small_collision_scene(n=n, freq=3)
+    verts = np.array([[-1, 0, -1], [-1, 0, 1], [1, 0, 1], [1, 0, -1]], np.float32)
+    tris = np.array([[0, 1, 2], [0, 2, 3]], np.int32)
+    v0 = np.zeros_like(x0)
+    v0[:, 1] = -3.0
+    inp = W.ClothInputs(nx=n, ny=n, x0=x0, v0=v0, mass=base.mass, pinned=base.pinned,
+                        ends=base.ends, rest=base.rest, k=base.k, c=base.c, kind=base.kind,
+                        verts=verts, tris=tris, gravity=(0.0, 0.0, 0.0), thickness=th,
+                        cell_size=0.05, dt=1e-3, n_substeps=1, n_steps=1)
+    with B.Cloth(inp, flags=MT | B.CLOTH_F_NO_STABILITY_CHECK) as sim:
+        sim.step(dt=1e-3, n_substeps=1, n_steps=1)
+        x, v = sim.read_state()
+    assert np.allclose(x[:, 1], th, rtol=0, atol=2e-9)
+    assert np.allclose(v[:, 1], 1.5, rtol=0, atol=1e-5)
+
+
+def test_mt_batch_equals_plain_and_graphs_equal_stream_launches():
+    cl = W.config3(n_cloths=3, seed=12, side_lo=12, side_hi=26, freq=6, n_steps=40)
+    with B.ClothBatch(cl, flags=MT) as b:
+        b.step(n_steps=40)
+        got = [b.read_state(i) for i in range(len(cl))]
+    for i, c in enumerate(cl):
+        for graph in (1, 0):
+            with B.Cloth(c, flags=MT) as s:
+                s.set_launch(use_graph=graph, kernel=B.CLOTH_KERNEL_DIRECT)
+                s.step(n_steps=40)
+                xp, vp = s.read_state()
+            assert np.array_equal(got[i][0], xp) and np.array_equal(got[i][1], vp), (i, graph)
+
+
+def test_mt_handles_refuse_rollouts():
+    import torch
+    inp = W.small_collision_scene(n=8, freq=3)
+    dev = torch.device("cuda")
+    with B.Cloth(inp, flags=MT) as sim:
+        k = torch.tensor(inp.k, device=dev)
+        c = torch.tensor(inp.c, device=dev)
+        out = torch.zeros((1, inp.n_nodes, 3), device=dev)
+        with pytest.raises(B.ClothError) as ei:
+            B.cloth_rollout_forward(sim.h, k.data_ptr(), c.data_ptr(), 0, inp.dt, inp.n_substeps,
+                                    4, 2, [4], out.data_ptr())
+        assert ei.value.status == B.CLOTH_EINVAL
