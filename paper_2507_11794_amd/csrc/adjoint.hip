@@ -99,8 +99,9 @@ __global__ void __launch_bounds__(256)
     const int base = cv.slice_ptr[i >> 6] + (i & 63);
     for (int r = 0; r < deg; ++r) {
         const int q = base + r * 64;
-        const int j = cv.nbr[q];
-        const float k = cv.ik[q], c = cv.ic[q], L0 = cv.il[q];
+        const float4 rec = cv.inc4[q];
+        const int j = __float_as_int(rec.w);
+        const float k = rec.x, c = rec.y, L0 = rec.z;
         const float dx = xs[j] - xi, dy = xs[ld + j] - yi, dz = xs[2 * ld + j] - zi;
         const float ex = vs[j] - vxi, ey = vs[ld + j] - vyi, ez = vs[2 * ld + j] - vzi;
         const float lx = fbx - fb[j], ly = fby - fb[ld + j], lz = fbz - fb[2 * ld + j];
@@ -199,6 +200,17 @@ __global__ void k_set_params(size_t m, const int* __restrict__ code, const float
     ic[q] = c[s];
 }
 
+__global__ void k_set_params_inc4(size_t m, const int* __restrict__ code,
+                                  const float* __restrict__ k, const float* __restrict__ c,
+                                  float4* __restrict__ inc4) {
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    const int s0 = code[q];
+    const int s = s0 >= 0 ? s0 : ~s0;
+    inc4[q].x = k[s];
+    inc4[q].y = c[s];
+}
+
 __global__ void k_set_params_plan(size_t m, const int* __restrict__ sid, const float* __restrict__ k,
                                   const float* __restrict__ c, float4* __restrict__ inc) {
     const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -264,6 +276,13 @@ hipError_t launch_set_params(size_t m, const int* code, const float* k, const fl
                              float* ic, hipStream_t st) {
     if (m == 0) return hipSuccess;
     k_set_params<<<blocks(m, 256), 256, 0, st>>>(m, code, k, c, ik, ic);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_params_inc4(size_t m, const int* code, const float* k, const float* c,
+                                  float4* inc4, hipStream_t st) {
+    if (m == 0) return hipSuccess;
+    k_set_params_inc4<<<blocks(m, 256), 256, 0, st>>>(m, code, k, c, inc4);
     return hipGetLastError();
 }
 

@@ -8,6 +8,22 @@
 
 namespace cloth {
 
+// Loads through these pointers are global-memory loads: the flat form the compiler uses for
+// pointers it cannot place (fields of structures read from device memory) also counts
+// against the LDS wait counter, which serialises global loads with LDS traffic.
+template <class T>
+using gptr = const __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> gmem(const T* p) {
+    return (gptr<T>)p;
+}
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+// Element i of a float4 array, as one global 16-byte load.
+__device__ __forceinline__ float4 ldg4(const float4* p, size_t i) {
+    const f32x4 v = gmem(reinterpret_cast<const f32x4*>(p))[i];
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
 // Unclamped grid coordinate of one axis, floor((p - org) * inv_cell) in FP32.  Monotone
 // non-decreasing in p (each FP32 operation rounds to nearest and floor is monotone), so a
 // triangle registered in the cells cell(lo)..cell(hi) of its inflated box is found from
@@ -59,43 +75,40 @@ __device__ __forceinline__ void spring_force(float dx, float dy, float dz, float
     fz += s * dz;
 }
 
-// a1 gather of one node over a sliced-CSR incidence list in global memory, four incidences
-// at a time: their records, then their neighbours' states, are loaded together before the
-// forces are summed in incidence order (so the sum is the same as a one-by-one loop).
+// a1 gather of one node over a sliced-CSR incidence list in global memory, up to twelve
+// incidences per round (a grid cloth's interior degree): all their records, then all their
+// neighbours' states, are loaded back to back (indices clamped to the list, so no load
+// depends on a branch), and the forces are then summed in incidence order, which keeps the
+// sum identical to a one-by-one loop.
 __device__ __forceinline__ void gather_global(const ClothView& cv, const float* __restrict__ xs,
                                               const float* __restrict__ vs, int i, float xi,
                                               float yi, float zi, float vxi, float vyi,
                                               float vzi, float& fx, float& fy, float& fz) {
+    constexpr int R = 12;
     const int ld = cv.ld;
     const int deg = cv.deg[i];
     const int base = cv.slice_ptr[i >> 6] + (i & 63);
-    for (int r0 = 0; r0 < deg; r0 += 4) {
-        int j[4];
-        float k[4], c[4], L0[4];
+    const gptr<float> X = gmem(xs), V = gmem(vs);
+    for (int r0 = 0; r0 < deg; r0 += R) {
+        float4 e[R];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int qq = base + (r0 + q) * 64;
-            const bool ok = r0 + q < deg;
-            j[q] = ok ? cv.nbr[qq] : i;
-            k[q] = ok ? cv.ik[qq] : 0.0f;
-            c[q] = ok ? cv.ic[qq] : 0.0f;
-            L0[q] = ok ? cv.il[qq] : 0.0f;
-        }
-        float nx[4], ny[4], nz[4], mx[4], my[4], mz[4];
+        for (int q = 0; q < R; ++q) e[q] = ldg4(cv.inc4, (size_t)(base + min(r0 + q, deg - 1) * 64));
+        float nx[R], ny[R], nz[R], mx[R], my[R], mz[R];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            nx[q] = xs[j[q]];
-            ny[q] = xs[ld + j[q]];
-            nz[q] = xs[2 * ld + j[q]];
-            mx[q] = vs[j[q]];
-            my[q] = vs[ld + j[q]];
-            mz[q] = vs[2 * ld + j[q]];
+        for (int q = 0; q < R; ++q) {
+            const int j = __float_as_int(e[q].w);
+            nx[q] = X[j];
+            ny[q] = X[ld + j];
+            nz[q] = X[2 * ld + j];
+            mx[q] = V[j];
+            my[q] = V[ld + j];
+            mz[q] = V[2 * ld + j];
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < R; ++q)
             if (r0 + q < deg)
                 spring_force(nx[q] - xi, ny[q] - yi, nz[q] - zi, mx[q] - vxi, my[q] - vyi,
-                             mz[q] - vzi, k[q], c[q], L0[q], fx, fy, fz);
+                             mz[q] - vzi, e[q].x, e[q].y, e[q].z, fx, fy, fz);
     }
 }
 
@@ -185,19 +198,27 @@ __device__ __forceinline__ int narrow_visit(const SurfaceView& sv, uint32_t t, c
     return 0;
 }
 
-// Narrow phase for up to 4 box hits at once: their geometry loads are issued together, then
-// the hits are visited in the given (ascending) order.
+// Position (0..63) of the lowest set bit, and that bit cleared.
+__device__ __forceinline__ int pop_low(unsigned long long& m) {
+    const int k = __builtin_ctzll(m);
+    m &= m - 1ULL;
+    return k;
+}
+
+// Narrow phase of up to four box hits whose triangle ids are t[0..n) (ascending): their
+// geometry loads are issued together (ids past n repeat the last one and are not visited).
 template <class Visit>
-__device__ __forceinline__ int narrow_batch(const SurfaceView& sv, const uint32_t* t, int n,
-                                            float px, float py, float pz, Visit&& visit) {
+__device__ __forceinline__ int narrow4(const SurfaceView& sv, uint32_t t0, uint32_t t1, uint32_t t2,
+                                       uint32_t t3, int n, float px, float py, float pz,
+                                       Visit&& visit) {
+    const uint32_t t[4] = {t0, t1, t2, t3};
     float4 g[4][3];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-        if (q < n) {
-            g[q][0] = sv.geo[3 * t[q]];
-            g[q][1] = sv.geo[3 * t[q] + 1];
-            g[q][2] = sv.geo[3 * t[q] + 2];
-        }
+    for (int q = 0; q < 4; ++q) {
+        g[q][0] = ldg4(sv.geo, 3 * (size_t)t[q]);
+        g[q][1] = ldg4(sv.geo, 3 * (size_t)t[q] + 1);
+        g[q][2] = ldg4(sv.geo, 3 * (size_t)t[q] + 2);
+    }
     int cnt = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -205,44 +226,74 @@ __device__ __forceinline__ int narrow_batch(const SurfaceView& sv, const uint32_
     return cnt;
 }
 
+// Visits the box hits recorded in `mask` (bit k = entry k of a run of references, ascending
+// triangle id), four per round of geometry loads; id(k) gives entry k's triangle id.
+template <class Id, class Visit>
+__device__ __forceinline__ int narrow_mask(const SurfaceView& sv, unsigned long long mask, Id&& id,
+                                           float px, float py, float pz, Visit&& visit) {
+    int cnt = 0;
+    while (mask) {
+        const int n = min(__popcll(mask), 4);
+        const int k0 = pop_low(mask);
+        const int k1 = n > 1 ? pop_low(mask) : k0;
+        const int k2 = n > 2 ? pop_low(mask) : k1;
+        const int k3 = n > 3 ? pop_low(mask) : k2;
+        cnt += narrow4(sv, id(k0), id(k1), id(k2), id(k3), n, px, py, pz, visit);
+    }
+    return cnt;
+}
+
 // a3 + a4 contact search for a node at predicted position p: candidates are the triangles
 // listed in p's cell whose inflated box holds p (ascending id); a candidate is a contact iff
 // the point-triangle distance is < thickness, and visit(n, s, t) is then called with the
-// triangle's unit normal n, the signed plane distance s = (p - A).n and the triangle id t.  References are
-// read from the inline reference boxes four at a time (the arrays carry at least four
-// entries of padding).  Returns the contact count.
+// triangle's unit normal n, the signed plane distance s = (p - A).n and the triangle id t.
+// Reference boxes are loaded eight at a time (the arrays carry eight entries of padding, so
+// the loads need no bounds test).  Returns the contact count.
 template <class Visit>
 __device__ __forceinline__ int contacts_visit(const SurfaceView& sv, float px, float py, float pz,
                                               Visit&& visit) {
     const int cell = cell_of(sv, px, py, pz);
     if (cell < 0) return 0;
-    const uint32_t b = sv.cell_start[cell], e = sv.cell_start[cell + 1];
+    const gptr<uint32_t> cs = gmem(sv.cell_start);
+    const uint32_t b = cs[cell], e = cs[cell + 1];
     int cnt = 0;
-    uint32_t hit[4];
-    int nh = 0;
-    for (uint32_t r = b; r < e; r += 4) {
-        float4 lo[4], hi[4];
+    for (uint32_t r = b; r < e; r += 8) {
+        float4 lo[8], hi[8];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            lo[q] = sv.ref_lo[r + q];
-            hi[q] = sv.ref_hi[r + q];
+        for (int q = 0; q < 8; ++q) {
+            lo[q] = ldg4(sv.ref_lo, r + q);
+            hi[q] = ldg4(sv.ref_hi, r + q);
         }
+        unsigned long long mask = 0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (r + q < e && in_box(lo[q], hi[q], px, py, pz)) {
-                hit[nh++] = (uint32_t)__float_as_int(lo[q].w);
-                if (nh == 4) {
-                    cnt += narrow_batch(sv, hit, 4, px, py, pz, visit);
-                    nh = 0;
-                }
-            }
+        for (int q = 0; q < 8; ++q)
+            if (r + q < e && in_box(lo[q], hi[q], px, py, pz)) mask |= 1ULL << q;
+        // a hit's triangle id is re-read from the box just loaded (a cache hit): selecting it
+        // from the registers above would make the compiler spill them to scratch
+        auto id = [&](int k) {
+            return (uint32_t)gmem(reinterpret_cast<const int*>(sv.ref_lo))[4 * (size_t)(r + k) + 3];
+        };
+        cnt += narrow_mask(sv, mask, id, px, py, pz, visit);
     }
-    if (nh) cnt += narrow_batch(sv, hit, nh, px, py, pz, visit);
     return cnt;
 }
 
 // Response of Alg. 2 with the averaged direction: with at least one contact, p moves by the
 // mean of (th - s_t) n_t over the contacts and q becomes -restitution q.
+__device__ __forceinline__ void respond(int cnt, float sx, float sy, float sz, float restitution,
+                                        float& px, float& py, float& pz, float& qx, float& qy,
+                                        float& qz) {
+    if (cnt > 0) {
+        const float inv = 1.0f / (float)cnt;
+        px += sx * inv;
+        py += sy * inv;
+        pz += sz * inv;
+        qx = -restitution * qx;
+        qy = -restitution * qy;
+        qz = -restitution * qz;
+    }
+}
+
 __device__ __forceinline__ int collide(const SurfaceView& sv, float restitution, float& px,
                                        float& py, float& pz, float& qx, float& qy, float& qz) {
     float sx = 0.0f, sy = 0.0f, sz = 0.0f;
@@ -253,15 +304,7 @@ __device__ __forceinline__ int collide(const SurfaceView& sv, float restitution,
         sy += push * n.y;
         sz += push * n.z;
     });
-    if (cnt > 0) {
-        const float inv = 1.0f / (float)cnt;
-        px += sx * inv;
-        py += sy * inv;
-        pz += sz * inv;
-        qx = -restitution * qx;
-        qy = -restitution * qy;
-        qz = -restitution * qz;
-    }
+    respond(cnt, sx, sy, sz, restitution, px, py, pz, qx, qy, qz);
     return cnt;
 }
 
@@ -276,9 +319,10 @@ __device__ __forceinline__ void wave_sync() {
 // call it (active = the lane holds an unpinned node).  The lanes' distinct grid cells are
 // found by leader election, their reference boxes (stage_cap at most) are staged into this
 // wavefront's LDS area with independent loads, and each lane then tests its own cell's range
-// from LDS.  Hits are visited in ascending triangle id, exactly as contacts_visit does, so
-// both give the same contacts and the same sums.  More than stage_cap references fall back to
-// contacts_visit.  Returns the lane's contact count after applying the response.
+// from LDS into a bit mask of hits, whose geometry is loaded four hits at a time.  Hits are
+// visited in ascending triangle id, exactly as contacts_visit does, so both give the same
+// contacts and the same sums.  More than stage_cap references fall back to contacts_visit.
+// Returns the lane's contact count after applying the response.
 __device__ __forceinline__ int collide_wave(const SurfaceView& sv, float4* stage_lo,
                                             float4* stage_hi, int stage_cap, bool active,
                                             float restitution, float& px, float& py, float& pz,
@@ -297,10 +341,11 @@ __device__ __forceinline__ int collide_wave(const SurfaceView& sv, float4* stage
         ++n_u;
         pending &= ~same;
     }
+    const gptr<uint32_t> cs = gmem(sv.cell_start);
     uint32_t b = 0, cnt = 0;
     if (lane < n_u) {
-        b = sv.cell_start[ucell];
-        cnt = sv.cell_start[ucell + 1] - b;
+        b = cs[ucell];
+        cnt = cs[ucell + 1] - b;
     }
     uint32_t incl = cnt;
 #pragma unroll
@@ -321,13 +366,14 @@ __device__ __forceinline__ int collide_wave(const SurfaceView& sv, float4* stage
         sz += push * n.z;
     };
     if (M <= (uint32_t)stage_cap) {
+        // staging: entry j of the wavefront's list lives in the unique cell k whose range
+        // [off_k, off_k + cnt_k) holds it; four entries per lane per round, all loads first
         for (uint32_t j0 = 0; j0 < M; j0 += 256) {
             float4 lo[4], hi[4];
-            uint32_t jj[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const uint32_t j = j0 + q * 64 + lane;
-                int k = 0;  // the unique cell whose range holds entry j
+                const uint32_t j = min(j0 + q * 64 + lane, M - 1);
+                int k = 0;
 #pragma unroll
                 for (int step = 32; step >= 1; step >>= 1) {
                     const int cand = k + step;
@@ -335,48 +381,38 @@ __device__ __forceinline__ int collide_wave(const SurfaceView& sv, float4* stage
                     if (cand < n_u && oc <= j) k = cand;
                 }
                 const uint32_t r = __shfl(b, k) + (j - __shfl(off, k));
-                jj[q] = j;
-                if (j < M) {
-                    lo[q] = sv.ref_lo[r];
-                    hi[q] = sv.ref_hi[r];
-                }
+                lo[q] = ldg4(sv.ref_lo, r);
+                hi[q] = ldg4(sv.ref_hi, r);
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (jj[q] < M) {
-                    stage_lo[jj[q]] = lo[q];
-                    stage_hi[jj[q]] = hi[q];
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t j = j0 + q * 64 + lane;
+                if (j < M) {
+                    stage_lo[j] = lo[q];
+                    stage_hi[j] = hi[q];
                 }
+            }
         }
         wave_sync();
         if (cell >= 0) {
-            uint32_t hit[4];
-            int nh = 0;
-            for (uint32_t r = my_off; r < my_off + my_cnt; ++r) {
-                const float4 lo = stage_lo[r], hi = stage_hi[r];
-                if (in_box(lo, hi, px, py, pz)) {
-                    hit[nh++] = (uint32_t)__float_as_int(lo.w);
-                    if (nh == 4) {
-                        contacts += narrow_batch(sv, hit, 4, px, py, pz, accumulate);
-                        nh = 0;
-                    }
-                }
+            for (uint32_t c0 = 0; c0 < my_cnt; c0 += 64) {
+                const uint32_t n = min(my_cnt - c0, 64u);
+                const float4* slo = stage_lo + my_off + c0;
+                const float4* shi = stage_hi + my_off + c0;
+                unsigned long long mask = 0;
+#pragma unroll 4
+                for (uint32_t k = 0; k < n; ++k)
+                    if (in_box(slo[k], shi[k], px, py, pz)) mask |= 1ULL << k;
+                contacts += narrow_mask(
+                    sv, mask, [&](int k) { return (uint32_t)__float_as_int(slo[k].w); }, px, py,
+                    pz, accumulate);
             }
-            if (nh) contacts += narrow_batch(sv, hit, nh, px, py, pz, accumulate);
         }
         wave_sync();  // the stage is reused by the next call
     } else if (cell >= 0) {
         contacts = contacts_visit(sv, px, py, pz, accumulate);
     }
-    if (contacts > 0) {
-        const float inv = 1.0f / (float)contacts;
-        px += sx * inv;
-        py += sy * inv;
-        pz += sz * inv;
-        qx = -restitution * qx;
-        qy = -restitution * qy;
-        qz = -restitution * qz;
-    }
+    respond(contacts, sx, sy, sz, restitution, px, py, pz, qx, qy, qz);
     return contacts;
 }
 

@@ -34,7 +34,7 @@ struct SurfaceView {
 //   Incidences use a sliced CSR layout: nodes are grouped in slices of 64 (one wavefront),
 //   and the r-th incidence of node i (r < deg[i]) sits at slice_ptr[i/64] + r*64 + i%64, so
 //   the 64 lanes of a wavefront read incidence r with one coalesced access.  Per incidence:
-//   nbr (neighbour node), ik/ic/il (the spring's stiffness, damping, rest length) and
+//   inc4 = (k, c, rest length, neighbour node as int bits), one 16-byte record, and
 //   inc_spring (spring id, bitwise-negated (~s) when node i is the spring's second end b).
 //   Each node's incidences are in ascending (neighbour, spring) order.
 struct ClothView {
@@ -43,10 +43,7 @@ struct ClothView {
     const float* w;  // [n] inverse mass, 0 = pinned
     const int* deg;        // [n]
     const int* slice_ptr;  // [ceil(n/64) + 1]
-    const int* nbr;
-    const float* ik;
-    const float* ic;
-    const float* il;
+    const float4* inc4;
     const int* inc_spring;
 };
 
@@ -181,6 +178,9 @@ hipError_t launch_export(int n, int ld, const int* slot, const float* soa, float
 // Per-incidence k, c from per-spring arrays (sliced CSR and tile plan forms).
 hipError_t launch_set_params(size_t m, const int* code, const float* k, const float* c, float* ik,
                              float* ic, hipStream_t st);
+// Per-incidence k, c into the packed records (code as inc_spring: ~s for a second end).
+hipError_t launch_set_params_inc4(size_t m, const int* code, const float* k, const float* c,
+                                  float4* inc4, hipStream_t st);
 hipError_t launch_set_params_plan(size_t m, const int* sid, const float* k, const float* c,
                                   float4* inc, hipStream_t st);
 hipError_t launch_d2f(size_t n, const double* a, float* b, hipStream_t st);

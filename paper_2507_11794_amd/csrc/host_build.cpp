@@ -276,10 +276,15 @@ int upload_cloth(const ClothHost& h, DeviceArena& arena, hipStream_t stream, Clo
     const size_t M = h.nbr.size();
     hipError_t e;
     if ((e = arena.alloc(&d->w, (size_t)N)) || (e = arena.alloc(&d->deg, (size_t)N)) ||
-        (e = arena.alloc(&d->slice_ptr, h.slice_ptr.size())) || (e = arena.alloc(&d->nbr, M)) ||
-        (e = arena.alloc(&d->ik, M)) || (e = arena.alloc(&d->ic, M)) ||
-        (e = arena.alloc(&d->il, M)) || (e = arena.alloc(&d->inc_spring, M)))
+        (e = arena.alloc(&d->slice_ptr, h.slice_ptr.size())) || (e = arena.alloc(&d->inc4, M)) ||
+        (e = arena.alloc(&d->inc_spring, M)))
         return hip_fail(e, "hipMalloc cloth arrays");
+    std::vector<float4> inc4(M);
+    for (size_t q = 0; q < M; ++q) {
+        float nb;
+        std::memcpy(&nb, &h.nbr[q], 4);
+        inc4[q] = make_float4(h.ik[q], h.ic[q], h.il[q], nb);
+    }
     struct Cp {
         void* dst;
         const void* src;
@@ -290,16 +295,15 @@ int upload_cloth(const ClothHost& h, DeviceArena& arena, hipStream_t stream, Clo
         {d->w, h.w.data(), h.w.size() * 4},
         {d->deg, h.deg.data(), h.deg.size() * 4},
         {d->slice_ptr, h.slice_ptr.data(), h.slice_ptr.size() * 4},
-        {d->nbr, h.nbr.data(), M * 4},
-        {d->ik, h.ik.data(), M * 4},
-        {d->ic, h.ic.data(), M * 4},
-        {d->il, h.il.data(), M * 4},
+        {d->inc4, inc4.data(), M * 16},
         {d->inc_spring, h.inc_spring.data(), M * 4},
     };
     for (auto& c : cps)
         if (c.bytes)
             if ((e = hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyHostToDevice, stream)))
                 return hip_fail(e, "upload cloth");
+    // the packed records live on this stack frame: finish the copies before returning
+    if ((e = hipStreamSynchronize(stream))) return hip_fail(e, "upload cloth");
     d->cur = 0;
     return CLOTH_OK;
 }
@@ -311,10 +315,7 @@ ClothView ClothDevice::view() const {
     v.w = w;
     v.deg = deg;
     v.slice_ptr = slice_ptr;
-    v.nbr = nbr;
-    v.ik = ik;
-    v.ic = ic;
-    v.il = il;
+    v.inc4 = inc4;
     v.inc_spring = inc_spring;
     return v;
 }

@@ -76,10 +76,7 @@ struct ClothDevice {
     float* w = nullptr;
     int* deg = nullptr;
     int* slice_ptr = nullptr;
-    int* nbr = nullptr;
-    float* ik = nullptr;
-    float* ic = nullptr;
-    float* il = nullptr;
+    float4* inc4 = nullptr;
     int* inc_spring = nullptr;
     ClothView view() const;
 };

@@ -38,8 +38,8 @@ int set_spring_params(cloth_sim* s, const float* k_dev, const float* c_dev) {
         s->host.ik[q] = k[sid];
         s->host.ic[q] = c[sid];
     }
-    if ((e = launch_set_params(s->host.inc_spring.size(), s->dev.inc_spring, k_dev, c_dev,
-                               s->dev.ik, s->dev.ic, s->stream)))
+    if ((e = launch_set_params_inc4(s->host.inc_spring.size(), s->dev.inc_spring, k_dev, c_dev,
+                                    s->dev.inc4, s->stream)))
         return hip_fail(e, "set spring parameters");
     if (s->plan.inc_count &&
         (e = launch_set_params_plan(s->plan.inc_count, s->plan.inc_sid, k_dev, c_dev,
