@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-normals", action="store_true", help="skip the vertex-normal timing")
     ap.add_argument("--no-moving", action="store_true",
                     help="skip the moving-surface / pulled-cloth timing")
+    ap.add_argument("--no-forces-ab", action="store_true",
+                    help="skip the gather / scatter force-accumulation comparison")
     return ap.parse_args()
 
 
@@ -191,6 +193,45 @@ def bench_moving(frames: int = 60):
             "surface_update_ms": t_upd * 1e3 / frames}
 
 
+FORCES_AB = ["kernel=direct", "kernel=tile,tile=256,K=1", "kernel=tile,tile=256,K=4",
+             "kernel=scatter_f32", "kernel=scatter_fix"]
+
+
+def bench_forces_ab(frames: int = 40):
+    """Force accumulation compared on the 800x800 hanging cloth (640,000 nodes, 3.83M
+    springs, no collision, so the spring pass dominates): the node-centric gather (one
+    launch per substep, and temporally blocked tiles) against Alg. 1's spring-centric scatter
+    with FP32 atomics and with int32 fixed-point atomics.  Microseconds per substep from HIP
+    events over the same frames from the same state."""
+    import torch
+
+    from paper_2507_11794_amd import cloth, workloads
+
+    inp = workloads.config2()
+    stream = torch.cuda.current_stream()
+    sim = cloth.Cloth(inp, stream=stream.cuda_stream)
+    sim.step(n_steps=10)
+    x0, v0 = sim.read_state()
+    out = {"nodes": inp.n_nodes, "springs": inp.n_springs, "frames": frames,
+           "substeps_per_frame": inp.n_substeps}
+    for text in FORCES_AB:
+        sim.set_launch(**parse_launch(text))
+        sim.write_state(x0, v0)
+        sim.step(n_steps=2)
+        sim.write_state(x0, v0)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        sim.step(n_steps=frames)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        out[text.replace("kernel=", "")] = round(ev0.elapsed_time(ev1) * 1e3 /
+                                                 (frames * inp.n_substeps), 3)
+    sim.close()
+    return out
+
+
 def parse_launch(text: str) -> dict:
     from paper_2507_11794_amd import cloth
 
@@ -200,7 +241,9 @@ def parse_launch(text: str) -> dict:
     for part in filter(None, text.split(",")):
         k, v = part.split("=")
         if k == "kernel":
-            cfg["kernel"] = cloth.CLOTH_KERNEL_TILE if v == "tile" else cloth.CLOTH_KERNEL_DIRECT
+            cfg["kernel"] = {"tile": cloth.CLOTH_KERNEL_TILE, "direct": cloth.CLOTH_KERNEL_DIRECT,
+                             "scatter_f32": cloth.CLOTH_KERNEL_SCATTER_F32,
+                             "scatter_fix": cloth.CLOTH_KERNEL_SCATTER_FIX}[v]
         else:
             cfg[names.get(k, k)] = int(v)
     return cfg
@@ -212,7 +255,8 @@ SWEEP = [
     "kernel=tile,tile=64,K=1,stage=384", "kernel=tile,tile=256,K=1,stage=0",
     "kernel=tile,tile=256,K=1,stage=384", "kernel=tile,tile=256,K=2,stage=256",
     "kernel=tile,tile=128,K=2,stage=384", "kernel=tile,tile=256,K=4,stage=256",
-    "kernel=tile,tile=512,K=2,stage=256",
+    "kernel=tile,tile=512,K=2,stage=256", "kernel=scatter_f32,stage=384",
+    "kernel=scatter_fix,stage=384",
 ]
 
 
@@ -383,6 +427,8 @@ def main():
         out["normals"] = normals
     if not args.no_moving:
         out["moving_surface"] = bench_moving()
+    if not args.no_forces_ab:
+        out["forces_ab_us_per_substep"] = bench_forces_ab()
     if not args.no_batch:
         out["batched"] = bench_batched(args.batch_cloths, 200)
     if not args.no_adjoint:
