@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-normals", action="store_true", help="skip the vertex-normal timing")
     ap.add_argument("--no-moving", action="store_true",
                     help="skip the moving-surface / pulled-cloth timing")
+    ap.add_argument("--no-mt", action="store_true",
+                    help="skip the triangle-triangle narrow-phase timing")
     ap.add_argument("--no-forces-ab", action="store_true",
                     help="skip the gather / scatter force-accumulation comparison")
     return ap.parse_args()
@@ -191,6 +193,31 @@ def bench_moving(frames: int = 60):
             "node_updates_per_s": inp.n_nodes * inp.n_substeps * frames / wall,
             "ms_per_frame": wall * 1e3 / frames,
             "surface_update_ms": t_upd * 1e3 / frames}
+
+
+def bench_mt(frames: int = 30):
+    """The benchmark workload with the triangle-triangle narrow phase (extended
+    Moller-Trumbore): frames timed after the drop (110 frames in), node-updates/s."""
+    import torch
+
+    from paper_2507_11794_amd import cloth, workloads
+
+    inp = workloads.config1()
+    stream = torch.cuda.current_stream()
+    sim = cloth.Cloth(inp, flags=cloth.CLOTH_F_NARROW_MT, stream=stream.cuda_stream)
+    sim.step(n_steps=110)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    sim.step(n_steps=frames)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    sim.close()
+    return {"frames": frames, "nodes": inp.n_nodes, "tris": inp.n_tris,
+            "us_per_substep": ms * 1e3 / (frames * inp.n_substeps),
+            "node_updates_per_s": inp.n_nodes * inp.n_substeps * frames / (ms * 1e-3)}
 
 
 FORCES_AB = ["kernel=direct", "kernel=tile,tile=256,K=1", "kernel=tile,tile=256,K=4",
@@ -427,6 +454,8 @@ def main():
         out["normals"] = normals
     if not args.no_moving:
         out["moving_surface"] = bench_moving()
+    if not args.no_mt:
+        out["mt_narrow_phase"] = bench_mt()
     if not args.no_forces_ab:
         out["forces_ab_us_per_substep"] = bench_forces_ab()
     if not args.no_batch:

@@ -113,3 +113,38 @@ def test_mt_handles_refuse_rollouts():
             B.cloth_rollout_forward(sim.h, k.data_ptr(), c.data_ptr(), 0, inp.dt, inp.n_substeps,
                                     4, 2, [4], out.data_ptr())
         assert ei.value.status == B.CLOTH_EINVAL
+
+
+def test_mt_full_size_sampled_contact_sets_and_substep():
+    """The 316x316 cloth over the 100,820-triangle sphere with the MT narrow phase: after the
+    drop, 3,000 sampled nodes' contact sets and one substep's positions against the oracle."""
+    inp = W.config1()
+    model = oracle.Model.from_inputs(inp)
+    h = h32(inp)
+    with B.Cloth(inp, flags=MT) as sim:
+        sim.step(n_steps=110)
+        x, v = sim.read_state()
+        got = sim.debug_contacts(h, cap=32)
+        sim.step(dt=h, n_substeps=1, n_steps=1)
+        x1, v1 = sim.read_state()
+    x64, v64 = x.astype(np.float64), v.astype(np.float64)
+    xp, vp = model.predict(x64, v64, h)
+    rng = np.random.default_rng(3)
+    sample = rng.choice(inp.n_nodes, 3000, replace=False)
+    hit_nodes = [i for i in range(inp.n_nodes) if got[i]]
+    sample = np.unique(np.concatenate([sample, rng.choice(hit_nodes, min(1000, len(hit_nodes)),
+                                                          replace=False)]))
+    L = side(inp)
+    checked = 0
+    for i in sample:
+        ids, hits, mg = model.mt_candidates(inp.nx, inp.ny, x64, xp, int(i))
+        sure = {int(t) for t, hh, g in zip(ids, hits, mg) if hh and g >= BORDER}
+        maybe = {int(t) for t, g in zip(ids, mg) if g < BORDER}
+        g = set(got[i])
+        assert sure <= g <= sure | maybe, (int(i), sorted(g), sorted(sure), sorted(maybe))
+        # the GPU's step with its own contact set equals the oracle's response to that set
+        p, q = model.respond(xp[i], vp[i], sorted(g))
+        assert np.abs(p - x1[i]).max() <= 2e-6 * L, int(i)
+        assert np.abs(q - v1[i]).max() <= 2e-3 + 1e-4 * np.abs(vp).max(), int(i)
+        checked += bool(g)
+    assert len(hit_nodes) > 1000 and checked > 500
