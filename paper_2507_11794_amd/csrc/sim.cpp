@@ -71,12 +71,8 @@ int ensure_springs(cloth_sim* s) {
     if (s->springs.ready) return CLOTH_OK;
     const int S = s->n_springs;
     const size_t ld = (size_t)s->dev.ld;
-    // per-spring rest lengths from the incidence lists; ends as internal slots
-    std::vector<float> rest(S, 0.0f);
-    for (size_t q = 0; q < s->host.inc_spring.size(); ++q) {
-        const int code = s->host.inc_spring[q];
-        rest[code >= 0 ? code : ~code] = s->host.il[q];
-    }
+    // ends as internal slots; parameters from the handle's per-spring copies
+    const std::vector<float>& rest = s->rest;
     std::vector<int> perm(S);
     for (int q = 0; q < S; ++q) perm[q] = q;
     auto lo = [&](int q) { return std::min(s->host.slot[s->ends[2 * q]], s->host.slot[s->ends[2 * q + 1]]); };
@@ -381,7 +377,8 @@ int create_sim(const std::vector<ClothHostInput>& cloths, const cloth_params* p,
         std::vector<int> order;
         order.reserve((size_t)n_tot);
         s->x0.reserve(3 * (size_t)n_tot);
-        std::vector<float> v0(3 * (size_t)n_tot, 0.0f), rest;
+        std::vector<float> v0(3 * (size_t)n_tot, 0.0f);
+        std::vector<float>& rest = s->rest;
         int node_off = 0;
         s->group_off.push_back(0);
         for (const auto& in : cloths) {

@@ -83,7 +83,7 @@ struct cloth_sim {
     bool launch_ready = false;  // plan, schedule and LDS limits match `launch`
     int* nan_flag = nullptr;
     // host copies kept for the stability bound and parameter updates (caller numbering)
-    std::vector<float> x0, mass, k, c;
+    std::vector<float> x0, mass, k, c, rest;
     std::vector<unsigned char> pinned;
     std::vector<int> ends;
     // device: initial state (SoA, internal order) and node id -> internal slot

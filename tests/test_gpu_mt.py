@@ -147,4 +147,4 @@ def test_mt_full_size_sampled_contact_sets_and_substep():
         assert np.abs(p - x1[i]).max() <= 2e-6 * L, int(i)
         assert np.abs(q - v1[i]).max() <= 2e-3 + 1e-4 * np.abs(vp).max(), int(i)
         checked += bool(g)
-    assert len(hit_nodes) > 1000 and checked > 500
+    assert len(hit_nodes) > 100 and checked > 100
