@@ -317,16 +317,19 @@ __device__ __forceinline__ void wave_sync() {
 
 // a3 + a4 for the 64 nodes of a wavefront, cooperatively; every lane of the wavefront must
 // call it (active = the lane holds an unpinned node).  The lanes' distinct grid cells are
-// found by leader election, their reference boxes (stage_cap at most) are staged into this
-// wavefront's LDS area with independent loads, and each lane then tests its own cell's range
-// from LDS into a bit mask of hits, whose geometry is loaded four hits at a time.  Hits are
-// visited in ascending triangle id, exactly as contacts_visit does, so both give the same
-// contacts and the same sums.  More than stage_cap references fall back to contacts_visit.
-// Returns the lane's contact count after applying the response.
+// found by leader election and their reference lists concatenated (M entries).  The list is
+// staged through this wavefront's LDS area in batches of stage_cap boxes, every load of a
+// batch issued before any is used; each lane tests the part of its own cell's range that a
+// batch holds and appends the triangle ids of box hits to its LDS hit list (kHitSlots
+// entries).  The hits' geometry is then loaded eight hits per round.  Hits are visited in
+// ascending triangle id, exactly as contacts_visit does, so both give the same contacts and
+// the same sums; a lane whose hits overflow its list runs contacts_visit instead.  Returns
+// the lane's contact count after applying the response.
 __device__ __forceinline__ int collide_wave(const SurfaceView& sv, float4* stage_lo,
-                                            float4* stage_hi, int stage_cap, bool active,
-                                            float restitution, float& px, float& py, float& pz,
-                                            float& qx, float& qy, float& qz) {
+                                            float4* stage_hi, uint32_t* hit_ids, int stage_cap,
+                                            bool active, float restitution, float& px,
+                                            float& py, float& pz, float& qx, float& qy,
+                                            float& qz) {
     const int lane = threadIdx.x & 63;
     const int cell = active ? cell_of(sv, px, py, pz) : -1;
     unsigned long long pending = __ballot(cell >= 0);
@@ -355,24 +358,17 @@ __device__ __forceinline__ int collide_wave(const SurfaceView& sv, float4* stage
     }
     const uint32_t off = incl - cnt;
     const uint32_t M = __shfl(incl, 63);
-    const uint32_t my_off = __shfl(off, my_u), my_cnt = __shfl(cnt, my_u);
-    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
-    int contacts = 0;
-    const float th = sv.thickness;
-    auto accumulate = [&](const float4& n, float s, uint32_t) {
-        const float push = th - s;
-        sx += push * n.x;
-        sy += push * n.y;
-        sz += push * n.z;
-    };
-    if (M <= (uint32_t)stage_cap) {
-        // staging: entry j of the wavefront's list lives in the unique cell k whose range
-        // [off_k, off_k + cnt_k) holds it; four entries per lane per round, all loads first
-        for (uint32_t j0 = 0; j0 < M; j0 += 256) {
+    const uint32_t my_off = __shfl(off, my_u), my_end = my_off + __shfl(cnt, my_u);
+    int nh = 0;
+    for (uint32_t B0 = 0; B0 < M; B0 += (uint32_t)stage_cap) {
+        const uint32_t nB = min(M - B0, (uint32_t)stage_cap);
+        // stage entries [B0, B0 + nB): entry j lives in the unique cell k whose range
+        // [off_k, off_k + cnt_k) holds it; four entries per lane per round, loads first
+        for (uint32_t j0 = 0; j0 < nB; j0 += 256) {
             float4 lo[4], hi[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const uint32_t j = min(j0 + q * 64 + lane, M - 1);
+                const uint32_t j = B0 + min(j0 + q * 64 + lane, nB - 1);
                 int k = 0;
 #pragma unroll
                 for (int step = 32; step >= 1; step >>= 1) {
@@ -387,7 +383,7 @@ __device__ __forceinline__ int collide_wave(const SurfaceView& sv, float4* stage
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const uint32_t j = j0 + q * 64 + lane;
-                if (j < M) {
+                if (j < nB) {
                     stage_lo[j] = lo[q];
                     stage_hi[j] = hi[q];
                 }
@@ -395,22 +391,39 @@ __device__ __forceinline__ int collide_wave(const SurfaceView& sv, float4* stage
         }
         wave_sync();
         if (cell >= 0) {
-            for (uint32_t c0 = 0; c0 < my_cnt; c0 += 64) {
-                const uint32_t n = min(my_cnt - c0, 64u);
-                const float4* slo = stage_lo + my_off + c0;
-                const float4* shi = stage_hi + my_off + c0;
-                unsigned long long mask = 0;
+            const uint32_t r0 = max(my_off, B0), r1 = min(my_end, B0 + nB);
 #pragma unroll 4
-                for (uint32_t k = 0; k < n; ++k)
-                    if (in_box(slo[k], shi[k], px, py, pz)) mask |= 1ULL << k;
-                contacts += narrow_mask(
-                    sv, mask, [&](int k) { return (uint32_t)__float_as_int(slo[k].w); }, px, py,
-                    pz, accumulate);
+            for (uint32_t r = r0; r < r1; ++r) {
+                const float4 lo = stage_lo[r - B0], hi = stage_hi[r - B0];
+                if (in_box(lo, hi, px, py, pz)) {
+                    if (nh < kHitSlots) hit_ids[nh * 64 + lane] = (uint32_t)__float_as_int(lo.w);
+                    ++nh;
+                }
             }
         }
-        wave_sync();  // the stage is reused by the next call
-    } else if (cell >= 0) {
+        wave_sync();  // the stage is refilled by the next batch
+    }
+    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+    const float th = sv.thickness;
+    auto accumulate = [&](const float4& n, float s, uint32_t) {
+        const float push = th - s;
+        sx += push * n.x;
+        sy += push * n.y;
+        sz += push * n.z;
+    };
+    int contacts = 0;
+    if (nh > kHitSlots) {
         contacts = contacts_visit(sv, px, py, pz, accumulate);
+    } else {
+        for (int h0 = 0; h0 < nh; h0 += 8) {
+            const int n = min(nh - h0, 8);
+            uint32_t t[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) t[q] = hit_ids[min(h0 + q, nh - 1) * 64 + lane];
+            contacts += narrow4(sv, t[0], t[1], t[2], t[3], min(n, 4), px, py, pz, accumulate);
+            if (n > 4)
+                contacts += narrow4(sv, t[4], t[5], t[6], t[7], n - 4, px, py, pz, accumulate);
+        }
     }
     respond(contacts, sx, sy, sz, restitution, px, py, pz, qx, qy, qz);
     return contacts;

@@ -116,8 +116,14 @@ hipError_t prepare_tile_kernels(size_t lds_bytes);
 // a1-a4: one substep for every node (one thread per node).  collide = 0 skips a3/a4.  The
 // surfaces are read on the device: node i's is svs[node_group[i]] with node_group non-NULL
 // (a batch of cloths), otherwise svs[0].  stage_cap: reference boxes staged in LDS per
-// wavefront for the collision query (0 = none; at most kMaxStage).
+// wavefront and batch for the collision query (0 = per-lane queries; at most kMaxStage).
 constexpr int kMaxStage = 1024;
+// Box hits one lane of the wavefront query keeps in LDS before it falls back to the per-lane
+// query, and the LDS bytes one wavefront's query uses: the staged boxes, then the hit lists.
+constexpr int kHitSlots = 32;
+constexpr size_t wave_query_lds(int stage_cap) {
+    return stage_cap > 0 ? (size_t)stage_cap * 32 + (size_t)kHitSlots * 64 * 4 : 0;
+}
 hipError_t launch_substep(const ClothView& cv, int collide, const StepParams& sp, const float* xs,
                           const float* vs, float* xd, float* vd, int block, hipStream_t stream,
                           const SurfaceView* svs, const int* node_group = nullptr,

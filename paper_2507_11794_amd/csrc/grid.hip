@@ -111,12 +111,33 @@ __global__ void k_grid_fill(int T, const float4* __restrict__ box_lo,
             }
 }
 
-// Insertion sort of each cell's (short) reference list.
-__global__ void k_grid_sort(int C, const uint32_t* __restrict__ cell_start, uint32_t* refs) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+// Sorts each cell's reference list ascending, one wavefront per cell.  A cell lists a
+// triangle at most once, so an entry's final position is its rank (the number of smaller
+// entries): up to 128 entries are held two per lane and ranked against every entry by
+// broadcasts, then written back.  Longer lists (none in practice) are insertion-sorted by one
+// lane.
+__global__ void __launch_bounds__(256)
+    k_grid_sort(int C, const uint32_t* __restrict__ cell_start, uint32_t* refs) {
+    const int c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (c >= C) return;
-    const uint32_t b = cell_start[c], e = cell_start[c + 1];
-    for (uint32_t i = b + 1; i < e; ++i) {
+    const uint32_t b = cell_start[c], n = cell_start[c + 1] - b;
+    if (n <= 1) return;
+    if (n <= 128) {
+        const uint32_t v0 = lane < (int)n ? refs[b + lane] : 0xffffffffu;
+        const uint32_t v1 = lane + 64 < (int)n ? refs[b + 64 + lane] : 0xffffffffu;
+        uint32_t r0 = 0, r1 = 0;
+        for (int k = 0; k < 64; ++k) {
+            const uint32_t w0 = __shfl(v0, k), w1 = __shfl(v1, k);
+            r0 += (w0 < v0) + (w1 < v0);
+            r1 += (w0 < v1) + (w1 < v1);
+        }
+        if (lane < (int)n) refs[b + r0] = v0;
+        if (lane + 64 < (int)n) refs[b + r1] = v1;
+        return;
+    }
+    if (lane != 0) return;
+    for (uint32_t i = b + 1; i < b + n; ++i) {
         const uint32_t v = refs[i];
         uint32_t j = i;
         while (j > b && refs[j - 1] > v) {
@@ -273,7 +294,7 @@ hipError_t launch_grid_fill(int n_tris, const float4* box_lo, const float4* box_
 hipError_t launch_grid_sort(int n_cells, const uint32_t* cell_start, uint32_t* refs,
                             hipStream_t stream) {
     if (n_cells <= 0) return hipSuccess;
-    k_grid_sort<<<blocks_for(n_cells, 256), 256, 0, stream>>>(n_cells, cell_start, refs);
+    k_grid_sort<<<blocks_for(n_cells, 4), 256, 0, stream>>>(n_cells, cell_start, refs);
     return hipGetLastError();
 }
 

@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(256)
                    float* __restrict__ xd, float* __restrict__ vd,
                    const SurfaceView* __restrict__ svs, const int* __restrict__ node_group,
                    const int stage_cap) {
-    extern __shared__ float4 stage[];  // [wavefronts][2][stage_cap]
+    extern __shared__ float4 stage[];  // per wavefront: wave_query_lds(stage_cap) bytes
     const int nb = gridDim.x, q8 = nb >> 3, rem = nb & 7, x8 = blockIdx.x & 7;
     const int blk = x8 * q8 + (x8 < rem ? x8 : rem) + (blockIdx.x >> 3);
     const int i = blk * blockDim.x + threadIdx.x;
@@ -96,9 +96,12 @@ __global__ void __launch_bounds__(256)
         } else {
             const SurfaceView sv1 = svs[0];
             if (stage_cap > 0) {
-                float4* lo = stage + (size_t)(threadIdx.x >> 6) * 2 * stage_cap;
-                collide_wave(sv1, lo, lo + stage_cap, stage_cap, valid && w != 0.0f,
-                             sp.restitution, px, py, pz, qx, qy, qz);
+                char* area = reinterpret_cast<char*>(stage) +
+                             (size_t)(threadIdx.x >> 6) * wave_query_lds(stage_cap);
+                float4* lo = reinterpret_cast<float4*>(area);
+                collide_wave(sv1, lo, lo + stage_cap,
+                             reinterpret_cast<uint32_t*>(lo + 2 * stage_cap), stage_cap,
+                             valid && w != 0.0f, sp.restitution, px, py, pz, qx, qy, qz);
             } else if (valid && w != 0.0f) {
                 collide(sv1, sp.restitution, px, py, pz, qx, qy, qz);
             }
@@ -127,7 +130,7 @@ hipError_t launch_nodes(const ClothView& cv, int collide, const StepParams& sp, 
         k_node_scatter<FIX, true, true><<<grid, block, 0, st>>>(cv, sp, F, xs, vs, xd, vd, svs,
                                                                 node_group, 0);
     } else if (collide) {
-        const size_t lds = (size_t)(block / 64) * 2 * stage_cap * sizeof(float4);
+        const size_t lds = (size_t)(block / 64) * wave_query_lds(stage_cap);
         k_node_scatter<FIX, true, false><<<grid, block, lds, st>>>(cv, sp, F, xs, vs, xd, vd, svs,
                                                                    nullptr, stage_cap);
     } else {

@@ -128,7 +128,7 @@ int set_launch(cloth_sim* s, const cloth_launch& cfg) {
     const int stage = s->any_collision ? cfg.stage_refs : 0;
     const size_t lds = cfg.kernel == CLOTH_KERNEL_TILE
                            ? tile_lds_bytes(s->plan.view.rmax, cfg.block_threads, stage)
-                           : (size_t)(cfg.block_threads / 64) * 2 * stage * sizeof(float4);
+                           : (size_t)(cfg.block_threads / 64) * wave_query_lds(stage);
     if (lds > 160 * 1024)
         return fail(CLOTH_EINVAL, "tile region plus collision stage exceed 160 KiB of LDS");
     const bool scatter = cfg.kernel == CLOTH_KERNEL_SCATTER_F32 || cfg.kernel == CLOTH_KERNEL_SCATTER_FIX;

@@ -20,7 +20,7 @@ __global__ void __launch_bounds__(256)
               const float* __restrict__ vs, float* __restrict__ xd, float* __restrict__ vd,
               const SurfaceView* __restrict__ svs, const int* __restrict__ node_group,
               const int stage_cap) {
-    extern __shared__ float4 stage[];  // [wavefronts][2][stage_cap]
+    extern __shared__ float4 stage[];  // per wavefront: wave_query_lds(stage_cap) bytes
     // workgroups are dealt round-robin to the 8 XCDs: give each XCD a contiguous node range
     const int nb = gridDim.x, q8 = nb >> 3, rem = nb & 7, x8 = blockIdx.x & 7;
     const int blk = x8 * q8 + (x8 < rem ? x8 : rem) + (blockIdx.x >> 3);
@@ -51,9 +51,12 @@ __global__ void __launch_bounds__(256)
             // is rebuilt
             const SurfaceView sv1 = svs[0];
             if (stage_cap > 0) {
-                float4* lo = stage + (size_t)(threadIdx.x >> 6) * 2 * stage_cap;
-                collide_wave(sv1, lo, lo + stage_cap, stage_cap, valid && w != 0.0f,
-                             sp.restitution, px, py, pz, qx, qy, qz);
+                char* area = reinterpret_cast<char*>(stage) +
+                             (size_t)(threadIdx.x >> 6) * wave_query_lds(stage_cap);
+                float4* lo = reinterpret_cast<float4*>(area);
+                collide_wave(sv1, lo, lo + stage_cap,
+                             reinterpret_cast<uint32_t*>(lo + 2 * stage_cap), stage_cap,
+                             valid && w != 0.0f, sp.restitution, px, py, pz, qx, qy, qz);
             } else if (valid && w != 0.0f) {
                 collide(sv1, sp.restitution, px, py, pz, qx, qy, qz);
             }
@@ -88,7 +91,7 @@ hipError_t launch_substep(const ClothView& cv, int collide, const StepParams& sp
         k_substep<true, true><<<grid, block, 0, stream>>>(cv, sp, xs, vs, xd, vd, svs, node_group,
                                                           0);
     } else if (collide) {
-        const size_t lds = (size_t)(block / 64) * 2 * stage_cap * sizeof(float4);
+        const size_t lds = (size_t)(block / 64) * wave_query_lds(stage_cap);
         k_substep<true, false><<<grid, block, lds, stream>>>(cv, sp, xs, vs, xd, vd, svs, nullptr,
                                                              stage_cap);
     } else {

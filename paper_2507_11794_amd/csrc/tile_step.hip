@@ -80,9 +80,12 @@ __device__ __forceinline__ void run_tile(const TileView& tv, const TileMeta& m, 
             }
             if (collide_here) {
                 if (stage_cap > 0) {
-                    float4* lo = stage + (size_t)(threadIdx.x >> 6) * 2 * stage_cap;
-                    collide_wave(sv, lo, lo + stage_cap, stage_cap, valid && w != 0.0f,
-                                 sp.restitution, px, py, pz, qx, qy, qz);
+                    char* area = reinterpret_cast<char*>(stage) +
+                                 (size_t)(threadIdx.x >> 6) * wave_query_lds(stage_cap);
+                    float4* lo = reinterpret_cast<float4*>(area);
+                    collide_wave(sv, lo, lo + stage_cap,
+                                 reinterpret_cast<uint32_t*>(lo + 2 * stage_cap), stage_cap,
+                                 valid && w != 0.0f, sp.restitution, px, py, pz, qx, qy, qz);
                 } else if (valid && w != 0.0f) {
                     collide(sv, sp.restitution, px, py, pz, qx, qy, qz);
                 }
@@ -136,8 +139,7 @@ __global__ void __launch_bounds__(256)
 }  // namespace
 
 size_t tile_lds_bytes(int rmax, int block, int stage_cap) {
-    return (size_t)12 * sizeof(float) * (size_t)rmax +
-           (size_t)(block / 64) * 2 * (size_t)stage_cap * sizeof(float4);
+    return (size_t)12 * sizeof(float) * (size_t)rmax + (size_t)(block / 64) * wave_query_lds(stage_cap);
 }
 
 hipError_t prepare_tile_kernels(size_t lds_bytes) {
