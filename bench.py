@@ -277,13 +277,13 @@ def parse_launch(text: str) -> dict:
 
 
 SWEEP = [
-    "kernel=direct,stage=0", "kernel=direct,stage=256", "kernel=direct,stage=512",
-    "kernel=direct,stage=1024", "kernel=direct,block=128,stage=512",
-    "kernel=tile,tile=64,K=1,stage=384", "kernel=tile,tile=256,K=1,stage=0",
-    "kernel=tile,tile=256,K=1,stage=384", "kernel=tile,tile=256,K=2,stage=256",
-    "kernel=tile,tile=128,K=2,stage=384", "kernel=tile,tile=256,K=4,stage=256",
-    "kernel=tile,tile=512,K=2,stage=256", "kernel=scatter_f32,stage=384",
-    "kernel=scatter_fix,stage=384",
+    "kernel=direct,stage=0", "kernel=direct,stage=128", "kernel=direct,stage=256",
+    "kernel=direct,stage=384", "kernel=direct,stage=512", "kernel=direct,stage=256,sched=2",
+    "kernel=direct,block=128,stage=256", "kernel=direct,block=128,stage=256,sched=2",
+    "kernel=direct,block=64,stage=256,sched=2",
+    "kernel=tile,tile=64,K=1,stage=256", "kernel=tile,tile=128,K=1,stage=256",
+    "kernel=tile,tile=256,K=1,stage=256", "kernel=tile,tile=128,K=2,stage=256",
+    "kernel=scatter_f32,stage=256", "kernel=scatter_fix,stage=256",
 ]
 
 

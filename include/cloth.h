@@ -96,10 +96,13 @@ typedef struct cloth_launch {
     int substeps_per_launch; /* tile kernel: substeps advanced per launch, 1..8 */
     int block_threads;       /* threads per workgroup: 64, 128, 192 or 256 */
     int use_graph;           /* nonzero: replay launches from a captured hipGraph */
-    int schedule;            /* tile kernel: enum cloth_schedule */
+    int schedule;            /* tile kernel: enum cloth_schedule; one-thread-per-node kernels:
+                                CLOTH_SCHED_GRID gives each XCD a contiguous run of nodes,
+                                CLOTH_SCHED_RR keeps the hardware's round-robin order */
     int workgroups;          /* persistent schedules: number of workgroups (> 0) */
-    int stage_refs;          /* grid references staged in LDS per wavefront for the
-                                collision query, 0..1024 (0 = read them from memory) */
+    int stage_refs;          /* grid reference boxes staged in LDS per wavefront and batch
+                                by the collision query, 0..1024 (0 = each lane reads its
+                                cell's boxes from memory) */
 } cloth_launch;
 
 /*

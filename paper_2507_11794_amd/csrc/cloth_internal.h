@@ -124,10 +124,11 @@ constexpr int kHitSlots = 32;
 constexpr size_t wave_query_lds(int stage_cap) {
     return stage_cap > 0 ? (size_t)stage_cap * 32 + (size_t)kHitSlots * 64 * 4 : 0;
 }
+// xcd_runs: give each XCD a contiguous run of workgroups (else the hardware's order).
 hipError_t launch_substep(const ClothView& cv, int collide, const StepParams& sp, const float* xs,
                           const float* vs, float* xd, float* vd, int block, hipStream_t stream,
                           const SurfaceView* svs, const int* node_group = nullptr,
-                          int stage_cap = 0);
+                          int stage_cap = 0, int xcd_runs = 1);
 // Raise the one-substep kernel's dynamic LDS limit when its stage needs more than 64 KiB.
 hipError_t prepare_substep_kernels(size_t lds_bytes);
 // One substep with spring-centric forces: the spring pass accumulates into F (SoA [3][ld],
@@ -138,7 +139,7 @@ hipError_t launch_scatter_substep(const ClothView& cv, const SpringList& sl, int
                                   const StepParams& sp, float* F, const float* xs,
                                   const float* vs, float* xd, float* vd, int block,
                                   hipStream_t st, const SurfaceView* svs, const int* node_group,
-                                  int stage_cap);
+                                  int stage_cap, int xcd_runs);
 hipError_t prepare_scatter_kernels(size_t lds_bytes);
 
 // Cloth-grid topology for the triangle-triangle narrow phase: order[slot] = node id,

@@ -60,10 +60,12 @@ __global__ void __launch_bounds__(256)
                    const float* __restrict__ xs, const float* __restrict__ vs,
                    float* __restrict__ xd, float* __restrict__ vd,
                    const SurfaceView* __restrict__ svs, const int* __restrict__ node_group,
-                   const int stage_cap) {
+                   const int stage_cap, const int xcd_runs) {
     extern __shared__ float4 stage[];  // per wavefront: wave_query_lds(stage_cap) bytes
+    // workgroups are dealt round-robin to the 8 XCDs: with xcd_runs each XCD gets a
+    // contiguous node range (neighbours share its L2), else the hardware order is kept
     const int nb = gridDim.x, q8 = nb >> 3, rem = nb & 7, x8 = blockIdx.x & 7;
-    const int blk = x8 * q8 + (x8 < rem ? x8 : rem) + (blockIdx.x >> 3);
+    const int blk = xcd_runs ? x8 * q8 + (x8 < rem ? x8 : rem) + (blockIdx.x >> 3) : blockIdx.x;
     const int i = blk * blockDim.x + threadIdx.x;
     const bool valid = i < cv.n;
     const int ld = cv.ld;
@@ -124,18 +126,18 @@ template <bool FIX>
 hipError_t launch_nodes(const ClothView& cv, int collide, const StepParams& sp, float* F,
                         const float* xs, const float* vs, float* xd, float* vd, int block,
                         hipStream_t st, const SurfaceView* svs, const int* node_group,
-                        int stage_cap) {
+                        int stage_cap, int xcd_runs) {
     const int grid = (cv.n + block - 1) / block;
     if (collide && node_group) {
         k_node_scatter<FIX, true, true><<<grid, block, 0, st>>>(cv, sp, F, xs, vs, xd, vd, svs,
-                                                                node_group, 0);
+                                                                node_group, 0, xcd_runs);
     } else if (collide) {
         const size_t lds = (size_t)(block / 64) * wave_query_lds(stage_cap);
         k_node_scatter<FIX, true, false><<<grid, block, lds, st>>>(cv, sp, F, xs, vs, xd, vd, svs,
-                                                                   nullptr, stage_cap);
+                                                                   nullptr, stage_cap, xcd_runs);
     } else {
         k_node_scatter<FIX, false, false><<<grid, block, 0, st>>>(cv, sp, F, xs, vs, xd, vd, svs,
-                                                                  nullptr, 0);
+                                                                  nullptr, 0, xcd_runs);
     }
     return hipGetLastError();
 }
@@ -155,7 +157,7 @@ hipError_t launch_scatter_substep(const ClothView& cv, const SpringList& sl, int
                                   const StepParams& sp, float* F, const float* xs,
                                   const float* vs, float* xd, float* vd, int block,
                                   hipStream_t st, const SurfaceView* svs, const int* node_group,
-                                  int stage_cap) {
+                                  int stage_cap, int xcd_runs) {
     if (cv.n <= 0) return hipSuccess;
     if (block <= 0 || block > 256 || (block & 63)) block = 256;
     if (sl.n > 0) {
@@ -168,9 +170,9 @@ hipError_t launch_scatter_substep(const ClothView& cv, const SpringList& sl, int
         if (e != hipSuccess) return e;
     }
     return fix ? launch_nodes<true>(cv, collide, sp, F, xs, vs, xd, vd, block, st, svs,
-                                    node_group, stage_cap)
+                                    node_group, stage_cap, xcd_runs)
                : launch_nodes<false>(cv, collide, sp, F, xs, vs, xd, vd, block, st, svs,
-                                     node_group, stage_cap);
+                                     node_group, stage_cap, xcd_runs);
 }
 
 }  // namespace cloth

@@ -19,11 +19,12 @@ __global__ void __launch_bounds__(256)
     k_substep(const ClothView cv, const StepParams sp, const float* __restrict__ xs,
               const float* __restrict__ vs, float* __restrict__ xd, float* __restrict__ vd,
               const SurfaceView* __restrict__ svs, const int* __restrict__ node_group,
-              const int stage_cap) {
+              const int stage_cap, const int xcd_runs) {
     extern __shared__ float4 stage[];  // per wavefront: wave_query_lds(stage_cap) bytes
-    // workgroups are dealt round-robin to the 8 XCDs: give each XCD a contiguous node range
+    // workgroups are dealt round-robin to the 8 XCDs: with xcd_runs each XCD gets a
+    // contiguous node range (neighbours share its L2), else the hardware order is kept
     const int nb = gridDim.x, q8 = nb >> 3, rem = nb & 7, x8 = blockIdx.x & 7;
-    const int blk = x8 * q8 + (x8 < rem ? x8 : rem) + (blockIdx.x >> 3);
+    const int blk = xcd_runs ? x8 * q8 + (x8 < rem ? x8 : rem) + (blockIdx.x >> 3) : blockIdx.x;
     const int i = blk * blockDim.x + threadIdx.x;
     const bool valid = i < cv.n;
     const int ld = cv.ld;
@@ -83,20 +84,21 @@ hipError_t prepare_substep_kernels(size_t lds_bytes) {
 
 hipError_t launch_substep(const ClothView& cv, int collide, const StepParams& sp, const float* xs,
                           const float* vs, float* xd, float* vd, int block, hipStream_t stream,
-                          const SurfaceView* svs, const int* node_group, int stage_cap) {
+                          const SurfaceView* svs, const int* node_group, int stage_cap,
+                          int xcd_runs) {
     if (cv.n <= 0) return hipSuccess;
     if (block <= 0 || block > 256 || (block & 63)) block = 256;
     const int grid = (cv.n + block - 1) / block;
     if (collide && node_group) {
         k_substep<true, true><<<grid, block, 0, stream>>>(cv, sp, xs, vs, xd, vd, svs, node_group,
-                                                          0);
+                                                          0, xcd_runs);
     } else if (collide) {
         const size_t lds = (size_t)(block / 64) * wave_query_lds(stage_cap);
         k_substep<true, false><<<grid, block, lds, stream>>>(cv, sp, xs, vs, xd, vd, svs, nullptr,
-                                                             stage_cap);
+                                                             stage_cap, xcd_runs);
     } else {
         k_substep<false, false><<<grid, block, 0, stream>>>(cv, sp, xs, vs, xd, vd, svs, nullptr,
-                                                            0);
+                                                            0, xcd_runs);
     }
     return hipGetLastError();
 }
