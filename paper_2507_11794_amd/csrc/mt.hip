@@ -7,7 +7,10 @@
 //   (B) an edge of t (oriented from the lower vertex id) crosses a cloth triangle at i, or
 //   (C) i's path from its start position to its prediction crosses t.
 // The cloth mesh is the grid's quads split along their (r, c)-(r+1, c+1) diagonals.
-// Candidates come from the grid cells covering the box of i's path, edges and triangles; a
+// Each segment test is preceded by exact-in-principle rejections (the segment's ends strictly
+// on one side of the triangle's plane, or boxes that do not meet), which differ from the
+// full test only at decision boundaries.  Candidates come from the grid cells covering the
+// box of i's path, edges and triangles; a
 // triangle listed in several of those cells is tested only in the first of them (the cell
 // whose coordinates are the maxima of its own and the query's low cells), so each
 // candidate is tested once, in a fixed order.  The response is the averaged push of Alg. 2:
@@ -54,6 +57,23 @@ __device__ __noinline__ bool mt_cross(float3 S, float3 E, float3 V0, float3 V1, 
     if (v < 0.0f || u + v > 1.0f) return false;
     const float t = f * dot3(e2, q);
     return kMtEps < t && t < len;
+}
+
+// False only when a and b are both strictly positive or both strictly negative.
+__device__ __forceinline__ bool straddles(float a, float b) {
+    return !((a > 0.0f && b > 0.0f) || (a < 0.0f && b < 0.0f));
+}
+
+__device__ __forceinline__ bool seg_meets_box(float3 a, float3 b, const float4& lo, const float4& hi) {
+    return fmaxf(a.x, b.x) >= lo.x && fminf(a.x, b.x) <= hi.x && fmaxf(a.y, b.y) >= lo.y &&
+           fminf(a.y, b.y) <= hi.y && fmaxf(a.z, b.z) >= lo.z && fminf(a.z, b.z) <= hi.z;
+}
+
+__device__ __forceinline__ bool tri_meets_box(float3 a, float3 b, float3 c, const float4& lo,
+                                              const float4& hi) {
+    return fmaxf(fmaxf(a.x, b.x), c.x) >= lo.x && fminf(fminf(a.x, b.x), c.x) <= hi.x &&
+           fmaxf(fmaxf(a.y, b.y), c.y) >= lo.y && fminf(fminf(a.y, b.y), c.y) <= hi.y &&
+           fmaxf(fmaxf(a.z, b.z), c.z) >= lo.z && fminf(fminf(a.z, b.z), c.z) <= hi.z;
 }
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -138,9 +158,9 @@ __global__ void __launch_bounds__(256)
                 for (int cy = q0y; cy <= q1y; ++cy)
                     for (int cx = q0x; cx <= q1x; ++cx) {
                         const int cell = (cz * sv.dim[1] + cy) * sv.dim[0] + cx;
-                        const uint32_t b = sv.cell_start[cell], e = sv.cell_start[cell + 1];
+                        const uint32_t b = gmem(sv.cell_start)[cell], e = gmem(sv.cell_start)[cell + 1];
                         for (uint32_t rr = b; rr < e; ++rr) {
-                            const float4 blo = sv.ref_lo[rr], bhi = sv.ref_hi[rr];
+                            const float4 blo = ldg4(sv.ref_lo, rr), bhi = ldg4(sv.ref_hi, rr);
                             if (bhi.x < lo.x || blo.x > hi.x || bhi.y < lo.y || blo.y > hi.y ||
                                 bhi.z < lo.z || blo.z > hi.z)
                                 continue;
@@ -150,34 +170,52 @@ __global__ void __launch_bounds__(256)
                                 max(cell_axis(blo.z, sv.org[2], sv.inv_cell, sv.dim[2]), q0z) != cz)
                                 continue;
                             const uint32_t t = (uint32_t)__float_as_int(blo.w);
-                            const float4 a0 = sv.tri_v[3 * t], a1 = sv.tri_v[3 * t + 1],
-                                         a2 = sv.tri_v[3 * t + 2];
+                            const float4 a0 = ldg4(sv.tri_v, 3 * (size_t)t),
+                                         a1 = ldg4(sv.tri_v, 3 * (size_t)t + 1),
+                                         a2 = ldg4(sv.tri_v, 3 * (size_t)t + 2);
                             const float3 V0 = f3(a0), V1 = f3(a1), V2 = f3(a2);
-                            bool hit = mt_cross(x0, xp, V0, V1, V2);  // (C)
+                            // cheap rejections before each segment test: a crossing needs
+                            // the segment's ends on both sides of (or on) the triangle's
+                            // plane, and the segment's box to meet the triangle's box
+                            const float3 Nt = cross3(sub3(V1, V0), sub3(V2, V0));
+                            const float sp_ = dot3(sub3(xp, V0), Nt);
+                            bool hit = false;
+                            if (straddles(dot3(sub3(x0, V0), Nt), sp_) && seg_meets_box(x0, xp, blo, bhi))
+                                hit = mt_cross(x0, xp, V0, V1, V2);  // (C)
 #pragma unroll
                             for (int k = 0; k < 6; ++k)  // (A)
-                                if (!hit && ok[k])
+                                if (!hit && ok[k] && straddles(sp_, dot3(sub3(q[k], V0), Nt)) &&
+                                    seg_meets_box(xp, q[k], blo, bhi))
                                     hit = id < nid[k] ? mt_cross(xp, q[k], V0, V1, V2)
                                                       : mt_cross(q[k], xp, V0, V1, V2);
                             const float3 Vs[3] = {V0, V1, V2};
                             const int vid[3] = {__float_as_int(a0.w), __float_as_int(a1.w),
                                                 __float_as_int(a2.w)};
 #pragma unroll
-                            for (int z = 0; z < 3; ++z) {  // (B)
-                                const int z1 = z == 2 ? 0 : z + 1;
-                                const bool fwd = vid[z] < vid[z1];
-                                const float3 S = fwd ? Vs[z] : Vs[z1], E = fwd ? Vs[z1] : Vs[z];
+                            for (int k = 0; k < 6; ++k) {  // (B)
+                                if (hit || !tok[k]) continue;
+                                const float3 P0 = vert(T0[k]), P1 = vert(T1[k]), P2 = vert(T2[k]);
+                                if (!tri_meets_box(P0, P1, P2, blo, bhi)) continue;
+                                const float3 Nc = cross3(sub3(P1, P0), sub3(P2, P0));
+                                float sv3[3];
 #pragma unroll
-                                for (int k = 0; k < 6; ++k)
-                                    if (!hit && tok[k])
-                                        hit = mt_cross(S, E, vert(T0[k]), vert(T1[k]), vert(T2[k]));
+                                for (int z = 0; z < 3; ++z) sv3[z] = dot3(sub3(Vs[z], P0), Nc);
+#pragma unroll
+                                for (int z = 0; z < 3; ++z) {
+                                    const int z1 = z == 2 ? 0 : z + 1;
+                                    if (hit || !straddles(sv3[z], sv3[z1])) continue;
+                                    const bool fwd = vid[z] < vid[z1];
+                                    const float3 S = fwd ? Vs[z] : Vs[z1], E = fwd ? Vs[z1] : Vs[z];
+                                    hit = mt_cross(S, E, P0, P1, P2);
+                                }
                             }
                             if (hit) {
                                 if (DEBUG) {
                                     if (cnt < cap) ids[(size_t)p * cap + cnt] = (int)t;
                                 } else {
-                                    const float4 g0 = sv.geo[3 * t], g1 = sv.geo[3 * t + 1],
-                                                 g2 = sv.geo[3 * t + 2];
+                                    const float4 g0 = ldg4(sv.geo, 3 * (size_t)t),
+                                                 g1 = ldg4(sv.geo, 3 * (size_t)t + 1),
+                                                 g2 = ldg4(sv.geo, 3 * (size_t)t + 2);
                                     const float3 n = make_float3(g0.w, g1.w, g2.w);
                                     const float s = dot3(sub3(xp, f3(g0)), n);
                                     const float push = th - s;
