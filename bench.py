@@ -242,7 +242,7 @@ def bench_forces_ab(frames: int = 40):
     out = {"nodes": inp.n_nodes, "springs": inp.n_springs, "frames": frames,
            "substeps_per_frame": inp.n_substeps}
     for text in FORCES_AB:
-        sim.set_launch(**parse_launch(text))
+        sim.set_launch(**{**cloth.launch_dict(cloth.make_launch()), **parse_launch(text)})
         sim.write_state(x0, v0)
         sim.step(n_steps=2)
         sim.write_state(x0, v0)
@@ -301,7 +301,8 @@ def sweep(inp, frames: int = 40):
     for text in SWEEP:
         sim.write_state(x0, v0)
         try:
-            sim.set_launch(**parse_launch(text))
+            # every entry starts from the library's defaults, not from the previous entry
+            sim.set_launch(**{**cloth.launch_dict(cloth.make_launch()), **parse_launch(text)})
         except cloth.ClothError as e:
             print(json.dumps({"sweep": text, "error": str(e)}), flush=True)
             continue
