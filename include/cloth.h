@@ -100,9 +100,10 @@ typedef struct cloth_launch {
                                 CLOTH_SCHED_GRID gives each XCD a contiguous run of nodes,
                                 CLOTH_SCHED_RR keeps the hardware's round-robin order */
     int workgroups;          /* persistent schedules: number of workgroups (> 0) */
-    int stage_refs;          /* grid reference boxes staged in LDS per wavefront and batch
-                                by the collision query, 0..1024 (0 = each lane reads its
-                                cell's boxes from memory) */
+    int hit_slots;           /* collision query: box hits each node lists in LDS before
+                                their geometry is loaded (eight per round), 0..64; 0 = no
+                                list (hits resolved per round of sixteen references); a node
+                                with more hits than slots takes the no-list path */
 } cloth_launch;
 
 /*
@@ -170,7 +171,7 @@ int cloth_info(const cloth_sim* sim, long long* out);
 /*
  * cloth_set_launch / cloth_get_launch -- choose how cloth_step schedules substeps.
  * Default: tile kernel, 256 tile nodes, 1 substep per launch, 256 threads, graphs on,
- * grid schedule, 384 staged references.
+ * grid schedule, 32 hit slots.
  * cloth_set_launch validates the configuration and rebuilds the tile plan if needed
  * (synchronises the handle's stream).  Errors: CLOTH_EINVAL for an out-of-range field or a
  * tile region that does not fit in LDS (the previous configuration stays in effect).

@@ -33,7 +33,7 @@ class ClothError(RuntimeError):
 class cloth_launch(C.Structure):
     _fields_ = [("kernel", C.c_int), ("tile_nodes", C.c_int), ("substeps_per_launch", C.c_int),
                 ("block_threads", C.c_int), ("use_graph", C.c_int), ("schedule", C.c_int),
-                ("workgroups", C.c_int), ("stage_refs", C.c_int)]
+                ("workgroups", C.c_int), ("hit_slots", C.c_int)]
 
 
 CLOTH_KERNEL_TILE, CLOTH_KERNEL_DIRECT = 0, 1
@@ -239,10 +239,10 @@ def cloth_debug_candidates(h, points):
 
 def make_launch(kernel=CLOTH_KERNEL_TILE, tile_nodes=256, substeps_per_launch=1,
                 block_threads=256, use_graph=1, schedule=CLOTH_SCHED_GRID, workgroups=0,
-                stage_refs=384):
+                hit_slots=32):
     return cloth_launch(int(kernel), int(tile_nodes), int(substeps_per_launch),
                         int(block_threads), int(use_graph), int(schedule), int(workgroups),
-                        int(stage_refs))
+                        int(hit_slots))
 
 
 def launch_dict(cfg: cloth_launch) -> dict:

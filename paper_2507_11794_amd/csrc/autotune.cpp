@@ -66,7 +66,7 @@ bool cache_lookup(const std::string& key, cloth_launch* out) {
         std::string k;
         cloth_launch c{};
         if (is >> k >> c.kernel >> c.tile_nodes >> c.substeps_per_launch >> c.block_threads >>
-            c.use_graph >> c.schedule >> c.workgroups >> c.stage_refs) {
+            c.use_graph >> c.schedule >> c.workgroups >> c.hit_slots) {
             if (k == key && check_launch(c) == CLOTH_OK) {
                 *out = c;
                 found = true;  // the last entry for a key wins
@@ -82,12 +82,12 @@ void cache_store(const std::string& key, const cloth_launch& c) {
     std::ofstream f(path, std::ios::app);
     f << key << ' ' << c.kernel << ' ' << c.tile_nodes << ' ' << c.substeps_per_launch << ' '
       << c.block_threads << ' ' << c.use_graph << ' ' << c.schedule << ' ' << c.workgroups << ' '
-      << c.stage_refs << '\n';
+      << c.hit_slots << '\n';
 }
 
 std::vector<cloth_launch> candidates(int cus, bool collide) {
     std::vector<cloth_launch> v;
-    const int stages[] = {0, 256, 512};
+    const int stages[] = {0, 32};
     for (int st : stages) {
         if (!collide && st) continue;
         v.push_back({CLOTH_KERNEL_DIRECT, 256, 1, 256, 1, CLOTH_SCHED_GRID, 0, st});
@@ -100,8 +100,8 @@ std::vector<cloth_launch> candidates(int cus, bool collide) {
             v.push_back({CLOTH_KERNEL_TILE, t[0], t[1], 256, 1, CLOTH_SCHED_GRID, 0, st});
         }
     for (int m : {2, 4}) {
-        v.push_back({CLOTH_KERNEL_TILE, 256, 2, 256, 1, CLOTH_SCHED_LPT, m * cus, collide ? 256 : 0});
-        v.push_back({CLOTH_KERNEL_TILE, 256, 2, 256, 1, CLOTH_SCHED_RR, m * cus, collide ? 256 : 0});
+        v.push_back({CLOTH_KERNEL_TILE, 256, 2, 256, 1, CLOTH_SCHED_LPT, m * cus, collide ? 32 : 0});
+        v.push_back({CLOTH_KERNEL_TILE, 256, 2, 256, 1, CLOTH_SCHED_RR, m * cus, collide ? 32 : 0});
     }
     return v;
 }

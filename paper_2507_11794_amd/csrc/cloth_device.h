@@ -247,8 +247,8 @@ __device__ __forceinline__ int narrow_mask(const SurfaceView& sv, unsigned long 
 // listed in p's cell whose inflated box holds p (ascending id); a candidate is a contact iff
 // the point-triangle distance is < thickness, and visit(n, s, t) is then called with the
 // triangle's unit normal n, the signed plane distance s = (p - A).n and the triangle id t.
-// Reference boxes are loaded eight at a time (the arrays carry eight entries of padding, so
-// the loads need no bounds test).  Returns the contact count.
+// Reference boxes are loaded sixteen at a time (the arrays carry sixteen entries of padding,
+// so the loads need no bounds test).  Returns the contact count.
 template <class Visit>
 __device__ __forceinline__ int contacts_visit(const SurfaceView& sv, float px, float py, float pz,
                                               Visit&& visit) {
@@ -257,16 +257,16 @@ __device__ __forceinline__ int contacts_visit(const SurfaceView& sv, float px, f
     const gptr<uint32_t> cs = gmem(sv.cell_start);
     const uint32_t b = cs[cell], e = cs[cell + 1];
     int cnt = 0;
-    for (uint32_t r = b; r < e; r += 8) {
-        float4 lo[8], hi[8];
+    for (uint32_t r = b; r < e; r += kRefRound) {
+        float4 lo[kRefRound], hi[kRefRound];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < kRefRound; ++q) {
             lo[q] = ldg4(sv.ref_lo, r + q);
             hi[q] = ldg4(sv.ref_hi, r + q);
         }
         unsigned long long mask = 0;
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
+        for (int q = 0; q < kRefRound; ++q)
             if (r + q < e && in_box(lo[q], hi[q], px, py, pz)) mask |= 1ULL << q;
         // a hit's triangle id is re-read from the box just loaded (a cache hit): selecting it
         // from the registers above would make the compiler spill them to scratch
@@ -308,100 +308,34 @@ __device__ __forceinline__ int collide(const SurfaceView& sv, float restitution,
     return cnt;
 }
 
-// Orders LDS writes of some lanes of a wavefront before later LDS reads of other lanes.
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// a3 + a4 for the 64 nodes of a wavefront, cooperatively; every lane of the wavefront must
-// call it (active = the lane holds an unpinned node).  The lanes' distinct grid cells are
-// found by leader election and their reference lists concatenated (M entries).  The list is
-// staged through this wavefront's LDS area in batches of stage_cap boxes, every load of a
-// batch issued before any is used; each lane tests the part of its own cell's range that a
-// batch holds and appends the triangle ids of box hits to its LDS hit list (kHitSlots
-// entries).  The hits' geometry is then loaded eight hits per round.  Hits are visited in
-// ascending triangle id, exactly as contacts_visit does, so both give the same contacts and
-// the same sums; a lane whose hits overflow its list runs contacts_visit instead.  Returns
-// the lane's contact count after applying the response.
-__device__ __forceinline__ int collide_wave(const SurfaceView& sv, float4* stage_lo,
-                                            float4* stage_hi, uint32_t* hit_ids, int stage_cap,
-                                            bool active, float restitution, float& px,
-                                            float& py, float& pz, float& qx, float& qy,
-                                            float& qz) {
-    const int lane = threadIdx.x & 63;
-    const int cell = active ? cell_of(sv, px, py, pz) : -1;
-    unsigned long long pending = __ballot(cell >= 0);
-    if (pending == 0ULL) return 0;
-    int my_u = 0, n_u = 0, ucell = 0;
-    while (pending) {
-        const int leader = __builtin_ctzll(pending);
-        const int c = __shfl(cell, leader);
-        const unsigned long long same = __ballot(cell == c);
-        if (cell == c) my_u = n_u;
-        if (lane == n_u) ucell = c;
-        ++n_u;
-        pending &= ~same;
-    }
+// a3 + a4 with the box hits of the whole cell collected first: the cell's reference boxes
+// are tested kRefRound per round of loads, the triangle ids of hits go to this lane's list
+// in LDS (list[k * 64], k < slots), and the hits' geometry is then loaded eight hits per
+// round, so a node with many box hits waits for few round trips.  Hits are visited in
+// ascending triangle id, exactly as contacts_visit does (same contacts, same sums); a lane
+// with more hits than slots runs contacts_visit instead.  Returns the contact count after
+// applying the response.
+__device__ __forceinline__ int collide_listed(const SurfaceView& sv, uint32_t* list, int slots,
+                                              float restitution, float& px, float& py,
+                                              float& pz, float& qx, float& qy, float& qz) {
+    const int cell = cell_of(sv, px, py, pz);
+    if (cell < 0) return 0;
     const gptr<uint32_t> cs = gmem(sv.cell_start);
-    uint32_t b = 0, cnt = 0;
-    if (lane < n_u) {
-        b = cs[ucell];
-        cnt = cs[ucell + 1] - b;
-    }
-    uint32_t incl = cnt;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t t = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += t;
-    }
-    const uint32_t off = incl - cnt;
-    const uint32_t M = __shfl(incl, 63);
-    const uint32_t my_off = __shfl(off, my_u), my_end = my_off + __shfl(cnt, my_u);
+    const uint32_t b = cs[cell], e = cs[cell + 1];
     int nh = 0;
-    for (uint32_t B0 = 0; B0 < M; B0 += (uint32_t)stage_cap) {
-        const uint32_t nB = min(M - B0, (uint32_t)stage_cap);
-        // stage entries [B0, B0 + nB): entry j lives in the unique cell k whose range
-        // [off_k, off_k + cnt_k) holds it; four entries per lane per round, loads first
-        for (uint32_t j0 = 0; j0 < nB; j0 += 256) {
-            float4 lo[4], hi[4];
+    for (uint32_t r = b; r < e; r += kRefRound) {
+        float4 lo[kRefRound], hi[kRefRound];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint32_t j = B0 + min(j0 + q * 64 + lane, nB - 1);
-                int k = 0;
-#pragma unroll
-                for (int step = 32; step >= 1; step >>= 1) {
-                    const int cand = k + step;
-                    const uint32_t oc = __shfl(off, cand < 64 ? cand : 63);
-                    if (cand < n_u && oc <= j) k = cand;
-                }
-                const uint32_t r = __shfl(b, k) + (j - __shfl(off, k));
-                lo[q] = ldg4(sv.ref_lo, r);
-                hi[q] = ldg4(sv.ref_hi, r);
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint32_t j = j0 + q * 64 + lane;
-                if (j < nB) {
-                    stage_lo[j] = lo[q];
-                    stage_hi[j] = hi[q];
-                }
-            }
+        for (int q = 0; q < kRefRound; ++q) {
+            lo[q] = ldg4(sv.ref_lo, r + q);
+            hi[q] = ldg4(sv.ref_hi, r + q);
         }
-        wave_sync();
-        if (cell >= 0) {
-            const uint32_t r0 = max(my_off, B0), r1 = min(my_end, B0 + nB);
-#pragma unroll 4
-            for (uint32_t r = r0; r < r1; ++r) {
-                const float4 lo = stage_lo[r - B0], hi = stage_hi[r - B0];
-                if (in_box(lo, hi, px, py, pz)) {
-                    if (nh < kHitSlots) hit_ids[nh * 64 + lane] = (uint32_t)__float_as_int(lo.w);
-                    ++nh;
-                }
+#pragma unroll
+        for (int q = 0; q < kRefRound; ++q)
+            if (r + q < e && in_box(lo[q], hi[q], px, py, pz)) {
+                if (nh < slots) list[nh * 64] = (uint32_t)__float_as_int(lo[q].w);
+                ++nh;
             }
-        }
-        wave_sync();  // the stage is refilled by the next batch
     }
     float sx = 0.0f, sy = 0.0f, sz = 0.0f;
     const float th = sv.thickness;
@@ -412,17 +346,26 @@ __device__ __forceinline__ int collide_wave(const SurfaceView& sv, float4* stage
         sz += push * n.z;
     };
     int contacts = 0;
-    if (nh > kHitSlots) {
+    if (nh > slots) {
         contacts = contacts_visit(sv, px, py, pz, accumulate);
     } else {
         for (int h0 = 0; h0 < nh; h0 += 8) {
             const int n = min(nh - h0, 8);
             uint32_t t[8];
+            float4 g[8][3];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) t[q] = hit_ids[min(h0 + q, nh - 1) * 64 + lane];
-            contacts += narrow4(sv, t[0], t[1], t[2], t[3], min(n, 4), px, py, pz, accumulate);
-            if (n > 4)
-                contacts += narrow4(sv, t[4], t[5], t[6], t[7], n - 4, px, py, pz, accumulate);
+            for (int q = 0; q < 8; ++q) t[q] = list[min(h0 + q, nh - 1) * 64];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                g[q][0] = ldg4(sv.geo, 3 * (size_t)t[q]);
+                g[q][1] = ldg4(sv.geo, 3 * (size_t)t[q] + 1);
+                g[q][2] = ldg4(sv.geo, 3 * (size_t)t[q] + 2);
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (q < n)
+                    contacts += narrow_visit(sv, t[q], g[q][0], g[q][1], g[q][2], px, py, pz,
+                                             accumulate);
         }
     }
     respond(contacts, sx, sy, sz, restitution, px, py, pz, qx, qy, qz);

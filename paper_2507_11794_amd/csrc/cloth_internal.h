@@ -107,28 +107,26 @@ struct TileView {
 // collide = 0 skips the collision stage for every cloth (no cloth has a surface).
 hipError_t launch_tiles(const TileView& tv, int K, int collide, const StepParams& sp,
                         const float* xs, const float* vs, float* xd, float* vd, int block,
-                        int stage_cap, hipStream_t stream);
+                        int hit_slots, hipStream_t stream);
 // LDS of one tile workgroup: the region state plus the collision stage of its wavefronts.
-size_t tile_lds_bytes(int rmax, int block = 256, int stage_cap = 0);
+size_t tile_lds_bytes(int rmax, int block = 256, int hit_slots = 0);
 // Raise the tile kernels' dynamic LDS limit when a plan needs more than 64 KiB.
 hipError_t prepare_tile_kernels(size_t lds_bytes);
 
 // a1-a4: one substep for every node (one thread per node).  collide = 0 skips a3/a4.  The
 // surfaces are read on the device: node i's is svs[node_group[i]] with node_group non-NULL
-// (a batch of cloths), otherwise svs[0].  stage_cap: reference boxes staged in LDS per
-// wavefront and batch for the collision query (0 = per-lane queries; at most kMaxStage).
-constexpr int kMaxStage = 1024;
-// Box hits one lane of the wavefront query keeps in LDS before it falls back to the per-lane
-// query, and the LDS bytes one wavefront's query uses: the staged boxes, then the hit lists.
-constexpr int kHitSlots = 32;
-constexpr size_t wave_query_lds(int stage_cap) {
-    return stage_cap > 0 ? (size_t)stage_cap * 32 + (size_t)kHitSlots * 64 * 4 : 0;
-}
+// (a batch of cloths), otherwise svs[0].  hit_slots: length of each lane's LDS list of box
+// hits in the collision query (0 = no list: hits are resolved per round of references; at
+// most kMaxHitSlots).  Reference boxes are tested kRefRound per round of loads.
+constexpr int kMaxHitSlots = 64;
+constexpr int kRefRound = 16;
+// LDS bytes one wavefront's collision query uses for its lanes' hit lists.
+constexpr size_t wave_query_lds(int hit_slots) { return (size_t)hit_slots * 64 * 4; }
 // xcd_runs: give each XCD a contiguous run of workgroups (else the hardware's order).
 hipError_t launch_substep(const ClothView& cv, int collide, const StepParams& sp, const float* xs,
                           const float* vs, float* xd, float* vd, int block, hipStream_t stream,
                           const SurfaceView* svs, const int* node_group = nullptr,
-                          int stage_cap = 0, int xcd_runs = 1);
+                          int hit_slots = 0, int xcd_runs = 1);
 // Raise the one-substep kernel's dynamic LDS limit when its stage needs more than 64 KiB.
 hipError_t prepare_substep_kernels(size_t lds_bytes);
 // One substep with spring-centric forces: the spring pass accumulates into F (SoA [3][ld],
@@ -139,7 +137,7 @@ hipError_t launch_scatter_substep(const ClothView& cv, const SpringList& sl, int
                                   const StepParams& sp, float* F, const float* xs,
                                   const float* vs, float* xd, float* vd, int block,
                                   hipStream_t st, const SurfaceView* svs, const int* node_group,
-                                  int stage_cap, int xcd_runs);
+                                  int hit_slots, int xcd_runs);
 hipError_t prepare_scatter_kernels(size_t lds_bytes);
 
 // Cloth-grid topology for the triangle-triangle narrow phase: order[slot] = node id,

@@ -320,7 +320,7 @@ ClothView ClothDevice::view() const {
     return v;
 }
 
-constexpr size_t kRefPad = 8;
+constexpr size_t kRefPad = kRefRound;
 
 // Uniform grid over the surface: origin fl32(min vertex) - thickness, cells of edge
 // cell_size, dims floor((fl32(max vertex + thickness) - origin) / cell_size) + 1 per axis.
@@ -447,8 +447,8 @@ int rebuild_surface(SurfaceDevice* sd, const float* verts, DeviceArena& arena,
             return hip_fail(e, "hipMalloc grid");
         sd->cap_refs = cap;
     }
-    // kRefPad zero entries after the last reference let the query loop load references in
-    // groups of four without a bounds test (triangle 0 is always a valid index)
+    // kRefPad zero entries after the last reference let the query loop load a round of
+    // references without a bounds test (triangle 0 is always a valid index)
     if ((e = hipMemsetAsync(sd->refs + total, 0, 4 * kRefPad, stream)) ||
         (e = hipMemsetAsync(sd->counts, 0, 4 * C, stream)) ||
         (e = launch_grid_count(T, sd->box_lo, sd->box_hi, sv.org, sv.inv_cell, sv.dim, sd->counts,

@@ -60,8 +60,8 @@ __global__ void __launch_bounds__(256)
                    const float* __restrict__ xs, const float* __restrict__ vs,
                    float* __restrict__ xd, float* __restrict__ vd,
                    const SurfaceView* __restrict__ svs, const int* __restrict__ node_group,
-                   const int stage_cap, const int xcd_runs) {
-    extern __shared__ float4 stage[];  // per wavefront: wave_query_lds(stage_cap) bytes
+                   const int hit_slots, const int xcd_runs) {
+    extern __shared__ uint32_t hit_lds[];  // per wavefront: wave_query_lds(hit_slots) bytes
     // workgroups are dealt round-robin to the 8 XCDs: with xcd_runs each XCD gets a
     // contiguous node range (neighbours share its L2), else the hardware order is kept
     const int nb = gridDim.x, q8 = nb >> 3, rem = nb & 7, x8 = blockIdx.x & 7;
@@ -89,24 +89,14 @@ __global__ void __launch_bounds__(256)
         add_external(sp, i, fx, fy, fz);
         integrate(w, sp.h, sp.g, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz, px, py, pz, qx, qy, qz);
     }
-    if (COLLIDE) {
-        if (GROUPED) {
-            if (valid && w != 0.0f) {
-                const SurfaceView sv = svs[node_group[i]];
-                if (sv.n_tris > 0) collide(sv, sp.restitution, px, py, pz, qx, qy, qz);
-            }
-        } else {
-            const SurfaceView sv1 = svs[0];
-            if (stage_cap > 0) {
-                char* area = reinterpret_cast<char*>(stage) +
-                             (size_t)(threadIdx.x >> 6) * wave_query_lds(stage_cap);
-                float4* lo = reinterpret_cast<float4*>(area);
-                collide_wave(sv1, lo, lo + stage_cap,
-                             reinterpret_cast<uint32_t*>(lo + 2 * stage_cap), stage_cap,
-                             valid && w != 0.0f, sp.restitution, px, py, pz, qx, qy, qz);
-            } else if (valid && w != 0.0f) {
-                collide(sv1, sp.restitution, px, py, pz, qx, qy, qz);
-            }
+    if (COLLIDE && valid && w != 0.0f) {
+        const SurfaceView sv = svs[GROUPED ? node_group[i] : 0];
+        if (sv.n_tris > 0) {
+            if (hit_slots > 0)
+                collide_listed(sv, hit_lds + (threadIdx.x >> 6) * hit_slots * 64 + (threadIdx.x & 63),
+                               hit_slots, sp.restitution, px, py, pz, qx, qy, qz);
+            else
+                collide(sv, sp.restitution, px, py, pz, qx, qy, qz);
         }
     }
     if (!valid) return;
@@ -126,15 +116,15 @@ template <bool FIX>
 hipError_t launch_nodes(const ClothView& cv, int collide, const StepParams& sp, float* F,
                         const float* xs, const float* vs, float* xd, float* vd, int block,
                         hipStream_t st, const SurfaceView* svs, const int* node_group,
-                        int stage_cap, int xcd_runs) {
+                        int hit_slots, int xcd_runs) {
     const int grid = (cv.n + block - 1) / block;
+    const size_t lds = collide ? (size_t)(block / 64) * wave_query_lds(hit_slots) : 0;
     if (collide && node_group) {
-        k_node_scatter<FIX, true, true><<<grid, block, 0, st>>>(cv, sp, F, xs, vs, xd, vd, svs,
-                                                                node_group, 0, xcd_runs);
+        k_node_scatter<FIX, true, true><<<grid, block, lds, st>>>(cv, sp, F, xs, vs, xd, vd, svs,
+                                                                  node_group, hit_slots, xcd_runs);
     } else if (collide) {
-        const size_t lds = (size_t)(block / 64) * wave_query_lds(stage_cap);
         k_node_scatter<FIX, true, false><<<grid, block, lds, st>>>(cv, sp, F, xs, vs, xd, vd, svs,
-                                                                   nullptr, stage_cap, xcd_runs);
+                                                                   nullptr, hit_slots, xcd_runs);
     } else {
         k_node_scatter<FIX, false, false><<<grid, block, 0, st>>>(cv, sp, F, xs, vs, xd, vd, svs,
                                                                   nullptr, 0, xcd_runs);
@@ -146,18 +136,23 @@ hipError_t launch_nodes(const ClothView& cv, int collide, const StepParams& sp, 
 
 hipError_t prepare_scatter_kernels(size_t lds_bytes) {
     if (lds_bytes <= 64 * 1024) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute((const void*)k_node_scatter<false, true, false>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)k_node_scatter<true, true, false>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    const void* fns[] = {(const void*)k_node_scatter<false, true, false>,
+                         (const void*)k_node_scatter<true, true, false>,
+                         (const void*)k_node_scatter<false, true, true>,
+                         (const void*)k_node_scatter<true, true, true>};
+    for (const void* f : fns) {
+        const hipError_t e =
+            hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_scatter_substep(const ClothView& cv, const SpringList& sl, int fix, int collide,
                                   const StepParams& sp, float* F, const float* xs,
                                   const float* vs, float* xd, float* vd, int block,
                                   hipStream_t st, const SurfaceView* svs, const int* node_group,
-                                  int stage_cap, int xcd_runs) {
+                                  int hit_slots, int xcd_runs) {
     if (cv.n <= 0) return hipSuccess;
     if (block <= 0 || block > 256 || (block & 63)) block = 256;
     if (sl.n > 0) {
@@ -170,9 +165,9 @@ hipError_t launch_scatter_substep(const ClothView& cv, const SpringList& sl, int
         if (e != hipSuccess) return e;
     }
     return fix ? launch_nodes<true>(cv, collide, sp, F, xs, vs, xd, vd, block, st, svs,
-                                    node_group, stage_cap, xcd_runs)
+                                    node_group, hit_slots, xcd_runs)
                : launch_nodes<false>(cv, collide, sp, F, xs, vs, xd, vd, block, st, svs,
-                                     node_group, stage_cap, xcd_runs);
+                                     node_group, hit_slots, xcd_runs);
 }
 
 }  // namespace cloth

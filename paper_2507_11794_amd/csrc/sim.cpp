@@ -18,8 +18,8 @@ int check_launch(const cloth_launch& c) {
         return fail(CLOTH_EINVAL, "unknown kernel");
     if (c.block_threads < 64 || c.block_threads > 256 || (c.block_threads & 63))
         return fail(CLOTH_EINVAL, "block_threads must be 64, 128, 192 or 256");
-    if (c.stage_refs < 0 || c.stage_refs > kMaxStage)
-        return fail(CLOTH_EINVAL, "stage_refs must be in 0..1024");
+    if (c.hit_slots < 0 || c.hit_slots > kMaxHitSlots)
+        return fail(CLOTH_EINVAL, "hit_slots must be in 0..64");
     if (c.kernel == CLOTH_KERNEL_TILE) {
         if (c.tile_nodes < 64 || c.tile_nodes > 4096 || (c.tile_nodes & 63))
             return fail(CLOTH_EINVAL, "tile_nodes must be a multiple of 64 in 64..4096");
@@ -125,12 +125,12 @@ int set_launch(cloth_sim* s, const cloth_launch& cfg) {
     s->launch_ready = false;
     if ((st = ensure_plan(s, cfg)) != CLOTH_OK) return st;
     // dynamic LDS of the chosen kernel: check it fits and raise the kernels' limit
-    const int stage = s->any_collision ? cfg.stage_refs : 0;
+    const int slots = s->any_collision ? cfg.hit_slots : 0;
     const size_t lds = cfg.kernel == CLOTH_KERNEL_TILE
-                           ? tile_lds_bytes(s->plan.view.rmax, cfg.block_threads, stage)
-                           : (size_t)(cfg.block_threads / 64) * wave_query_lds(stage);
+                           ? tile_lds_bytes(s->plan.view.rmax, cfg.block_threads, slots)
+                           : (size_t)(cfg.block_threads / 64) * wave_query_lds(slots);
     if (lds > 160 * 1024)
-        return fail(CLOTH_EINVAL, "tile region plus collision stage exceed 160 KiB of LDS");
+        return fail(CLOTH_EINVAL, "tile region plus hit lists exceed 160 KiB of LDS");
     const bool scatter = cfg.kernel == CLOTH_KERNEL_SCATTER_F32 || cfg.kernel == CLOTH_KERNEL_SCATTER_FIX;
     if (scatter && (st = ensure_springs(s)) != CLOTH_OK) return st;
     hipError_t pe = cfg.kernel == CLOTH_KERNEL_TILE ? prepare_tile_kernels(lds)
@@ -170,7 +170,7 @@ hipError_t launch_once(cloth_sim* s, const StepParams& sp, int K, int src, hipSt
     if (s->launch.kernel == CLOTH_KERNEL_TILE)
         return launch_tiles(s->plan.view, K, s->any_collision, sp, s->dev.x[src], s->dev.v[src],
                             s->dev.x[dst], s->dev.v[dst], s->launch.block_threads,
-                            s->launch.stage_refs, st);
+                            s->launch.hit_slots, st);
     if (s->launch.kernel == CLOTH_KERNEL_SCATTER_F32 || s->launch.kernel == CLOTH_KERNEL_SCATTER_FIX)
         return launch_scatter_substep(s->dev.view(), s->springs.view,
                                       s->launch.kernel == CLOTH_KERNEL_SCATTER_FIX,
@@ -178,11 +178,11 @@ hipError_t launch_once(cloth_sim* s, const StepParams& sp, int K, int src, hipSt
                                       s->dev.v[src], s->dev.x[dst], s->dev.v[dst],
                                       s->launch.block_threads, st, s->svs_dev,
                                       s->groups.size() > 1 ? s->node_group_dev : nullptr,
-                                      s->launch.stage_refs, s->launch.schedule != CLOTH_SCHED_RR);
+                                      s->launch.hit_slots, s->launch.schedule != CLOTH_SCHED_RR);
     if (s->groups.size() == 1)
         return launch_substep(s->dev.view(), s->surfs[0].view.n_tris > 0, sp, s->dev.x[src],
                               s->dev.v[src], s->dev.x[dst], s->dev.v[dst], s->launch.block_threads,
-                              st, s->svs_dev, nullptr, s->launch.stage_refs,
+                              st, s->svs_dev, nullptr, s->launch.hit_slots,
                               s->launch.schedule != CLOTH_SCHED_RR);
     return launch_substep(s->dev.view(), s->any_collision, sp, s->dev.x[src], s->dev.v[src],
                           s->dev.x[dst], s->dev.v[dst], s->launch.block_threads, st, s->svs_dev,

@@ -19,8 +19,8 @@ __global__ void __launch_bounds__(256)
     k_substep(const ClothView cv, const StepParams sp, const float* __restrict__ xs,
               const float* __restrict__ vs, float* __restrict__ xd, float* __restrict__ vd,
               const SurfaceView* __restrict__ svs, const int* __restrict__ node_group,
-              const int stage_cap, const int xcd_runs) {
-    extern __shared__ float4 stage[];  // per wavefront: wave_query_lds(stage_cap) bytes
+              const int hit_slots, const int xcd_runs) {
+    extern __shared__ uint32_t hit_lds[];  // per wavefront: wave_query_lds(hit_slots) bytes
     // workgroups are dealt round-robin to the 8 XCDs: with xcd_runs each XCD gets a
     // contiguous node range (neighbours share its L2), else the hardware order is kept
     const int nb = gridDim.x, q8 = nb >> 3, rem = nb & 7, x8 = blockIdx.x & 7;
@@ -41,26 +41,16 @@ __global__ void __launch_bounds__(256)
         integrate(w, sp.h, sp.g, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz, px, py, pz, qx, qy, qz);
     }
     // a3 + a4: broad phase, narrow phase, response
-    if (COLLIDE) {
-        if (GROUPED) {
-            if (valid && w != 0.0f) {
-                const SurfaceView sv = svs[node_group[i]];
-                if (sv.n_tris > 0) collide(sv, sp.restitution, px, py, pz, qx, qy, qz);
-            }
-        } else {
-            // the surface is read from device memory, so captured graphs stay valid when it
-            // is rebuilt
-            const SurfaceView sv1 = svs[0];
-            if (stage_cap > 0) {
-                char* area = reinterpret_cast<char*>(stage) +
-                             (size_t)(threadIdx.x >> 6) * wave_query_lds(stage_cap);
-                float4* lo = reinterpret_cast<float4*>(area);
-                collide_wave(sv1, lo, lo + stage_cap,
-                             reinterpret_cast<uint32_t*>(lo + 2 * stage_cap), stage_cap,
-                             valid && w != 0.0f, sp.restitution, px, py, pz, qx, qy, qz);
-            } else if (valid && w != 0.0f) {
-                collide(sv1, sp.restitution, px, py, pz, qx, qy, qz);
-            }
+    if (COLLIDE && valid && w != 0.0f) {
+        // the surface is read from device memory, so captured graphs stay valid when it is
+        // rebuilt
+        const SurfaceView sv = svs[GROUPED ? node_group[i] : 0];
+        if (sv.n_tris > 0) {
+            if (hit_slots > 0)
+                collide_listed(sv, hit_lds + (threadIdx.x >> 6) * hit_slots * 64 + (threadIdx.x & 63),
+                               hit_slots, sp.restitution, px, py, pz, qx, qy, qz);
+            else
+                collide(sv, sp.restitution, px, py, pz, qx, qy, qz);
         }
     }
     if (!valid) return;
@@ -78,24 +68,27 @@ __global__ void __launch_bounds__(256)
 
 hipError_t prepare_substep_kernels(size_t lds_bytes) {
     if (lds_bytes <= 64 * 1024) return hipSuccess;
-    return hipFuncSetAttribute((const void*)k_substep<true, false>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_substep<true, false>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_substep<true, true>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
 }
 
 hipError_t launch_substep(const ClothView& cv, int collide, const StepParams& sp, const float* xs,
                           const float* vs, float* xd, float* vd, int block, hipStream_t stream,
-                          const SurfaceView* svs, const int* node_group, int stage_cap,
+                          const SurfaceView* svs, const int* node_group, int hit_slots,
                           int xcd_runs) {
     if (cv.n <= 0) return hipSuccess;
     if (block <= 0 || block > 256 || (block & 63)) block = 256;
     const int grid = (cv.n + block - 1) / block;
+    const size_t lds = collide ? (size_t)(block / 64) * wave_query_lds(hit_slots) : 0;
     if (collide && node_group) {
-        k_substep<true, true><<<grid, block, 0, stream>>>(cv, sp, xs, vs, xd, vd, svs, node_group,
-                                                          0, xcd_runs);
+        k_substep<true, true><<<grid, block, lds, stream>>>(cv, sp, xs, vs, xd, vd, svs, node_group,
+                                                            hit_slots, xcd_runs);
     } else if (collide) {
-        const size_t lds = (size_t)(block / 64) * wave_query_lds(stage_cap);
         k_substep<true, false><<<grid, block, lds, stream>>>(cv, sp, xs, vs, xd, vd, svs, nullptr,
-                                                             stage_cap, xcd_runs);
+                                                             hit_slots, xcd_runs);
     } else {
         k_substep<false, false><<<grid, block, 0, stream>>>(cv, sp, xs, vs, xd, vd, svs, nullptr,
                                                             0, xcd_runs);

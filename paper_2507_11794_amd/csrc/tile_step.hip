@@ -17,8 +17,8 @@ template <bool COLLIDE>
 __device__ __forceinline__ void run_tile(const TileView& tv, const TileMeta& m, const int K,
                                          const StepParams& sp, const float* __restrict__ xs,
                                          const float* __restrict__ vs, float* __restrict__ xd,
-                                         float* __restrict__ vd, float* lds, float4* stage,
-                                         int stage_cap) {
+                                         float* __restrict__ vd, float* lds, uint32_t* hit_lds,
+                                         int hit_slots) {
     const int rmax = tv.rmax, ld = tv.ld;
     float* X0 = lds;
     float* X1 = lds + 3 * rmax;
@@ -78,17 +78,13 @@ __device__ __forceinline__ void run_tile(const TileView& tv, const TileMeta& m, 
                 integrate(w, sp.h, sp.g, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz, px, py, pz, qx,
                           qy, qz);
             }
-            if (collide_here) {
-                if (stage_cap > 0) {
-                    char* area = reinterpret_cast<char*>(stage) +
-                                 (size_t)(threadIdx.x >> 6) * wave_query_lds(stage_cap);
-                    float4* lo = reinterpret_cast<float4*>(area);
-                    collide_wave(sv, lo, lo + stage_cap,
-                                 reinterpret_cast<uint32_t*>(lo + 2 * stage_cap), stage_cap,
-                                 valid && w != 0.0f, sp.restitution, px, py, pz, qx, qy, qz);
-                } else if (valid && w != 0.0f) {
+            if (collide_here && valid && w != 0.0f) {
+                if (hit_slots > 0)
+                    collide_listed(sv,
+                                   hit_lds + (threadIdx.x >> 6) * hit_slots * 64 + (threadIdx.x & 63),
+                                   hit_slots, sp.restitution, px, py, pz, qx, qy, qz);
+                else
                     collide(sv, sp.restitution, px, py, pz, qx, qy, qz);
-                }
             }
             if (valid) {
                 Xd[u] = px;
@@ -124,22 +120,22 @@ template <bool COLLIDE>
 __global__ void __launch_bounds__(256)
     k_tile(const TileView tv, const int K, const StepParams sp, const float* __restrict__ xs,
            const float* __restrict__ vs, float* __restrict__ xd, float* __restrict__ vd,
-           const int stage_cap) {
+           const int hit_slots) {
     extern __shared__ float4 lds4[];
     float* lds = reinterpret_cast<float*>(lds4);
-    float4* stage = lds4 + 3 * (size_t)tv.rmax;  // after 12 * rmax floats of state
+    uint32_t* hit_lds = reinterpret_cast<uint32_t*>(lds4 + 3 * (size_t)tv.rmax);  // after the state
     const int b0 = tv.item_ptr[blockIdx.x], b1 = tv.item_ptr[blockIdx.x + 1];
     for (int it = b0; it < b1; ++it) {
         const TileMeta& m = tv.meta[tv.items[it]];
-        run_tile<COLLIDE>(tv, m, K, sp, xs, vs, xd, vd, lds, stage, stage_cap);
+        run_tile<COLLIDE>(tv, m, K, sp, xs, vs, xd, vd, lds, hit_lds, hit_slots);
         __syncthreads();  // LDS is reused by the next tile
     }
 }
 
 }  // namespace
 
-size_t tile_lds_bytes(int rmax, int block, int stage_cap) {
-    return (size_t)12 * sizeof(float) * (size_t)rmax + (size_t)(block / 64) * wave_query_lds(stage_cap);
+size_t tile_lds_bytes(int rmax, int block, int hit_slots) {
+    return (size_t)12 * sizeof(float) * (size_t)rmax + (size_t)(block / 64) * wave_query_lds(hit_slots);
 }
 
 hipError_t prepare_tile_kernels(size_t lds_bytes) {
@@ -153,14 +149,14 @@ hipError_t prepare_tile_kernels(size_t lds_bytes) {
 
 hipError_t launch_tiles(const TileView& tv, int K, int collide, const StepParams& sp,
                         const float* xs, const float* vs, float* xd, float* vd, int block,
-                        int stage_cap, hipStream_t stream) {
+                        int hit_slots, hipStream_t stream) {
     if (tv.n_tiles <= 0 || tv.n_workgroups <= 0) return hipSuccess;
     if (block <= 0 || block > 256 || (block & 63)) block = 256;
-    if (!collide) stage_cap = 0;
-    const size_t lds = tile_lds_bytes(tv.rmax, block, stage_cap);
+    if (!collide) hit_slots = 0;
+    const size_t lds = tile_lds_bytes(tv.rmax, block, hit_slots);
     if (collide)
         k_tile<true><<<tv.n_workgroups, block, lds, stream>>>(tv, K, sp, xs, vs, xd, vd,
-                                                              stage_cap);
+                                                              hit_slots);
     else
         k_tile<false><<<tv.n_workgroups, block, lds, stream>>>(tv, K, sp, xs, vs, xd, vd, 0);
     return hipGetLastError();

@@ -110,8 +110,8 @@ LAUNCHES = [
     dict(kernel=B.CLOTH_KERNEL_TILE, use_graph=1),
     dict(kernel=B.CLOTH_KERNEL_TILE, use_graph=1, substeps_per_launch=2, tile_nodes=128),
     dict(kernel=B.CLOTH_KERNEL_DIRECT, use_graph=0),
-    dict(kernel=B.CLOTH_KERNEL_DIRECT, use_graph=1, stage_refs=0),
-    dict(kernel=B.CLOTH_KERNEL_DIRECT, use_graph=1, stage_refs=256),
+    dict(kernel=B.CLOTH_KERNEL_DIRECT, use_graph=1, hit_slots=0),
+    dict(kernel=B.CLOTH_KERNEL_DIRECT, use_graph=1, hit_slots=16),
 ]
 
 
