@@ -264,7 +264,7 @@ def parse_launch(text: str) -> dict:
 
     cfg = {}
     names = {"tile": "tile_nodes", "K": "substeps_per_launch", "block": "block_threads",
-             "graph": "use_graph", "hits": "hit_slots", "sched": "schedule", "wg": "workgroups"}
+             "graph": "use_graph", "hits": "hit_slots", "xcd": "xcd_runs", "sched": "schedule", "wg": "workgroups"}
     for part in filter(None, text.split(",")):
         k, v = part.split("=")
         if k == "kernel":
@@ -277,12 +277,10 @@ def parse_launch(text: str) -> dict:
 
 
 SWEEP = [
-    "kernel=direct,hits=0", "kernel=direct,hits=16", "kernel=direct,hits=32",
-    "kernel=direct,hits=32,sched=2", "kernel=direct,block=128,hits=32",
-    "kernel=direct,block=64,hits=32", "kernel=direct,block=64,hits=32,sched=2",
-    "kernel=tile,tile=64,K=1,hits=32", "kernel=tile,tile=128,K=1,hits=32",
-    "kernel=tile,tile=256,K=1,hits=32", "kernel=tile,tile=256,K=1,hits=0",
-    "kernel=tile,tile=128,K=2,hits=32", "kernel=scatter_f32,hits=32", "kernel=scatter_fix,hits=32",
+    "kernel=direct", "kernel=direct,hits=0", "kernel=direct,hits=24", "kernel=direct,hits=48",
+    "kernel=direct,xcd=1", "kernel=direct,block=128", "kernel=direct,block=256",
+    "kernel=tile,tile=128,K=1", "kernel=tile,tile=256,K=1", "kernel=tile,tile=256,K=1,hits=0",
+    "kernel=tile,tile=128,K=2", "kernel=scatter_f32", "kernel=scatter_fix",
 ]
 
 

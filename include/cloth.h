@@ -96,14 +96,15 @@ typedef struct cloth_launch {
     int substeps_per_launch; /* tile kernel: substeps advanced per launch, 1..8 */
     int block_threads;       /* threads per workgroup: 64, 128, 192 or 256 */
     int use_graph;           /* nonzero: replay launches from a captured hipGraph */
-    int schedule;            /* tile kernel: enum cloth_schedule; one-thread-per-node kernels:
-                                CLOTH_SCHED_GRID gives each XCD a contiguous run of nodes,
-                                CLOTH_SCHED_RR keeps the hardware's round-robin order */
+    int schedule;            /* tile kernel: enum cloth_schedule */
     int workgroups;          /* persistent schedules: number of workgroups (> 0) */
     int hit_slots;           /* collision query: box hits each node lists in LDS before
                                 their geometry is loaded (eight per round), 0..64; 0 = no
                                 list (hits resolved per round of sixteen references); a node
                                 with more hits than slots takes the no-list path */
+    int xcd_runs;            /* one-thread-per-node kernels: nonzero gives each of the 8 XCDs
+                                a contiguous run of workgroups (nodes), 0 keeps the
+                                hardware's round-robin order */
 } cloth_launch;
 
 /*
@@ -170,8 +171,9 @@ int cloth_info(const cloth_sim* sim, long long* out);
 
 /*
  * cloth_set_launch / cloth_get_launch -- choose how cloth_step schedules substeps.
- * Default: tile kernel, 256 tile nodes, 1 substep per launch, 256 threads, graphs on,
- * grid schedule, 32 hit slots.
+ * Default: one-thread-per-node kernel, 64 threads per workgroup in the hardware's
+ * round-robin order, graphs on, 32 hit slots (tile fields: 256 nodes, 1 substep, grid
+ * schedule).
  * cloth_set_launch validates the configuration and rebuilds the tile plan if needed
  * (synchronises the handle's stream).  Errors: CLOTH_EINVAL for an out-of-range field or a
  * tile region that does not fit in LDS (the previous configuration stays in effect).

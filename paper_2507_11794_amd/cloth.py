@@ -33,7 +33,8 @@ class ClothError(RuntimeError):
 class cloth_launch(C.Structure):
     _fields_ = [("kernel", C.c_int), ("tile_nodes", C.c_int), ("substeps_per_launch", C.c_int),
                 ("block_threads", C.c_int), ("use_graph", C.c_int), ("schedule", C.c_int),
-                ("workgroups", C.c_int), ("hit_slots", C.c_int)]
+                ("workgroups", C.c_int), ("hit_slots", C.c_int),
+                ("xcd_runs", C.c_int)]
 
 
 CLOTH_KERNEL_TILE, CLOTH_KERNEL_DIRECT = 0, 1
@@ -237,12 +238,12 @@ def cloth_debug_candidates(h, points):
     return pairs[:n.value].copy()
 
 
-def make_launch(kernel=CLOTH_KERNEL_TILE, tile_nodes=256, substeps_per_launch=1,
-                block_threads=256, use_graph=1, schedule=CLOTH_SCHED_GRID, workgroups=0,
-                hit_slots=32):
+def make_launch(kernel=CLOTH_KERNEL_DIRECT, tile_nodes=256, substeps_per_launch=1,
+                block_threads=64, use_graph=1, schedule=CLOTH_SCHED_GRID, workgroups=0,
+                hit_slots=32, xcd_runs=0):
     return cloth_launch(int(kernel), int(tile_nodes), int(substeps_per_launch),
                         int(block_threads), int(use_graph), int(schedule), int(workgroups),
-                        int(hit_slots))
+                        int(hit_slots), int(xcd_runs))
 
 
 def launch_dict(cfg: cloth_launch) -> dict:

@@ -139,7 +139,7 @@ int set_launch(cloth_sim* s, const cloth_launch& cfg) {
     if (pe != hipSuccess) return hip_fail(pe, "kernel LDS attribute");
     cloth_launch norm = cfg;
     if (cfg.kernel != CLOTH_KERNEL_TILE) {
-        norm.schedule = cfg.schedule == CLOTH_SCHED_RR ? CLOTH_SCHED_RR : CLOTH_SCHED_GRID;
+        norm.schedule = CLOTH_SCHED_GRID;
         norm.workgroups = 0;
     }
     if (std::memcmp(&norm, &s->launch, sizeof(cloth_launch)) != 0) {
@@ -178,15 +178,15 @@ hipError_t launch_once(cloth_sim* s, const StepParams& sp, int K, int src, hipSt
                                       s->dev.v[src], s->dev.x[dst], s->dev.v[dst],
                                       s->launch.block_threads, st, s->svs_dev,
                                       s->groups.size() > 1 ? s->node_group_dev : nullptr,
-                                      s->launch.hit_slots, s->launch.schedule != CLOTH_SCHED_RR);
+                                      s->launch.hit_slots, s->launch.xcd_runs != 0);
     if (s->groups.size() == 1)
         return launch_substep(s->dev.view(), s->surfs[0].view.n_tris > 0, sp, s->dev.x[src],
                               s->dev.v[src], s->dev.x[dst], s->dev.v[dst], s->launch.block_threads,
                               st, s->svs_dev, nullptr, s->launch.hit_slots,
-                              s->launch.schedule != CLOTH_SCHED_RR);
+                              s->launch.xcd_runs != 0);
     return launch_substep(s->dev.view(), s->any_collision, sp, s->dev.x[src], s->dev.v[src],
                           s->dev.x[dst], s->dev.v[dst], s->launch.block_threads, st, s->svs_dev,
-                          s->node_group_dev, 0, s->launch.schedule != CLOTH_SCHED_RR);
+                          s->node_group_dev, 0, s->launch.xcd_runs != 0);
 }
 
 // A captured graph of `chunk` (even) launches of K substeps starting from buffer `parity`.

@@ -79,7 +79,7 @@ struct cloth_sim {
     cloth::SpringDevice springs;
     long long plan_version = 0;
     std::vector<cloth::GraphEntry> graphs;
-    cloth_launch launch{CLOTH_KERNEL_TILE, 256, 1, 256, 1, CLOTH_SCHED_GRID, 0, 32};
+    cloth_launch launch{CLOTH_KERNEL_DIRECT, 256, 1, 64, 1, CLOTH_SCHED_GRID, 0, 32, 0};
     bool launch_ready = false;  // plan, schedule and LDS limits match `launch`
     int* nan_flag = nullptr;
     // host copies kept for the stability bound and parameter updates (caller numbering)
