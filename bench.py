@@ -220,7 +220,7 @@ def bench_mt(frames: int = 30):
             "node_updates_per_s": inp.n_nodes * inp.n_substeps * frames / (ms * 1e-3)}
 
 
-FORCES_AB = ["kernel=direct", "kernel=tile,tile=256,K=1", "kernel=tile,tile=256,K=4",
+FORCES_AB = ["kernel=direct", "kernel=tile,tile=256,K=1,block=256", "kernel=tile,tile=256,K=4,block=256",
              "kernel=scatter_f32", "kernel=scatter_fix"]
 
 
@@ -279,8 +279,9 @@ def parse_launch(text: str) -> dict:
 SWEEP = [
     "kernel=direct", "kernel=direct,hits=0", "kernel=direct,hits=24", "kernel=direct,hits=48",
     "kernel=direct,xcd=1", "kernel=direct,block=128", "kernel=direct,block=256",
-    "kernel=tile,tile=128,K=1", "kernel=tile,tile=256,K=1", "kernel=tile,tile=256,K=1,hits=0",
-    "kernel=tile,tile=128,K=2", "kernel=scatter_f32", "kernel=scatter_fix",
+    "kernel=tile,tile=128,K=1,block=256", "kernel=tile,tile=256,K=1,block=256",
+    "kernel=tile,tile=256,K=1,block=256,hits=0", "kernel=tile,tile=128,K=2,block=256",
+    "kernel=scatter_f32", "kernel=scatter_fix",
 ]
 
 
@@ -335,6 +336,36 @@ def calibrate_copy(mib: int, reps: int = 5):
     torch.cuda.synchronize()
     print(json.dumps({"calibrate_copy_bytes_read": n * 4, "bytes_written": n * 4, "reps": reps}))
     return 0
+
+
+def sources_sha256() -> str:
+    """Hash of the HIP library's sources (file names and contents, sorted)."""
+    import glob
+    import hashlib
+
+    csrc = os.path.join(ROOT, "paper_2507_11794_amd", "csrc")
+    files = sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h")) +
+                   glob.glob(os.path.join(csrc, "*.cpp")))
+    h = hashlib.sha256()
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def counter_traffic(launch: dict):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE counter summary, if it
+    was taken on these kernel sources with this launch configuration; else None."""
+    path = os.path.join(ROOT, "profiles", "k_substep_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("sources_sha256") != sources_sha256():
+        return None
+    if any(launch.get(k) != v for k, v in rec.get("launch", {}).items()):
+        return None
+    return rec.get("traffic_bytes_per_launch")
 
 
 def algorithmic_bytes_per_substep(n_nodes: int, n_springs: int) -> float:
@@ -443,7 +474,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": counter_traffic(launch),
             "bytes_per_launch": bps,
             "avg_launch_us": kernel_s * 1e6,
         },

@@ -216,11 +216,15 @@ def test_every_launch_configuration_is_bit_identical(scene):
     assert moved > 0.01
 
 
-def test_tile_kernel_default_matches_oracle_one_substep():
+@pytest.mark.parametrize("kernel", [B.CLOTH_KERNEL_DIRECT, B.CLOTH_KERNEL_TILE])
+def test_default_and_tile_kernels_match_oracle_one_substep(kernel):
     inp = W.config1(n=96, freq=24)
     model = oracle.Model.from_inputs(inp)
     with B.Cloth(inp) as sim:
-        assert sim.get_launch()["kernel"] == B.CLOTH_KERNEL_TILE
+        if kernel == B.CLOTH_KERNEL_DIRECT:
+            assert sim.get_launch()["kernel"] == B.CLOTH_KERNEL_DIRECT  # the default
+        else:
+            sim.set_launch(kernel=kernel, block_threads=256)
         sim.step(n_steps=120)
         for _ in range(3):
             x, v = sim.read_state()
