@@ -264,7 +264,7 @@ def parse_launch(text: str) -> dict:
 
     cfg = {}
     names = {"tile": "tile_nodes", "K": "substeps_per_launch", "block": "block_threads",
-             "graph": "use_graph", "hits": "hit_slots", "xcd": "xcd_runs", "sched": "schedule", "wg": "workgroups"}
+             "graph": "use_graph", "hits": "hit_slots", "xcd": "xcd_runs", "split": "split_refs", "sched": "schedule", "wg": "workgroups"}
     for part in filter(None, text.split(",")):
         k, v = part.split("=")
         if k == "kernel":
@@ -277,10 +277,10 @@ def parse_launch(text: str) -> dict:
 
 
 SWEEP = [
-    "kernel=direct", "kernel=direct,hits=0", "kernel=direct,hits=24", "kernel=direct,hits=48",
-    "kernel=direct,xcd=1", "kernel=direct,block=128", "kernel=direct,block=256",
+    "kernel=direct", "kernel=direct,split=0", "kernel=direct,split=24", "kernel=direct,split=32",
+    "kernel=direct,split=64", "kernel=direct,split=96", "kernel=direct,split=32,block=128",
+    "kernel=direct,split=32,hits=48", "kernel=direct,split=0,hits=0",
     "kernel=tile,tile=128,K=1,block=256", "kernel=tile,tile=256,K=1,block=256",
-    "kernel=tile,tile=256,K=1,block=256,hits=0", "kernel=tile,tile=128,K=2,block=256",
     "kernel=scatter_f32", "kernel=scatter_fix",
 ]
 

@@ -34,7 +34,7 @@ class cloth_launch(C.Structure):
     _fields_ = [("kernel", C.c_int), ("tile_nodes", C.c_int), ("substeps_per_launch", C.c_int),
                 ("block_threads", C.c_int), ("use_graph", C.c_int), ("schedule", C.c_int),
                 ("workgroups", C.c_int), ("hit_slots", C.c_int),
-                ("xcd_runs", C.c_int)]
+                ("xcd_runs", C.c_int), ("split_refs", C.c_int)]
 
 
 CLOTH_KERNEL_TILE, CLOTH_KERNEL_DIRECT = 0, 1
@@ -240,10 +240,10 @@ def cloth_debug_candidates(h, points):
 
 def make_launch(kernel=CLOTH_KERNEL_DIRECT, tile_nodes=256, substeps_per_launch=1,
                 block_threads=64, use_graph=1, schedule=CLOTH_SCHED_GRID, workgroups=0,
-                hit_slots=32, xcd_runs=0):
+                hit_slots=32, xcd_runs=0, split_refs=48):
     return cloth_launch(int(kernel), int(tile_nodes), int(substeps_per_launch),
                         int(block_threads), int(use_graph), int(schedule), int(workgroups),
-                        int(hit_slots), int(xcd_runs))
+                        int(hit_slots), int(xcd_runs), int(split_refs))
 
 
 def launch_dict(cfg: cloth_launch) -> dict:

@@ -66,7 +66,7 @@ bool cache_lookup(const std::string& key, cloth_launch* out) {
         std::string k;
         cloth_launch c{};
         if (is >> k >> c.kernel >> c.tile_nodes >> c.substeps_per_launch >> c.block_threads >>
-            c.use_graph >> c.schedule >> c.workgroups >> c.hit_slots >> c.xcd_runs) {
+            c.use_graph >> c.schedule >> c.workgroups >> c.hit_slots >> c.xcd_runs >> c.split_refs) {
             if (k == key && check_launch(c) == CLOTH_OK) {
                 *out = c;
                 found = true;  // the last entry for a key wins
@@ -82,7 +82,7 @@ void cache_store(const std::string& key, const cloth_launch& c) {
     std::ofstream f(path, std::ios::app);
     f << key << ' ' << c.kernel << ' ' << c.tile_nodes << ' ' << c.substeps_per_launch << ' '
       << c.block_threads << ' ' << c.use_graph << ' ' << c.schedule << ' ' << c.workgroups << ' '
-      << c.hit_slots << ' ' << c.xcd_runs << '\n';
+      << c.hit_slots << ' ' << c.xcd_runs << ' ' << c.split_refs << '\n';
 }
 
 std::vector<cloth_launch> candidates(int cus, bool collide) {
@@ -91,17 +91,21 @@ std::vector<cloth_launch> candidates(int cus, bool collide) {
     for (int st : stages) {
         if (!collide && st) continue;
         for (int bt : {64, 128, 256})
-            for (int xr : {0, 1}) v.push_back({CLOTH_KERNEL_DIRECT, 256, 1, bt, 1, CLOTH_SCHED_GRID, 0, st, xr});
+            for (int xr : {0, 1})
+                for (int sr : {0, 48}) {
+                    if (!collide && sr) continue;
+                    v.push_back({CLOTH_KERNEL_DIRECT, 256, 1, bt, 1, CLOTH_SCHED_GRID, 0, st, xr, sr});
+                }
     }
     const int tk[][2] = {{64, 1}, {256, 1}, {128, 2}, {256, 2}, {128, 4}, {256, 4}, {512, 4}};
     for (const auto& t : tk)
         for (int st : stages) {
             if (!collide && st) continue;
-            v.push_back({CLOTH_KERNEL_TILE, t[0], t[1], 256, 1, CLOTH_SCHED_GRID, 0, st, 0});
+            v.push_back({CLOTH_KERNEL_TILE, t[0], t[1], 256, 1, CLOTH_SCHED_GRID, 0, st, 0, 0});
         }
     for (int m : {2, 4}) {
-        v.push_back({CLOTH_KERNEL_TILE, 256, 2, 256, 1, CLOTH_SCHED_LPT, m * cus, collide ? 32 : 0, 0});
-        v.push_back({CLOTH_KERNEL_TILE, 256, 2, 256, 1, CLOTH_SCHED_RR, m * cus, collide ? 32 : 0, 0});
+        v.push_back({CLOTH_KERNEL_TILE, 256, 2, 256, 1, CLOTH_SCHED_LPT, m * cus, collide ? 32 : 0, 0, 0});
+        v.push_back({CLOTH_KERNEL_TILE, 256, 2, 256, 1, CLOTH_SCHED_RR, m * cus, collide ? 32 : 0, 0, 0});
     }
     return v;
 }
@@ -114,7 +118,7 @@ int autotune_sim(cloth_sim* s, float dt, int n_substeps, int frames, cloth_launc
     const float h = dt / (float)n_substeps;
     char hex[32];
     std::snprintf(hex, sizeof(hex), "%016llx", (unsigned long long)workload_hash(s, h, n_substeps));
-    const std::string key = device_key() + ":v2:" + hex;
+    const std::string key = device_key() + ":v3:" + hex;
     cloth_launch chosen;
     if (cache_lookup(key, &chosen)) {
         int st = set_launch(s, chosen);

@@ -20,6 +20,7 @@ int check_launch(const cloth_launch& c) {
         return fail(CLOTH_EINVAL, "block_threads must be 64, 128, 192 or 256");
     if (c.hit_slots < 0 || c.hit_slots > kMaxHitSlots)
         return fail(CLOTH_EINVAL, "hit_slots must be in 0..64");
+    if (c.split_refs < 0) return fail(CLOTH_EINVAL, "split_refs must be >= 0");
     if (c.kernel == CLOTH_KERNEL_TILE) {
         if (c.tile_nodes < 64 || c.tile_nodes > 4096 || (c.tile_nodes & 63))
             return fail(CLOTH_EINVAL, "tile_nodes must be a multiple of 64 in 64..4096");
@@ -133,6 +134,10 @@ int set_launch(cloth_sim* s, const cloth_launch& cfg) {
         return fail(CLOTH_EINVAL, "tile region plus hit lists exceed 160 KiB of LDS");
     const bool scatter = cfg.kernel == CLOTH_KERNEL_SCATTER_F32 || cfg.kernel == CLOTH_KERNEL_SCATTER_FIX;
     if (scatter && (st = ensure_springs(s)) != CLOTH_OK) return st;
+    if (cfg.kernel == CLOTH_KERNEL_DIRECT && cfg.split_refs > 0 && !s->heavy_dev) {
+        hipError_t e = s->arena.alloc(&s->heavy_dev, (size_t)s->dev.ld);
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc second-pass flags");
+    }
     hipError_t pe = cfg.kernel == CLOTH_KERNEL_TILE ? prepare_tile_kernels(lds)
                     : scatter                       ? prepare_scatter_kernels(lds)
                                                     : prepare_substep_kernels(lds);
@@ -142,6 +147,7 @@ int set_launch(cloth_sim* s, const cloth_launch& cfg) {
         norm.schedule = CLOTH_SCHED_GRID;
         norm.workgroups = 0;
     }
+    if (cfg.kernel != CLOTH_KERNEL_DIRECT) norm.split_refs = 0;
     if (std::memcmp(&norm, &s->launch, sizeof(cloth_launch)) != 0) {
         // captured graphs hold the old configuration's kernels and arguments
         hipError_t e = hipStreamSynchronize(s->stream);
@@ -183,10 +189,11 @@ hipError_t launch_once(cloth_sim* s, const StepParams& sp, int K, int src, hipSt
         return launch_substep(s->dev.view(), s->surfs[0].view.n_tris > 0, sp, s->dev.x[src],
                               s->dev.v[src], s->dev.x[dst], s->dev.v[dst], s->launch.block_threads,
                               st, s->svs_dev, nullptr, s->launch.hit_slots,
-                              s->launch.xcd_runs != 0);
+                              s->launch.xcd_runs != 0, s->launch.split_refs, s->heavy_dev);
     return launch_substep(s->dev.view(), s->any_collision, sp, s->dev.x[src], s->dev.v[src],
                           s->dev.x[dst], s->dev.v[dst], s->launch.block_threads, st, s->svs_dev,
-                          s->node_group_dev, 0, s->launch.xcd_runs != 0);
+                          s->node_group_dev, s->launch.hit_slots, s->launch.xcd_runs != 0,
+                          s->launch.split_refs, s->heavy_dev);
 }
 
 // A captured graph of `chunk` (even) launches of K substeps starting from buffer `parity`.

@@ -79,7 +79,8 @@ struct cloth_sim {
     cloth::SpringDevice springs;
     long long plan_version = 0;
     std::vector<cloth::GraphEntry> graphs;
-    cloth_launch launch{CLOTH_KERNEL_DIRECT, 256, 1, 64, 1, CLOTH_SCHED_GRID, 0, 32, 0};
+    cloth_launch launch{CLOTH_KERNEL_DIRECT, 256, 1, 64, 1, CLOTH_SCHED_GRID, 0, 32, 0, 48};
+    int* heavy_dev = nullptr;  // per-node flags of the second pass (allocated on first use)
     bool launch_ready = false;  // plan, schedule and LDS limits match `launch`
     int* nan_flag = nullptr;
     // host copies kept for the stability bound and parameter updates (caller numbering)

@@ -19,7 +19,8 @@ __global__ void __launch_bounds__(256)
     k_substep(const ClothView cv, const StepParams sp, const float* __restrict__ xs,
               const float* __restrict__ vs, float* __restrict__ xd, float* __restrict__ vd,
               const SurfaceView* __restrict__ svs, const int* __restrict__ node_group,
-              const int hit_slots, const int xcd_runs) {
+              const int hit_slots, const int xcd_runs, const int split_refs,
+              int* __restrict__ heavy) {
     extern __shared__ uint32_t hit_lds[];  // per wavefront: wave_query_lds(hit_slots) bytes
     // workgroups are dealt round-robin to the 8 XCDs: with xcd_runs each XCD gets a
     // contiguous node range (neighbours share its L2), else the hardware order is kept
@@ -41,11 +42,21 @@ __global__ void __launch_bounds__(256)
         integrate(w, sp.h, sp.g, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz, px, py, pz, qx, qy, qz);
     }
     // a3 + a4: broad phase, narrow phase, response
+    int is_heavy = 0;
     if (COLLIDE && valid && w != 0.0f) {
         // the surface is read from device memory, so captured graphs stay valid when it is
         // rebuilt
         const SurfaceView sv = svs[GROUPED ? node_group[i] : 0];
-        if (sv.n_tris > 0) {
+        if (sv.n_tris > 0 && split_refs > 0) {
+            // a node whose cell lists more than split_refs references is left to the
+            // four-lane second pass (its prediction is written below)
+            const int cell = cell_of(sv, px, py, pz);
+            if (cell >= 0) {
+                const gptr<uint32_t> cs = gmem(sv.cell_start);
+                is_heavy = cs[cell + 1] - cs[cell] > (uint32_t)split_refs;
+            }
+        }
+        if (sv.n_tris > 0 && !is_heavy) {
             if (hit_slots > 0)
                 collide_listed(sv, hit_lds + (threadIdx.x >> 6) * hit_slots * 64 + (threadIdx.x & 63),
                                hit_slots, sp.restitution, px, py, pz, qx, qy, qz);
@@ -54,6 +65,7 @@ __global__ void __launch_bounds__(256)
         }
     }
     if (!valid) return;
+    if (split_refs > 0) heavy[i] = is_heavy;
     xd[i] = px;
     xd[ld + i] = py;
     xd[2 * ld + i] = pz;
@@ -78,22 +90,25 @@ hipError_t prepare_substep_kernels(size_t lds_bytes) {
 hipError_t launch_substep(const ClothView& cv, int collide, const StepParams& sp, const float* xs,
                           const float* vs, float* xd, float* vd, int block, hipStream_t stream,
                           const SurfaceView* svs, const int* node_group, int hit_slots,
-                          int xcd_runs) {
+                          int xcd_runs, int split_refs, int* heavy) {
     if (cv.n <= 0) return hipSuccess;
     if (block <= 0 || block > 256 || (block & 63)) block = 256;
     const int grid = (cv.n + block - 1) / block;
+    if (!collide || !heavy) split_refs = 0;
     const size_t lds = collide ? (size_t)(block / 64) * wave_query_lds(hit_slots) : 0;
     if (collide && node_group) {
         k_substep<true, true><<<grid, block, lds, stream>>>(cv, sp, xs, vs, xd, vd, svs, node_group,
-                                                            hit_slots, xcd_runs);
+                                                            hit_slots, xcd_runs, split_refs, heavy);
     } else if (collide) {
         k_substep<true, false><<<grid, block, lds, stream>>>(cv, sp, xs, vs, xd, vd, svs, nullptr,
-                                                             hit_slots, xcd_runs);
+                                                             hit_slots, xcd_runs, split_refs, heavy);
     } else {
         k_substep<false, false><<<grid, block, 0, stream>>>(cv, sp, xs, vs, xd, vd, svs, nullptr,
-                                                            0, xcd_runs);
+                                                            0, xcd_runs, 0, nullptr);
     }
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && split_refs > 0) e = launch_heavy(cv, sp, heavy, xd, vd, svs, node_group, stream);
+    return e;
 }
 
 }  // namespace cloth

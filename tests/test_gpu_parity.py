@@ -183,8 +183,10 @@ def test_nan_flag_reported():
 
 
 LAUNCHES = [
-    dict(kernel=B.CLOTH_KERNEL_DIRECT, block_threads=64, use_graph=0),
-    dict(kernel=B.CLOTH_KERNEL_DIRECT, block_threads=256, use_graph=1, hit_slots=0),
+    dict(kernel=B.CLOTH_KERNEL_DIRECT, block_threads=64, use_graph=0, split_refs=0),
+    dict(kernel=B.CLOTH_KERNEL_DIRECT, block_threads=256, use_graph=1, hit_slots=0, split_refs=0),
+    dict(kernel=B.CLOTH_KERNEL_DIRECT, block_threads=64, use_graph=1, split_refs=8),
+    dict(kernel=B.CLOTH_KERNEL_DIRECT, block_threads=128, use_graph=0, split_refs=1, hit_slots=2),
     dict(kernel=B.CLOTH_KERNEL_DIRECT, block_threads=128, use_graph=1, hit_slots=4, xcd_runs=1),
     dict(kernel=B.CLOTH_KERNEL_TILE, tile_nodes=64, substeps_per_launch=1, use_graph=0),
     dict(kernel=B.CLOTH_KERNEL_TILE, tile_nodes=256, substeps_per_launch=2, use_graph=1),
