@@ -123,17 +123,24 @@ constexpr int kRefRound = 16;
 // LDS bytes one wavefront's collision query uses for its lanes' hit lists.
 constexpr size_t wave_query_lds(int hit_slots) { return (size_t)hit_slots * 64 * 4; }
 // xcd_runs: give each XCD a contiguous run of workgroups (else the hardware's order).
-// split_refs > 0 (with heavy, an int per node): nodes whose cell lists more than split_refs
-// references are resolved by a second launch with four lanes per node (launch_heavy).
+// split_refs > 0: nodes whose cell lists more than split_refs references are resolved by a
+// second launch with four lanes per node (launch_heavy).  heavy holds two counters, then two
+// node lists of ld entries at kHeavyListOff; the first pass appends to list `parity`, the
+// second pass reads it and clears the other parity's counter for the next substep, so
+// consecutive substeps (alternating buffers) alternate lists.  Both counters must be zero when
+// the scheme starts (heavy_words() ints in all).
+constexpr int kHeavyListOff = 64;
+constexpr size_t heavy_words(int ld) { return kHeavyListOff + 2 * (size_t)ld; }
 hipError_t launch_substep(const ClothView& cv, int collide, const StepParams& sp, const float* xs,
                           const float* vs, float* xd, float* vd, int block, hipStream_t stream,
                           const SurfaceView* svs, const int* node_group = nullptr,
                           int hit_slots = 0, int xcd_runs = 1, int split_refs = 0,
-                          int* heavy = nullptr);
-// The second pass: heavy[i] != 0 marks node i; its prediction is in (xd, vd) and is replaced
-// by the collision-resolved state.
-hipError_t launch_heavy(const ClothView& cv, const StepParams& sp, const int* heavy, float* xd,
-                        float* vd, const SurfaceView* svs, const int* node_group, hipStream_t st);
+                          int* heavy = nullptr, int parity = 0);
+// The second pass over list `parity` of heavy (see launch_substep): each listed node's
+// prediction is in (xd, vd) and is replaced by the collision-resolved state.
+hipError_t launch_heavy(const ClothView& cv, const StepParams& sp, int* heavy, int parity,
+                        float* xd, float* vd, const SurfaceView* svs, const int* node_group,
+                        hipStream_t st);
 // Raise the one-substep kernel's dynamic LDS limit when its stage needs more than 64 KiB.
 hipError_t prepare_substep_kernels(size_t lds_bytes);
 // One substep with spring-centric forces: the spring pass accumulates into F (SoA [3][ld],

@@ -134,9 +134,14 @@ int set_launch(cloth_sim* s, const cloth_launch& cfg) {
         return fail(CLOTH_EINVAL, "tile region plus hit lists exceed 160 KiB of LDS");
     const bool scatter = cfg.kernel == CLOTH_KERNEL_SCATTER_F32 || cfg.kernel == CLOTH_KERNEL_SCATTER_FIX;
     if (scatter && (st = ensure_springs(s)) != CLOTH_OK) return st;
-    if (cfg.kernel == CLOTH_KERNEL_DIRECT && cfg.split_refs > 0 && !s->heavy_dev) {
-        hipError_t e = s->arena.alloc(&s->heavy_dev, (size_t)s->dev.ld);
-        if (e != hipSuccess) return hip_fail(e, "hipMalloc second-pass flags");
+    if (cfg.kernel == CLOTH_KERNEL_DIRECT && cfg.split_refs > 0) {
+        // the second pass's node lists; both counters start at zero
+        hipError_t e = hipSuccess;
+        if (!s->heavy_dev) e = s->arena.alloc(&s->heavy_dev, heavy_words(s->dev.ld));
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(s->heavy_dev, 0, 2 * sizeof(int), s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return hip_fail(e, "second-pass lists");
     }
     hipError_t pe = cfg.kernel == CLOTH_KERNEL_TILE ? prepare_tile_kernels(lds)
                     : scatter                       ? prepare_scatter_kernels(lds)
@@ -189,11 +194,11 @@ hipError_t launch_once(cloth_sim* s, const StepParams& sp, int K, int src, hipSt
         return launch_substep(s->dev.view(), s->surfs[0].view.n_tris > 0, sp, s->dev.x[src],
                               s->dev.v[src], s->dev.x[dst], s->dev.v[dst], s->launch.block_threads,
                               st, s->svs_dev, nullptr, s->launch.hit_slots,
-                              s->launch.xcd_runs != 0, s->launch.split_refs, s->heavy_dev);
+                              s->launch.xcd_runs != 0, s->launch.split_refs, s->heavy_dev, src);
     return launch_substep(s->dev.view(), s->any_collision, sp, s->dev.x[src], s->dev.v[src],
                           s->dev.x[dst], s->dev.v[dst], s->launch.block_threads, st, s->svs_dev,
                           s->node_group_dev, s->launch.hit_slots, s->launch.xcd_runs != 0,
-                          s->launch.split_refs, s->heavy_dev);
+                          s->launch.split_refs, s->heavy_dev, src);
 }
 
 // A captured graph of `chunk` (even) launches of K substeps starting from buffer `parity`.

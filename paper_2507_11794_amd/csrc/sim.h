@@ -80,7 +80,7 @@ struct cloth_sim {
     long long plan_version = 0;
     std::vector<cloth::GraphEntry> graphs;
     cloth_launch launch{CLOTH_KERNEL_DIRECT, 256, 1, 64, 1, CLOTH_SCHED_GRID, 0, 32, 0, 48};
-    int* heavy_dev = nullptr;  // per-node flags of the second pass (allocated on first use)
+    int* heavy_dev = nullptr;  // the second pass's counters and node lists (first use)
     bool launch_ready = false;  // plan, schedule and LDS limits match `launch`
     int* nan_flag = nullptr;
     // host copies kept for the stability bound and parameter updates (caller numbering)

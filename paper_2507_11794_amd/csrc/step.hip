@@ -20,7 +20,7 @@ __global__ void __launch_bounds__(256)
               const float* __restrict__ vs, float* __restrict__ xd, float* __restrict__ vd,
               const SurfaceView* __restrict__ svs, const int* __restrict__ node_group,
               const int hit_slots, const int xcd_runs, const int split_refs,
-              int* __restrict__ heavy) {
+              int* __restrict__ heavy, const int parity) {
     extern __shared__ uint32_t hit_lds[];  // per wavefront: wave_query_lds(hit_slots) bytes
     // workgroups are dealt round-robin to the 8 XCDs: with xcd_runs each XCD gets a
     // contiguous node range (neighbours share its L2), else the hardware order is kept
@@ -64,8 +64,19 @@ __global__ void __launch_bounds__(256)
                 collide(sv, sp.restitution, px, py, pz, qx, qy, qz);
         }
     }
+    if (split_refs > 0) {
+        // append the wavefront's heavy nodes to this parity's list, one atomic per wavefront
+        const unsigned long long m = __ballot(is_heavy != 0);
+        if (m) {
+            const int lane = threadIdx.x & 63, leader = __builtin_ctzll(m);
+            int base = 0;
+            if (lane == leader) base = atomicAdd(heavy + parity, __popcll(m));
+            base = __shfl(base, leader);
+            const int pos = base + __popcll(m & ((1ULL << lane) - 1ULL));
+            if (is_heavy && pos < cv.ld) heavy[kHeavyListOff + (size_t)parity * cv.ld + pos] = i;
+        }
+    }
     if (!valid) return;
-    if (split_refs > 0) heavy[i] = is_heavy;
     xd[i] = px;
     xd[ld + i] = py;
     xd[2 * ld + i] = pz;
@@ -90,7 +101,7 @@ hipError_t prepare_substep_kernels(size_t lds_bytes) {
 hipError_t launch_substep(const ClothView& cv, int collide, const StepParams& sp, const float* xs,
                           const float* vs, float* xd, float* vd, int block, hipStream_t stream,
                           const SurfaceView* svs, const int* node_group, int hit_slots,
-                          int xcd_runs, int split_refs, int* heavy) {
+                          int xcd_runs, int split_refs, int* heavy, int parity) {
     if (cv.n <= 0) return hipSuccess;
     if (block <= 0 || block > 256 || (block & 63)) block = 256;
     const int grid = (cv.n + block - 1) / block;
@@ -98,16 +109,17 @@ hipError_t launch_substep(const ClothView& cv, int collide, const StepParams& sp
     const size_t lds = collide ? (size_t)(block / 64) * wave_query_lds(hit_slots) : 0;
     if (collide && node_group) {
         k_substep<true, true><<<grid, block, lds, stream>>>(cv, sp, xs, vs, xd, vd, svs, node_group,
-                                                            hit_slots, xcd_runs, split_refs, heavy);
+                                                            hit_slots, xcd_runs, split_refs, heavy, parity);
     } else if (collide) {
         k_substep<true, false><<<grid, block, lds, stream>>>(cv, sp, xs, vs, xd, vd, svs, nullptr,
-                                                             hit_slots, xcd_runs, split_refs, heavy);
+                                                             hit_slots, xcd_runs, split_refs, heavy, parity);
     } else {
         k_substep<false, false><<<grid, block, 0, stream>>>(cv, sp, xs, vs, xd, vd, svs, nullptr,
-                                                            0, xcd_runs, 0, nullptr);
+                                                            0, xcd_runs, 0, nullptr, 0);
     }
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess && split_refs > 0) e = launch_heavy(cv, sp, heavy, xd, vd, svs, node_group, stream);
+    if (e == hipSuccess && split_refs > 0)
+        e = launch_heavy(cv, sp, heavy, parity, xd, vd, svs, node_group, stream);
     return e;
 }
 
