@@ -277,7 +277,7 @@ def parse_launch(text: str) -> dict:
 
 
 SWEEP = [
-    "kernel=direct", "kernel=direct,split=0", "kernel=direct,split=24", "kernel=direct,split=32",
+    "kernel=direct,split=0", "kernel=direct,split=16", "kernel=direct,split=24", "kernel=direct,split=32", "kernel=direct,split=48",
     "kernel=direct,split=64", "kernel=direct,split=96", "kernel=direct,split=32,block=128",
     "kernel=direct,split=32,hits=48", "kernel=direct,split=0,hits=0",
     "kernel=tile,tile=128,K=1,block=256", "kernel=tile,tile=256,K=1,block=256",

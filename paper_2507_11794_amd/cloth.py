@@ -240,7 +240,7 @@ def cloth_debug_candidates(h, points):
 
 def make_launch(kernel=CLOTH_KERNEL_DIRECT, tile_nodes=256, substeps_per_launch=1,
                 block_threads=64, use_graph=1, schedule=CLOTH_SCHED_GRID, workgroups=0,
-                hit_slots=32, xcd_runs=0, split_refs=48):
+                hit_slots=32, xcd_runs=0, split_refs=0):
     return cloth_launch(int(kernel), int(tile_nodes), int(substeps_per_launch),
                         int(block_threads), int(use_graph), int(schedule), int(workgroups),
                         int(hit_slots), int(xcd_runs), int(split_refs))

@@ -79,7 +79,7 @@ struct cloth_sim {
     cloth::SpringDevice springs;
     long long plan_version = 0;
     std::vector<cloth::GraphEntry> graphs;
-    cloth_launch launch{CLOTH_KERNEL_DIRECT, 256, 1, 64, 1, CLOTH_SCHED_GRID, 0, 32, 0, 48};
+    cloth_launch launch{CLOTH_KERNEL_DIRECT, 256, 1, 64, 1, CLOTH_SCHED_GRID, 0, 32, 0, 0};
     int* heavy_dev = nullptr;  // the second pass's counters and node lists (first use)
     bool launch_ready = false;  // plan, schedule and LDS limits match `launch`
     int* nan_flag = nullptr;
