@@ -277,9 +277,10 @@ def parse_launch(text: str) -> dict:
 
 
 SWEEP = [
-    "kernel=direct,split=0", "kernel=direct,split=16", "kernel=direct,split=24", "kernel=direct,split=32", "kernel=direct,split=48",
-    "kernel=direct,split=64", "kernel=direct,split=96", "kernel=direct,split=32,block=128",
-    "kernel=direct,split=32,hits=48", "kernel=direct,split=0,hits=0",
+    "kernel=direct", "kernel=direct,xcd=1", "kernel=direct,xcd=2", "kernel=direct,xcd=4",
+    "kernel=direct,xcd=8", "kernel=direct,xcd=16", "kernel=direct,xcd=32", "kernel=direct,xcd=64",
+    "kernel=direct,block=128,xcd=8", "kernel=direct,block=256,xcd=4", "kernel=direct,split=48",
+    "kernel=direct,hits=48", "kernel=direct,hits=0",
     "kernel=tile,tile=128,K=1,block=256", "kernel=tile,tile=256,K=1,block=256",
     "kernel=scatter_f32", "kernel=scatter_fix",
 ]

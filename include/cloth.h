@@ -99,12 +99,14 @@ typedef struct cloth_launch {
     int schedule;            /* tile kernel: enum cloth_schedule */
     int workgroups;          /* persistent schedules: number of workgroups (> 0) */
     int hit_slots;           /* collision query: box hits each node lists in LDS before
-                                their geometry is loaded (eight per round), 0..64; 0 = no
+                                their geometry is loaded (twelve per round), 0..64; 0 = no
                                 list (hits resolved per round of sixteen references); a node
                                 with more hits than slots takes the no-list path */
-    int xcd_runs;            /* one-thread-per-node kernels: nonzero gives each of the 8 XCDs
-                                a contiguous run of workgroups (nodes), 0 keeps the
-                                hardware's round-robin order */
+    int xcd_runs;            /* one-thread-per-node kernels, 0..4096: how workgroups (node
+                                ranges) map to the 8 XCDs, each with its own L2.  0 keeps
+                                the hardware's round-robin order; 1 gives each XCD one
+                                contiguous run; k >= 2 deals chunks of k consecutive
+                                workgroups to the XCDs in turn */
     int split_refs;          /* one-thread-per-node kernel: nodes whose grid cell lists more
                                 than split_refs references are finished by a second launch
                                 with four lanes per node (same results); 0 = off */

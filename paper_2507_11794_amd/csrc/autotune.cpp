@@ -91,7 +91,7 @@ std::vector<cloth_launch> candidates(int cus, bool collide) {
     for (int st : stages) {
         if (!collide && st) continue;
         for (int bt : {64, 128, 256})
-            for (int xr : {0, 1})
+            for (int xr : {0, 1, 16})
                 for (int sr : {0, 48}) {
                     if (!collide && sr) continue;
                     v.push_back({CLOTH_KERNEL_DIRECT, 256, 1, bt, 1, CLOTH_SCHED_GRID, 0, st, xr, sr});
@@ -118,7 +118,7 @@ int autotune_sim(cloth_sim* s, float dt, int n_substeps, int frames, cloth_launc
     const float h = dt / (float)n_substeps;
     char hex[32];
     std::snprintf(hex, sizeof(hex), "%016llx", (unsigned long long)workload_hash(s, h, n_substeps));
-    const std::string key = device_key() + ":v3:" + hex;
+    const std::string key = device_key() + ":v4:" + hex;
     cloth_launch chosen;
     if (cache_lookup(key, &chosen)) {
         int st = set_launch(s, chosen);

@@ -24,6 +24,23 @@ __device__ __forceinline__ float4 ldg4(const float4* p, size_t i) {
     return make_float4(v.x, v.y, v.z, v.w);
 }
 
+// Logical workgroup of this workgroup.  The hardware deals workgroup b to XCD b mod 8, and
+// each XCD has its own L2.  xcd_runs = 0 keeps that order; 1 gives each XCD one contiguous
+// run of the logical workgroups; k >= 2 deals chunks of k consecutive logical workgroups to
+// the XCDs in turn (XCD x holds chunks x, x + 8, ...), so an XCD's nodes are spatially
+// coherent pieces spread over the whole cloth.  For k >= 2 the grid is padded to a multiple
+// of 8k (xcd_grid) and a padding workgroup gets n_logical, i.e. no valid node.
+__device__ __forceinline__ int xcd_block(int xcd_runs, int n_logical) {
+    const int b = blockIdx.x, x8 = b & 7, j = b >> 3;
+    if (xcd_runs == 0) return b;
+    if (xcd_runs == 1) {
+        const int q8 = n_logical >> 3, rem = n_logical & 7;
+        return x8 * q8 + (x8 < rem ? x8 : rem) + j;
+    }
+    const int blk = ((j / xcd_runs) * 8 + x8) * xcd_runs + j % xcd_runs;
+    return blk < n_logical ? blk : n_logical;
+}
+
 // Unclamped grid coordinate of one axis, floor((p - org) * inv_cell) in FP32.  Monotone
 // non-decreasing in p (each FP32 operation rounds to nearest and floor is monotone), so a
 // triangle registered in the cells cell(lo)..cell(hi) of its inflated box is found from
@@ -118,37 +135,46 @@ __device__ __forceinline__ void gather_global(const ClothView& cv, const float* 
 __device__ __forceinline__ float point_tri_dist2(float apx, float apy, float apz, float e1x,
                                                  float e1y, float e1z, float e2x, float e2y,
                                                  float e2z, float s) {
-    float d1 = e1x * apx + e1y * apy + e1z * apz;
-    float d2 = e2x * apx + e2y * apy + e2z * apz;
-    if (d1 <= 0.0f && d2 <= 0.0f) return apx * apx + apy * apy + apz * apz;  // vertex A
-    float bpx = apx - e1x, bpy = apy - e1y, bpz = apz - e1z;                  // p - B
-    float d3 = e1x * bpx + e1y * bpy + e1z * bpz;
-    float d4 = e2x * bpx + e2y * bpy + e2z * bpz;
-    if (d3 >= 0.0f && d4 <= d3) return bpx * bpx + bpy * bpy + bpz * bpz;  // vertex B
-    float vc = d1 * d4 - d3 * d2;
-    if (vc <= 0.0f && d1 >= 0.0f && d3 <= 0.0f) {  // edge AB
-        float t = d1 / (d1 - d3);
-        float qx = apx - t * e1x, qy = apy - t * e1y, qz = apz - t * e1z;
-        return qx * qx + qy * qy + qz * qz;
-    }
-    float cpx = apx - e2x, cpy = apy - e2y, cpz = apz - e2z;  // p - C
-    float d5 = e1x * cpx + e1y * cpy + e1z * cpz;
-    float d6 = e2x * cpx + e2y * cpy + e2z * cpz;
-    if (d6 >= 0.0f && d5 <= d6) return cpx * cpx + cpy * cpy + cpz * cpz;  // vertex C
-    float vb = d5 * d2 - d1 * d6;
-    if (vb <= 0.0f && d2 >= 0.0f && d6 <= 0.0f) {  // edge AC
-        float t = d2 / (d2 - d6);
-        float qx = apx - t * e2x, qy = apy - t * e2y, qz = apz - t * e2z;
-        return qx * qx + qy * qy + qz * qz;
-    }
-    float va = d3 * d6 - d5 * d4;
-    if (va <= 0.0f && (d4 - d3) >= 0.0f && (d5 - d6) >= 0.0f) {  // edge BC
-        float t = (d4 - d3) / ((d4 - d3) + (d5 - d6));
-        // q = B + t (C - B);  p - q = bp - t (e2 - e1)
-        float qx = bpx - t * (e2x - e1x), qy = bpy - t * (e2y - e1y), qz = bpz - t * (e2z - e1z);
-        return qx * qx + qy * qy + qz * qz;
-    }
-    return s * s;  // face region: distance to the plane
+    // Every region's quantities are computed and the region is picked by selects in the
+    // order A, B, AB, C, AC, BC, face, so lanes of a wavefront never diverge.  The closest
+    // point is base - t * dir: (ap, 0, 0) for A, (bp, 0, 0) for B, (cp, 0, 0) for C,
+    // (ap, t, e1) for AB, (ap, t, e2) for AC, (bp, t, C - B) for BC; with t = 0 the
+    // difference is base itself, exactly.
+    const float d1 = e1x * apx + e1y * apy + e1z * apz;
+    const float d2 = e2x * apx + e2y * apy + e2z * apz;
+    const float bpx = apx - e1x, bpy = apy - e1y, bpz = apz - e1z;  // p - B
+    const float d3 = e1x * bpx + e1y * bpy + e1z * bpz;
+    const float d4 = e2x * bpx + e2y * bpy + e2z * bpz;
+    const float cpx = apx - e2x, cpy = apy - e2y, cpz = apz - e2z;  // p - C
+    const float d5 = e1x * cpx + e1y * cpy + e1z * cpz;
+    const float d6 = e2x * cpx + e2y * cpy + e2z * cpz;
+    const float vc = d1 * d4 - d3 * d2;
+    const float vb = d5 * d2 - d1 * d6;
+    const float va = d3 * d6 - d5 * d4;
+    const float d43 = d4 - d3, d56 = d5 - d6;
+    const bool rA = d1 <= 0.0f && d2 <= 0.0f;
+    const bool rB = !rA && d3 >= 0.0f && d4 <= d3;
+    bool done = rA || rB;
+    const bool rAB = !done && vc <= 0.0f && d1 >= 0.0f && d3 <= 0.0f;
+    done = done || rAB;
+    const bool rC = !done && d6 >= 0.0f && d5 <= d6;
+    done = done || rC;
+    const bool rAC = !done && vb <= 0.0f && d2 >= 0.0f && d6 <= 0.0f;
+    done = done || rAC;
+    const bool rBC = !done && va <= 0.0f && d43 >= 0.0f && d56 >= 0.0f;
+    done = done || rBC;
+    const float num = rAB ? d1 : rAC ? d2 : rBC ? d43 : 0.0f;
+    const float den = rAB ? d1 - d3 : rAC ? d2 - d6 : rBC ? d43 + d56 : 1.0f;
+    const float t = num / den;
+    const bool onB = rB || rBC;
+    const float bx = onB ? bpx : rC ? cpx : apx;
+    const float by = onB ? bpy : rC ? cpy : apy;
+    const float bz = onB ? bpz : rC ? cpz : apz;
+    const float dx = rAB ? e1x : rAC ? e2x : rBC ? e2x - e1x : 0.0f;
+    const float dy = rAB ? e1y : rAC ? e2y : rBC ? e2y - e1y : 0.0f;
+    const float dz = rAB ? e1z : rAC ? e2z : rBC ? e2z - e1z : 0.0f;
+    const float qx = bx - t * dx, qy = by - t * dy, qz = bz - t * dz;
+    return done ? qx * qx + qy * qy + qz * qz : s * s;  // else the face region: plane distance
 }
 
 // External force of the node in internal slot `slot`, added to its spring-force sum.
@@ -349,20 +375,20 @@ __device__ __forceinline__ int collide_listed(const SurfaceView& sv, uint32_t* l
     if (nh > slots) {
         contacts = contacts_visit(sv, px, py, pz, accumulate);
     } else {
-        for (int h0 = 0; h0 < nh; h0 += 8) {
-            const int n = min(nh - h0, 8);
-            uint32_t t[8];
-            float4 g[8][3];
+        for (int h0 = 0; h0 < nh; h0 += kHitRound) {
+            const int n = min(nh - h0, kHitRound);
+            uint32_t t[kHitRound];
+            float4 g[kHitRound][3];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) t[q] = list[min(h0 + q, nh - 1) * 64];
+            for (int q = 0; q < kHitRound; ++q) t[q] = list[min(h0 + q, nh - 1) * 64];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
+            for (int q = 0; q < kHitRound; ++q) {
                 g[q][0] = ldg4(sv.geo, 3 * (size_t)t[q]);
                 g[q][1] = ldg4(sv.geo, 3 * (size_t)t[q] + 1);
                 g[q][2] = ldg4(sv.geo, 3 * (size_t)t[q] + 2);
             }
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
+            for (int q = 0; q < kHitRound; ++q)
                 if (q < n)
                     contacts += narrow_visit(sv, t[q], g[q][0], g[q][1], g[q][2], px, py, pz,
                                              accumulate);

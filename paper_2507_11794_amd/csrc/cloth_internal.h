@@ -119,7 +119,17 @@ hipError_t prepare_tile_kernels(size_t lds_bytes);
 // hits in the collision query (0 = no list: hits are resolved per round of references; at
 // most kMaxHitSlots).  Reference boxes are tested kRefRound per round of loads.
 constexpr int kMaxHitSlots = 64;
+constexpr int kMaxXcdRuns = 4096;
 constexpr int kRefRound = 16;
+constexpr int kHitRound = 12;  // box hits whose geometry is loaded per round
+
+// Grid size of a one-thread-per-node launch of n_logical workgroups under xcd_runs (see
+// xcd_block): padded to a multiple of 8 * xcd_runs when xcd_runs >= 2.
+inline int xcd_grid(int n_logical, int xcd_runs) {
+    if (xcd_runs < 2) return n_logical;
+    const long long c = 8LL * xcd_runs;
+    return (int)((n_logical + c - 1) / c * c);
+}
 // LDS bytes one wavefront's collision query uses for its lanes' hit lists.
 constexpr size_t wave_query_lds(int hit_slots) { return (size_t)hit_slots * 64 * 4; }
 // xcd_runs: give each XCD a contiguous run of workgroups (else the hardware's order).

@@ -62,11 +62,8 @@ __global__ void __launch_bounds__(256)
                    const SurfaceView* __restrict__ svs, const int* __restrict__ node_group,
                    const int hit_slots, const int xcd_runs) {
     extern __shared__ uint32_t hit_lds[];  // per wavefront: wave_query_lds(hit_slots) bytes
-    // workgroups are dealt round-robin to the 8 XCDs: with xcd_runs each XCD gets a
-    // contiguous node range (neighbours share its L2), else the hardware order is kept
-    const int nb = gridDim.x, q8 = nb >> 3, rem = nb & 7, x8 = blockIdx.x & 7;
-    const int blk = xcd_runs ? x8 * q8 + (x8 < rem ? x8 : rem) + (blockIdx.x >> 3) : blockIdx.x;
-    const int i = blk * blockDim.x + threadIdx.x;
+    const int i = xcd_block(xcd_runs, (cv.n + blockDim.x - 1) / blockDim.x) * blockDim.x +
+                  threadIdx.x;
     const bool valid = i < cv.n;
     const int ld = cv.ld;
     float px = 0.0f, py = 0.0f, pz = 0.0f, qx = 0.0f, qy = 0.0f, qz = 0.0f, w = 0.0f;
@@ -117,7 +114,8 @@ hipError_t launch_nodes(const ClothView& cv, int collide, const StepParams& sp, 
                         const float* xs, const float* vs, float* xd, float* vd, int block,
                         hipStream_t st, const SurfaceView* svs, const int* node_group,
                         int hit_slots, int xcd_runs) {
-    const int grid = (cv.n + block - 1) / block;
+    if (xcd_runs < 0 || xcd_runs > kMaxXcdRuns) xcd_runs = 0;
+    const int grid = xcd_grid((cv.n + block - 1) / block, xcd_runs);
     const size_t lds = collide ? (size_t)(block / 64) * wave_query_lds(hit_slots) : 0;
     if (collide && node_group) {
         k_node_scatter<FIX, true, true><<<grid, block, lds, st>>>(cv, sp, F, xs, vs, xd, vd, svs,

@@ -21,6 +21,8 @@ int check_launch(const cloth_launch& c) {
     if (c.hit_slots < 0 || c.hit_slots > kMaxHitSlots)
         return fail(CLOTH_EINVAL, "hit_slots must be in 0..64");
     if (c.split_refs < 0) return fail(CLOTH_EINVAL, "split_refs must be >= 0");
+    if (c.xcd_runs < 0 || c.xcd_runs > kMaxXcdRuns)
+        return fail(CLOTH_EINVAL, "xcd_runs must be in 0..4096");
     if (c.kernel == CLOTH_KERNEL_TILE) {
         if (c.tile_nodes < 64 || c.tile_nodes > 4096 || (c.tile_nodes & 63))
             return fail(CLOTH_EINVAL, "tile_nodes must be a multiple of 64 in 64..4096");
@@ -189,15 +191,15 @@ hipError_t launch_once(cloth_sim* s, const StepParams& sp, int K, int src, hipSt
                                       s->dev.v[src], s->dev.x[dst], s->dev.v[dst],
                                       s->launch.block_threads, st, s->svs_dev,
                                       s->groups.size() > 1 ? s->node_group_dev : nullptr,
-                                      s->launch.hit_slots, s->launch.xcd_runs != 0);
+                                      s->launch.hit_slots, s->launch.xcd_runs);
     if (s->groups.size() == 1)
         return launch_substep(s->dev.view(), s->surfs[0].view.n_tris > 0, sp, s->dev.x[src],
                               s->dev.v[src], s->dev.x[dst], s->dev.v[dst], s->launch.block_threads,
                               st, s->svs_dev, nullptr, s->launch.hit_slots,
-                              s->launch.xcd_runs != 0, s->launch.split_refs, s->heavy_dev, src);
+                              s->launch.xcd_runs, s->launch.split_refs, s->heavy_dev, src);
     return launch_substep(s->dev.view(), s->any_collision, sp, s->dev.x[src], s->dev.v[src],
                           s->dev.x[dst], s->dev.v[dst], s->launch.block_threads, st, s->svs_dev,
-                          s->node_group_dev, s->launch.hit_slots, s->launch.xcd_runs != 0,
+                          s->node_group_dev, s->launch.hit_slots, s->launch.xcd_runs,
                           s->launch.split_refs, s->heavy_dev, src);
 }
 

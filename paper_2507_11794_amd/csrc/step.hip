@@ -22,11 +22,8 @@ __global__ void __launch_bounds__(256)
               const int hit_slots, const int xcd_runs, const int split_refs,
               int* __restrict__ heavy, const int parity) {
     extern __shared__ uint32_t hit_lds[];  // per wavefront: wave_query_lds(hit_slots) bytes
-    // workgroups are dealt round-robin to the 8 XCDs: with xcd_runs each XCD gets a
-    // contiguous node range (neighbours share its L2), else the hardware order is kept
-    const int nb = gridDim.x, q8 = nb >> 3, rem = nb & 7, x8 = blockIdx.x & 7;
-    const int blk = xcd_runs ? x8 * q8 + (x8 < rem ? x8 : rem) + (blockIdx.x >> 3) : blockIdx.x;
-    const int i = blk * blockDim.x + threadIdx.x;
+    const int i = xcd_block(xcd_runs, (cv.n + blockDim.x - 1) / blockDim.x) * blockDim.x +
+                  threadIdx.x;
     const bool valid = i < cv.n;
     const int ld = cv.ld;
     float px = 0.0f, py = 0.0f, pz = 0.0f, qx = 0.0f, qy = 0.0f, qz = 0.0f, w = 0.0f;
@@ -104,7 +101,8 @@ hipError_t launch_substep(const ClothView& cv, int collide, const StepParams& sp
                           int xcd_runs, int split_refs, int* heavy, int parity) {
     if (cv.n <= 0) return hipSuccess;
     if (block <= 0 || block > 256 || (block & 63)) block = 256;
-    const int grid = (cv.n + block - 1) / block;
+    if (xcd_runs < 0 || xcd_runs > kMaxXcdRuns) xcd_runs = 0;
+    const int grid = xcd_grid((cv.n + block - 1) / block, xcd_runs);
     if (!collide || !heavy) split_refs = 0;
     const size_t lds = collide ? (size_t)(block / 64) * wave_query_lds(hit_slots) : 0;
     if (collide && node_group) {

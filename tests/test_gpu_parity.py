@@ -188,6 +188,8 @@ LAUNCHES = [
     dict(kernel=B.CLOTH_KERNEL_DIRECT, block_threads=64, use_graph=1, split_refs=8),
     dict(kernel=B.CLOTH_KERNEL_DIRECT, block_threads=128, use_graph=0, split_refs=1, hit_slots=2),
     dict(kernel=B.CLOTH_KERNEL_DIRECT, block_threads=128, use_graph=1, hit_slots=4, xcd_runs=1),
+    dict(kernel=B.CLOTH_KERNEL_DIRECT, block_threads=64, use_graph=1, xcd_runs=3),
+    dict(kernel=B.CLOTH_KERNEL_DIRECT, block_threads=256, use_graph=0, xcd_runs=16),
     dict(kernel=B.CLOTH_KERNEL_TILE, tile_nodes=64, substeps_per_launch=1, use_graph=0),
     dict(kernel=B.CLOTH_KERNEL_TILE, tile_nodes=256, substeps_per_launch=2, use_graph=1),
     dict(kernel=B.CLOTH_KERNEL_TILE, tile_nodes=256, substeps_per_launch=3, use_graph=1),
@@ -234,3 +236,50 @@ def test_default_and_tile_kernels_match_oracle_one_substep(kernel):
             x1, v1 = sim.read_state()
             r = one_substep_check(inp, x, v, x1, v1, model, tag="tile default")
     assert r["contacts"] > 100
+
+
+def _sliver_fan_scene(n_fan=400, n=24, spacing=0.008, drop=0.02):
+    """A cloth dropped on a disc made of a fan of thin triangles (apex angle 360/n_fan
+    degrees, so every fan triangle meets the centre cell) plus a ring of wide ones."""
+    rng = np.random.default_rng(31)
+    half = 0.5 * spacing * (n - 1)
+    cloth = W.make_cloth(n, n, spacing, (-half, drop, -half), W.K_STRUCT, W.K_SHEAR, W.K_BEND,
+                         W.DAMPING, W.NODE_MASS, pins=[], rng=rng)
+    th = 2 * np.pi * np.arange(n_fan) / n_fan
+    rim = np.stack([0.08 * np.cos(th), np.zeros(n_fan), 0.08 * np.sin(th)], 1)
+    out = np.stack([0.16 * np.cos(th), np.zeros(n_fan) - 0.004, 0.16 * np.sin(th)], 1)
+    verts = np.concatenate([[[0.0, 0.0, 0.0]], rim, out]).astype(np.float32)
+    tris = []
+    for k in range(n_fan):
+        k1 = (k + 1) % n_fan
+        tris.append((0, 1 + k1, 1 + k))  # normal +y
+        tris.append((1 + k, 1 + k1, 1 + n_fan + k))
+        tris.append((1 + k1, 1 + n_fan + k1, 1 + n_fan + k))
+    tris = np.asarray(tris, dtype=np.int32)
+    return W._inputs(cloth, verts, tris, thickness=0.005,
+                     cell_size=W._surface_cell(verts, tris), dt=1.0 / 600.0, n_substeps=4,
+                     n_steps=110, name="cloth on a sliver fan")
+
+
+def test_sliver_triangles_listed_and_unlisted_queries_agree():
+    """On a surface of sliver triangles (closest points on long edges, a crowded centre cell
+    that overflows the hit list) the listed query, the unlisted one and a 64-slot list give
+    the same bits, and one substep matches the oracle."""
+    inp = _sliver_fan_scene()
+    outs = []
+    for cfg in (dict(), dict(hit_slots=0), dict(hit_slots=64, block_threads=256)):
+        with B.Cloth(inp) as sim:
+            if cfg:
+                sim.set_launch(**cfg)
+            sim.step(n_steps=inp.n_steps)
+            outs.append(sim.read_state())
+    for x, v in outs[1:]:
+        assert np.array_equal(x, outs[0][0]) and np.array_equal(v, outs[0][1])
+    model = oracle.Model.from_inputs(inp)
+    with B.Cloth(inp) as sim:
+        sim.step(n_steps=inp.n_steps)
+        x, v = sim.read_state()
+        sim.step(dt=h32(inp), n_substeps=1, n_steps=1)
+        x1, v1 = sim.read_state()
+    r = one_substep_check(inp, x, v, x1, v1, model, tag="sliver fan")
+    assert r["contacts"] > 50

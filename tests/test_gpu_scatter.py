@@ -80,7 +80,8 @@ def test_scatter_with_graphs_batches_and_forces():
     outs = []
     for graph in (0, 1):
         with B.ClothBatch(cl) as b:
-            b.set_launch(kernel=B.CLOTH_KERNEL_SCATTER_FIX, use_graph=graph)
+            # graphs, and chunks of 3 workgroups dealt to the XCDs: the same bits
+            b.set_launch(kernel=B.CLOTH_KERNEL_SCATTER_FIX, use_graph=graph, xcd_runs=3 * graph)
             b.set_external_force(f)
             b.step(n_steps=20)
             outs.append([b.read_state(i) for i in range(len(cl))])
