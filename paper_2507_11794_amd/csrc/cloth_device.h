@@ -45,9 +45,49 @@ __device__ __forceinline__ int xcd_block(int xcd_runs, int n_logical) {
 // non-decreasing in p (each FP32 operation rounds to nearest and floor is monotone), so a
 // triangle registered in the cells cell(lo)..cell(hi) of its inflated box is found from
 // any point inside the box.  No contraction: build and query must agree bit for bit.
-__device__ __forceinline__ float cell_coord_f(float p, float org, float inv_cell) {
+__device__ __forceinline__ float cell_coord_raw(float p, float org, float inv_cell) {
 #pragma clang fp contract(off)
-    return floorf((p - org) * inv_cell);
+    return (p - org) * inv_cell;
+}
+__device__ __forceinline__ float cell_coord_f(float p, float org, float inv_cell) {
+    return floorf(cell_coord_raw(p, org, inv_cell));
+}
+
+// Coded box test.  On each axis, g = (p - org) * inv_cell as computed above is monotone in
+// p, so g(p) < g(lo) implies p < lo and g(p) > g(lo) implies p > lo.  Within the cell c the
+// bucket Q(p) = floor((g(p) - c) * 2^15) is computed exactly (the difference and the
+// scaling are exact for g in [c, c + 1)), so comparing buckets decides lo <= p <= hi except
+// when p shares a bucket with lo or hi.  A reference stores per axis the 32-bit word
+// (Q(lo) + 1) | (0xffff - Q(hi)) << 16, with Q(lo) + 1 = 0 when lo lies before the cell and
+// Q(hi) = 2^15 when hi lies beyond it; the point uses Q(p) | (0xfffe - Q(p)) << 16.  The
+// saturating 16-bit differences word - point are 0 when the axis is certainly inside, 1
+// when p shares a bucket with lo or hi and at least 2 when it is certainly outside, so the
+// maximum over the six halves is 0 for a box hit, 1 for "decide with the exact box" and
+// >= 2 for a miss.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+constexpr int kCodeBits = 15;
+__device__ __forceinline__ uint32_t point_code(float g, float c) {
+#pragma clang fp contract(off)
+    const int q = (int)floorf((g - c) * (float)(1 << kCodeBits));  // 0 .. 2^15 - 1
+    return (uint32_t)q | ((uint32_t)(0xfffe - q) << 16);
+}
+__device__ __forceinline__ uint32_t box_code(const uint4& w, uint32_t cx, uint32_t cy,
+                                             uint32_t cz) {
+    const u16x2 tx = __builtin_elementwise_sub_sat(__builtin_bit_cast(u16x2, w.x),
+                                                   __builtin_bit_cast(u16x2, cx));
+    const u16x2 ty = __builtin_elementwise_sub_sat(__builtin_bit_cast(u16x2, w.y),
+                                                   __builtin_bit_cast(u16x2, cy));
+    const u16x2 tz = __builtin_elementwise_sub_sat(__builtin_bit_cast(u16x2, w.z),
+                                                   __builtin_bit_cast(u16x2, cz));
+    const u16x2 m = __builtin_elementwise_max(__builtin_elementwise_max(tx, ty), tz);
+    return (uint32_t)(m.x > m.y ? m.x : m.y);
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+// Element i of a uint4 array, as one global 16-byte load.
+__device__ __forceinline__ uint4 ldgu4(const uint4* p, size_t i) {
+    const u32x4 v = gmem(reinterpret_cast<const u32x4*>(p))[i];
+    return make_uint4(v.x, v.y, v.z, v.w);
 }
 
 __device__ __forceinline__ int cell_axis(float p, float org, float inv_cell, int dim) {
@@ -344,24 +384,33 @@ __device__ __forceinline__ int collide(const SurfaceView& sv, float restitution,
 __device__ __forceinline__ int collide_listed(const SurfaceView& sv, uint32_t* list, int slots,
                                               float restitution, float& px, float& py,
                                               float& pz, float& qx, float& qy, float& qz) {
-    const int cell = cell_of(sv, px, py, pz);
-    if (cell < 0) return 0;
+    const float gx = cell_coord_raw(px, sv.org[0], sv.inv_cell);
+    const float gy = cell_coord_raw(py, sv.org[1], sv.inv_cell);
+    const float gz = cell_coord_raw(pz, sv.org[2], sv.inv_cell);
+    const float fx = floorf(gx), fy = floorf(gy), fz = floorf(gz);
+    // the test of cell_of, on the same values
+    if (!(fx >= 0.0f && fx <= (float)(sv.dim[0] - 1) && fy >= 0.0f &&
+          fy <= (float)(sv.dim[1] - 1) && fz >= 0.0f && fz <= (float)(sv.dim[2] - 1)))
+        return 0;
+    const int cell = ((int)fz * sv.dim[1] + (int)fy) * sv.dim[0] + (int)fx;
+    const uint32_t cx = point_code(gx, fx), cy = point_code(gy, fy), cz = point_code(gz, fz);
     const gptr<uint32_t> cs = gmem(sv.cell_start);
     const uint32_t b = cs[cell], e = cs[cell + 1];
+    // box hits go to the list as triangle ids; a hit whose coded test was undecided
+    // carries bit 31 and is decided with the exact box before its narrow test
     int nh = 0;
     for (uint32_t r = b; r < e; r += kRefRound) {
-        float4 lo[kRefRound], hi[kRefRound];
+        uint4 w[kRefRound];
+#pragma unroll
+        for (int q = 0; q < kRefRound; ++q) w[q] = ldgu4(sv.ref_q, r + q);
 #pragma unroll
         for (int q = 0; q < kRefRound; ++q) {
-            lo[q] = ldg4(sv.ref_lo, r + q);
-            hi[q] = ldg4(sv.ref_hi, r + q);
-        }
-#pragma unroll
-        for (int q = 0; q < kRefRound; ++q)
-            if (r + q < e && in_box(lo[q], hi[q], px, py, pz)) {
-                if (nh < slots) list[nh * 64] = (uint32_t)__float_as_int(lo[q].w);
+            const uint32_t m = box_code(w[q], cx, cy, cz);
+            if (r + q < e && m <= 1u) {
+                if (nh < slots) list[nh * 64] = w[q].w | (m << 31);
                 ++nh;
             }
+        }
     }
     float sx = 0.0f, sy = 0.0f, sz = 0.0f;
     const float th = sv.thickness;
@@ -383,15 +432,21 @@ __device__ __forceinline__ int collide_listed(const SurfaceView& sv, uint32_t* l
             for (int q = 0; q < kHitRound; ++q) t[q] = list[min(h0 + q, nh - 1) * 64];
 #pragma unroll
             for (int q = 0; q < kHitRound; ++q) {
-                g[q][0] = ldg4(sv.geo, 3 * (size_t)t[q]);
-                g[q][1] = ldg4(sv.geo, 3 * (size_t)t[q] + 1);
-                g[q][2] = ldg4(sv.geo, 3 * (size_t)t[q] + 2);
+                const size_t id = t[q] & 0x7fffffffu;
+                g[q][0] = ldg4(sv.geo, 3 * id);
+                g[q][1] = ldg4(sv.geo, 3 * id + 1);
+                g[q][2] = ldg4(sv.geo, 3 * id + 2);
             }
 #pragma unroll
-            for (int q = 0; q < kHitRound; ++q)
-                if (q < n)
-                    contacts += narrow_visit(sv, t[q], g[q][0], g[q][1], g[q][2], px, py, pz,
+            for (int q = 0; q < kHitRound; ++q) {
+                const uint32_t id = t[q] & 0x7fffffffu;
+                bool hit = q < n;
+                if (hit && (t[q] >> 31))
+                    hit = in_box(ldg4(sv.box_lo, id), ldg4(sv.box_hi, id), px, py, pz);
+                if (hit)
+                    contacts += narrow_visit(sv, id, g[q][0], g[q][1], g[q][2], px, py, pz,
                                              accumulate);
+            }
         }
     }
     respond(contacts, sx, sy, sz, restitution, px, py, pz, qx, qy, qz);

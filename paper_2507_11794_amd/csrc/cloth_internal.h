@@ -23,6 +23,8 @@ struct SurfaceView {
     const uint32_t* refs;        // [refs]
     const float4* ref_lo;        // [refs]: inflated box of refs[r]; .w = triangle id (int bits)
     const float4* ref_hi;        // [refs]: .w unused
+    const uint4* ref_q;          // [refs]: the box coded against its cell (ref_code), and
+                                 // the triangle id in .w
     const float4* box_lo;        // [T] inflated box, .w unused
     const float4* box_hi;        // [T]
     const float4* geo;           // [T*3]: (A, n.x), (B-A, n.y), (C-A, n.z); n = unit outward normal
@@ -237,6 +239,12 @@ hipError_t launch_grid_fill(int n_tris, const float4* box_lo, const float4* box_
 hipError_t launch_grid_sort(int n_cells, const uint32_t* cell_start, uint32_t* refs,
                             hipStream_t stream);
 // ref_lo[r] = (box_lo[refs[r]].xyz, refs[r] as int bits), ref_hi[r] = box_hi[refs[r]] for r < n.
+// Coded reference records (ref_q) of every cell's references; the entries are cell-major as
+// refs, which must be sorted already.
+hipError_t launch_ref_codes(int n_cells, const float org[3], float inv_cell, const int dim[3],
+                            const uint32_t* cell_start, const uint32_t* refs,
+                            const float4* box_lo, const float4* box_hi, uint4* ref_q,
+                            hipStream_t stream);
 hipError_t launch_ref_boxes(size_t n, const uint32_t* refs, const float4* box_lo,
                             const float4* box_hi, float4* ref_lo, float4* ref_hi,
                             hipStream_t stream);

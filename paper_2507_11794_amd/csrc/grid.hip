@@ -160,6 +160,39 @@ __global__ void k_ref_boxes(size_t n, const uint32_t* __restrict__ refs,
     ref_hi[r] = box_hi[t];
 }
 
+// Coded records of the references (see box_code): one wavefront per cell, so each record is
+// coded against the cell that lists it.
+__global__ void __launch_bounds__(256)
+    k_ref_codes(int C, Dims g, const uint32_t* __restrict__ cell_start,
+                const uint32_t* __restrict__ refs, const float4* __restrict__ box_lo,
+                const float4* __restrict__ box_hi, uint4* ref_q) {
+#pragma clang fp contract(off)
+    const int c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (c >= C) return;
+    const uint32_t b = cell_start[c], e = cell_start[c + 1];
+    const float cc[3] = {(float)(c % g.dim[0]), (float)((c / g.dim[0]) % g.dim[1]),
+                         (float)(c / (g.dim[0] * g.dim[1]))};
+    const float scale = (float)(1 << kCodeBits);
+    for (uint32_t r = b + lane; r < e; r += 64) {
+        const uint32_t t = refs[r];
+        const float4 lo = box_lo[t], hi = box_hi[t];
+        const float l[3] = {lo.x, lo.y, lo.z}, h[3] = {hi.x, hi.y, hi.z};
+        uint32_t wd[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            // clamping keeps every answer sound: a low corner before the cell reads as
+            // "certainly below any point", a high corner beyond it as "certainly above"
+            const float gl = cell_coord_raw(l[a], g.org[a], g.inv_cell) - cc[a];
+            const float gh = cell_coord_raw(h[a], g.org[a], g.inv_cell) - cc[a];
+            const float ql = fminf(fmaxf(floorf(gl * scale) + 1.0f, 0.0f), scale);
+            const float qh = fminf(fmaxf(floorf(gh * scale), 0.0f), scale);
+            wd[a] = (uint32_t)ql | ((0xffffu - (uint32_t)qh) << 16);
+        }
+        ref_q[r] = make_uint4(wd[0], wd[1], wd[2], t);
+    }
+}
+
 // ------------------------------------------------------------------ prefix sum
 constexpr int kScanThreads = 1024;
 constexpr int kScanItems = 4;
@@ -295,6 +328,16 @@ hipError_t launch_grid_sort(int n_cells, const uint32_t* cell_start, uint32_t* r
                             hipStream_t stream) {
     if (n_cells <= 0) return hipSuccess;
     k_grid_sort<<<blocks_for(n_cells, 4), 256, 0, stream>>>(n_cells, cell_start, refs);
+    return hipGetLastError();
+}
+
+hipError_t launch_ref_codes(int n_cells, const float org[3], float inv_cell, const int dim[3],
+                            const uint32_t* cell_start, const uint32_t* refs,
+                            const float4* box_lo, const float4* box_hi, uint4* ref_q,
+                            hipStream_t stream) {
+    if (n_cells <= 0) return hipSuccess;
+    k_ref_codes<<<blocks_for(n_cells, 4), 256, 0, stream>>>(
+        n_cells, make_dims(org, inv_cell, dim), cell_start, refs, box_lo, box_hi, ref_q);
     return hipGetLastError();
 }
 

@@ -438,18 +438,21 @@ int rebuild_surface(SurfaceDevice* sd, const float* verts, DeviceArena& arena,
         arena.free_one(sd->refs);
         arena.free_one(sd->ref_lo);
         arena.free_one(sd->ref_hi);
+        arena.free_one(sd->ref_q);
         sd->refs = nullptr;
         sd->ref_lo = sd->ref_hi = nullptr;
+        sd->ref_q = nullptr;
         sd->cap_refs = 0;
         const size_t cap = (size_t)total + (size_t)total / 4 + kRefPad;
         if ((e = arena.alloc(&sd->refs, cap)) || (e = arena.alloc(&sd->ref_lo, cap)) ||
-            (e = arena.alloc(&sd->ref_hi, cap)))
+            (e = arena.alloc(&sd->ref_hi, cap)) || (e = arena.alloc(&sd->ref_q, cap)))
             return hip_fail(e, "hipMalloc grid");
         sd->cap_refs = cap;
     }
     // kRefPad zero entries after the last reference let the query loop load a round of
     // references without a bounds test (triangle 0 is always a valid index)
     if ((e = hipMemsetAsync(sd->refs + total, 0, 4 * kRefPad, stream)) ||
+        (e = hipMemsetAsync(sd->ref_q + total, 0, sizeof(uint4) * kRefPad, stream)) ||
         (e = hipMemsetAsync(sd->counts, 0, 4 * C, stream)) ||
         (e = launch_grid_count(T, sd->box_lo, sd->box_hi, sv.org, sv.inv_cell, sv.dim, sd->counts,
                                stream)) ||
@@ -459,12 +462,15 @@ int rebuild_surface(SurfaceDevice* sd, const float* verts, DeviceArena& arena,
                               sd->cell_start, sd->counts, sd->refs, stream)) ||
         (e = launch_grid_sort((int)C, sd->cell_start, sd->refs, stream)) ||
         (e = launch_ref_boxes((size_t)total + kRefPad, sd->refs, sd->box_lo, sd->box_hi,
-                              sd->ref_lo, sd->ref_hi, stream)))
+                              sd->ref_lo, sd->ref_hi, stream)) ||
+        (e = launch_ref_codes((int)C, sv.org, sv.inv_cell, sv.dim, sd->cell_start, sd->refs,
+                              sd->box_lo, sd->box_hi, sd->ref_q, stream)))
         return hip_fail(e, "grid build");
     sv.cell_start = sd->cell_start;
     sv.refs = sd->refs;
     sv.ref_lo = sd->ref_lo;
     sv.ref_hi = sd->ref_hi;
+    sv.ref_q = sd->ref_q;
     sv.box_lo = sd->box_lo;
     sv.box_hi = sd->box_hi;
     sv.geo = sd->geo;

@@ -107,6 +107,7 @@ struct SurfaceDevice {
     float4 *box_lo = nullptr, *box_hi = nullptr, *geo = nullptr, *tri_v = nullptr;
     uint32_t *counts = nullptr, *cell_start = nullptr, *tmp = nullptr, *refs = nullptr;
     float4 *ref_lo = nullptr, *ref_hi = nullptr;
+    uint4* ref_q = nullptr;
     size_t cap_cells = 0, cap_refs = 0;
     bool dirty = false;  // a rebuild started rewriting the arrays and has not completed
 };
