@@ -176,9 +176,10 @@ int cloth_info(const cloth_sim* sim, long long* out);
 
 /*
  * cloth_set_launch / cloth_get_launch -- choose how cloth_step schedules substeps.
- * Default: one-thread-per-node kernel, 64 threads per workgroup in the hardware's
- * round-robin order, graphs on, 32 hit slots, no second pass (tile fields: 256 nodes,
- * 1 substep, grid schedule).
+ * Default with a collision surface: one-thread-per-node kernel, 64 threads per workgroup
+ * in the hardware's round-robin order, graphs on, 32 hit slots, no second pass (tile
+ * fields: 256 nodes, 1 substep, grid schedule).  Without one: the tile kernel, 256-node
+ * tiles, 1 substep per launch, 256 threads per workgroup, graphs on.
  * cloth_set_launch validates the configuration and rebuilds the tile plan if needed
  * (synchronises the handle's stream).  Errors: CLOTH_EINVAL for an out-of-range field or a
  * tile region that does not fit in LDS (the previous configuration stays in effect).

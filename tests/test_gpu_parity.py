@@ -283,3 +283,17 @@ def test_sliver_triangles_listed_and_unlisted_queries_agree():
         x1, v1 = sim.read_state()
     r = one_substep_check(inp, x, v, x1, v1, model, tag="sliver fan")
     assert r["contacts"] > 50
+
+
+def test_no_collision_default_is_the_tile_kernel_and_matches_direct():
+    inp = W.config0(n=48, n_steps=20)
+    outs = []
+    for cfg in (None, dict(kernel=B.CLOTH_KERNEL_DIRECT, block_threads=64)):
+        with B.Cloth(inp) as sim:
+            if cfg is None:
+                assert sim.get_launch()["kernel"] == B.CLOTH_KERNEL_TILE
+            else:
+                sim.set_launch(**cfg)
+            sim.step(n_steps=inp.n_steps)
+            outs.append(sim.read_state())
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
