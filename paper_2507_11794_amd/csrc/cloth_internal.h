@@ -236,18 +236,11 @@ hipError_t launch_grid_fill(int n_tris, const float4* box_lo, const float4* box_
                             const float org[3], float inv_cell, const int dim[3],
                             const uint32_t* cell_start, uint32_t* fill, uint32_t* refs,
                             hipStream_t stream);
-hipError_t launch_grid_sort(int n_cells, const uint32_t* cell_start, uint32_t* refs,
-                            hipStream_t stream);
-// ref_lo[r] = (box_lo[refs[r]].xyz, refs[r] as int bits), ref_hi[r] = box_hi[refs[r]] for r < n.
-// Coded reference records (ref_q) of every cell's references; the entries are cell-major as
-// refs, which must be sorted already.
-hipError_t launch_ref_codes(int n_cells, const float org[3], float inv_cell, const int dim[3],
-                            const uint32_t* cell_start, const uint32_t* refs,
-                            const float4* box_lo, const float4* box_hi, uint4* ref_q,
-                            hipStream_t stream);
-hipError_t launch_ref_boxes(size_t n, const uint32_t* refs, const float4* box_lo,
-                            const float4* box_hi, float4* ref_lo, float4* ref_hi,
-                            hipStream_t stream);
+// Sorts each cell's references ascending and writes their records (ref_lo, ref_hi, ref_q).
+hipError_t launch_grid_finish(int n_cells, const float org[3], float inv_cell, const int dim[3],
+                              const uint32_t* cell_start, uint32_t* refs, const float4* box_lo,
+                              const float4* box_hi, float4* ref_lo, float4* ref_hi, uint4* ref_q,
+                              hipStream_t stream);
 
 // Exclusive prefix sum of in[0..n) into out[0..n] (out[n] = total) with wavefront scans.
 // tmp must hold scan_tmp_words(n) words.

@@ -82,47 +82,159 @@ __global__ void k_tri_prep(int T, const float* __restrict__ verts, const int* __
     atomicAdd(total_refs, n);
 }
 
-__global__ void k_grid_count(int T, const float4* __restrict__ box_lo,
-                             const float4* __restrict__ box_hi, Dims g, uint32_t* counts) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= T) return;
-    int c0[3], c1[3];
-    cell_range(g, box_lo[t], box_hi[t], c0, c1);
-    for (int z = c0[2]; z <= c1[2]; ++z)
-        for (int y = c0[1]; y <= c1[1]; ++y)
-            for (int x = c0[0]; x <= c1[0]; ++x)
-                atomicAdd(&counts[(z * g.dim[1] + y) * g.dim[0] + x], 1u);
+// Workgroup-private counting.  A workgroup's 256 consecutive triangles are usually a compact
+// patch of the mesh, so their cell ranges fall in a small box of cells; when that box holds
+// at most kLocalCells cells the workgroup counts its (triangle, cell) pairs with LDS atomics
+// and adds one global atomic per touched cell, instead of one per pair (neighbouring
+// triangles share cells, and same-address global atomics serialise).  Otherwise it uses
+// global atomics per pair.
+constexpr int kLocalCells = 4096;
+
+struct Region {
+    int lo[3], ext[3];
+    int vol;  // 0: the box is empty or too large
+};
+
+// Every thread of the workgroup calls this (it synchronises).
+__device__ Region block_region(bool valid, const int c0[3], const int c1[3], int* sreg) {
+    if (threadIdx.x < 3) {
+        sreg[threadIdx.x] = INT_MAX;
+        sreg[3 + threadIdx.x] = INT_MIN;
+    }
+    __syncthreads();
+    if (valid)
+        for (int a = 0; a < 3; ++a) {
+            atomicMin(&sreg[a], c0[a]);
+            atomicMax(&sreg[3 + a], c1[a]);
+        }
+    __syncthreads();
+    Region r;
+    long long vol = 1;
+    for (int a = 0; a < 3; ++a) {
+        r.lo[a] = sreg[a];
+        r.ext[a] = sreg[3 + a] >= sreg[a] ? sreg[3 + a] - sreg[a] + 1 : 0;
+        vol *= r.ext[a];
+    }
+    r.vol = vol > 0 && vol <= kLocalCells ? (int)vol : 0;
+    return r;
 }
 
-__global__ void k_grid_fill(int T, const float4* __restrict__ box_lo,
-                            const float4* __restrict__ box_hi, Dims g,
-                            const uint32_t* __restrict__ cell_start, uint32_t* fill,
-                            uint32_t* refs) {
+__device__ __forceinline__ int local_cell(const Region& r, int x, int y, int z) {
+    return ((z - r.lo[2]) * r.ext[1] + (y - r.lo[1])) * r.ext[0] + (x - r.lo[0]);
+}
+__device__ __forceinline__ int global_cell(const Region& r, const Dims& g, int k) {
+    const int x = r.lo[0] + k % r.ext[0], y = r.lo[1] + (k / r.ext[0]) % r.ext[1],
+              z = r.lo[2] + k / (r.ext[0] * r.ext[1]);
+    return (z * g.dim[1] + y) * g.dim[0] + x;
+}
+
+__global__ void __launch_bounds__(256)
+    k_grid_count(int T, const float4* __restrict__ box_lo, const float4* __restrict__ box_hi,
+                 Dims g, uint32_t* counts) {
+    __shared__ uint32_t local[kLocalCells];
+    __shared__ int sreg[6];
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= T) return;
-    int c0[3], c1[3];
-    cell_range(g, box_lo[t], box_hi[t], c0, c1);
+    const bool valid = t < T;
+    int c0[3] = {0, 0, 0}, c1[3] = {-1, -1, -1};
+    if (valid) cell_range(g, box_lo[t], box_hi[t], c0, c1);
+    const Region r = block_region(valid, c0, c1, sreg);
+    if (r.vol == 0) {
+        for (int z = c0[2]; z <= c1[2]; ++z)
+            for (int y = c0[1]; y <= c1[1]; ++y)
+                for (int x = c0[0]; x <= c1[0]; ++x)
+                    atomicAdd(&counts[(z * g.dim[1] + y) * g.dim[0] + x], 1u);
+        return;
+    }
+    for (int k = threadIdx.x; k < r.vol; k += blockDim.x) local[k] = 0;
+    __syncthreads();
+    for (int z = c0[2]; z <= c1[2]; ++z)
+        for (int y = c0[1]; y <= c1[1]; ++y)
+            for (int x = c0[0]; x <= c1[0]; ++x) atomicAdd(&local[local_cell(r, x, y, z)], 1u);
+    __syncthreads();
+    for (int k = threadIdx.x; k < r.vol; k += blockDim.x)
+        if (local[k]) atomicAdd(&counts[global_cell(r, g, k)], local[k]);
+}
+
+// Scatters the triangle ids into their cells' ranges (in an arbitrary order; k_grid_finish
+// sorts each cell).  Workgroup-private as k_grid_count: one global atomic per touched cell
+// reserves the workgroup's run of slots in that cell.
+__global__ void __launch_bounds__(256)
+    k_grid_fill(int T, const float4* __restrict__ box_lo, const float4* __restrict__ box_hi,
+                Dims g, const uint32_t* __restrict__ cell_start, uint32_t* fill, uint32_t* refs) {
+    __shared__ uint32_t local[kLocalCells];  // pair counts, then the run's first slot
+    __shared__ uint32_t next[kLocalCells];   // slots taken within the run
+    __shared__ int sreg[6];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = t < T;
+    int c0[3] = {0, 0, 0}, c1[3] = {-1, -1, -1};
+    if (valid) cell_range(g, box_lo[t], box_hi[t], c0, c1);
+    const Region r = block_region(valid, c0, c1, sreg);
+    if (r.vol == 0) {
+        for (int z = c0[2]; z <= c1[2]; ++z)
+            for (int y = c0[1]; y <= c1[1]; ++y)
+                for (int x = c0[0]; x <= c1[0]; ++x) {
+                    const int c = (z * g.dim[1] + y) * g.dim[0] + x;
+                    refs[cell_start[c] + atomicAdd(&fill[c], 1u)] = (uint32_t)t;
+                }
+        return;
+    }
+    for (int k = threadIdx.x; k < r.vol; k += blockDim.x) local[k] = next[k] = 0;
+    __syncthreads();
+    for (int z = c0[2]; z <= c1[2]; ++z)
+        for (int y = c0[1]; y <= c1[1]; ++y)
+            for (int x = c0[0]; x <= c1[0]; ++x) atomicAdd(&local[local_cell(r, x, y, z)], 1u);
+    __syncthreads();
+    for (int k = threadIdx.x; k < r.vol; k += blockDim.x)
+        if (local[k]) local[k] = atomicAdd(&fill[global_cell(r, g, k)], local[k]);
+    __syncthreads();
     for (int z = c0[2]; z <= c1[2]; ++z)
         for (int y = c0[1]; y <= c1[1]; ++y)
             for (int x = c0[0]; x <= c1[0]; ++x) {
+                const int k = local_cell(r, x, y, z);
                 const int c = (z * g.dim[1] + y) * g.dim[0] + x;
-                const uint32_t slot = atomicAdd(&fill[c], 1u);
-                refs[cell_start[c] + slot] = (uint32_t)t;
+                refs[cell_start[c] + local[k] + atomicAdd(&next[k], 1u)] = (uint32_t)t;
             }
 }
 
-// Sorts each cell's reference list ascending, one wavefront per cell.  A cell lists a
-// triangle at most once, so an entry's final position is its rank (the number of smaller
-// entries): up to 128 entries are held two per lane and ranked against every entry by
-// broadcasts, then written back.  Longer lists (none in practice) are insertion-sorted by one
-// lane.
+// One axis of a coded record (see box_code): (Q(lo) + 1) | (0xffff - Q(hi)) << 16 against
+// cell coordinate cc, clamped so a corner outside the cell reads as certainly below or
+// above every point of it.
+__device__ __forceinline__ uint32_t code_axis(float l, float h, float org, float inv_cell,
+                                              float cc) {
+#pragma clang fp contract(off)
+    const float scale = (float)(1 << kCodeBits);
+    const float gl = cell_coord_raw(l, org, inv_cell) - cc;
+    const float gh = cell_coord_raw(h, org, inv_cell) - cc;
+    const float ql = fminf(fmaxf(floorf(gl * scale) + 1.0f, 0.0f), scale);
+    const float qh = fminf(fmaxf(floorf(gh * scale), 0.0f), scale);
+    return (uint32_t)ql | ((0xffffu - (uint32_t)qh) << 16);
+}
+
+// Sorts each cell's reference list ascending and writes the references' records: the
+// inflated box inline (ref_lo with the triangle id in .w, ref_hi) and the coded record
+// (ref_q).  One wavefront per cell.  A cell lists a triangle at most once, so an entry's
+// final position is its rank (the number of smaller entries): up to 128 entries are held
+// two per lane and ranked against every entry by broadcasts.  Longer lists (none in
+// practice) are insertion-sorted by one lane.
 __global__ void __launch_bounds__(256)
-    k_grid_sort(int C, const uint32_t* __restrict__ cell_start, uint32_t* refs) {
+    k_grid_finish(int C, Dims g, const uint32_t* __restrict__ cell_start, uint32_t* refs,
+                  const float4* __restrict__ box_lo, const float4* __restrict__ box_hi,
+                  float4* ref_lo, float4* ref_hi, uint4* ref_q) {
     const int c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (c >= C) return;
     const uint32_t b = cell_start[c], n = cell_start[c + 1] - b;
-    if (n <= 1) return;
+    if (n == 0) return;
+    const float cc[3] = {(float)(c % g.dim[0]), (float)((c / g.dim[0]) % g.dim[1]),
+                         (float)(c / (g.dim[0] * g.dim[1]))};
+    auto emit = [&](uint32_t pos, uint32_t t) {
+        const float4 lo = box_lo[t], hi = box_hi[t];
+        ref_lo[pos] = make_float4(lo.x, lo.y, lo.z, __int_as_float((int)t));
+        ref_hi[pos] = hi;
+        ref_q[pos] = make_uint4(code_axis(lo.x, hi.x, g.org[0], g.inv_cell, cc[0]),
+                                code_axis(lo.y, hi.y, g.org[1], g.inv_cell, cc[1]),
+                                code_axis(lo.z, hi.z, g.org[2], g.inv_cell, cc[2]), t);
+    };
     if (n <= 128) {
         const uint32_t v0 = lane < (int)n ? refs[b + lane] : 0xffffffffu;
         const uint32_t v1 = lane + 64 < (int)n ? refs[b + 64 + lane] : 0xffffffffu;
@@ -132,8 +244,14 @@ __global__ void __launch_bounds__(256)
             r0 += (w0 < v0) + (w1 < v0);
             r1 += (w0 < v1) + (w1 < v1);
         }
-        if (lane < (int)n) refs[b + r0] = v0;
-        if (lane + 64 < (int)n) refs[b + r1] = v1;
+        if (lane < (int)n) {
+            refs[b + r0] = v0;
+            emit(b + r0, v0);
+        }
+        if (lane + 64 < (int)n) {
+            refs[b + r1] = v1;
+            emit(b + r1, v1);
+        }
         return;
     }
     if (lane != 0) return;
@@ -146,51 +264,7 @@ __global__ void __launch_bounds__(256)
         }
         refs[j] = v;
     }
-}
-
-__global__ void k_ref_boxes(size_t n, const uint32_t* __restrict__ refs,
-                            const float4* __restrict__ box_lo, const float4* __restrict__ box_hi,
-                            float4* ref_lo, float4* ref_hi) {
-    const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    const uint32_t t = refs[r];
-    float4 lo = box_lo[t];
-    lo.w = __int_as_float((int)t);
-    ref_lo[r] = lo;
-    ref_hi[r] = box_hi[t];
-}
-
-// Coded records of the references (see box_code): one wavefront per cell, so each record is
-// coded against the cell that lists it.
-__global__ void __launch_bounds__(256)
-    k_ref_codes(int C, Dims g, const uint32_t* __restrict__ cell_start,
-                const uint32_t* __restrict__ refs, const float4* __restrict__ box_lo,
-                const float4* __restrict__ box_hi, uint4* ref_q) {
-#pragma clang fp contract(off)
-    const int c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (c >= C) return;
-    const uint32_t b = cell_start[c], e = cell_start[c + 1];
-    const float cc[3] = {(float)(c % g.dim[0]), (float)((c / g.dim[0]) % g.dim[1]),
-                         (float)(c / (g.dim[0] * g.dim[1]))};
-    const float scale = (float)(1 << kCodeBits);
-    for (uint32_t r = b + lane; r < e; r += 64) {
-        const uint32_t t = refs[r];
-        const float4 lo = box_lo[t], hi = box_hi[t];
-        const float l[3] = {lo.x, lo.y, lo.z}, h[3] = {hi.x, hi.y, hi.z};
-        uint32_t wd[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            // clamping keeps every answer sound: a low corner before the cell reads as
-            // "certainly below any point", a high corner beyond it as "certainly above"
-            const float gl = cell_coord_raw(l[a], g.org[a], g.inv_cell) - cc[a];
-            const float gh = cell_coord_raw(h[a], g.org[a], g.inv_cell) - cc[a];
-            const float ql = fminf(fmaxf(floorf(gl * scale) + 1.0f, 0.0f), scale);
-            const float qh = fminf(fmaxf(floorf(gh * scale), 0.0f), scale);
-            wd[a] = (uint32_t)ql | ((0xffffu - (uint32_t)qh) << 16);
-        }
-        ref_q[r] = make_uint4(wd[0], wd[1], wd[2], t);
-    }
+    for (uint32_t i = b; i < b + n; ++i) emit(i, refs[i]);
 }
 
 // ------------------------------------------------------------------ prefix sum
@@ -324,29 +398,14 @@ hipError_t launch_grid_fill(int n_tris, const float4* box_lo, const float4* box_
     return hipGetLastError();
 }
 
-hipError_t launch_grid_sort(int n_cells, const uint32_t* cell_start, uint32_t* refs,
-                            hipStream_t stream) {
+hipError_t launch_grid_finish(int n_cells, const float org[3], float inv_cell, const int dim[3],
+                              const uint32_t* cell_start, uint32_t* refs, const float4* box_lo,
+                              const float4* box_hi, float4* ref_lo, float4* ref_hi, uint4* ref_q,
+                              hipStream_t stream) {
     if (n_cells <= 0) return hipSuccess;
-    k_grid_sort<<<blocks_for(n_cells, 4), 256, 0, stream>>>(n_cells, cell_start, refs);
-    return hipGetLastError();
-}
-
-hipError_t launch_ref_codes(int n_cells, const float org[3], float inv_cell, const int dim[3],
-                            const uint32_t* cell_start, const uint32_t* refs,
-                            const float4* box_lo, const float4* box_hi, uint4* ref_q,
-                            hipStream_t stream) {
-    if (n_cells <= 0) return hipSuccess;
-    k_ref_codes<<<blocks_for(n_cells, 4), 256, 0, stream>>>(
-        n_cells, make_dims(org, inv_cell, dim), cell_start, refs, box_lo, box_hi, ref_q);
-    return hipGetLastError();
-}
-
-hipError_t launch_ref_boxes(size_t n, const uint32_t* refs, const float4* box_lo,
-                            const float4* box_hi, float4* ref_lo, float4* ref_hi,
-                            hipStream_t stream) {
-    if (n == 0) return hipSuccess;
-    k_ref_boxes<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(n, refs, box_lo, box_hi, ref_lo,
-                                                               ref_hi);
+    k_grid_finish<<<blocks_for(n_cells, 4), 256, 0, stream>>>(
+        n_cells, make_dims(org, inv_cell, dim), cell_start, refs, box_lo, box_hi, ref_lo, ref_hi,
+        ref_q);
     return hipGetLastError();
 }
 

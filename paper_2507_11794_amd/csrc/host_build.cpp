@@ -449,9 +449,11 @@ int rebuild_surface(SurfaceDevice* sd, const float* verts, DeviceArena& arena,
             return hip_fail(e, "hipMalloc grid");
         sd->cap_refs = cap;
     }
-    // kRefPad zero entries after the last reference let the query loop load a round of
-    // references without a bounds test (triangle 0 is always a valid index)
+    // kRefPad zero entries after the last reference let the query loops load a round of
+    // references without a bounds test (the loaded values past a cell's end are never used)
     if ((e = hipMemsetAsync(sd->refs + total, 0, 4 * kRefPad, stream)) ||
+        (e = hipMemsetAsync(sd->ref_lo + total, 0, sizeof(float4) * kRefPad, stream)) ||
+        (e = hipMemsetAsync(sd->ref_hi + total, 0, sizeof(float4) * kRefPad, stream)) ||
         (e = hipMemsetAsync(sd->ref_q + total, 0, sizeof(uint4) * kRefPad, stream)) ||
         (e = hipMemsetAsync(sd->counts, 0, 4 * C, stream)) ||
         (e = launch_grid_count(T, sd->box_lo, sd->box_hi, sv.org, sv.inv_cell, sv.dim, sd->counts,
@@ -460,11 +462,9 @@ int rebuild_surface(SurfaceDevice* sd, const float* verts, DeviceArena& arena,
         (e = hipMemsetAsync(sd->counts, 0, 4 * C, stream)) ||
         (e = launch_grid_fill(T, sd->box_lo, sd->box_hi, sv.org, sv.inv_cell, sv.dim,
                               sd->cell_start, sd->counts, sd->refs, stream)) ||
-        (e = launch_grid_sort((int)C, sd->cell_start, sd->refs, stream)) ||
-        (e = launch_ref_boxes((size_t)total + kRefPad, sd->refs, sd->box_lo, sd->box_hi,
-                              sd->ref_lo, sd->ref_hi, stream)) ||
-        (e = launch_ref_codes((int)C, sv.org, sv.inv_cell, sv.dim, sd->cell_start, sd->refs,
-                              sd->box_lo, sd->box_hi, sd->ref_q, stream)))
+        (e = launch_grid_finish((int)C, sv.org, sv.inv_cell, sv.dim, sd->cell_start, sd->refs,
+                                sd->box_lo, sd->box_hi, sd->ref_lo, sd->ref_hi, sd->ref_q,
+                                stream)))
         return hip_fail(e, "grid build");
     sv.cell_start = sd->cell_start;
     sv.refs = sd->refs;
