@@ -109,9 +109,11 @@ def bench_adjoint(frames: int = 200):
     stream = torch.cuda.current_stream()
     sim = cloth.Cloth(inp, stream=stream.cuda_stream)
     sim.step(n_steps=frames)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    # plain stepping of the same frames, timed after a warm-up pass (graph capture) from the
+    # initial state
     sim2 = cloth.Cloth(inp, stream=stream.cuda_stream)
+    sim2.step(n_steps=frames)
+    sim2.write_state(inp.x0, inp.v0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim2.step(n_steps=frames)

@@ -193,8 +193,10 @@ int cloth_rollout_backward(cloth_sim* s, const float* gx_out_dev, float* gk_dev,
         for (long long r = 1; r < top - base; ++r) {
             const float* xs = R.seg + (size_t)(r - 1) * state;
             float* xd = R.seg + (size_t)r * state;
+            // the listed collision query, as the forward pass (any launch gives the same bits)
             if ((e = launch_substep(cv, s->surfs[0].view.n_tris > 0, sp, xs, xs + 3 * ld, xd,
-                                    xd + 3 * ld, 256, s->stream, s->svs_dev)))
+                                    xd + 3 * ld, 256, s->stream, s->svs_dev, nullptr,
+                                    s->launch.hit_slots)))
                 return hip_fail(e, "recompute segment");
         }
         for (long long t = top; t > base; --t) {
