@@ -27,7 +27,9 @@ __global__ void __launch_bounds__(256)
     k_adj_node(const ClothView cv, const SurfaceView sv, const StepParams sp,
                const float* __restrict__ xs, const float* __restrict__ vs,
                const float* __restrict__ xb_out, const float* __restrict__ vb_out,
-               float* __restrict__ fb, float* __restrict__ xb_part, float* __restrict__ vb_part) {
+               float* __restrict__ fb, float* __restrict__ xb_part, float* __restrict__ vb_part,
+               int hit_slots) {
+    extern __shared__ uint32_t hit_lds[];  // per wavefront: wave_query_lds(hit_slots) bytes
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cv.n) return;
     const int ld = cv.ld;
@@ -53,12 +55,18 @@ __global__ void __launch_bounds__(256)
     float sx = bx, sy = by, sz = bz, tx = cx, ty = cy, tz = cz;
     if (sv.n_tris > 0) {
         float ax = 0.0f, ay = 0.0f, az = 0.0f;
-        const int cnt = contacts_visit(sv, px, py, pz, [&](const float4& n, float, uint32_t) {
+        auto project = [&](const float4& n, float, uint32_t) {
             const float proj = n.x * bx + n.y * by + n.z * bz;
             ax += proj * n.x;
             ay += proj * n.y;
             az += proj * n.z;
-        });
+        };
+        // the forward kernels' contact set, in their order
+        const int cnt = hit_slots > 0
+                            ? contacts_listed(sv, hit_lds + (threadIdx.x >> 6) * hit_slots * 64 +
+                                                      (threadIdx.x & 63),
+                                              hit_slots, px, py, pz, project)
+                            : contacts_visit(sv, px, py, pz, project);
         if (cnt > 0) {
             const float inv = 1.0f / (float)cnt;
             sx = bx - ax * inv;
@@ -95,38 +103,65 @@ __global__ void __launch_bounds__(256)
     const float fbx = fb[i], fby = fb[ld + i], fbz = fb[2 * ld + i];
     float gx = xb_part[i], gy = xb_part[ld + i], gz = xb_part[2 * ld + i];
     float hx = vb_part[i], hy = vb_part[ld + i], hz = vb_part[2 * ld + i];
+    // all of a round's incidence records, then all their neighbours' states and force
+    // adjoints, are loaded back to back (indices clamped to the list), then used in
+    // incidence order, as the forward gather does
+    constexpr int R = 12;
     const int deg = cv.deg[i];
     const int base = cv.slice_ptr[i >> 6] + (i & 63);
-    for (int r = 0; r < deg; ++r) {
-        const int q = base + r * 64;
-        const float4 rec = cv.inc4[q];
-        const int j = __float_as_int(rec.w);
-        const float k = rec.x, c = rec.y, L0 = rec.z;
-        const float dx = xs[j] - xi, dy = xs[ld + j] - yi, dz = xs[2 * ld + j] - zi;
-        const float ex = vs[j] - vxi, ey = vs[ld + j] - vyi, ez = vs[2 * ld + j] - vzi;
-        const float lx = fbx - fb[j], ly = fby - fb[ld + j], lz = fbz - fb[2 * ld + j];
-        const float l2 = dx * dx + dy * dy + dz * dz;
-        const float il = __builtin_amdgcn_rsqf(l2);
-        const float len = l2 * il;
-        const float ux = dx * il, uy = dy * il, uz = dz * il;
-        const float dvu = ex * ux + ey * uy + ez * uz;
-        const float phi = k * (len - L0) + c * dvu;
-        const float ul = ux * lx + uy * ly + uz * lz;
-        const float a = phi * il, b = c * il * ul, kk = k * ul;
-        const float dbx = a * (lx - ux * ul) + kk * ux + b * (ex - ux * dvu);
-        const float dby = a * (ly - uy * ul) + kk * uy + b * (ey - uy * dvu);
-        const float dbz = a * (lz - uz * ul) + kk * uz + b * (ez - uz * dvu);
-        const float cu = c * ul;
-        gx -= dbx;
-        gy -= dby;
-        gz -= dbz;
-        hx -= cu * ux;
-        hy -= cu * uy;
-        hz -= cu * uz;
-        const int code = cv.inc_spring[q];
-        if (code >= 0) {  // node i is the spring's first end: it owns the spring's gradients
-            kb[code] += (double)((len - L0) * ul);
-            cb[code] += (double)(dvu * ul);
+    const gptr<float> X = gmem(xs), Vv = gmem(vs), FB = gmem(fb);
+    for (int r0 = 0; r0 < deg; r0 += R) {
+        float4 rec[R];
+        int code[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const size_t at = (size_t)(base + min(r0 + q, deg - 1) * 64);
+            rec[q] = ldg4(cv.inc4, at);
+            code[q] = gmem(cv.inc_spring)[at];
+        }
+        float nx[R], ny[R], nz[R], mx[R], my[R], mz[R], ox[R], oy[R], oz[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int j = __float_as_int(rec[q].w);
+            nx[q] = X[j];
+            ny[q] = X[ld + j];
+            nz[q] = X[2 * ld + j];
+            mx[q] = Vv[j];
+            my[q] = Vv[ld + j];
+            mz[q] = Vv[2 * ld + j];
+            ox[q] = FB[j];
+            oy[q] = FB[ld + j];
+            oz[q] = FB[2 * ld + j];
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            if (r0 + q >= deg) continue;
+            const float k = rec[q].x, c = rec[q].y, L0 = rec[q].z;
+            const float dx = nx[q] - xi, dy = ny[q] - yi, dz = nz[q] - zi;
+            const float ex = mx[q] - vxi, ey = my[q] - vyi, ez = mz[q] - vzi;
+            const float lx = fbx - ox[q], ly = fby - oy[q], lz = fbz - oz[q];
+            const float l2 = dx * dx + dy * dy + dz * dz;
+            const float il = __builtin_amdgcn_rsqf(l2);
+            const float len = l2 * il;
+            const float ux = dx * il, uy = dy * il, uz = dz * il;
+            const float dvu = ex * ux + ey * uy + ez * uz;
+            const float phi = k * (len - L0) + c * dvu;
+            const float ul = ux * lx + uy * ly + uz * lz;
+            const float a = phi * il, b = c * il * ul, kk = k * ul;
+            const float dbx = a * (lx - ux * ul) + kk * ux + b * (ex - ux * dvu);
+            const float dby = a * (ly - uy * ul) + kk * uy + b * (ey - uy * dvu);
+            const float dbz = a * (lz - uz * ul) + kk * uz + b * (ez - uz * dvu);
+            const float cu = c * ul;
+            gx -= dbx;
+            gy -= dby;
+            gz -= dbz;
+            hx -= cu * ux;
+            hy -= cu * uy;
+            hz -= cu * uz;
+            if (code[q] >= 0) {  // node i is the spring's first end: it owns the spring's gradients
+                kb[code[q]] += (double)((len - L0) * ul);
+                cb[code[q]] += (double)(dvu * ul);
+            }
         }
     }
     xb_in[i] = gx;
@@ -233,10 +268,12 @@ inline unsigned blocks(size_t n, int b) { return (unsigned)((n + b - 1) / b); }
 hipError_t launch_adj_node(const ClothView& cv, const SurfaceView& sv, const StepParams& sp,
                            const float* xs, const float* vs, const float* xb_out,
                            const float* vb_out, float* fb, float* xb_part, float* vb_part,
-                           hipStream_t st) {
+                           int hit_slots, hipStream_t st) {
     if (cv.n <= 0) return hipSuccess;
-    k_adj_node<<<blocks(cv.n, 256), 256, 0, st>>>(cv, sv, sp, xs, vs, xb_out, vb_out, fb, xb_part,
-                                                  vb_part);
+    if (hit_slots < 0 || hit_slots > kMaxHitSlots) hit_slots = 0;
+    const size_t lds = (size_t)(256 / 64) * wave_query_lds(hit_slots);  // at most 64 KiB
+    k_adj_node<<<blocks(cv.n, 256), 256, lds, st>>>(cv, sv, sp, xs, vs, xb_out, vb_out, fb,
+                                                    xb_part, vb_part, hit_slots);
     return hipGetLastError();
 }
 

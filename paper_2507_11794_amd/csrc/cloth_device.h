@@ -374,16 +374,16 @@ __device__ __forceinline__ int collide(const SurfaceView& sv, float restitution,
     return cnt;
 }
 
-// a3 + a4 with the box hits of the whole cell collected first: the cell's reference boxes
-// are tested kRefRound per round of loads, the triangle ids of hits go to this lane's list
-// in LDS (list[k * 64], k < slots), and the hits' geometry is then loaded eight hits per
-// round, so a node with many box hits waits for few round trips.  Hits are visited in
-// ascending triangle id, exactly as contacts_visit does (same contacts, same sums); a lane
-// with more hits than slots runs contacts_visit instead.  Returns the contact count after
-// applying the response.
-__device__ __forceinline__ int collide_listed(const SurfaceView& sv, uint32_t* list, int slots,
-                                              float restitution, float& px, float& py,
-                                              float& pz, float& qx, float& qy, float& qz) {
+// a3 + a4 contact search with the box hits of the whole cell collected first: the cell's
+// coded reference records are tested kRefRound per round of loads, the triangle ids of hits
+// go to this lane's list in LDS (list[k * 64], k < slots), and the hits' geometry is then
+// loaded kHitRound hits per round, so a node with many box hits waits for few round trips.
+// Contacts are visited in ascending triangle id, exactly as contacts_visit visits them
+// (same contacts, same order); a lane with more hits than slots runs contacts_visit
+// instead.  Returns the contact count.
+template <class Visit>
+__device__ __forceinline__ int contacts_listed(const SurfaceView& sv, uint32_t* list, int slots,
+                                               float px, float py, float pz, Visit&& visit) {
     const float gx = cell_coord_raw(px, sv.org[0], sv.inv_cell);
     const float gy = cell_coord_raw(py, sv.org[1], sv.inv_cell);
     const float gz = cell_coord_raw(pz, sv.org[2], sv.inv_cell);
@@ -412,18 +412,9 @@ __device__ __forceinline__ int collide_listed(const SurfaceView& sv, uint32_t* l
             }
         }
     }
-    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
-    const float th = sv.thickness;
-    auto accumulate = [&](const float4& n, float s, uint32_t) {
-        const float push = th - s;
-        sx += push * n.x;
-        sy += push * n.y;
-        sz += push * n.z;
-    };
+    if (nh > slots) return contacts_visit(sv, px, py, pz, visit);
     int contacts = 0;
-    if (nh > slots) {
-        contacts = contacts_visit(sv, px, py, pz, accumulate);
-    } else {
+    {
         for (int h0 = 0; h0 < nh; h0 += kHitRound) {
             const int n = min(nh - h0, kHitRound);
             uint32_t t[kHitRound];
@@ -445,10 +436,26 @@ __device__ __forceinline__ int collide_listed(const SurfaceView& sv, uint32_t* l
                     hit = in_box(ldg4(sv.box_lo, id), ldg4(sv.box_hi, id), px, py, pz);
                 if (hit)
                     contacts += narrow_visit(sv, id, g[q][0], g[q][1], g[q][2], px, py, pz,
-                                             accumulate);
+                                             visit);
             }
         }
     }
+    return contacts;
+}
+
+// collide_listed: contacts_listed with the averaged response.
+__device__ __forceinline__ int collide_listed(const SurfaceView& sv, uint32_t* list, int slots,
+                                              float restitution, float& px, float& py,
+                                              float& pz, float& qx, float& qy, float& qz) {
+    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+    const float th = sv.thickness;
+    auto accumulate = [&](const float4& n, float s, uint32_t) {
+        const float push = th - s;
+        sx += push * n.x;
+        sy += push * n.y;
+        sz += push * n.z;
+    };
+    const int contacts = contacts_listed(sv, list, slots, px, py, pz, accumulate);
     respond(contacts, sx, sy, sz, restitution, px, py, pz, qx, qy, qz);
     return contacts;
 }

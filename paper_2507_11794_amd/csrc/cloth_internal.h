@@ -189,10 +189,11 @@ hipError_t launch_mt_debug_contacts(const ClothView& cv, const StepParams& sp,
 // --- a6 adjoint ----------------------------------------------------------------------------
 // Response and integration transpose of one substep at state (xs, vs): partial adjoints and
 // the force adjoint fb = h w vtot (see adjoint.hip).
+// hit_slots: the contact search's LDS list (0 = unlisted search); the results are the same.
 hipError_t launch_adj_node(const ClothView& cv, const SurfaceView& sv, const StepParams& sp,
                            const float* xs, const float* vs, const float* xb_out,
                            const float* vb_out, float* fb, float* xb_part, float* vb_part,
-                           hipStream_t st);
+                           int hit_slots, hipStream_t st);
 // Spring-force transpose: xb_in / vb_in = partial + spring terms; adds dL/dk, dL/dc.
 hipError_t launch_adj_springs(const ClothView& cv, const float* xs, const float* vs,
                               const float* fb, const float* xb_part, const float* vb_part,

@@ -202,7 +202,7 @@ int cloth_rollout_backward(cloth_sim* s, const float* gx_out_dev, float* gk_dev,
         for (long long t = top; t > base; --t) {
             const float* xs = R.seg + (size_t)(t - 1 - base) * state;
             if ((e = launch_adj_node(cv, s->surfs[0].view, sp, xs, xs + 3 * ld, xb, vb, fb, xbp, vbp,
-                                     s->stream)) ||
+                                     s->launch.hit_slots, s->stream)) ||
                 (e = launch_adj_springs(cv, xs, xs + 3 * ld, fb, xbp, vbp, xb2, vb2, R.kb, R.cb,
                                         s->stream)))
                 return hip_fail(e, "adjoint substep");
