@@ -23,21 +23,18 @@ namespace cloth {
 
 namespace {
 
-__global__ void __launch_bounds__(256)
-    k_adj_node(const ClothView cv, const SurfaceView sv, const StepParams sp,
-               const float* __restrict__ xs, const float* __restrict__ vs,
-               const float* __restrict__ xb_out, const float* __restrict__ vb_out,
-               float* __restrict__ fb, float* __restrict__ xb_part, float* __restrict__ vb_part,
-               int hit_slots) {
-    extern __shared__ uint32_t hit_lds[];  // per wavefront: wave_query_lds(hit_slots) bytes
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cv.n) return;
+// Node pass of one substep for node i (see the header comment): the forward prediction is
+// recomputed from (xs, vs), the contact set found as the forward kernels find it, and the
+// node's partial adjoints written.  (bx, by, bz), (cx, cy, cz): the adjoints of x' and v'.
+__device__ __forceinline__ void adj_node_at(const ClothView& cv, const SurfaceView& sv,
+                                            const StepParams& sp, const float* __restrict__ xs,
+                                            const float* __restrict__ vs, int i, float bx,
+                                            float by, float bz, float cx, float cy, float cz,
+                                            uint32_t* list, int hit_slots, float* __restrict__ fb,
+                                            float* __restrict__ xb_part,
+                                            float* __restrict__ vb_part) {
     const int ld = cv.ld;
-    const float xi = xs[i], yi = xs[ld + i], zi = xs[2 * ld + i];
-    const float vxi = vs[i], vyi = vs[ld + i], vzi = vs[2 * ld + i];
     const float w = cv.w[i];
-    const float bx = xb_out[i], by = xb_out[ld + i], bz = xb_out[2 * ld + i];
-    const float cx = vb_out[i], cy = vb_out[ld + i], cz = vb_out[2 * ld + i];
     if (w == 0.0f) {
         xb_part[i] = bx;
         xb_part[ld + i] = by;
@@ -46,6 +43,8 @@ __global__ void __launch_bounds__(256)
         fb[i] = fb[ld + i] = fb[2 * ld + i] = 0.0f;
         return;
     }
+    const float xi = xs[i], yi = xs[ld + i], zi = xs[2 * ld + i];
+    const float vxi = vs[i], vyi = vs[ld + i], vzi = vs[2 * ld + i];
     // recompute the forward prediction exactly as the forward kernels do
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
     gather_global(cv, xs, vs, i, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz);
@@ -62,11 +61,8 @@ __global__ void __launch_bounds__(256)
             az += proj * n.z;
         };
         // the forward kernels' contact set, in their order
-        const int cnt = hit_slots > 0
-                            ? contacts_listed(sv, hit_lds + (threadIdx.x >> 6) * hit_slots * 64 +
-                                                      (threadIdx.x & 63),
-                                              hit_slots, px, py, pz, project)
-                            : contacts_visit(sv, px, py, pz, project);
+        const int cnt = hit_slots > 0 ? contacts_listed(sv, list, hit_slots, px, py, pz, project)
+                                      : contacts_visit(sv, px, py, pz, project);
         if (cnt > 0) {
             const float inv = 1.0f / (float)cnt;
             sx = bx - ax * inv;
@@ -90,22 +86,28 @@ __global__ void __launch_bounds__(256)
     fb[2 * ld + i] = h * w * uz;
 }
 
-__global__ void __launch_bounds__(256)
-    k_adj_springs(const ClothView cv, const float* __restrict__ xs, const float* __restrict__ vs,
-                  const float* __restrict__ fb, const float* __restrict__ xb_part,
-                  const float* __restrict__ vb_part, float* __restrict__ xb_in,
-                  float* __restrict__ vb_in, double* __restrict__ kb, double* __restrict__ cb) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cv.n) return;
+// Spring pass of one substep for node i: the adjoints (g, hv) of the node's state at the
+// substep's start, and the gradients of the springs node i owns.  All of a round's incidence
+// records, then all their neighbours' states and force adjoints, are loaded back to back
+// (indices clamped to the list), then used in incidence order, as the forward gather does.
+__device__ __forceinline__ void adj_springs_at(const ClothView& cv, const float* __restrict__ xs,
+                                               const float* __restrict__ vs,
+                                               const float* __restrict__ fb,
+                                               const float* __restrict__ xb_part,
+                                               const float* __restrict__ vb_part, int i,
+                                               double* __restrict__ kb, double* __restrict__ cb,
+                                               float& gx, float& gy, float& gz, float& hx,
+                                               float& hy, float& hz) {
     const int ld = cv.ld;
     const float xi = xs[i], yi = xs[ld + i], zi = xs[2 * ld + i];
     const float vxi = vs[i], vyi = vs[ld + i], vzi = vs[2 * ld + i];
     const float fbx = fb[i], fby = fb[ld + i], fbz = fb[2 * ld + i];
-    float gx = xb_part[i], gy = xb_part[ld + i], gz = xb_part[2 * ld + i];
-    float hx = vb_part[i], hy = vb_part[ld + i], hz = vb_part[2 * ld + i];
-    // all of a round's incidence records, then all their neighbours' states and force
-    // adjoints, are loaded back to back (indices clamped to the list), then used in
-    // incidence order, as the forward gather does
+    gx = xb_part[i];
+    gy = xb_part[ld + i];
+    gz = xb_part[2 * ld + i];
+    hx = vb_part[i];
+    hy = vb_part[ld + i];
+    hz = vb_part[2 * ld + i];
     constexpr int R = 12;
     const int deg = cv.deg[i];
     const int base = cv.slice_ptr[i >> 6] + (i & 63);
@@ -164,12 +166,79 @@ __global__ void __launch_bounds__(256)
             }
         }
     }
+}
+
+__global__ void __launch_bounds__(256)
+    k_adj_node(const ClothView cv, const SurfaceView sv, const StepParams sp,
+               const float* __restrict__ xs, const float* __restrict__ vs,
+               const float* __restrict__ xb_out, const float* __restrict__ vb_out,
+               float* __restrict__ fb, float* __restrict__ xb_part, float* __restrict__ vb_part,
+               int hit_slots) {
+    extern __shared__ uint32_t hit_lds[];  // per wavefront: wave_query_lds(hit_slots) bytes
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cv.n) return;
+    const int ld = cv.ld;
+    adj_node_at(cv, sv, sp, xs, vs, i, xb_out[i], xb_out[ld + i], xb_out[2 * ld + i], vb_out[i],
+                vb_out[ld + i], vb_out[2 * ld + i],
+                hit_lds + (threadIdx.x >> 6) * hit_slots * 64 + (threadIdx.x & 63), hit_slots, fb,
+                xb_part, vb_part);
+}
+
+__global__ void __launch_bounds__(256)
+    k_adj_springs(const ClothView cv, const float* __restrict__ xs, const float* __restrict__ vs,
+                  const float* __restrict__ fb, const float* __restrict__ xb_part,
+                  const float* __restrict__ vb_part, float* __restrict__ xb_in,
+                  float* __restrict__ vb_in, double* __restrict__ kb, double* __restrict__ cb) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cv.n) return;
+    const int ld = cv.ld;
+    float gx, gy, gz, hx, hy, hz;
+    adj_springs_at(cv, xs, vs, fb, xb_part, vb_part, i, kb, cb, gx, gy, gz, hx, hy, hz);
     xb_in[i] = gx;
     xb_in[ld + i] = gy;
     xb_in[2 * ld + i] = gz;
     vb_in[i] = hx;
     vb_in[ld + i] = hy;
     vb_in[2 * ld + i] = hz;
+}
+
+// Spring pass of substep t fused with the node pass of substep t - 1: the node pass of a
+// node needs only that node's own adjoints from the spring pass, so one launch does both.
+// (xs_a, vs_a): the state at the start of substep t; (xs_b, vs_b): at the start of
+// substep t - 1.  fb_t is read (the neighbours' values) and fb_prev written, so they are
+// distinct buffers; xb_part / vb_part are read and then rewritten by the same thread.
+// gout: when an output is recorded at the state between the two substeps, its loss adjoint
+// in caller order (AoS), added before the node pass as the import kernel adds it.
+__global__ void __launch_bounds__(256)
+    k_adj_fused(const ClothView cv, const SurfaceView sv, const StepParams sp,
+                const float* __restrict__ xs_a, const float* __restrict__ vs_a,
+                const float* __restrict__ xs_b, const float* __restrict__ vs_b,
+                const float* __restrict__ fb_t, float* __restrict__ fb_prev,
+                float* __restrict__ xb_part, float* __restrict__ vb_part,
+                float* __restrict__ xb, float* __restrict__ vb, double* __restrict__ kb,
+                double* __restrict__ cb, const float* __restrict__ gout,
+                const int* __restrict__ order, int hit_slots) {
+    extern __shared__ uint32_t hit_lds[];  // per wavefront: wave_query_lds(hit_slots) bytes
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cv.n) return;
+    const int ld = cv.ld;
+    float gx, gy, gz, hx, hy, hz;
+    adj_springs_at(cv, xs_a, vs_a, fb_t, xb_part, vb_part, i, kb, cb, gx, gy, gz, hx, hy, hz);
+    if (gout) {
+        const size_t id = (size_t)order[i];
+        gx = gx + gout[3 * id];
+        gy = gy + gout[3 * id + 1];
+        gz = gz + gout[3 * id + 2];
+    }
+    xb[i] = gx;
+    xb[ld + i] = gy;
+    xb[2 * ld + i] = gz;
+    vb[i] = hx;
+    vb[ld + i] = hy;
+    vb[2 * ld + i] = hz;
+    adj_node_at(cv, sv, sp, xs_b, vs_b, i, gx, gy, gz, hx, hy, hz,
+                hit_lds + (threadIdx.x >> 6) * hit_slots * 64 + (threadIdx.x & 63), hit_slots,
+                fb_prev, xb_part, vb_part);
 }
 
 // Contact set each node would get in a substep of length h from (xs, vs): counts[slot] and
@@ -274,6 +343,20 @@ hipError_t launch_adj_node(const ClothView& cv, const SurfaceView& sv, const Ste
     const size_t lds = (size_t)(256 / 64) * wave_query_lds(hit_slots);  // at most 64 KiB
     k_adj_node<<<blocks(cv.n, 256), 256, lds, st>>>(cv, sv, sp, xs, vs, xb_out, vb_out, fb,
                                                     xb_part, vb_part, hit_slots);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_fused(const ClothView& cv, const SurfaceView& sv, const StepParams& sp,
+                            const float* xs_a, const float* vs_a, const float* xs_b,
+                            const float* vs_b, const float* fb_t, float* fb_prev, float* xb_part,
+                            float* vb_part, float* xb, float* vb, double* kb, double* cb,
+                            const float* gout, const int* order, int hit_slots, hipStream_t st) {
+    if (cv.n <= 0) return hipSuccess;
+    if (hit_slots < 0 || hit_slots > kMaxHitSlots) hit_slots = 0;
+    const size_t lds = (size_t)(256 / 64) * wave_query_lds(hit_slots);  // at most 64 KiB
+    k_adj_fused<<<blocks(cv.n, 256), 256, lds, st>>>(cv, sv, sp, xs_a, vs_a, xs_b, vs_b, fb_t,
+                                                     fb_prev, xb_part, vb_part, xb, vb, kb, cb,
+                                                     gout, order, hit_slots);
     return hipGetLastError();
 }
 

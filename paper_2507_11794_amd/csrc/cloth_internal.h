@@ -195,6 +195,13 @@ hipError_t launch_adj_node(const ClothView& cv, const SurfaceView& sv, const Ste
                            const float* vb_out, float* fb, float* xb_part, float* vb_part,
                            int hit_slots, hipStream_t st);
 // Spring-force transpose: xb_in / vb_in = partial + spring terms; adds dL/dk, dL/dc.
+// The spring pass of substep t and the node pass of substep t - 1 in one launch (see
+// k_adj_fused); gout: an output's loss adjoint added between them, or NULL.
+hipError_t launch_adj_fused(const ClothView& cv, const SurfaceView& sv, const StepParams& sp,
+                            const float* xs_a, const float* vs_a, const float* xs_b,
+                            const float* vs_b, const float* fb_t, float* fb_prev, float* xb_part,
+                            float* vb_part, float* xb, float* vb, double* kb, double* cb,
+                            const float* gout, const int* order, int hit_slots, hipStream_t st);
 hipError_t launch_adj_springs(const ClothView& cv, const float* xs, const float* vs,
                               const float* fb, const float* xb_part, const float* vb_part,
                               float* xb_in, float* vb_in, double* kb, double* cb, hipStream_t st);

@@ -161,11 +161,12 @@ int cloth_rollout_backward(cloth_sim* s, const float* gx_out_dev, float* gk_dev,
             (e = R.arena.alloc(&R.cb, S + 1)))
             return hip_fail(e, "hipMalloc adjoint buffers");
     }
+    int st = ensure_topology(s);  // the slot -> node order, for outputs added in a fused launch
+    if (st != CLOTH_OK) return st;
     float* xb = R.adj;
     float* vb = R.adj + 3 * ld;
-    float* xb2 = R.adj + 6 * ld;
-    float* vb2 = R.adj + 9 * ld;
-    float* fb = R.adj + 12 * ld;
+    float* fb = R.adj + 6 * ld;
+    float* fb2 = R.adj + 9 * ld;
     float* xbp = R.adj + 15 * ld;
     float* vbp = R.adj + 18 * ld;
     if ((e = hipMemsetAsync(xb, 0, 4 * 6 * ld, s->stream)) ||
@@ -199,16 +200,38 @@ int cloth_rollout_backward(cloth_sim* s, const float* gx_out_dev, float* gk_dev,
                                     s->launch.hit_slots)))
                 return hip_fail(e, "recompute segment");
         }
+        // (xb, vb) hold the adjoint of the state after substep top.  The node pass of
+        // substep t needs the state before it, s[t - 1]; the spring pass of substep t and the
+        // node pass of substep t - 1 run as one launch while both states are in the segment.
+        const SurfaceView& sv0 = s->surfs[0].view;
+        const int slots = s->launch.hit_slots;
+        auto state_at = [&](long long t) { return R.seg + (size_t)(t - base) * state; };
+        if ((e = launch_adj_node(cv, sv0, sp, state_at(top - 1), state_at(top - 1) + 3 * ld, xb, vb,
+                                 fb, xbp, vbp, slots, s->stream)))
+            return hip_fail(e, "adjoint substep");
         for (long long t = top; t > base; --t) {
-            const float* xs = R.seg + (size_t)(t - 1 - base) * state;
-            if ((e = launch_adj_node(cv, s->surfs[0].view, sp, xs, xs + 3 * ld, xb, vb, fb, xbp, vbp,
-                                     s->launch.hit_slots, s->stream)) ||
-                (e = launch_adj_springs(cv, xs, xs + 3 * ld, fb, xbp, vbp, xb2, vb2, R.kb, R.cb,
-                                        s->stream)))
-                return hip_fail(e, "adjoint substep");
-            std::swap(xb, xb2);
-            std::swap(vb, vb2);
-            if ((e = add_outputs(t - 1))) return hip_fail(e, "add output adjoint");
+            const float* xa = state_at(t - 1);
+            int outs = 0;  // outputs recorded at the state between substeps t - 1 and t
+            while (j - outs >= 0 && R.out_sub[j - outs] == t - 1) ++outs;
+            if (t - 1 > base && outs <= 1) {
+                const float* xbs = state_at(t - 2);
+                const float* gout = outs ? gx_out_dev + (size_t)j * 3 * N : nullptr;
+                if ((e = launch_adj_fused(cv, sv0, sp, xa, xa + 3 * ld, xbs, xbs + 3 * ld, fb, fb2,
+                                          xbp, vbp, xb, vb, R.kb, R.cb, gout, s->order_dev,
+                                          slots, s->stream)))
+                    return hip_fail(e, "adjoint substep");
+                j -= outs;
+                std::swap(fb, fb2);
+            } else {
+                if ((e = launch_adj_springs(cv, xa, xa + 3 * ld, fb, xbp, vbp, xb, vb, R.kb, R.cb,
+                                            s->stream)) ||
+                    (e = add_outputs(t - 1)))
+                    return hip_fail(e, "adjoint substep");
+                if (t - 1 > base &&
+                    (e = launch_adj_node(cv, sv0, sp, state_at(t - 2), state_at(t - 2) + 3 * ld, xb,
+                                         vb, fb, xbp, vbp, slots, s->stream)))
+                    return hip_fail(e, "adjoint substep");
+            }
         }
     }
     if ((gv0_dev && (e = launch_export(N, (int)ld, s->slot_dev, vb, gv0_dev, s->stream))) ||
