@@ -30,8 +30,9 @@ __device__ __forceinline__ void adj_node_at(const ClothView& cv, const SurfaceVi
                                             const StepParams& sp, const float* __restrict__ xs,
                                             const float* __restrict__ vs, int i, float bx,
                                             float by, float bz, float cx, float cy, float cz,
-                                            uint32_t* list, int hit_slots, float* __restrict__ fb,
-                                            float* __restrict__ xb_part,
+                                            uint32_t* list, int hit_slots,
+                                            const float* __restrict__ pred,
+                                            float* __restrict__ fb, float* __restrict__ xb_part,
                                             float* __restrict__ vb_part) {
     const int ld = cv.ld;
     const float w = cv.w[i];
@@ -43,14 +44,20 @@ __device__ __forceinline__ void adj_node_at(const ClothView& cv, const SurfaceVi
         fb[i] = fb[ld + i] = fb[2 * ld + i] = 0.0f;
         return;
     }
-    const float xi = xs[i], yi = xs[ld + i], zi = xs[2 * ld + i];
-    const float vxi = vs[i], vyi = vs[ld + i], vzi = vs[2 * ld + i];
-    // recompute the forward prediction exactly as the forward kernels do
-    float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-    gather_global(cv, xs, vs, i, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz);
-    add_external(sp, i, fx, fy, fz);
-    float px, py, pz, qx, qy, qz;
-    integrate(w, sp.h, sp.g, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz, px, py, pz, qx, qy, qz);
+    float px, py, pz;
+    if (pred) {  // the forward prediction, stored by the recompute
+        px = pred[i];
+        py = pred[ld + i];
+        pz = pred[2 * ld + i];
+    } else {  // recompute it exactly as the forward kernels do
+        const float xi = xs[i], yi = xs[ld + i], zi = xs[2 * ld + i];
+        const float vxi = vs[i], vyi = vs[ld + i], vzi = vs[2 * ld + i];
+        float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+        gather_global(cv, xs, vs, i, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz);
+        add_external(sp, i, fx, fy, fz);
+        float qx, qy, qz;
+        integrate(w, sp.h, sp.g, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz, px, py, pz, qx, qy, qz);
+    }
     float sx = bx, sy = by, sz = bz, tx = cx, ty = cy, tz = cz;
     if (sv.n_tris > 0) {
         float ax = 0.0f, ay = 0.0f, az = 0.0f;
@@ -173,15 +180,15 @@ __global__ void __launch_bounds__(256)
                const float* __restrict__ xs, const float* __restrict__ vs,
                const float* __restrict__ xb_out, const float* __restrict__ vb_out,
                float* __restrict__ fb, float* __restrict__ xb_part, float* __restrict__ vb_part,
-               int hit_slots) {
+               int hit_slots, const float* __restrict__ pred) {
     extern __shared__ uint32_t hit_lds[];  // per wavefront: wave_query_lds(hit_slots) bytes
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cv.n) return;
     const int ld = cv.ld;
     adj_node_at(cv, sv, sp, xs, vs, i, xb_out[i], xb_out[ld + i], xb_out[2 * ld + i], vb_out[i],
                 vb_out[ld + i], vb_out[2 * ld + i],
-                hit_lds + (threadIdx.x >> 6) * hit_slots * 64 + (threadIdx.x & 63), hit_slots, fb,
-                xb_part, vb_part);
+                hit_lds + (threadIdx.x >> 6) * hit_slots * 64 + (threadIdx.x & 63), hit_slots,
+                pred, fb, xb_part, vb_part);
 }
 
 __global__ void __launch_bounds__(256)
@@ -205,15 +212,17 @@ __global__ void __launch_bounds__(256)
 // Spring pass of substep t fused with the node pass of substep t - 1: the node pass of a
 // node needs only that node's own adjoints from the spring pass, so one launch does both.
 // (xs_a, vs_a): the state at the start of substep t; (xs_b, vs_b): at the start of
-// substep t - 1.  fb_t is read (the neighbours' values) and fb_prev written, so they are
-// distinct buffers; xb_part / vb_part are read and then rewritten by the same thread.
+// substep t - 1, pred_b the prediction of substep t - 1 (or NULL to recompute it).  fb_t is
+// read (the neighbours' values) and fb_prev written, so they are distinct buffers; xb_part /
+// vb_part are read and then rewritten by the same thread.
 // gout: when an output is recorded at the state between the two substeps, its loss adjoint
 // in caller order (AoS), added before the node pass as the import kernel adds it.
 __global__ void __launch_bounds__(256)
     k_adj_fused(const ClothView cv, const SurfaceView sv, const StepParams sp,
                 const float* __restrict__ xs_a, const float* __restrict__ vs_a,
                 const float* __restrict__ xs_b, const float* __restrict__ vs_b,
-                const float* __restrict__ fb_t, float* __restrict__ fb_prev,
+                const float* __restrict__ pred_b, const float* __restrict__ fb_t,
+                float* __restrict__ fb_prev,
                 float* __restrict__ xb_part, float* __restrict__ vb_part,
                 float* __restrict__ xb, float* __restrict__ vb, double* __restrict__ kb,
                 double* __restrict__ cb, const float* __restrict__ gout,
@@ -238,7 +247,7 @@ __global__ void __launch_bounds__(256)
     vb[2 * ld + i] = hz;
     adj_node_at(cv, sv, sp, xs_b, vs_b, i, gx, gy, gz, hx, hy, hz,
                 hit_lds + (threadIdx.x >> 6) * hit_slots * 64 + (threadIdx.x & 63), hit_slots,
-                fb_prev, xb_part, vb_part);
+                pred_b, fb_prev, xb_part, vb_part);
 }
 
 // Contact set each node would get in a substep of length h from (xs, vs): counts[slot] and
@@ -337,26 +346,27 @@ inline unsigned blocks(size_t n, int b) { return (unsigned)((n + b - 1) / b); }
 hipError_t launch_adj_node(const ClothView& cv, const SurfaceView& sv, const StepParams& sp,
                            const float* xs, const float* vs, const float* xb_out,
                            const float* vb_out, float* fb, float* xb_part, float* vb_part,
-                           int hit_slots, hipStream_t st) {
+                           int hit_slots, const float* pred, hipStream_t st) {
     if (cv.n <= 0) return hipSuccess;
     if (hit_slots < 0 || hit_slots > kMaxHitSlots) hit_slots = 0;
     const size_t lds = (size_t)(256 / 64) * wave_query_lds(hit_slots);  // at most 64 KiB
     k_adj_node<<<blocks(cv.n, 256), 256, lds, st>>>(cv, sv, sp, xs, vs, xb_out, vb_out, fb,
-                                                    xb_part, vb_part, hit_slots);
+                                                    xb_part, vb_part, hit_slots, pred);
     return hipGetLastError();
 }
 
 hipError_t launch_adj_fused(const ClothView& cv, const SurfaceView& sv, const StepParams& sp,
                             const float* xs_a, const float* vs_a, const float* xs_b,
-                            const float* vs_b, const float* fb_t, float* fb_prev, float* xb_part,
-                            float* vb_part, float* xb, float* vb, double* kb, double* cb,
-                            const float* gout, const int* order, int hit_slots, hipStream_t st) {
+                            const float* vs_b, const float* pred_b, const float* fb_t,
+                            float* fb_prev, float* xb_part, float* vb_part, float* xb, float* vb,
+                            double* kb, double* cb, const float* gout, const int* order,
+                            int hit_slots, hipStream_t st) {
     if (cv.n <= 0) return hipSuccess;
     if (hit_slots < 0 || hit_slots > kMaxHitSlots) hit_slots = 0;
     const size_t lds = (size_t)(256 / 64) * wave_query_lds(hit_slots);  // at most 64 KiB
-    k_adj_fused<<<blocks(cv.n, 256), 256, lds, st>>>(cv, sv, sp, xs_a, vs_a, xs_b, vs_b, fb_t,
-                                                     fb_prev, xb_part, vb_part, xb, vb, kb, cb,
-                                                     gout, order, hit_slots);
+    k_adj_fused<<<blocks(cv.n, 256), 256, lds, st>>>(cv, sv, sp, xs_a, vs_a, xs_b, vs_b, pred_b,
+                                                     fb_t, fb_prev, xb_part, vb_part, xb, vb, kb,
+                                                     cb, gout, order, hit_slots);
     return hipGetLastError();
 }
 

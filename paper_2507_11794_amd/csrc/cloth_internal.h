@@ -134,7 +134,8 @@ inline int xcd_grid(int n_logical, int xcd_runs) {
 }
 // LDS bytes one wavefront's collision query uses for its lanes' hit lists.
 constexpr size_t wave_query_lds(int hit_slots) { return (size_t)hit_slots * 64 * 4; }
-// xcd_runs: give each XCD a contiguous run of workgroups (else the hardware's order).
+// xcd_runs: the workgroup-to-XCD mapping (see xcd_block; 0 = the hardware's order).
+// pred: if non-NULL, receives every node's prediction before collision (SoA, ld).
 // split_refs > 0: nodes whose cell lists more than split_refs references are resolved by a
 // second launch with four lanes per node (launch_heavy).  heavy holds two counters, then two
 // node lists of ld entries at kHeavyListOff; the first pass appends to list `parity`, the
@@ -146,8 +147,8 @@ constexpr size_t heavy_words(int ld) { return kHeavyListOff + 2 * (size_t)ld; }
 hipError_t launch_substep(const ClothView& cv, int collide, const StepParams& sp, const float* xs,
                           const float* vs, float* xd, float* vd, int block, hipStream_t stream,
                           const SurfaceView* svs, const int* node_group = nullptr,
-                          int hit_slots = 0, int xcd_runs = 1, int split_refs = 0,
-                          int* heavy = nullptr, int parity = 0);
+                          int hit_slots = 0, int xcd_runs = 0, int split_refs = 0,
+                          int* heavy = nullptr, int parity = 0, float* pred = nullptr);
 // The second pass over list `parity` of heavy (see launch_substep): each listed node's
 // prediction is in (xd, vd) and is replaced by the collision-resolved state.
 hipError_t launch_heavy(const ClothView& cv, const StepParams& sp, int* heavy, int parity,
@@ -189,19 +190,21 @@ hipError_t launch_mt_debug_contacts(const ClothView& cv, const StepParams& sp,
 // --- a6 adjoint ----------------------------------------------------------------------------
 // Response and integration transpose of one substep at state (xs, vs): partial adjoints and
 // the force adjoint fb = h w vtot (see adjoint.hip).
-// hit_slots: the contact search's LDS list (0 = unlisted search); the results are the same.
+// hit_slots: the contact search's LDS list (0 = unlisted search); pred: the forward
+// prediction stored by launch_substep, or NULL to recompute it.  The results are the same.
 hipError_t launch_adj_node(const ClothView& cv, const SurfaceView& sv, const StepParams& sp,
                            const float* xs, const float* vs, const float* xb_out,
                            const float* vb_out, float* fb, float* xb_part, float* vb_part,
-                           int hit_slots, hipStream_t st);
+                           int hit_slots, const float* pred, hipStream_t st);
 // Spring-force transpose: xb_in / vb_in = partial + spring terms; adds dL/dk, dL/dc.
 // The spring pass of substep t and the node pass of substep t - 1 in one launch (see
 // k_adj_fused); gout: an output's loss adjoint added between them, or NULL.
 hipError_t launch_adj_fused(const ClothView& cv, const SurfaceView& sv, const StepParams& sp,
                             const float* xs_a, const float* vs_a, const float* xs_b,
-                            const float* vs_b, const float* fb_t, float* fb_prev, float* xb_part,
-                            float* vb_part, float* xb, float* vb, double* kb, double* cb,
-                            const float* gout, const int* order, int hit_slots, hipStream_t st);
+                            const float* vs_b, const float* pred_b, const float* fb_t,
+                            float* fb_prev, float* xb_part, float* vb_part, float* xb, float* vb,
+                            double* kb, double* cb, const float* gout, const int* order,
+                            int hit_slots, hipStream_t st);
 hipError_t launch_adj_springs(const ClothView& cv, const float* xs, const float* vs,
                               const float* fb, const float* xb_part, const float* vb_part,
                               float* xb_in, float* vb_in, double* kb, double* cb, hipStream_t st);

@@ -107,6 +107,7 @@ int cloth_rollout_forward(cloth_sim* s, const float* k_dev, const float* c_dev,
     if ((e = hipStreamSynchronize(s->stream))) return hip_fail(e, "synchronise");
     R.arena.release();
     R.seg = nullptr;
+    R.pred = nullptr;
     R.adj = nullptr;
     R.kb = R.cb = nullptr;
     if ((e = R.arena.alloc(&R.ck, (size_t)R.n_ck * state)))
@@ -157,6 +158,7 @@ int cloth_rollout_backward(cloth_sim* s, const float* gx_out_dev, float* gk_dev,
     hipError_t e;
     if (!R.seg) {
         if ((e = R.arena.alloc(&R.seg, (size_t)(R.ckpt + 1) * state)) ||
+            (e = R.arena.alloc(&R.pred, (size_t)R.ckpt * 3 * ld)) ||
             (e = R.arena.alloc(&R.adj, 7 * 3 * ld)) || (e = R.arena.alloc(&R.kb, S + 1)) ||
             (e = R.arena.alloc(&R.cb, S + 1)))
             return hip_fail(e, "hipMalloc adjoint buffers");
@@ -191,13 +193,16 @@ int cloth_rollout_backward(cloth_sim* s, const float* gx_out_dev, float* gk_dev,
         if ((e = hipMemcpyAsync(R.seg, R.ck + (size_t)seg * state, 4 * state,
                                 hipMemcpyDeviceToDevice, s->stream)))
             return hip_fail(e, "restore checkpoint");
-        for (long long r = 1; r < top - base; ++r) {
+        // the segment's states and every substep's prediction (substep r of the segment
+        // stores it at pred[r - 1]); the listed collision query, as the forward pass (any
+        // launch gives the same bits)
+        for (long long r = 1; r <= top - base; ++r) {
             const float* xs = R.seg + (size_t)(r - 1) * state;
             float* xd = R.seg + (size_t)r * state;
-            // the listed collision query, as the forward pass (any launch gives the same bits)
             if ((e = launch_substep(cv, s->surfs[0].view.n_tris > 0, sp, xs, xs + 3 * ld, xd,
                                     xd + 3 * ld, 256, s->stream, s->svs_dev, nullptr,
-                                    s->launch.hit_slots)))
+                                    s->launch.hit_slots, 0, 0, nullptr, 0,
+                                    R.pred + (size_t)(r - 1) * 3 * ld)))
                 return hip_fail(e, "recompute segment");
         }
         // (xb, vb) hold the adjoint of the state after substep top.  The node pass of
@@ -206,8 +211,9 @@ int cloth_rollout_backward(cloth_sim* s, const float* gx_out_dev, float* gk_dev,
         const SurfaceView& sv0 = s->surfs[0].view;
         const int slots = s->launch.hit_slots;
         auto state_at = [&](long long t) { return R.seg + (size_t)(t - base) * state; };
+        auto pred_of = [&](long long t) { return R.pred + (size_t)(t - 1 - base) * 3 * ld; };
         if ((e = launch_adj_node(cv, sv0, sp, state_at(top - 1), state_at(top - 1) + 3 * ld, xb, vb,
-                                 fb, xbp, vbp, slots, s->stream)))
+                                 fb, xbp, vbp, slots, pred_of(top), s->stream)))
             return hip_fail(e, "adjoint substep");
         for (long long t = top; t > base; --t) {
             const float* xa = state_at(t - 1);
@@ -216,9 +222,9 @@ int cloth_rollout_backward(cloth_sim* s, const float* gx_out_dev, float* gk_dev,
             if (t - 1 > base && outs <= 1) {
                 const float* xbs = state_at(t - 2);
                 const float* gout = outs ? gx_out_dev + (size_t)j * 3 * N : nullptr;
-                if ((e = launch_adj_fused(cv, sv0, sp, xa, xa + 3 * ld, xbs, xbs + 3 * ld, fb, fb2,
-                                          xbp, vbp, xb, vb, R.kb, R.cb, gout, s->order_dev,
-                                          slots, s->stream)))
+                if ((e = launch_adj_fused(cv, sv0, sp, xa, xa + 3 * ld, xbs, xbs + 3 * ld,
+                                          pred_of(t - 1), fb, fb2, xbp, vbp, xb, vb, R.kb, R.cb,
+                                          gout, s->order_dev, slots, s->stream)))
                     return hip_fail(e, "adjoint substep");
                 j -= outs;
                 std::swap(fb, fb2);
@@ -229,7 +235,7 @@ int cloth_rollout_backward(cloth_sim* s, const float* gx_out_dev, float* gk_dev,
                     return hip_fail(e, "adjoint substep");
                 if (t - 1 > base &&
                     (e = launch_adj_node(cv, sv0, sp, state_at(t - 2), state_at(t - 2) + 3 * ld, xb,
-                                         vb, fb, xbp, vbp, slots, s->stream)))
+                                         vb, fb, xbp, vbp, slots, pred_of(t - 1), s->stream)))
                     return hip_fail(e, "adjoint substep");
             }
         }

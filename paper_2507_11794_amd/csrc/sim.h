@@ -43,7 +43,8 @@ struct RolloutState {
     float* ck = nullptr;             // checkpoints: [n_ck][6][ld] (x then v)
     long long n_ck = 0;
     float* seg = nullptr;    // one segment of states: [ckpt + 1][6][ld]
-    float* adj = nullptr;    // xb[2], vb[2], fb, xb_part, vb_part: 7 x [3][ld]
+    float* pred = nullptr;   // the segment's predictions before collision: [ckpt][3][ld]
+    float* adj = nullptr;    // xb, vb, fb[2], (unused), xb_part, vb_part: 7 x [3][ld]
     double* kb = nullptr;    // [S]
     double* cb = nullptr;    // [S]
 };

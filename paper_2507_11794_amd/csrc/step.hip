@@ -20,7 +20,7 @@ __global__ void __launch_bounds__(256)
               const float* __restrict__ vs, float* __restrict__ xd, float* __restrict__ vd,
               const SurfaceView* __restrict__ svs, const int* __restrict__ node_group,
               const int hit_slots, const int xcd_runs, const int split_refs,
-              int* __restrict__ heavy, const int parity) {
+              int* __restrict__ heavy, const int parity, float* __restrict__ pred) {
     extern __shared__ uint32_t hit_lds[];  // per wavefront: wave_query_lds(hit_slots) bytes
     const int i = xcd_block(xcd_runs, (cv.n + blockDim.x - 1) / blockDim.x) * blockDim.x +
                   threadIdx.x;
@@ -37,6 +37,11 @@ __global__ void __launch_bounds__(256)
         add_external(sp, i, fx, fy, fz);
         // a2: integrate
         integrate(w, sp.h, sp.g, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz, px, py, pz, qx, qy, qz);
+        if (pred) {  // the prediction before collision, for the adjoint
+            pred[i] = px;
+            pred[ld + i] = py;
+            pred[2 * ld + i] = pz;
+        }
     }
     // a3 + a4: broad phase, narrow phase, response
     int is_heavy = 0;
@@ -98,7 +103,7 @@ hipError_t prepare_substep_kernels(size_t lds_bytes) {
 hipError_t launch_substep(const ClothView& cv, int collide, const StepParams& sp, const float* xs,
                           const float* vs, float* xd, float* vd, int block, hipStream_t stream,
                           const SurfaceView* svs, const int* node_group, int hit_slots,
-                          int xcd_runs, int split_refs, int* heavy, int parity) {
+                          int xcd_runs, int split_refs, int* heavy, int parity, float* pred) {
     if (cv.n <= 0) return hipSuccess;
     if (block <= 0 || block > 256 || (block & 63)) block = 256;
     if (xcd_runs < 0 || xcd_runs > kMaxXcdRuns) xcd_runs = 0;
@@ -107,13 +112,15 @@ hipError_t launch_substep(const ClothView& cv, int collide, const StepParams& sp
     const size_t lds = collide ? (size_t)(block / 64) * wave_query_lds(hit_slots) : 0;
     if (collide && node_group) {
         k_substep<true, true><<<grid, block, lds, stream>>>(cv, sp, xs, vs, xd, vd, svs, node_group,
-                                                            hit_slots, xcd_runs, split_refs, heavy, parity);
+                                                            hit_slots, xcd_runs, split_refs, heavy, parity,
+                                                            pred);
     } else if (collide) {
         k_substep<true, false><<<grid, block, lds, stream>>>(cv, sp, xs, vs, xd, vd, svs, nullptr,
-                                                             hit_slots, xcd_runs, split_refs, heavy, parity);
+                                                             hit_slots, xcd_runs, split_refs, heavy, parity,
+                                                            pred);
     } else {
         k_substep<false, false><<<grid, block, 0, stream>>>(cv, sp, xs, vs, xd, vd, svs, nullptr,
-                                                            0, xcd_runs, 0, nullptr, 0);
+                                                            0, xcd_runs, 0, nullptr, 0, pred);
     }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && split_refs > 0)
