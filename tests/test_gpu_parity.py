@@ -10,6 +10,8 @@ must stay within 1e-5 of the cloth side length.  A contact decision with |dist -
 1e-6 m of the threshold may legitimately differ between FP32 and FP64; such nodes are
 checked against every valid resolution of their near-threshold triangles.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -83,9 +85,16 @@ def _tiny_surfaces():
     yield W.small_collision_scene(n=8, freq=6)
     c1 = W.config1(n=20, freq=4)
     yield c1
+    # a grid of more cells than a workgroup can count in LDS, with the triangles in a random
+    # order: every workgroup's cell box spans the grid, so the build takes its global-atomic
+    # path (the surface in mesh order takes the LDS path)
+    c2 = W.config1(n=20, freq=24)
+    yield c2
+    perm = np.random.default_rng(5).permutation(c2.tris.shape[0])
+    yield dataclasses.replace(c2, tris=np.ascontiguousarray(c2.tris[perm]))
 
 
-@pytest.mark.parametrize("which", [0, 1, 2])
+@pytest.mark.parametrize("which", [0, 1, 2, 3, 4])
 def test_broadphase_candidates_equal_fp32_brute_force(which):
     inp = list(_tiny_surfaces())[which]
     rng = np.random.default_rng(100 + which)
