@@ -159,8 +159,14 @@ __global__ void __launch_bounds__(256)
                     for (int cx = q0x; cx <= q1x; ++cx) {
                         const int cell = (cz * sv.dim[1] + cy) * sv.dim[0] + cx;
                         const uint32_t b = gmem(sv.cell_start)[cell], e = gmem(sv.cell_start)[cell + 1];
+                        // each reference's box is loaded one iteration ahead (the padding after
+                        // the last reference keeps the look-ahead in bounds), so its latency
+                        // overlaps the tests of the current candidate
+                        float4 nlo = ldg4(sv.ref_lo, b), nhi = ldg4(sv.ref_hi, b);
                         for (uint32_t rr = b; rr < e; ++rr) {
-                            const float4 blo = ldg4(sv.ref_lo, rr), bhi = ldg4(sv.ref_hi, rr);
+                            const float4 blo = nlo, bhi = nhi;
+                            nlo = ldg4(sv.ref_lo, rr + 1);
+                            nhi = ldg4(sv.ref_hi, rr + 1);
                             if (bhi.x < lo.x || blo.x > hi.x || bhi.y < lo.y || blo.y > hi.y ||
                                 bhi.z < lo.z || blo.z > hi.z)
                                 continue;
