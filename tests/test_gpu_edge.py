@@ -1,0 +1,100 @@
+"""Edge cases of the HIP path through the C ABI: a single node without springs landing on a
+single triangle, a one-node-wide strip, a cloth of one wavefront plus one node (ragged last
+wavefront) over a surface, a fully pinned cloth, and a zero-frame step.  Each is checked
+against the FP64 oracle (one substep at a time where contacts occur) or against the exact
+invariant."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.parity import substep_parity
+from paper_2507_11794_amd import cloth as B
+from paper_2507_11794_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def h32(inp):
+    return float(np.float32(np.float32(inp.dt) / np.float32(inp.n_substeps)))
+
+
+def _floor(size=0.5, y=0.0):
+    """One upward-facing triangle (counter-clockwise seen from +y) covering the origin."""
+    verts = np.array([[-size, y, -size], [-size, y, 2 * size], [2 * size, y, -size]],
+                     dtype=np.float32)
+    return verts, np.array([[0, 1, 2]], dtype=np.int32)
+
+
+def _scene(nx, ny, drop, spacing=0.01, pins=(), surface=True, n_steps=40, seed=3):
+    rng = np.random.default_rng(seed)
+    cloth = W.make_cloth(nx, ny, spacing, (0.0, drop, 0.0), W.K_STRUCT, W.K_SHEAR, W.K_BEND,
+                         W.DAMPING, W.NODE_MASS, pins=list(pins), rng=rng)
+    if not surface:
+        return W._inputs(cloth, dt=1.0 / 600.0, n_substeps=4, n_steps=n_steps, name="edge")
+    verts, tris = _floor()
+    return W._inputs(cloth, verts, tris, thickness=0.005, cell_size=0.05, dt=1.0 / 600.0,
+                     n_substeps=4, n_steps=n_steps, name="edge")
+
+
+def _run_with_parity(inp, frames):
+    """Step frame by frame, checking one substep against the oracle after every frame;
+    returns the final state and the contacts seen."""
+    model = oracle.Model.from_inputs(inp)
+    L = max(float(np.max(np.ptp(inp.x0.astype(np.float64), axis=0))), 0.01)
+    contacts = 0
+    with B.Cloth(inp) as sim:
+        for _ in range(frames):
+            sim.step(n_steps=1)
+            x, v = sim.read_state()
+            sim.step(dt=h32(inp), n_substeps=1, n_steps=1)
+            x1, v1 = sim.read_state()
+            r = substep_parity(model, x, v, h32(inp), x1, v1, L, border=1e-6, tag="edge")
+            contacts += r["contacts"]
+        return sim.read_state(), contacts
+
+
+def test_single_node_without_springs_lands_at_the_thickness():
+    inp = _scene(1, 1, drop=0.02, n_steps=120)
+    assert inp.ends.shape[0] == 0
+    (x, v), contacts = _run_with_parity(inp, 120)
+    assert contacts > 0
+    # resting on the plane y = 0 at the thickness, up to one substep of gravity
+    h = h32(inp)
+    assert abs(float(x[0, 1]) - 0.005) <= 9.81 * h * h * 4
+
+
+def test_strip_one_node_wide_matches_oracle_trajectory():
+    inp = _scene(1, 37, drop=0.5, surface=False, pins=[(0, 0)], n_steps=50)
+    with B.Cloth(inp) as sim:
+        sim.step(n_steps=inp.n_steps)
+        x, _ = sim.read_state()
+    model = oracle.Model.from_inputs(inp)
+    xr, _ = model.run(inp.x0, inp.v0, h32(inp), inp.n_steps * inp.n_substeps)
+    side = float(np.max(np.ptp(inp.x0.astype(np.float64), axis=0)))
+    assert np.abs(x.astype(np.float64) - xr).max() <= 1e-5 * side
+
+
+def test_one_wavefront_plus_one_node_over_a_triangle():
+    inp = _scene(13, 5, drop=0.012, spacing=0.008, n_steps=30)
+    assert inp.n_nodes == 65
+    _, contacts = _run_with_parity(inp, 30)
+    assert contacts > 0
+
+
+def test_fully_pinned_cloth_does_not_move():
+    pins = [(r, c) for r in range(6) for c in range(7)]
+    inp = _scene(7, 6, drop=0.003, pins=pins, n_steps=10)
+    with B.Cloth(inp) as sim:
+        sim.step(n_steps=10)
+        x, v = sim.read_state()
+    assert np.array_equal(x, inp.x0) and np.all(v == 0)
+
+
+def test_zero_frames_leave_the_state_unchanged():
+    inp = _scene(8, 8, drop=0.05, n_steps=5)
+    with B.Cloth(inp) as sim:
+        sim.step(n_steps=3)
+        before = sim.read_state()
+        sim.step(n_steps=0)
+        after = sim.read_state()
+    assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
