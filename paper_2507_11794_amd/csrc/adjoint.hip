@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(256)
     const int ld = cv.ld;
     adj_node_at(cv, sv, sp, xs, vs, i, xb_out[i], xb_out[ld + i], xb_out[2 * ld + i], vb_out[i],
                 vb_out[ld + i], vb_out[2 * ld + i],
-                hit_lds + (threadIdx.x >> 6) * hit_slots * 64 + (threadIdx.x & 63), hit_slots,
+                hit_lds + (threadIdx.x >> 6) * list_stride(hit_slots) + (threadIdx.x & 63), hit_slots,
                 pred, fb, xb_part, vb_part);
 }
 
@@ -246,7 +246,7 @@ __global__ void __launch_bounds__(256)
     vb[ld + i] = hy;
     vb[2 * ld + i] = hz;
     adj_node_at(cv, sv, sp, xs_b, vs_b, i, gx, gy, gz, hx, hy, hz,
-                hit_lds + (threadIdx.x >> 6) * hit_slots * 64 + (threadIdx.x & 63), hit_slots,
+                hit_lds + (threadIdx.x >> 6) * list_stride(hit_slots) + (threadIdx.x & 63), hit_slots,
                 pred_b, fb_prev, xb_part, vb_part);
 }
 
@@ -349,7 +349,10 @@ hipError_t launch_adj_node(const ClothView& cv, const SurfaceView& sv, const Ste
                            int hit_slots, const float* pred, hipStream_t st) {
     if (cv.n <= 0) return hipSuccess;
     if (hit_slots < 0 || hit_slots > kMaxHitSlots) hit_slots = 0;
-    const size_t lds = (size_t)(256 / 64) * wave_query_lds(hit_slots);  // at most 64 KiB
+    // four wavefronts' lists within 64 KiB; a shorter list only sends more lanes to the
+    // unlisted search, which finds the same contacts in the same order
+    hit_slots = std::min(hit_slots, kMaxHitSlots - 1);
+    const size_t lds = (size_t)(256 / 64) * wave_query_lds(hit_slots);
     k_adj_node<<<blocks(cv.n, 256), 256, lds, st>>>(cv, sv, sp, xs, vs, xb_out, vb_out, fb,
                                                     xb_part, vb_part, hit_slots, pred);
     return hipGetLastError();
@@ -363,7 +366,10 @@ hipError_t launch_adj_fused(const ClothView& cv, const SurfaceView& sv, const St
                             int hit_slots, hipStream_t st) {
     if (cv.n <= 0) return hipSuccess;
     if (hit_slots < 0 || hit_slots > kMaxHitSlots) hit_slots = 0;
-    const size_t lds = (size_t)(256 / 64) * wave_query_lds(hit_slots);  // at most 64 KiB
+    // four wavefronts' lists within 64 KiB; a shorter list only sends more lanes to the
+    // unlisted search, which finds the same contacts in the same order
+    hit_slots = std::min(hit_slots, kMaxHitSlots - 1);
+    const size_t lds = (size_t)(256 / 64) * wave_query_lds(hit_slots);
     k_adj_fused<<<blocks(cv.n, 256), 256, lds, st>>>(cv, sv, sp, xs_a, vs_a, xs_b, vs_b, pred_b,
                                                      fb_t, fb_prev, xb_part, vb_part, xb, vb, kb,
                                                      cb, gout, order, hit_slots);

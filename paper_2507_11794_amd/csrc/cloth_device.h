@@ -169,52 +169,46 @@ __device__ __forceinline__ void gather_global(const ClothView& cv, const float* 
     }
 }
 
-// Squared distance from p to triangle (A, A+e1, A+e2) by Voronoi regions (Ericson,
-// Real-Time Collision Detection, Sec. 5.1.5).  ap = p - A; s = ap . n (signed plane
-// distance along the unit normal n), used for the face region.
+// Squared distance from p to triangle (A, A+e1, A+e2); ap = p - A, s = ap . n (signed plane
+// distance along the unit normal n).  The closest point of the triangle is p's projection on
+// its plane when that projection lies inside the triangle (distance |s|), else the closest
+// point of one of its three edges.  Branch- and division-free: an edge e from P is reached
+// at the clamped parameter t = clamp((p - P).e / |e|^2, 0, 1) (the quotient through the
+// hardware reciprocal) at squared distance |p - P - t e|^2, formed from the vector so that
+// its rounding error scales with the distance, not with |p - P|.  The inside test uses the
+// barycentric numerators of the projection over the Gram matrix of (e1, e2); on the
+// boundary the face and edge distances coincide, so rounding in that test moves the result
+// by no more than rounding in the distances does.
+__device__ __forceinline__ float edge_dist2(float px, float py, float pz, float ex, float ey,
+                                            float ez, float pe, float ee) {
+    const float t = fminf(fmaxf(pe * __builtin_amdgcn_rcpf(ee), 0.0f), 1.0f);
+    const float qx = px - t * ex, qy = py - t * ey, qz = pz - t * ez;
+    return qx * qx + qy * qy + qz * qz;
+}
+
 __device__ __forceinline__ float point_tri_dist2(float apx, float apy, float apz, float e1x,
                                                  float e1y, float e1z, float e2x, float e2y,
                                                  float e2z, float s) {
-    // Every region's quantities are computed and the region is picked by selects in the
-    // order A, B, AB, C, AC, BC, face, so lanes of a wavefront never diverge.  The closest
-    // point is base - t * dir: (ap, 0, 0) for A, (bp, 0, 0) for B, (cp, 0, 0) for C,
-    // (ap, t, e1) for AB, (ap, t, e2) for AC, (bp, t, C - B) for BC; with t = 0 the
-    // difference is base itself, exactly.
     const float d1 = e1x * apx + e1y * apy + e1z * apz;
     const float d2 = e2x * apx + e2y * apy + e2z * apz;
+    const float g11 = e1x * e1x + e1y * e1y + e1z * e1z;
+    const float g22 = e2x * e2x + e2y * e2y + e2z * e2z;
+    const float g12 = e1x * e2x + e1y * e2y + e1z * e2z;
+    const float dab = edge_dist2(apx, apy, apz, e1x, e1y, e1z, d1, g11);
+    const float dac = edge_dist2(apx, apy, apz, e2x, e2y, e2z, d2, g22);
+    const float e3x = e2x - e1x, e3y = e2y - e1y, e3z = e2z - e1z;  // C - B
     const float bpx = apx - e1x, bpy = apy - e1y, bpz = apz - e1z;  // p - B
-    const float d3 = e1x * bpx + e1y * bpy + e1z * bpz;
-    const float d4 = e2x * bpx + e2y * bpy + e2z * bpz;
-    const float cpx = apx - e2x, cpy = apy - e2y, cpz = apz - e2z;  // p - C
-    const float d5 = e1x * cpx + e1y * cpy + e1z * cpz;
-    const float d6 = e2x * cpx + e2y * cpy + e2z * cpz;
-    const float vc = d1 * d4 - d3 * d2;
-    const float vb = d5 * d2 - d1 * d6;
-    const float va = d3 * d6 - d5 * d4;
-    const float d43 = d4 - d3, d56 = d5 - d6;
-    const bool rA = d1 <= 0.0f && d2 <= 0.0f;
-    const bool rB = !rA && d3 >= 0.0f && d4 <= d3;
-    bool done = rA || rB;
-    const bool rAB = !done && vc <= 0.0f && d1 >= 0.0f && d3 <= 0.0f;
-    done = done || rAB;
-    const bool rC = !done && d6 >= 0.0f && d5 <= d6;
-    done = done || rC;
-    const bool rAC = !done && vb <= 0.0f && d2 >= 0.0f && d6 <= 0.0f;
-    done = done || rAC;
-    const bool rBC = !done && va <= 0.0f && d43 >= 0.0f && d56 >= 0.0f;
-    done = done || rBC;
-    const float num = rAB ? d1 : rAC ? d2 : rBC ? d43 : 0.0f;
-    const float den = rAB ? d1 - d3 : rAC ? d2 - d6 : rBC ? d43 + d56 : 1.0f;
-    const float t = num / den;
-    const bool onB = rB || rBC;
-    const float bx = onB ? bpx : rC ? cpx : apx;
-    const float by = onB ? bpy : rC ? cpy : apy;
-    const float bz = onB ? bpz : rC ? cpz : apz;
-    const float dx = rAB ? e1x : rAC ? e2x : rBC ? e2x - e1x : 0.0f;
-    const float dy = rAB ? e1y : rAC ? e2y : rBC ? e2y - e1y : 0.0f;
-    const float dz = rAB ? e1z : rAC ? e2z : rBC ? e2z - e1z : 0.0f;
-    const float qx = bx - t * dx, qy = by - t * dy, qz = bz - t * dz;
-    return done ? qx * qx + qy * qy + qz * qz : s * s;  // else the face region: plane distance
+    const float d3 = e3x * bpx + e3y * bpy + e3z * bpz;
+    const float g33 = e3x * e3x + e3y * e3y + e3z * e3z;
+    const float dbc = edge_dist2(bpx, bpy, bpz, e3x, e3y, e3z, d3, g33);
+    // projection = A + (u e1 + v e2) / det with det = |e1 x e2|^2 > 0
+    const float u = g22 * d1 - g12 * d2;
+    const float v = g11 * d2 - g12 * d1;
+    const float det = g11 * g22 - g12 * g12;
+    const bool inside = (u >= 0.0f) & (v >= 0.0f) & (u + v <= det);
+    // every edge distance is >= s^2, so the minimum below is s^2 inside and the nearest
+    // edge's distance outside; written this way no lane skips the edge terms
+    return fminf(inside ? s * s : __builtin_inff(), fminf(fminf(dab, dac), dbc));
 }
 
 // External force of the node in internal slot `slot`, added to its spring-force sum.
@@ -376,7 +370,8 @@ __device__ __forceinline__ int collide(const SurfaceView& sv, float restitution,
 
 // a3 + a4 contact search with the box hits of the whole cell collected first: the cell's
 // coded reference records are tested kRefRound per round of loads, the triangle ids of hits
-// go to this lane's list in LDS (list[k * 64], k < slots), and the hits' geometry is then
+// go to this lane's list in LDS (list[k * 64], k < slots; entry `slots` is scratch, written
+// by every reference that is not a hit or does not fit), and the hits' geometry is then
 // loaded kHitRound hits per round, so a node with many box hits waits for few round trips.
 // Contacts are visited in ascending triangle id, exactly as contacts_visit visits them
 // (same contacts, same order); a lane with more hits than slots runs contacts_visit
@@ -401,15 +396,14 @@ __device__ __forceinline__ int contacts_listed(const SurfaceView& sv, uint32_t* 
     int nh = 0;
     for (uint32_t r = b; r < e; r += kRefRound) {
         uint4 w[kRefRound];
+        const uint4* rq = sv.ref_q + r;  // one address, the round's entries at fixed offsets
 #pragma unroll
-        for (int q = 0; q < kRefRound; ++q) w[q] = ldgu4(sv.ref_q, r + q);
+        for (int q = 0; q < kRefRound; ++q) w[q] = ldgu4(rq, q);
 #pragma unroll
         for (int q = 0; q < kRefRound; ++q) {
             const uint32_t m = box_code(w[q], cx, cy, cz);
-            if (r + q < e && m <= 1u) {
-                if (nh < slots) list[nh * 64] = w[q].w | (m << 31);
-                ++nh;
-            }
+            list[min(nh, slots) * 64] = w[q].w | (m << 31);
+            nh += (r + q < e && m <= 1u) ? 1 : 0;
         }
     }
     if (nh > slots) return contacts_visit(sv, px, py, pz, visit);

@@ -132,8 +132,12 @@ inline int xcd_grid(int n_logical, int xcd_runs) {
     const long long c = 8LL * xcd_runs;
     return (int)((n_logical + c - 1) / c * c);
 }
+// A lane's hit list holds hit_slots entries plus one scratch entry that takes the writes of
+// references that are not hits (so the box loop appends without a branch); the lists of a
+// wavefront's 64 lanes are interleaved, list_stride(hit_slots) words per wavefront.
+constexpr int list_stride(int hit_slots) { return hit_slots > 0 ? (hit_slots + 1) * 64 : 0; }
 // LDS bytes one wavefront's collision query uses for its lanes' hit lists.
-constexpr size_t wave_query_lds(int hit_slots) { return (size_t)hit_slots * 64 * 4; }
+constexpr size_t wave_query_lds(int hit_slots) { return (size_t)list_stride(hit_slots) * 4; }
 // xcd_runs: the workgroup-to-XCD mapping (see xcd_block; 0 = the hardware's order).
 // pred: if non-NULL, receives every node's prediction before collision (SoA, ld).
 // split_refs > 0: nodes whose cell lists more than split_refs references are resolved by a

@@ -60,7 +60,7 @@ __global__ void __launch_bounds__(256)
         }
         if (sv.n_tris > 0 && !is_heavy) {
             if (hit_slots > 0)
-                collide_listed(sv, hit_lds + (threadIdx.x >> 6) * hit_slots * 64 + (threadIdx.x & 63),
+                collide_listed(sv, hit_lds + (threadIdx.x >> 6) * list_stride(hit_slots) + (threadIdx.x & 63),
                                hit_slots, sp.restitution, px, py, pz, qx, qy, qz);
             else
                 collide(sv, sp.restitution, px, py, pz, qx, qy, qz);

@@ -81,7 +81,7 @@ __device__ __forceinline__ void run_tile(const TileView& tv, const TileMeta& m, 
             if (collide_here && valid && w != 0.0f) {
                 if (hit_slots > 0)
                     collide_listed(sv,
-                                   hit_lds + (threadIdx.x >> 6) * hit_slots * 64 + (threadIdx.x & 63),
+                                   hit_lds + (threadIdx.x >> 6) * list_stride(hit_slots) + (threadIdx.x & 63),
                                    hit_slots, sp.restitution, px, py, pz, qx, qy, qz);
                 else
                     collide(sv, sp.restitution, px, py, pz, qx, qy, qz);
