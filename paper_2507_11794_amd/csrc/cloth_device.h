@@ -394,17 +394,36 @@ __device__ __forceinline__ int contacts_listed(const SurfaceView& sv, uint32_t* 
     // box hits go to the list as triangle ids; a hit whose coded test was undecided
     // carries bit 31 and is decided with the exact box before its narrow test
     int nh = 0;
-    for (uint32_t r = b; r < e; r += kRefRound) {
-        uint4 w[kRefRound];
-        const uint4* rq = sv.ref_q + r;  // one address, the round's entries at fixed offsets
+    // a round's entries load from one address at fixed offsets
+    auto load = [&](uint4 (&w)[kRefRound], uint32_t r) {
+        const uint4* rq = sv.ref_q + r;
 #pragma unroll
         for (int q = 0; q < kRefRound; ++q) w[q] = ldgu4(rq, q);
+    };
+    auto test = [&](const uint4 (&w)[kRefRound], uint32_t r) {
 #pragma unroll
         for (int q = 0; q < kRefRound; ++q) {
             const uint32_t m = box_code(w[q], cx, cy, cz);
             list[min(nh, slots) * 64] = w[q].w | (m << 31);
             nh += (r + q < e && m <= 1u) ? 1 : 0;
         }
+    };
+    // Two rounds in flight: the next round's loads are issued before this round is tested.
+    // The loop body has no branch, so the loads stay ahead of the tests and the compiler
+    // counts them exactly: every load is unconditional (a lane without a further round
+    // reloads its current one, which is cached; an empty cell loads at b <= the reference
+    // count, which the arrays' padding covers), and a round past the cell's end is tested
+    // without effect (its entries fail r + q < e).
+    uint4 wa[kRefRound], wb[kRefRound];
+    load(wa, b);
+    for (uint32_t r = b; r < e; r += 2 * kRefRound) {
+        const uint32_t r1 = r + kRefRound, r2 = r1 + kRefRound;
+        load(wb, r1 < e ? r1 : r);
+        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the tests
+        test(wa, r);
+        load(wa, r2 < e ? r2 : r);
+        __builtin_amdgcn_sched_barrier(0);
+        test(wb, r1);
     }
     if (nh > slots) return contacts_visit(sv, px, py, pz, visit);
     int contacts = 0;
@@ -422,16 +441,27 @@ __device__ __forceinline__ int contacts_listed(const SurfaceView& sv, uint32_t* 
                 g[q][1] = ldg4(sv.geo, 3 * id + 1);
                 g[q][2] = ldg4(sv.geo, 3 * id + 2);
             }
+            // live entries of the round as bits; undecided ones are settled with the exact
+            // box in one branch, which the wavefront skips when none of its lanes has one
+            uint32_t live = (1u << n) - 1u, und = 0;
 #pragma unroll
-            for (int q = 0; q < kHitRound; ++q) {
-                const uint32_t id = t[q] & 0x7fffffffu;
-                bool hit = q < n;
-                if (hit && (t[q] >> 31))
-                    hit = in_box(ldg4(sv.box_lo, id), ldg4(sv.box_hi, id), px, py, pz);
-                if (hit)
-                    contacts += narrow_visit(sv, id, g[q][0], g[q][1], g[q][2], px, py, pz,
-                                             visit);
+            for (int q = 0; q < kHitRound; ++q) und |= (t[q] >> 31) << q;
+            und &= live;
+            if (und) {
+#pragma unroll
+                for (int q = 0; q < kHitRound; ++q)
+                    if ((und >> q) & 1u) {
+                        const uint32_t id = t[q] & 0x7fffffffu;
+                        if (!in_box(ldg4(sv.box_lo, id), ldg4(sv.box_hi, id), px, py, pz))
+                            live &= ~(1u << q);
+                    }
             }
+            // (a wavefront skips a slot none of its lanes holds, e.g. in its last round)
+#pragma unroll
+            for (int q = 0; q < kHitRound; ++q)
+                if ((live >> q) & 1u)
+                    contacts += narrow_visit(sv, t[q] & 0x7fffffffu, g[q][0], g[q][1], g[q][2],
+                                             px, py, pz, visit);
         }
     }
     return contacts;
