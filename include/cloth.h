@@ -101,7 +101,9 @@ typedef struct cloth_launch {
     int hit_slots;           /* collision query: box hits each node lists in LDS before
                                 their geometry is loaded (twelve per round), 0..64; 0 = no
                                 list (hits resolved per round of sixteen references); a node
-                                with more hits than slots takes the no-list path */
+                                with more hits than slots takes the no-list path (same
+                                contacts, same order).  LDS: (hit_slots + 1) * 256 bytes per
+                                64 threads. */
     int xcd_runs;            /* one-thread-per-node kernels, 0..4096: how workgroups (node
                                 ranges) map to the 8 XCDs, each with its own L2.  0 keeps
                                 the hardware's round-robin order; 1 gives each XCD one
