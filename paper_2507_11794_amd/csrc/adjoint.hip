@@ -125,7 +125,9 @@ __device__ __forceinline__ void adj_springs_at(const ClothView& cv, const float*
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             const size_t at = (size_t)(base + min(r0 + q, deg - 1) * 64);
-            rec[q] = ldg4(cv.inc4, at);
+            const uint2 r = ldgu2(cv.inc2, at);
+            const float4 pk = ldg4(cv.ptab, r.y);
+            rec[q] = make_float4(pk.x, pk.y, pk.z, __int_as_float((int)r.x));
             code[q] = gmem(cv.inc_spring)[at];
         }
         float nx[R], ny[R], nz[R], mx[R], my[R], mz[R], ox[R], oy[R], oz[R];
@@ -313,25 +315,13 @@ __global__ void k_set_params(size_t m, const int* __restrict__ code, const float
     ic[q] = c[s];
 }
 
-__global__ void k_set_params_inc4(size_t m, const int* __restrict__ code,
-                                  const float* __restrict__ k, const float* __restrict__ c,
-                                  float4* __restrict__ inc4) {
+__global__ void k_set_entries(size_t m, const int* __restrict__ code, int negated,
+                              const int* __restrict__ entry, uint2* __restrict__ rec) {
     const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= m) return;
     const int s0 = code[q];
-    const int s = s0 >= 0 ? s0 : ~s0;
-    inc4[q].x = k[s];
-    inc4[q].y = c[s];
-}
-
-__global__ void k_set_params_plan(size_t m, const int* __restrict__ sid, const float* __restrict__ k,
-                                  const float* __restrict__ c, float4* __restrict__ inc) {
-    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= m) return;
-    const int s = sid[q];
-    if (s < 0) return;
-    inc[q].x = k[s];
-    inc[q].y = c[s];
+    const int s = negated ? (s0 >= 0 ? s0 : ~s0) : s0;
+    rec[q].y = s >= 0 ? (uint32_t)entry[s] : 0u;
 }
 
 __global__ void k_d2f(size_t n, const double* __restrict__ a, float* __restrict__ b) {
@@ -415,17 +405,10 @@ hipError_t launch_set_params(size_t m, const int* code, const float* k, const fl
     return hipGetLastError();
 }
 
-hipError_t launch_set_params_inc4(size_t m, const int* code, const float* k, const float* c,
-                                  float4* inc4, hipStream_t st) {
+hipError_t launch_set_entries(size_t m, const int* code, int negated, const int* entry,
+                              uint2* rec, hipStream_t st) {
     if (m == 0) return hipSuccess;
-    k_set_params_inc4<<<blocks(m, 256), 256, 0, st>>>(m, code, k, c, inc4);
-    return hipGetLastError();
-}
-
-hipError_t launch_set_params_plan(size_t m, const int* sid, const float* k, const float* c,
-                                  float4* inc, hipStream_t st) {
-    if (m == 0) return hipSuccess;
-    k_set_params_plan<<<blocks(m, 256), 256, 0, st>>>(m, sid, k, c, inc);
+    k_set_entries<<<blocks(m, 256), 256, 0, st>>>(m, code, negated, entry, rec);
     return hipGetLastError();
 }
 

@@ -89,6 +89,12 @@ __device__ __forceinline__ uint4 ldgu4(const uint4* p, size_t i) {
     const u32x4 v = gmem(reinterpret_cast<const u32x4*>(p))[i];
     return make_uint4(v.x, v.y, v.z, v.w);
 }
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+// Element i of a uint2 array, as one global 8-byte load.
+__device__ __forceinline__ uint2 ldgu2(const uint2* p, size_t i) {
+    const u32x2 v = gmem(reinterpret_cast<const u32x2*>(p))[i];
+    return make_uint2(v.x, v.y);
+}
 
 __device__ __forceinline__ int cell_axis(float p, float org, float inv_cell, int dim) {
     float f = cell_coord_f(p, org, inv_cell);
@@ -134,9 +140,9 @@ __device__ __forceinline__ void spring_force(float dx, float dy, float dz, float
 
 // a1 gather of one node over a sliced-CSR incidence list in global memory, up to twelve
 // incidences per round (a grid cloth's interior degree): all their records, then all their
-// neighbours' states, are loaded back to back (indices clamped to the list, so no load
-// depends on a branch), and the forces are then summed in incidence order, which keeps the
-// sum identical to a one-by-one loop.
+// springs' parameters and neighbours' states, are loaded back to back (indices clamped to
+// the list, so no load depends on a branch), and the forces are then summed in incidence
+// order, which keeps the sum identical to a one-by-one loop.
 __device__ __forceinline__ void gather_global(const ClothView& cv, const float* __restrict__ xs,
                                               const float* __restrict__ vs, int i, float xi,
                                               float yi, float zi, float vxi, float vyi,
@@ -147,13 +153,15 @@ __device__ __forceinline__ void gather_global(const ClothView& cv, const float* 
     const int base = cv.slice_ptr[i >> 6] + (i & 63);
     const gptr<float> X = gmem(xs), V = gmem(vs);
     for (int r0 = 0; r0 < deg; r0 += R) {
-        float4 e[R];
+        uint2 rec[R];
 #pragma unroll
-        for (int q = 0; q < R; ++q) e[q] = ldg4(cv.inc4, (size_t)(base + min(r0 + q, deg - 1) * 64));
+        for (int q = 0; q < R; ++q) rec[q] = ldgu2(cv.inc2, (size_t)(base + min(r0 + q, deg - 1) * 64));
+        float4 e[R];  // (k, c, rest length, 0)
         float nx[R], ny[R], nz[R], mx[R], my[R], mz[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            const int j = __float_as_int(e[q].w);
+            e[q] = ldg4(cv.ptab, rec[q].y);
+            const int j = (int)rec[q].x;
             nx[q] = X[j];
             ny[q] = X[ld + j];
             nz[q] = X[2 * ld + j];

@@ -36,16 +36,20 @@ struct SurfaceView {
 //   Incidences use a sliced CSR layout: nodes are grouped in slices of 64 (one wavefront),
 //   and the r-th incidence of node i (r < deg[i]) sits at slice_ptr[i/64] + r*64 + i%64, so
 //   the 64 lanes of a wavefront read incidence r with one coalesced access.  Per incidence:
-//   inc4 = (k, c, rest length, neighbour node as int bits), one 16-byte record, and
-//   inc_spring (spring id, bitwise-negated (~s) when node i is the spring's second end b).
-//   Each node's incidences are in ascending (neighbour, spring) order.
+//   inc2 = (neighbour node, entry of the spring's parameters in ptab), one 8-byte record,
+//   and inc_spring (spring id, bitwise-negated (~s) when node i is the spring's second end
+//   b).  ptab holds the distinct (k, c, rest length) triples of the springs (a cloth has a
+//   few spring types, so the table stays in cache; after per-spring parameters are set it
+//   may hold one entry per spring).  Each node's incidences are in ascending (neighbour,
+//   spring) order.
 struct ClothView {
     int n;
     int ld;  // SoA leading dimension (>= n)
     const float* w;  // [n] inverse mass, 0 = pinned
     const int* deg;        // [n]
     const int* slice_ptr;  // [ceil(n/64) + 1]
-    const float4* inc4;
+    const uint2* inc2;
+    const float4* ptab;  // (k, c, rest length, 0)
     const int* inc_spring;
 };
 
@@ -101,7 +105,8 @@ struct TileView {
     const TileMeta* meta;
     const int* region_slot;
     const int* comp_deg;
-    const float4* inc;
+    const uint2* inc;     // (neighbour's region index, parameter entry)
+    const float4* ptab;   // the cloth's parameter table (ClothView::ptab)
     const float* w;  // inverse mass by global slot
 };
 
@@ -224,11 +229,11 @@ hipError_t launch_export(int n, int ld, const int* slot, const float* soa, float
 // Per-incidence k, c from per-spring arrays (sliced CSR and tile plan forms).
 hipError_t launch_set_params(size_t m, const int* code, const float* k, const float* c, float* ik,
                              float* ic, hipStream_t st);
-// Per-incidence k, c into the packed records (code as inc_spring: ~s for a second end).
-hipError_t launch_set_params_inc4(size_t m, const int* code, const float* k, const float* c,
-                                  float4* inc4, hipStream_t st);
-hipError_t launch_set_params_plan(size_t m, const int* sid, const float* k, const float* c,
-                                  float4* inc, hipStream_t st);
+// Re-point incidence records at new parameter-table entries: record q takes
+// entry[spring of code[q]].  negated = 1: code is in inc_spring's form (~s for a second end);
+// negated = 0: code is a spring id, or -1 for padding (entry 0).
+hipError_t launch_set_entries(size_t m, const int* code, int negated, const int* entry,
+                              uint2* rec, hipStream_t st);
 hipError_t launch_d2f(size_t n, const double* a, float* b, hipStream_t st);
 // Per-vertex normals of the state x (SoA [3][ld], internal slots) into out (AoS, caller
 // numbering); order[slot] = node id, groups[g] = (node_off, nx, ny, 0), node_group[slot]

@@ -5,9 +5,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -242,27 +244,52 @@ int build_cloth_host(const ClothHostInput& in, ClothHost* out, const std::vector
     }
     const size_t M = (size_t)out->slice_ptr[n_slices];
     out->nbr.assign(M, 0);
-    out->ik.assign(M, 0.0f);
-    out->ic.assign(M, 0.0f);
-    out->il.assign(M, 1.0f);
     out->inc_spring.assign(M, 0);
     for (int p = 0; p < N; ++p) {
         const size_t base = (size_t)out->slice_ptr[p >> 6] + (p & 63);
         for (int r = 0; r < deg[p]; ++r) {
             const auto& e = inc[start[p] + r];
-            const int s = e.second >= 0 ? e.second : ~e.second;
             const size_t q = base + (size_t)r * 64;
             out->nbr[q] = (int)(e.first >> 32);
-            out->ik[q] = in.k[s];
-            out->ic[q] = in.c[s];
-            out->il[q] = in.rest[s];
             out->inc_spring[q] = e.second;
         }
-        // padding slots point at the node itself with zero stiffness (never read)
+        // padding slots point at the node itself and at spring 0 (never read)
         for (int r = deg[p]; r < (out->slice_ptr[(p >> 6) + 1] - out->slice_ptr[p >> 6]) / 64; ++r)
             out->nbr[base + (size_t)r * 64] = p;
     }
+    param_table(in.k, in.c, in.rest, in.n_springs, &out->ptab, &out->spring_entry);
     return CLOTH_OK;
+}
+
+void param_table(const float* k, const float* c, const float* rest, int S,
+                 std::vector<float4>* tab, std::vector<int>* entry) {
+    struct Key {
+        uint32_t a, b, c;
+        bool operator==(const Key& o) const { return a == o.a && b == o.b && c == o.c; }
+    };
+    struct Hash {
+        size_t operator()(const Key& x) const {
+            uint64_t h = x.a * 0x9e3779b97f4a7c15ULL;
+            h ^= (h >> 29) + x.b * 0xbf58476d1ce4e5b9ULL;
+            h ^= (h >> 31) + x.c * 0x94d049bb133111ebULL;
+            return (size_t)(h ^ (h >> 32));
+        }
+    };
+    std::unordered_map<Key, int, Hash> index;
+    tab->clear();
+    entry->assign((size_t)S, 0);
+    for (int s = 0; s < S; ++s) {
+        Key key;
+        std::memcpy(&key.a, k + s, 4);
+        std::memcpy(&key.b, c + s, 4);
+        std::memcpy(&key.c, rest + s, 4);
+        auto it = index.find(key);
+        if (it == index.end()) {
+            it = index.emplace(key, (int)tab->size()).first;
+            tab->push_back(make_float4(k[s], c[s], rest[s], 0.0f));
+        }
+        (*entry)[s] = it->second;
+    }
 }
 
 int upload_cloth(const ClothHost& h, DeviceArena& arena, hipStream_t stream, ClothDevice* d) {
@@ -274,16 +301,21 @@ int upload_cloth(const ClothHost& h, DeviceArena& arena, hipStream_t stream, Clo
         if (hipError_t e = arena.alloc(&d->v[b], 3 * (size_t)h.ld)) return hip_fail(e, "hipMalloc state");
     }
     const size_t M = h.nbr.size();
+    const size_t S = h.spring_entry.size();
+    d->n_springs = (int)S;
     hipError_t e;
+    // the table has room for one entry per spring, so a parameter update never moves it
+    // (captured graphs keep its address)
     if ((e = arena.alloc(&d->w, (size_t)N)) || (e = arena.alloc(&d->deg, (size_t)N)) ||
-        (e = arena.alloc(&d->slice_ptr, h.slice_ptr.size())) || (e = arena.alloc(&d->inc4, M)) ||
-        (e = arena.alloc(&d->inc_spring, M)))
+        (e = arena.alloc(&d->slice_ptr, h.slice_ptr.size())) || (e = arena.alloc(&d->inc2, M)) ||
+        (e = arena.alloc(&d->inc_spring, M)) || (e = arena.alloc(&d->ptab, std::max<size_t>(S, 1))) ||
+        (e = arena.alloc(&d->spring_entry, std::max<size_t>(S, 1))))
         return hip_fail(e, "hipMalloc cloth arrays");
-    std::vector<float4> inc4(M);
+    std::vector<uint2> inc2(M);
     for (size_t q = 0; q < M; ++q) {
-        float nb;
-        std::memcpy(&nb, &h.nbr[q], 4);
-        inc4[q] = make_float4(h.ik[q], h.ic[q], h.il[q], nb);
+        const int code = h.inc_spring[q];
+        const int s = code >= 0 ? code : ~code;
+        inc2[q] = make_uint2((uint32_t)h.nbr[q], S ? (uint32_t)h.spring_entry[s] : 0u);
     }
     struct Cp {
         void* dst;
@@ -295,8 +327,10 @@ int upload_cloth(const ClothHost& h, DeviceArena& arena, hipStream_t stream, Clo
         {d->w, h.w.data(), h.w.size() * 4},
         {d->deg, h.deg.data(), h.deg.size() * 4},
         {d->slice_ptr, h.slice_ptr.data(), h.slice_ptr.size() * 4},
-        {d->inc4, inc4.data(), M * 16},
+        {d->inc2, inc2.data(), M * sizeof(uint2)},
         {d->inc_spring, h.inc_spring.data(), M * 4},
+        {d->ptab, h.ptab.data(), h.ptab.size() * sizeof(float4)},
+        {d->spring_entry, h.spring_entry.data(), S * 4},
     };
     for (auto& c : cps)
         if (c.bytes)
@@ -315,9 +349,34 @@ ClothView ClothDevice::view() const {
     v.w = w;
     v.deg = deg;
     v.slice_ptr = slice_ptr;
-    v.inc4 = inc4;
+    v.inc2 = inc2;
+    v.ptab = ptab;
     v.inc_spring = inc_spring;
     return v;
+}
+
+int upload_param_table(const std::vector<float4>& tab, const std::vector<int>& entry,
+                       ClothDevice* d, size_t n_inc, uint2* plan_rec, const int* plan_sid,
+                       size_t n_plan, hipStream_t stream) {
+    if (entry.size() != (size_t)d->n_springs || tab.size() > std::max<size_t>(entry.size(), 1))
+        return fail(CLOTH_EINVAL, "parameter table does not match the springs");
+    hipError_t e;
+    if ((tab.size() &&
+         (e = hipMemcpyAsync(d->ptab, tab.data(), tab.size() * sizeof(float4),
+                             hipMemcpyHostToDevice, stream))) ||
+        (entry.size() && (e = hipMemcpyAsync(d->spring_entry, entry.data(), entry.size() * 4,
+                                             hipMemcpyHostToDevice, stream))))
+        return hip_fail(e, "upload parameter table");
+    if (entry.size()) {
+        if ((e = launch_set_entries(n_inc, d->inc_spring, 1, d->spring_entry, d->inc2, stream)))
+            return hip_fail(e, "re-point incidence records");
+        if (plan_rec && n_plan &&
+            (e = launch_set_entries(n_plan, plan_sid, 0, d->spring_entry, plan_rec, stream)))
+            return hip_fail(e, "re-point tile records");
+    }
+    // the host vectors are the copies' sources: finish before returning
+    if ((e = hipStreamSynchronize(stream))) return hip_fail(e, "upload parameter table");
+    return CLOTH_OK;
 }
 
 constexpr size_t kRefPad = kRefRound;

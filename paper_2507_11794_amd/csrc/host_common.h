@@ -59,7 +59,9 @@ struct ClothHost {
     std::vector<int> order, slot;  // order[slot] = node id; slot[node id] = internal slot
     std::vector<float> x, v, w;
     std::vector<int> deg, slice_ptr, nbr, inc_spring;
-    std::vector<float> ik, ic, il;
+    // the distinct (k, c, rest length) triples and each spring's entry (param_table)
+    std::vector<float4> ptab;
+    std::vector<int> spring_entry;
     // The state copies are only needed for the upload; the incidence lists stay for
     // rebuilding tile plans.
     void release_state() {
@@ -76,8 +78,11 @@ struct ClothDevice {
     float* w = nullptr;
     int* deg = nullptr;
     int* slice_ptr = nullptr;
-    float4* inc4 = nullptr;
+    uint2* inc2 = nullptr;
     int* inc_spring = nullptr;
+    float4* ptab = nullptr;       // room for one entry per spring (at least one)
+    int* spring_entry = nullptr;  // [springs]: re-points the records after a parameter update
+    int n_springs = 0;
     ClothView view() const;
 };
 
@@ -121,6 +126,15 @@ bool unstable(double omega2, double gamma, double h);
 int build_cloth_host(const ClothHostInput& in, ClothHost* out,
                      const std::vector<int>* order = nullptr);
 int upload_cloth(const ClothHost& h, DeviceArena& arena, hipStream_t stream, ClothDevice* d);
+// The distinct (k, c, rest length) triples of S springs, compared by their exact FP32 bits,
+// in order of first occurrence, and each spring's entry in that table.
+void param_table(const float* k, const float* c, const float* rest, int S,
+                 std::vector<float4>* tab, std::vector<int>* entry);
+// Upload a parameter table and the springs' entries, then re-point the cloth's incidence
+// records (and the tile plan's records, if rec/sid are given) at them; synchronises.
+int upload_param_table(const std::vector<float4>& tab, const std::vector<int>& entry,
+                       ClothDevice* d, size_t n_inc, uint2* plan_rec, const int* plan_sid,
+                       size_t n_plan, hipStream_t stream);
 int build_surface(const ClothHostInput& in, const cloth_params& p, DeviceArena& arena,
                   hipStream_t stream, SurfaceDevice* sd);
 // Rebuild the grid and every per-triangle array for new vertex positions [n_verts][3] (host)

@@ -32,19 +32,14 @@ int set_spring_params(cloth_sim* s, const float* k_dev, const float* c_dev) {
             return fail(CLOTH_EINVAL, "spring " + std::to_string(q) + " needs finite k, c >= 0");
     s->k = k;
     s->c = c;
-    for (size_t q = 0; q < s->host.inc_spring.size(); ++q) {
-        const int code = s->host.inc_spring[q];
-        const int sid = code >= 0 ? code : ~code;
-        s->host.ik[q] = k[sid];
-        s->host.ic[q] = c[sid];
-    }
-    if ((e = launch_set_params_inc4(s->host.inc_spring.size(), s->dev.inc_spring, k_dev, c_dev,
-                                    s->dev.inc4, s->stream)))
-        return hip_fail(e, "set spring parameters");
-    if (s->plan.inc_count &&
-        (e = launch_set_params_plan(s->plan.inc_count, s->plan.inc_sid, k_dev, c_dev,
-                                    const_cast<float4*>(s->plan.view.inc), s->stream)))
-        return hip_fail(e, "set tile parameters");
+    // a new table of the distinct triples (one entry per spring at most: it fits in place)
+    // and the records of the cloth and of the tile plan re-pointed at it
+    param_table(s->k.data(), s->c.data(), s->rest.data(), (int)S, &s->host.ptab,
+                &s->host.spring_entry);
+    int st = upload_param_table(s->host.ptab, s->host.spring_entry, &s->dev,
+                                s->host.inc_spring.size(), const_cast<uint2*>(s->plan.view.inc),
+                                s->plan.inc_sid, s->plan.inc_count, s->stream);
+    if (st != CLOTH_OK) return st;
     if (s->springs.ready &&
         (e = launch_set_params(S, s->springs.sid, k_dev, c_dev, s->springs.k, s->springs.c,
                                s->stream)))

@@ -57,6 +57,7 @@ int ensure_plan(cloth_sim* s, const cloth_launch& c) {
         s->plan.K = fresh.K;
         s->plan.view = fresh.view;
         s->plan.view.w = s->dev.w;
+        s->plan.view.ptab = s->dev.ptab;
         s->plan.view.svs = s->svs_dev;
         s->plan.inc_sid = fresh.inc_sid;
         s->plan.inc_count = fresh.inc_count;

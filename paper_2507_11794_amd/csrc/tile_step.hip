@@ -55,19 +55,22 @@ __device__ __forceinline__ void run_tile(const TileView& tv, const TileMeta& m, 
                 const float vxi = Vs[u], vyi = Vs[rmax + u], vzi = Vs[2 * rmax + u];
                 w = tv.w[rs[u]];
                 const int deg = tv.comp_deg[m.comp_off + u];
-                const float4* inc = tv.inc + m.inc_off + u;
+                const uint2* inc = tv.inc + m.inc_off + u;
                 float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-                // records of four incidences are loaded together, then summed in order
+                // records of four incidences and their parameters are loaded together, then
+                // summed in order
                 for (int r0 = 0; r0 < deg; r0 += 4) {
-                    float4 e[4];
+                    uint2 rec[4];
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
-                        e[q] = r0 + q < deg ? inc[(r0 + q) * m.inc_pad]
-                                            : make_float4(0.0f, 0.0f, 0.0f, __int_as_float(u));
+                        rec[q] = r0 + q < deg ? inc[(r0 + q) * m.inc_pad] : make_uint2(u, 0u);
+                    float4 e[4];  // (k, c, rest length, 0)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) e[q] = ldg4(tv.ptab, rec[q].y);
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
                         if (r0 + q < deg) {
-                            const int j = __float_as_int(e[q].w);
+                            const int j = (int)rec[q].x;
                             spring_force(Xs[j] - xi, Xs[rmax + j] - yi, Xs[2 * rmax + j] - zi,
                                          Vs[j] - vxi, Vs[rmax + j] - vyi,
                                          Vs[2 * rmax + j] - vzi, e[q].x, e[q].y, e[q].z, fx,

@@ -29,7 +29,7 @@ int build_tile_plan(const ClothHost& h, const std::vector<int>& group_off, int t
     tile_begin.push_back(N);
     std::vector<TileMeta> meta(n_tiles);
     std::vector<int> region_slot, comp_deg;
-    std::vector<float4> inc;
+    std::vector<uint2> inc;
     std::vector<int> inc_sid;  // spring id of each incidence entry, -1 for padding
     std::vector<int> stamp(N, -1), local(N, 0);
     std::vector<int> region;
@@ -82,7 +82,7 @@ int build_tile_plan(const ClothHost& h, const std::vector<int>& group_off, int t
         m.inc_off = (int)inc.size();
         rmax = std::max(rmax, m.region_n);
         region_slot.insert(region_slot.end(), region.begin(), region.end());
-        inc.resize(inc.size() + (size_t)maxdeg * m.inc_pad, make_float4(0.f, 0.f, 1.f, 0.f));
+        inc.resize(inc.size() + (size_t)maxdeg * m.inc_pad, make_uint2(0u, 0u));
         inc_sid.resize(inc.size(), -1);
         for (int u = 0; u < n_comp; ++u) {
             const int p = region[u];
@@ -91,15 +91,11 @@ int build_tile_plan(const ClothHost& h, const std::vector<int>& group_off, int t
             for (int r = 0; r < h.deg[p]; ++r) {
                 const size_t q = base + (size_t)r * 64;
                 const int j = h.nbr[q];
-                float4 e;
-                e.x = h.ik[q];
-                e.y = h.ic[q];
-                e.z = h.il[q];
-                int lj = local[j];
-                std::memcpy(&e.w, &lj, 4);
-                inc[(size_t)m.inc_off + (size_t)r * m.inc_pad + u] = e;
                 const int code = h.inc_spring[q];
-                inc_sid[(size_t)m.inc_off + (size_t)r * m.inc_pad + u] = code >= 0 ? code : ~code;
+                const int sid = code >= 0 ? code : ~code;
+                inc[(size_t)m.inc_off + (size_t)r * m.inc_pad + u] =
+                    make_uint2((uint32_t)local[j], (uint32_t)h.spring_entry[sid]);
+                inc_sid[(size_t)m.inc_off + (size_t)r * m.inc_pad + u] = sid;
             }
         }
     }
@@ -109,7 +105,7 @@ int build_tile_plan(const ClothHost& h, const std::vector<int>& group_off, int t
     hipError_t e;
     TileMeta* d_meta;
     int *d_rs, *d_deg;
-    float4* d_inc;
+    uint2* d_inc;
     int* d_sid;
     if ((e = out->arena.alloc(&d_meta, meta.size())) ||
         (e = out->arena.alloc(&d_sid, inc_sid.size() + 1)) ||
@@ -123,7 +119,7 @@ int build_tile_plan(const ClothHost& h, const std::vector<int>& group_off, int t
                             hipMemcpyHostToDevice, stream)) ||
         (comp_deg.size() && (e = hipMemcpyAsync(d_deg, comp_deg.data(), comp_deg.size() * 4,
                                                 hipMemcpyHostToDevice, stream))) ||
-        (inc.size() && (e = hipMemcpyAsync(d_inc, inc.data(), inc.size() * sizeof(float4),
+        (inc.size() && (e = hipMemcpyAsync(d_inc, inc.data(), inc.size() * sizeof(uint2),
                                            hipMemcpyHostToDevice, stream))) ||
         (inc_sid.size() && (e = hipMemcpyAsync(d_sid, inc_sid.data(), inc_sid.size() * 4,
                                                hipMemcpyHostToDevice, stream))) ||
@@ -141,7 +137,7 @@ int build_tile_plan(const ClothHost& h, const std::vector<int>& group_off, int t
     out->inc_sid = d_sid;
     out->inc_count = inc.size();
     out->bytes = meta.size() * sizeof(TileMeta) + region_slot.size() * 4 + comp_deg.size() * 4 +
-                 inc.size() * sizeof(float4);
+                 inc.size() * sizeof(uint2);
     long long comp = 0;
     for (const auto& m : meta) comp += m.level[K - 1];
     out->computed_per_launch_first = comp;
