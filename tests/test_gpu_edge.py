@@ -1,8 +1,10 @@
 """Edge cases of the HIP path through the C ABI: a single node without springs landing on a
 single triangle, a one-node-wide strip, a cloth of one wavefront plus one node (ragged last
-wavefront) over a surface, a fully pinned cloth, and a zero-frame step.  Each is checked
-against the FP64 oracle (one substep at a time where contacts occur) or against the exact
-invariant."""
+wavefront) over a surface, a fully pinned cloth, a zero-frame step, and springs that all
+have their own parameters.  Each is checked against the FP64 oracle (one substep at a time
+where contacts occur) or against the exact invariant."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -98,3 +100,27 @@ def test_zero_frames_leave_the_state_unchanged():
         sim.step(n_steps=0)
         after = sim.read_state()
     assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+
+
+def test_every_spring_with_its_own_parameters():
+    """Stiffness, damping and rest length drawn per spring, so the parameter table holds one
+    entry per spring from the start: every frame's substep matches the oracle, and the
+    one-substep and tile kernels agree bit for bit."""
+    inp = _scene(24, 20, drop=0.012, n_steps=40, seed=11)
+    rng = np.random.default_rng(12)
+    S = inp.ends.shape[0]
+    inp = dataclasses.replace(inp, k=(inp.k * rng.uniform(0.5, 1.0, S)).astype(np.float32),
+                              c=(inp.c * rng.uniform(0.0, 2.0, S)).astype(np.float32),
+                              rest=(inp.rest * rng.uniform(0.97, 1.03, S)).astype(np.float32))
+    triples = set(zip(inp.k.tolist(), inp.c.tolist(), inp.rest.tolist()))
+    assert len(triples) == S
+    (x, v), contacts = _run_with_parity(inp, 30)
+    print(f"{S} springs, {contacts} contacts")
+    assert contacts > 0
+    outs = []
+    for kernel in (B.CLOTH_KERNEL_DIRECT, B.CLOTH_KERNEL_TILE):
+        with B.Cloth(inp) as sim:
+            sim.set_launch(kernel=kernel)
+            sim.step(n_steps=25)
+            outs.append(sim.read_state())
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
