@@ -170,6 +170,31 @@ def test_gradients_independent_of_checkpoint_interval():
             assert np.array_equal(a, b)
 
 
+def test_gradients_independent_of_the_hit_list_length():
+    """The contact search with no hit list, short lists that often overflow to the unlisted
+    search, the default and the longest list (which the adjoint's kernels cap at 63 so four
+    wavefronts' lists fit 64 KiB) finds the same contacts in the same order: gradients are
+    bit-identical."""
+    import torch
+    inp = W.small_collision_scene(n=14, freq=5, drop=0.165, spacing=0.02)
+    dev = torch.device("cuda")
+    grads = []
+    for slots in (32, 0, 2, 64):
+        with B.Cloth(inp) as sim:
+            sim.set_launch(hit_slots=slots)
+            k = torch.tensor(inp.k, device=dev, requires_grad=True)
+            c = torch.tensor(inp.c, device=dev, requires_grad=True)
+            v0 = torch.zeros((inp.n_nodes, 3), device=dev, requires_grad=True)
+            x = _rollout(sim, k, c, v0, 60, 20, [30, 60])
+            w = torch.linspace(-1, 1, x.numel(), device=dev).reshape(x.shape)
+            (x * w).sum().backward()
+            grads.append([t.grad.cpu().numpy() for t in (k, c, v0)])
+    assert np.any(grads[0][0] != 0)
+    for g in grads[1:]:
+        for a, b in zip(g, grads[0]):
+            assert np.array_equal(a, b)
+
+
 def test_backward_without_forward_is_a_state_error():
     inp = W.small_collision_scene(n=8, freq=3)
     with B.Cloth(inp) as sim:
