@@ -1,0 +1,66 @@
+"""Host logic of the benchmark: it refuses more than one GPU, counts the algorithmic bytes of
+a substep, parses launch strings, and reports counter traffic only for the kernel sources
+and launch configuration the committed counters were taken on."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr and r.stdout.strip() == ""
+
+
+def test_algorithmic_bytes_of_the_316_workload():
+    # 52 B per node (x, v read and written, inverse mass) + 20 B per spring
+    n = 316
+    springs = 6 * n * n - 10 * n + 2
+    assert springs == 595978
+    assert bench.algorithmic_bytes_per_substep(n * n, springs) == 52 * 99856 + 20 * 595978
+
+
+def test_parse_launch():
+    from paper_2507_11794_amd import cloth
+    cfg = bench.parse_launch("kernel=tile,tile=128,K=2,block=256,graph=0,hits=16,xcd=4")
+    assert cfg == {"kernel": cloth.CLOTH_KERNEL_TILE, "tile_nodes": 128,
+                   "substeps_per_launch": 2, "block_threads": 256, "use_graph": 0,
+                   "hit_slots": 16, "xcd_runs": 4}
+    assert bench.parse_launch("") == {}
+
+
+def test_counter_traffic_is_reported_only_for_matching_sources_and_launch(monkeypatch):
+    rec = json.load(open(os.path.join(ROOT, "profiles", "k_substep_traffic.json")))
+    launch = dict(rec["launch"])
+    monkeypatch.setattr(bench, "sources_sha256", lambda: rec["sources_sha256"])
+    assert bench.counter_traffic(launch) == rec["traffic_bytes_per_launch"]
+    other = dict(launch, block_threads=launch["block_threads"] * 2)
+    assert bench.counter_traffic(other) is None
+    monkeypatch.setattr(bench, "sources_sha256", lambda: "0" * 64)
+    assert bench.counter_traffic(launch) is None
+
+
+def test_sources_hash_follows_the_kernel_sources(tmp_path, monkeypatch):
+    csrc = tmp_path / "paper_2507_11794_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    (csrc / "a.hip").write_text("kernel A\n")
+    (csrc / "b.h").write_text("header\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h0 = bench.sources_sha256()
+    (csrc / "a.hip").write_text("kernel A changed\n")
+    h1 = bench.sources_sha256()
+    (csrc / "README.txt").write_text("not a source\n")
+    assert h0 != h1 and bench.sources_sha256() == h1
+
+
+if __name__ == "__main__":
+    sys.exit(pytest.main([__file__, "-q"]))
