@@ -378,8 +378,9 @@ __device__ __forceinline__ int collide(const SurfaceView& sv, float restitution,
 
 // a3 + a4 contact search with the box hits of the whole cell collected first: the cell's
 // coded reference records are tested kRefRound per round of loads, the triangle ids of hits
-// go to this lane's list in LDS (list[k * 64], k < slots; entry `slots` is scratch, written
-// by every reference that is not a hit or does not fit), and the hits' geometry is then
+// go to this lane's list in LDS (list[k * 64], k < slots, plus a scratch entry k = slots:
+// every reference is written at the next free entry, or at the scratch entry once the list
+// is full, and only a hit advances the count), and the hits' geometry is then
 // loaded kHitRound hits per round, so a node with many box hits waits for few round trips.
 // Contacts are visited in ascending triangle id, exactly as contacts_visit visits them
 // (same contacts, same order); a lane with more hits than slots runs contacts_visit
