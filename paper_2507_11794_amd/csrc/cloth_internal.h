@@ -262,8 +262,12 @@ hipError_t launch_grid_finish(int n_cells, const float org[3], float inv_cell, c
                               const float4* box_hi, float4* ref_lo, float4* ref_hi, uint4* ref_q,
                               hipStream_t stream);
 
-// Exclusive prefix sum of in[0..n) into out[0..n] (out[n] = total) with wavefront scans.
-// tmp must hold scan_tmp_words(n) words.
+// Exclusive prefix sum of in[0..n) into out[0..n] (out[n] = total) with wavefront scans:
+// each 1024-thread workgroup scans a tile of kScanTile entries (kScanItems per thread), the
+// tile totals are scanned recursively and added back.  tmp must hold scan_tmp_words(n) words.
+constexpr int kScanThreads = 1024;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanThreads * kScanItems;
 size_t scan_tmp_words(size_t n);
 hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, size_t n, uint32_t* tmp,
                               hipStream_t stream);

@@ -283,9 +283,7 @@ __global__ void __launch_bounds__(256)
 }
 
 // ------------------------------------------------------------------ prefix sum
-constexpr int kScanThreads = 1024;
-constexpr int kScanItems = 4;
-constexpr int kScanTile = kScanThreads * kScanItems;
+// (kScanThreads, kScanItems, kScanTile: cloth_internal.h)
 
 // Inclusive scan across the 64 lanes of a wavefront.
 __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
@@ -422,13 +420,6 @@ hipError_t launch_grid_finish(int n_cells, const float org[3], float inv_cell, c
         n_cells, make_dims(org, inv_cell, dim), cell_start, refs, box_lo, box_hi, ref_lo, ref_hi,
         ref_q);
     return hipGetLastError();
-}
-
-size_t scan_tmp_words(size_t n) {
-    const size_t m = n + 1;
-    const size_t nb = (m + kScanTile - 1) / kScanTile;
-    if (nb <= 1) return 1;
-    return nb + (nb + 1) + scan_tmp_words(nb);
 }
 
 hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, size_t n, uint32_t* tmp,

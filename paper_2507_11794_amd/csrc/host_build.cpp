@@ -46,6 +46,21 @@ hipError_t DeviceArena::alloc_bytes(void** p, size_t bytes) {
     return e;
 }
 
+// Scratch words of scan_exclusive_u32 over n entries: the tile totals and their offsets at
+// every level of the recursion.
+size_t scan_tmp_words(size_t n) {
+    const size_t m = n + 1;
+    const size_t nb = (m + kScanTile - 1) / kScanTile;
+    if (nb <= 1) return 1;
+    return nb + (nb + 1) + scan_tmp_words(nb);
+}
+
+// LDS of one tile workgroup: two copies (ping-pong) of the region's x and v, 12 floats per
+// node, plus the hit lists of its wavefronts.
+size_t tile_lds_bytes(int rmax, int block, int hit_slots) {
+    return (size_t)12 * sizeof(float) * (size_t)rmax + (size_t)(block / 64) * wave_query_lds(hit_slots);
+}
+
 void DeviceArena::free_one(void* p) {
     if (!p) return;
     auto it = std::find(ptrs.begin(), ptrs.end(), p);
@@ -312,6 +327,7 @@ int upload_cloth(const ClothHost& h, DeviceArena& arena, hipStream_t stream, Clo
         (e = arena.alloc(&d->spring_entry, std::max<size_t>(S, 1))))
         return hip_fail(e, "hipMalloc cloth arrays");
     std::vector<uint2> inc2(M);
+    StreamFence fence{stream};
     for (size_t q = 0; q < M; ++q) {
         const int code = h.inc_spring[q];
         const int s = code >= 0 ? code : ~code;
@@ -336,7 +352,8 @@ int upload_cloth(const ClothHost& h, DeviceArena& arena, hipStream_t stream, Clo
         if (c.bytes)
             if ((e = hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyHostToDevice, stream)))
                 return hip_fail(e, "upload cloth");
-    // the packed records live on this stack frame: finish the copies before returning
+    // the packed records live on this stack frame: finish the copies before returning (the
+    // fence covers the error returns)
     if ((e = hipStreamSynchronize(stream))) return hip_fail(e, "upload cloth");
     d->cur = 0;
     return CLOTH_OK;
@@ -360,6 +377,7 @@ int upload_param_table(const std::vector<float4>& tab, const std::vector<int>& e
                        size_t n_plan, hipStream_t stream) {
     if (entry.size() != (size_t)d->n_springs || tab.size() > std::max<size_t>(entry.size(), 1))
         return fail(CLOTH_EINVAL, "parameter table does not match the springs");
+    StreamFence fence{stream};
     hipError_t e;
     if ((tab.size() &&
          (e = hipMemcpyAsync(d->ptab, tab.data(), tab.size() * sizeof(float4),
@@ -390,6 +408,7 @@ int build_surface(const ClothHostInput& in, const cloth_params& p, DeviceArena& 
     sd->view = SurfaceView{};
     if (!(p.thickness > 0.0f) || in.n_tris == 0) return CLOTH_OK;
     const int T = in.n_tris, Vn = in.n_verts;
+    StreamFence fence{stream};  // in.tris and in.verts are the caller's: copies finish here
     double cell = p.cell_size;
     if (!(cell > 0.0)) {
         // 2 x mean length of the unique edges
@@ -435,6 +454,9 @@ int rebuild_surface(SurfaceDevice* sd, const float* verts, DeviceArena& arena,
                     hipStream_t stream) {
     SurfaceView& sv = sd->view;
     const int T = sv.n_tris, Vn = sd->n_verts;
+    // verts is the caller's and `total` below lives here: the copies finish before any return
+    unsigned long long total = 0;
+    StreamFence fence{stream};
     float vmin[3] = {INFINITY, INFINITY, INFINITY}, vmax[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int i = 0; i < Vn; ++i)
         for (int q = 0; q < 3; ++q) {
@@ -488,7 +510,6 @@ int rebuild_surface(SurfaceDevice* sd, const float* verts, DeviceArena& arena,
     if ((e = launch_tri_prep(T, sd->verts, sd->tris, sv.thickness, sv.org, sv.inv_cell, sv.dim,
                              sd->box_lo, sd->box_hi, sd->geo, sd->tri_v, sd->total, stream)))
         return hip_fail(e, "triangle prep");
-    unsigned long long total = 0;
     if ((e = hipMemcpyAsync(&total, sd->total, 8, hipMemcpyDeviceToHost, stream)) ||
         (e = hipStreamSynchronize(stream)))
         return hip_fail(e, "read reference count");

@@ -16,6 +16,18 @@ int fail(int code, const std::string& msg);
 int hip_fail(hipError_t e, const char* what);
 extern thread_local std::string g_last_error;
 
+// Waits for a stream when it goes out of scope.  The runtime may perform a copy from or to
+// pageable host memory after hipMemcpyAsync has returned (when the stream still has work
+// queued ahead of it), so a host buffer must outlive every copy that uses it.  Declared
+// after such buffers, a fence is destroyed before them on every return path, error returns
+// included.
+struct StreamFence {
+    hipStream_t stream;
+    StreamFence(const StreamFence&) = delete;
+    StreamFence& operator=(const StreamFence&) = delete;
+    ~StreamFence() { (void)hipStreamSynchronize(stream); }
+};
+
 // Device allocations owned by one handle, released together.
 struct DeviceArena {
     std::vector<void*> ptrs;

@@ -23,6 +23,7 @@ int set_spring_params(cloth_sim* s, const float* k_dev, const float* c_dev) {
     if (S == 0) return CLOTH_OK;
     hipError_t e;
     std::vector<float> k(S), c(S);
+    StreamFence fence{s->stream};
     if ((e = hipMemcpyAsync(k.data(), k_dev, 4 * S, hipMemcpyDeviceToHost, s->stream)) ||
         (e = hipMemcpyAsync(c.data(), c_dev, 4 * S, hipMemcpyDeviceToHost, s->stream)) ||
         (e = hipStreamSynchronize(s->stream)))
@@ -255,6 +256,7 @@ int cloth_debug_contacts(cloth_sim* s, float h, int* counts, int* ids, int cap) 
     if ((e = tmp.alloc(&d_cnt, (size_t)N)) || (e = tmp.alloc(&d_ids, (size_t)N * cap + 1)))
         return hip_fail(e, "hipMalloc contacts");
     std::vector<int> cnt(N), id((size_t)N * cap + 1);
+    StreamFence fence{s->stream};
     const hipError_t le =
         s->mt ? launch_mt_debug_contacts(s->dev.view(), step_params(s, h),
                                          MtTopology{s->order_dev, s->slot_dev, nullptr,

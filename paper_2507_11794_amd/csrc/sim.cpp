@@ -86,6 +86,7 @@ int ensure_springs(cloth_sim* s) {
     });
     std::vector<int> a(S), b(S);
     std::vector<float> k(S), c(S), L0(S);
+    StreamFence fence{s->stream};
     for (int r = 0; r < S; ++r) {
         const int q = perm[r];
         a[r] = s->host.slot[s->ends[2 * q]];
@@ -339,6 +340,7 @@ int read_state_range(const cloth_sim* s, int group, float* x_out, float* v_out) 
     const size_t ld = (size_t)s->dev.ld, n = (size_t)g.n;
     std::vector<float> xs(3 * n), vs(v_out ? 3 * n : 0);
     int flag = 0;
+    StreamFence fence{s->stream};
     hipError_t e;
     for (int q = 0; q < 3; ++q) {
         if ((e = hipMemcpyAsync(xs.data() + q * n, s->dev.x[s->dev.cur] + q * ld + g.slot_off,
@@ -456,7 +458,10 @@ int create_sim(const std::vector<ClothHostInput>& cloths, const cloth_params* p,
     if (st == CLOTH_OK) {
         const size_t N = (size_t)n_tot, G = cloths.size();
         const size_t ld = (size_t)s->dev.ld;
+        // host sources of the copies below; the fence waits for the copies before they go
         std::vector<SurfaceView> svs(G);
+        std::vector<int> grp(G > 1 ? N : 0);
+        StreamFence fence{s->stream};
         for (size_t g = 0; g < G; ++g) svs[g] = s->surfs[g].view;
         hipError_t e;
         if ((e = s->arena.alloc(&s->nan_flag, 1)) || (e = s->arena.alloc(&s->x_init, 3 * ld)) ||
@@ -471,7 +476,6 @@ int create_sim(const std::vector<ClothHostInput>& cloths, const cloth_params* p,
                                 s->stream)))
             st = hip_fail(e, "create");
         if (st == CLOTH_OK && G > 1) {
-            std::vector<int> grp(N);
             for (size_t g = 0; g < G; ++g)
                 for (int q = s->group_off[g]; q < s->group_off[g + 1]; ++q) grp[q] = (int)g;
             if ((e = s->arena.alloc(&s->node_group_dev, N)) ||
@@ -526,6 +530,7 @@ int set_external_force(cloth_sim* s, const float* f) {
     }
     const size_t N = (size_t)s->n_nodes, ld = (size_t)s->dev.ld;
     std::vector<float> soa(3 * ld, 0.0f);
+    StreamFence fence{s->stream};
     for (size_t p = 0; p < N; ++p) {
         const size_t id = (size_t)s->host.order[p];
         for (int q = 0; q < 3; ++q) {
@@ -554,6 +559,7 @@ int ensure_topology(cloth_sim* s) {
     if (!s->order_dev) {
         const size_t G = s->groups.size();
         std::vector<int4> desc(G);
+        StreamFence fence{s->stream};
         for (size_t g = 0; g < G; ++g)
             desc[g] = make_int4(s->groups[g].node_off, s->groups[g].nx, s->groups[g].ny, 0);
         int* order = nullptr;
@@ -642,6 +648,7 @@ int cloth_write_state(cloth_sim* s, const float* x, const float* v) {
     if (!s || !x) return fail(CLOTH_EINVAL, "NULL argument");
     const int N = s->dev.n, ld = s->dev.ld;
     std::vector<float> xs(3 * (size_t)ld, 0.0f), vs(3 * (size_t)ld, 0.0f);
+    StreamFence fence{s->stream};
     for (int p = 0; p < N; ++p) {
         const int id = s->host.order[p];
         for (int q = 0; q < 3; ++q) {
@@ -718,6 +725,7 @@ int cloth_debug_candidates(cloth_sim* s, int n_points, const float* points, int*
     for (size_t i = 0; i < n; ++i)
         for (int q = 0; q < 3; ++q) soa[q * n + i] = points[3 * i + q];
     uint32_t total = 0;
+    StreamFence fence{s->stream};
     if ((e = hipMemcpyAsync(d_p, soa.data(), 12 * n, hipMemcpyHostToDevice, s->stream)) ||
         (e = launch_candidates_count(n_points, n_points, d_p, sv, d_cnt, s->stream)) ||
         (e = scan_exclusive_u32(d_cnt, d_off, n, d_scan, s->stream)) ||

@@ -137,10 +137,6 @@ __global__ void __launch_bounds__(256)
 
 }  // namespace
 
-size_t tile_lds_bytes(int rmax, int block, int hit_slots) {
-    return (size_t)12 * sizeof(float) * (size_t)rmax + (size_t)(block / 64) * wave_query_lds(hit_slots);
-}
-
 hipError_t prepare_tile_kernels(size_t lds_bytes) {
     if (lds_bytes <= 64 * 1024) return hipSuccess;
     hipError_t e = hipFuncSetAttribute((const void*)k_tile<true>,

@@ -33,6 +33,7 @@ int build_tile_plan(const ClothHost& h, const std::vector<int>& group_off, int t
     std::vector<int> inc_sid;  // spring id of each incidence entry, -1 for padding
     std::vector<int> stamp(N, -1), local(N, 0);
     std::vector<int> region;
+    StreamFence fence{stream};  // the vectors above are the sources of the uploads below
     int rmax = 0;
     auto nbr_at = [&](int p, int r) { return h.nbr[(size_t)h.slice_ptr[p >> 6] + (size_t)r * 64 + (p & 63)]; };
     for (int t = 0; t < n_tiles; ++t) {
@@ -154,6 +155,7 @@ int build_schedule(TilePlanDevice* plan, int mode, int n_workgroups, hipStream_t
     const int n = plan->view.n_tiles;
     const int K = plan->K;
     std::vector<int> items, ptr;
+    StreamFence fence{stream};
     if (mode == 0 || n_workgroups <= 0 || n_workgroups >= n) {
         const int q = n >> 3, rem = n & 7;
         items.resize(n);
