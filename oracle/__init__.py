@@ -63,6 +63,10 @@ def _load():
     lib.orc_candidates_f32.argtypes = [C.c_int, fp, C.c_int, fp, ip, C.c_float, ip, C.c_longlong]
     lib.orc_substep_vjp.argtypes = [P, dp, dp, C.c_double, dp, dp, dp, dp, dp, dp]
     lib.orc_substep_vjp_given.argtypes = [P, dp, dp, C.c_double, ip, ip, dp, dp, dp, dp, dp, dp]
+    lib.orc_substep_given.argtypes = [P, dp, dp, C.c_double, ip, ip]
+    lib.orc_run_given.argtypes = [P, dp, dp, C.c_double, C.c_int, ip, ip]
+    lib.orc_check_contacts.restype = C.c_int
+    lib.orc_check_contacts.argtypes = [P, dp, C.c_double, ip, ip, ip, C.POINTER(C.c_longlong)]
     lib.orc_rollout_grad.argtypes = [P, dp, dp, C.c_double, C.c_int, C.c_int, ip, dp, C.c_int,
                                      dp, dp, dp, dp, dp]
     lib.orc_model_triangle.argtypes = [P, C.c_int, dp, dp, dp, dp]
@@ -252,12 +256,10 @@ class Model:
 
     def substep_vjp_given(self, x, v, h, contacts, xb_out, vb_out):
         """Adjoint of one substep at (x, v) with node i's contact triangles given as
-        contacts[i] (a sequence of ids); returns (xb_in, vb_in, kb, cb)."""
+        contacts[i] (a sequence of ids, or a (off, ids) pair as from contact_csr);
+        returns (xb_in, vb_in, kb, cb)."""
         x, v = _d(x).reshape(-1, 3), _d(v).reshape(-1, 3)
-        off = np.zeros(self.N + 1, dtype=np.int32)
-        off[1:] = np.cumsum([len(c) for c in contacts])
-        ids = _i(np.concatenate([np.sort(np.asarray(c, dtype=np.int64)) for c in contacts])
-                 if off[-1] else np.zeros(1))
+        off, ids = self.contact_csr(contacts)
         xbo, vbo = _d(xb_out).reshape(-1, 3), _d(vb_out).reshape(-1, 3)
         xbi, vbi = np.zeros((self.N, 3)), np.zeros((self.N, 3))
         kb, cb = np.zeros(self.S), np.zeros(self.S)
@@ -265,6 +267,57 @@ class Model:
                                         _dp(xbo), _dp(vbo), _dp(xbi), _dp(vbi), _dp(kb),
                                         _dp(cb))
         return xbi, vbi, kb, cb
+
+    def contact_csr(self, contacts):
+        """Per-node contact sets as (off [N+1], ids) int32 arrays, each set ascending.
+        contacts: a sequence of N id sequences, or an (off, ids) pair (returned as is)."""
+        if isinstance(contacts, tuple):
+            off, ids = contacts
+            return _i(off), _i(ids if len(ids) else np.zeros(1))
+        off = np.zeros(self.N + 1, dtype=np.int32)
+        off[1:] = np.cumsum([len(c) for c in contacts])
+        ids = _i(np.concatenate([np.sort(np.asarray(c, dtype=np.int64)) for c in contacts])
+                 if off[-1] else np.zeros(1))
+        return off, ids
+
+    def substep_given(self, x, v, h, contacts):
+        """One substep with the contact sets held fixed (contacts as for contact_csr):
+        the prediction, then each unpinned node's response to its given triangles."""
+        x, v = _d(x).reshape(-1, 3).copy(), _d(v).reshape(-1, 3).copy()
+        off, ids = self.contact_csr(contacts)
+        self._lib.orc_substep_given(self._h, _dp(x), _dp(v), float(h), _ip(off), _ip(ids))
+        return x, v
+
+    def run_given(self, x, v, h, sets):
+        """len(sets) substeps of substep_given; sets[s] = (off, ids) of substep s."""
+        x, v = _d(x).reshape(-1, 3).copy(), _d(v).reshape(-1, 3).copy()
+        n = len(sets)
+        if n == 0:
+            return x, v
+        offs, chunks, base = [], [], 0
+        for off, ids in sets:
+            off = np.asarray(off, dtype=np.int64)
+            offs.append(off + base)
+            chunks.append(np.asarray(ids[:off[-1]], dtype=np.int64))
+            base += int(off[-1])
+        off_all = _i(np.concatenate(offs))
+        ids_all = _i(np.concatenate(chunks) if base else np.zeros(1))
+        self._lib.orc_run_given(self._h, _dp(x), _dp(v), float(h), n, _ip(off_all),
+                                _ip(ids_all))
+        return x, v
+
+    def check_contacts(self, xp, contacts, border):
+        """Validity of another implementation's contact sets at predicted positions xp:
+        (status [N] with 0 = valid, 1 = a listed triangle farther than th + border, 2 = a
+        triangle closer than th - border missing, 3 = contacts on a pinned node; the number
+        of listed triangles within border of th)."""
+        xp = _d(xp).reshape(-1, 3)
+        off, ids = self.contact_csr(contacts)
+        st = np.zeros(self.N, dtype=np.int32)
+        nb = C.c_longlong(0)
+        self._lib.orc_check_contacts(self._h, _dp(xp), float(border), _ip(off), _ip(ids),
+                                     _ip(st), C.byref(nb))
+        return st, int(nb.value)
 
     def rollout_grad(self, x0, v0, h, n_sub, out_sub, xbar, ckpt=1):
         """Checkpointed rollout gradient.

@@ -423,6 +423,81 @@ void orc_run(const orc_model *m, double *x, double *v, double h, int n_sub)
     for (int s = 0; s < n_sub; ++s) orc_substep(m, x, v, h, NULL, NULL);
 }
 
+/* One substep with the contact sets held fixed: the prediction of orc_predict, then node
+ * i's response to the triangles ids[off[i] .. off[i+1]) (ascending), whatever their
+ * distance to the prediction.  With the sets orc_substep finds this is orc_substep; with
+ * any fixed sets it is one smooth piece of the step, the function whose derivative the
+ * adjoint computes (contact set frozen). */
+void orc_substep_given(const orc_model *m, double *x, double *v, double h, const int *off,
+                       const int *ids)
+{
+    orc_predict(m, x, v, h);
+    for (int i = 0; i < m->N; ++i) {
+        if (m->w[i] == 0.0) continue; /* pinned nodes never collide */
+        orc_respond(m, x + 3 * i, v + 3 * i, ids + off[i], off[i + 1] - off[i]);
+    }
+}
+
+/* n_sub substeps of orc_substep_given; substep s uses the sets off[s*(N+1) + i] ..
+ * off[s*(N+1) + i + 1] of ids (offsets into the one ids array). */
+void orc_run_given(const orc_model *m, double *x, double *v, double h, int n_sub,
+                   const int *off, const int *ids)
+{
+    for (int s = 0; s < n_sub; ++s)
+        orc_substep_given(m, x, v, h, off + (size_t)s * (m->N + 1), ids);
+}
+
+/* Checks another implementation's contact sets against the distances at the predicted
+ * positions xp: node i's set ids[off[i] .. off[i+1]) is valid iff it holds every triangle
+ * within th - border of xp_i and only triangles within th + border (a decision closer than
+ * border to the threshold may go either way in lower precision), and a pinned node has
+ * none.  status[i] = 0 valid, 1 a listed triangle is too far, 2 a sure contact is missing,
+ * 3 a pinned node has contacts.  Returns the number of invalid nodes; *n_border (optional)
+ * receives the number of listed triangles whose distance lies within border of th. */
+int orc_check_contacts(const orc_model *m, const double *xp, double border, const int *off,
+                       const int *ids, int *status, long long *n_border)
+{
+    int bad = 0;
+    long long nb = 0;
+    int sure[ORC_MAX_CONTACTS];
+    for (int i = 0; i < m->N; ++i) {
+        const double *p = xp + 3 * i;
+        int st = 0, n = off[i + 1] - off[i];
+        if (m->w[i] == 0.0) {
+            if (n > 0) st = 3;
+        } else {
+            for (int r = 0; r < n && !st; ++r) {
+                int t = ids[off[i] + r];
+                if (t < 0 || t >= m->T) { st = 1; break; }
+                double d = sqrt(orc_point_tri_dist2(p, m->verts + 3 * m->tris[3 * t],
+                                                    m->verts + 3 * m->tris[3 * t + 1],
+                                                    m->verts + 3 * m->tris[3 * t + 2]));
+                if (d >= m->th + border) st = 1;
+                else if (d >= m->th - border) ++nb;
+            }
+            if (!st && m->T > 0) {
+                /* the triangles within th - border are among those within th */
+                int ns = contacts_of(m, p, sure, ORC_MAX_CONTACTS, NULL);
+                if (ns > ORC_MAX_CONTACTS) ns = ORC_MAX_CONTACTS;
+                for (int a = 0; a < ns && !st; ++a) {
+                    int t = sure[a];
+                    double d = sqrt(orc_point_tri_dist2(p, m->verts + 3 * m->tris[3 * t],
+                                                        m->verts + 3 * m->tris[3 * t + 1],
+                                                        m->verts + 3 * m->tris[3 * t + 2]));
+                    if (d >= m->th - border) continue;
+                    int found = 0;
+                    for (int r = 0; r < n; ++r) found |= ids[off[i] + r] == t;
+                    if (!found) st = 2;
+                }
+            }
+        }
+        if (status) status[i] = st;
+        bad += st != 0;
+    }
+    if (n_border) *n_border = nb;
+    return bad;
+}
+
 /* Number of contacts a node at p would get, and the contact triangle ids (ascending). */
 int orc_contacts(const orc_model *m, const double *p, int *out, int cap)
 {
@@ -475,90 +550,55 @@ long long orc_candidates_f32(int N, const float *x, int T, const float *verts, c
 
 /* Reverse-mode derivative of orc_substep at state (x, v) with the contact set held fixed.
  * Given xb_out, vb_out = dL/d(x, v) after the substep, writes xb_in, vb_in = dL/d(x, v)
- * before it and ADDS dL/dk, dL/dc into kb, cb (either may be NULL). */
+ * before it and ADDS dL/dk, dL/dc into kb, cb (either may be NULL).  The contact sets are
+ * those orc_substep finds at the prediction; the transpose itself is orc_substep_vjp_given. */
+void orc_substep_vjp_given(const orc_model *m, const double *x, const double *v, double h,
+                           const int *off, const int *ids, const double *xb_out,
+                           const double *vb_out, double *xb_in, double *vb_in, double *kb,
+                           double *cb);
+
 void orc_substep_vjp(const orc_model *m, const double *x, const double *v, double h,
                      const double *xb_out, const double *vb_out, double *xb_in, double *vb_in,
                      double *kb, double *cb)
 {
     int N = m->N;
-    double *F = malloc(sizeof(double) * 3 * (size_t)N);
-    double *Fb = calloc(3 * (size_t)N, sizeof(double));
-    orc_forces(m, x, v, F);
-    int ids[ORC_MAX_CONTACTS];
+    double *xp = malloc(sizeof(double) * 3 * (size_t)N);
+    double *vp = malloc(sizeof(double) * 3 * (size_t)N);
+    int *off = malloc(sizeof(int) * ((size_t)N + 1));
+    size_t cap = 4 * (size_t)N + 16, len = 0;
+    int *ids = malloc(sizeof(int) * cap);
+    memcpy(xp, x, sizeof(double) * 3 * (size_t)N);
+    memcpy(vp, v, sizeof(double) * 3 * (size_t)N);
+    orc_predict(m, xp, vp, h);
+    int buf[ORC_MAX_CONTACTS];
+    off[0] = 0;
     for (int i = 0; i < N; ++i) {
-        if (m->w[i] == 0.0) {
-            /* pinned: x* = x, v* = 0, and no contact */
-            for (int q = 0; q < 3; ++q) { xb_in[3 * i + q] = xb_out[3 * i + q]; vb_in[3 * i + q] = 0.0; }
-            continue;
+        int n = 0;
+        if (m->w[i] != 0.0) {
+            n = contacts_of(m, xp + 3 * i, buf, ORC_MAX_CONTACTS, NULL);
+            if (n > ORC_MAX_CONTACTS) n = ORC_MAX_CONTACTS;
         }
-        double vs[3], xs[3];
-        for (int q = 0; q < 3; ++q) {
-            vs[q] = v[3 * i + q] + h * (m->w[i] * (F[3 * i + q] + fext_of(m, i, q)) + m->g[q]);
-            xs[q] = x[3 * i + q] + h * vs[q];
+        if (len + (size_t)n > cap) {
+            cap = 2 * (len + (size_t)n);
+            ids = realloc(ids, sizeof(int) * cap);
         }
-        int n = contacts_of(m, xs, ids, ORC_MAX_CONTACTS, NULL);
-        if (n > ORC_MAX_CONTACTS) n = ORC_MAX_CONTACTS;
-        double xbs[3], vbs[3];
-        for (int q = 0; q < 3; ++q) { xbs[q] = xb_out[3 * i + q]; vbs[q] = vb_out[3 * i + q]; }
-        if (n > 0) {
-            /* x' = x* + mean_t (th - (x* - A_t).n_t) n_t  ->  dx'/dx* = I - mean_t n_t n_t^T
-             * v' = -r v*                                  ->  dv'/dv* = -r I */
-            double acc[3] = {0, 0, 0};
-            for (int r = 0; r < n; ++r) {
-                const double *nt = m->tn + 3 * ids[r];
-                double s = dot3(nt, xbs);
-                for (int q = 0; q < 3; ++q) acc[q] += s * nt[q];
-            }
-            for (int q = 0; q < 3; ++q) {
-                xbs[q] = xbs[q] - acc[q] / n;
-                vbs[q] = -m->restitution * vbs[q];
-            }
-        }
-        /* x* = x + h v*,  v* = v + h (w F + g) */
-        for (int q = 0; q < 3; ++q) {
-            double vtot = vbs[q] + h * xbs[q];
-            xb_in[3 * i + q] = xbs[q];
-            vb_in[3 * i + q] = vtot;
-            Fb[3 * i + q] = h * m->w[i] * vtot;
-        }
+        memcpy(ids + len, buf, sizeof(int) * (size_t)n);
+        len += (size_t)n;
+        off[i + 1] = (int)len;
     }
-    /* spring forces, transposed spring by spring */
-    for (int s = 0; s < m->S; ++s) {
-        int a = m->ends[2 * s], b = m->ends[2 * s + 1];
-        double d[3], u[3], dv[3], lam[3];
-        sub3(x + 3 * b, x + 3 * a, d);
-        sub3(v + 3 * b, v + 3 * a, dv);
-        sub3(Fb + 3 * a, Fb + 3 * b, lam); /* f enters F_a with +, F_b with - */
-        double len = sqrt(dot3(d, d));
-        for (int q = 0; q < 3; ++q) u[q] = d[q] / len;
-        double dvu = dot3(dv, u);
-        double phi = m->k[s] * (len - m->rest[s]) + m->c[s] * dvu;
-        double ul = dot3(u, lam);
-        /* f = phi u(d) with phi = k (|d| - L0) + c (dv . u):
-         *   df = phi (I - u u^T)/|d| dd + u (k u + c (I - u u^T) dv/|d|)^T dd + c u u^T ddv */
-        double db[3], dvb[3];
-        for (int q = 0; q < 3; ++q) {
-            double perp_l = lam[q] - u[q] * ul;
-            double perp_dv = dv[q] - u[q] * dvu;
-            db[q] = phi / len * perp_l + m->k[s] * u[q] * ul + m->c[s] / len * perp_dv * ul;
-            dvb[q] = m->c[s] * u[q] * ul;
-        }
-        for (int q = 0; q < 3; ++q) {
-            xb_in[3 * b + q] += db[q];
-            xb_in[3 * a + q] -= db[q];
-            vb_in[3 * b + q] += dvb[q];
-            vb_in[3 * a + q] -= dvb[q];
-        }
-        if (kb) kb[s] += (len - m->rest[s]) * ul;
-        if (cb) cb[s] += dvu * ul;
-    }
-    free(F);
-    free(Fb);
+    orc_substep_vjp_given(m, x, v, h, off, ids, xb_out, vb_out, xb_in, vb_in, kb, cb);
+    free(xp);
+    free(vp);
+    free(off);
+    free(ids);
 }
 
-/* The same adjoint with the contact set given explicitly instead of recomputed: node i's
- * contact triangles are ids[off[i] .. off[i+1]) (ascending).  Used to evaluate the adjoint
- * on another implementation's trajectory and contact decisions. */
+/* Reverse-mode derivative of orc_substep_given (the substep with node i's contact
+ * triangles ids[off[i] .. off[i+1]), ascending, held fixed):
+ *   response  x' = x* + mean_t (th - (x* - A_t).n_t) n_t, so dx'/dx* = I - mean_t n_t n_t^T,
+ *             and v' = -r v*, so dv'/dv* = -r I (identity for a node without contacts);
+ *   integration x* = x + h v*, v* = v + h (w F + g);
+ *   spring forces transposed spring by spring. */
 void orc_substep_vjp_given(const orc_model *m, const double *x, const double *v, double h,
                            const int *off, const int *ids, const double *xb_out,
                            const double *vb_out, double *xb_in, double *vb_in, double *kb,

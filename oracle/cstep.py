@@ -7,7 +7,8 @@ directional derivative, exact to rounding for eps ~ 1e-30 (no subtractive cancel
 
 The substep is written out again here in numpy -- spring forces as in Alg. 1, semi-implicit
 Euler with pins, contact response averaged over the hits of a node -- with the contact set
-held at the one the real-valued step finds, which is how the adjoint treats it.  It does not
+held at the one the real-valued step finds (or at given sets), which is how the adjoint
+treats it.  It does not
 call the C oracle's arithmetic except to list contact triangles, so it is an independent
 check of the hand-written reverse-mode adjoint (``Model.substep_vjp``) through the identity
 <J delta, lambda> = <delta, J^T lambda>.
@@ -17,8 +18,10 @@ from __future__ import annotations
 import numpy as np
 
 
-def substep_jvp_cs(model, x, v, h, dx, dv, dk=None, dc=None, eps=1e-30):
-    """Returns (x', v') real parts and (dx', dv') tangents of one substep at (x, v)."""
+def substep_jvp_cs(model, x, v, h, dx, dv, dk=None, dc=None, eps=1e-30, contacts=None):
+    """Returns (x', v') real parts and (dx', dv') tangents of one substep at (x, v).
+    contacts: node i's contact triangles as contacts[i] (held fixed whatever their distance);
+    None = the sets the real-valued step finds."""
     x = np.asarray(x, dtype=np.float64).reshape(-1, 3)
     v = np.asarray(v, dtype=np.float64).reshape(-1, 3)
     N = x.shape[0]
@@ -50,7 +53,8 @@ def substep_jvp_cs(model, x, v, h, dx, dv, dk=None, dc=None, eps=1e-30):
         nrm = np.cross(P[model.tris[:, 1]] - A, P[model.tris[:, 2]] - A)
         nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
         for i in np.nonzero(free)[0]:
-            ids = model.contacts(Xs[i].real)
+            ids = (model.contacts(Xs[i].real) if contacts is None
+                   else np.sort(np.asarray(contacts[i], dtype=np.int64)))
             if len(ids) == 0:
                 continue
             push = model.thickness - np.sum((Xs[i][None, :] - A[ids]) * nrm[ids], axis=1)
