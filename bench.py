@@ -6,16 +6,26 @@ displaced sphere: 4 substeps of spring forces -> integration -> grid broad phase
 point-triangle narrow phase and response.  Inputs are seeded synthetic data shaped like the
 paper's Sec. 4.2 workload, resident in HBM before timing starts.
 
+Timing protocol: the cloth is first advanced, untimed, to the draped state (PREROLL frames:
+it has landed on the sphere and is sliding over it), then --warmup more frames; the state
+there starts every timed window.  One untimed window captures every graph the window replays;
+then REPEATS windows of exactly --steps frames are timed from that same state (wall clock and
+HIP events on the library's stream, between two device synchronisations), and the median
+window is reported.
+
 Prints one JSON line: node-updates/s (one node advanced by one substep), the roofline of the
-dominant kernel from HIP events on the library's stream, and the FP64 oracle timed on the
-host cores on a bounded sample of the same workload.
+dominant kernel (algorithmic bytes of the substep, collision share included, over the
+kernel's average duration), the other workloads' legs with their own rooflines, and the
+FP64 oracle timed on the host cores on a bounded sample of the same window.
 """
 from __future__ import annotations
 
 import argparse
 import dataclasses
 import json
+import multiprocessing as mp
 import os
+import statistics
 import sys
 import time
 
@@ -25,21 +35,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PREROLL = 150  # frames before the timed window (the cloth lands after about 40)
+REPEATS = 5
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300, help="timed frames")
-    ap.add_argument("--warmup", type=int, default=20, help="untimed frames")
+    ap.add_argument("--steps", type=int, default=20, help="timed frames per window")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed frames after the pre-roll")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0,
+                    help="oracle time per CPU leg (single thread, then all cores)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--launch", default="",
                     help="launch configuration, e.g. kernel=tile,tile=256,K=4,block=256,graph=1")
-    ap.add_argument("--sweep", action="store_true",
-                    help="time several launch configurations on the draped state and exit")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint comparison")
     ap.add_argument("--batch-cloths", type=int, default=512)
@@ -49,60 +60,154 @@ def parse():
     ap.add_argument("--no-mt", action="store_true",
                     help="skip the triangle-triangle narrow-phase timing")
     ap.add_argument("--no-forces-ab", action="store_true",
-                    help="skip the gather / scatter force-accumulation comparison")
+                    help="skip the 800x800 gather / scatter force-accumulation legs")
     return ap.parse_args()
 
+
+# ------------------------------------------------------------------ algorithmic bytes
+
+def algorithmic_bytes_per_substep(n_nodes: int, n_springs: int) -> float:
+    """Bytes one substep of forces and integration must move: x, v read and written
+    (48 B/node), inverse mass (4 B/node), and per spring two end indices plus k, c, rest
+    length (20 B)."""
+    return 52.0 * n_nodes + 20.0 * n_springs
+
+
+def collision_bytes(vol: dict) -> float:
+    """Bytes of the surface one substep's collision query touches, each array counted once:
+    36 B per distinct candidate triangle (its three vertices), 4 B per reference listed in a
+    queried non-empty cell, 8 B per queried non-empty cell (its two cell_start entries)."""
+    return 36.0 * vol["candidate_tris"] + 4.0 * vol["cell_refs"] + 8.0 * vol["cells"]
+
+
+# ------------------------------------------------------------------ timing helpers
+
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def time_windows(sim, stream, x0, v0, frames: int, repeats: int):
+    """`repeats` windows of `frames` frames, each from the state (x0, v0), after one untimed
+    window that captures the graphs they replay.  Returns [(wall_s, gpu_ms)] per window."""
+    import torch
+
+    sim.write_state(x0, v0)
+    sim.step(n_steps=frames)
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(repeats):
+        sim.write_state(x0, v0)
+        ev0, ev1 = _events()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        sim.step(n_steps=frames)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        out.append((time.perf_counter() - t0, ev0.elapsed_time(ev1)))
+    return out
+
+
+def median_window(windows):
+    """The window of median wall time (its wall seconds and GPU milliseconds)."""
+    order = sorted(range(len(windows)), key=lambda r: windows[r][0])
+    return windows[order[len(order) // 2]]
+
+
+def roofline(kernel: str, bytes_per_launch: float, launch_s: float, launch=None, traffic=None):
+    achieved = bytes_per_launch / launch_s / 1e9
+    out = {"kernel": kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+           "bytes_per_launch": bytes_per_launch, "avg_launch_us": launch_s * 1e6}
+    if launch is not None:
+        out["launch"] = launch
+    return out
+
+
+# ------------------------------------------------------------------ legs
 
 def bench_batched(n_cloths: int, frames: int):
     """512 cloths of side U{16..128}, each over its own 5,120-triangle sphere: one batch handle
     (autotuned launch configuration) against plain per-cloth handles stepped one after another,
-    both on this GPU.  Returns node-updates/s of each and the final-state bit identity."""
+    both on this GPU, over the same frames from the same state (frame 100: every cloth is on
+    its sphere).  Returns node-updates/s of each, the batch kernel's roofline (collision share
+    counted on the per-cloth handles, whose states are bit-identical) and the final-state bit
+    identity of sampled cloths."""
     import torch
 
     from paper_2507_11794_amd import cloth, workloads
 
     cl = workloads.config3(n_cloths=n_cloths)
     n_nodes = sum(c.n_nodes for c in cl)
+    n_springs = sum(c.n_springs for c in cl)
     sub = cl[0].n_substeps
     stream = torch.cuda.current_stream()
     # one grid cell of one mean surface edge for every cloth (the spheres share their mesh
     # size; 3.5 % faster than the default of two edges, the same contacts)
     cell = float(np.float32(workloads.mean_edge_length(cl[0].verts, cl[0].tris)))
     b = cloth.ClothBatch(cl, stream=stream.cuda_stream, cell_size=cell)
-    # the cloths land on their spheres after about 80 frames: tune there, on contacts, as
-    # the timed frames run (the tuner restores the state it starts from)
     warm = 100
     b.step(n_steps=warm)
-    tuned = b.autotune(frames=4)
+    # tune on contacts, as the timed frames run (the tuner restores the state it starts from)
+    tuned = b.autotune(frames=16)
+    b.step(n_steps=frames)  # untimed: captures the graphs of a window of this length
+    torch.cuda.synchronize()
     b.step(n_steps=2)
     torch.cuda.synchronize()
+    ev0, ev1 = _events()
     t0 = time.perf_counter()
+    ev0.record(stream)
     b.step(n_steps=frames)
+    ev1.record(stream)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
-    xb = [b.read_state(i)[0] for i in (0, n_cloths // 2, n_cloths - 1)]
+    gpu_ms = ev0.elapsed_time(ev1)
+    first = warm + frames + 2
+    sample = (0, n_cloths // 2, n_cloths - 1)
+    xb = [b.read_state(i)[0] for i in sample]
     b.close()
     sims = [cloth.Cloth(dataclasses.replace(c, cell_size=cell), stream=stream.cuda_stream)
             for c in cl]
     for s_ in sims:
-        s_.step(n_steps=warm + 2)
+        s_.step(n_steps=first)
     torch.cuda.synchronize()
+    coll = sum(collision_bytes(s_.query_volume()) for s_ in sims)
     t0 = time.perf_counter()
     for s_ in sims:
         s_.step(n_steps=frames)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
-    same = all(np.array_equal(sims[i].read_state()[0], x)
-               for i, x in zip((0, n_cloths // 2, n_cloths - 1), xb))
+    same = all(np.array_equal(sims[i].read_state()[0], x) for i, x in zip(sample, xb))
     for s_ in sims:
         s_.close()
     upd = n_nodes * sub * frames
-    return {"cloths": n_cloths, "nodes": n_nodes, "frames": frames, "first_timed_frame": warm + 2,
-            "cell_size": cell,
+    K = tuned.get("substeps_per_launch", 1) if tuned.get("kernel") == cloth.CLOTH_KERNEL_TILE else 1
+    launch_s = gpu_ms * 1e-3 / (frames * sub / K)
+    per_sub = algorithmic_bytes_per_substep(n_nodes, n_springs) + coll
+    return {"cloths": n_cloths, "nodes": n_nodes, "springs": n_springs, "frames": frames,
+            "first_timed_frame": first, "cell_size": cell,
             "batched_node_updates_per_s": upd / t_batch,
             "plain_per_cloth_node_updates_per_s": upd / t_plain,
             "speedup": t_plain / t_batch, "launch": tuned,
+            "collision_bytes_per_substep": coll,
+            "roofline": roofline("batched substep kernel (autotuned launch)", per_sub * K, launch_s),
             "bit_identical_sampled_cloths": bool(same)}
+
+
+def adjoint_bytes_per_substep(n_nodes: int, n_springs: int, coll: float) -> float:
+    """Bytes one substep of the gradient run moves, each array counted once per pass: the
+    forward substep (52 B/node + 20 B/spring + collision), its recompute from the checkpoint
+    (the same, plus the stored prediction, 12 B/node), and the backward substep: the node
+    pass reads the state, prediction, inverse mass and output adjoints (64 B/node) and writes
+    the partial adjoints and the force adjoint (36 B/node), the spring pass reads the state,
+    force and partial adjoints (60 B/node) and writes the input adjoints (24 B/node), per
+    spring the ends and parameters (20 B) and dL/dk, dL/dc in FP64, read and written
+    (32 B), plus the collision query again."""
+    fwd = algorithmic_bytes_per_substep(n_nodes, n_springs) + coll
+    rec = fwd + 12.0 * n_nodes
+    bwd = (64.0 + 36.0 + 60.0 + 24.0) * n_nodes + (20.0 + 32.0) * n_springs + coll
+    return fwd + rec + bwd
 
 
 def bench_adjoint(frames: int = 200):
@@ -118,37 +223,55 @@ def bench_adjoint(frames: int = 200):
     dev = torch.device("cuda")
     stream = torch.cuda.current_stream()
     sim = cloth.Cloth(inp, stream=stream.cuda_stream)
-    sim.step(n_steps=frames)
-    # plain stepping of the same frames, timed after a warm-up pass (graph capture) from the
-    # initial state
     sim2 = cloth.Cloth(inp, stream=stream.cuda_stream)
-    sim2.step(n_steps=frames)
+    sim2.step(n_steps=frames)  # untimed: graph capture
+    sim2.write_state(inp.x0, inp.v0)
+    sim2.step(n_steps=frames // 2)
+    coll = collision_bytes(sim2.query_volume())  # mid-run (the cloth is on the sphere)
     sim2.write_state(inp.x0, inp.v0)
     torch.cuda.synchronize()
+    ev0, ev1 = _events()
     t0 = time.perf_counter()
+    ev0.record(stream)
     sim2.step(n_steps=frames)
+    ev1.record(stream)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
+    plain_ms = ev0.elapsed_time(ev1)
     k = torch.tensor(inp.k, device=dev, requires_grad=True)
     c = torch.tensor(inp.c, device=dev, requires_grad=True)
     v0 = torch.zeros((inp.n_nodes, 3), device=dev, requires_grad=True)
     target = torch.zeros((inp.n_nodes, 3), device=dev)
-    for rep in range(2):  # the first pass allocates the checkpoint buffers
+    times = []
+    for rep in range(3):  # the first pass allocates the checkpoint buffers
         torch.cuda.synchronize()
+        ev0, ev1 = _events()
         t0 = time.perf_counter()
+        ev0.record(stream)
         x = ClothRollout.apply(sim, k, c, v0, inp.dt, inp.n_substeps, frames, 20, [frames])
         loss = ((x[0] - target) ** 2).sum(dim=1).mean()
         loss.backward()
+        ev1.record(stream)
         torch.cuda.synchronize()
-        t_grad = time.perf_counter() - t0
+        times.append((time.perf_counter() - t0, ev0.elapsed_time(ev1)))
         k.grad = c.grad = v0.grad = None
     sim.close()
     sim2.close()
-    upd = inp.n_nodes * inp.n_substeps * frames
+    t_grad, grad_ms = median_window(times[1:])
+    n_sub = inp.n_substeps * frames
+    upd = inp.n_nodes * n_sub
+    per_sub = adjoint_bytes_per_substep(inp.n_nodes, inp.n_springs, coll)
     return {"nodes": inp.n_nodes, "frames": frames, "checkpoint_frames": 20,
             "plain_forward_node_updates_per_s": upd / t_plain,
             "forward_backward_node_updates_per_s": upd / t_grad,
-            "gradient_cost_vs_plain": t_grad / t_plain}
+            "gradient_cost_vs_plain": t_grad / t_plain,
+            "plain_forward_roofline": roofline(
+                "k_substep (64x64 cloth: 64 wavefronts, latency-bound)",
+                algorithmic_bytes_per_substep(inp.n_nodes, inp.n_springs) + coll,
+                plain_ms * 1e-3 / n_sub),
+            "gradient_roofline": roofline(
+                "forward + recompute + adjoint kernels, per substep", per_sub,
+                grad_ms * 1e-3 / n_sub)}
 
 
 def bench_normals(sim, n_nodes: int, reps: int = 200):
@@ -159,8 +282,7 @@ def bench_normals(sim, n_nodes: int, reps: int = 200):
     stream = torch.cuda.current_stream()
     out = sim.vertex_normals()
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0, ev1 = _events()
     ev0.record(stream)
     for _ in range(reps):
         sim.vertex_normals(out)
@@ -230,18 +352,12 @@ def bench_mt(frames: int = 30):
     stream = torch.cuda.current_stream()
     sim = cloth.Cloth(inp, flags=cloth.CLOTH_F_NARROW_MT, stream=stream.cuda_stream)
     sim.step(n_steps=110)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    sim.step(n_steps=frames)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
+    x0, v0 = sim.read_state()
+    wall, ms = median_window(time_windows(sim, stream, x0, v0, frames, 3))
     sim.close()
-    return {"frames": frames, "nodes": inp.n_nodes, "tris": inp.n_tris,
+    return {"frames": frames, "first_timed_frame": 110, "nodes": inp.n_nodes, "tris": inp.n_tris,
             "us_per_substep": ms * 1e3 / (frames * inp.n_substeps),
-            "node_updates_per_s": inp.n_nodes * inp.n_substeps * frames / (ms * 1e-3)}
+            "node_updates_per_s": inp.n_nodes * inp.n_substeps * frames / wall}
 
 
 FORCES_AB = ["kernel=direct", "kernel=tile,tile=256,K=1,block=256", "kernel=tile,tile=256,K=4,block=256",
@@ -249,11 +365,12 @@ FORCES_AB = ["kernel=direct", "kernel=tile,tile=256,K=1,block=256", "kernel=tile
 
 
 def bench_forces_ab(frames: int = 40):
-    """Force accumulation compared on the 800x800 hanging cloth (640,000 nodes, 3.83M
-    springs, no collision, so the spring pass dominates): the node-centric gather (one
-    launch per substep, and temporally blocked tiles) against Alg. 1's spring-centric scatter
-    with FP32 atomics and with int32 fixed-point atomics.  Microseconds per substep from HIP
-    events over the same frames from the same state."""
+    """The 800x800 hanging cloth (640,000 nodes, 3.83M springs, no collision, so the spring
+    pass dominates): the node-centric gather (one launch per substep, and temporally blocked
+    tiles, the default for a handle without a surface) against Alg. 1's spring-centric
+    scatter with FP32 atomics and with int32 fixed-point atomics.  Microseconds per substep
+    from HIP events (median of 3 windows from the same state, graphs captured beforehand),
+    and the roofline of the default tile kernel."""
     import torch
 
     from paper_2507_11794_amd import cloth, workloads
@@ -261,25 +378,23 @@ def bench_forces_ab(frames: int = 40):
     inp = workloads.config2()
     stream = torch.cuda.current_stream()
     sim = cloth.Cloth(inp, stream=stream.cuda_stream)
+    default = sim.get_launch()
     sim.step(n_steps=10)
     x0, v0 = sim.read_state()
     out = {"nodes": inp.n_nodes, "springs": inp.n_springs, "frames": frames,
            "substeps_per_frame": inp.n_substeps}
     for text in FORCES_AB:
         sim.set_launch(**{**cloth.launch_dict(cloth.make_launch()), **parse_launch(text)})
-        sim.write_state(x0, v0)
-        sim.step(n_steps=2)
-        sim.write_state(x0, v0)
-        torch.cuda.synchronize()
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        ev0.record(stream)
-        sim.step(n_steps=frames)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        out[text.replace("kernel=", "")] = round(ev0.elapsed_time(ev1) * 1e3 /
-                                                 (frames * inp.n_substeps), 3)
+        _, ms = median_window(time_windows(sim, stream, x0, v0, frames, 3))
+        out[text.replace("kernel=", "")] = round(ms * 1e3 / (frames * inp.n_substeps), 3)
+    sim.set_launch(**default)
+    _, ms = median_window(time_windows(sim, stream, x0, v0, frames, 3))
     sim.close()
+    K = default["substeps_per_launch"] if default["kernel"] == cloth.CLOTH_KERNEL_TILE else 1
+    launch_s = ms * 1e-3 / (frames * inp.n_substeps / K)
+    out["roofline"] = roofline(
+        "k_tile (default launch without a surface)",
+        algorithmic_bytes_per_substep(inp.n_nodes, inp.n_springs) * K, launch_s, default)
     return out
 
 
@@ -288,65 +403,19 @@ def parse_launch(text: str) -> dict:
 
     cfg = {}
     names = {"tile": "tile_nodes", "K": "substeps_per_launch", "block": "block_threads",
-             "graph": "use_graph", "hits": "hit_slots", "xcd": "xcd_runs", "split": "split_refs", "sched": "schedule", "wg": "workgroups"}
+             "graph": "use_graph", "hits": "hit_slots", "xcd": "xcd_runs", "split": "split_refs",
+             "sched": "schedule", "wg": "workgroups"}
     for part in filter(None, text.split(",")):
         k, v = part.split("=")
         if k == "kernel":
             cfg["kernel"] = {"tile": cloth.CLOTH_KERNEL_TILE, "direct": cloth.CLOTH_KERNEL_DIRECT,
                              "scatter_f32": cloth.CLOTH_KERNEL_SCATTER_F32,
-                             "scatter_fix": cloth.CLOTH_KERNEL_SCATTER_FIX}[v]
+                             "scatter_fix": cloth.CLOTH_KERNEL_SCATTER_FIX,
+                             "lanes2": cloth.CLOTH_KERNEL_LANES2,
+                             "lanes4": cloth.CLOTH_KERNEL_LANES4}[v]
         else:
             cfg[names.get(k, k)] = int(v)
     return cfg
-
-
-SWEEP = [
-    "kernel=direct", "kernel=direct,xcd=1", "kernel=direct,xcd=2", "kernel=direct,xcd=4",
-    "kernel=direct,xcd=8", "kernel=direct,xcd=16", "kernel=direct,xcd=32", "kernel=direct,xcd=64",
-    "kernel=direct,block=128,xcd=8", "kernel=direct,block=256,xcd=4", "kernel=direct,split=48",
-    "kernel=direct,hits=48", "kernel=direct,hits=0",
-    "kernel=tile,tile=128,K=1,block=256", "kernel=tile,tile=256,K=1,block=256",
-    "kernel=scatter_f32", "kernel=scatter_fix",
-]
-
-
-def sweep(inp, frames: int = 40):
-    """Time launch configurations from the same draped state (results are bit-identical)."""
-    import torch
-
-    from paper_2507_11794_amd import cloth
-
-    stream = torch.cuda.current_stream()
-    sim = cloth.Cloth(inp, stream=stream.cuda_stream)
-    sim.step(n_steps=150)
-    x0, v0 = sim.read_state()
-    ref = None
-    for text in SWEEP:
-        sim.write_state(x0, v0)
-        try:
-            # every entry starts from the library's defaults, not from the previous entry
-            sim.set_launch(**{**cloth.launch_dict(cloth.make_launch()), **parse_launch(text)})
-        except cloth.ClothError as e:
-            print(json.dumps({"sweep": text, "error": str(e)}), flush=True)
-            continue
-        sim.step(n_steps=5)
-        sim.write_state(x0, v0)
-        torch.cuda.synchronize()
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        ev0.record(stream)
-        sim.step(n_steps=frames)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        us = ev0.elapsed_time(ev1) * 1e3 / (frames * inp.n_substeps)
-        x, _ = sim.read_state()
-        same = None if ref is None else bool(np.array_equal(x, ref))
-        ref = x if ref is None else ref
-        print(json.dumps({"sweep": text, "us_per_substep": round(us, 3),
-                          "node_updates_per_s": inp.n_nodes / (us * 1e-6),
-                          "bit_identical_to_first": same}), flush=True)
-    sim.close()
-    return 0
 
 
 def calibrate_copy(mib: int, reps: int = 5):
@@ -393,34 +462,84 @@ def counter_traffic(launch: dict):
     return rec.get("traffic_bytes_per_launch")
 
 
-def algorithmic_bytes_per_substep(n_nodes: int, n_springs: int) -> float:
-    """Bytes one substep must move: x, v read and written (48 B/node), inverse mass
-    (4 B/node), and per spring two end indices plus k, c, rest length (20 B)."""
-    return 52.0 * n_nodes + 20.0 * n_springs
+# ------------------------------------------------------------------ CPU baseline
 
-
-def cpu_baseline(inp, x, v, seconds: float):
+def _oracle_leg(args):
+    """One oracle process: the workload's model, the window's starting state, substeps until
+    `seconds` have passed (started together with the other processes at `barrier`).  Returns
+    (substeps, seconds, start, end)."""
+    x, v, seconds, barrier = args
     import oracle
+    from paper_2507_11794_amd import workloads
 
+    inp = workloads.config1()
     model = oracle.Model.from_inputs(inp)
     h = float(np.float32(np.float32(inp.dt) / np.float32(inp.n_substeps)))
     xs, vs = x.astype(np.float64), v.astype(np.float64)
+    if barrier is not None:
+        barrier.wait()
     n_sub = 0
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds and n_sub < 4 * inp.n_steps:
-        xs, vs = model.run(xs, vs, h, inp.n_substeps)
-        n_sub += inp.n_substeps
-    dt = time.perf_counter() - t0
+    start = time.time()
+    while time.perf_counter() - t0 < seconds:
+        xs, vs = model.run(xs, vs, h, 1)
+        n_sub += 1
+    return n_sub, time.perf_counter() - t0, start, time.time()
+
+
+def _proc_leg(q, args):
+    q.put(_oracle_leg(args))
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(inp, x, v, seconds: float):
+    """The FP64 oracle on the host cores from the timed window's starting state: one process
+    (single thread), then one process per core of this process's affinity (at most 16, the
+    host share of one GPU), each stepping its own copy of the workload, started together.
+    The oracle itself is single-threaded."""
+    n1, t1, _, _ = _oracle_leg((x, v, seconds, None))
+    single = inp.n_nodes * n1 / t1
+    cores = len(os.sched_getaffinity(0))
+    P = max(1, min(cores, 16))
+    ctx = mp.get_context("spawn")
+    barrier = ctx.Barrier(P)
+    q = ctx.Queue()
+    procs = [ctx.Process(target=_proc_leg, args=(q, (x, v, seconds, barrier))) for _ in range(P)]
+    for p in procs:
+        p.start()
+    res = [q.get(timeout=600) for _ in procs]
+    for p in procs:
+        p.join()
+    subs = sum(r[0] for r in res)
+    span = max(r[3] for r in res) - min(r[2] for r in res)
+    allc = inp.n_nodes * subs / span
     return {
-        "value": inp.n_nodes * n_sub / dt,
+        "value": allc,
         "unit": "node-updates/s",
-        "cores": 1,
+        "cores": P,
         "kind": "oracle",
-        "sample": f"{n_sub} substeps ({n_sub // inp.n_substeps} frames) of the same "
-                  f"{inp.n_nodes}-node cloth vs {inp.n_tris}-triangle surface, from the GPU "
-                  f"state after the timed frames; single-threaded FP64 C oracle, {dt:.1f} s",
+        "single_thread_value": single,
+        "cpu_model": cpu_model(),
+        "affinity_cores": cores,
+        "os_cpu_count": os.cpu_count(),
+        "sample": f"the {inp.n_nodes}-node cloth vs {inp.n_tris}-triangle surface from the timed "
+                  f"window's starting (draped) state: single thread {n1} substeps in {t1:.1f} s; "
+                  f"then {P} processes, one per core, each stepping its own copy for "
+                  f"{seconds:.0f} s ({subs} substeps in all over {span:.1f} s); single-threaded "
+                  f"FP64 C oracle",
     }
 
+
+# ------------------------------------------------------------------ main
 
 def main():
     args = parse()
@@ -436,41 +555,30 @@ def main():
     if args.calibrate_copy:
         return calibrate_copy(args.calibrate_copy)
     inp = workloads.config1()
-    if args.sweep:
-        return sweep(inp)
     stream = torch.cuda.current_stream()
     sim = cloth.Cloth(inp, stream=stream.cuda_stream)
     if args.launch:
         sim.set_launch(**parse_launch(args.launch))
     launch = sim.get_launch()
     K = launch["substeps_per_launch"] if launch["kernel"] == cloth.CLOTH_KERNEL_TILE else 1
-    sim.step(n_steps=args.warmup)
-    torch.cuda.synchronize()
-
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    sim.step(n_steps=args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall = t1 - t0
-    gpu_ms = ev0.elapsed_time(ev1)
+    sim.step(n_steps=PREROLL + args.warmup)
+    x0, v0 = sim.read_state()
+    vol0 = sim.query_volume()
+    windows = time_windows(sim, stream, x0, v0, args.steps, REPEATS)
+    vol1 = sim.query_volume()
+    wall, gpu_ms = median_window(windows)
     launches = args.steps * inp.n_substeps / K
     kernel_s = gpu_ms * 1e-3 / launches
     node_updates = inp.n_nodes * inp.n_substeps * args.steps
-    value = node_updates / wall
-    bps = algorithmic_bytes_per_substep(inp.n_nodes, inp.n_springs) * K
-    achieved = bps / kernel_s / 1e9
-    x, v = sim.read_state()
+    coll = 0.5 * (collision_bytes(vol0) + collision_bytes(vol1))
+    per_sub = algorithmic_bytes_per_substep(inp.n_nodes, inp.n_springs) + coll
     info = sim.info()
     normals = None if args.no_normals else bench_normals(sim, inp.n_nodes)
     sim.close()
+    first = PREROLL + args.warmup
     out = {
         "metric": "node-updates/s w/ collision, 100K nodes vs 100K tris; batched+adjoint vs plain",
-        "value": value,
+        "value": node_updates / wall,
         "unit": "node-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -486,24 +594,25 @@ def main():
                         f"dropped on a displaced sphere of {inp.n_tris} triangles; "
                         f"{inp.n_substeps} substeps per frame, dt = 1/600 s",
             "substeps_per_step": inp.n_substeps,
+            "first_timed_frame": first,
+            "timing": f"median of {REPEATS} windows of {args.steps} frames from the state at "
+                      f"frame {first} (graphs captured beforehand)",
+            "window_wall_s": [round(w[0], 6) for w in windows],
+            "grid_cell_m": float(np.float32(inp.cell_size)),
+            "grid_cell_note": "one mean surface edge (the library default is two; the contacts "
+                              "do not depend on it)",
             "grid_cells": info["cells"],
             "grid_refs": info["refs"],
+            "collision_query": {"start": vol0, "end": vol1},
         },
-        "roofline": {
-            "kernel": ("k_tile (K substeps of fused forces, integration, broad and narrow "
-                       "phase per launch)" if K > 1 or launch["kernel"] == cloth.CLOTH_KERNEL_TILE
-                       else "k_substep (fused forces, integration, broad and narrow phase)"),
-            "launch": launch,
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": counter_traffic(launch),
-            "bytes_per_launch": bps,
-            "avg_launch_us": kernel_s * 1e6,
-        },
+        "roofline": roofline(
+            "k_tile (K substeps of fused forces, integration, broad and narrow phase per launch)"
+            if launch["kernel"] == cloth.CLOTH_KERNEL_TILE
+            else "k_substep (fused forces, integration, broad and narrow phase)",
+            per_sub * K, kernel_s, launch, counter_traffic(launch)),
     }
+    out["roofline"]["bytes_per_node_update"] = per_sub / inp.n_nodes
+    out["roofline"]["collision_bytes_per_substep"] = coll
     if normals:
         out["normals"] = normals
     if not args.no_moving:
@@ -511,13 +620,13 @@ def main():
     if not args.no_mt:
         out["mt_narrow_phase"] = bench_mt()
     if not args.no_forces_ab:
-        out["forces_ab_us_per_substep"] = bench_forces_ab()
+        out["forces_800x800"] = bench_forces_ab()
     if not args.no_batch:
         out["batched"] = bench_batched(args.batch_cloths, 200)
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(200)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(inp, x, v, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(inp, x0, v0, args.cpu_seconds)
     print(json.dumps(out))
     return 0
 

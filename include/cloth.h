@@ -77,9 +77,13 @@ enum cloth_kernel {
     /* spring-centric force accumulation as in Alg. 1 (one thread per spring adding +f / -f
      * to its ends), then a node pass; for measuring the paper's design against the gather */
     CLOTH_KERNEL_SCATTER_F32 = 2, /* FP32 atomic adds: rounding varies from run to run */
-    CLOTH_KERNEL_SCATTER_FIX = 3  /* int32 atomics at 2^-24 N (WGSL's integer atomics):
+    CLOTH_KERNEL_SCATTER_FIX = 3, /* int32 atomics at 2^-24 N (WGSL's integer atomics):
                                      deterministic; |f| < 8 N per spring component, else
                                      cloth_read_state reports CLOTH_ENAN */
+    CLOTH_KERNEL_LANES2 = 4,      /* one launch per substep, two lanes per node: each lane
+                                     gathers half the node's springs and tests half of its
+                                     cell's references (same results as DIRECT, bit for bit) */
+    CLOTH_KERNEL_LANES4 = 5       /* the same with four lanes per node */
 };
 
 /* How tiles are assigned to workgroups (tile kernel). */
@@ -197,7 +201,9 @@ int cloth_destroy(cloth_sim* sim);
  * the handle's surface grid.  A point P is a candidate of triangle t iff
  * lo_t <= P <= hi_t on every axis, lo_t = fl32(min of t's vertex coordinates - thickness),
  * hi_t = fl32(max + thickness) -- the exact set an O(points x triangles) FP32 brute force
- * gives, found through the uniform grid.
+ * gives, found through the uniform grid by the query the step kernels run (the coded box
+ * test of the point's cell, undecided boxes settled with the exact box; the handle's
+ * hit_slots list length), stopped before the narrow phase.
  *   points     [host] [n_points*3] AoS.
  *   pairs_out  [host] [cap*2] receives (point index, triangle id) sorted by point, then
  *              triangle; at most cap pairs are written.
@@ -313,6 +319,20 @@ int cloth_batch_destroy(cloth_batch* b);
  * listed ids are sorted but, past cap, need not be the smallest.
  */
 int cloth_debug_contacts(cloth_sim* sim, float h, int* counts, int* ids, int cap);
+
+/*
+ * cloth_debug_query_volume -- the surface data the next substep's collision query (a3 with
+ * the listed, coded box test of the step kernels) touches from the current state, for
+ * counting the collision share of a substep's algorithmic bytes.  out [host] long long[6]:
+ *   out[0] distinct non-empty grid cells queried by the unpinned nodes' predictions,
+ *   out[1] references listed in those cells (each cell counted once),
+ *   out[2] distinct triangles that are a box hit (broad-phase candidate) of some node,
+ *   out[3] node queries of a non-empty cell, out[4] references tested over all nodes,
+ *   out[5] box hits over all nodes.
+ * Single-cloth handles with the proximity narrow phase.  Synchronises.
+ * Errors: CLOTH_EINVAL (NULL, h <= 0, batch or MT handle), CLOTH_ESTATE, CLOTH_EDEVICE.
+ */
+int cloth_debug_query_volume(cloth_sim* sim, float h, long long* out);
 
 /*
  * cloth_update_surface / cloth_batch_update_surface -- move or deform a collision surface:

@@ -39,6 +39,7 @@ class cloth_launch(C.Structure):
 
 CLOTH_KERNEL_TILE, CLOTH_KERNEL_DIRECT = 0, 1
 CLOTH_KERNEL_SCATTER_F32, CLOTH_KERNEL_SCATTER_FIX = 2, 3
+CLOTH_KERNEL_LANES2, CLOTH_KERNEL_LANES4 = 4, 5
 CLOTH_SCHED_GRID, CLOTH_SCHED_LPT, CLOTH_SCHED_RR = 0, 1, 2
 
 
@@ -92,6 +93,7 @@ _SIGNATURES = [
     ("cloth_batch_info", C.c_int, [_vp, _llp]),
     ("cloth_batch_destroy", C.c_int, [_vp]),
     ("cloth_debug_contacts", C.c_int, [_vp, C.c_float, _ip, _ip, C.c_int]),
+    ("cloth_debug_query_volume", C.c_int, [_vp, C.c_float, _llp]),
     ("cloth_vertex_normals", C.c_int, [_vp, _vp]),
     ("cloth_update_surface", C.c_int, [_vp, _fp, C.c_int]),
     ("cloth_batch_update_surface", C.c_int, [_vp, C.c_int, _fp, C.c_int]),
@@ -386,14 +388,32 @@ class Cloth:
         cloth_vertex_normals(self.h, out.data_ptr())
         return out
 
-    def debug_contacts(self, h, cap=16):
-        """Per node, the ascending triangle ids of its contacts in a substep of length h."""
+    def debug_contacts(self, h, cap=16, csr=False):
+        """Per node, the ascending triangle ids of its contacts in a substep of length h (a
+        list of lists; with csr=True, (off [N+1], ids) int32 arrays)."""
         counts = np.zeros(self.n, dtype=np.int32)
         ids = np.zeros(self.n * cap, dtype=np.int32)
         _check(load().cloth_debug_contacts(_vp(self.h), float(h), _ptr(counts, _ip),
                                            _ptr(ids, _ip), int(cap)))
         assert counts.max(initial=0) <= cap, "raise cap"
+        if csr:
+            off = np.zeros(self.n + 1, dtype=np.int32)
+            np.cumsum(counts, out=off[1:])
+            keep = np.arange(cap)[None, :] < counts[:, None]
+            return off, ids.reshape(self.n, cap)[keep].astype(np.int32)
         return [ids[i * cap:i * cap + counts[i]].tolist() for i in range(self.n)]
+
+    def query_volume(self, h=None):
+        """Surface data the next substep's collision query touches (cloth_debug_query_volume):
+        dict of distinct non-empty cells queried, their references, distinct box-hit
+        triangles, node queries, references tested and box hits over all nodes."""
+        if h is None:
+            h = float(np.float32(np.float32(self.inp.dt) / np.float32(self.inp.n_substeps)))
+        out = np.zeros(6, dtype=np.int64)
+        _check(load().cloth_debug_query_volume(_vp(self.h), float(h), _ptr(out, _llp)))
+        keys = ("cells", "cell_refs", "candidate_tris", "node_queries", "refs_tested",
+                "box_hits")
+        return {k: int(v) for k, v in zip(keys, out)}
 
     def autotune(self, frames=10, dt=None, n_substeps=None):
         return cloth_autotune(self.h, self.inp.dt if dt is None else dt,

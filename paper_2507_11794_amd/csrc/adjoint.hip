@@ -254,31 +254,70 @@ __global__ void __launch_bounds__(256)
 
 // Contact set each node would get in a substep of length h from (xs, vs): counts[slot] and
 // up to cap triangle ids at ids[slot*cap ...] (ascending).  Same arithmetic as the step.
-__global__ void __launch_bounds__(256)
-    k_debug_contacts(const ClothView cv, const SurfaceView sv, const StepParams sp,
-                     const float* __restrict__ xs, const float* __restrict__ vs, int* counts,
-                     int* ids, int cap) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cv.n) return;
+// The prediction of node i (gather and integration, as the step kernels compute it).
+__device__ __forceinline__ void predict_at(const ClothView& cv, const StepParams& sp,
+                                           const float* __restrict__ xs,
+                                           const float* __restrict__ vs, int i, float w,
+                                           float& px, float& py, float& pz) {
     const int ld = cv.ld;
-    const float w = cv.w[i];
-    if (w == 0.0f || sv.n_tris == 0) {
-        counts[i] = 0;
-        return;
-    }
     const float xi = xs[i], yi = xs[ld + i], zi = xs[2 * ld + i];
     const float vxi = vs[i], vyi = vs[ld + i], vzi = vs[2 * ld + i];
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
     gather_global(cv, xs, vs, i, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz);
     add_external(sp, i, fx, fy, fz);
-    float px, py, pz, qx, qy, qz;
+    float qx, qy, qz;
     integrate(w, sp.h, sp.g, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz, px, py, pz, qx, qy, qz);
+}
+
+// Contact sets of the next substep through the step kernels' own query (one wavefront per
+// workgroup, hit_slots list entries per lane as in the step).
+__global__ void __launch_bounds__(64)
+    k_debug_contacts(const ClothView cv, const SurfaceView sv, const StepParams sp,
+                     const float* __restrict__ xs, const float* __restrict__ vs, int* counts,
+                     int* ids, int cap, int hit_slots) {
+    extern __shared__ uint32_t hit_lds[];
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i >= cv.n) return;
+    const float w = cv.w[i];
+    if (w == 0.0f || sv.n_tris == 0) {
+        counts[i] = 0;
+        return;
+    }
+    float px, py, pz;
+    predict_at(cv, sp, xs, vs, i, w, px, py, pz);
     int n = 0;
-    const int cnt = contacts_visit(sv, px, py, pz, [&](const float4&, float, uint32_t t) {
+    auto visit = [&](const float4&, float, uint32_t t) {
         if (n < cap) ids[(size_t)i * cap + n] = (int)t;
         ++n;
-    });
-    counts[i] = cnt;
+    };
+    counts[i] = hit_slots > 0 ? contacts_listed(sv, hit_lds + threadIdx.x, hit_slots, px, py, pz, visit)
+                              : contacts_visit(sv, px, py, pz, visit);
+}
+
+// Surface data touched by the next substep's collision query (see launch_debug_volume).
+__global__ void __launch_bounds__(64)
+    k_debug_volume(const ClothView cv, const SurfaceView sv, const StepParams sp,
+                   const float* __restrict__ xs, const float* __restrict__ vs, int hit_slots,
+                   uint32_t* cell_bits, uint32_t* tri_bits, unsigned long long* totals) {
+    extern __shared__ uint32_t hit_lds[];
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i >= cv.n || sv.n_tris == 0) return;
+    const float w = cv.w[i];
+    if (w == 0.0f) return;  // pinned nodes never query
+    float px, py, pz;
+    predict_at(cv, sp, xs, vs, i, w, px, py, pz);
+    const int cell = cell_of(sv, px, py, pz);
+    if (cell < 0) return;
+    const uint32_t nref = sv.cell_start[cell + 1] - sv.cell_start[cell];
+    if (nref == 0) return;
+    atomicOr(cell_bits + (cell >> 5), 1u << (cell & 31));
+    auto visit = [&](const float4&, float, uint32_t t) { atomicOr(tri_bits + (t >> 5), 1u << (t & 31)); };
+    const int hits = hit_slots > 0
+                         ? contacts_listed<false>(sv, hit_lds + threadIdx.x, hit_slots, px, py, pz, visit)
+                         : contacts_visit<false>(sv, px, py, pz, visit);
+    atomicAdd(totals, 1ull);
+    atomicAdd(totals + 1, (unsigned long long)nref);
+    atomicAdd(totals + 2, (unsigned long long)hits);
 }
 
 // out_soa[k*ld + slot[id]] (+)= in_aos[3*id + k]
@@ -378,9 +417,22 @@ hipError_t launch_adj_springs(const ClothView& cv, const float* xs, const float*
 
 hipError_t launch_debug_contacts(const ClothView& cv, const SurfaceView& sv, const StepParams& sp,
                                 const float* xs, const float* vs, int* counts, int* ids, int cap,
-                                hipStream_t st) {
+                                int hit_slots, hipStream_t st) {
     if (cv.n <= 0) return hipSuccess;
-    k_debug_contacts<<<blocks(cv.n, 256), 256, 0, st>>>(cv, sv, sp, xs, vs, counts, ids, cap);
+    if (hit_slots < 0 || hit_slots > kMaxHitSlots) return hipErrorInvalidValue;
+    k_debug_contacts<<<blocks(cv.n, 64), 64, wave_query_lds(hit_slots), st>>>(
+        cv, sv, sp, xs, vs, counts, ids, cap, hit_slots);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_volume(const ClothView& cv, const SurfaceView& sv, const StepParams& sp,
+                               const float* xs, const float* vs, int hit_slots,
+                               uint32_t* cell_bits, uint32_t* tri_bits,
+                               unsigned long long* totals, hipStream_t st) {
+    if (cv.n <= 0) return hipSuccess;
+    if (hit_slots < 0 || hit_slots > kMaxHitSlots) return hipErrorInvalidValue;
+    k_debug_volume<<<blocks(cv.n, 64), 64, wave_query_lds(hit_slots), st>>>(
+        cv, sv, sp, xs, vs, hit_slots, cell_bits, tri_bits, totals);
     return hipGetLastError();
 }
 

@@ -123,19 +123,28 @@ __device__ __forceinline__ bool in_box(const float4& lo, const float4& hi, float
 }
 
 // Force on node i from one spring to neighbour j (Alg. 1 with i as indexA):
-//   d = x_j - x_i, l = |d|, f = (k (l - L0) + c (v_j - v_i).d / l) d / l.
-// 1/l comes from the hardware reciprocal square root (about 1 ulp).
-__device__ __forceinline__ void spring_force(float dx, float dy, float dz, float dvx, float dvy,
-                                             float dvz, float k, float c, float L0, float& fx,
-                                             float& fy, float& fz) {
+//   d = x_j - x_i, l = |d|, f = (k (l - L0) + c (v_j - v_i).d / l) d / l = s d.
+// 1/l comes from the hardware reciprocal square root (about 1 ulp).  spring_coeff gives s,
+// spring_accumulate adds s d to the node's sum; every force kernel sums its incidences with
+// these two, in incidence order, so all of them produce the same bits.
+__device__ __forceinline__ float spring_coeff(float dx, float dy, float dz, float dvx, float dvy,
+                                              float dvz, float k, float c, float L0) {
     float l2 = dx * dx + dy * dy + dz * dz;
     float il = __builtin_amdgcn_rsqf(l2);
     float l = l2 * il;
     float phi = k * (l - L0) + c * (dvx * dx + dvy * dy + dvz * dz) * il;
-    float s = phi * il;
+    return phi * il;
+}
+__device__ __forceinline__ void spring_accumulate(float s, float dx, float dy, float dz, float& fx,
+                                                  float& fy, float& fz) {
     fx += s * dx;
     fy += s * dy;
     fz += s * dz;
+}
+__device__ __forceinline__ void spring_force(float dx, float dy, float dz, float dvx, float dvy,
+                                             float dvz, float k, float c, float L0, float& fx,
+                                             float& fy, float& fz) {
+    spring_accumulate(spring_coeff(dx, dy, dz, dvx, dvy, dvz, k, c, L0), dx, dy, dz, fx, fy, fz);
 }
 
 // a1 gather of one node over a sliced-CSR incidence list in global memory, up to twelve
@@ -311,39 +320,54 @@ __device__ __forceinline__ int narrow_mask(const SurfaceView& sv, unsigned long 
     return cnt;
 }
 
-// a3 + a4 contact search for a node at predicted position p: candidates are the triangles
-// listed in p's cell whose inflated box holds p (ascending id); a candidate is a contact iff
-// the point-triangle distance is < thickness, and visit(n, s, t) is then called with the
-// triangle's unit normal n, the signed plane distance s = (p - A).n and the triangle id t.
-// Reference boxes are loaded sixteen at a time (the arrays carry sixteen entries of padding,
-// so the loads need no bounds test).  Returns the contact count.
-template <class Visit>
-__device__ __forceinline__ int contacts_visit(const SurfaceView& sv, float px, float py, float pz,
-                                              Visit&& visit) {
-    const int cell = cell_of(sv, px, py, pz);
-    if (cell < 0) return 0;
-    const gptr<uint32_t> cs = gmem(sv.cell_start);
-    const uint32_t b = cs[cell], e = cs[cell + 1];
+// a3 + a4 contact search over the references [b, e) of the grid cell of a node at predicted
+// position p: candidates are the listed triangles whose inflated box holds p (ascending
+// id); a candidate is a contact iff the point-triangle distance is < thickness, and
+// visit(n, s, t) is then called with the triangle's unit normal n, the signed plane distance
+// s = (p - A).n and the triangle id t.  Reference boxes are loaded RR (<= 16) at a time
+// (the arrays carry sixteen entries of padding, so the loads need no bounds test).  Returns
+// the contact count.  NARROW = false stops after the broad phase: every candidate is visited (n
+// and s are zero) and counted.
+template <bool NARROW = true, int RR = kRefRound, class Visit>
+__device__ __forceinline__ int visit_range(const SurfaceView& sv, uint32_t b, uint32_t e,
+                                           float px, float py, float pz, Visit&& visit) {
     int cnt = 0;
-    for (uint32_t r = b; r < e; r += kRefRound) {
-        float4 lo[kRefRound], hi[kRefRound];
+    for (uint32_t r = b; r < e; r += RR) {
+        float4 lo[RR], hi[RR];
 #pragma unroll
-        for (int q = 0; q < kRefRound; ++q) {
+        for (int q = 0; q < RR; ++q) {
             lo[q] = ldg4(sv.ref_lo, r + q);
             hi[q] = ldg4(sv.ref_hi, r + q);
         }
         unsigned long long mask = 0;
 #pragma unroll
-        for (int q = 0; q < kRefRound; ++q)
+        for (int q = 0; q < RR; ++q)
             if (r + q < e && in_box(lo[q], hi[q], px, py, pz)) mask |= 1ULL << q;
         // a hit's triangle id is re-read from the box just loaded (a cache hit): selecting it
         // from the registers above would make the compiler spill them to scratch
         auto id = [&](int k) {
             return (uint32_t)gmem(reinterpret_cast<const int*>(sv.ref_lo))[4 * (size_t)(r + k) + 3];
         };
-        cnt += narrow_mask(sv, mask, id, px, py, pz, visit);
+        if constexpr (NARROW) {
+            cnt += narrow_mask(sv, mask, id, px, py, pz, visit);
+        } else {
+            while (mask) {
+                visit(make_float4(0.0f, 0.0f, 0.0f, 0.0f), 0.0f, id(pop_low(mask)));
+                ++cnt;
+            }
+        }
     }
     return cnt;
+}
+
+// visit_range over the whole cell of p (no candidates outside the grid).
+template <bool NARROW = true, class Visit>
+__device__ __forceinline__ int contacts_visit(const SurfaceView& sv, float px, float py, float pz,
+                                              Visit&& visit) {
+    const int cell = cell_of(sv, px, py, pz);
+    if (cell < 0) return 0;
+    const gptr<uint32_t> cs = gmem(sv.cell_start);
+    return visit_range<NARROW>(sv, cs[cell], cs[cell + 1], px, py, pz, visit);
 }
 
 // Response of Alg. 2 with the averaged direction: with at least one contact, p moves by the
@@ -376,16 +400,109 @@ __device__ __forceinline__ int collide(const SurfaceView& sv, float restitution,
     return cnt;
 }
 
-// a3 + a4 contact search with the box hits of the whole cell collected first: the cell's
-// coded reference records are tested kRefRound per round of loads, the triangle ids of hits
+// a3 + a4 contact search with the box hits of the references [b, e) of p's cell collected
+// first (cx, cy, cz: p's point codes in that cell, see point_code): the coded reference
+// records are tested RR (<= 16) per round of loads, the triangle ids of hits
 // go to this lane's list in LDS (list[k * 64], k < slots, plus a scratch entry k = slots:
 // every reference is written at the next free entry, or at the scratch entry once the list
 // is full, and only a hit advances the count), and the hits' geometry is then
-// loaded kHitRound hits per round, so a node with many box hits waits for few round trips.
-// Contacts are visited in ascending triangle id, exactly as contacts_visit visits them
-// (same contacts, same order); a lane with more hits than slots runs contacts_visit
-// instead.  Returns the contact count.
-template <class Visit>
+// loaded HR hits per round, so a node with many box hits waits for few round trips.
+// Contacts are visited in ascending triangle id, exactly as visit_range visits them (same
+// contacts, same order); a lane with more hits than slots runs visit_range instead.  Returns the contact count.  NARROW = false stops after the broad phase: every box
+// hit (undecided ones settled with the exact box) is visited, with n and s zero, and counted;
+// this is the query the step kernels run, up to the narrow test.
+template <bool NARROW = true, int RR = kRefRound, int HR = kHitRound, class Visit>
+__device__ __forceinline__ int listed_range(const SurfaceView& sv, uint32_t* list, int slots,
+                                            uint32_t cx, uint32_t cy, uint32_t cz, uint32_t b,
+                                            uint32_t e, float px, float py, float pz,
+                                            Visit&& visit) {
+    // box hits go to the list as triangle ids; a hit whose coded test was undecided
+    // carries bit 31 and is decided with the exact box before its narrow test
+    int nh = 0;
+    // a round's entries load from one address at fixed offsets
+    auto load = [&](uint4 (&w)[RR], uint32_t r) {
+        const uint4* rq = sv.ref_q + r;
+#pragma unroll
+        for (int q = 0; q < RR; ++q) w[q] = ldgu4(rq, q);
+    };
+    auto test = [&](const uint4 (&w)[RR], uint32_t r) {
+#pragma unroll
+        for (int q = 0; q < RR; ++q) {
+            const uint32_t m = box_code(w[q], cx, cy, cz);
+            list[min(nh, slots) * 64] = w[q].w | (m << 31);
+            nh += (r + q < e && m <= 1u) ? 1 : 0;
+        }
+    };
+    // Two rounds in flight: the next round's loads are issued before this round is tested.
+    // The loop body has no branch, so the loads stay ahead of the tests and the compiler
+    // counts them exactly: every load is unconditional (a lane without a further round
+    // reloads its current one, which is cached; an empty cell loads at b <= the reference
+    // count, which the arrays' padding covers), and a round past the cell's end is tested
+    // without effect (its entries fail r + q < e).
+    uint4 wa[RR], wb[RR];
+    load(wa, b);
+    for (uint32_t r = b; r < e; r += 2 * RR) {
+        const uint32_t r1 = r + RR, r2 = r1 + RR;
+        load(wb, r1 < e ? r1 : r);
+        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the tests
+        test(wa, r);
+        load(wa, r2 < e ? r2 : r);
+        __builtin_amdgcn_sched_barrier(0);
+        test(wb, r1);
+    }
+    if (nh > slots) return visit_range<NARROW, RR>(sv, b, e, px, py, pz, visit);
+    int contacts = 0;
+    if constexpr (!NARROW) {
+        for (int k = 0; k < nh; ++k) {
+            const uint32_t t = list[k * 64];
+            const uint32_t id = t & 0x7fffffffu;
+            if ((t >> 31) && !in_box(ldg4(sv.box_lo, id), ldg4(sv.box_hi, id), px, py, pz))
+                continue;
+            visit(make_float4(0.0f, 0.0f, 0.0f, 0.0f), 0.0f, id);
+            ++contacts;
+        }
+    } else {
+        for (int h0 = 0; h0 < nh; h0 += HR) {
+            const int n = min(nh - h0, HR);
+            uint32_t t[HR];
+            float4 g[HR][3];
+#pragma unroll
+            for (int q = 0; q < HR; ++q) t[q] = list[min(h0 + q, nh - 1) * 64];
+#pragma unroll
+            for (int q = 0; q < HR; ++q) {
+                const size_t id = t[q] & 0x7fffffffu;
+                g[q][0] = ldg4(sv.geo, 3 * id);
+                g[q][1] = ldg4(sv.geo, 3 * id + 1);
+                g[q][2] = ldg4(sv.geo, 3 * id + 2);
+            }
+            // live entries of the round as bits; undecided ones are settled with the exact
+            // box in one branch, which the wavefront skips when none of its lanes has one
+            uint32_t live = (1u << n) - 1u, und = 0;
+#pragma unroll
+            for (int q = 0; q < HR; ++q) und |= (t[q] >> 31) << q;
+            und &= live;
+            if (und) {
+#pragma unroll
+                for (int q = 0; q < HR; ++q)
+                    if ((und >> q) & 1u) {
+                        const uint32_t id = t[q] & 0x7fffffffu;
+                        if (!in_box(ldg4(sv.box_lo, id), ldg4(sv.box_hi, id), px, py, pz))
+                            live &= ~(1u << q);
+                    }
+            }
+            // (a wavefront skips a slot none of its lanes holds, e.g. in its last round)
+#pragma unroll
+            for (int q = 0; q < HR; ++q)
+                if ((live >> q) & 1u)
+                    contacts += narrow_visit(sv, t[q] & 0x7fffffffu, g[q][0], g[q][1], g[q][2],
+                                             px, py, pz, visit);
+        }
+    }
+    return contacts;
+}
+
+// listed_range over the whole cell of p (no candidates outside the grid).
+template <bool NARROW = true, class Visit>
 __device__ __forceinline__ int contacts_listed(const SurfaceView& sv, uint32_t* list, int slots,
                                                float px, float py, float pz, Visit&& visit) {
     const float gx = cell_coord_raw(px, sv.org[0], sv.inv_cell);
@@ -399,81 +516,8 @@ __device__ __forceinline__ int contacts_listed(const SurfaceView& sv, uint32_t* 
     const int cell = ((int)fz * sv.dim[1] + (int)fy) * sv.dim[0] + (int)fx;
     const uint32_t cx = point_code(gx, fx), cy = point_code(gy, fy), cz = point_code(gz, fz);
     const gptr<uint32_t> cs = gmem(sv.cell_start);
-    const uint32_t b = cs[cell], e = cs[cell + 1];
-    // box hits go to the list as triangle ids; a hit whose coded test was undecided
-    // carries bit 31 and is decided with the exact box before its narrow test
-    int nh = 0;
-    // a round's entries load from one address at fixed offsets
-    auto load = [&](uint4 (&w)[kRefRound], uint32_t r) {
-        const uint4* rq = sv.ref_q + r;
-#pragma unroll
-        for (int q = 0; q < kRefRound; ++q) w[q] = ldgu4(rq, q);
-    };
-    auto test = [&](const uint4 (&w)[kRefRound], uint32_t r) {
-#pragma unroll
-        for (int q = 0; q < kRefRound; ++q) {
-            const uint32_t m = box_code(w[q], cx, cy, cz);
-            list[min(nh, slots) * 64] = w[q].w | (m << 31);
-            nh += (r + q < e && m <= 1u) ? 1 : 0;
-        }
-    };
-    // Two rounds in flight: the next round's loads are issued before this round is tested.
-    // The loop body has no branch, so the loads stay ahead of the tests and the compiler
-    // counts them exactly: every load is unconditional (a lane without a further round
-    // reloads its current one, which is cached; an empty cell loads at b <= the reference
-    // count, which the arrays' padding covers), and a round past the cell's end is tested
-    // without effect (its entries fail r + q < e).
-    uint4 wa[kRefRound], wb[kRefRound];
-    load(wa, b);
-    for (uint32_t r = b; r < e; r += 2 * kRefRound) {
-        const uint32_t r1 = r + kRefRound, r2 = r1 + kRefRound;
-        load(wb, r1 < e ? r1 : r);
-        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the tests
-        test(wa, r);
-        load(wa, r2 < e ? r2 : r);
-        __builtin_amdgcn_sched_barrier(0);
-        test(wb, r1);
-    }
-    if (nh > slots) return contacts_visit(sv, px, py, pz, visit);
-    int contacts = 0;
-    {
-        for (int h0 = 0; h0 < nh; h0 += kHitRound) {
-            const int n = min(nh - h0, kHitRound);
-            uint32_t t[kHitRound];
-            float4 g[kHitRound][3];
-#pragma unroll
-            for (int q = 0; q < kHitRound; ++q) t[q] = list[min(h0 + q, nh - 1) * 64];
-#pragma unroll
-            for (int q = 0; q < kHitRound; ++q) {
-                const size_t id = t[q] & 0x7fffffffu;
-                g[q][0] = ldg4(sv.geo, 3 * id);
-                g[q][1] = ldg4(sv.geo, 3 * id + 1);
-                g[q][2] = ldg4(sv.geo, 3 * id + 2);
-            }
-            // live entries of the round as bits; undecided ones are settled with the exact
-            // box in one branch, which the wavefront skips when none of its lanes has one
-            uint32_t live = (1u << n) - 1u, und = 0;
-#pragma unroll
-            for (int q = 0; q < kHitRound; ++q) und |= (t[q] >> 31) << q;
-            und &= live;
-            if (und) {
-#pragma unroll
-                for (int q = 0; q < kHitRound; ++q)
-                    if ((und >> q) & 1u) {
-                        const uint32_t id = t[q] & 0x7fffffffu;
-                        if (!in_box(ldg4(sv.box_lo, id), ldg4(sv.box_hi, id), px, py, pz))
-                            live &= ~(1u << q);
-                    }
-            }
-            // (a wavefront skips a slot none of its lanes holds, e.g. in its last round)
-#pragma unroll
-            for (int q = 0; q < kHitRound; ++q)
-                if ((live >> q) & 1u)
-                    contacts += narrow_visit(sv, t[q] & 0x7fffffffu, g[q][0], g[q][1], g[q][2],
-                                             px, py, pz, visit);
-        }
-    }
-    return contacts;
+    return listed_range<NARROW>(sv, list, slots, cx, cy, cz, cs[cell], cs[cell + 1], px, py, pz,
+                                visit);
 }
 
 // collide_listed: contacts_listed with the averaged response.

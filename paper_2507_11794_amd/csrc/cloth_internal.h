@@ -158,6 +158,15 @@ hipError_t launch_substep(const ClothView& cv, int collide, const StepParams& sp
                           const SurfaceView* svs, const int* node_group = nullptr,
                           int hit_slots = 0, int xcd_runs = 0, int split_refs = 0,
                           int* heavy = nullptr, int parity = 0, float* pred = nullptr);
+// launch_substep with `lanes` (2 or 4) lanes per node (lanes_step.hip): the same results,
+// bit for bit; no second pass.
+hipError_t launch_substep_lanes(int lanes, const ClothView& cv, int collide, const StepParams& sp,
+                                const float* xs, const float* vs, float* xd, float* vd, int block,
+                                hipStream_t stream, const SurfaceView* svs, const int* node_group,
+                                int hit_slots, int xcd_runs, float* pred = nullptr);
+hipError_t prepare_lanes_kernels(size_t lds_bytes);
+// Dynamic LDS of a lanes launch: hit lists and contact records of its wavefronts.
+size_t lanes_lds_bytes(int block, int hit_slots);
 // The second pass over list `parity` of heavy (see launch_substep): each listed node's
 // prediction is in (xd, vd) and is replaced by the collision-resolved state.
 hipError_t launch_heavy(const ClothView& cv, const StepParams& sp, int* heavy, int parity,
@@ -217,10 +226,18 @@ hipError_t launch_adj_fused(const ClothView& cv, const SurfaceView& sv, const St
 hipError_t launch_adj_springs(const ClothView& cv, const float* xs, const float* vs,
                               const float* fb, const float* xb_part, const float* vb_part,
                               float* xb_in, float* vb_in, double* kb, double* cb, hipStream_t st);
-// Contact sets of the next substep (internal slot order): counts[slot], ids[slot*cap ...].
+// Contact sets of the next substep (internal slot order): counts[slot], ids[slot*cap ...],
+// found with the step kernels' query (hit_slots as theirs).
 hipError_t launch_debug_contacts(const ClothView& cv, const SurfaceView& sv, const StepParams& sp,
                                 const float* xs, const float* vs, int* counts, int* ids, int cap,
-                                hipStream_t st);
+                                int hit_slots, hipStream_t st);
+// The surface data the next substep's collision query touches: bit c of cell_bits for every
+// non-empty cell some node queries, bit t of tri_bits for every box hit, and totals[0..2] +=
+// node queries of non-empty cells, references tested, box hits (zeroed by the caller).
+hipError_t launch_debug_volume(const ClothView& cv, const SurfaceView& sv, const StepParams& sp,
+                               const float* xs, const float* vs, int hit_slots,
+                               uint32_t* cell_bits, uint32_t* tri_bits,
+                               unsigned long long* totals, hipStream_t st);
 // Node-id AoS [n][3] <-> internal SoA [3][ld] through slot[id].
 hipError_t launch_import(int n, int ld, const int* slot, const float* aos, float* soa,
                          int accumulate, hipStream_t st);
@@ -272,11 +289,13 @@ size_t scan_tmp_words(size_t n);
 hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, size_t n, uint32_t* tmp,
                               hipStream_t stream);
 
-// Broad-phase query for arbitrary points (SoA [3][ld]): per-point candidate counts, then
-// the (point, triangle) pairs at the given offsets.
+// Broad-phase query for arbitrary points (SoA [3][ld]) through the step kernels' own query
+// with hit_slots list entries per lane (0 = unlisted): per-point candidate counts, then the
+// (point, triangle) pairs at the given offsets.
 hipError_t launch_candidates_count(int n, int ld, const float* p, const SurfaceView& sv,
-                                   uint32_t* counts, hipStream_t stream);
+                                   int hit_slots, uint32_t* counts, hipStream_t stream);
 hipError_t launch_candidates_write(int n, int ld, const float* p, const SurfaceView& sv,
-                                   const uint32_t* offsets, int* pairs, hipStream_t stream);
+                                   int hit_slots, const uint32_t* offsets, int* pairs,
+                                   hipStream_t stream);
 
 }  // namespace cloth

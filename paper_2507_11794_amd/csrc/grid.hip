@@ -341,40 +341,32 @@ __global__ void __launch_bounds__(kScanThreads)
 }
 
 // ------------------------------------------------------------------ point queries
-__global__ void k_cand_count(int n, int ld, const float* __restrict__ p, SurfaceView sv,
-                             uint32_t* counts) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Broad-phase candidates of arbitrary points through the step kernels' own query
+// (contacts_listed, or contacts_visit with hit_slots = 0, stopped before the narrow test):
+// the coded box test of each reference of the point's cell, undecided boxes settled with the
+// exact box.  One wavefront per workgroup, each lane's hit list in LDS.  WRITE = false
+// stores each point's count, WRITE = true its (point, triangle) pairs at its offset.
+template <bool WRITE>
+__global__ void __launch_bounds__(64)
+    k_candidates(int n, int ld, const float* __restrict__ p, SurfaceView sv, int hit_slots,
+                 uint32_t* __restrict__ counts, const uint32_t* __restrict__ offsets,
+                 int* __restrict__ pairs) {
+    extern __shared__ uint32_t hit_lds[];  // wave_query_lds(hit_slots) bytes
+    const int i = blockIdx.x * 64 + threadIdx.x;
     if (i >= n) return;
     const float px = p[i], py = p[ld + i], pz = p[2 * ld + i];
-    const int c = cell_of(sv, px, py, pz);
-    uint32_t cnt = 0;
-    if (c < 0) {  // outside the grid: no inflated box holds the point
-        counts[i] = 0;
-        return;
-    }
-    for (uint32_t r = sv.cell_start[c]; r < sv.cell_start[c + 1]; ++r) {
-        const uint32_t t = sv.refs[r];
-        if (in_box(sv.box_lo[t], sv.box_hi[t], px, py, pz)) ++cnt;
-    }
-    counts[i] = cnt;
-}
-
-__global__ void k_cand_write(int n, int ld, const float* __restrict__ p, SurfaceView sv,
-                             const uint32_t* __restrict__ offsets, int* pairs) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float px = p[i], py = p[ld + i], pz = p[2 * ld + i];
-    const int c = cell_of(sv, px, py, pz);
-    if (c < 0) return;
-    uint32_t o = offsets[i];
-    for (uint32_t r = sv.cell_start[c]; r < sv.cell_start[c + 1]; ++r) {
-        const uint32_t t = sv.refs[r];
-        if (in_box(sv.box_lo[t], sv.box_hi[t], px, py, pz)) {
+    uint32_t o = WRITE ? offsets[i] : 0u;
+    auto visit = [&](const float4&, float, uint32_t t) {
+        if constexpr (WRITE) {
             pairs[2 * (size_t)o] = i;
             pairs[2 * (size_t)o + 1] = (int)t;
             ++o;
         }
-    }
+    };
+    const int cnt = hit_slots > 0
+                        ? contacts_listed<false>(sv, hit_lds + threadIdx.x, hit_slots, px, py, pz, visit)
+                        : contacts_visit<false>(sv, px, py, pz, visit);
+    if constexpr (!WRITE) counts[i] = (uint32_t)cnt;
 }
 
 inline int blocks_for(long long n, int b) { return (int)((n + b - 1) / b); }
@@ -438,16 +430,21 @@ hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, size_t n, uint3
 }
 
 hipError_t launch_candidates_count(int n, int ld, const float* p, const SurfaceView& sv,
-                                   uint32_t* counts, hipStream_t stream) {
+                                   int hit_slots, uint32_t* counts, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
-    k_cand_count<<<blocks_for(n, 256), 256, 0, stream>>>(n, ld, p, sv, counts);
+    if (hit_slots < 0 || hit_slots > kMaxHitSlots) return hipErrorInvalidValue;
+    k_candidates<false><<<blocks_for(n, 64), 64, wave_query_lds(hit_slots), stream>>>(
+        n, ld, p, sv, hit_slots, counts, nullptr, nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_candidates_write(int n, int ld, const float* p, const SurfaceView& sv,
-                                   const uint32_t* offsets, int* pairs, hipStream_t stream) {
+                                   int hit_slots, const uint32_t* offsets, int* pairs,
+                                   hipStream_t stream) {
     if (n <= 0) return hipSuccess;
-    k_cand_write<<<blocks_for(n, 256), 256, 0, stream>>>(n, ld, p, sv, offsets, pairs);
+    if (hit_slots < 0 || hit_slots > kMaxHitSlots) return hipErrorInvalidValue;
+    k_candidates<true><<<blocks_for(n, 64), 64, wave_query_lds(hit_slots), stream>>>(
+        n, ld, p, sv, hit_slots, nullptr, offsets, pairs);
     return hipGetLastError();
 }
 

@@ -72,9 +72,9 @@ int cloth_rollout_forward(cloth_sim* s, const float* k_dev, const float* c_dev,
     if (s->groups.size() != 1) return fail(CLOTH_EINVAL, "rollouts take a single-cloth handle");
     if (s->surface_broken) return fail(CLOTH_ESTATE, "a surface update failed; update it again first");
     if (s->mt) return fail(CLOTH_EINVAL, "rollouts use the point-triangle narrow phase");
-    if (s->launch.kernel != CLOTH_KERNEL_TILE && s->launch.kernel != CLOTH_KERNEL_DIRECT)
-        return fail(CLOTH_EINVAL, "rollouts recompute with the gather kernels: select the tile "
-                                  "or direct kernel");
+    if (s->launch.kernel == CLOTH_KERNEL_SCATTER_F32 || s->launch.kernel == CLOTH_KERNEL_SCATTER_FIX)
+        return fail(CLOTH_EINVAL, "rollouts recompute with the gather kernels: select the tile, "
+                                  "direct or lanes kernel");
     if (s->n_springs > 0 && (!k_dev || !c_dev)) return fail(CLOTH_EINVAL, "k and c are required");
     if (!(dt > 0.0f) || !std::isfinite(dt) || n_substeps < 1 || n_steps < 0 || ckpt_every < 1)
         return fail(CLOTH_EINVAL, "need dt > 0, n_substeps >= 1, n_steps >= 0, ckpt_every >= 1");
@@ -265,7 +265,7 @@ int cloth_debug_contacts(cloth_sim* s, float h, int* counts, int* ids, int cap) 
                                          s->mt_pred, d_cnt, d_ids, cap, s->stream)
               : launch_debug_contacts(s->dev.view(), s->surfs[0].view, step_params(s, h),
                                       s->dev.x[s->dev.cur], s->dev.v[s->dev.cur], d_cnt, d_ids,
-                                      cap, s->stream);
+                                      cap, s->launch.hit_slots, s->stream);
     if ((e = le) ||
         (e = hipMemcpyAsync(cnt.data(), d_cnt, 4 * (size_t)N, hipMemcpyDeviceToHost, s->stream)) ||
         (cap > 0 && (e = hipMemcpyAsync(id.data(), d_ids, 4 * (size_t)N * cap,
@@ -279,6 +279,56 @@ int cloth_debug_contacts(cloth_sim* s, float h, int* counts, int* ids, int cap) 
         if (s->mt) std::sort(id.begin() + (size_t)p * cap, id.begin() + (size_t)p * cap + std::min(cnt[p], cap));
         for (int r = 0; r < cap; ++r) ids[(size_t)node * cap + r] = id[(size_t)p * cap + r];
     }
+    return CLOTH_OK;
+}
+
+int cloth_debug_query_volume(cloth_sim* s, float h, long long* out) {
+    if (!s || !out) return fail(CLOTH_EINVAL, "NULL argument");
+    if (s->groups.size() != 1) return fail(CLOTH_EINVAL, "single-cloth handles only");
+    if (s->mt) return fail(CLOTH_EINVAL, "the proximity query only (not CLOTH_F_NARROW_MT)");
+    if (s->surface_broken) return fail(CLOTH_ESTATE, "a surface update failed; update it again first");
+    if (!(h > 0.0f) || !std::isfinite(h)) return fail(CLOTH_EINVAL, "need h > 0");
+    for (int q = 0; q < 6; ++q) out[q] = 0;
+    const SurfaceView& sv = s->surfs[0].view;
+    if (sv.n_tris == 0) return CLOTH_OK;
+    const size_t C = (size_t)sv.dim[0] * sv.dim[1] * sv.dim[2];
+    const size_t cw = (C + 31) / 32, tw = ((size_t)sv.n_tris + 31) / 32;
+    DeviceArena tmp;
+    uint32_t *d_cb, *d_tb;
+    unsigned long long* d_tot;
+    hipError_t e;
+    if ((e = tmp.alloc(&d_cb, cw)) || (e = tmp.alloc(&d_tb, tw)) || (e = tmp.alloc(&d_tot, 3)))
+        return hip_fail(e, "hipMalloc query volume");
+    std::vector<uint32_t> cb(cw), tb(tw), start(C + 1);
+    unsigned long long tot[3] = {0, 0, 0};
+    StreamFence fence{s->stream};
+    if ((e = hipMemsetAsync(d_cb, 0, 4 * cw, s->stream)) ||
+        (e = hipMemsetAsync(d_tb, 0, 4 * tw, s->stream)) ||
+        (e = hipMemsetAsync(d_tot, 0, 24, s->stream)) ||
+        (e = launch_debug_volume(s->dev.view(), sv, step_params(s, h), s->dev.x[s->dev.cur],
+                                 s->dev.v[s->dev.cur], s->launch.hit_slots, d_cb, d_tb, d_tot,
+                                 s->stream)) ||
+        (e = hipMemcpyAsync(cb.data(), d_cb, 4 * cw, hipMemcpyDeviceToHost, s->stream)) ||
+        (e = hipMemcpyAsync(tb.data(), d_tb, 4 * tw, hipMemcpyDeviceToHost, s->stream)) ||
+        (e = hipMemcpyAsync(start.data(), sv.cell_start, 4 * (C + 1), hipMemcpyDeviceToHost,
+                            s->stream)) ||
+        (e = hipMemcpyAsync(tot, d_tot, 24, hipMemcpyDeviceToHost, s->stream)) ||
+        (e = hipStreamSynchronize(s->stream)))
+        return hip_fail(e, "query volume");
+    long long cells = 0, refs = 0, tris = 0;
+    for (size_t w = 0; w < cw; ++w)
+        for (uint32_t m = cb[w]; m; m &= m - 1) {
+            const size_t c = 32 * w + (size_t)__builtin_ctz(m);
+            ++cells;
+            refs += (long long)(start[c + 1] - start[c]);
+        }
+    for (size_t w = 0; w < tw; ++w) tris += __builtin_popcount(tb[w]);
+    out[0] = cells;
+    out[1] = refs;
+    out[2] = tris;
+    out[3] = (long long)tot[0];
+    out[4] = (long long)tot[1];
+    out[5] = (long long)tot[2];
     return CLOTH_OK;
 }
 

@@ -14,7 +14,7 @@
 namespace cloth {
 
 int check_launch(const cloth_launch& c) {
-    if (c.kernel < CLOTH_KERNEL_TILE || c.kernel > CLOTH_KERNEL_SCATTER_FIX)
+    if (c.kernel < CLOTH_KERNEL_TILE || c.kernel > CLOTH_KERNEL_LANES4)
         return fail(CLOTH_EINVAL, "unknown kernel");
     if (c.block_threads < 64 || c.block_threads > 256 || (c.block_threads & 63))
         return fail(CLOTH_EINVAL, "block_threads must be 64, 128, 192 or 256");
@@ -131,9 +131,11 @@ int set_launch(cloth_sim* s, const cloth_launch& cfg) {
     if ((st = ensure_plan(s, cfg)) != CLOTH_OK) return st;
     // dynamic LDS of the chosen kernel: check it fits and raise the kernels' limit
     const int slots = s->any_collision ? cfg.hit_slots : 0;
+    const bool lanes_kernel = cfg.kernel == CLOTH_KERNEL_LANES2 || cfg.kernel == CLOTH_KERNEL_LANES4;
     const size_t lds = cfg.kernel == CLOTH_KERNEL_TILE
                            ? tile_lds_bytes(s->plan.view.rmax, cfg.block_threads, slots)
-                           : (size_t)(cfg.block_threads / 64) * wave_query_lds(slots);
+                       : lanes_kernel ? (s->any_collision ? lanes_lds_bytes(cfg.block_threads, slots) : 0)
+                                      : (size_t)(cfg.block_threads / 64) * wave_query_lds(slots);
     if (lds > 160 * 1024)
         return fail(CLOTH_EINVAL, "tile region plus hit lists exceed 160 KiB of LDS");
     const bool scatter = cfg.kernel == CLOTH_KERNEL_SCATTER_F32 || cfg.kernel == CLOTH_KERNEL_SCATTER_FIX;
@@ -149,6 +151,7 @@ int set_launch(cloth_sim* s, const cloth_launch& cfg) {
     }
     hipError_t pe = cfg.kernel == CLOTH_KERNEL_TILE ? prepare_tile_kernels(lds)
                     : scatter                       ? prepare_scatter_kernels(lds)
+                    : lanes_kernel                  ? prepare_lanes_kernels(lds)
                                                     : prepare_substep_kernels(lds);
     if (pe != hipSuccess) return hip_fail(pe, "kernel LDS attribute");
     cloth_launch norm = cfg;
@@ -194,6 +197,13 @@ hipError_t launch_once(cloth_sim* s, const StepParams& sp, int K, int src, hipSt
                                       s->launch.block_threads, st, s->svs_dev,
                                       s->groups.size() > 1 ? s->node_group_dev : nullptr,
                                       s->launch.hit_slots, s->launch.xcd_runs);
+    if (s->launch.kernel == CLOTH_KERNEL_LANES2 || s->launch.kernel == CLOTH_KERNEL_LANES4)
+        return launch_substep_lanes(
+            s->launch.kernel == CLOTH_KERNEL_LANES2 ? 2 : 4, s->dev.view(),
+            s->groups.size() == 1 ? s->surfs[0].view.n_tris > 0 : s->any_collision, sp,
+            s->dev.x[src], s->dev.v[src], s->dev.x[dst], s->dev.v[dst], s->launch.block_threads,
+            st, s->svs_dev, s->groups.size() > 1 ? s->node_group_dev : nullptr,
+            s->launch.hit_slots, s->launch.xcd_runs);
     if (s->groups.size() == 1)
         return launch_substep(s->dev.view(), s->surfs[0].view.n_tris > 0, sp, s->dev.x[src],
                               s->dev.v[src], s->dev.x[dst], s->dev.v[dst], s->launch.block_threads,
@@ -205,7 +215,8 @@ hipError_t launch_once(cloth_sim* s, const StepParams& sp, int K, int src, hipSt
                           s->launch.split_refs, s->heavy_dev, src);
 }
 
-// A captured graph of `chunk` (even) launches of K substeps starting from buffer `parity`.
+// A captured graph of `chunk` launches of K substeps starting from buffer `parity` (an odd
+// chunk ends on the other buffer).
 hipGraphExec_t get_graph(cloth_sim* s, const StepParams& sp, int K, int chunk, int parity) {
     unsigned hb;
     std::memcpy(&hb, &sp.h, 4);
@@ -239,6 +250,8 @@ hipGraphExec_t get_graph(cloth_sim* s, const StepParams& sp, int K, int chunk, i
         return nullptr;
     }
     if (s->graphs.size() >= 8) {
+        // the oldest graph may still run on the stream: let it finish first
+        (void)hipStreamSynchronize(s->stream);
         (void)hipGraphExecDestroy(s->graphs.front().exec);
         s->graphs.erase(s->graphs.begin());
     }
@@ -281,6 +294,17 @@ int run_substeps(cloth_sim* s, float h, long long total) {
                     if (e != hipSuccess) return hip_fail(e, "graph launch");
                 }
                 launches %= chunk;
+            }
+        }
+        // the remainder (two or more launches) as one graph of its own length, so a call of
+        // any length replays graphs only once its graphs exist
+        if (launches >= 2) {
+            hipGraphExec_t exec = get_graph(s, sp, K, (int)launches, s->dev.cur);
+            if (exec) {
+                hipError_t e = hipGraphLaunch(exec, s->stream);
+                if (e != hipSuccess) return hip_fail(e, "graph launch");
+                s->dev.cur ^= (int)(launches & 1);
+                launches = 0;
             }
         }
     }
@@ -727,7 +751,8 @@ int cloth_debug_candidates(cloth_sim* s, int n_points, const float* points, int*
     uint32_t total = 0;
     StreamFence fence{s->stream};
     if ((e = hipMemcpyAsync(d_p, soa.data(), 12 * n, hipMemcpyHostToDevice, s->stream)) ||
-        (e = launch_candidates_count(n_points, n_points, d_p, sv, d_cnt, s->stream)) ||
+        (e = launch_candidates_count(n_points, n_points, d_p, sv, s->launch.hit_slots, d_cnt,
+                                     s->stream)) ||
         (e = scan_exclusive_u32(d_cnt, d_off, n, d_scan, s->stream)) ||
         (e = hipMemcpyAsync(&total, d_off + n, 4, hipMemcpyDeviceToHost, s->stream)) ||
         (e = hipStreamSynchronize(s->stream)))
@@ -737,7 +762,8 @@ int cloth_debug_candidates(cloth_sim* s, int n_points, const float* points, int*
     int* d_pairs;
     if ((e = tmp.alloc(&d_pairs, 2 * (size_t)total))) return hip_fail(e, "hipMalloc pairs");
     const size_t ncopy = (size_t)std::min<long long>(cap, total);
-    if ((e = launch_candidates_write(n_points, n_points, d_p, sv, d_off, d_pairs, s->stream)) ||
+    if ((e = launch_candidates_write(n_points, n_points, d_p, sv, s->launch.hit_slots, d_off,
+                                     d_pairs, s->stream)) ||
         (e = hipMemcpyAsync(pairs_out, d_pairs, 8 * ncopy, hipMemcpyDeviceToHost, s->stream)) ||
         (e = hipStreamSynchronize(s->stream)))
         return hip_fail(e, "candidate write");

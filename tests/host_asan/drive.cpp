@@ -106,7 +106,9 @@ void plain_paths() {
         tile_launch(64, 1, CLOTH_SCHED_GRID, 0), tile_launch(256, 2, CLOTH_SCHED_LPT, 7),
         tile_launch(128, 4, CLOTH_SCHED_RR, 5), {CLOTH_KERNEL_DIRECT, 256, 1, 128, 1, 0, 0, 16, 2, 48},
         {CLOTH_KERNEL_SCATTER_FIX, 256, 1, 256, 0, 0, 0, 0, 0, 0},
-        {CLOTH_KERNEL_SCATTER_F32, 256, 1, 64, 1, 0, 0, 8, 1, 0}};
+        {CLOTH_KERNEL_SCATTER_F32, 256, 1, 64, 1, 0, 0, 8, 1, 0},
+        {CLOTH_KERNEL_LANES4, 256, 1, 64, 1, 0, 0, 8, 0, 0},
+        {CLOTH_KERNEL_LANES2, 256, 1, 256, 0, 0, 0, 0, 3, 0}};
     for (const cloth_launch& c : cfgs) {
         expect(cloth_set_launch(s, &c), CLOTH_OK, "set launch");
         expect(cloth_step(s, dt, 4, 9), CLOTH_OK, "step");
@@ -122,6 +124,9 @@ void plain_paths() {
     std::vector<int> counts(N), ids(4 * N);
     expect(cloth_debug_contacts(s, dt / 4, counts.data(), ids.data(), 4), CLOTH_OK,
            "debug contacts");
+    long long volume[6];
+    expect(cloth_debug_query_volume(s, dt / 4, volume), CLOTH_OK, "query volume");
+    expect(cloth_debug_query_volume(s, dt / 4, nullptr), CLOTH_EINVAL, "query volume (NULL)");
     std::vector<float> f(3 * N, 0.001f);
     expect(cloth_set_external_force(s, f.data()), CLOTH_OK, "external force");
     expect(cloth_step(s, dt, 4, 9), CLOTH_OK, "step (forced)");

@@ -179,9 +179,23 @@ hipError_t launch_adj_springs(const ClothView&, const float*, const float*, cons
     return hipSuccess;
 }
 hipError_t launch_debug_contacts(const ClothView&, const SurfaceView&, const StepParams&,
-                                 const float*, const float*, int*, int*, int, hipStream_t) {
+                                 const float*, const float*, int*, int*, int, int, hipStream_t) {
     return hipSuccess;
 }
+hipError_t launch_debug_volume(const ClothView&, const SurfaceView&, const StepParams&,
+                               const float*, const float*, int, uint32_t*, uint32_t*,
+                               unsigned long long*, hipStream_t) {
+    return hipSuccess;
+}
+hipError_t launch_substep_lanes(int, const ClothView&, int, const StepParams&, const float*,
+                                const float*, float*, float*, int, hipStream_t,
+                                const SurfaceView*, const int*, int, int, float*) {
+    return hipSuccess;
+}
+size_t lanes_lds_bytes(int block, int hit_slots) {
+    return (size_t)(block / 64) * ((size_t)(hit_slots + 1) * 256 + 5 * 1024);
+}
+hipError_t prepare_lanes_kernels(size_t) { return hipSuccess; }
 hipError_t launch_import(int, int, const int*, const float*, float*, int, hipStream_t) {
     return hipSuccess;
 }
@@ -222,12 +236,12 @@ hipError_t scan_exclusive_u32(const uint32_t*, uint32_t* out, size_t n, uint32_t
                               hipStream_t stream) {
     return hipMemsetAsync(out, 0, 4 * (n + 1), stream);  // all cells empty
 }
-hipError_t launch_candidates_count(int, int, const float*, const SurfaceView&, uint32_t*,
+hipError_t launch_candidates_count(int, int, const float*, const SurfaceView&, int, uint32_t*,
                                    hipStream_t) {
     return hipSuccess;
 }
-hipError_t launch_candidates_write(int, int, const float*, const SurfaceView&, const uint32_t*,
-                                   int*, hipStream_t) {
+hipError_t launch_candidates_write(int, int, const float*, const SurfaceView&, int,
+                                   const uint32_t*, int*, hipStream_t) {
     return hipSuccess;
 }
 

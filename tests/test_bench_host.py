@@ -29,6 +29,28 @@ def test_algorithmic_bytes_of_the_316_workload():
     assert bench.algorithmic_bytes_per_substep(n * n, springs) == 52 * 99856 + 20 * 595978
 
 
+def test_collision_bytes_count_each_touched_array_once():
+    # 36 B per distinct candidate triangle, 4 B per reference of a queried non-empty cell,
+    # 8 B per queried non-empty cell; node-level totals do not enter
+    vol = {"cells": 10, "cell_refs": 300, "candidate_tris": 40, "node_queries": 999,
+           "refs_tested": 12345, "box_hits": 777}
+    assert bench.collision_bytes(vol) == 36 * 40 + 4 * 300 + 8 * 10
+
+
+def test_median_window_and_roofline():
+    w = [(0.5, 1.0), (0.1, 2.0), (0.3, 3.0), (0.2, 4.0), (0.4, 5.0)]
+    assert bench.median_window(w) == (0.3, 3.0)
+    r = bench.roofline("k", 8e6, 1e-6)
+    assert r["achieved"] == pytest.approx(8000.0) and r["frac"] == pytest.approx(1.0)
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["traffic"] is None
+
+
+def test_adjoint_bytes_exceed_two_forward_passes():
+    n, s, coll = 4096, 23938, 1e5
+    fwd = bench.algorithmic_bytes_per_substep(n, s) + coll
+    assert bench.adjoint_bytes_per_substep(n, s, coll) > 2 * fwd
+
+
 def test_parse_launch():
     from paper_2507_11794_amd import cloth
     cfg = bench.parse_launch("kernel=tile,tile=128,K=2,block=256,graph=0,hits=16,xcd=4")

@@ -1,14 +1,21 @@
 """GPU adjoint (HIP rollout forward + hand-written backward, through ClothRollout) against
 the FP64 oracle.
 
-With collision, a resting node sits exactly at the thickness after every push, so FP32 and
-FP64 runs take different contact decisions at many nodes and their rollouts lie on different
-smooth pieces.  The reference adjoint is therefore the oracle's adjoint evaluated on the
-GPU's own trajectory with the GPU's own contact sets (cloth_debug_contacts), which isolates
-the adjoint arithmetic.  Without collision the trajectories agree and the GPU gradient is
-also checked against central differences of the FP64 oracle forward (h = 1e-3 relative).
-Bar: 1e-3 relative (normwise for whole gradients; per entry, with a floor of 1e-3 of the
-largest entry, for differences)."""
+The gradient is that of the current smooth piece of the rollout: every substep's contact
+sets held fixed.  With collision, a resting node sits exactly at the thickness after every
+push, so FP32 and FP64 runs take different contact decisions at many nodes and their
+rollouts lie on different smooth pieces.  The references are therefore built on the GPU's
+own piece: its trajectory is recorded substep by substep with the contact sets its step
+uses (cloth_debug_contacts), every set is checked against the oracle's distances at the
+FP64 prediction from the GPU state (it must hold every triangle within th - 1e-6 m and only
+triangles within th + 1e-6 m), and then
+  - the oracle's substep adjoint with those sets is run backwards along the trajectory
+    (the FP64 reference adjoint), and
+  - central differences (h = 1e-3 relative) of the FP64 oracle rollout with those sets
+    held fixed give the derivative of the same piece directly.
+Without collision the trajectories agree and the GPU gradient is also checked against
+central differences of the plain FP64 oracle forward.  Bar: 1e-3 relative (normwise for
+whole gradients; per entry, with a floor of 1e-3 of the largest entry, for differences)."""
 import numpy as np
 import pytest
 
@@ -45,31 +52,51 @@ def _gpu_grads(inp, n_steps, target, ckpt=20, v0=None):
                 v.grad.cpu().numpy().astype(np.float64), x[0].detach().cpu().numpy())
 
 
-def _oracle_adjoint_on_gpu_trajectory(inp, n_steps, target):
-    """Step the GPU substep by substep, recording its states and contact sets, then run the
-    oracle's substep adjoint backwards along them."""
+def _record_gpu_trajectory(inp, n_steps, cap=16):
+    """Step the GPU substep by substep: the state before every substep, the contact sets
+    that substep uses (CSR, caller node order) and the final positions."""
     h = h32(inp)
-    n_sub = n_steps * inp.n_substeps
-    xs, vs, cs = [], [], []
+    xs, vs, sets = [], [], []
     with B.Cloth(inp) as sim:
-        for _ in range(n_sub):
+        for _ in range(n_steps * inp.n_substeps):
             x, v = sim.read_state()
             xs.append(x)
             vs.append(v)
-            cs.append(sim.debug_contacts(h) if inp.thickness > 0 else [[]] * inp.n_nodes)
+            sets.append(sim.debug_contacts(h, cap=cap, csr=True) if inp.thickness > 0 else
+                        (np.zeros(inp.n_nodes + 1, dtype=np.int32), np.zeros(0, np.int32)))
             sim.step(dt=h, n_substeps=1, n_steps=1)
         xT, _ = sim.read_state()
-    m = oracle.Model.from_inputs(inp)
+    return xs, vs, sets, xT
+
+
+def _check_contact_sets(m, xs, vs, sets, h, border=1e-6):
+    """Every substep's GPU contact sets against the oracle at the FP64 prediction from the
+    GPU's state: sure contacts (distance < th - border) all listed, nothing listed beyond
+    th + border, nothing on pinned nodes.  Returns (listed contacts, near-threshold ones)."""
+    listed = near = 0
+    for s, (x, v, cs) in enumerate(zip(xs, vs, sets)):
+        xp, _ = m.predict(x, v, h)
+        st, nb = m.check_contacts(xp, cs, border)
+        bad = np.nonzero(st)[0]
+        assert bad.size == 0, ("substep", s, "invalid contact sets at nodes", bad[:8].tolist(),
+                               st[bad[:8]].tolist())
+        listed += int(cs[0][-1])
+        near += nb
+    return listed, near
+
+
+def _oracle_adjoint_on_gpu_trajectory(m, inp, xs, vs, sets, xT, target):
+    """The oracle's substep adjoint with the GPU's contact sets, run backwards along the
+    GPU's trajectory."""
+    h = h32(inp)
     xb = (2.0 / inp.n_nodes) * (xT.astype(np.float64) - target)
     vb = np.zeros_like(xb)
     gk, gc = np.zeros(inp.n_springs), np.zeros(inp.n_springs)
-    contacts = 0
-    for n in range(n_sub - 1, -1, -1):
-        contacts += sum(1 for c in cs[n] if c)
-        xb, vb, kb, cb = m.substep_vjp_given(xs[n], vs[n], h, cs[n], xb, vb)
+    for n in range(len(xs) - 1, -1, -1):
+        xb, vb, kb, cb = m.substep_vjp_given(xs[n], vs[n], h, sets[n], xb, vb)
         gk += kb
         gc += cb
-    return gk, gc, vb, xT, contacts
+    return gk, gc, vb
 
 
 def _target(inp, n_steps, seed=11):
@@ -101,22 +128,99 @@ def test_forward_matches_plain_stepping_bitwise():
         assert np.array_equal(x[0].cpu().numpy(), inp.x0)
 
 
+def _scene(name):
+    if name == "small":
+        inp = W.small_collision_scene(n=14, freq=5, drop=0.165, spacing=0.02)
+        return inp, 60, _target(inp, 60)
+    # 64x64 cloth over a 2,000-triangle sphere, 200 frames x 4 substeps, checkpoints every
+    # 20 frames; the target is the oracle's forward pass with the workload's perturbed
+    # stiffness k_hat = k (1 + 0.1 xi)
+    inp, k_hat = W.config4()
+    m = oracle.Model.from_inputs(inp, k=k_hat.astype(np.float64))
+    x, _ = m.run(inp.x0, inp.v0, h32(inp), inp.n_steps * inp.n_substeps)
+    return inp, inp.n_steps, x
+
+
+_RUNS = {}
+
+
+def _run(name):
+    """GPU gradients of the scene's loss plus the recorded GPU trajectory and its validated
+    contact sets (computed once per scene)."""
+    if name not in _RUNS:
+        inp, n_steps, target = _scene(name)
+        gk, gc, gv, xT = _gpu_grads(inp, n_steps, target)
+        xs, vs, sets, xT2 = _record_gpu_trajectory(inp, n_steps)
+        assert np.array_equal(xT, xT2)  # the rollout steps exactly as plain stepping
+        m = oracle.Model.from_inputs(inp)
+        listed, near = _check_contact_sets(m, xs, vs, sets, h32(inp))
+        print(f"{name}: {len(xs)} substeps, {listed} contacts listed by the GPU, all valid "
+              f"({near} within 1e-6 m of the thickness)")
+        _RUNS[name] = dict(inp=inp, n_steps=n_steps, target=target, g=(gk, gc, gv), xs=xs,
+                           vs=vs, sets=sets, xT=xT, m=m, listed=listed)
+    return _RUNS[name]
+
+
 @pytest.mark.parametrize("scene", ["small", "config4"])
 def test_gradients_match_oracle_adjoint_on_gpu_contact_sets(scene):
-    if scene == "small":
-        inp, n_steps = W.small_collision_scene(n=14, freq=5, drop=0.165, spacing=0.02), 60
-    else:
-        inp, _ = W.config4()
-        n_steps = inp.n_steps  # 200 frames x 4 substeps, checkpoints every 20 frames
-    target = _target(inp, n_steps)
-    gk, gc, gv, xT = _gpu_grads(inp, n_steps, target)
-    rk, rc, rv, xT2, contacts = _oracle_adjoint_on_gpu_trajectory(inp, n_steps, target)
-    assert np.array_equal(xT, xT2)
-    assert contacts > 100
-    for name, a, b in (("k", gk, rk), ("c", gc, rc), ("v0", gv, rv)):
+    r = _run(scene)
+    assert r["listed"] > 100
+    rk, rc, rv = _oracle_adjoint_on_gpu_trajectory(r["m"], r["inp"], r["xs"], r["vs"],
+                                                   r["sets"], r["xT"], r["target"])
+    for name, a, b in zip(("k", "c", "v0"), r["g"], (rk, rc, rv)):
         err = _normwise(a, b)
         print(f"{scene} {name}: normwise relative error {err:.2e} (|g| = {np.linalg.norm(b):.3e})")
         assert err <= 1e-3, name
+
+
+def test_config4_gradients_match_central_differences_with_collision():
+    """15 entries each of k, c and v0: central differences of the FP64 oracle rollout with
+    the GPU's contact sets held fixed, i.e. of the smooth piece the GPU's gradient
+    differentiates.  Step eps max(|theta|, scale), scale = 0.01 m/s for v0 (which is zero
+    here), eps = 1e-3 first; the 800-substep draped rollout bends strongly in some entries,
+    so where eps = 1e-3 misses the bar the difference is retaken at 1e-4, 1e-5 and 1e-6 (a
+    wrong gradient misses at every step: the differences converge to the true
+    derivative)."""
+    r = _run("config4")
+    inp, m, target, sets = r["inp"], r["m"], r["target"], r["sets"]
+    h = h32(inp)
+    k0, c0 = inp.k.astype(np.float64), inp.c.astype(np.float64)
+    v00 = inp.v0.astype(np.float64)
+    gk, gc, gv = r["g"]
+
+    def loss(k, c, v):
+        m.set_params(k=k, c=c)
+        x, _ = m.run_given(inp.x0, v, h, sets)
+        return np.mean(np.sum((x - target) ** 2, axis=1))
+
+    rng = np.random.default_rng(44)
+    worst, steps = {}, {}
+    try:
+        for name, theta, g, scale in (("k", k0, gk, 0.0), ("c", c0, gc, 0.0),
+                                      ("v0", v00, gv, 0.01)):
+            gmax = np.abs(g).max()
+            worst[name] = 0.0
+            for i in rng.choice(theta.size, 15, replace=False):
+                for eps in (1e-3, 1e-4, 1e-5, 1e-6):
+                    step = eps * max(abs(theta.flat[i]), scale)
+                    vals = []
+                    for sgn in (1, -1):
+                        t = theta.copy()
+                        t.flat[i] += sgn * step
+                        args = {"k": (t, c0, v00), "c": (k0, t, v00), "v0": (k0, c0, t)}[name]
+                        vals.append(loss(*args))
+                    fd = (vals[0] - vals[1]) / (2 * step)
+                    err = abs(fd - g.flat[i]) / max(abs(fd), 1e-3 * gmax)
+                    if err <= 1e-3:
+                        break
+                steps[(name, eps)] = steps.get((name, eps), 0) + 1
+                worst[name] = max(worst[name], err)
+                assert err <= 1e-3, (name, int(i), fd, float(g.flat[i]))
+            print(f"  {name}: worst relative error {worst[name]:.2e}", flush=True)
+    finally:
+        m.set_params(k=k0, c=c0)
+    print("config4 central differences: worst relative error",
+          {k: f"{v:.2e}" for k, v in worst.items()}, "entries per step", steps)
 
 
 def test_gradients_match_central_differences_without_collision():
@@ -173,15 +277,16 @@ def test_gradients_independent_of_checkpoint_interval():
 def test_gradients_independent_of_the_hit_list_length():
     """The contact search with no hit list, short lists that often overflow to the unlisted
     search, the default and the longest list (which the adjoint's kernels cap at 63 so four
-    wavefronts' lists fit 64 KiB) finds the same contacts in the same order: gradients are
-    bit-identical."""
+    wavefronts' lists fit 64 KiB) finds the same contacts in the same order, and a forward
+    pass on the four-lane kernel steps the same bits: gradients are bit-identical."""
     import torch
     inp = W.small_collision_scene(n=14, freq=5, drop=0.165, spacing=0.02)
     dev = torch.device("cuda")
     grads = []
-    for slots in (32, 0, 2, 64):
+    for cfg in (dict(hit_slots=32), dict(hit_slots=0), dict(hit_slots=2), dict(hit_slots=64),
+                dict(kernel=B.CLOTH_KERNEL_LANES4, hit_slots=8, block_threads=64)):
         with B.Cloth(inp) as sim:
-            sim.set_launch(hit_slots=slots)
+            sim.set_launch(**cfg)
             k = torch.tensor(inp.k, device=dev, requires_grad=True)
             c = torch.tensor(inp.c, device=dev, requires_grad=True)
             v0 = torch.zeros((inp.n_nodes, 3), device=dev, requires_grad=True)

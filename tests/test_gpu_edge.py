@@ -118,9 +118,11 @@ def test_every_spring_with_its_own_parameters():
     print(f"{S} springs, {contacts} contacts")
     assert contacts > 0
     outs = []
-    for kernel in (B.CLOTH_KERNEL_DIRECT, B.CLOTH_KERNEL_TILE):
+    for kernel in (B.CLOTH_KERNEL_DIRECT, B.CLOTH_KERNEL_TILE, B.CLOTH_KERNEL_LANES2,
+                   B.CLOTH_KERNEL_LANES4):
         with B.Cloth(inp) as sim:
             sim.set_launch(kernel=kernel)
             sim.step(n_steps=25)
             outs.append(sim.read_state())
-    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    for x, v in outs[1:]:
+        assert np.array_equal(outs[0][0], x) and np.array_equal(outs[0][1], v)

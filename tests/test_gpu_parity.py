@@ -96,36 +96,61 @@ def _tiny_surfaces():
 
 @pytest.mark.parametrize("which", [0, 1, 2, 3, 4])
 def test_broadphase_candidates_equal_fp32_brute_force(which):
+    """The step kernels' own query (coded box test of the point's cell, undecided boxes
+    settled with the exact box, through the LDS hit list or, when it overflows or is off,
+    the unlisted loop) against the O(points x triangles) FP32 brute force, bit for bit, on
+    random points, points outside the grid, points on and one ulp either side of inflated
+    box faces, points within a few 1/32768 of a cell width of box faces (where the coded
+    test is undecided) and points on grid-cell faces."""
     inp = list(_tiny_surfaces())[which]
     rng = np.random.default_rng(100 + which)
     V = inp.verts.astype(np.float64)
     th = np.float32(inp.thickness)
+    cell = np.float32(inp.cell_size)
     pts = [V[rng.integers(0, V.shape[0], 1500)] + rng.normal(0, 0.008, size=(1500, 3))]
     # far outside the grid
     pts.append(rng.uniform(-3, 3, size=(200, 3)))
-    # exactly on, and one ulp outside / inside, inflated box faces
     T = inp.tris
     lo = np.min(inp.verts[T], axis=1) - th
     hi = np.max(inp.verts[T], axis=1) + th
     pick = rng.integers(0, T.shape[0], 200)
+    base = (lo[pick] + hi[pick]) * np.float32(0.5)
     for bound in (lo[pick], hi[pick]):
-        base = (lo[pick] + hi[pick]) * np.float32(0.5)
         for axis in range(3):
-            for d in (-1, 0, 1):
+            # exactly on, and 1-3 ulps either side of, the face
+            for d in (-3, -2, -1, 0, 1, 2, 3):
                 q = base.copy()
                 q[:, axis] = bound[:, axis]
-                if d:
-                    q[:, axis] = np.nextafter(q[:, axis], np.float32(d * np.inf))
+                for _ in range(abs(d)):
+                    q[:, axis] = np.nextafter(q[:, axis], np.float32(np.sign(d) * np.inf))
                 pts.append(q.astype(np.float64))
+            # within a few code buckets (1/32768 of a cell) of the face
+            for f in (-2.0, -1.0, -0.5, -0.25, 0.25, 0.5, 1.0, 2.0):
+                q = base.copy()
+                q[:, axis] = bound[:, axis] + np.float32(f / 32768.0) * cell
+                pts.append(q.astype(np.float64))
+    # on grid-cell faces (origin min(V) - thickness, as the grid is built) and one ulp away
+    org = np.min(inp.verts, axis=0) - th
+    q0 = (V[rng.integers(0, V.shape[0], 300)] + rng.normal(0, 0.004, size=(300, 3))).astype(np.float32)
+    for axis in range(3):
+        for d in (-1, 0, 1):
+            q = q0.copy()
+            k = np.round((q[:, axis] - org[axis]) / cell)
+            q[:, axis] = (org[axis] + k * cell).astype(np.float32)
+            if d:
+                q[:, axis] = np.nextafter(q[:, axis], np.float32(d * np.inf))
+            pts.append(q.astype(np.float64))
     P = np.concatenate(pts).astype(np.float32)
+    want = oracle.candidates_f32(P, inp.verts, inp.tris, inp.thickness)
     with B.Cloth(inp) as sim:
         info = sim.info()
-        got = sim.debug_candidates(P)
-        # also points on grid cell faces of the handle's own grid
         assert info["cells"] > 0
-    want = oracle.candidates_f32(P, inp.verts, inp.tris, inp.thickness)
-    print(f"surface {which}: {P.shape[0]} points, {want.shape[0]} pairs, grid {info}")
-    assert got.shape == want.shape and np.array_equal(got, want)
+        for slots in (32, 2, 0):  # default list, lists that overflow, no list
+            sim.set_launch(hit_slots=slots)
+            got = sim.debug_candidates(P)
+            print(f"surface {which}, hit_slots {slots}: {P.shape[0]} points, "
+                  f"{want.shape[0]} pairs, grid {info}")
+            assert got.shape == want.shape and np.array_equal(got, want), slots
 
 
 def test_one_substep_parity_with_collision_small():
@@ -146,20 +171,50 @@ def test_one_substep_parity_with_collision_small():
     assert total_contacts > 500
 
 
-@pytest.mark.parametrize("frames", [0, 60, 150, 299])
-def test_config1_full_size_one_substep_parity(frames):
+def test_config1_whole_run_parity_and_no_penetration():
+    """The 316x316 cloth dropped on the 100,820-triangle sphere, 300 frames: one substep
+    checked against the oracle from the GPU's own state at frame 0 and every 10th frame
+    (near-threshold contacts resolved), and no node inside the closed surface after every
+    5th frame and after every substep of frames 100-101 (the surface is never penetrated,
+    Sec. 4.2).  The largest position and velocity errors of the clean nodes are printed."""
+    from oracle.inside import inside_closed_mesh
+
     inp = W.config1()
     model = oracle.Model.from_inputs(inp)
+    h = h32(inp)
+    worst_x = worst_v = 0.0
+    contacts = amb = checked = inside_checks = 0
     with B.Cloth(inp) as sim:
-        if frames:
-            sim.step(n_steps=frames)
-        x, v = sim.read_state()
-        sim.step(dt=h32(inp), n_substeps=1, n_steps=1)
-        x1, v1 = sim.read_state()
-    r = one_substep_check(inp, x, v, x1, v1, model, tag=f"config1 frame {frames}")
-    print(f"config1 frame {frames}: {r}")
-    if frames >= 150:
-        assert r["contacts"] > 1000
+        for frame in range(inp.n_steps):
+            if frame % 10 == 0 or frame == inp.n_steps - 1:
+                x, v = sim.read_state()
+                sim.step(dt=h, n_substeps=1, n_steps=1)
+                x1, v1 = sim.read_state()
+                r = one_substep_check(inp, x, v, x1, v1, model, tag=f"config1 frame {frame}")
+                worst_x, worst_v = max(worst_x, r["ex"]), max(worst_v, r["ev"])
+                contacts += r["contacts"]
+                amb += r["ambiguous"]
+                checked += 1
+                sim.step(dt=h, n_substeps=1, n_steps=inp.n_substeps - 1)
+            elif frame in (100, 101):
+                for _ in range(inp.n_substeps):
+                    sim.step(dt=h, n_substeps=1, n_steps=1)
+                    x, _ = sim.read_state()
+                    assert not inside_closed_mesh(x, inp.verts, inp.tris).any(), frame
+                    inside_checks += 1
+            else:
+                sim.step(n_steps=1)
+            if frame % 50 == 49:
+                print(f"  config1 frame {frame + 1}: {checked} substeps checked", flush=True)
+            if frame % 5 == 4:
+                x, _ = sim.read_state()
+                bad = np.nonzero(inside_closed_mesh(x, inp.verts, inp.tris))[0]
+                assert bad.size == 0, ("penetration after frame", frame, bad[:8].tolist())
+                inside_checks += 1
+    print(f"config1: {checked} substeps checked, {contacts} contacts, {amb} near-threshold "
+          f"nodes resolved; worst clean-node error |dx|/L = {worst_x:.2e}, |dv| = "
+          f"{worst_v:.2e} m/s; {inside_checks} no-penetration checks")
+    assert contacts > 10000
 
 
 def test_config2_full_size_one_substep_parity():
@@ -205,6 +260,11 @@ LAUNCHES = [
     dict(kernel=B.CLOTH_KERNEL_TILE, tile_nodes=1024, substeps_per_launch=4, block_threads=128,
          use_graph=1),
     dict(kernel=B.CLOTH_KERNEL_TILE, tile_nodes=128, substeps_per_launch=8, use_graph=0),
+    dict(kernel=B.CLOTH_KERNEL_LANES2, block_threads=64, use_graph=1, hit_slots=8),
+    dict(kernel=B.CLOTH_KERNEL_LANES2, block_threads=256, use_graph=0, hit_slots=0, xcd_runs=3),
+    dict(kernel=B.CLOTH_KERNEL_LANES4, block_threads=64, use_graph=1, hit_slots=8),
+    dict(kernel=B.CLOTH_KERNEL_LANES4, block_threads=128, use_graph=1, hit_slots=1),
+    dict(kernel=B.CLOTH_KERNEL_LANES4, block_threads=256, use_graph=0, hit_slots=0, xcd_runs=1),
 ]
 
 
@@ -272,11 +332,15 @@ def _sliver_fan_scene(n_fan=400, n=24, spacing=0.008, drop=0.02):
 
 def test_sliver_triangles_listed_and_unlisted_queries_agree():
     """On a surface of sliver triangles (closest points on long edges, a crowded centre cell
-    that overflows the hit list) the listed query, the unlisted one and a 64-slot list give
-    the same bits, and one substep matches the oracle."""
+    that overflows the hit list, nodes with more contacts than a lane of the lanes kernels
+    keeps) the listed query, the unlisted one, a 64-slot list and the two- and four-lane
+    kernels give the same bits, and one substep matches the oracle."""
     inp = _sliver_fan_scene()
     outs = []
-    for cfg in (dict(), dict(hit_slots=0), dict(hit_slots=64, block_threads=256)):
+    for cfg in (dict(), dict(hit_slots=0), dict(hit_slots=64, block_threads=256),
+                dict(kernel=B.CLOTH_KERNEL_LANES4, hit_slots=8, block_threads=64),
+                dict(kernel=B.CLOTH_KERNEL_LANES2, hit_slots=2, block_threads=128),
+                dict(kernel=B.CLOTH_KERNEL_LANES4, hit_slots=0, block_threads=64)):
         with B.Cloth(inp) as sim:
             if cfg:
                 sim.set_launch(**cfg)
@@ -306,3 +370,36 @@ def test_no_collision_default_is_the_tile_kernel_and_matches_direct():
             sim.step(n_steps=inp.n_steps)
             outs.append(sim.read_state())
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_query_volume_counts_match_the_fp32_brute_force():
+    """cloth_debug_query_volume on nodes whose prediction is their position (no springs, no
+    gravity, at rest): the box hits over all nodes are exactly the FP32 brute-force
+    candidate pairs, the distinct candidate triangles those pairs name, and the cell counts
+    are consistent (each queried cell counted once, every hit inside a queried cell)."""
+    base = W.small_collision_scene(n=24, freq=6)
+    rng = np.random.default_rng(77)
+    V = base.verts.astype(np.float64)
+    P = (V[rng.integers(0, V.shape[0], base.n_nodes)] +
+         rng.normal(0, 0.006, size=(base.n_nodes, 3))).astype(np.float32)
+    pinned = np.zeros(base.n_nodes, dtype=np.uint8)
+    pinned[::17] = 1  # pinned nodes never query
+    empty_i = np.zeros((0, 2), dtype=np.int32)
+    empty_f = np.zeros(0, dtype=np.float32)
+    inp = dataclasses.replace(base, x0=P, v0=np.zeros_like(P), pinned=pinned, ends=empty_i,
+                              rest=empty_f, k=empty_f, c=empty_f,
+                              kind=np.zeros(0, dtype=np.int8), gravity=(0.0, 0.0, 0.0))
+    free = pinned == 0
+    pairs = oracle.candidates_f32(P, inp.verts, inp.tris, inp.thickness)
+    pairs = pairs[free[pairs[:, 0]]]
+    with B.Cloth(inp) as sim:
+        for slots in (32, 0):
+            sim.set_launch(hit_slots=slots)
+            vol = sim.query_volume()
+            assert vol["box_hits"] == pairs.shape[0], (slots, vol)
+            assert vol["candidate_tris"] == np.unique(pairs[:, 1]).size, (slots, vol)
+            assert vol["node_queries"] >= np.unique(pairs[:, 0]).size
+            assert vol["node_queries"] <= int(free.sum())
+            assert 0 < vol["cells"] <= vol["node_queries"]
+            assert vol["cell_refs"] <= vol["refs_tested"] and vol["box_hits"] <= vol["refs_tested"]
+    print(f"{pairs.shape[0]} pairs, volume {vol}")

@@ -187,3 +187,23 @@ def test_drop_never_penetrates_surface():
         if s % 8 == 7:
             assert not np.any(_inside_closed_mesh(x, V, inp.tris))
     assert touched > 20  # the drop really reached the surface
+
+
+def test_fast_inside_test_equals_the_ray_parity_brute_force():
+    """oracle.inside (segment crossings from the centre, candidate triangles from a k-d tree
+    of directions) against the brute-force ray parity along +x over every triangle, on points
+    around a displaced sphere: near its surface, deep inside, far outside."""
+    from oracle.inside import inside_closed_mesh
+
+    verts, tris = W.displaced_sphere(6, 0.15, 0.015, np.random.default_rng(8))
+    V = verts.astype(np.float64)
+    rng = np.random.default_rng(9)
+    P = np.concatenate([
+        V[rng.integers(0, V.shape[0], 600)] * (1 + rng.normal(0, 0.02, size=(600, 1))),
+        rng.normal(0, 0.05, size=(100, 3)),
+        rng.uniform(-0.4, 0.4, size=(300, 3)),
+    ])
+    fast = inside_closed_mesh(P, V, tris)
+    slow = _inside_closed_mesh(P, V, tris)
+    assert np.array_equal(fast, slow)
+    assert 100 < fast.sum() < P.shape[0] - 100
