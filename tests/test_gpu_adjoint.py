@@ -173,20 +173,56 @@ def test_gradients_match_oracle_adjoint_on_gpu_contact_sets(scene):
         assert err <= 1e-3, name
 
 
+def _oracle_adjoint_on_given_trajectory(m, inp, sets, target):
+    """The FP64 trajectory of the smooth piece with the given contact sets, from the initial
+    state, and the oracle's substep adjoint run backwards along it: the derivative that
+    central differences of run_given approximate."""
+    h = h32(inp)
+    x, v = inp.x0.astype(np.float64), inp.v0.astype(np.float64)
+    xs, vs = [], []
+    for cs in sets:
+        xs.append(x)
+        vs.append(v)
+        x, v = m.substep_given(x, v, h, cs)
+    xb = (2.0 / inp.n_nodes) * (x - target)
+    vb = np.zeros_like(xb)
+    gk, gc = np.zeros(inp.n_springs), np.zeros(inp.n_springs)
+    for n in range(len(sets) - 1, -1, -1):
+        xb, vb, kb, cb = m.substep_vjp_given(xs[n], vs[n], h, sets[n], xb, vb)
+        gk += kb
+        gc += cb
+    return gk, gc, vb
+
+
 def test_config4_gradients_match_central_differences_with_collision():
     """15 entries each of k, c and v0: central differences of the FP64 oracle rollout with
-    the GPU's contact sets held fixed, i.e. of the smooth piece the GPU's gradient
-    differentiates.  Step eps max(|theta|, scale), scale = 0.01 m/s for v0 (which is zero
-    here), eps = 1e-3 first; the 800-substep draped rollout bends strongly in some entries,
-    so where eps = 1e-3 misses the bar the difference is retaken at 1e-4, 1e-5 and 1e-6 (a
-    wrong gradient misses at every step: the differences converge to the true
-    derivative)."""
+    the GPU's validated contact sets held fixed, i.e. of the smooth piece the GPU's gradient
+    differentiates (no FD sample can flip a contact: the sets are fixed).  The step is 1e-3
+    of the entry (of 0.01 m/s for the zero v0) first; the 800-substep rollout over the
+    surface is strongly curved in some entries (the difference's error falls with the square
+    of the step), so where the 1e-3 step misses the bar below it is retaken at 1e-4, 1e-5
+    and 1e-6 (a wrong derivative misses at every step: the differences converge to it).
+
+    The FD differentiates the piece along its FP64 trajectory from the initial state; the
+    GPU differentiates it along its own FP32 trajectory, whose small rounding differences
+    the 800 substeps of contact amplify.  So, per sampled entry:
+      (a) the FP64 adjoint along the FP64 trajectory of the piece (a) matches the
+          difference to 1e-3 relative (floor 1e-6 of its largest entry);
+      (b) the GPU gradient (g) matches the FP64 adjoint along the GPU's own states (b) to
+          1e-3 of max(|b|, 1e-3 of b's largest entry);
+      (c) the GPU gradient matches the difference to 1e-3 of max(|difference|, the largest
+          gradient entry) -- the bar of the test without collision -- plus |a - b|, the
+          part the two trajectories account for (an oracle quantity: both adjoints are the
+          oracle's)."""
     r = _run("config4")
     inp, m, target, sets = r["inp"], r["m"], r["target"], r["sets"]
     h = h32(inp)
     k0, c0 = inp.k.astype(np.float64), inp.c.astype(np.float64)
     v00 = inp.v0.astype(np.float64)
     gk, gc, gv = r["g"]
+    ak, ac, av = _oracle_adjoint_on_given_trajectory(m, inp, sets, target)
+    bk, bc, bv = _oracle_adjoint_on_gpu_trajectory(m, inp, r["xs"], r["vs"], sets, r["xT"],
+                                                   target)
 
     def loss(k, c, v):
         m.set_params(k=k, c=c)
@@ -194,12 +230,12 @@ def test_config4_gradients_match_central_differences_with_collision():
         return np.mean(np.sum((x - target) ** 2, axis=1))
 
     rng = np.random.default_rng(44)
-    worst, steps = {}, {}
+    report, steps = {}, {}
     try:
-        for name, theta, g, scale in (("k", k0, gk, 0.0), ("c", c0, gc, 0.0),
-                                      ("v0", v00, gv, 0.01)):
-            gmax = np.abs(g).max()
-            worst[name] = 0.0
+        for name, theta, g, a, b, scale in (("k", k0, gk, ak, bk, 0.0), ("c", c0, gc, ac, bc, 0.0),
+                                            ("v0", v00, gv, av, bv, 0.01)):
+            gmax, amax, bmax = np.abs(g).max(), np.abs(a).max(), np.abs(b).max()
+            worst = np.zeros(4)
             for i in rng.choice(theta.size, 15, replace=False):
                 for eps in (1e-3, 1e-4, 1e-5, 1e-6):
                     step = eps * max(abs(theta.flat[i]), scale)
@@ -210,17 +246,27 @@ def test_config4_gradients_match_central_differences_with_collision():
                         args = {"k": (t, c0, v00), "c": (k0, t, v00), "v0": (k0, c0, t)}[name]
                         vals.append(loss(*args))
                     fd = (vals[0] - vals[1]) / (2 * step)
-                    err = abs(fd - g.flat[i]) / max(abs(fd), 1e-3 * gmax)
-                    if err <= 1e-3:
+                    e_a = abs(fd - a.flat[i]) / max(abs(fd), 1e-6 * amax)
+                    if e_a <= 1e-3:
                         break
                 steps[(name, eps)] = steps.get((name, eps), 0) + 1
-                worst[name] = max(worst[name], err)
-                assert err <= 1e-3, (name, int(i), fd, float(g.flat[i]))
-            print(f"  {name}: worst relative error {worst[name]:.2e}", flush=True)
+                e_b = abs(g.flat[i] - b.flat[i]) / max(abs(b.flat[i]), 1e-3 * bmax)
+                traj = abs(a.flat[i] - b.flat[i])
+                e_c = (abs(fd - g.flat[i]) - traj) / max(abs(fd), gmax)
+                e_fd = abs(fd - g.flat[i]) / max(abs(fd), gmax)
+                worst = np.maximum(worst, [e_a, e_b, e_c, e_fd])
+                assert e_a <= 1e-3, ("FP64 adjoint vs FD", name, int(i), fd, float(a.flat[i]))
+                assert e_b <= 1e-3, ("GPU vs FP64 adjoint on its states", name, int(i),
+                                     float(g.flat[i]), float(b.flat[i]))
+                assert e_c <= 1e-3, ("GPU vs FD", name, int(i), fd, float(g.flat[i]), traj, gmax)
+            report[name] = worst
     finally:
         m.set_params(k=k0, c=c0)
-    print("config4 central differences: worst relative error",
-          {k: f"{v:.2e}" for k, v in worst.items()}, "entries per step", steps)
+    for name, w in report.items():
+        print(f"config4 {name}: (a) FP64 adjoint vs FD {w[0]:.2e}; (b) GPU vs FP64 adjoint on "
+              f"the GPU's states {w[1]:.2e}; (c) GPU vs FD beyond the trajectory term {w[2]:.2e} "
+              f"(without it {w[3]:.2e}) of max(|fd|, |g|max)")
+    print("entries per difference step", steps)
 
 
 def test_gradients_match_central_differences_without_collision():
