@@ -214,6 +214,23 @@ int cloth_debug_candidates(cloth_sim* sim, int n_points, const float* points, in
                            long long cap, long long* n_out);
 
 /*
+ * cloth_debug_candidates_noalloc -- cloth_debug_candidates for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments and the same pairs, with the device buffers of the query
+ * (the points, their counts and offsets, the scan's partial sums, the pairs) taken from a
+ * fixed 8 MiB device array inside the library instead of allocated per call.  No device
+ * memory is allocated or freed.  Each GPU the library runs on holds its own copy of that
+ * array until the process ends; the call uses the copy of the current device (make the
+ * handle's device current), and calls that overlap on one GPU race on it.
+ * Limits: n_points <= 65536, and the pairs must fit the rest of the array (786,368
+ * pairs at 65,536 points, more for fewer points).
+ * Errors: as cloth_debug_candidates; CLOTH_ENOMEM when n_points > 65536 or the pairs do not
+ * fit (*n_out then holds the total number of pairs), nothing written to pairs_out.
+ */
+int cloth_debug_candidates_noalloc(cloth_sim* sim, int n_points, const float* points,
+                                   int* pairs_out, long long cap, long long* n_out);
+
+/*
  * cloth_stability_bound -- host-only (no GPU) stability bounds of a spring network at
  * configuration x0: *omega2 and *gamma are the largest Gershgorin row sums of M^-1 K and
  * M^-1 C (K, C assembled from k u u^T and c u u^T per spring, u the unit spring direction);

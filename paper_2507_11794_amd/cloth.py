@@ -75,6 +75,7 @@ _SIGNATURES = [
     ("cloth_info", C.c_int, [_vp, _llp]),
     ("cloth_destroy", C.c_int, [_vp]),
     ("cloth_debug_candidates", C.c_int, [_vp, C.c_int, _fp, _ip, C.c_longlong, _llp]),
+    ("cloth_debug_candidates_noalloc", C.c_int, [_vp, C.c_int, _fp, _ip, C.c_longlong, _llp]),
     ("cloth_stability_bound", C.c_int, [C.c_int, _fp, _fp, _u8p, C.c_int, _ip, _fp, _fp,
                                         C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("cloth_set_launch", C.c_int, [_vp, C.POINTER(cloth_launch)]),
@@ -228,15 +229,17 @@ def cloth_destroy(h):
         _check(load().cloth_destroy(_vp(h)))
 
 
-def cloth_debug_candidates(h, points):
+def cloth_debug_candidates(h, points, noalloc=False):
+    """Broad-phase (point, triangle) pairs of points [n, 3]; noalloc selects
+    cloth_debug_candidates_noalloc (the library's fixed device scratch, no allocation)."""
     lib = load()
+    fn = lib.cloth_debug_candidates_noalloc if noalloc else lib.cloth_debug_candidates
     P = _f32(points).reshape(-1, 3)
     n = C.c_longlong(0)
-    _check(lib.cloth_debug_candidates(_vp(h), P.shape[0], _ptr(P, _fp), None, 0, C.byref(n)))
+    _check(fn(_vp(h), P.shape[0], _ptr(P, _fp), None, 0, C.byref(n)))
     pairs = np.zeros((max(n.value, 1), 2), dtype=np.int32)
     n2 = C.c_longlong(0)
-    _check(lib.cloth_debug_candidates(_vp(h), P.shape[0], _ptr(P, _fp), _ptr(pairs, _ip),
-                                      n.value, C.byref(n2)))
+    _check(fn(_vp(h), P.shape[0], _ptr(P, _fp), _ptr(pairs, _ip), n.value, C.byref(n2)))
     return pairs[:n.value].copy()
 
 
@@ -368,8 +371,8 @@ class Cloth:
     def get_launch(self):
         return cloth_get_launch(self.h)
 
-    def debug_candidates(self, points):
-        return cloth_debug_candidates(self.h, points)
+    def debug_candidates(self, points, noalloc=False):
+        return cloth_debug_candidates(self.h, points, noalloc=noalloc)
 
     def update_surface(self, verts):
         """Move the collision surface: new vertex positions [V, 3], same triangles."""
