@@ -412,7 +412,8 @@ def parse_launch(text: str) -> dict:
                              "scatter_f32": cloth.CLOTH_KERNEL_SCATTER_F32,
                              "scatter_fix": cloth.CLOTH_KERNEL_SCATTER_FIX,
                              "lanes2": cloth.CLOTH_KERNEL_LANES2,
-                             "lanes4": cloth.CLOTH_KERNEL_LANES4}[v]
+                             "lanes4": cloth.CLOTH_KERNEL_LANES4,
+                             "grid": cloth.CLOTH_KERNEL_GRID}[v]
         else:
             cfg[names.get(k, k)] = int(v)
     return cfg

@@ -83,7 +83,13 @@ enum cloth_kernel {
     CLOTH_KERNEL_LANES2 = 4,      /* one launch per substep, two lanes per node: each lane
                                      gathers half the node's springs and tests half of its
                                      cell's references (same results as DIRECT, bit for bit) */
-    CLOTH_KERNEL_LANES4 = 5       /* the same with four lanes per node */
+    CLOTH_KERNEL_LANES4 = 5,      /* the same with four lanes per node */
+    CLOTH_KERNEL_GRID = 6         /* grid cloths whose springs join nodes at most two rows or
+                                     columns apart (one spring per offset): one launch per
+                                     substep, one wavefront per 8x8 tile of nodes, the tile and
+                                     a two-node halo staged in LDS (same results as DIRECT, bit
+                                     for bit; block_threads is 64); CLOTH_EINVAL for other
+                                     spring graphs */
 };
 
 /* How tiles are assigned to workgroups (tile kernel). */

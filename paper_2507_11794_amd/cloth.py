@@ -39,7 +39,7 @@ class cloth_launch(C.Structure):
 
 CLOTH_KERNEL_TILE, CLOTH_KERNEL_DIRECT = 0, 1
 CLOTH_KERNEL_SCATTER_F32, CLOTH_KERNEL_SCATTER_FIX = 2, 3
-CLOTH_KERNEL_LANES2, CLOTH_KERNEL_LANES4 = 4, 5
+CLOTH_KERNEL_LANES2, CLOTH_KERNEL_LANES4, CLOTH_KERNEL_GRID = 4, 5, 6
 CLOTH_SCHED_GRID, CLOTH_SCHED_LPT, CLOTH_SCHED_RR = 0, 1, 2
 
 

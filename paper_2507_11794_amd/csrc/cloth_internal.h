@@ -40,8 +40,8 @@ struct SurfaceView {
 //   and inc_spring (spring id, bitwise-negated (~s) when node i is the spring's second end
 //   b).  ptab holds the distinct (k, c, rest length) triples of the springs (a cloth has a
 //   few spring types, so the table stays in cache; after per-spring parameters are set it
-//   may hold one entry per spring).  Each node's incidences are in ascending (neighbour,
-//   spring) order.
+//   may hold one entry per spring).  Each node's incidences are in ascending (neighbour
+//   node id, spring) order.
 struct ClothView {
     int n;
     int ld;  // SoA leading dimension (>= n)
@@ -51,6 +51,27 @@ struct ClothView {
     const uint2* inc2;
     const float4* ptab;  // (k, c, rest length, 0)
     const int* inc_spring;
+};
+
+// Grid stencil of cloths whose springs join only nodes at the offsets (row, column)
+// (-2,0) (-1,-1) (-1,0) (-1,1) (0,-2) (0,-1) (0,1) (0,2) (1,-1) (1,0) (1,1) (2,0), in that
+// order (ascending neighbour id, the order of every node's incidence list), one spring per
+// node and offset at most.  The stencil kernel runs one wavefront per 8x8 tile of the
+// internal order (tiles row by row, nodes row-major in a tile).  A cloth is described by
+// (first slot, nx | ny << 16, first tile, cloth index): `one` for a handle of one cloth,
+// tiles[t] per tile for a batch.  idx[d * ld + p] is the parameter-table entry of the
+// spring from slot p in direction d, or kNoSpring; n_tab points at the table's current
+// entry count (kept on the device so captured graphs stay valid when parameters change);
+// tab_cap is the table's capacity.
+constexpr int kStencilDirs = 12;
+constexpr uint32_t kNoSpring = 0xffffffffu;
+struct GridView {
+    int n_tiles;
+    int4 one;
+    const int4* tiles;
+    const uint32_t* idx;
+    const int* n_tab;
+    int tab_cap;
 };
 
 // Springs for the spring-centric (scatter) force pass: ends as internal slots, parameters
@@ -160,6 +181,20 @@ hipError_t launch_substep(const ClothView& cv, int collide, const StepParams& sp
                           int* heavy = nullptr, int parity = 0, float* pred = nullptr);
 // launch_substep with `lanes` (2 or 4) lanes per node (lanes_step.hip): the same results,
 // bit for bit; no second pass.
+// launch_substep through the grid stencil (grid_step.hip): one wavefront per 8x8 tile stages
+// the tile and a two-node halo in LDS and sums each node's springs from there, in the
+// incidence order; the same results, bit for bit.
+hipError_t launch_grid_substep(const ClothView& cv, const GridView& gv, int collide,
+                               const StepParams& sp, const float* xs, const float* vs, float* xd,
+                               float* vd, hipStream_t stream, const SurfaceView* svs,
+                               int grouped, int hit_slots, int xcd_runs, float* pred = nullptr);
+hipError_t prepare_grid_kernels(size_t lds_bytes);
+// Dynamic LDS of a stencil launch (the hit lists of its one wavefront per workgroup).
+size_t grid_lds_bytes(int hit_slots);
+// Stencil parameter entries from per-spring entries: idx[q] = entry[code[q]], or kNoSpring
+// where code[q] < 0.
+hipError_t launch_set_stencil_entries(size_t m, const int* code, const int* entry,
+                                      uint32_t* idx, hipStream_t st);
 hipError_t launch_substep_lanes(int lanes, const ClothView& cv, int collide, const StepParams& sp,
                                 const float* xs, const float* vs, float* xd, float* vd, int block,
                                 hipStream_t stream, const SurfaceView* svs, const int* node_group,

@@ -1,0 +1,221 @@
+// a1-a4 fused for grid cloths: one substep, one wavefront per 8x8 tile of the internal order,
+// the same results as k_substep bit for bit.
+//
+// The one-thread-per-node gather issues, per node, a load for every incidence record, every
+// parameter entry and every component of every neighbour's state, about a hundred scattered
+// loads per wavefront, and the address units of the compute units become the limit of the
+// whole substep.  On a grid cloth the neighbours sit at fixed offsets (row, column), so here
+//   1. each wavefront loads its tile and a two-node halo (12 x 12 nodes, both state vectors)
+//      into LDS with row-coalesced loads whose slots follow from the grid shape alone (no
+//      index loads first), together with its nodes' parameter-table entries per direction
+//      and, when the table is small, the table itself;
+//   2. each lane sums its node's springs from LDS in the incidence order (ascending
+//      neighbour id = ascending offset (row, column)), with the same spring_force
+//      arithmetic as every other kernel;
+//   3. integration, the grid broad phase, the narrow phase and the response are those of
+//      k_substep.
+#include "cloth_device.h"
+#include "cloth_internal.h"
+
+namespace cloth {
+
+namespace {
+
+constexpr int kSide = 12;                  // region side: the tile and two nodes either side
+constexpr int kRegion = kSide * kSide;     // 144 nodes
+constexpr int kTabLds = 128;               // tables up to this size are read from LDS
+
+// Offsets of the stencil's directions in the region (row * kSide + column), in incidence
+// order.
+__device__ __forceinline__ constexpr int region_offset(int d) {
+    constexpr int off[kStencilDirs] = {-2 * kSide,     -kSide - 1, -kSide, -kSide + 1,
+                                       -2,             -1,         1,      2,
+                                       kSide - 1,      kSide,      kSide + 1, 2 * kSide};
+    return off[d];
+}
+
+// Internal slot of node (row gr, column gc) of a cloth whose tiles start at slot `first`:
+// the tile rows above hold 8 nx nodes each, the tiles to the left in its tile row 8 h nodes
+// each (h: that row's tile height), and nodes are row-major within their tile (w: the tile's
+// width).
+__device__ __forceinline__ int grid_slot(int first, int nx, int ny, int gr, int gc) {
+    const int tr = gr >> 3, tc = gc >> 3;
+    const int h = min(8, ny - 8 * tr), w = min(8, nx - 8 * tc);
+    return first + 8 * nx * tr + 8 * h * tc + (gr & 7) * w + (gc & 7);
+}
+
+template <bool COLLIDE, bool GROUPED>
+__global__ void __launch_bounds__(64, 2)
+    k_grid(const ClothView cv, const GridView gv, const StepParams sp,
+           const float* __restrict__ xs, const float* __restrict__ vs, float* __restrict__ xd,
+           float* __restrict__ vd, const SurfaceView* __restrict__ svs, const int hit_slots,
+           const int xcd_runs, float* __restrict__ pred) {
+    __shared__ float reg[6 * kRegion];  // x, y, z, vx, vy, vz of the region
+    __shared__ float4 tab[kTabLds];
+    extern __shared__ uint32_t hit_lds[];  // wave_query_lds(hit_slots) bytes
+    const int t = xcd_block(xcd_runs, gv.n_tiles);
+    if (t >= gv.n_tiles) return;  // the whole workgroup (one wavefront)
+    const int4 cd = GROUPED ? gv.tiles[t] : gv.one;
+    const int nx = cd.y & 0xffff, ny = cd.y >> 16;
+    const int tl = t - cd.z, tx = (nx + 7) >> 3;
+    const int gr0 = 8 * (tl / tx), gc0 = 8 * (tl % tx);
+    const int lane = threadIdx.x;
+    const int ld = cv.ld;
+    const int r = lane >> 3, c = lane & 7;
+    const bool active = gr0 + r < ny && gc0 + c < nx;
+    const int i = active ? grid_slot(cd.x, nx, ny, gr0 + r, gc0 + c) : 0;
+
+    // 1. every load of the gather in one round
+    float w = 0.0f;
+    uint32_t idx[kStencilDirs];
+#pragma unroll
+    for (int d = 0; d < kStencilDirs; ++d) idx[d] = kNoSpring;
+    if (active) {
+        w = cv.w[i];
+#pragma unroll
+        for (int d = 0; d < kStencilDirs; ++d) idx[d] = gv.idx[(size_t)d * ld + i];
+    }
+    const int n_tab = *gv.n_tab;
+    float4 tv0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), tv1 = tv0;
+    if (lane < gv.tab_cap) tv0 = ldg4(cv.ptab, lane);
+    if (lane + 64 < min(gv.tab_cap, kTabLds)) tv1 = ldg4(cv.ptab, lane + 64);
+    float sv_[3][6];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int e = lane + 64 * j;
+        const int gr = gr0 + e / kSide - 2, gc = gc0 + e % kSide - 2;
+        const bool ok = e < kRegion && gr >= 0 && gr < ny && gc >= 0 && gc < nx;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) sv_[j][k] = 0.0f;
+        if (ok) {
+            const int p = grid_slot(cd.x, nx, ny, gr, gc);
+            sv_[j][0] = xs[p];
+            sv_[j][1] = xs[ld + p];
+            sv_[j][2] = xs[2 * ld + p];
+            sv_[j][3] = vs[p];
+            sv_[j][4] = vs[ld + p];
+            sv_[j][5] = vs[2 * ld + p];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int e = lane + 64 * j;
+        if (e < kRegion) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) reg[k * kRegion + e] = sv_[j][k];
+        }
+    }
+    tab[lane] = tv0;
+    tab[lane + 64] = tv1;
+    __syncthreads();
+
+    // 2. the springs of each node from LDS, in incidence order; 3. integration
+    float px = 0.0f, py = 0.0f, pz = 0.0f, qx = 0.0f, qy = 0.0f, qz = 0.0f;
+    if (active) {
+        const int e0 = (r + 2) * kSide + (c + 2);
+        const float xi = reg[e0], yi = reg[kRegion + e0], zi = reg[2 * kRegion + e0];
+        const float vxi = reg[3 * kRegion + e0], vyi = reg[4 * kRegion + e0],
+                    vzi = reg[5 * kRegion + e0];
+        float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+        float4 e[kStencilDirs];
+        if (n_tab <= kTabLds) {
+#pragma unroll
+            for (int d = 0; d < kStencilDirs; ++d) e[d] = tab[idx[d] == kNoSpring ? 0 : idx[d]];
+        } else {
+#pragma unroll
+            for (int d = 0; d < kStencilDirs; ++d)
+                e[d] = ldg4(cv.ptab, idx[d] == kNoSpring ? 0 : idx[d]);
+        }
+#pragma unroll
+        for (int d = 0; d < kStencilDirs; ++d) {
+            if (idx[d] == kNoSpring) continue;
+            const int e2 = e0 + region_offset(d);
+            spring_force(reg[e2] - xi, reg[kRegion + e2] - yi, reg[2 * kRegion + e2] - zi,
+                         reg[3 * kRegion + e2] - vxi, reg[4 * kRegion + e2] - vyi,
+                         reg[5 * kRegion + e2] - vzi, e[d].x, e[d].y, e[d].z, fx, fy, fz);
+        }
+        add_external(sp, i, fx, fy, fz);
+        integrate(w, sp.h, sp.g, xi, yi, zi, vxi, vyi, vzi, fx, fy, fz, px, py, pz, qx, qy, qz);
+        if (pred) {  // the prediction before collision, for the adjoint
+            pred[i] = px;
+            pred[ld + i] = py;
+            pred[2 * ld + i] = pz;
+        }
+    }
+    // a3 + a4: broad phase, narrow phase, response (as k_substep)
+    if (COLLIDE && active && w != 0.0f) {
+        const SurfaceView sv = svs[GROUPED ? cd.w : 0];
+        if (sv.n_tris > 0) {
+            if (hit_slots > 0)
+                collide_listed(sv, hit_lds + lane, hit_slots, sp.restitution, px, py, pz, qx, qy,
+                               qz);
+            else
+                collide(sv, sp.restitution, px, py, pz, qx, qy, qz);
+        }
+    }
+    if (!active) return;
+    xd[i] = px;
+    xd[ld + i] = py;
+    xd[2 * ld + i] = pz;
+    vd[i] = qx;
+    vd[ld + i] = qy;
+    vd[2 * ld + i] = qz;
+    if (sp.check_nan) {
+        const float sum = px + py + pz + qx + qy + qz;
+        if (!__builtin_isfinite(sum)) atomicOr(sp.nan_flag, 1);
+    }
+}
+
+__global__ void k_set_stencil_entries(size_t m, const int* __restrict__ code,
+                                      const int* __restrict__ entry, uint32_t* __restrict__ idx) {
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    const int s = code[q];
+    idx[q] = s >= 0 ? (uint32_t)entry[s] : kNoSpring;
+}
+
+}  // namespace
+
+size_t grid_lds_bytes(int hit_slots) { return wave_query_lds(hit_slots); }
+
+hipError_t prepare_grid_kernels(size_t lds_bytes) {
+    if (lds_bytes <= 32 * 1024) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void*)k_grid<true, false>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_grid<true, true>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+}
+
+hipError_t launch_grid_substep(const ClothView& cv, const GridView& gv, int collide,
+                               const StepParams& sp, const float* xs, const float* vs, float* xd,
+                               float* vd, hipStream_t stream, const SurfaceView* svs,
+                               int grouped, int hit_slots, int xcd_runs, float* pred) {
+    if (gv.n_tiles <= 0) return hipSuccess;
+    if (xcd_runs < 0 || xcd_runs > kMaxXcdRuns) xcd_runs = 0;
+    if (hit_slots < 0 || hit_slots > kMaxHitSlots) return hipErrorInvalidValue;
+    const int grid = xcd_grid(gv.n_tiles, xcd_runs);
+    const size_t lds = collide ? grid_lds_bytes(hit_slots) : 0;
+    if (collide && grouped)
+        k_grid<true, true><<<grid, 64, lds, stream>>>(cv, gv, sp, xs, vs, xd, vd, svs, hit_slots,
+                                                      xcd_runs, pred);
+    else if (collide)
+        k_grid<true, false><<<grid, 64, lds, stream>>>(cv, gv, sp, xs, vs, xd, vd, svs, hit_slots,
+                                                       xcd_runs, pred);
+    else if (grouped)
+        k_grid<false, true><<<grid, 64, 0, stream>>>(cv, gv, sp, xs, vs, xd, vd, svs, 0, xcd_runs,
+                                                     pred);
+    else
+        k_grid<false, false><<<grid, 64, 0, stream>>>(cv, gv, sp, xs, vs, xd, vd, svs, 0,
+                                                      xcd_runs, pred);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_stencil_entries(size_t m, const int* code, const int* entry, uint32_t* idx,
+                                      hipStream_t st) {
+    if (m == 0) return hipSuccess;
+    k_set_stencil_entries<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(m, code, entry, idx);
+    return hipGetLastError();
+}
+
+}  // namespace cloth

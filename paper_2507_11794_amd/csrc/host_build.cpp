@@ -70,33 +70,75 @@ void DeviceArena::free_one(void* p) {
     }
 }
 
-// Internal node order: the nx-by-ny grid is cut into 8x8 tiles, the tiles are ordered along
-// a Morton (Z-order) curve over their (column, row) coordinates, and nodes are row-major
-// within a tile.  A wavefront of 64 consecutive slots is then one 8x8 patch, and any aligned
-// run of 4^k tiles is a square patch, which keeps spring neighbours and grid cells of
-// consecutive slots close together.
-std::vector<int> tile_order(int nx, int ny) {
+// Internal node order: the nx-by-ny grid is cut into 8x8 tiles (narrower in the last tile
+// column, shorter in the last tile row), the tiles are taken row by row, and nodes are
+// row-major within a tile.  A wavefront of 64 consecutive slots is then one 8x8 patch, and
+// the slot of node (row, column) is plain arithmetic on the grid shape (see k_grid).
+std::vector<std::pair<int, int>> tile_list(int nx, int ny) {
     const int T = 8;
     const int tx = (nx + T - 1) / T, ty = (ny + T - 1) / T;
-    auto spread = [](unsigned long long v) {
-        unsigned long long r = 0;
-        for (int b = 0; b < 32; ++b) r |= ((v >> b) & 1ULL) << (2 * b);
-        return r;
-    };
-    std::vector<std::pair<unsigned long long, int>> tiles;
-    tiles.reserve((size_t)tx * ty);
+    std::vector<std::pair<int, int>> out;
+    out.reserve((size_t)tx * ty);
     for (int j = 0; j < ty; ++j)
-        for (int i = 0; i < tx; ++i)
-            tiles.emplace_back(spread((unsigned)i) | (spread((unsigned)j) << 1), j * tx + i);
-    std::sort(tiles.begin(), tiles.end());
+        for (int i = 0; i < tx; ++i) out.emplace_back(i, j);
+    return out;
+}
+
+std::vector<int> tile_order(int nx, int ny) {
+    const int T = 8;
     std::vector<int> order;
     order.reserve((size_t)nx * ny);
-    for (const auto& tl : tiles) {
-        const int ti = tl.second % tx, tj = tl.second / tx;
+    for (const auto& [ti, tj] : tile_list(nx, ny))
         for (int i = tj * T; i < std::min(ny, tj * T + T); ++i)
             for (int j = ti * T; j < std::min(nx, ti * T + T); ++j) order.push_back(i * nx + j);
-    }
     return order;
+}
+
+// Grid stencil of a handle whose cloths are all grids (sides below 2^15) with springs only
+// between nodes at the twelve offsets (row, column) of the stencil, one spring per node and
+// offset at most.  code[d * ld + p]: the spring from slot p to its neighbour in direction d,
+// or -1.  tiles: per 8x8 tile of the handle, in slot order, its cloth as (first slot,
+// nx | ny << 16, first tile of the cloth, cloth index).
+bool build_stencil(const std::vector<StencilCloth>& cloths, const std::vector<int>& ends,
+                   const std::vector<int>& slot, int ld, std::vector<int>* code,
+                   std::vector<int4>* tiles) {
+    static const int dr[kStencilDirs] = {-2, -1, -1, -1, 0, 0, 0, 0, 1, 1, 1, 2};
+    static const int dc[kStencilDirs] = {0, -1, 0, 1, -2, -1, 1, 2, -1, 0, 1, 0};
+    int dir_of[5][5];
+    for (auto& row : dir_of)
+        for (int& v : row) v = -1;
+    for (int d = 0; d < kStencilDirs; ++d) dir_of[dr[d] + 2][dc[d] + 2] = d;
+    code->assign((size_t)kStencilDirs * ld, -1);
+    tiles->clear();
+    for (size_t g = 0; g < cloths.size(); ++g) {
+        const StencilCloth& c = cloths[g];
+        if (c.nx >= (1 << 15) || c.ny >= (1 << 15)) return false;
+        for (int s = c.spring_off; s < c.spring_off + c.n_springs; ++s) {
+            const int a = ends[2 * (size_t)s] - c.node_off, b = ends[2 * (size_t)s + 1] - c.node_off;
+            const int rr = b / c.nx - a / c.nx, cc = b % c.nx - a % c.nx;
+            if (rr < -2 || rr > 2 || cc < -2 || cc > 2) return false;
+            const int da = dir_of[rr + 2][cc + 2], db = dir_of[2 - rr][2 - cc];
+            if (da < 0) return false;
+            int& ca = (*code)[(size_t)da * ld + slot[c.node_off + a]];
+            int& cb = (*code)[(size_t)db * ld + slot[c.node_off + b]];
+            if (ca >= 0 || cb >= 0) return false;  // a second spring at the same offset
+            ca = s;
+            cb = s;
+        }
+        // the stencil kernel computes slots from the grid shape: they must be these
+        for (int gr = 0; gr < c.ny; ++gr)
+            for (int gc = 0; gc < c.nx; ++gc) {
+                const int tr = gr >> 3, tc = gc >> 3;
+                const int h = std::min(8, c.ny - 8 * tr), w = std::min(8, c.nx - 8 * tc);
+                const int want = c.slot_off + 8 * c.nx * tr + 8 * h * tc + (gr & 7) * w + (gc & 7);
+                if (slot[c.node_off + gr * c.nx + gc] != want) return false;
+            }
+        const int first = (int)tiles->size();
+        const size_t n_t = tile_list(c.nx, c.ny).size();
+        for (size_t q = 0; q < n_t; ++q)
+            tiles->push_back(make_int4(c.slot_off, c.nx | (c.ny << 16), first, (int)g));
+    }
+    return true;
 }
 
 int validate_cloth(const ClothHostInput& in) {
@@ -233,7 +275,9 @@ int build_cloth_host(const ClothHostInput& in, ClothHost* out, const std::vector
         const bool pin = in.pinned && in.pinned[id];
         out->w[p] = pin ? 0.0f : 1.0f / in.mass[id];
     }
-    // incidences per internal node, sorted by (neighbour slot, spring id)
+    // incidences per internal node, sorted by (neighbour node id, spring id): on a grid cloth
+    // that is the order of the offsets (row, column) of the neighbours, the same for every
+    // node, so the stencil kernel sums in this order too
     std::vector<int> deg(N, 0);
     for (int s = 0; s < in.n_springs; ++s) {
         ++deg[out->slot[in.ends[2 * s]]];
@@ -241,12 +285,19 @@ int build_cloth_host(const ClothHostInput& in, ClothHost* out, const std::vector
     }
     std::vector<int> start(N + 1, 0);
     for (int p = 0; p < N; ++p) start[p + 1] = start[p] + deg[p];
-    std::vector<std::pair<long long, int>> inc(start[N]);  // (nbr slot << 32 | spring, code)
+    struct Inc {
+        long long key;  // neighbour id << 32 | spring
+        int nbr;        // neighbour slot
+        int code;       // spring, ~spring at its second end
+        bool operator<(const Inc& o) const { return key < o.key; }
+    };
+    std::vector<Inc> inc(start[N]);
     std::vector<int> fill(N, 0);
     for (int s = 0; s < in.n_springs; ++s) {
-        const int pa = out->slot[in.ends[2 * s]], pb = out->slot[in.ends[2 * s + 1]];
-        inc[start[pa] + fill[pa]++] = {((long long)pb << 32) | (unsigned)s, s};
-        inc[start[pb] + fill[pb]++] = {((long long)pa << 32) | (unsigned)s, ~s};
+        const int ia = in.ends[2 * s], ib = in.ends[2 * s + 1];
+        const int pa = out->slot[ia], pb = out->slot[ib];
+        inc[start[pa] + fill[pa]++] = {((long long)ib << 32) | (unsigned)s, pb, s};
+        inc[start[pb] + fill[pb]++] = {((long long)ia << 32) | (unsigned)s, pa, ~s};
     }
     for (int p = 0; p < N; ++p) std::sort(inc.begin() + start[p], inc.begin() + start[p + 1]);
     const int n_slices = (N + 63) / 64;
@@ -265,8 +316,8 @@ int build_cloth_host(const ClothHostInput& in, ClothHost* out, const std::vector
         for (int r = 0; r < deg[p]; ++r) {
             const auto& e = inc[start[p] + r];
             const size_t q = base + (size_t)r * 64;
-            out->nbr[q] = (int)(e.first >> 32);
-            out->inc_spring[q] = e.second;
+            out->nbr[q] = e.nbr;
+            out->inc_spring[q] = e.code;
         }
         // padding slots point at the node itself and at spring 0 (never read)
         for (int r = deg[p]; r < (out->slice_ptr[(p >> 6) + 1] - out->slice_ptr[p >> 6]) / 64; ++r)
@@ -324,9 +375,11 @@ int upload_cloth(const ClothHost& h, DeviceArena& arena, hipStream_t stream, Clo
     if ((e = arena.alloc(&d->w, (size_t)N)) || (e = arena.alloc(&d->deg, (size_t)N)) ||
         (e = arena.alloc(&d->slice_ptr, h.slice_ptr.size())) || (e = arena.alloc(&d->inc2, M)) ||
         (e = arena.alloc(&d->inc_spring, M)) || (e = arena.alloc(&d->ptab, std::max<size_t>(S, 1))) ||
-        (e = arena.alloc(&d->spring_entry, std::max<size_t>(S, 1))))
+        (e = arena.alloc(&d->spring_entry, std::max<size_t>(S, 1))) ||
+        (e = arena.alloc(&d->n_tab, 1)))
         return hip_fail(e, "hipMalloc cloth arrays");
     std::vector<uint2> inc2(M);
+    const int n_tab = (int)h.ptab.size();
     StreamFence fence{stream};
     for (size_t q = 0; q < M; ++q) {
         const int code = h.inc_spring[q];
@@ -347,6 +400,7 @@ int upload_cloth(const ClothHost& h, DeviceArena& arena, hipStream_t stream, Clo
         {d->inc_spring, h.inc_spring.data(), M * 4},
         {d->ptab, h.ptab.data(), h.ptab.size() * sizeof(float4)},
         {d->spring_entry, h.spring_entry.data(), S * 4},
+        {d->n_tab, &n_tab, sizeof(int)},
     };
     for (auto& c : cps)
         if (c.bytes)
@@ -357,6 +411,17 @@ int upload_cloth(const ClothHost& h, DeviceArena& arena, hipStream_t stream, Clo
     if ((e = hipStreamSynchronize(stream))) return hip_fail(e, "upload cloth");
     d->cur = 0;
     return CLOTH_OK;
+}
+
+GridView ClothDevice::grid_view() const {
+    GridView g;
+    g.n_tiles = n_tiles;
+    g.one = one_cloth;
+    g.tiles = tiles;
+    g.idx = sten_idx;
+    g.n_tab = this->n_tab;
+    g.tab_cap = std::max(n_springs, 1);
+    return g;
 }
 
 ClothView ClothDevice::view() const {
@@ -391,7 +456,14 @@ int upload_param_table(const std::vector<float4>& tab, const std::vector<int>& e
         if (plan_rec && n_plan &&
             (e = launch_set_entries(n_plan, plan_sid, 0, d->spring_entry, plan_rec, stream)))
             return hip_fail(e, "re-point tile records");
+        if (d->sten_code &&
+            (e = launch_set_stencil_entries((size_t)kStencilDirs * d->ld, d->sten_code,
+                                            d->spring_entry, d->sten_idx, stream)))
+            return hip_fail(e, "re-point stencil entries");
     }
+    const int n_tab = (int)tab.size();
+    if ((e = hipMemcpyAsync(d->n_tab, &n_tab, sizeof(int), hipMemcpyHostToDevice, stream)))
+        return hip_fail(e, "upload parameter table");
     // the host vectors are the copies' sources: finish before returning
     if ((e = hipStreamSynchronize(stream))) return hip_fail(e, "upload parameter table");
     return CLOTH_OK;

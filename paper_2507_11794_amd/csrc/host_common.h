@@ -95,6 +95,14 @@ struct ClothDevice {
     float4* ptab = nullptr;       // room for one entry per spring (at least one)
     int* spring_entry = nullptr;  // [springs]: re-points the records after a parameter update
     int n_springs = 0;
+    int* n_tab = nullptr;         // [1]: entries in ptab (read by the stencil kernel)
+    // grid stencil (build_stencil), when every cloth of the handle has one
+    int n_tiles = 0;
+    int4 one_cloth{};                // the cloth of a one-cloth handle (GridView::one)
+    int4* tiles = nullptr;           // [n_tiles] per-tile cloth (batches), else NULL
+    int* sten_code = nullptr;        // [kStencilDirs][ld] spring or -1
+    uint32_t* sten_idx = nullptr;    // [kStencilDirs][ld] ptab entry or kNoSpring
+    GridView grid_view() const;
     ClothView view() const;
 };
 
@@ -130,6 +138,17 @@ struct SurfaceDevice {
 };
 
 std::vector<int> tile_order(int nx, int ny);
+// The 8x8 tiles of an nx-by-ny grid as (column, row) tile coordinates, in slot order
+// (row by row).
+std::vector<std::pair<int, int>> tile_list(int nx, int ny);
+// One cloth of a handle, for build_stencil: grid shape, first node id, first internal slot,
+// first spring and spring count.
+struct StencilCloth {
+    int nx, ny, node_off, slot_off, spring_off, n_springs;
+};
+bool build_stencil(const std::vector<StencilCloth>& cloths, const std::vector<int>& ends,
+                   const std::vector<int>& slot, int ld, std::vector<int>* code,
+                   std::vector<int4>* tiles);
 int validate_cloth(const ClothHostInput& in);
 int validate_params(const cloth_params* p);
 void stability_bounds(const ClothHostInput& in, double* omega2, double* gamma);

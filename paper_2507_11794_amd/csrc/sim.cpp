@@ -14,7 +14,7 @@
 namespace cloth {
 
 int check_launch(const cloth_launch& c) {
-    if (c.kernel < CLOTH_KERNEL_TILE || c.kernel > CLOTH_KERNEL_LANES4)
+    if (c.kernel < CLOTH_KERNEL_TILE || c.kernel > CLOTH_KERNEL_GRID)
         return fail(CLOTH_EINVAL, "unknown kernel");
     if (c.block_threads < 64 || c.block_threads > 256 || (c.block_threads & 63))
         return fail(CLOTH_EINVAL, "block_threads must be 64, 128, 192 or 256");
@@ -126,6 +126,9 @@ int ensure_springs(cloth_sim* s) {
 int set_launch(cloth_sim* s, const cloth_launch& cfg) {
     int st = check_launch(cfg);
     if (st != CLOTH_OK) return st;
+    if (cfg.kernel == CLOTH_KERNEL_GRID && !s->dev.sten_code)
+        return fail(CLOTH_EINVAL, "the grid kernel needs grid cloths whose springs join nodes at "
+                                  "most two rows or columns apart (the stencil), one per offset");
     // until this call succeeds the plan may not match s->launch; the next run re-applies it
     s->launch_ready = false;
     if ((st = ensure_plan(s, cfg)) != CLOTH_OK) return st;
@@ -135,6 +138,7 @@ int set_launch(cloth_sim* s, const cloth_launch& cfg) {
     const size_t lds = cfg.kernel == CLOTH_KERNEL_TILE
                            ? tile_lds_bytes(s->plan.view.rmax, cfg.block_threads, slots)
                        : lanes_kernel ? (s->any_collision ? lanes_lds_bytes(cfg.block_threads, slots) : 0)
+                       : cfg.kernel == CLOTH_KERNEL_GRID ? grid_lds_bytes(slots)
                                       : (size_t)(cfg.block_threads / 64) * wave_query_lds(slots);
     if (lds > 160 * 1024)
         return fail(CLOTH_EINVAL, "tile region plus hit lists exceed 160 KiB of LDS");
@@ -152,6 +156,7 @@ int set_launch(cloth_sim* s, const cloth_launch& cfg) {
     hipError_t pe = cfg.kernel == CLOTH_KERNEL_TILE ? prepare_tile_kernels(lds)
                     : scatter                       ? prepare_scatter_kernels(lds)
                     : lanes_kernel                  ? prepare_lanes_kernels(lds)
+                    : cfg.kernel == CLOTH_KERNEL_GRID ? prepare_grid_kernels(lds)
                                                     : prepare_substep_kernels(lds);
     if (pe != hipSuccess) return hip_fail(pe, "kernel LDS attribute");
     cloth_launch norm = cfg;
@@ -159,6 +164,7 @@ int set_launch(cloth_sim* s, const cloth_launch& cfg) {
         norm.schedule = CLOTH_SCHED_GRID;
         norm.workgroups = 0;
     }
+    if (cfg.kernel == CLOTH_KERNEL_GRID) norm.block_threads = 64;  // one wavefront per tile
     if (cfg.kernel != CLOTH_KERNEL_DIRECT) norm.split_refs = 0;
     if (std::memcmp(&norm, &s->launch, sizeof(cloth_launch)) != 0) {
         // captured graphs hold the old configuration's kernels and arguments
@@ -197,6 +203,12 @@ hipError_t launch_once(cloth_sim* s, const StepParams& sp, int K, int src, hipSt
                                       s->launch.block_threads, st, s->svs_dev,
                                       s->groups.size() > 1 ? s->node_group_dev : nullptr,
                                       s->launch.hit_slots, s->launch.xcd_runs);
+    if (s->launch.kernel == CLOTH_KERNEL_GRID)
+        return launch_grid_substep(
+            s->dev.view(), s->dev.grid_view(),
+            s->groups.size() == 1 ? s->surfs[0].view.n_tris > 0 : s->any_collision, sp,
+            s->dev.x[src], s->dev.v[src], s->dev.x[dst], s->dev.v[dst], st, s->svs_dev,
+            s->groups.size() > 1, s->launch.hit_slots, s->launch.xcd_runs);
     if (s->launch.kernel == CLOTH_KERNEL_LANES2 || s->launch.kernel == CLOTH_KERNEL_LANES4)
         return launch_substep_lanes(
             s->launch.kernel == CLOTH_KERNEL_LANES2 ? 2 : 4, s->dev.view(),
@@ -392,6 +404,41 @@ int read_state_range(const cloth_sim* s, int group, float* x_out, float* v_out) 
     return CLOTH_OK;
 }
 
+// The grid stencil of the handle's cloths (build_stencil), on the device, when they have
+// one; otherwise the grid kernel stays unavailable.
+int build_stencil_device(cloth_sim* s) {
+    std::vector<StencilCloth> sc;
+    for (const GroupInfo& g : s->groups)
+        sc.push_back(StencilCloth{g.nx, g.ny, g.node_off, g.slot_off, g.spring_off, g.n_springs});
+    std::vector<int> code;
+    std::vector<int4> tiles;
+    if (!build_stencil(sc, s->ends, s->host.slot, s->dev.ld, &code, &tiles)) return CLOTH_OK;
+    const size_t m = code.size();
+    std::vector<uint32_t> idx(m);
+    for (size_t q = 0; q < m; ++q)
+        idx[q] = code[q] >= 0 ? (uint32_t)s->host.spring_entry[code[q]] : kNoSpring;
+    ClothDevice& d = s->dev;
+    StreamFence fence{s->stream};
+    hipError_t e;
+    int *dc = nullptr;
+    uint32_t* di = nullptr;
+    int4* dt = nullptr;
+    if ((e = s->arena.alloc(&dc, m)) || (e = s->arena.alloc(&di, m)) ||
+        (s->groups.size() > 1 && (e = s->arena.alloc(&dt, tiles.size()))) ||
+        (e = hipMemcpyAsync(dc, code.data(), 4 * m, hipMemcpyHostToDevice, s->stream)) ||
+        (e = hipMemcpyAsync(di, idx.data(), 4 * m, hipMemcpyHostToDevice, s->stream)) ||
+        (dt && (e = hipMemcpyAsync(dt, tiles.data(), tiles.size() * sizeof(int4),
+                                   hipMemcpyHostToDevice, s->stream))) ||
+        (e = hipStreamSynchronize(s->stream)))
+        return hip_fail(e, "grid stencil");
+    d.sten_code = dc;
+    d.sten_idx = di;
+    d.tiles = dt;
+    d.n_tiles = (int)tiles.size();
+    d.one_cloth = tiles.empty() ? int4{} : tiles[0];
+    return CLOTH_OK;
+}
+
 int create_sim(const std::vector<ClothHostInput>& cloths, const cloth_params* p,
                hipStream_t stream, cloth_sim** out) {
     *out = nullptr;
@@ -507,6 +554,7 @@ int create_sim(const std::vector<ClothHostInput>& cloths, const cloth_params* p,
                                     s->stream)))
                 st = hip_fail(e, "create");
         }
+        if (st == CLOTH_OK) st = build_stencil_device(s);
         if (st == CLOTH_OK && (p->flags & CLOTH_F_NARROW_MT) && s->any_collision) {
             s->mt = true;
             if ((e = s->arena.alloc(&s->mt_pred, 6 * ld))) st = hip_fail(e, "create");

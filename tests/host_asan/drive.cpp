@@ -108,7 +108,8 @@ void plain_paths() {
         {CLOTH_KERNEL_SCATTER_FIX, 256, 1, 256, 0, 0, 0, 0, 0, 0},
         {CLOTH_KERNEL_SCATTER_F32, 256, 1, 64, 1, 0, 0, 8, 1, 0},
         {CLOTH_KERNEL_LANES4, 256, 1, 64, 1, 0, 0, 8, 0, 0},
-        {CLOTH_KERNEL_LANES2, 256, 1, 256, 0, 0, 0, 0, 3, 0}};
+        {CLOTH_KERNEL_LANES2, 256, 1, 256, 0, 0, 0, 0, 3, 0},
+        {CLOTH_KERNEL_GRID, 256, 1, 64, 1, 0, 0, 32, 2, 0}};
     for (const cloth_launch& c : cfgs) {
         expect(cloth_set_launch(s, &c), CLOTH_OK, "set launch");
         expect(cloth_step(s, dt, 4, 9), CLOTH_OK, "step");

@@ -196,6 +196,16 @@ size_t lanes_lds_bytes(int block, int hit_slots) {
     return (size_t)(block / 64) * ((size_t)(hit_slots + 1) * 256 + 5 * 1024);
 }
 hipError_t prepare_lanes_kernels(size_t) { return hipSuccess; }
+hipError_t launch_grid_substep(const ClothView&, const GridView&, int, const StepParams&,
+                               const float*, const float*, float*, float*, hipStream_t,
+                               const SurfaceView*, int, int, int, float*) {
+    return hipSuccess;
+}
+hipError_t prepare_grid_kernels(size_t) { return hipSuccess; }
+size_t grid_lds_bytes(int hit_slots) { return (size_t)(hit_slots + 1) * 256; }
+hipError_t launch_set_stencil_entries(size_t, const int*, const int*, uint32_t*, hipStream_t) {
+    return hipSuccess;
+}
 hipError_t launch_import(int, int, const int*, const float*, float*, int, hipStream_t) {
     return hipSuccess;
 }

@@ -46,6 +46,8 @@ SCHEDULES = [
          schedule=B.CLOTH_SCHED_RR, workgroups=7, use_graph=0),
     dict(kernel=B.CLOTH_KERNEL_LANES4, block_threads=64, hit_slots=8),
     dict(kernel=B.CLOTH_KERNEL_LANES2, block_threads=256, hit_slots=4, xcd_runs=2),
+    dict(kernel=B.CLOTH_KERNEL_GRID),
+    dict(kernel=B.CLOTH_KERNEL_GRID, hit_slots=4, xcd_runs=2),
 ]
 
 
@@ -70,7 +72,8 @@ def test_autotune_picks_a_valid_configuration_without_changing_results():
         ref.step(n_steps=10)
         best = b.autotune(frames=2)
         assert best["kernel"] in (B.CLOTH_KERNEL_TILE, B.CLOTH_KERNEL_DIRECT,
-                                  B.CLOTH_KERNEL_LANES2, B.CLOTH_KERNEL_LANES4)
+                                  B.CLOTH_KERNEL_LANES2, B.CLOTH_KERNEL_LANES4,
+                                  B.CLOTH_KERNEL_GRID)
         assert b.get_launch() == best
         b.step(n_steps=15)
         ref.step(n_steps=15)

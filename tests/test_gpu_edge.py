@@ -119,10 +119,58 @@ def test_every_spring_with_its_own_parameters():
     assert contacts > 0
     outs = []
     for kernel in (B.CLOTH_KERNEL_DIRECT, B.CLOTH_KERNEL_TILE, B.CLOTH_KERNEL_LANES2,
-                   B.CLOTH_KERNEL_LANES4):
+                   B.CLOTH_KERNEL_LANES4, B.CLOTH_KERNEL_GRID):
         with B.Cloth(inp) as sim:
             sim.set_launch(kernel=kernel)
             sim.step(n_steps=25)
             outs.append(sim.read_state())
     for x, v in outs[1:]:
         assert np.array_equal(outs[0][0], x) and np.array_equal(outs[0][1], v)
+
+
+@pytest.mark.parametrize("shape", [(1, 37), (37, 1), (2, 2), (3, 5), (9, 17), (65, 3), (20, 20)])
+def test_grid_kernel_on_ragged_shapes_equals_the_one_thread_kernel(shape):
+    """The stencil kernel on cloths whose sides are not multiples of the 8x8 tile (narrow
+    last tile columns, short last tile rows, one-node-wide strips), over the floor triangle
+    with a pinned corner: the same bits as the one-thread-per-node kernel after every frame,
+    and its node order is the grid's tiles row by row."""
+    nx, ny = shape
+    inp = _scene(nx, ny, drop=0.012, spacing=0.008, pins=[(0, 0)], n_steps=30)
+    outs = []
+    for kernel in (B.CLOTH_KERNEL_DIRECT, B.CLOTH_KERNEL_GRID):
+        with B.Cloth(inp) as sim:
+            sim.set_launch(kernel=kernel)
+            states = []
+            for _ in range(inp.n_steps):
+                sim.step(n_steps=1)
+                states.append(sim.read_state())
+            order = sim.node_order()
+        outs.append(states)
+    for (xa, va), (xb, vb) in zip(*outs):
+        assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+    want = [i * nx + j for tj in range(0, ny, 8) for ti in range(0, nx, 8)
+            for i in range(tj, min(ny, tj + 8)) for j in range(ti, min(nx, ti + 8))]
+    assert np.array_equal(order, want)
+
+
+def test_grid_kernel_refused_for_springs_off_the_stencil():
+    """A spring three columns long, or a second spring between the same two nodes, leaves
+    the grid stencil: the grid kernel is refused (CLOTH_EINVAL) and the other kernels run."""
+    base = _scene(6, 6, drop=0.02, n_steps=5)
+    long_spring = dataclasses.replace(
+        base, ends=np.concatenate([base.ends, [[0, 3]]]).astype(np.int32),
+        rest=np.append(base.rest, np.float32(0.03)), k=np.append(base.k, np.float32(50.0)),
+        c=np.append(base.c, np.float32(0.05)))
+    doubled = dataclasses.replace(
+        base, ends=np.concatenate([base.ends, base.ends[:1]]).astype(np.int32),
+        rest=np.append(base.rest, base.rest[0]), k=np.append(base.k, base.k[0]),
+        c=np.append(base.c, base.c[0]))
+    for inp in (long_spring, doubled):
+        with B.Cloth(inp) as sim:
+            with pytest.raises(B.ClothError) as ei:
+                sim.set_launch(kernel=B.CLOTH_KERNEL_GRID)
+            assert ei.value.status == B.CLOTH_EINVAL
+            sim.step(n_steps=5)
+    with B.Cloth(base) as sim:
+        sim.set_launch(kernel=B.CLOTH_KERNEL_GRID)
+        sim.step(n_steps=5)

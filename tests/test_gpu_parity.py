@@ -265,6 +265,9 @@ LAUNCHES = [
     dict(kernel=B.CLOTH_KERNEL_LANES4, block_threads=64, use_graph=1, hit_slots=8),
     dict(kernel=B.CLOTH_KERNEL_LANES4, block_threads=128, use_graph=1, hit_slots=1),
     dict(kernel=B.CLOTH_KERNEL_LANES4, block_threads=256, use_graph=0, hit_slots=0, xcd_runs=1),
+    dict(kernel=B.CLOTH_KERNEL_GRID, use_graph=1),
+    dict(kernel=B.CLOTH_KERNEL_GRID, use_graph=0, hit_slots=0),
+    dict(kernel=B.CLOTH_KERNEL_GRID, use_graph=1, hit_slots=4, xcd_runs=3),
 ]
 
 
@@ -340,7 +343,9 @@ def test_sliver_triangles_listed_and_unlisted_queries_agree():
     for cfg in (dict(), dict(hit_slots=0), dict(hit_slots=64, block_threads=256),
                 dict(kernel=B.CLOTH_KERNEL_LANES4, hit_slots=8, block_threads=64),
                 dict(kernel=B.CLOTH_KERNEL_LANES2, hit_slots=2, block_threads=128),
-                dict(kernel=B.CLOTH_KERNEL_LANES4, hit_slots=0, block_threads=64)):
+                dict(kernel=B.CLOTH_KERNEL_LANES4, hit_slots=0, block_threads=64),
+                dict(kernel=B.CLOTH_KERNEL_GRID, hit_slots=64),
+                dict(kernel=B.CLOTH_KERNEL_GRID, hit_slots=2)):
         with B.Cloth(inp) as sim:
             if cfg:
                 sim.set_launch(**cfg)
