@@ -115,6 +115,13 @@ def median_window(windows):
     return windows[order[len(order) // 2]]
 
 
+KERNEL_NAMES = {0: "k_tile", 1: "k_substep", 4: "k_lanes<2>", 5: "k_lanes<4>", 6: "k_grid"}
+
+
+def kernel_name(launch: dict) -> str:
+    return KERNEL_NAMES.get(launch.get("kernel"), "kernel %d" % launch.get("kernel", -1))
+
+
 def roofline(kernel: str, bytes_per_launch: float, launch_s: float, launch=None, traffic=None):
     achieved = bytes_per_launch / launch_s / 1e9
     out = {"kernel": kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -224,6 +231,7 @@ def bench_adjoint(frames: int = 200):
     stream = torch.cuda.current_stream()
     sim = cloth.Cloth(inp, stream=stream.cuda_stream)
     sim2 = cloth.Cloth(inp, stream=stream.cuda_stream)
+    fwd_kernel = kernel_name(sim2.get_launch())
     sim2.step(n_steps=frames)  # untimed: graph capture
     sim2.write_state(inp.x0, inp.v0)
     sim2.step(n_steps=frames // 2)
@@ -266,7 +274,7 @@ def bench_adjoint(frames: int = 200):
             "forward_backward_node_updates_per_s": upd / t_grad,
             "gradient_cost_vs_plain": t_grad / t_plain,
             "plain_forward_roofline": roofline(
-                "k_substep (64x64 cloth: 64 wavefronts, latency-bound)",
+                f"{fwd_kernel} (64x64 cloth: 64 wavefronts, latency-bound)",
                 algorithmic_bytes_per_substep(inp.n_nodes, inp.n_springs) + coll,
                 plain_ms * 1e-3 / n_sub),
             "gradient_roofline": roofline(
@@ -360,8 +368,8 @@ def bench_mt(frames: int = 30):
             "node_updates_per_s": inp.n_nodes * inp.n_substeps * frames / wall}
 
 
-FORCES_AB = ["kernel=direct", "kernel=tile,tile=256,K=1,block=256", "kernel=tile,tile=256,K=4,block=256",
-             "kernel=scatter_f32", "kernel=scatter_fix"]
+FORCES_AB = ["kernel=direct", "kernel=grid", "kernel=tile,tile=256,K=1,block=256",
+             "kernel=tile,tile=256,K=4,block=256", "kernel=scatter_f32", "kernel=scatter_fix"]
 
 
 def bench_forces_ab(frames: int = 40):
@@ -393,7 +401,7 @@ def bench_forces_ab(frames: int = 40):
     K = default["substeps_per_launch"] if default["kernel"] == cloth.CLOTH_KERNEL_TILE else 1
     launch_s = ms * 1e-3 / (frames * inp.n_substeps / K)
     out["roofline"] = roofline(
-        "k_tile (default launch without a surface)",
+        f"{kernel_name(default)} (default launch without a surface)",
         algorithmic_bytes_per_substep(inp.n_nodes, inp.n_springs) * K, launch_s, default)
     return out
 
@@ -451,7 +459,7 @@ def sources_sha256() -> str:
 def counter_traffic(launch: dict):
     """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE counter summary, if it
     was taken on these kernel sources with this launch configuration; else None."""
-    path = os.path.join(ROOT, "profiles", "k_substep_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel_name(launch)}_traffic.json")
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
@@ -607,9 +615,9 @@ def main():
             "collision_query": {"start": vol0, "end": vol1},
         },
         "roofline": roofline(
-            "k_tile (K substeps of fused forces, integration, broad and narrow phase per launch)"
-            if launch["kernel"] == cloth.CLOTH_KERNEL_TILE
-            else "k_substep (fused forces, integration, broad and narrow phase)",
+            f"{kernel_name(launch)} (K substeps of fused forces, integration, broad and narrow "
+            "phase per launch)" if launch["kernel"] == cloth.CLOTH_KERNEL_TILE
+            else f"{kernel_name(launch)} (fused forces, integration, broad and narrow phase)",
             per_sub * K, kernel_s, launch, counter_traffic(launch)),
     }
     out["roofline"]["bytes_per_node_update"] = per_sub / inp.n_nodes

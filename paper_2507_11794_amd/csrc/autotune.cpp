@@ -86,8 +86,14 @@ void cache_store(const std::string& key, const cloth_launch& c) {
       << c.hit_slots << ' ' << c.xcd_runs << ' ' << c.split_refs << '\n';
 }
 
-std::vector<cloth_launch> candidates(int cus, bool collide) {
+std::vector<cloth_launch> candidates(int cus, bool collide, bool grid) {
     std::vector<cloth_launch> v;
+    if (grid)  // the grid-stencil kernel (one wavefront per 8x8 tile)
+        for (int st : {0, 16, 32})
+            for (int xr : {0, 1, 2, 16}) {
+                if (!collide && st) continue;
+                v.push_back({CLOTH_KERNEL_GRID, 256, 1, 64, 1, CLOTH_SCHED_GRID, 0, st, xr, 0});
+            }
     const int stages[] = {0, 32};
     for (int st : stages) {
         if (!collide && st) continue;
@@ -159,7 +165,7 @@ int autotune_sim(cloth_sim* s, float dt, int n_substeps, int frames, cloth_launc
     float best_ms = 0.0f;
     bool have = false;
     if ((e = copy_state(true))) st = hip_fail(e, "autotune save");
-    for (const cloth_launch& c : candidates(cus, s->any_collision != 0)) {
+    for (const cloth_launch& c : candidates(cus, s->any_collision != 0, s->dev.sten_code != nullptr)) {
         if (st != CLOTH_OK) break;
         if (set_launch(s, c) != CLOTH_OK) continue;  // e.g. a region too large for LDS
         // an untimed run of the timed length captures every graph the timed runs replay;

@@ -520,8 +520,8 @@ int create_sim(const std::vector<ClothHostInput>& cloths, const cloth_params* p,
             if (st == CLOTH_OK && s->surfs[g].view.n_tris > 0) s->any_collision = 1;
         }
         if (!s->any_collision) {
-            // without collision the spring pass dominates, and the tile kernel's LDS gather
-            // is the faster default (30 against 47 us per substep on the 800x800 cloth)
+            // without collision the spring pass dominates, and for spring graphs off the grid
+            // stencil the tile kernel's LDS gather is the faster default
             s->launch.kernel = CLOTH_KERNEL_TILE;
             s->launch.block_threads = 256;
         }
@@ -555,6 +555,13 @@ int create_sim(const std::vector<ClothHostInput>& cloths, const cloth_params* p,
                 st = hip_fail(e, "create");
         }
         if (st == CLOTH_OK) st = build_stencil_device(s);
+        if (st == CLOTH_OK && s->dev.sten_code) {
+            // grid cloths: the stencil kernel is the faster default with a surface (16 against
+            // 18 us per substep on the 316x316 workload) and without one (22 against 27 us for
+            // the tile kernel on the 800x800 cloth)
+            s->launch.kernel = CLOTH_KERNEL_GRID;
+            s->launch.block_threads = 64;
+        }
         if (st == CLOTH_OK && (p->flags & CLOTH_F_NARROW_MT) && s->any_collision) {
             s->mt = true;
             if ((e = s->arena.alloc(&s->mt_pred, 6 * ld))) st = hip_fail(e, "create");

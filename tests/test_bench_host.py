@@ -61,7 +61,10 @@ def test_parse_launch():
 
 
 def test_counter_traffic_is_reported_only_for_matching_sources_and_launch(monkeypatch):
-    rec = json.load(open(os.path.join(ROOT, "profiles", "k_substep_traffic.json")))
+    import glob
+    paths = sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.json")))
+    assert paths
+    rec = json.load(open(paths[0]))
     launch = dict(rec["launch"])
     monkeypatch.setattr(bench, "sources_sha256", lambda: rec["sources_sha256"])
     assert bench.counter_traffic(launch) == rec["traffic_bytes_per_launch"]

@@ -292,15 +292,16 @@ def test_every_launch_configuration_is_bit_identical(scene):
     assert moved > 0.01
 
 
-@pytest.mark.parametrize("kernel", [B.CLOTH_KERNEL_DIRECT, B.CLOTH_KERNEL_TILE])
+@pytest.mark.parametrize("kernel", [B.CLOTH_KERNEL_GRID, B.CLOTH_KERNEL_DIRECT,
+                                    B.CLOTH_KERNEL_TILE])
 def test_default_and_tile_kernels_match_oracle_one_substep(kernel):
     inp = W.config1(n=96, freq=24)
     model = oracle.Model.from_inputs(inp)
     with B.Cloth(inp) as sim:
-        if kernel == B.CLOTH_KERNEL_DIRECT:
-            assert sim.get_launch()["kernel"] == B.CLOTH_KERNEL_DIRECT  # the default
+        if kernel == B.CLOTH_KERNEL_GRID:
+            assert sim.get_launch()["kernel"] == B.CLOTH_KERNEL_GRID  # the default
         else:
-            sim.set_launch(kernel=kernel, block_threads=256)
+            sim.set_launch(kernel=kernel, block_threads=256 if kernel == B.CLOTH_KERNEL_TILE else 64)
         sim.step(n_steps=120)
         for _ in range(3):
             x, v = sim.read_state()
@@ -363,18 +364,25 @@ def test_sliver_triangles_listed_and_unlisted_queries_agree():
     assert r["contacts"] > 50
 
 
-def test_no_collision_default_is_the_tile_kernel_and_matches_direct():
+def test_no_collision_defaults_match_direct():
+    """Without a surface a grid cloth defaults to the stencil kernel and any other spring
+    graph to the tile kernel; both give the one-thread kernel's bits."""
     inp = W.config0(n=48, n_steps=20)
-    outs = []
-    for cfg in (None, dict(kernel=B.CLOTH_KERNEL_DIRECT, block_threads=64)):
-        with B.Cloth(inp) as sim:
-            if cfg is None:
-                assert sim.get_launch()["kernel"] == B.CLOTH_KERNEL_TILE
-            else:
-                sim.set_launch(**cfg)
-            sim.step(n_steps=inp.n_steps)
-            outs.append(sim.read_state())
-    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    off = dataclasses.replace(inp, ends=np.concatenate([inp.ends, [[0, 47]]]).astype(np.int32),
+                              rest=np.append(inp.rest, np.float32(0.47)),
+                              k=np.append(inp.k, np.float32(1.0)),
+                              c=np.append(inp.c, np.float32(0.0)))
+    for scene, default in ((inp, B.CLOTH_KERNEL_GRID), (off, B.CLOTH_KERNEL_TILE)):
+        outs = []
+        for cfg in (None, dict(kernel=B.CLOTH_KERNEL_DIRECT, block_threads=64)):
+            with B.Cloth(scene) as sim:
+                if cfg is None:
+                    assert sim.get_launch()["kernel"] == default
+                else:
+                    sim.set_launch(**cfg)
+                sim.step(n_steps=scene.n_steps)
+                outs.append(sim.read_state())
+        assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
 def test_query_volume_counts_match_the_fp32_brute_force():
