@@ -109,8 +109,8 @@ typedef struct cloth_launch {
     int schedule;            /* tile kernel: enum cloth_schedule */
     int workgroups;          /* persistent schedules: number of workgroups (> 0) */
     int hit_slots;           /* collision query: box hits each node lists in LDS before
-                                their geometry is loaded (twelve per round), 0..64; 0 = no
-                                list (hits resolved per round of sixteen references); a node
+                                their geometry is loaded (eight per round), 0..64; 0 = no
+                                list (hits resolved per round of eight references); a node
                                 with more hits than slots takes the no-list path (same
                                 contacts, same order).  LDS: (hit_slots + 1) * 256 bytes per
                                 64 threads. */

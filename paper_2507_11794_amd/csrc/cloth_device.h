@@ -324,8 +324,8 @@ __device__ __forceinline__ int narrow_mask(const SurfaceView& sv, unsigned long 
 // position p: candidates are the listed triangles whose inflated box holds p (ascending
 // id); a candidate is a contact iff the point-triangle distance is < thickness, and
 // visit(n, s, t) is then called with the triangle's unit normal n, the signed plane distance
-// s = (p - A).n and the triangle id t.  Reference boxes are loaded RR (<= 16) at a time
-// (the arrays carry sixteen entries of padding, so the loads need no bounds test).  Returns
+// s = (p - A).n and the triangle id t.  Reference boxes are loaded RR (<= kRefRound) at a time
+// (the arrays carry kRefRound entries of padding, so the loads need no bounds test).  Returns
 // the contact count.  NARROW = false stops after the broad phase: every candidate is visited (n
 // and s are zero) and counted.
 template <bool NARROW = true, int RR = kRefRound, class Visit>
@@ -402,7 +402,7 @@ __device__ __forceinline__ int collide(const SurfaceView& sv, float restitution,
 
 // a3 + a4 contact search with the box hits of the references [b, e) of p's cell collected
 // first (cx, cy, cz: p's point codes in that cell, see point_code): the coded reference
-// records are tested RR (<= 16) per round of loads, the triangle ids of hits
+// records are tested RR (<= kRefRound) per round of loads, the triangle ids of hits
 // go to this lane's list in LDS (list[k * 64], k < slots, plus a scratch entry k = slots:
 // every reference is written at the next free entry, or at the scratch entry once the list
 // is full, and only a hit advances the count), and the hits' geometry is then

@@ -148,8 +148,8 @@ hipError_t prepare_tile_kernels(size_t lds_bytes);
 // most kMaxHitSlots).  Reference boxes are tested kRefRound per round of loads.
 constexpr int kMaxHitSlots = 64;
 constexpr int kMaxXcdRuns = 4096;
-constexpr int kRefRound = 16;
-constexpr int kHitRound = 12;  // box hits whose geometry is loaded per round
+constexpr int kRefRound = 8;
+constexpr int kHitRound = 8;  // box hits whose geometry is loaded per round
 
 // Grid size of a one-thread-per-node launch of n_logical workgroups under xcd_runs (see
 // xcd_block): padded to a multiple of 8 * xcd_runs when xcd_runs >= 2.
