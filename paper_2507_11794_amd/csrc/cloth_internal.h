@@ -60,16 +60,21 @@ struct ClothView {
 // internal order (tiles row by row, nodes row-major in a tile).  A cloth is described by
 // (first slot, nx | ny << 16, first tile, cloth index): `one` for a handle of one cloth,
 // tiles[t] per tile for a batch.  idx[d * ld + p] is the parameter-table entry of the
-// spring from slot p in direction d, or kNoSpring; n_tab points at the table's current
-// entry count (kept on the device so captured graphs stay valid when parameters change);
-// tab_cap is the table's capacity.
+// spring from slot p in direction d, or kNoSpring; while the table has at most kSmallTab
+// entries, byte d % 4 of idx8[(d / 4) * ld + p] holds the same entry (kNoSpring8 for none),
+// a quarter of the bytes.  n_tab points at the table's current entry count (kept on the
+// device so captured graphs stay valid when parameters change); tab_cap is the table's
+// capacity.
 constexpr int kStencilDirs = 12;
 constexpr uint32_t kNoSpring = 0xffffffffu;
+constexpr uint32_t kNoSpring8 = 0xffu;
+constexpr int kSmallTab = 255;
 struct GridView {
     int n_tiles;
     int4 one;
     const int4* tiles;
     const uint32_t* idx;
+    const uint32_t* idx8;
     const int* n_tab;
     int tab_cap;
 };
@@ -192,9 +197,9 @@ hipError_t prepare_grid_kernels(size_t lds_bytes);
 // Dynamic LDS of a stencil launch (the hit lists of its one wavefront per workgroup).
 size_t grid_lds_bytes(int hit_slots);
 // Stencil parameter entries from per-spring entries: idx[q] = entry[code[q]], or kNoSpring
-// where code[q] < 0.
-hipError_t launch_set_stencil_entries(size_t m, const int* code, const int* entry,
-                                      uint32_t* idx, hipStream_t st);
+// where code[q] < 0, and their byte form in idx8 (q = d * ld + p, see GridView).
+hipError_t launch_set_stencil_entries(int ld, const int* code, const int* entry, uint32_t* idx,
+                                      uint32_t* idx8, hipStream_t st);
 hipError_t launch_substep_lanes(int lanes, const ClothView& cv, int collide, const StepParams& sp,
                                 const float* xs, const float* vs, float* xd, float* vd, int block,
                                 hipStream_t stream, const SurfaceView* svs, const int* node_group,

@@ -8,7 +8,8 @@
 //   1. each wavefront loads its tile and a two-node halo (12 x 12 nodes, both state vectors)
 //      into LDS with row-coalesced loads whose slots follow from the grid shape alone (no
 //      index loads first), together with its nodes' parameter-table entries per direction
-//      and, when the table is small, the table itself;
+//      (one byte each while the table has at most 255 entries) and, when the table is
+//      small, the table itself;
 //   2. each lane sums its node's springs from LDS in the incidence order (ascending
 //      neighbour id = ascending offset (row, column)), with the same spring_force
 //      arithmetic as every other kernel;
@@ -67,13 +68,11 @@ __global__ void __launch_bounds__(64, 2)
 
     // 1. every load of the gather in one round
     float w = 0.0f;
-    uint32_t idx[kStencilDirs];
-#pragma unroll
-    for (int d = 0; d < kStencilDirs; ++d) idx[d] = kNoSpring;
+    uint32_t idx8[kStencilDirs / 4] = {};
     if (active) {
         w = cv.w[i];
 #pragma unroll
-        for (int d = 0; d < kStencilDirs; ++d) idx[d] = gv.idx[(size_t)d * ld + i];
+        for (int k = 0; k < kStencilDirs / 4; ++k) idx8[k] = gv.idx8[(size_t)k * ld + i];
     }
     const int n_tab = *gv.n_tab;
     float4 tv0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), tv1 = tv0;
@@ -108,6 +107,21 @@ __global__ void __launch_bounds__(64, 2)
     tab[lane] = tv0;
     tab[lane + 64] = tv1;
     __syncthreads();
+
+    // the parameter entries of the node's springs: bytes while the table is small, else (a
+    // second round of loads) the full entries
+    uint32_t idx[kStencilDirs];
+    if (n_tab <= kSmallTab) {
+#pragma unroll
+        for (int d = 0; d < kStencilDirs; ++d) {
+            const uint32_t b = (idx8[d / 4] >> (8 * (d % 4))) & 0xffu;
+            idx[d] = active && b != kNoSpring8 ? b : kNoSpring;
+        }
+    } else {
+#pragma unroll
+        for (int d = 0; d < kStencilDirs; ++d)
+            idx[d] = active ? gv.idx[(size_t)d * ld + i] : kNoSpring;
+    }
 
     // 2. the springs of each node from LDS, in incidence order; 3. integration
     float px = 0.0f, py = 0.0f, pz = 0.0f, qx = 0.0f, qy = 0.0f, qz = 0.0f;
@@ -166,12 +180,24 @@ __global__ void __launch_bounds__(64, 2)
     }
 }
 
-__global__ void k_set_stencil_entries(size_t m, const int* __restrict__ code,
-                                      const int* __restrict__ entry, uint32_t* __restrict__ idx) {
-    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= m) return;
-    const int s = code[q];
-    idx[q] = s >= 0 ? (uint32_t)entry[s] : kNoSpring;
+// One thread per slot: its kStencilDirs entries, then their byte form (one word per four
+// directions).
+__global__ void k_set_stencil_entries(int ld, const int* __restrict__ code,
+                                      const int* __restrict__ entry, uint32_t* __restrict__ idx,
+                                      uint32_t* __restrict__ idx8) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= ld) return;
+    uint32_t word = 0;
+    for (int d = 0; d < kStencilDirs; ++d) {
+        const int s = code[(size_t)d * ld + p];
+        const uint32_t v = s >= 0 ? (uint32_t)entry[s] : kNoSpring;
+        idx[(size_t)d * ld + p] = v;
+        word |= (v == kNoSpring ? kNoSpring8 : (v & 0xffu)) << (8 * (d % 4));
+        if (d % 4 == 3) {
+            idx8[(size_t)(d / 4) * ld + p] = word;
+            word = 0;
+        }
+    }
 }
 
 }  // namespace
@@ -211,10 +237,10 @@ hipError_t launch_grid_substep(const ClothView& cv, const GridView& gv, int coll
     return hipGetLastError();
 }
 
-hipError_t launch_set_stencil_entries(size_t m, const int* code, const int* entry, uint32_t* idx,
-                                      hipStream_t st) {
-    if (m == 0) return hipSuccess;
-    k_set_stencil_entries<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(m, code, entry, idx);
+hipError_t launch_set_stencil_entries(int ld, const int* code, const int* entry, uint32_t* idx,
+                                      uint32_t* idx8, hipStream_t st) {
+    if (ld <= 0) return hipSuccess;
+    k_set_stencil_entries<<<(unsigned)((ld + 255) / 256), 256, 0, st>>>(ld, code, entry, idx, idx8);
     return hipGetLastError();
 }
 

@@ -419,6 +419,7 @@ GridView ClothDevice::grid_view() const {
     g.one = one_cloth;
     g.tiles = tiles;
     g.idx = sten_idx;
+    g.idx8 = sten_idx8;
     g.n_tab = this->n_tab;
     g.tab_cap = std::max(n_springs, 1);
     return g;
@@ -457,8 +458,8 @@ int upload_param_table(const std::vector<float4>& tab, const std::vector<int>& e
             (e = launch_set_entries(n_plan, plan_sid, 0, d->spring_entry, plan_rec, stream)))
             return hip_fail(e, "re-point tile records");
         if (d->sten_code &&
-            (e = launch_set_stencil_entries((size_t)kStencilDirs * d->ld, d->sten_code,
-                                            d->spring_entry, d->sten_idx, stream)))
+            (e = launch_set_stencil_entries(d->ld, d->sten_code, d->spring_entry, d->sten_idx,
+                                            d->sten_idx8, stream)))
             return hip_fail(e, "re-point stencil entries");
     }
     const int n_tab = (int)tab.size();

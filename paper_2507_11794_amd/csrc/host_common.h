@@ -102,6 +102,7 @@ struct ClothDevice {
     int4* tiles = nullptr;           // [n_tiles] per-tile cloth (batches), else NULL
     int* sten_code = nullptr;        // [kStencilDirs][ld] spring or -1
     uint32_t* sten_idx = nullptr;    // [kStencilDirs][ld] ptab entry or kNoSpring
+    uint32_t* sten_idx8 = nullptr;   // [kStencilDirs / 4][ld] the entries as bytes
     GridView grid_view() const;
     ClothView view() const;
 };

@@ -413,26 +413,33 @@ int build_stencil_device(cloth_sim* s) {
     std::vector<int> code;
     std::vector<int4> tiles;
     if (!build_stencil(sc, s->ends, s->host.slot, s->dev.ld, &code, &tiles)) return CLOTH_OK;
-    const size_t m = code.size();
-    std::vector<uint32_t> idx(m);
-    for (size_t q = 0; q < m; ++q)
+    const size_t m = code.size(), ld = (size_t)s->dev.ld;
+    std::vector<uint32_t> idx(m), idx8(m / 4, 0u);
+    for (size_t q = 0; q < m; ++q) {
         idx[q] = code[q] >= 0 ? (uint32_t)s->host.spring_entry[code[q]] : kNoSpring;
+        const size_t d = q / ld, p = q % ld;
+        const uint32_t b = idx[q] == kNoSpring ? kNoSpring8 : (idx[q] & 0xffu);
+        idx8[(d / 4) * ld + p] |= b << (8 * (d % 4));
+    }
     ClothDevice& d = s->dev;
     StreamFence fence{s->stream};
     hipError_t e;
     int *dc = nullptr;
-    uint32_t* di = nullptr;
+    uint32_t *di = nullptr, *di8 = nullptr;
     int4* dt = nullptr;
     if ((e = s->arena.alloc(&dc, m)) || (e = s->arena.alloc(&di, m)) ||
+        (e = s->arena.alloc(&di8, m / 4)) ||
         (s->groups.size() > 1 && (e = s->arena.alloc(&dt, tiles.size()))) ||
         (e = hipMemcpyAsync(dc, code.data(), 4 * m, hipMemcpyHostToDevice, s->stream)) ||
         (e = hipMemcpyAsync(di, idx.data(), 4 * m, hipMemcpyHostToDevice, s->stream)) ||
+        (e = hipMemcpyAsync(di8, idx8.data(), m, hipMemcpyHostToDevice, s->stream)) ||
         (dt && (e = hipMemcpyAsync(dt, tiles.data(), tiles.size() * sizeof(int4),
                                    hipMemcpyHostToDevice, s->stream))) ||
         (e = hipStreamSynchronize(s->stream)))
         return hip_fail(e, "grid stencil");
     d.sten_code = dc;
     d.sten_idx = di;
+    d.sten_idx8 = di8;
     d.tiles = dt;
     d.n_tiles = (int)tiles.size();
     d.one_cloth = tiles.empty() ? int4{} : tiles[0];
