@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint comparison")
     ap.add_argument("--batch-cloths", type=int, default=512)
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batched leg: skip the plain per-cloth comparison (and its collision "
+                         "bytes, counted on the plain handles)")
     ap.add_argument("--no-normals", action="store_true", help="skip the vertex-normal timing")
     ap.add_argument("--no-moving", action="store_true",
                     help="skip the moving-surface / pulled-cloth timing")
@@ -61,6 +64,8 @@ def parse():
                     help="skip the triangle-triangle narrow-phase timing")
     ap.add_argument("--no-forces-ab", action="store_true",
                     help="skip the 800x800 gather / scatter force-accumulation legs")
+    ap.add_argument("--only", choices=["forces", "batch", "adjoint", "moving", "mt"],
+                    help="run only this leg and print its JSON object (for profiling it)")
     return ap.parse_args()
 
 
@@ -134,7 +139,7 @@ def roofline(kernel: str, bytes_per_launch: float, launch_s: float, launch=None,
 
 # ------------------------------------------------------------------ legs
 
-def bench_batched(n_cloths: int, frames: int):
+def bench_batched(n_cloths: int, frames: int, plain: bool = True):
     """512 cloths of side U{16..128}, each over its own 5,120-triangle sphere: one batch handle
     (autotuned launch configuration) against plain per-cloth handles stepped one after another,
     both on this GPU, over the same frames from the same state (frame 100: every cloth is on
@@ -174,6 +179,14 @@ def bench_batched(n_cloths: int, frames: int):
     sample = (0, n_cloths // 2, n_cloths - 1)
     xb = [b.read_state(i)[0] for i in sample]
     b.close()
+    upd = n_nodes * sub * frames
+    K = tuned.get("substeps_per_launch", 1) if tuned.get("kernel") == cloth.CLOTH_KERNEL_TILE else 1
+    launch_s = gpu_ms * 1e-3 / (frames * sub / K)
+    if not plain:
+        return {"cloths": n_cloths, "nodes": n_nodes, "springs": n_springs, "frames": frames,
+                "first_timed_frame": first, "cell_size": cell,
+                "batched_node_updates_per_s": upd / t_batch, "launch": tuned,
+                "avg_launch_us": launch_s * 1e6}
     sims = [cloth.Cloth(dataclasses.replace(c, cell_size=cell), stream=stream.cuda_stream)
             for c in cl]
     for s_ in sims:
@@ -188,9 +201,6 @@ def bench_batched(n_cloths: int, frames: int):
     same = all(np.array_equal(sims[i].read_state()[0], x) for i, x in zip(sample, xb))
     for s_ in sims:
         s_.close()
-    upd = n_nodes * sub * frames
-    K = tuned.get("substeps_per_launch", 1) if tuned.get("kernel") == cloth.CLOTH_KERNEL_TILE else 1
-    launch_s = gpu_ms * 1e-3 / (frames * sub / K)
     per_sub = algorithmic_bytes_per_substep(n_nodes, n_springs) + coll
     return {"cloths": n_cloths, "nodes": n_nodes, "springs": n_springs, "frames": frames,
             "first_timed_frame": first, "cell_size": cell,
@@ -198,7 +208,9 @@ def bench_batched(n_cloths: int, frames: int):
             "plain_per_cloth_node_updates_per_s": upd / t_plain,
             "speedup": t_plain / t_batch, "launch": tuned,
             "collision_bytes_per_substep": coll,
-            "roofline": roofline("batched substep kernel (autotuned launch)", per_sub * K, launch_s),
+            "roofline": roofline(f"{kernel_name(tuned)} (512 cloths, autotuned launch)",
+                                 per_sub * K, launch_s, tuned,
+                                 counter_traffic(tuned, "batch512")),
             "bit_identical_sampled_cloths": bool(same)}
 
 
@@ -402,7 +414,8 @@ def bench_forces_ab(frames: int = 40):
     launch_s = ms * 1e-3 / (frames * inp.n_substeps / K)
     out["roofline"] = roofline(
         f"{kernel_name(default)} (default launch without a surface)",
-        algorithmic_bytes_per_substep(inp.n_nodes, inp.n_springs) * K, launch_s, default)
+        algorithmic_bytes_per_substep(inp.n_nodes, inp.n_springs) * K, launch_s, default,
+        counter_traffic(default, "cloth800_hanging"))
     return out
 
 
@@ -456,19 +469,24 @@ def sources_sha256() -> str:
     return h.hexdigest()
 
 
-def counter_traffic(launch: dict):
-    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE counter summary, if it
-    was taken on these kernel sources with this launch configuration; else None."""
-    path = os.path.join(ROOT, "profiles", f"{kernel_name(launch)}_traffic.json")
+def counter_traffic(launch: dict, workload: str):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE counter summary of this
+    workload's kernel, if it was taken on these kernel sources with this launch
+    configuration; else None."""
+    path = os.path.join(ROOT, "profiles", "counter_traffic.json")
     try:
-        rec = json.load(open(path))
+        recs = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if rec.get("sources_sha256") != sources_sha256():
-        return None
-    if any(launch.get(k) != v for k, v in rec.get("launch", {}).items()):
-        return None
-    return rec.get("traffic_bytes_per_launch")
+    for rec in recs:
+        if rec.get("workload") != workload or rec.get("kernel") != kernel_name(launch):
+            continue
+        if rec.get("sources_sha256") != sources_sha256():
+            continue
+        if any(launch.get(k) != v for k, v in rec.get("launch", {}).items()):
+            continue
+        return rec.get("traffic_bytes_per_launch")
+    return None
 
 
 # ------------------------------------------------------------------ CPU baseline
@@ -563,6 +581,12 @@ def main():
     torch.cuda.set_device(0)
     if args.calibrate_copy:
         return calibrate_copy(args.calibrate_copy)
+    if args.only:
+        leg = {"forces": bench_forces_ab, "batch": lambda: bench_batched(args.batch_cloths, 200, not args.no_plain),
+               "adjoint": lambda: bench_adjoint(200), "moving": bench_moving,
+               "mt": bench_mt}[args.only]
+        print(json.dumps({args.only: leg()}))
+        return 0
     inp = workloads.config1()
     stream = torch.cuda.current_stream()
     sim = cloth.Cloth(inp, stream=stream.cuda_stream)
@@ -618,7 +642,7 @@ def main():
             f"{kernel_name(launch)} (K substeps of fused forces, integration, broad and narrow "
             "phase per launch)" if launch["kernel"] == cloth.CLOTH_KERNEL_TILE
             else f"{kernel_name(launch)} (fused forces, integration, broad and narrow phase)",
-            per_sub * K, kernel_s, launch, counter_traffic(launch)),
+            per_sub * K, kernel_s, launch, counter_traffic(launch, "cloth316_sphere100k")),
     }
     out["roofline"]["bytes_per_node_update"] = per_sub / inp.n_nodes
     out["roofline"]["collision_bytes_per_substep"] = coll

@@ -192,14 +192,19 @@ int cloth_rollout_backward(cloth_sim* s, const float* gx_out_dev, float* gk_dev,
         // the segment's states and every substep's prediction (substep r of the segment
         // stores it at pred[r - 1]); the listed collision query, as the forward pass (any
         // launch gives the same bits)
+        const bool collide = s->surfs[0].view.n_tris > 0;
         for (long long r = 1; r <= top - base; ++r) {
             const float* xs = R.seg + (size_t)(r - 1) * state;
             float* xd = R.seg + (size_t)r * state;
-            if ((e = launch_substep(cv, s->surfs[0].view.n_tris > 0, sp, xs, xs + 3 * ld, xd,
-                                    xd + 3 * ld, 256, s->stream, s->svs_dev, nullptr,
-                                    s->launch.hit_slots, 0, 0, nullptr, 0,
-                                    R.pred + (size_t)(r - 1) * 3 * ld)))
-                return hip_fail(e, "recompute segment");
+            float* pr = R.pred + (size_t)(r - 1) * 3 * ld;
+            e = s->dev.sten_code
+                    ? launch_grid_substep(cv, s->dev.grid_view(), collide, sp, xs, xs + 3 * ld, xd,
+                                          xd + 3 * ld, s->stream, s->svs_dev, 0,
+                                          s->launch.hit_slots, 0, pr)
+                    : launch_substep(cv, collide, sp, xs, xs + 3 * ld, xd, xd + 3 * ld, 256,
+                                     s->stream, s->svs_dev, nullptr, s->launch.hit_slots, 0, 0,
+                                     nullptr, 0, pr);
+            if (e) return hip_fail(e, "recompute segment");
         }
         // (xb, vb) hold the adjoint of the state after substep top.  The node pass of
         // substep t needs the state before it, s[t - 1]; the spring pass of substep t and the

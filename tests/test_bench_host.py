@@ -60,18 +60,20 @@ def test_parse_launch():
     assert bench.parse_launch("") == {}
 
 
-def test_counter_traffic_is_reported_only_for_matching_sources_and_launch(monkeypatch):
-    import glob
-    paths = sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.json")))
-    assert paths
-    rec = json.load(open(paths[0]))
-    launch = dict(rec["launch"])
-    monkeypatch.setattr(bench, "sources_sha256", lambda: rec["sources_sha256"])
-    assert bench.counter_traffic(launch) == rec["traffic_bytes_per_launch"]
-    other = dict(launch, block_threads=launch["block_threads"] * 2)
-    assert bench.counter_traffic(other) is None
+def test_counter_traffic_is_reported_only_for_matching_sources_and_launch(monkeypatch, tmp_path):
+    rec = {"kernel": "k_grid", "workload": "cloth316_sphere100k", "sources_sha256": "a" * 64,
+           "launch": {"kernel": 6, "hit_slots": 32}, "traffic_bytes_per_launch": 123.0}
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "counter_traffic.json").write_text(json.dumps([rec]))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "sources_sha256", lambda: "a" * 64)
+    launch = {"kernel": 6, "hit_slots": 32, "block_threads": 64}
+    assert bench.counter_traffic(launch, "cloth316_sphere100k") == 123.0
+    assert bench.counter_traffic(launch, "batch512") is None
+    assert bench.counter_traffic(dict(launch, hit_slots=16), "cloth316_sphere100k") is None
+    assert bench.counter_traffic(dict(launch, kernel=1), "cloth316_sphere100k") is None
     monkeypatch.setattr(bench, "sources_sha256", lambda: "0" * 64)
-    assert bench.counter_traffic(launch) is None
+    assert bench.counter_traffic(launch, "cloth316_sphere100k") is None
 
 
 def test_sources_hash_follows_the_kernel_sources(tmp_path, monkeypatch):

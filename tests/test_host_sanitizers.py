@@ -18,7 +18,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2507_11794_amd", "csrc")
 HOST_SOURCES = [os.path.join(CSRC, f + ".cpp")
-                for f in ("sim", "host_build", "tiles", "autotune", "rollout", "batch")]
+                for f in ("sim", "host_build", "tiles", "autotune", "rollout")]
 TEST_SOURCES = [os.path.join(ROOT, "tests", "host_asan", f) for f in ("drive.cpp", "hip_stub.cpp")]
 FLAGS = ["-std=c++17", "-g", "-O1", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
          "-fno-sanitize-recover=undefined", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]
