@@ -13,9 +13,21 @@ import itertools
 
 import numpy as np
 
+# Bars of a one-substep comparison of an FP32 result with the FP64 oracle.  Positions: 1e-6
+# of the cloth's extent L per coordinate; an FP32 coordinate of a ~1 m cloth rounds to
+# ~6e-8 m, and the measured worst clean-node error on the 316x316 workload is 3.0e-8 L.  Velocities: 2e-5 m/s plus 1e-5 of the largest speed; the spring
+# force sums about twelve differences of FP32 positions, and h w F moves v by a few 1e-7 m/s
+# (measured worst 7.9e-7 m/s on the 316x316 workload, 5.9e-7 m/s on the 800x800 cloth),
+# while dropping a spring's damping for one substep moves it by h w c |dv| = 2e-2 |dv| at
+# the workloads' h, w, c, i.e. above the bar wherever neighbours' velocities differ by more
+# than about 1e-3 m/s.
+XTOL = 1e-6
+VTOL_ABS = 2e-5
+VTOL_REL = 1e-5
 
-def substep_parity(model, x, v, h, x1, v1, L, border=1e-6, xtol=2e-6, vtol_abs=2e-3,
-                   vtol_rel=1e-4, tag=""):
+
+def substep_parity(model, x, v, h, x1, v1, L, border=1e-6, xtol=XTOL, vtol_abs=VTOL_ABS,
+                   vtol_rel=VTOL_REL, tag=""):
     """Raises AssertionError on a mismatch; returns summary statistics.
 
     x, v: the state the device started from (FP32 arrays, [N,3]); x1, v1: the device's state
@@ -57,8 +69,8 @@ def substep_parity(model, x, v, h, x1, v1, L, border=1e-6, xtol=2e-6, vtol_abs=2
                 ev=float(ev[clean].max()) if clean.any() else 0.0)
 
 
-def resolve_contacts(model, x, v, h, x1, v1, L, border=1e-6, xtol=2e-6, vtol_abs=2e-3,
-                     vtol_rel=1e-4):
+def resolve_contacts(model, x, v, h, x1, v1, L, border=1e-6, xtol=XTOL, vtol_abs=VTOL_ABS,
+                     vtol_rel=VTOL_REL):
     """The contact set another implementation used in one substep from (x, v) to (x1, v1):
     per node, the oracle's sure contacts plus the subset of near-threshold triangles whose
     response reproduces (x1, v1).  Raises AssertionError if no valid set does."""
@@ -90,8 +102,8 @@ def resolve_contacts(model, x, v, h, x1, v1, L, border=1e-6, xtol=2e-6, vtol_abs
     return out
 
 
-def mt_substep_parity(model, nx, ny, x, v, h, x1, v1, L, border=2e-6, xtol=2e-6, vtol_abs=2e-3,
-                      vtol_rel=1e-4, tag=""):
+def mt_substep_parity(model, nx, ny, x, v, h, x1, v1, L, border=2e-6, xtol=XTOL,
+                      vtol_abs=VTOL_ABS, vtol_rel=VTOL_REL, tag=""):
     """substep_parity for the triangle-triangle narrow phase: nodes whose tests all lie at
     least ``border`` from a decision boundary must match the oracle's substep; the others
     must match the response to the sure contacts plus some subset of the near-boundary

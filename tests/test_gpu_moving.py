@@ -1,8 +1,8 @@
 """GPU moving surface (cloth_update_surface: per-frame grid rebuild) and external pull forces
 (cloth_set_external_force) against the FP64 oracle, plus bitwise identity of every launch
 configuration (graphs included) across surface updates, and batch == plain handles.
-Tolerances as in the other parity tests (one substep: 2e-6 of the cloth side, 2e-3 m/s plus
-1e-4 relative; near-threshold contacts resolved)."""
+Tolerances as in the other parity tests (one substep: 1e-6 of the cloth side, 2e-5 m/s plus
+1e-5 of the largest speed; near-threshold contacts resolved)."""
 import numpy as np
 import pytest
 

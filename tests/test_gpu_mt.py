@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle.parity import mt_substep_parity
+from oracle.parity import VTOL_ABS, VTOL_REL, XTOL, mt_substep_parity
 from paper_2507_11794_amd import cloth as B
 from paper_2507_11794_amd import workloads as W
 
@@ -144,7 +144,7 @@ def test_mt_full_size_sampled_contact_sets_and_substep():
         assert sure <= g <= sure | maybe, (int(i), sorted(g), sorted(sure), sorted(maybe))
         # the GPU's step with its own contact set equals the oracle's response to that set
         p, q = model.respond(xp[i], vp[i], sorted(g))
-        assert np.abs(p - x1[i]).max() <= 2e-6 * L, int(i)
-        assert np.abs(q - v1[i]).max() <= 2e-3 + 1e-4 * np.abs(vp).max(), int(i)
+        assert np.abs(p - x1[i]).max() <= XTOL * L, int(i)
+        assert np.abs(q - v1[i]).max() <= VTOL_ABS + VTOL_REL * np.abs(vp).max(), int(i)
         checked += bool(g)
     assert len(hit_nodes) > 100 and checked > 100

@@ -3,9 +3,10 @@ inputs.
 
 Tolerances.  FP32 rounds positions of ~1 m magnitude to ~6e-8 m; one substep moves a node by
 h v* with v* carrying the spring-force rounding (differences of FP32 positions, ~1e-7
-relative) divided by the node mass, so one-substep positions agree to a few ulps of the
-coordinates (bar: 2e-6 of the cloth side) and velocities to ~1e-4 m/s (bar: 2e-3 m/s plus
-1e-4 relative).  Over 100 frames of the collision-free hanging cloth the FP32 trajectory
+relative) scaled by h w, so one-substep positions agree to about an ulp of the coordinates
+(bar: 1e-6 of the cloth side; measured worst 3.0e-8 on the 316x316 workload) and velocities
+to a few 1e-7 m/s (bar: 2e-5 m/s plus 1e-5 of the largest speed; measured worst 7.9e-7 m/s),
+the bars of oracle/parity.py.  Over 100 frames of the collision-free hanging cloth the FP32 trajectory
 must stay within 1e-5 of the cloth side length.  A contact decision with |dist - th| within
 1e-6 m of the threshold may legitimately differ between FP32 and FP64; such nodes are
 checked against every valid resolution of their near-threshold triangles.

@@ -27,6 +27,20 @@ def test_accepts_oracle_result_and_rejects_perturbation():
         substep_parity(m, x, v, inp.h, x1, badv, L)
 
 
+def test_rejects_a_substep_that_drops_the_damping():
+    """The velocity bar is tight enough to see one substep taken without spring damping on
+    the draped scene (the step differs from the true one by h w c |dv| per spring)."""
+    inp = W.small_collision_scene(n=14, freq=5, drop=0.165, spacing=0.02)
+    m = oracle.Model.from_inputs(inp)
+    x, v = m.run(inp.x0, inp.v0, inp.h, 200)
+    x1, v1, _, _ = m.substep(x, v, inp.h)
+    undamped = oracle.Model.from_inputs(inp, c=np.zeros(inp.n_springs))
+    x1b, v1b, _, _ = undamped.substep(x, v, inp.h)
+    assert np.abs(v1b - v1).max() > 10 * 2e-5
+    with pytest.raises(AssertionError):
+        substep_parity(m, x, v, inp.h, x1b, v1b, 0.26)
+
+
 def test_near_threshold_contact_accepts_both_resolutions_only():
     verts = np.array([[0, 0, 0], [1, 0, 0], [1, 0, 1], [0, 0, 1]], dtype=np.float64)
     tris = np.array([[0, 2, 1], [0, 3, 2]])
