@@ -380,17 +380,18 @@ def bench_mt(frames: int = 30):
             "node_updates_per_s": inp.n_nodes * inp.n_substeps * frames / wall}
 
 
-FORCES_AB = ["kernel=direct", "kernel=grid", "kernel=tile,tile=256,K=1,block=256",
+FORCES_AB = ["kernel=direct", "kernel=grid", "kernel=grid,xcd=16", "kernel=tile,tile=256,K=1,block=256",
              "kernel=tile,tile=256,K=4,block=256", "kernel=scatter_f32", "kernel=scatter_fix"]
 
 
 def bench_forces_ab(frames: int = 40):
     """The 800x800 hanging cloth (640,000 nodes, 3.83M springs, no collision, so the spring
-    pass dominates): the node-centric gather (one launch per substep, and temporally blocked
-    tiles, the default for a handle without a surface) against Alg. 1's spring-centric
-    scatter with FP32 atomics and with int32 fixed-point atomics.  Microseconds per substep
-    from HIP events (median of 3 windows from the same state, graphs captured beforehand),
-    and the roofline of the default tile kernel."""
+    pass dominates): the node-centric gathers (one thread per node from the incidence lists;
+    the grid-stencil kernel, in the hardware's workgroup order and in chunks of 16 tiles per
+    XCD, its default; temporally blocked tiles) against Alg. 1's spring-centric scatter with
+    FP32 atomics and with int32 fixed-point atomics.  Microseconds per substep from HIP
+    events (median of 3 windows from the same state, graphs captured beforehand), and the
+    roofline of the default launch."""
     import torch
 
     from paper_2507_11794_amd import cloth, workloads
