@@ -109,13 +109,15 @@ typedef struct cloth_launch {
     int schedule;            /* tile kernel: enum cloth_schedule */
     int workgroups;          /* persistent schedules: number of workgroups (> 0) */
     int hit_slots;           /* collision query: box hits each node lists in LDS before
-                                their geometry is loaded (eight per round), 0..64; 0 = no
+                                their geometry is loaded (eight per round; four in the grid
+                                kernel when hit_slots <= 16), 0..64; 0 = no
                                 list (hits resolved per round of eight references); a node
                                 with more hits than slots takes the no-list path (same
                                 contacts, same order).  LDS: (hit_slots + 1) * 256 bytes per
                                 64 threads. */
-    int xcd_runs;            /* one-thread-per-node kernels, 0..4096: how workgroups (node
-                                ranges) map to the 8 XCDs, each with its own L2.  0 keeps
+    int xcd_runs;            /* one-thread-per-node and grid kernels, 0..4096: how
+                                workgroups (node ranges, tiles) map to the 8 XCDs, each with
+                                its own L2 (16 by default for grid cloths).  0 keeps
                                 the hardware's round-robin order; 1 gives each XCD one
                                 contiguous run; k >= 2 deals chunks of k consecutive
                                 workgroups to the XCDs in turn */

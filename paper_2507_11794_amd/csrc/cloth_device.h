@@ -502,7 +502,7 @@ __device__ __forceinline__ int listed_range(const SurfaceView& sv, uint32_t* lis
 }
 
 // listed_range over the whole cell of p (no candidates outside the grid).
-template <bool NARROW = true, class Visit>
+template <bool NARROW = true, int HR = kHitRound, class Visit>
 __device__ __forceinline__ int contacts_listed(const SurfaceView& sv, uint32_t* list, int slots,
                                                float px, float py, float pz, Visit&& visit) {
     const float gx = cell_coord_raw(px, sv.org[0], sv.inv_cell);
@@ -516,11 +516,13 @@ __device__ __forceinline__ int contacts_listed(const SurfaceView& sv, uint32_t* 
     const int cell = ((int)fz * sv.dim[1] + (int)fy) * sv.dim[0] + (int)fx;
     const uint32_t cx = point_code(gx, fx), cy = point_code(gy, fy), cz = point_code(gz, fz);
     const gptr<uint32_t> cs = gmem(sv.cell_start);
-    return listed_range<NARROW>(sv, list, slots, cx, cy, cz, cs[cell], cs[cell + 1], px, py, pz,
-                                visit);
+    return listed_range<NARROW, kRefRound, HR>(sv, list, slots, cx, cy, cz, cs[cell],
+                                               cs[cell + 1], px, py, pz, visit);
 }
 
-// collide_listed: contacts_listed with the averaged response.
+// collide_listed: contacts_listed with the averaged response (HR box hits per round of
+// geometry loads).
+template <int HR = kHitRound>
 __device__ __forceinline__ int collide_listed(const SurfaceView& sv, uint32_t* list, int slots,
                                               float restitution, float& px, float& py,
                                               float& pz, float& qx, float& qy, float& qz) {
@@ -532,7 +534,7 @@ __device__ __forceinline__ int collide_listed(const SurfaceView& sv, uint32_t* l
         sy += push * n.y;
         sz += push * n.z;
     };
-    const int contacts = contacts_listed(sv, list, slots, px, py, pz, accumulate);
+    const int contacts = contacts_listed<true, HR>(sv, list, slots, px, py, pz, accumulate);
     respond(contacts, sx, sy, sz, restitution, px, py, pz, qx, qy, qz);
     return contacts;
 }

@@ -59,12 +59,13 @@ struct ClothView {
 // node and offset at most.  The stencil kernel runs one wavefront per 8x8 tile of the
 // internal order (tiles row by row, nodes row-major in a tile).  A cloth is described by
 // (first slot, nx | ny << 16, first tile, cloth index): `one` for a handle of one cloth,
-// tiles[t] per tile for a batch.  idx[d * ld + p] is the parameter-table entry of the
-// spring from slot p in direction d, or kNoSpring; while the table has at most kSmallTab
-// entries, byte d % 4 of idx8[(d / 4) * ld + p] holds the same entry (kNoSpring8 for none),
-// a quarter of the bytes.  n_tab points at the table's current entry count (kept on the
-// device so captured graphs stay valid when parameters change); tab_cap is the table's
-// capacity.
+// tiles[t] per tile for a batch.  Each cloth's entries in the parameter table are one
+// contiguous range starting at tab_base[cloth] (0 for a one-cloth handle).  idx[d * ld + p]
+// is the table entry of the spring from slot p in direction d, or kNoSpring; while no cloth
+// has more than kSmallTab entries, byte d % 4 of idx8[(d / 4) * ld + p] holds the same entry
+// relative to its cloth's first (kNoSpring8 for none), a quarter of the bytes.  n_tab points
+// at the largest number of entries of one cloth (kept on the device so captured graphs stay
+// valid when parameters change); tab_cap is the table's capacity.
 constexpr int kStencilDirs = 12;
 constexpr uint32_t kNoSpring = 0xffffffffu;
 constexpr uint32_t kNoSpring8 = 0xffu;
@@ -77,6 +78,7 @@ struct GridView {
     const uint32_t* idx8;
     const int* n_tab;
     int tab_cap;
+    const int* tab_base;  // [cloths] first table entry of each cloth (batches), else NULL
 };
 
 // Springs for the spring-centric (scatter) force pass: ends as internal slots, parameters
@@ -197,8 +199,10 @@ hipError_t prepare_grid_kernels(size_t lds_bytes);
 // Dynamic LDS of a stencil launch (the hit lists of its one wavefront per workgroup).
 size_t grid_lds_bytes(int hit_slots);
 // Stencil parameter entries from per-spring entries: idx[q] = entry[code[q]], or kNoSpring
-// where code[q] < 0, and their byte form in idx8 (q = d * ld + p, see GridView).
-hipError_t launch_set_stencil_entries(int ld, const int* code, const int* entry, uint32_t* idx,
+// where code[q] < 0, and their byte form in idx8 (q = d * ld + p, see GridView), relative to
+// tab_base[slot_cloth[p]] when both are given.
+hipError_t launch_set_stencil_entries(int ld, const int* code, const int* entry,
+                                      const int* slot_cloth, const int* tab_base, uint32_t* idx,
                                       uint32_t* idx8, hipStream_t st);
 hipError_t launch_substep_lanes(int lanes, const ClothView& cv, int collide, const StepParams& sp,
                                 const float* xs, const float* vs, float* xd, float* vd, int block,

@@ -25,6 +25,9 @@ namespace {
 constexpr int kSide = 12;                  // region side: the tile and two nodes either side
 constexpr int kRegion = kSide * kSide;     // 144 nodes
 constexpr int kTabLds = 128;               // tables up to this size are read from LDS
+// Lists of at most kShortListSlots hits load the geometry of kShortHitRound hits per round.
+constexpr int kShortListSlots = 16;
+constexpr int kShortHitRound = 4;
 
 // Offsets of the stencil's directions in the region (row * kSide + column), in incidence
 // order.
@@ -45,7 +48,7 @@ __device__ __forceinline__ int grid_slot(int first, int nx, int ny, int gr, int 
     return first + 8 * nx * tr + 8 * h * tc + (gr & 7) * w + (gc & 7);
 }
 
-template <bool COLLIDE, bool GROUPED>
+template <bool COLLIDE, bool GROUPED, int HR>
 __global__ void __launch_bounds__(64, 2)
     k_grid(const ClothView cv, const GridView gv, const StepParams sp,
            const float* __restrict__ xs, const float* __restrict__ vs, float* __restrict__ xd,
@@ -74,10 +77,13 @@ __global__ void __launch_bounds__(64, 2)
 #pragma unroll
         for (int k = 0; k < kStencilDirs / 4; ++k) idx8[k] = gv.idx8[(size_t)k * ld + i];
     }
+    // the cloth's entries of the parameter table start at tb; a small table is staged in LDS
     const int n_tab = *gv.n_tab;
+    const int tb = GROUPED && gv.tab_base ? gv.tab_base[cd.w] : 0;
+    const int tab_here = min(gv.tab_cap - tb, kTabLds);
     float4 tv0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), tv1 = tv0;
-    if (lane < gv.tab_cap) tv0 = ldg4(cv.ptab, lane);
-    if (lane + 64 < min(gv.tab_cap, kTabLds)) tv1 = ldg4(cv.ptab, lane + 64);
+    if (lane < tab_here) tv0 = ldg4(cv.ptab, tb + lane);
+    if (lane + 64 < tab_here) tv1 = ldg4(cv.ptab, tb + lane + 64);
     float sv_[3][6];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
@@ -108,8 +114,8 @@ __global__ void __launch_bounds__(64, 2)
     tab[lane + 64] = tv1;
     __syncthreads();
 
-    // the parameter entries of the node's springs: bytes while the table is small, else (a
-    // second round of loads) the full entries
+    // the parameter entries of the node's springs, relative to the cloth's first: bytes
+    // while every cloth has few entries, else (a second round of loads) the full entries
     uint32_t idx[kStencilDirs];
     if (n_tab <= kSmallTab) {
 #pragma unroll
@@ -119,8 +125,10 @@ __global__ void __launch_bounds__(64, 2)
         }
     } else {
 #pragma unroll
-        for (int d = 0; d < kStencilDirs; ++d)
-            idx[d] = active ? gv.idx[(size_t)d * ld + i] : kNoSpring;
+        for (int d = 0; d < kStencilDirs; ++d) {
+            const uint32_t v = active ? gv.idx[(size_t)d * ld + i] : kNoSpring;
+            idx[d] = v == kNoSpring ? kNoSpring : v - (uint32_t)tb;
+        }
     }
 
     // 2. the springs of each node from LDS, in incidence order; 3. integration
@@ -138,7 +146,7 @@ __global__ void __launch_bounds__(64, 2)
         } else {
 #pragma unroll
             for (int d = 0; d < kStencilDirs; ++d)
-                e[d] = ldg4(cv.ptab, idx[d] == kNoSpring ? 0 : idx[d]);
+                e[d] = ldg4(cv.ptab, tb + (idx[d] == kNoSpring ? 0 : idx[d]));
         }
 #pragma unroll
         for (int d = 0; d < kStencilDirs; ++d) {
@@ -161,8 +169,8 @@ __global__ void __launch_bounds__(64, 2)
         const SurfaceView sv = svs[GROUPED ? cd.w : 0];
         if (sv.n_tris > 0) {
             if (hit_slots > 0)
-                collide_listed(sv, hit_lds + lane, hit_slots, sp.restitution, px, py, pz, qx, qy,
-                               qz);
+                collide_listed<HR>(sv, hit_lds + lane, hit_slots, sp.restitution, px, py, pz, qx,
+                                   qy, qz);
             else
                 collide(sv, sp.restitution, px, py, pz, qx, qy, qz);
         }
@@ -180,19 +188,22 @@ __global__ void __launch_bounds__(64, 2)
     }
 }
 
-// One thread per slot: its kStencilDirs entries, then their byte form (one word per four
-// directions).
+// One thread per slot: its kStencilDirs entries, then their byte form relative to the
+// slot's cloth's first entry (one word per four directions).
 __global__ void k_set_stencil_entries(int ld, const int* __restrict__ code,
-                                      const int* __restrict__ entry, uint32_t* __restrict__ idx,
+                                      const int* __restrict__ entry,
+                                      const int* __restrict__ slot_cloth,
+                                      const int* __restrict__ tab_base, uint32_t* __restrict__ idx,
                                       uint32_t* __restrict__ idx8) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= ld) return;
+    const uint32_t base = slot_cloth && tab_base ? (uint32_t)tab_base[slot_cloth[p]] : 0u;
     uint32_t word = 0;
     for (int d = 0; d < kStencilDirs; ++d) {
         const int s = code[(size_t)d * ld + p];
         const uint32_t v = s >= 0 ? (uint32_t)entry[s] : kNoSpring;
         idx[(size_t)d * ld + p] = v;
-        word |= (v == kNoSpring ? kNoSpring8 : (v & 0xffu)) << (8 * (d % 4));
+        word |= (v == kNoSpring ? kNoSpring8 : ((v - base) & 0xffu)) << (8 * (d % 4));
         if (d % 4 == 3) {
             idx8[(size_t)(d / 4) * ld + p] = word;
             word = 0;
@@ -206,11 +217,16 @@ size_t grid_lds_bytes(int hit_slots) { return wave_query_lds(hit_slots); }
 
 hipError_t prepare_grid_kernels(size_t lds_bytes) {
     if (lds_bytes <= 32 * 1024) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute((const void*)k_grid<true, false>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)k_grid<true, true>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    const void* fns[] = {(const void*)k_grid<true, false, kHitRound>,
+                         (const void*)k_grid<true, true, kHitRound>,
+                         (const void*)k_grid<true, false, kShortHitRound>,
+                         (const void*)k_grid<true, true, kShortHitRound>};
+    for (const void* f : fns) {
+        hipError_t e =
+            hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_grid_substep(const ClothView& cv, const GridView& gv, int collide,
@@ -222,25 +238,37 @@ hipError_t launch_grid_substep(const ClothView& cv, const GridView& gv, int coll
     if (hit_slots < 0 || hit_slots > kMaxHitSlots) return hipErrorInvalidValue;
     const int grid = xcd_grid(gv.n_tiles, xcd_runs);
     const size_t lds = collide ? grid_lds_bytes(hit_slots) : 0;
-    if (collide && grouped)
-        k_grid<true, true><<<grid, 64, lds, stream>>>(cv, gv, sp, xs, vs, xd, vd, svs, hit_slots,
-                                                      xcd_runs, pred);
+    // short hit lists go with short rounds of geometry loads: fewer registers, more
+    // wavefronts per SIMD for workloads whose collision work is spread over many of them
+    const bool short_round = hit_slots <= kShortListSlots;
+    if (collide && grouped && short_round)
+        k_grid<true, true, kShortHitRound><<<grid, 64, lds, stream>>>(
+            cv, gv, sp, xs, vs, xd, vd, svs, hit_slots, xcd_runs, pred);
+    else if (collide && grouped)
+        k_grid<true, true, kHitRound><<<grid, 64, lds, stream>>>(cv, gv, sp, xs, vs, xd, vd, svs,
+                                                                 hit_slots, xcd_runs, pred);
+    else if (collide && short_round)
+        k_grid<true, false, kShortHitRound><<<grid, 64, lds, stream>>>(
+            cv, gv, sp, xs, vs, xd, vd, svs, hit_slots, xcd_runs, pred);
     else if (collide)
-        k_grid<true, false><<<grid, 64, lds, stream>>>(cv, gv, sp, xs, vs, xd, vd, svs, hit_slots,
-                                                       xcd_runs, pred);
+        k_grid<true, false, kHitRound><<<grid, 64, lds, stream>>>(cv, gv, sp, xs, vs, xd, vd, svs,
+                                                                  hit_slots, xcd_runs, pred);
     else if (grouped)
-        k_grid<false, true><<<grid, 64, 0, stream>>>(cv, gv, sp, xs, vs, xd, vd, svs, 0, xcd_runs,
-                                                     pred);
+        k_grid<false, true, kHitRound><<<grid, 64, 0, stream>>>(cv, gv, sp, xs, vs, xd, vd, svs, 0,
+                                                                xcd_runs, pred);
     else
-        k_grid<false, false><<<grid, 64, 0, stream>>>(cv, gv, sp, xs, vs, xd, vd, svs, 0,
-                                                      xcd_runs, pred);
+        k_grid<false, false, kHitRound><<<grid, 64, 0, stream>>>(cv, gv, sp, xs, vs, xd, vd, svs,
+                                                                 0, xcd_runs, pred);
     return hipGetLastError();
 }
 
-hipError_t launch_set_stencil_entries(int ld, const int* code, const int* entry, uint32_t* idx,
+hipError_t launch_set_stencil_entries(int ld, const int* code, const int* entry,
+                                      const int* slot_cloth, const int* tab_base, uint32_t* idx,
                                       uint32_t* idx8, hipStream_t st) {
     if (ld <= 0) return hipSuccess;
-    k_set_stencil_entries<<<(unsigned)((ld + 255) / 256), 256, 0, st>>>(ld, code, entry, idx, idx8);
+    k_set_stencil_entries<<<(unsigned)((ld + 255) / 256), 256, 0, st>>>(ld, code, entry,
+                                                                         slot_cloth, tab_base,
+                                                                         idx, idx8);
     return hipGetLastError();
 }
 

@@ -256,7 +256,8 @@ bool unstable(double omega2, double gamma, double h) {
 }
 
 // Host-side cloth arrays in internal order.
-int build_cloth_host(const ClothHostInput& in, ClothHost* out, const std::vector<int>* order) {
+int build_cloth_host(const ClothHostInput& in, ClothHost* out, const std::vector<int>* order,
+                     const std::vector<int>* segs) {
     const int N = in.nx * in.ny;
     out->n = N;
     out->order = order ? *order : tile_order(in.nx, in.ny);
@@ -323,12 +324,14 @@ int build_cloth_host(const ClothHostInput& in, ClothHost* out, const std::vector
         for (int r = deg[p]; r < (out->slice_ptr[(p >> 6) + 1] - out->slice_ptr[p >> 6]) / 64; ++r)
             out->nbr[base + (size_t)r * 64] = p;
     }
-    param_table(in.k, in.c, in.rest, in.n_springs, &out->ptab, &out->spring_entry);
+    param_table(in.k, in.c, in.rest, in.n_springs, segs, &out->ptab, &out->spring_entry,
+                &out->tab_span);
     return CLOTH_OK;
 }
 
 void param_table(const float* k, const float* c, const float* rest, int S,
-                 std::vector<float4>* tab, std::vector<int>* entry) {
+                 const std::vector<int>* segs, std::vector<float4>* tab,
+                 std::vector<int>* entry, int* span) {
     struct Key {
         uint32_t a, b, c;
         bool operator==(const Key& o) const { return a == o.a && b == o.b && c == o.c; }
@@ -344,7 +347,15 @@ void param_table(const float* k, const float* c, const float* rest, int S,
     std::unordered_map<Key, int, Hash> index;
     tab->clear();
     entry->assign((size_t)S, 0);
+    *span = 0;
+    size_t seg = 1, first = 0;  // the current segment ends before (*segs)[seg]
     for (int s = 0; s < S; ++s) {
+        if (segs && seg < segs->size() && s >= (*segs)[seg]) {
+            while (seg < segs->size() && s >= (*segs)[seg]) ++seg;
+            *span = std::max(*span, (int)(tab->size() - first));
+            first = tab->size();
+            index.clear();
+        }
         Key key;
         std::memcpy(&key.a, k + s, 4);
         std::memcpy(&key.b, c + s, 4);
@@ -356,6 +367,14 @@ void param_table(const float* k, const float* c, const float* rest, int S,
         }
         (*entry)[s] = it->second;
     }
+    *span = std::max(*span, (int)(tab->size() - first));
+}
+
+std::vector<int> segment_bases(const std::vector<int>& segs, const std::vector<int>& entry) {
+    std::vector<int> b;
+    for (size_t g = 0; g + 1 < segs.size(); ++g)
+        b.push_back(segs[g] < segs[g + 1] ? entry[(size_t)segs[g]] : 0);
+    return b;
 }
 
 int upload_cloth(const ClothHost& h, DeviceArena& arena, hipStream_t stream, ClothDevice* d) {
@@ -379,7 +398,7 @@ int upload_cloth(const ClothHost& h, DeviceArena& arena, hipStream_t stream, Clo
         (e = arena.alloc(&d->n_tab, 1)))
         return hip_fail(e, "hipMalloc cloth arrays");
     std::vector<uint2> inc2(M);
-    const int n_tab = (int)h.ptab.size();
+    const int n_tab = h.tab_span;
     StreamFence fence{stream};
     for (size_t q = 0; q < M; ++q) {
         const int code = h.inc_spring[q];
@@ -422,6 +441,7 @@ GridView ClothDevice::grid_view() const {
     g.idx8 = sten_idx8;
     g.n_tab = this->n_tab;
     g.tab_cap = std::max(n_springs, 1);
+    g.tab_base = tab_base;
     return g;
 }
 
@@ -438,9 +458,9 @@ ClothView ClothDevice::view() const {
     return v;
 }
 
-int upload_param_table(const std::vector<float4>& tab, const std::vector<int>& entry,
-                       ClothDevice* d, size_t n_inc, uint2* plan_rec, const int* plan_sid,
-                       size_t n_plan, hipStream_t stream) {
+int upload_param_table(const std::vector<float4>& tab, const std::vector<int>& entry, int span,
+                       const std::vector<int>& bases, ClothDevice* d, size_t n_inc,
+                       uint2* plan_rec, const int* plan_sid, size_t n_plan, hipStream_t stream) {
     if (entry.size() != (size_t)d->n_springs || tab.size() > std::max<size_t>(entry.size(), 1))
         return fail(CLOTH_EINVAL, "parameter table does not match the springs");
     StreamFence fence{stream};
@@ -451,6 +471,10 @@ int upload_param_table(const std::vector<float4>& tab, const std::vector<int>& e
         (entry.size() && (e = hipMemcpyAsync(d->spring_entry, entry.data(), entry.size() * 4,
                                              hipMemcpyHostToDevice, stream))))
         return hip_fail(e, "upload parameter table");
+    if (d->tab_base && bases.size() &&
+        (e = hipMemcpyAsync(d->tab_base, bases.data(), bases.size() * 4, hipMemcpyHostToDevice,
+                            stream)))
+        return hip_fail(e, "upload parameter table");
     if (entry.size()) {
         if ((e = launch_set_entries(n_inc, d->inc_spring, 1, d->spring_entry, d->inc2, stream)))
             return hip_fail(e, "re-point incidence records");
@@ -458,11 +482,11 @@ int upload_param_table(const std::vector<float4>& tab, const std::vector<int>& e
             (e = launch_set_entries(n_plan, plan_sid, 0, d->spring_entry, plan_rec, stream)))
             return hip_fail(e, "re-point tile records");
         if (d->sten_code &&
-            (e = launch_set_stencil_entries(d->ld, d->sten_code, d->spring_entry, d->sten_idx,
-                                            d->sten_idx8, stream)))
+            (e = launch_set_stencil_entries(d->ld, d->sten_code, d->spring_entry, d->slot_cloth,
+                                            d->tab_base, d->sten_idx, d->sten_idx8, stream)))
             return hip_fail(e, "re-point stencil entries");
     }
-    const int n_tab = (int)tab.size();
+    const int n_tab = span;
     if ((e = hipMemcpyAsync(d->n_tab, &n_tab, sizeof(int), hipMemcpyHostToDevice, stream)))
         return hip_fail(e, "upload parameter table");
     // the host vectors are the copies' sources: finish before returning

@@ -71,9 +71,11 @@ struct ClothHost {
     std::vector<int> order, slot;  // order[slot] = node id; slot[node id] = internal slot
     std::vector<float> x, v, w;
     std::vector<int> deg, slice_ptr, nbr, inc_spring;
-    // the distinct (k, c, rest length) triples and each spring's entry (param_table)
+    // the distinct (k, c, rest length) triples of each cloth and each spring's entry
+    // (param_table); tab_span: the most entries any one cloth has
     std::vector<float4> ptab;
     std::vector<int> spring_entry;
+    int tab_span = 0;
     // The state copies are only needed for the upload; the incidence lists stay for
     // rebuilding tile plans.
     void release_state() {
@@ -95,14 +97,17 @@ struct ClothDevice {
     float4* ptab = nullptr;       // room for one entry per spring (at least one)
     int* spring_entry = nullptr;  // [springs]: re-points the records after a parameter update
     int n_springs = 0;
-    int* n_tab = nullptr;         // [1]: entries in ptab (read by the stencil kernel)
+    int* n_tab = nullptr;         // [1]: the most entries one cloth has in ptab (stencil kernel)
     // grid stencil (build_stencil), when every cloth of the handle has one
     int n_tiles = 0;
     int4 one_cloth{};                // the cloth of a one-cloth handle (GridView::one)
     int4* tiles = nullptr;           // [n_tiles] per-tile cloth (batches), else NULL
     int* sten_code = nullptr;        // [kStencilDirs][ld] spring or -1
     uint32_t* sten_idx = nullptr;    // [kStencilDirs][ld] ptab entry or kNoSpring
-    uint32_t* sten_idx8 = nullptr;   // [kStencilDirs / 4][ld] the entries as bytes
+    uint32_t* sten_idx8 = nullptr;   // [kStencilDirs / 4][ld] the entries as bytes, relative
+                                     // to the cloth's first (GridView)
+    int* tab_base = nullptr;         // [cloths] first ptab entry of each cloth (batches), else NULL
+    const int* slot_cloth = nullptr; // [ld] cloth of each slot (batches), else NULL
     GridView grid_view() const;
     ClothView view() const;
 };
@@ -154,19 +159,30 @@ int validate_cloth(const ClothHostInput& in);
 int validate_params(const cloth_params* p);
 void stability_bounds(const ClothHostInput& in, double* omega2, double* gamma);
 bool unstable(double omega2, double gamma, double h);
-// order: internal slot -> node id; NULL = the 8x8-tile Morton order of (nx, ny).
+// order: internal slot -> node id; NULL = the 8x8-tile Morton order of (nx, ny).  segs: the
+// first spring of each cloth of a merged input, then the spring count (NULL = one cloth).
 int build_cloth_host(const ClothHostInput& in, ClothHost* out,
-                     const std::vector<int>* order = nullptr);
+                     const std::vector<int>* order = nullptr,
+                     const std::vector<int>* segs = nullptr);
 int upload_cloth(const ClothHost& h, DeviceArena& arena, hipStream_t stream, ClothDevice* d);
 // The distinct (k, c, rest length) triples of S springs, compared by their exact FP32 bits,
-// in order of first occurrence, and each spring's entry in that table.
+// in order of first occurrence, and each spring's entry in that table.  The triples are
+// distinct per segment of springs (segs: each segment's first spring, then S; NULL or empty =
+// one segment), so each segment's entries are one contiguous range starting at the entry of
+// its first spring; *span gets the largest range.
 void param_table(const float* k, const float* c, const float* rest, int S,
-                 std::vector<float4>* tab, std::vector<int>* entry);
+                 const std::vector<int>* segs, std::vector<float4>* tab,
+                 std::vector<int>* entry, int* span);
+// First entry of each segment (the entry of its first spring; 0 for a segment without
+// springs).
+std::vector<int> segment_bases(const std::vector<int>& segs, const std::vector<int>& entry);
 // Upload a parameter table and the springs' entries, then re-point the cloth's incidence
 // records (and the tile plan's records, if rec/sid are given) at them; synchronises.
-int upload_param_table(const std::vector<float4>& tab, const std::vector<int>& entry,
-                       ClothDevice* d, size_t n_inc, uint2* plan_rec, const int* plan_sid,
-                       size_t n_plan, hipStream_t stream);
+// span: the most entries one segment (cloth) has; bases: each cloth's first entry, uploaded
+// to d->tab_base when the handle has one.
+int upload_param_table(const std::vector<float4>& tab, const std::vector<int>& entry, int span,
+                       const std::vector<int>& bases, ClothDevice* d, size_t n_inc,
+                       uint2* plan_rec, const int* plan_sid, size_t n_plan, hipStream_t stream);
 int build_surface(const ClothHostInput& in, const cloth_params& p, DeviceArena& arena,
                   hipStream_t stream, SurfaceDevice* sd);
 // Rebuild the grid and every per-triangle array for new vertex positions [n_verts][3] (host)

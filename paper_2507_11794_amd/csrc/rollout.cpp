@@ -35,9 +35,11 @@ int set_spring_params(cloth_sim* s, const float* k_dev, const float* c_dev) {
     s->c = c;
     // a new table of the distinct triples (one entry per spring at most: it fits in place)
     // and the records of the cloth and of the tile plan re-pointed at it
-    param_table(s->k.data(), s->c.data(), s->rest.data(), (int)S, &s->host.ptab,
-                &s->host.spring_entry);
-    int st = upload_param_table(s->host.ptab, s->host.spring_entry, &s->dev,
+    const std::vector<int> segs = spring_segments(s);
+    param_table(s->k.data(), s->c.data(), s->rest.data(), (int)S, &segs, &s->host.ptab,
+                &s->host.spring_entry, &s->host.tab_span);
+    int st = upload_param_table(s->host.ptab, s->host.spring_entry, s->host.tab_span,
+                                segment_bases(segs, s->host.spring_entry), &s->dev,
                                 s->host.inc_spring.size(), const_cast<uint2*>(s->plan.view.inc),
                                 s->plan.inc_sid, s->plan.inc_count, s->stream);
     if (st != CLOTH_OK) return st;

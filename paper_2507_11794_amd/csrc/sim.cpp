@@ -407,6 +407,14 @@ int read_state_range(const cloth_sim* s, int group, float* x_out, float* v_out) 
     return CLOTH_OK;
 }
 
+// First spring of each cloth of the handle, then the spring count.
+std::vector<int> spring_segments(const cloth_sim* s) {
+    std::vector<int> segs;
+    for (const GroupInfo& g : s->groups) segs.push_back(g.spring_off);
+    segs.push_back(s->n_springs);
+    return segs;
+}
+
 // The grid stencil of the handle's cloths (build_stencil), on the device, when they have
 // one; otherwise the grid kernel stays unavailable.
 int build_stencil_device(cloth_sim* s) {
@@ -417,22 +425,32 @@ int build_stencil_device(cloth_sim* s) {
     std::vector<int4> tiles;
     if (!build_stencil(sc, s->ends, s->host.slot, s->dev.ld, &code, &tiles)) return CLOTH_OK;
     const size_t m = code.size(), ld = (size_t)s->dev.ld;
+    const size_t G = s->groups.size();
+    // bytes relative to the first entry of the slot's cloth
+    const std::vector<int> bases = segment_bases(spring_segments(s), s->host.spring_entry);
+    std::vector<int> slot_base(ld, 0);
+    for (size_t g = 0; g < G; ++g)
+        for (int q = s->group_off[g]; q < s->group_off[g + 1]; ++q) slot_base[q] = bases[g];
     std::vector<uint32_t> idx(m), idx8(m / 4, 0u);
     for (size_t q = 0; q < m; ++q) {
         idx[q] = code[q] >= 0 ? (uint32_t)s->host.spring_entry[code[q]] : kNoSpring;
         const size_t d = q / ld, p = q % ld;
-        const uint32_t b = idx[q] == kNoSpring ? kNoSpring8 : (idx[q] & 0xffu);
+        const uint32_t b =
+            idx[q] == kNoSpring ? kNoSpring8 : ((idx[q] - (uint32_t)slot_base[p]) & 0xffu);
         idx8[(d / 4) * ld + p] |= b << (8 * (d % 4));
     }
     ClothDevice& d = s->dev;
     StreamFence fence{s->stream};
     hipError_t e;
-    int *dc = nullptr;
+    int *dc = nullptr, *dbase = nullptr;
     uint32_t *di = nullptr, *di8 = nullptr;
     int4* dt = nullptr;
     if ((e = s->arena.alloc(&dc, m)) || (e = s->arena.alloc(&di, m)) ||
         (e = s->arena.alloc(&di8, m / 4)) ||
-        (s->groups.size() > 1 && (e = s->arena.alloc(&dt, tiles.size()))) ||
+        (G > 1 && (e = s->arena.alloc(&dt, tiles.size()))) ||
+        (G > 1 && (e = s->arena.alloc(&dbase, G))) ||
+        (dbase && (e = hipMemcpyAsync(dbase, bases.data(), 4 * G, hipMemcpyHostToDevice,
+                                      s->stream))) ||
         (e = hipMemcpyAsync(dc, code.data(), 4 * m, hipMemcpyHostToDevice, s->stream)) ||
         (e = hipMemcpyAsync(di, idx.data(), 4 * m, hipMemcpyHostToDevice, s->stream)) ||
         (e = hipMemcpyAsync(di8, idx8.data(), m, hipMemcpyHostToDevice, s->stream)) ||
@@ -443,6 +461,8 @@ int build_stencil_device(cloth_sim* s) {
     d.sten_code = dc;
     d.sten_idx = di;
     d.sten_idx8 = di8;
+    d.tab_base = dbase;
+    d.slot_cloth = G > 1 ? s->node_group_dev : nullptr;
     d.tiles = dt;
     d.n_tiles = (int)tiles.size();
     d.one_cloth = tiles.empty() ? int4{} : tiles[0];
@@ -514,7 +534,9 @@ int create_sim(const std::vector<ClothHostInput>& cloths, const cloth_params* p,
         merged.rest = rest.data();
         merged.k = s->k.data();
         merged.c = s->c.data();
-        st = build_cloth_host(merged, &s->host, &order);
+        // parameter entries are distinct per cloth: each cloth's are one contiguous range
+        const std::vector<int> segs = spring_segments(s);
+        st = build_cloth_host(merged, &s->host, &order, &segs);
         for (size_t g = 0; g < cloths.size() && st == CLOTH_OK; ++g)
             stability_bounds(cloths[g], &s->groups[g].omega2, &s->groups[g].gamma);
     } catch (const std::bad_alloc&) {

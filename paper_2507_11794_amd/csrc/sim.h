@@ -142,6 +142,8 @@ void refresh_stability(cloth_sim* s);
 int read_state_range(const cloth_sim* s, int group, float* x_out, float* v_out);
 // New vertex positions for cloth `group`'s surface (same triangles): rebuilds its grid.
 int update_surface(cloth_sim* s, int group, const float* verts, int n_verts);
+// First spring of each cloth of the handle, then the spring count (param_table's segments).
+std::vector<int> spring_segments(const cloth_sim* s);
 // Per-node external forces [n_nodes][3] in caller numbering (NULL removes them).
 int set_external_force(cloth_sim* s, const float* f);
 // Device tables of the cloth-grid topology (node order, per-cloth sizes), made once.

@@ -203,8 +203,8 @@ hipError_t launch_grid_substep(const ClothView&, const GridView&, int, const Ste
 }
 hipError_t prepare_grid_kernels(size_t) { return hipSuccess; }
 size_t grid_lds_bytes(int hit_slots) { return (size_t)(hit_slots + 1) * 256; }
-hipError_t launch_set_stencil_entries(int, const int*, const int*, uint32_t*, uint32_t*,
-                                      hipStream_t) {
+hipError_t launch_set_stencil_entries(int, const int*, const int*, const int*, const int*,
+                                      uint32_t*, uint32_t*, hipStream_t) {
     return hipSuccess;
 }
 hipError_t launch_import(int, int, const int*, const float*, float*, int, hipStream_t) {

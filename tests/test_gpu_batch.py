@@ -1,5 +1,7 @@
 """GPU batched mode: many uneven cloths in one handle evolve exactly (bit for bit) as plain
 per-cloth handles do, for every launch configuration and schedule, and after autotuning."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -35,6 +37,37 @@ def test_batch_equals_plain_per_cloth_bitwise():
         assert np.array_equal(got[i][0], xp) and np.array_equal(got[i][1], vp), i
     moved = max(np.abs(g[0] - c.x0).max() for g, c in zip(got, cl))
     assert moved > 0.01
+
+
+def _with_distinct_k(c, n_distinct, seed):
+    """c with its first n_distinct springs given their own stiffness (a table entry each)."""
+    k = c.k.copy()
+    k[:n_distinct] *= 1.0 + np.random.default_rng(seed).uniform(0.01, 0.05, n_distinct).astype(np.float32)
+    return dataclasses.replace(c, k=k)
+
+
+@pytest.mark.parametrize("case", ["bytes, table in LDS", "bytes, table in memory",
+                                  "full entries"])
+def test_batch_parameter_tables_per_cloth_equal_plain_handles(case):
+    """Each cloth's parameter entries form their own range of the table: with 90 cloths of
+    three entries each (270 in all, more than one byte can index) the stencil kernel still
+    reads byte entries relative to the cloth's first and stages the cloth's entries in LDS;
+    with cloths of 129-255 entries it reads the table from memory; with a cloth of more than
+    255 it reads the full entries.  Every cloth ends bit-identical to its own handle."""
+    if case == "bytes, table in LDS":
+        cl = W.config3(n_cloths=90, seed=31, side_lo=16, side_hi=16, freq=6, n_steps=10)
+    else:
+        base = W.config3(n_cloths=3, seed=32, side_lo=16, side_hi=20, freq=6, n_steps=10)
+        n = [150, 200, 40] if case == "bytes, table in memory" else [150, 400, 40]
+        cl = [_with_distinct_k(c, m, 40 + i) for i, (c, m) in enumerate(zip(base, n))]
+    frames = 10
+    with B.ClothBatch(cl) as b:
+        assert b.get_launch()["kernel"] == B.CLOTH_KERNEL_GRID
+        b.step(n_steps=frames)
+        got = [b.read_state(i) for i in range(len(cl))]
+    for i, c in enumerate(cl):
+        xp, vp = _plain(c, frames)
+        assert np.array_equal(got[i][0], xp) and np.array_equal(got[i][1], vp), (case, i)
 
 
 SCHEDULES = [
