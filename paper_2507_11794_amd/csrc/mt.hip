@@ -9,8 +9,11 @@
 // The cloth mesh is the grid's quads split along their (r, c)-(r+1, c+1) diagonals.
 // Each segment test is preceded by exact-in-principle rejections (the segment's ends strictly
 // on one side of the triangle's plane, or boxes that do not meet), which differ from the
-// full test only at decision boundaries.  Candidates come from the grid cells covering the
-// box of i's path, edges and triangles; a
+// full test only at decision boundaries.  A crossing lies in the triangle, so the boxes
+// tested are the triangle's own (the grid's boxes, grown by the thickness for the proximity
+// query, shrunk back to the triangle plus a margin of a thousandth of the thickness, at
+// least 1 um, far above the rounding of either box).  Candidates come from the grid cells
+// covering the box of i's path, edges and triangles; a
 // triangle listed in several of those cells is tested only in the first of them (the cell
 // whose coordinates are the maxima of its own and the query's low cells), so each
 // candidate is tested once, in a fixed order.  The response is the averaged push of Alg. 2:
@@ -23,6 +26,7 @@ namespace cloth {
 namespace {
 
 constexpr float kMtEps = 1e-7f;
+constexpr float kMtBoxMargin = 1e-3f;  // of the thickness (see above)
 
 __device__ __forceinline__ float3 f3(const float4& a) { return make_float3(a.x, a.y, a.z); }
 __device__ __forceinline__ float3 sub3(float3 a, float3 b) {
@@ -78,6 +82,11 @@ __device__ __forceinline__ bool tri_meets_box(float3 a, float3 b, float3 c, cons
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Candidates a lane lists in LDS before their triangles are loaded and tested, and
+// reference boxes tested per round of loads.
+constexpr int kMtSlots = 24;
+constexpr int kMtRefRound = 8;
+
 template <bool DEBUG>
 __global__ void __launch_bounds__(256)
     k_mt_collide(const ClothView cv, const StepParams sp, const int* __restrict__ order,
@@ -85,6 +94,8 @@ __global__ void __launch_bounds__(256)
                  const int4* __restrict__ groups, const SurfaceView* __restrict__ svs,
                  const float* __restrict__ xs, const float* __restrict__ P, float* __restrict__ xd,
                  float* __restrict__ vd, int* __restrict__ counts, int* __restrict__ ids, int cap) {
+    __shared__ uint32_t lists[4 * 64 * kMtSlots];  // each lane's list: every 64th word
+    uint32_t* list = lists + (threadIdx.x >> 6) * 64 * kMtSlots + (threadIdx.x & 63);
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= cv.n) return;
     const int ld = cv.ld;
@@ -154,85 +165,145 @@ __global__ void __launch_bounds__(256)
             const int q1y = cell_axis(hi.y, sv.org[1], sv.inv_cell, sv.dim[1]);
             const int q1z = cell_axis(hi.z, sv.org[2], sv.inv_cell, sv.dim[2]);
             const float th = sv.thickness;
-            for (int cz = q0z; cz <= q1z; ++cz)
-                for (int cy = q0y; cy <= q1y; ++cy)
-                    for (int cx = q0x; cx <= q1x; ++cx) {
-                        const int cell = (cz * sv.dim[1] + cy) * sv.dim[0] + cx;
-                        const uint32_t b = gmem(sv.cell_start)[cell], e = gmem(sv.cell_start)[cell + 1];
-                        // each reference's box is loaded one iteration ahead (the padding after
-                        // the last reference keeps the look-ahead in bounds), so its latency
-                        // overlaps the tests of the current candidate
-                        float4 nlo = ldg4(sv.ref_lo, b), nhi = ldg4(sv.ref_hi, b);
-                        for (uint32_t rr = b; rr < e; ++rr) {
-                            const float4 blo = nlo, bhi = nhi;
-                            nlo = ldg4(sv.ref_lo, rr + 1);
-                            nhi = ldg4(sv.ref_hi, rr + 1);
-                            if (bhi.x < lo.x || blo.x > hi.x || bhi.y < lo.y || blo.y > hi.y ||
-                                bhi.z < lo.z || blo.z > hi.z)
-                                continue;
-                            // test each triangle in the first query cell that lists it
-                            if (max(cell_axis(blo.x, sv.org[0], sv.inv_cell, sv.dim[0]), q0x) != cx ||
-                                max(cell_axis(blo.y, sv.org[1], sv.inv_cell, sv.dim[1]), q0y) != cy ||
-                                max(cell_axis(blo.z, sv.org[2], sv.inv_cell, sv.dim[2]), q0z) != cz)
-                                continue;
-                            const uint32_t t = (uint32_t)__float_as_int(blo.w);
-                            const float4 a0 = ldg4(sv.tri_v, 3 * (size_t)t),
-                                         a1 = ldg4(sv.tri_v, 3 * (size_t)t + 1),
-                                         a2 = ldg4(sv.tri_v, 3 * (size_t)t + 2);
-                            const float3 V0 = f3(a0), V1 = f3(a1), V2 = f3(a2);
-                            // cheap rejections before each segment test: a crossing needs
-                            // the segment's ends on both sides of (or on) the triangle's
-                            // plane, and the segment's box to meet the triangle's box
-                            const float3 Nt = cross3(sub3(V1, V0), sub3(V2, V0));
-                            const float sp_ = dot3(sub3(xp, V0), Nt);
-                            bool hit = false;
-                            if (straddles(dot3(sub3(x0, V0), Nt), sp_) && seg_meets_box(x0, xp, blo, bhi))
-                                hit = mt_cross(x0, xp, V0, V1, V2);  // (C)
+            // the grid's boxes are the triangles' grown by th: shrink them to the triangle
+            // plus the margin
+            const float shrink = fmaxf(th - fmaxf(th * kMtBoxMargin, 1e-6f), 0.0f);
+            auto own_box = [&](float4& blo, float4& bhi) {
+                blo = make_float4(blo.x + shrink, blo.y + shrink, blo.z + shrink, blo.w);
+                bhi = make_float4(bhi.x - shrink, bhi.y - shrink, bhi.z - shrink, bhi.w);
+            };
+            // one candidate: does any of the node's segments cross triangle t, or an edge of t
+            // cross one of the node's cloth triangles?
+            auto test = [&](uint32_t t, const float4& blo, const float4& bhi, const float4& a0,
+                            const float4& a1, const float4& a2) {
+                const float3 V0 = f3(a0), V1 = f3(a1), V2 = f3(a2);
+                // cheap rejections before each segment test: a crossing needs the segment's
+                // ends on both sides of (or on) the triangle's plane, and the segment's box
+                // to meet the triangle's box
+                const float3 Nt = cross3(sub3(V1, V0), sub3(V2, V0));
+                const float sp_ = dot3(sub3(xp, V0), Nt);
+                bool hit = false;
+                if (straddles(dot3(sub3(x0, V0), Nt), sp_) && seg_meets_box(x0, xp, blo, bhi))
+                    hit = mt_cross(x0, xp, V0, V1, V2);  // (C)
 #pragma unroll
-                            for (int k = 0; k < 6; ++k)  // (A)
-                                if (!hit && ok[k] && straddles(sp_, dot3(sub3(q[k], V0), Nt)) &&
-                                    seg_meets_box(xp, q[k], blo, bhi))
-                                    hit = id < nid[k] ? mt_cross(xp, q[k], V0, V1, V2)
-                                                      : mt_cross(q[k], xp, V0, V1, V2);
-                            const float3 Vs[3] = {V0, V1, V2};
-                            const int vid[3] = {__float_as_int(a0.w), __float_as_int(a1.w),
-                                                __float_as_int(a2.w)};
+                for (int k = 0; k < 6; ++k)  // (A)
+                    if (!hit && ok[k] && straddles(sp_, dot3(sub3(q[k], V0), Nt)) &&
+                        seg_meets_box(xp, q[k], blo, bhi))
+                        hit = id < nid[k] ? mt_cross(xp, q[k], V0, V1, V2)
+                                          : mt_cross(q[k], xp, V0, V1, V2);
+                const float3 Vs[3] = {V0, V1, V2};
+                const int vid[3] = {__float_as_int(a0.w), __float_as_int(a1.w),
+                                    __float_as_int(a2.w)};
 #pragma unroll
-                            for (int k = 0; k < 6; ++k) {  // (B)
-                                if (hit || !tok[k]) continue;
-                                const float3 P0 = vert(T0[k]), P1 = vert(T1[k]), P2 = vert(T2[k]);
-                                if (!tri_meets_box(P0, P1, P2, blo, bhi)) continue;
-                                const float3 Nc = cross3(sub3(P1, P0), sub3(P2, P0));
-                                float sv3[3];
+                for (int k = 0; k < 6; ++k) {  // (B)
+                    if (hit || !tok[k]) continue;
+                    const float3 P0 = vert(T0[k]), P1 = vert(T1[k]), P2 = vert(T2[k]);
+                    if (!tri_meets_box(P0, P1, P2, blo, bhi)) continue;
+                    const float3 Nc = cross3(sub3(P1, P0), sub3(P2, P0));
+                    float sv3[3];
 #pragma unroll
-                                for (int z = 0; z < 3; ++z) sv3[z] = dot3(sub3(Vs[z], P0), Nc);
+                    for (int z = 0; z < 3; ++z) sv3[z] = dot3(sub3(Vs[z], P0), Nc);
 #pragma unroll
-                                for (int z = 0; z < 3; ++z) {
-                                    const int z1 = z == 2 ? 0 : z + 1;
-                                    if (hit || !straddles(sv3[z], sv3[z1])) continue;
-                                    const bool fwd = vid[z] < vid[z1];
-                                    const float3 S = fwd ? Vs[z] : Vs[z1], E = fwd ? Vs[z1] : Vs[z];
-                                    hit = mt_cross(S, E, P0, P1, P2);
-                                }
-                            }
-                            if (hit) {
-                                if (DEBUG) {
-                                    if (cnt < cap) ids[(size_t)p * cap + cnt] = (int)t;
-                                } else {
-                                    const float4 g0 = ldg4(sv.geo, 3 * (size_t)t),
-                                                 g1 = ldg4(sv.geo, 3 * (size_t)t + 1),
-                                                 g2 = ldg4(sv.geo, 3 * (size_t)t + 2);
-                                    const float3 n = make_float3(g0.w, g1.w, g2.w);
-                                    const float s = dot3(sub3(xp, f3(g0)), n);
-                                    const float push = th - s;
-                                    acc.x += push * n.x;
-                                    acc.y += push * n.y;
-                                    acc.z += push * n.z;
-                                }
-                                ++cnt;
-                            }
+                    for (int z = 0; z < 3; ++z) {
+                        const int z1 = z == 2 ? 0 : z + 1;
+                        if (hit || !straddles(sv3[z], sv3[z1])) continue;
+                        const bool fwd = vid[z] < vid[z1];
+                        const float3 S = fwd ? Vs[z] : Vs[z1], E = fwd ? Vs[z1] : Vs[z];
+                        hit = mt_cross(S, E, P0, P1, P2);
+                    }
+                }
+                if (hit) {
+                    if (DEBUG) {
+                        if (cnt < cap) ids[(size_t)p * cap + cnt] = (int)t;
+                    } else {
+                        const float4 g0 = ldg4(sv.geo, 3 * (size_t)t),
+                                     g1 = ldg4(sv.geo, 3 * (size_t)t + 1),
+                                     g2 = ldg4(sv.geo, 3 * (size_t)t + 2);
+                        const float3 n = make_float3(g0.w, g1.w, g2.w);
+                        const float s = dot3(sub3(xp, f3(g0)), n);
+                        const float push = th - s;
+                        acc.x += push * n.x;
+                        acc.y += push * n.y;
+                        acc.z += push * n.z;
+                    }
+                    ++cnt;
+                }
+            };
+            // Listing and testing alternate in one loop so the tests are compiled once: a
+            // lane lists candidates from its query cells, kMtRefRound references per round of
+            // loads (the padding after the last reference keeps a round in bounds), and the
+            // lanes of the wavefront test their listed candidates together, in listing order,
+            // each triangle's box and vertices loaded one candidate ahead.  A triangle whose
+            // box meets the query box is listed in the first query cell that lists it, so
+            // each candidate is listed once.
+            int cx = q0x, cy = q0y, cz = q0z;
+            uint32_t r = gmem(sv.cell_start)[(cz * sv.dim[1] + cy) * sv.dim[0] + cx];
+            uint32_t e = gmem(sv.cell_start)[(cz * sv.dim[1] + cy) * sv.dim[0] + cx + 1];
+            bool done = false;
+            int nl = 0;
+            for (;;) {
+                while (!done && r >= e) {  // the next query cell
+                    if (++cx > q1x) {
+                        cx = q0x;
+                        if (++cy > q1y) {
+                            cy = q0y;
+                            if (++cz > q1z) done = true;
                         }
                     }
+                    if (!done) {
+                        const int cell = (cz * sv.dim[1] + cy) * sv.dim[0] + cx;
+                        r = gmem(sv.cell_start)[cell];
+                        e = gmem(sv.cell_start)[cell + 1];
+                    }
+                }
+                // the lanes test their lists together (the tests are long): when any lane's
+                // list could overflow in the next round, and once every lane is done
+                const bool all_done = __all(done);
+                if (all_done || __any(nl > kMtSlots - kMtRefRound)) {
+                    uint32_t t = nl > 0 ? list[0] : 0u;
+                    float4 blo = ldg4(sv.box_lo, t), bhi = ldg4(sv.box_hi, t);
+                    own_box(blo, bhi);
+                    float4 v0 = ldg4(sv.tri_v, 3 * (size_t)t), v1 = ldg4(sv.tri_v, 3 * (size_t)t + 1),
+                           v2 = ldg4(sv.tri_v, 3 * (size_t)t + 2);
+                    for (int h = 0; h < nl; ++h) {
+                        const uint32_t tc = t;
+                        const float4 clo = blo, chi = bhi, c0 = v0, c1 = v1, c2 = v2;
+                        t = list[min(h + 1, nl - 1) * 64];
+                        blo = ldg4(sv.box_lo, t);
+                        bhi = ldg4(sv.box_hi, t);
+                        own_box(blo, bhi);
+                        v0 = ldg4(sv.tri_v, 3 * (size_t)t);
+                        v1 = ldg4(sv.tri_v, 3 * (size_t)t + 1);
+                        v2 = ldg4(sv.tri_v, 3 * (size_t)t + 2);
+                        test(tc, clo, chi, c0, c1, c2);
+                    }
+                    nl = 0;
+                }
+                if (all_done) break;
+                if (done) continue;  // waits for the wavefront's other lanes
+                float4 blo[kMtRefRound], bhi[kMtRefRound];
+#pragma unroll
+                for (int k = 0; k < kMtRefRound; ++k) {
+                    blo[k] = ldg4(sv.ref_lo, r + k);
+                    bhi[k] = ldg4(sv.ref_hi, r + k);
+                }
+#pragma unroll
+                for (int k = 0; k < kMtRefRound; ++k) {
+                    // (the first-cell test below takes the grid's box, which chose the cells)
+                    float4 olo = blo[k], ohi = bhi[k];
+                    own_box(olo, ohi);
+                    const bool meets = r + k < e && !(ohi.x < lo.x || olo.x > hi.x ||
+                                                      ohi.y < lo.y || olo.y > hi.y ||
+                                                      ohi.z < lo.z || olo.z > hi.z);
+                    const bool first =
+                        max(cell_axis(blo[k].x, sv.org[0], sv.inv_cell, sv.dim[0]), q0x) == cx &&
+                        max(cell_axis(blo[k].y, sv.org[1], sv.inv_cell, sv.dim[1]), q0y) == cy &&
+                        max(cell_axis(blo[k].z, sv.org[2], sv.inv_cell, sv.dim[2]), q0z) == cz;
+                    list[nl * 64] = (uint32_t)__float_as_int(blo[k].w);
+                    nl += meets && first ? 1 : 0;
+                }
+                r += kMtRefRound;
+            }
         }
     }
     if (DEBUG) {
