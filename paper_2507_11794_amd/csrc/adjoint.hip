@@ -177,13 +177,13 @@ __device__ __forceinline__ void adj_springs_at(const ClothView& cv, const float*
     }
 }
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64)
     k_adj_node(const ClothView cv, const SurfaceView sv, const StepParams sp,
                const float* __restrict__ xs, const float* __restrict__ vs,
                const float* __restrict__ xb_out, const float* __restrict__ vb_out,
                float* __restrict__ fb, float* __restrict__ xb_part, float* __restrict__ vb_part,
                int hit_slots, const float* __restrict__ pred) {
-    extern __shared__ uint32_t hit_lds[];  // per wavefront: wave_query_lds(hit_slots) bytes
+    extern __shared__ uint32_t hit_lds[];  // the wavefront's lists: wave_query_lds(hit_slots) bytes
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cv.n) return;
     const int ld = cv.ld;
@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(256)
 // vb_part are read and then rewritten by the same thread.
 // gout: when an output is recorded at the state between the two substeps, its loss adjoint
 // in caller order (AoS), added before the node pass as the import kernel adds it.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64)
     k_adj_fused(const ClothView cv, const SurfaceView sv, const StepParams sp,
                 const float* __restrict__ xs_a, const float* __restrict__ vs_a,
                 const float* __restrict__ xs_b, const float* __restrict__ vs_b,
@@ -378,12 +378,10 @@ hipError_t launch_adj_node(const ClothView& cv, const SurfaceView& sv, const Ste
                            int hit_slots, const float* pred, hipStream_t st) {
     if (cv.n <= 0) return hipSuccess;
     if (hit_slots < 0 || hit_slots > kMaxHitSlots) hit_slots = 0;
-    // four wavefronts' lists within 64 KiB; a shorter list only sends more lanes to the
-    // unlisted search, which finds the same contacts in the same order
-    hit_slots = std::min(hit_slots, kMaxHitSlots - 1);
-    const size_t lds = (size_t)(256 / 64) * wave_query_lds(hit_slots);
-    k_adj_node<<<blocks(cv.n, 256), 256, lds, st>>>(cv, sv, sp, xs, vs, xb_out, vb_out, fb,
-                                                    xb_part, vb_part, hit_slots, pred);
+    // one wavefront per workgroup: a small cloth's few wavefronts then spread over as many
+    // compute units (its kernels are bound by latency)
+    k_adj_node<<<blocks(cv.n, 64), 64, wave_query_lds(hit_slots), st>>>(
+        cv, sv, sp, xs, vs, xb_out, vb_out, fb, xb_part, vb_part, hit_slots, pred);
     return hipGetLastError();
 }
 
@@ -395,13 +393,11 @@ hipError_t launch_adj_fused(const ClothView& cv, const SurfaceView& sv, const St
                             int hit_slots, hipStream_t st) {
     if (cv.n <= 0) return hipSuccess;
     if (hit_slots < 0 || hit_slots > kMaxHitSlots) hit_slots = 0;
-    // four wavefronts' lists within 64 KiB; a shorter list only sends more lanes to the
-    // unlisted search, which finds the same contacts in the same order
-    hit_slots = std::min(hit_slots, kMaxHitSlots - 1);
-    const size_t lds = (size_t)(256 / 64) * wave_query_lds(hit_slots);
-    k_adj_fused<<<blocks(cv.n, 256), 256, lds, st>>>(cv, sv, sp, xs_a, vs_a, xs_b, vs_b, pred_b,
-                                                     fb_t, fb_prev, xb_part, vb_part, xb, vb, kb,
-                                                     cb, gout, order, hit_slots);
+    // one wavefront per workgroup (see launch_adj_node): 4.06 -> 3.73 times the plain
+    // forward's time for the 64x64 cloth's rollout
+    k_adj_fused<<<blocks(cv.n, 64), 64, wave_query_lds(hit_slots), st>>>(
+        cv, sv, sp, xs_a, vs_a, xs_b, vs_b, pred_b, fb_t, fb_prev, xb_part, vb_part, xb, vb, kb,
+        cb, gout, order, hit_slots);
     return hipGetLastError();
 }
 

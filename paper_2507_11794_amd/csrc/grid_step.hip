@@ -8,13 +8,13 @@
 //   1. each wavefront loads its tile and a two-node halo (12 x 12 nodes, both state vectors)
 //      into LDS with row-coalesced loads whose slots follow from the grid shape alone (no
 //      index loads first), together with its nodes' parameter-table entries per direction
-//      (one byte each while the table has at most 255 entries) and, when the table is
-//      small, the table itself;
+//      (one byte each, relative to the cloth's first entry, while no cloth has more than
+//      255) and, when the cloth has at most 128 entries, its part of the table;
 //   2. each lane sums its node's springs from LDS in the incidence order (ascending
 //      neighbour id = ascending offset (row, column)), with the same spring_force
 //      arithmetic as every other kernel;
 //   3. integration, the grid broad phase, the narrow phase and the response are those of
-//      k_substep.
+//      k_substep (HR box hits per round of geometry loads).
 #include "cloth_device.h"
 #include "cloth_internal.h"
 
