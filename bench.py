@@ -15,8 +15,10 @@ window is reported.
 
 Prints one JSON line: node-updates/s (one node advanced by one substep), the roofline of the
 dominant kernel (algorithmic bytes of the substep, collision share included, over the
-kernel's average duration), the other workloads' legs with their own rooflines, and the
-FP64 oracle timed on the host cores on a bounded sample of the same window.
+kernel's average duration), the same frames with the state copied to the host after each
+frame (the PCIe-inclusive rate; never the headline value), the other workloads' legs with
+their own rooflines, and the FP64 oracle timed on the host cores on a bounded sample of the
+same window.
 """
 from __future__ import annotations
 
@@ -314,6 +316,27 @@ def bench_normals(sim, n_nodes: int, reps: int = 200):
             "achieved_gbs": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
 
 
+def bench_read_back(sim, x0, v0, n_nodes: int, n_substeps: int, frames: int):
+    """Stepping with the state copied to the host after every frame (cloth_read_state into
+    the same two arrays each time: AoS in node-id order, synchronising), from the state
+    (x0, v0): the rate a caller that takes host buffers over the boundary each frame sees,
+    PCIe copies included."""
+    x = np.empty((n_nodes, 3), dtype=np.float32)
+    v = np.empty((n_nodes, 3), dtype=np.float32)
+    sim.write_state(x0, v0)
+    sim.step(n_steps=1)
+    sim.read_state(x, v)
+    sim.write_state(x0, v0)
+    t0 = time.perf_counter()
+    for _ in range(frames):
+        sim.step(n_steps=1)
+        sim.read_state(x, v)
+    wall = time.perf_counter() - t0
+    return {"frames": frames, "ms_per_frame": wall * 1e3 / frames,
+            "node_updates_per_s": n_nodes * n_substeps * frames / wall,
+            "host_bytes_per_frame": 24 * n_nodes}
+
+
 def coarse_cells(inp):
     """The workload with a broad-phase grid cell of 2 x the mean surface edge."""
     from paper_2507_11794_amd import workloads
@@ -608,6 +631,7 @@ def main():
     per_sub = algorithmic_bytes_per_substep(inp.n_nodes, inp.n_springs) + coll
     info = sim.info()
     normals = None if args.no_normals else bench_normals(sim, inp.n_nodes)
+    read_back = bench_read_back(sim, x0, v0, inp.n_nodes, inp.n_substeps, args.steps)
     sim.close()
     first = PREROLL + args.warmup
     out = {
@@ -647,6 +671,7 @@ def main():
     }
     out["roofline"]["bytes_per_node_update"] = per_sub / inp.n_nodes
     out["roofline"]["collision_bytes_per_substep"] = coll
+    out["read_back_each_frame"] = read_back
     if normals:
         out["normals"] = normals
     if not args.no_moving:

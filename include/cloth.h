@@ -166,6 +166,9 @@ int cloth_step(cloth_sim* sim, float dt, int n_substeps, int n_steps);
 /*
  * cloth_read_state -- copy the current state to the host, AoS [N*3] in node-id order
  * (Alg. 2's output: updated positions and velocities).  v_out may be NULL.  Synchronises.
+ * The state is reordered on the device and copied through a pinned staging buffer that the
+ * first call allocates (24 bytes per node of the handle's largest cloth, on the device and
+ * in pinned host memory; released by cloth_destroy / cloth_batch_destroy).
  * Returns CLOTH_ENAN if CLOTH_F_CHECK_NAN is set and a non-finite value was produced.
  */
 int cloth_read_state(const cloth_sim* sim, float* x_out, float* v_out);
@@ -190,10 +193,13 @@ int cloth_info(const cloth_sim* sim, long long* out);
 
 /*
  * cloth_set_launch / cloth_get_launch -- choose how cloth_step schedules substeps.
- * Default with a collision surface: one-thread-per-node kernel, 64 threads per workgroup
- * in the hardware's round-robin order, graphs on, 32 hit slots, no second pass (tile
- * fields: 256 nodes, 1 substep, grid schedule).  Without one: the tile kernel, 256-node
- * tiles, 1 substep per launch, 256 threads per workgroup, graphs on.
+ * Default when every cloth is a grid whose springs fit the stencil (CLOTH_KERNEL_GRID's
+ * condition): the grid kernel, 64 threads per workgroup, chunks of 16 tiles per XCD,
+ * graphs on, 32 hit slots.  Otherwise, with a collision surface: the one-thread-per-node
+ * kernel, 64 threads per workgroup in the hardware's round-robin order, graphs on, 32 hit
+ * slots, no second pass (tile fields: 256 nodes, 1 substep, grid schedule); without one:
+ * the tile kernel, 256-node tiles, 1 substep per launch, 256 threads per workgroup, graphs
+ * on.
  * cloth_set_launch validates the configuration and rebuilds the tile plan if needed
  * (synchronises the handle's stream).  Errors: CLOTH_EINVAL for an out-of-range field or a
  * tile region that does not fit in LDS (the previous configuration stays in effect).

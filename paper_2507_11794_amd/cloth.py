@@ -192,9 +192,22 @@ def cloth_step(h, dt, n_substeps, n_steps):
     _check(load().cloth_step(_vp(h), float(dt), int(n_substeps), int(n_steps)))
 
 
-def cloth_read_state(h, n):
-    x = np.zeros((n, 3), dtype=np.float32)
-    v = np.zeros((n, 3), dtype=np.float32)
+def _state_out(a, n):
+    """A caller-supplied output array for n nodes' state: float32, C-contiguous, [n, 3],
+    writeable; None gives a new one."""
+    if a is None:
+        return np.empty((n, 3), dtype=np.float32)
+    if (not isinstance(a, np.ndarray) or a.dtype != np.float32 or a.shape != (n, 3)
+            or not a.flags.c_contiguous or not a.flags.writeable):
+        raise ValueError(f"state output must be a writeable C-contiguous float32 array of "
+                         f"shape ({n}, 3)")
+    return a
+
+
+def cloth_read_state(h, n, x=None, v=None):
+    """The state (x, v), AoS [n, 3] in node-id order; x and v may be arrays to fill."""
+    x = _state_out(x, n)
+    v = _state_out(v, n)
     _check(load().cloth_read_state(_vp(h), _ptr(x, _fp), _ptr(v, _fp)))
     return x, v
 
@@ -348,8 +361,8 @@ class Cloth:
         cloth_step(self.h, self.inp.dt if dt is None else dt,
                    self.inp.n_substeps if n_substeps is None else n_substeps, n_steps)
 
-    def read_state(self):
-        return cloth_read_state(self.h, self.n)
+    def read_state(self, x=None, v=None):
+        return cloth_read_state(self.h, self.n, x, v)
 
     def write_state(self, x, v=None):
         cloth_write_state(self.h, x, v)

@@ -377,28 +377,36 @@ void refresh_stability(cloth_sim* s) {
 int read_state_range(const cloth_sim* s, int group, float* x_out, float* v_out) {
     const GroupInfo& g = s->groups[group];
     const size_t ld = (size_t)s->dev.ld, n = (size_t)g.n;
-    std::vector<float> xs(3 * n), vs(v_out ? 3 * n : 0);
-    int flag = 0;
-    StreamFence fence{s->stream};
     hipError_t e;
-    for (int q = 0; q < 3; ++q) {
-        if ((e = hipMemcpyAsync(xs.data() + q * n, s->dev.x[s->dev.cur] + q * ld + g.slot_off,
-                                4 * n, hipMemcpyDeviceToHost, s->stream)))
-            return hip_fail(e, "read state");
-        if (v_out && (e = hipMemcpyAsync(vs.data() + q * n, s->dev.v[s->dev.cur] + q * ld + g.slot_off,
-                                         4 * n, hipMemcpyDeviceToHost, s->stream)))
-            return hip_fail(e, "read state");
-    }
-    if ((e = hipMemcpyAsync(&flag, s->nan_flag, 4, hipMemcpyDeviceToHost, s->stream)) ||
-        (e = hipStreamSynchronize(s->stream)))
-        return hip_fail(e, "read state");
-    for (size_t p = 0; p < n; ++p) {
-        const size_t id = (size_t)(s->host.order[g.slot_off + p] - g.node_off);
-        for (int q = 0; q < 3; ++q) {
-            x_out[3 * id + q] = xs[q * n + p];
-            if (v_out) v_out[3 * id + q] = vs[q * n + p];
+    if (!s->export_dev) {
+        size_t most = 1;
+        for (const GroupInfo& q : s->groups) most = std::max(most, (size_t)q.n);
+        if ((e = hipMalloc((void**)&s->export_dev, 24 * most)))
+            return hip_fail(e, "read state staging");
+        if ((e = hipHostMalloc((void**)&s->export_host, 24 * most + 4, hipHostMallocDefault))) {
+            (void)hipFree(s->export_dev);
+            s->export_dev = nullptr;
+            s->export_host = nullptr;
+            return hip_fail(e, "read state staging");
         }
     }
+    // AoS in node-id order on the device (slot_dev maps node id -> internal slot), then one
+    // copy of x (and v) and the status flag into pinned memory
+    const int* slot = s->slot_dev + g.node_off;
+    const size_t nv = v_out ? 2 : 1;
+    if ((e = launch_export((int)n, (int)ld, slot, s->dev.x[s->dev.cur], s->export_dev, s->stream)) ||
+        (v_out && (e = launch_export((int)n, (int)ld, slot, s->dev.v[s->dev.cur],
+                                     s->export_dev + 3 * n, s->stream))) ||
+        (e = hipMemcpyAsync(s->export_host, s->export_dev, 12 * n * nv, hipMemcpyDeviceToHost,
+                            s->stream)) ||
+        (e = hipMemcpyAsync(s->export_host + 6 * n, s->nan_flag, 4, hipMemcpyDeviceToHost,
+                            s->stream)) ||
+        (e = hipStreamSynchronize(s->stream)))
+        return hip_fail(e, "read state");
+    int flag = 0;
+    std::memcpy(&flag, s->export_host + 6 * n, 4);
+    std::memcpy(x_out, s->export_host, 12 * n);
+    if (v_out) std::memcpy(v_out, s->export_host + 3 * n, 12 * n);
     if (flag & 2)
         return fail(CLOTH_ENAN, "a spring force exceeded the fixed-point accumulator's range "
                                 "(8 N per component); use another kernel");

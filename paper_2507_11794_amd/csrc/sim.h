@@ -102,6 +102,11 @@ struct cloth_sim {
     bool mt = false;             // triangle-triangle narrow phase (CLOTH_F_NARROW_MT)
     float* mt_pred = nullptr;    // its prediction scratch, [6][ld]  // a surface rebuild failed part-way: stepping is refused
     cloth::RolloutState roll;
+    // read-back staging, allocated by the first read of the state (the handle is used by one
+    // thread at a time): device AoS x then v of the largest cloth in node-id order, and its
+    // pinned host copy followed by the status flag
+    mutable float* export_dev = nullptr;
+    mutable float* export_host = nullptr;
 
     void drop_graphs() {
         for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
@@ -111,6 +116,8 @@ struct cloth_sim {
         (void)hipStreamSynchronize(stream);
         drop_graphs();
         if (capture) (void)hipStreamDestroy(capture);
+        if (export_dev) (void)hipFree(export_dev);
+        if (export_host) (void)hipHostFree(export_host);
     }
 };
 

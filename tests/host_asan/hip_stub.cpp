@@ -54,6 +54,15 @@ hipError_t hipFree(void* p) {
     std::free(p);
     return hipSuccess;
 }
+hipError_t hipHostMalloc(void** p, size_t n, unsigned int) {
+    *p = std::calloc(1, n ? n : 1);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+hipError_t hipHostFree(void* p) {
+    drain();
+    std::free(p);
+    return hipSuccess;
+}
 hipError_t hipMemcpyAsync(void* dst, const void* src, size_t bytes, hipMemcpyKind, hipStream_t) {
     if (bytes) g_ops.push_back(Op{dst, src, bytes, 0});
     return hipSuccess;

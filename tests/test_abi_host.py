@@ -142,3 +142,16 @@ def test_config0_needs_substeps():
     for cfg in W.config3(n_cloths=8):
         w2b, gb = B.cloth_stability_bound(cfg.x0, cfg.mass, cfg.pinned, cfg.ends, cfg.k, cfg.c)
         assert w2b * cfg.h ** 2 + 2 * gb * cfg.h < 4
+
+
+def test_state_output_arrays_are_checked_before_the_call():
+    a = B._state_out(None, 5)
+    assert a.shape == (5, 3) and a.dtype == np.float32 and a.flags.c_contiguous
+    good = np.zeros((5, 3), np.float32)
+    assert B._state_out(good, 5) is good
+    ro = np.zeros((5, 3), np.float32)
+    ro.flags.writeable = False
+    for bad in (np.zeros((5, 3), np.float64), np.zeros((4, 3), np.float32),
+                np.zeros((3, 5), np.float32).T, ro, [[0.0] * 3] * 5):
+        with pytest.raises(ValueError):
+            B._state_out(bad, 5)
