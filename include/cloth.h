@@ -88,8 +88,10 @@ enum cloth_kernel {
                                      columns apart (one spring per offset): one launch per
                                      substep, one wavefront per 8x8 tile of nodes, the tile and
                                      a two-node halo staged in LDS (same results as DIRECT, bit
-                                     for bit; block_threads is 64); CLOTH_EINVAL for other
-                                     spring graphs */
+                                     for bit); block_threads 64, or 128 and more for a second
+                                     wavefront per tile that takes every other round of the
+                                     box hits' narrow tests (with a surface; same results);
+                                     CLOTH_EINVAL for other spring graphs */
 };
 
 /* How tiles are assigned to workgroups (tile kernel). */
@@ -104,7 +106,8 @@ typedef struct cloth_launch {
     int kernel;              /* enum cloth_kernel */
     int tile_nodes;          /* tile kernel: nodes per workgroup tile, multiple of 64 (64..4096) */
     int substeps_per_launch; /* tile kernel: substeps advanced per launch, 1..8 */
-    int block_threads;       /* threads per workgroup: 64, 128, 192 or 256 */
+    int block_threads;       /* threads per workgroup: 64, 128, 192 or 256 (grid kernel: 64
+                                one wavefront per tile, 128 and more two) */
     int use_graph;           /* nonzero: replay launches from a captured hipGraph */
     int schedule;            /* tile kernel: enum cloth_schedule */
     int workgroups;          /* persistent schedules: number of workgroups (> 0) */
@@ -194,8 +197,8 @@ int cloth_info(const cloth_sim* sim, long long* out);
 /*
  * cloth_set_launch / cloth_get_launch -- choose how cloth_step schedules substeps.
  * Default when every cloth is a grid whose springs fit the stencil (CLOTH_KERNEL_GRID's
- * condition): the grid kernel, 64 threads per workgroup, chunks of 16 tiles per XCD,
- * graphs on, 32 hit slots.  Otherwise, with a collision surface: the one-thread-per-node
+ * condition): the grid kernel, chunks of 16 tiles per XCD, graphs on, 32 hit slots, two
+ * wavefronts per tile (block_threads 128) for one cloth with a surface, else one (64).  Otherwise, with a collision surface: the one-thread-per-node
  * kernel, 64 threads per workgroup in the hardware's round-robin order, graphs on, 32 hit
  * slots, no second pass (tile fields: 256 nodes, 1 substep, grid schedule); without one:
  * the tile kernel, 256-node tiles, 1 substep per launch, 256 threads per workgroup, graphs

@@ -88,12 +88,13 @@ void cache_store(const std::string& key, const cloth_launch& c) {
 
 std::vector<cloth_launch> candidates(int cus, bool collide, bool grid) {
     std::vector<cloth_launch> v;
-    if (grid)  // the grid-stencil kernel (one wavefront per 8x8 tile)
-        for (int st : {0, 16, 32})
-            for (int xr : {0, 1, 2, 16}) {
-                if (!collide && st) continue;
-                v.push_back({CLOTH_KERNEL_GRID, 256, 1, 64, 1, CLOTH_SCHED_GRID, 0, st, xr, 0});
-            }
+    if (grid)  // the grid-stencil kernel (one or two wavefronts per 8x8 tile)
+        for (int bt : {64, 128})
+            for (int st : {0, 16, 32})
+                for (int xr : {0, 1, 2, 16}) {
+                    if (!collide && (st || bt > 64)) continue;
+                    v.push_back({CLOTH_KERNEL_GRID, 256, 1, bt, 1, CLOTH_SCHED_GRID, 0, st, xr, 0});
+                }
     const int stages[] = {0, 32};
     for (int st : stages) {
         if (!collide && st) continue;
@@ -125,7 +126,7 @@ int autotune_sim(cloth_sim* s, float dt, int n_substeps, int frames, cloth_launc
     const float h = dt / (float)n_substeps;
     char hex[32];
     std::snprintf(hex, sizeof(hex), "%016llx", (unsigned long long)workload_hash(s, h, n_substeps));
-    const std::string key = device_key() + ":v5:" + hex;
+    const std::string key = device_key() + ":v6:" + hex;
     cloth_launch chosen;
     if (cache_lookup(key, &chosen)) {
         int st = set_launch(s, chosen);

@@ -260,13 +260,25 @@ __device__ __forceinline__ void integrate(float w, float h, const float g[3], fl
 // Narrow phase against one broad-phase candidate whose packed geometry (A, n.x), (B-A, n.y),
 // (C-A, n.z) is g0, g1, g2: contact iff the point-triangle distance is < thickness; then
 // visit(n, s, t).  Returns 1 for a contact.
+// The unit normal n of a candidate's packed geometry (A, n.x), (B-A, n.y), (C-A, n.z), the
+// vector a = p - A and the signed plane distance s = a.n (returned).
+__device__ __forceinline__ float plane_offset(const float4& g0, const float4& g1,
+                                              const float4& g2, float px, float py, float pz,
+                                              float4& n, float& ax, float& ay, float& az) {
+    n = make_float4(g0.w, g1.w, g2.w, 0.0f);
+    ax = px - g0.x;
+    ay = py - g0.y;
+    az = pz - g0.z;
+    return ax * n.x + ay * n.y + az * n.z;
+}
+
 template <class Visit>
 __device__ __forceinline__ int narrow_visit(const SurfaceView& sv, uint32_t t, const float4& g0,
                                             const float4& g1, const float4& g2, float px,
                                             float py, float pz, Visit&& visit) {
-    const float4 n = make_float4(g0.w, g1.w, g2.w, 0.0f);
-    const float ax = px - g0.x, ay = py - g0.y, az = pz - g0.z;
-    const float s = ax * n.x + ay * n.y + az * n.z;
+    float4 n;
+    float ax, ay, az;
+    const float s = plane_offset(g0, g1, g2, px, py, pz, n, ax, ay, az);
     const float d2 = point_tri_dist2(ax, ay, az, g1.x, g1.y, g1.z, g2.x, g2.y, g2.z, s);
     if (d2 < sv.thickness2) {
         visit(n, s, t);
@@ -400,24 +412,18 @@ __device__ __forceinline__ int collide(const SurfaceView& sv, float restitution,
     return cnt;
 }
 
-// a3 + a4 contact search with the box hits of the references [b, e) of p's cell collected
-// first (cx, cy, cz: p's point codes in that cell, see point_code): the coded reference
-// records are tested RR (<= kRefRound) per round of loads, the triangle ids of hits
-// go to this lane's list in LDS (list[k * 64], k < slots, plus a scratch entry k = slots:
-// every reference is written at the next free entry, or at the scratch entry once the list
-// is full, and only a hit advances the count), and the hits' geometry is then
-// loaded HR hits per round, so a node with many box hits waits for few round trips.
-// Contacts are visited in ascending triangle id, exactly as visit_range visits them (same
-// contacts, same order); a lane with more hits than slots runs visit_range instead.  Returns the contact count.  NARROW = false stops after the broad phase: every box
-// hit (undecided ones settled with the exact box) is visited, with n and s zero, and counted;
-// this is the query the step kernels run, up to the narrow test.
-template <bool NARROW = true, int RR = kRefRound, int HR = kHitRound, class Visit>
-__device__ __forceinline__ int listed_range(const SurfaceView& sv, uint32_t* list, int slots,
-                                            uint32_t cx, uint32_t cy, uint32_t cz, uint32_t b,
-                                            uint32_t e, float px, float py, float pz,
-                                            Visit&& visit) {
-    // box hits go to the list as triangle ids; a hit whose coded test was undecided
-    // carries bit 31 and is decided with the exact box before its narrow test
+// The box hits among the references [b, e) of p's grid cell (cx, cy, cz: p's point codes in
+// that cell, see point_code), appended to this lane's list in LDS in reference order
+// (ascending triangle id): the coded reference records are tested RR (<= kRefRound) per
+// round of loads, and a hit's triangle id goes to list[k * 64] (k < slots), plus a scratch
+// entry k = slots: every reference is written at the next free entry, or at the scratch entry
+// once the list is full, and only a hit advances the count.  A hit whose coded test was
+// undecided carries bit 31 and is decided with the exact box before its narrow test.
+// Returns the number of hits, which may exceed slots (then the list holds the first slots).
+template <int RR = kRefRound>
+__device__ __forceinline__ int list_box_hits(const SurfaceView& sv, uint32_t* list, int slots,
+                                             uint32_t cx, uint32_t cy, uint32_t cz, uint32_t b,
+                                             uint32_t e) {
     int nh = 0;
     // a round's entries load from one address at fixed offsets
     auto load = [&](uint4 (&w)[RR], uint32_t r) {
@@ -450,6 +456,63 @@ __device__ __forceinline__ int listed_range(const SurfaceView& sv, uint32_t* lis
         __builtin_amdgcn_sched_barrier(0);
         test(wb, r1);
     }
+    return nh;
+}
+
+// One round of the listed box hits: entries h0 .. h0 + HR - 1 of a list of nh (1 <= nh <=
+// slots) entries.  Their geometry loads are issued together (entries past nh repeat the last
+// one and are not visited), undecided entries are settled with the exact box in one branch
+// (which the wavefront skips when none of its lanes has one), and on_hit(k, t, g0, g1, g2) is
+// called for each remaining entry k in ascending order, with its triangle id t and packed
+// geometry.
+template <int HR, class OnHit>
+__device__ __forceinline__ void hit_round(const SurfaceView& sv, const uint32_t* list, int nh,
+                                          int h0, float px, float py, float pz, OnHit&& on_hit) {
+    const int n = min(nh - h0, HR);
+    uint32_t t[HR];
+    float4 g[HR][3];
+#pragma unroll
+    for (int q = 0; q < HR; ++q) t[q] = list[min(h0 + q, nh - 1) * 64];
+#pragma unroll
+    for (int q = 0; q < HR; ++q) {
+        const size_t id = t[q] & 0x7fffffffu;
+        g[q][0] = ldg4(sv.geo, 3 * id);
+        g[q][1] = ldg4(sv.geo, 3 * id + 1);
+        g[q][2] = ldg4(sv.geo, 3 * id + 2);
+    }
+    uint32_t live = (1u << n) - 1u, und = 0;
+#pragma unroll
+    for (int q = 0; q < HR; ++q) und |= (t[q] >> 31) << q;
+    und &= live;
+    if (und) {
+#pragma unroll
+        for (int q = 0; q < HR; ++q)
+            if ((und >> q) & 1u) {
+                const uint32_t id = t[q] & 0x7fffffffu;
+                if (!in_box(ldg4(sv.box_lo, id), ldg4(sv.box_hi, id), px, py, pz))
+                    live &= ~(1u << q);
+            }
+    }
+    // (a wavefront skips a slot none of its lanes holds, e.g. in its last round)
+#pragma unroll
+    for (int q = 0; q < HR; ++q)
+        if ((live >> q) & 1u) on_hit(h0 + q, t[q] & 0x7fffffffu, g[q][0], g[q][1], g[q][2]);
+}
+
+// a3 + a4 contact search with the box hits of the references [b, e) of p's cell collected
+// first (list_box_hits), then their geometry loaded HR hits per round (hit_round), so a node
+// with many box hits waits for few round trips.  Contacts are visited in ascending triangle
+// id, exactly as visit_range visits them (same contacts, same order); a lane with more hits
+// than slots runs visit_range instead.  Returns the contact count.  NARROW = false stops
+// after the broad phase: every box hit (undecided ones settled with the exact box) is
+// visited, with n and s zero, and counted; this is the query the step kernels run, up to the
+// narrow test.
+template <bool NARROW = true, int RR = kRefRound, int HR = kHitRound, class Visit>
+__device__ __forceinline__ int listed_range(const SurfaceView& sv, uint32_t* list, int slots,
+                                            uint32_t cx, uint32_t cy, uint32_t cz, uint32_t b,
+                                            uint32_t e, float px, float py, float pz,
+                                            Visit&& visit) {
+    const int nh = list_box_hits<RR>(sv, list, slots, cx, cy, cz, b, e);
     if (nh > slots) return visit_range<NARROW, RR>(sv, b, e, px, py, pz, visit);
     int contacts = 0;
     if constexpr (!NARROW) {
@@ -462,49 +525,21 @@ __device__ __forceinline__ int listed_range(const SurfaceView& sv, uint32_t* lis
             ++contacts;
         }
     } else {
-        for (int h0 = 0; h0 < nh; h0 += HR) {
-            const int n = min(nh - h0, HR);
-            uint32_t t[HR];
-            float4 g[HR][3];
-#pragma unroll
-            for (int q = 0; q < HR; ++q) t[q] = list[min(h0 + q, nh - 1) * 64];
-#pragma unroll
-            for (int q = 0; q < HR; ++q) {
-                const size_t id = t[q] & 0x7fffffffu;
-                g[q][0] = ldg4(sv.geo, 3 * id);
-                g[q][1] = ldg4(sv.geo, 3 * id + 1);
-                g[q][2] = ldg4(sv.geo, 3 * id + 2);
-            }
-            // live entries of the round as bits; undecided ones are settled with the exact
-            // box in one branch, which the wavefront skips when none of its lanes has one
-            uint32_t live = (1u << n) - 1u, und = 0;
-#pragma unroll
-            for (int q = 0; q < HR; ++q) und |= (t[q] >> 31) << q;
-            und &= live;
-            if (und) {
-#pragma unroll
-                for (int q = 0; q < HR; ++q)
-                    if ((und >> q) & 1u) {
-                        const uint32_t id = t[q] & 0x7fffffffu;
-                        if (!in_box(ldg4(sv.box_lo, id), ldg4(sv.box_hi, id), px, py, pz))
-                            live &= ~(1u << q);
-                    }
-            }
-            // (a wavefront skips a slot none of its lanes holds, e.g. in its last round)
-#pragma unroll
-            for (int q = 0; q < HR; ++q)
-                if ((live >> q) & 1u)
-                    contacts += narrow_visit(sv, t[q] & 0x7fffffffu, g[q][0], g[q][1], g[q][2],
-                                             px, py, pz, visit);
-        }
+        for (int h0 = 0; h0 < nh; h0 += HR)
+            hit_round<HR>(sv, list, nh, h0, px, py, pz,
+                          [&](int, uint32_t t, const float4& g0, const float4& g1,
+                              const float4& g2) {
+                              contacts += narrow_visit(sv, t, g0, g1, g2, px, py, pz, visit);
+                          });
     }
     return contacts;
 }
 
-// listed_range over the whole cell of p (no candidates outside the grid).
-template <bool NARROW = true, int HR = kHitRound, class Visit>
-__device__ __forceinline__ int contacts_listed(const SurfaceView& sv, uint32_t* list, int slots,
-                                               float px, float py, float pz, Visit&& visit) {
+// p's grid cell: its reference range [b, e) and p's point codes in it (point_code); false
+// when p's cell coordinate falls outside the grid (no candidates).
+__device__ __forceinline__ bool cell_refs(const SurfaceView& sv, float px, float py, float pz,
+                                          uint32_t& cx, uint32_t& cy, uint32_t& cz, uint32_t& b,
+                                          uint32_t& e) {
     const float gx = cell_coord_raw(px, sv.org[0], sv.inv_cell);
     const float gy = cell_coord_raw(py, sv.org[1], sv.inv_cell);
     const float gz = cell_coord_raw(pz, sv.org[2], sv.inv_cell);
@@ -512,12 +547,25 @@ __device__ __forceinline__ int contacts_listed(const SurfaceView& sv, uint32_t* 
     // the test of cell_of, on the same values
     if (!(fx >= 0.0f && fx <= (float)(sv.dim[0] - 1) && fy >= 0.0f &&
           fy <= (float)(sv.dim[1] - 1) && fz >= 0.0f && fz <= (float)(sv.dim[2] - 1)))
-        return 0;
+        return false;
     const int cell = ((int)fz * sv.dim[1] + (int)fy) * sv.dim[0] + (int)fx;
-    const uint32_t cx = point_code(gx, fx), cy = point_code(gy, fy), cz = point_code(gz, fz);
+    cx = point_code(gx, fx);
+    cy = point_code(gy, fy);
+    cz = point_code(gz, fz);
     const gptr<uint32_t> cs = gmem(sv.cell_start);
-    return listed_range<NARROW, kRefRound, HR>(sv, list, slots, cx, cy, cz, cs[cell],
-                                               cs[cell + 1], px, py, pz, visit);
+    b = cs[cell];
+    e = cs[cell + 1];
+    return true;
+}
+
+// listed_range over the whole cell of p (no candidates outside the grid).
+template <bool NARROW = true, int HR = kHitRound, class Visit>
+__device__ __forceinline__ int contacts_listed(const SurfaceView& sv, uint32_t* list, int slots,
+                                               float px, float py, float pz, Visit&& visit) {
+    uint32_t cx, cy, cz, b, e;
+    if (!cell_refs(sv, px, py, pz, cx, cy, cz, b, e)) return 0;
+    return listed_range<NARROW, kRefRound, HR>(sv, list, slots, cx, cy, cz, b, e, px, py, pz,
+                                               visit);
 }
 
 // collide_listed: contacts_listed with the averaged response (HR box hits per round of

@@ -190,13 +190,17 @@ hipError_t launch_substep(const ClothView& cv, int collide, const StepParams& sp
 // bit for bit; no second pass.
 // launch_substep through the grid stencil (grid_step.hip): one wavefront per 8x8 tile stages
 // the tile and a two-node halo in LDS and sums each node's springs from there, in the
-// incidence order; the same results, bit for bit.
+// incidence order; the same results, bit for bit.  waves = 2 (with collision) adds a second
+// wavefront per tile that takes every other round of the box hits' narrow tests (same
+// results); without collision one wavefront is launched either way.
 hipError_t launch_grid_substep(const ClothView& cv, const GridView& gv, int collide,
                                const StepParams& sp, const float* xs, const float* vs, float* xd,
                                float* vd, hipStream_t stream, const SurfaceView* svs,
-                               int grouped, int hit_slots, int xcd_runs, float* pred = nullptr);
+                               int grouped, int hit_slots, int xcd_runs, int waves,
+                               float* pred = nullptr);
 hipError_t prepare_grid_kernels(size_t lds_bytes);
-// Dynamic LDS of a stencil launch (the hit lists of its one wavefront per workgroup).
+// Dynamic LDS of a stencil launch (the hit lists of each tile's first wavefront, the only
+// one that lists hits).
 size_t grid_lds_bytes(int hit_slots);
 // Stencil parameter entries from per-spring entries: idx[q] = entry[code[q]], or kNoSpring
 // where code[q] < 0, and their byte form in idx8 (q = d * ld + p, see GridView), relative to

@@ -48,8 +48,11 @@ __device__ __forceinline__ int grid_slot(int first, int nx, int ny, int gr, int 
     return first + 8 * nx * tr + 8 * h * tc + (gr & 7) * w + (gc & 7);
 }
 
-template <bool COLLIDE, bool GROUPED, int HR>
-__global__ void __launch_bounds__(64, 2)
+// NW wavefronts per tile: with NW = 2 the second wavefront helps stage the region and takes
+// every other round of the box hits' narrow tests, and the first visits the contacts of both
+// in list order (the same arithmetic in the same order as NW = 1).
+template <bool COLLIDE, bool GROUPED, int HR, int NW>
+__global__ void __launch_bounds__(64 * NW, 2)
     k_grid(const ClothView cv, const GridView gv, const StepParams sp,
            const float* __restrict__ xs, const float* __restrict__ vs, float* __restrict__ xd,
            float* __restrict__ vd, const SurfaceView* __restrict__ svs, const int hit_slots,
@@ -57,16 +60,18 @@ __global__ void __launch_bounds__(64, 2)
     __shared__ float reg[6 * kRegion];  // x, y, z, vx, vy, vz of the region
     __shared__ float4 tab[kTabLds];
     extern __shared__ uint32_t hit_lds[];  // wave_query_lds(hit_slots) bytes
+    static_assert(NW == 1 || (NW == 2 && COLLIDE), "one wavefront, or two with collision");
+    constexpr int kThreads = 64 * NW;
     const int t = xcd_block(xcd_runs, gv.n_tiles);
-    if (t >= gv.n_tiles) return;  // the whole workgroup (one wavefront)
+    if (t >= gv.n_tiles) return;  // the whole workgroup
     const int4 cd = GROUPED ? gv.tiles[t] : gv.one;
     const int nx = cd.y & 0xffff, ny = cd.y >> 16;
     const int tl = t - cd.z, tx = (nx + 7) >> 3;
     const int gr0 = 8 * (tl / tx), gc0 = 8 * (tl % tx);
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ld = cv.ld;
     const int r = lane >> 3, c = lane & 7;
-    const bool active = gr0 + r < ny && gc0 + c < nx;
+    const bool active = wave == 0 && gr0 + r < ny && gc0 + c < nx;
     const int i = active ? grid_slot(cd.x, nx, ny, gr0 + r, gc0 + c) : 0;
 
     // 1. every load of the gather in one round
@@ -81,13 +86,17 @@ __global__ void __launch_bounds__(64, 2)
     const int n_tab = *gv.n_tab;
     const int tb = GROUPED && gv.tab_base ? gv.tab_base[cd.w] : 0;
     const int tab_here = min(gv.tab_cap - tb, kTabLds);
-    float4 tv0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), tv1 = tv0;
-    if (lane < tab_here) tv0 = ldg4(cv.ptab, tb + lane);
-    if (lane + 64 < tab_here) tv1 = ldg4(cv.ptab, tb + lane + 64);
-    float sv_[3][6];
+    constexpr int kTabIters = kTabLds / kThreads, kRegionIters = (kRegion + kThreads - 1) / kThreads;
+    float4 tv[kTabIters];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const int e = lane + 64 * j;
+    for (int j = 0; j < kTabIters; ++j) {
+        tv[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (tid + kThreads * j < tab_here) tv[j] = ldg4(cv.ptab, tb + tid + kThreads * j);
+    }
+    float sv_[kRegionIters][6];
+#pragma unroll
+    for (int j = 0; j < kRegionIters; ++j) {
+        const int e = tid + kThreads * j;
         const int gr = gr0 + e / kSide - 2, gc = gc0 + e % kSide - 2;
         const bool ok = e < kRegion && gr >= 0 && gr < ny && gc >= 0 && gc < nx;
 #pragma unroll
@@ -103,15 +112,15 @@ __global__ void __launch_bounds__(64, 2)
         }
     }
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const int e = lane + 64 * j;
+    for (int j = 0; j < kRegionIters; ++j) {
+        const int e = tid + kThreads * j;
         if (e < kRegion) {
 #pragma unroll
             for (int k = 0; k < 6; ++k) reg[k * kRegion + e] = sv_[j][k];
         }
     }
-    tab[lane] = tv0;
-    tab[lane + 64] = tv1;
+#pragma unroll
+    for (int j = 0; j < kTabIters; ++j) tab[tid + kThreads * j] = tv[j];
     __syncthreads();
 
     // the parameter entries of the node's springs, relative to the cloth's first: bytes
@@ -165,14 +174,85 @@ __global__ void __launch_bounds__(64, 2)
         }
     }
     // a3 + a4: broad phase, narrow phase, response (as k_substep)
-    if (COLLIDE && active && w != 0.0f) {
+    if constexpr (NW == 1) {
+        if (COLLIDE && active && w != 0.0f) {
+            const SurfaceView sv = svs[GROUPED ? cd.w : 0];
+            if (sv.n_tris > 0) {
+                if (hit_slots > 0)
+                    collide_listed<HR>(sv, hit_lds + lane, hit_slots, sp.restitution, px, py, pz,
+                                       qx, qy, qz);
+                else
+                    collide(sv, sp.restitution, px, py, pz, qx, qy, qz);
+            }
+        }
+    } else {
+        // the first wavefront lists its nodes' box hits; the hit rounds h0 = 0, HR, 2 HR, ...
+        // of each list alternate between the two wavefronts, each recording its contacts as
+        // bits of the list entries; the first then visits the contacts in list order
+        __shared__ float p_lds[3 * 64];
+        __shared__ int nh_lds[64];
+        __shared__ unsigned long long bits_lds[64];
         const SurfaceView sv = svs[GROUPED ? cd.w : 0];
-        if (sv.n_tris > 0) {
-            if (hit_slots > 0)
-                collide_listed<HR>(sv, hit_lds + lane, hit_slots, sp.restitution, px, py, pz, qx,
-                                   qy, qz);
-            else
+        const bool coll = active && w != 0.0f && sv.n_tris > 0;
+        int nh = -1;  // -1: no list (outside the grid, or no collision for this node)
+        uint32_t rb = 0, re = 0;
+        if (wave == 0) {
+            uint32_t cx, cy, cz;
+            if (coll && hit_slots > 0 && cell_refs(sv, px, py, pz, cx, cy, cz, rb, re))
+                nh = list_box_hits(sv, hit_lds + lane, hit_slots, cx, cy, cz, rb, re);
+            nh_lds[lane] = nh >= 0 && nh <= hit_slots ? nh : 0;
+            p_lds[lane] = px;
+            p_lds[64 + lane] = py;
+            p_lds[128 + lane] = pz;
+        }
+        __syncthreads();
+        unsigned long long bits = 0;
+        {
+            const int nl = nh_lds[lane];
+            const float bx = p_lds[lane], by = p_lds[64 + lane], bz = p_lds[128 + lane];
+            for (int h0 = wave * HR; h0 < nl; h0 += NW * HR)
+                hit_round<HR>(sv, hit_lds + lane, nl, h0, bx, by, bz,
+                              [&](int k, uint32_t id, const float4& g0, const float4& g1,
+                                  const float4& g2) {
+                                  narrow_visit(sv, id, g0, g1, g2, bx, by, bz,
+                                               [&](const float4&, float, uint32_t) {
+                                                   bits |= 1ull << k;
+                                               });
+                              });
+        }
+        if (wave == 1) bits_lds[lane] = bits;
+        __syncthreads();
+        if (wave == 1) return;
+        if (coll) {
+            if (hit_slots == 0) {
                 collide(sv, sp.restitution, px, py, pz, qx, qy, qz);
+            } else {
+                float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+                const float th = sv.thickness;
+                auto accumulate = [&](const float4& n, float s, uint32_t) {
+                    const float push = th - s;
+                    sx += push * n.x;
+                    sy += push * n.y;
+                    sz += push * n.z;
+                };
+                int cnt = 0;
+                if (nh > hit_slots) {
+                    cnt = visit_range<true, kRefRound>(sv, rb, re, px, py, pz, accumulate);
+                } else if (nh > 0) {
+                    for (unsigned long long m = bits | bits_lds[lane]; m; m &= m - 1ull) {
+                        const uint32_t id = hit_lds[lane + 64 * __builtin_ctzll(m)] & 0x7fffffffu;
+                        float4 n;
+                        float ax, ay, az;
+                        const float s = plane_offset(ldg4(sv.geo, 3 * (size_t)id),
+                                                     ldg4(sv.geo, 3 * (size_t)id + 1),
+                                                     ldg4(sv.geo, 3 * (size_t)id + 2), px, py,
+                                                     pz, n, ax, ay, az);
+                        accumulate(n, s, id);
+                        ++cnt;
+                    }
+                }
+                respond(cnt, sx, sy, sz, sp.restitution, px, py, pz, qx, qy, qz);
+            }
         }
     }
     if (!active) return;
@@ -217,10 +297,12 @@ size_t grid_lds_bytes(int hit_slots) { return wave_query_lds(hit_slots); }
 
 hipError_t prepare_grid_kernels(size_t lds_bytes) {
     if (lds_bytes <= 32 * 1024) return hipSuccess;
-    const void* fns[] = {(const void*)k_grid<true, false, kHitRound>,
-                         (const void*)k_grid<true, true, kHitRound>,
-                         (const void*)k_grid<true, false, kShortHitRound>,
-                         (const void*)k_grid<true, true, kShortHitRound>};
+    const void* fns[] = {(const void*)k_grid<true, false, kHitRound, 1>,
+                         (const void*)k_grid<true, true, kHitRound, 1>,
+                         (const void*)k_grid<true, false, kShortHitRound, 1>,
+                         (const void*)k_grid<true, true, kShortHitRound, 1>,
+                         (const void*)k_grid<true, false, kShortHitRound, 2>,
+                         (const void*)k_grid<true, true, kShortHitRound, 2>};
     for (const void* f : fns) {
         hipError_t e =
             hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
@@ -232,33 +314,42 @@ hipError_t prepare_grid_kernels(size_t lds_bytes) {
 hipError_t launch_grid_substep(const ClothView& cv, const GridView& gv, int collide,
                                const StepParams& sp, const float* xs, const float* vs, float* xd,
                                float* vd, hipStream_t stream, const SurfaceView* svs,
-                               int grouped, int hit_slots, int xcd_runs, float* pred) {
+                               int grouped, int hit_slots, int xcd_runs, int waves, float* pred) {
     if (gv.n_tiles <= 0) return hipSuccess;
     if (xcd_runs < 0 || xcd_runs > kMaxXcdRuns) xcd_runs = 0;
     if (hit_slots < 0 || hit_slots > kMaxHitSlots) return hipErrorInvalidValue;
+    if (waves != 1 && waves != 2) return hipErrorInvalidValue;
     const int grid = xcd_grid(gv.n_tiles, xcd_runs);
     const size_t lds = collide ? grid_lds_bytes(hit_slots) : 0;
     // short hit lists go with short rounds of geometry loads: fewer registers, more
-    // wavefronts per SIMD for workloads whose collision work is spread over many of them
+    // wavefronts per SIMD for workloads whose collision work is spread over many of them;
+    // the two-wavefront form always takes short rounds (at about 100 registers every tile of
+    // a 100K-node cloth is resident at once; rounds of eight need 166)
     const bool short_round = hit_slots <= kShortListSlots;
-    if (collide && grouped && short_round)
-        k_grid<true, true, kShortHitRound><<<grid, 64, lds, stream>>>(
+    if (collide && waves == 2 && grouped)
+        k_grid<true, true, kShortHitRound, 2><<<grid, 128, lds, stream>>>(
+            cv, gv, sp, xs, vs, xd, vd, svs, hit_slots, xcd_runs, pred);
+    else if (collide && waves == 2)
+        k_grid<true, false, kShortHitRound, 2><<<grid, 128, lds, stream>>>(
+            cv, gv, sp, xs, vs, xd, vd, svs, hit_slots, xcd_runs, pred);
+    else if (collide && grouped && short_round)
+        k_grid<true, true, kShortHitRound, 1><<<grid, 64, lds, stream>>>(
             cv, gv, sp, xs, vs, xd, vd, svs, hit_slots, xcd_runs, pred);
     else if (collide && grouped)
-        k_grid<true, true, kHitRound><<<grid, 64, lds, stream>>>(cv, gv, sp, xs, vs, xd, vd, svs,
-                                                                 hit_slots, xcd_runs, pred);
+        k_grid<true, true, kHitRound, 1><<<grid, 64, lds, stream>>>(
+            cv, gv, sp, xs, vs, xd, vd, svs, hit_slots, xcd_runs, pred);
     else if (collide && short_round)
-        k_grid<true, false, kShortHitRound><<<grid, 64, lds, stream>>>(
+        k_grid<true, false, kShortHitRound, 1><<<grid, 64, lds, stream>>>(
             cv, gv, sp, xs, vs, xd, vd, svs, hit_slots, xcd_runs, pred);
     else if (collide)
-        k_grid<true, false, kHitRound><<<grid, 64, lds, stream>>>(cv, gv, sp, xs, vs, xd, vd, svs,
-                                                                  hit_slots, xcd_runs, pred);
+        k_grid<true, false, kHitRound, 1><<<grid, 64, lds, stream>>>(
+            cv, gv, sp, xs, vs, xd, vd, svs, hit_slots, xcd_runs, pred);
     else if (grouped)
-        k_grid<false, true, kHitRound><<<grid, 64, 0, stream>>>(cv, gv, sp, xs, vs, xd, vd, svs, 0,
-                                                                xcd_runs, pred);
+        k_grid<false, true, kHitRound, 1><<<grid, 64, 0, stream>>>(cv, gv, sp, xs, vs, xd, vd,
+                                                                   svs, 0, xcd_runs, pred);
     else
-        k_grid<false, false, kHitRound><<<grid, 64, 0, stream>>>(cv, gv, sp, xs, vs, xd, vd, svs,
-                                                                 0, xcd_runs, pred);
+        k_grid<false, false, kHitRound, 1><<<grid, 64, 0, stream>>>(cv, gv, sp, xs, vs, xd, vd,
+                                                                    svs, 0, xcd_runs, pred);
     return hipGetLastError();
 }
 

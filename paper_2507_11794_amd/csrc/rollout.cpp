@@ -202,7 +202,11 @@ int cloth_rollout_backward(cloth_sim* s, const float* gx_out_dev, float* gk_dev,
             e = s->dev.sten_code
                     ? launch_grid_substep(cv, s->dev.grid_view(), collide, sp, xs, xs + 3 * ld, xd,
                                           xd + 3 * ld, s->stream, s->svs_dev, 0,
-                                          s->launch.hit_slots, s->launch.xcd_runs, pr)
+                                          s->launch.hit_slots, s->launch.xcd_runs,
+                                          s->launch.kernel == CLOTH_KERNEL_GRID
+                                              ? s->launch.block_threads / 64
+                                              : 1,
+                                          pr)
                     : launch_substep(cv, collide, sp, xs, xs + 3 * ld, xd, xd + 3 * ld, 256,
                                      s->stream, s->svs_dev, nullptr, s->launch.hit_slots, 0, 0,
                                      nullptr, 0, pr);

@@ -167,7 +167,8 @@ int set_launch(cloth_sim* s, const cloth_launch& cfg) {
         norm.schedule = CLOTH_SCHED_GRID;
         norm.workgroups = 0;
     }
-    if (cfg.kernel == CLOTH_KERNEL_GRID) norm.block_threads = 64;  // one wavefront per tile
+    // grid kernel: one wavefront per tile, or two (128 threads and more ask for two)
+    if (cfg.kernel == CLOTH_KERNEL_GRID) norm.block_threads = cfg.block_threads >= 128 ? 128 : 64;
     if (cfg.kernel != CLOTH_KERNEL_DIRECT) norm.split_refs = 0;
     if (std::memcmp(&norm, &s->launch, sizeof(cloth_launch)) != 0) {
         // captured graphs hold the old configuration's kernels and arguments
@@ -211,7 +212,8 @@ hipError_t launch_once(cloth_sim* s, const StepParams& sp, int K, int src, hipSt
             s->dev.view(), s->dev.grid_view(),
             s->groups.size() == 1 ? s->surfs[0].view.n_tris > 0 : s->any_collision, sp,
             s->dev.x[src], s->dev.v[src], s->dev.x[dst], s->dev.v[dst], st, s->svs_dev,
-            s->groups.size() > 1, s->launch.hit_slots, s->launch.xcd_runs);
+            s->groups.size() > 1, s->launch.hit_slots, s->launch.xcd_runs,
+            s->launch.block_threads / 64);
     if (s->launch.kernel == CLOTH_KERNEL_LANES2 || s->launch.kernel == CLOTH_KERNEL_LANES4)
         return launch_substep_lanes(
             s->launch.kernel == CLOTH_KERNEL_LANES2 ? 2 : 4, s->dev.view(),
@@ -604,8 +606,12 @@ int create_sim(const std::vector<ClothHostInput>& cloths, const cloth_params* p,
             // -> 14.7 us on the draped 316x316 cloth (hardware order, or one contiguous run
             // per XCD, which puts the contact region on one or two XCDs: 17.5 us)
             s->launch.kernel = CLOTH_KERNEL_GRID;
-            s->launch.block_threads = 64;
             s->launch.xcd_runs = 16;
+            // a second wavefront per tile takes every other round of the narrow tests of the
+            // nodes resting on the surface: 14.9 -> 13.8 us per substep on the draped 316x316
+            // cloth, 7.0 -> 7.2 us in free fall; slower for the 512-cloth batch, whose
+            // collision work is spread over many wavefronts (138 -> 187 us), so one there
+            s->launch.block_threads = s->groups.size() == 1 && s->any_collision ? 128 : 64;
         }
         if (st == CLOTH_OK && (p->flags & CLOTH_F_NARROW_MT) && s->any_collision) {
             s->mt = true;

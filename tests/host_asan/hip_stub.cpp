@@ -207,7 +207,7 @@ size_t lanes_lds_bytes(int block, int hit_slots) {
 hipError_t prepare_lanes_kernels(size_t) { return hipSuccess; }
 hipError_t launch_grid_substep(const ClothView&, const GridView&, int, const StepParams&,
                                const float*, const float*, float*, float*, hipStream_t,
-                               const SurfaceView*, int, int, int, float*) {
+                               const SurfaceView*, int, int, int, int, float*) {
     return hipSuccess;
 }
 hipError_t prepare_grid_kernels(size_t) { return hipSuccess; }

@@ -331,7 +331,8 @@ def test_gradients_independent_of_the_hit_list_length():
     grads = []
     for cfg in (dict(hit_slots=32), dict(hit_slots=0), dict(hit_slots=2), dict(hit_slots=64),
                 dict(kernel=B.CLOTH_KERNEL_LANES4, hit_slots=8, block_threads=64),
-                dict(kernel=B.CLOTH_KERNEL_GRID)):
+                dict(kernel=B.CLOTH_KERNEL_GRID, block_threads=64),
+                dict(kernel=B.CLOTH_KERNEL_GRID, block_threads=128)):
         with B.Cloth(inp) as sim:
             sim.set_launch(**cfg)
             k = torch.tensor(inp.k, device=dev, requires_grad=True)

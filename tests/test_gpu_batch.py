@@ -63,6 +63,7 @@ def test_batch_parameter_tables_per_cloth_equal_plain_handles(case):
     frames = 10
     with B.ClothBatch(cl) as b:
         assert b.get_launch()["kernel"] == B.CLOTH_KERNEL_GRID
+        assert b.get_launch()["block_threads"] == 64  # one wavefront per tile for batches
         b.step(n_steps=frames)
         got = [b.read_state(i) for i in range(len(cl))]
     for i, c in enumerate(cl):
@@ -79,8 +80,10 @@ SCHEDULES = [
          schedule=B.CLOTH_SCHED_RR, workgroups=7, use_graph=0),
     dict(kernel=B.CLOTH_KERNEL_LANES4, block_threads=64, hit_slots=8),
     dict(kernel=B.CLOTH_KERNEL_LANES2, block_threads=256, hit_slots=4, xcd_runs=2),
-    dict(kernel=B.CLOTH_KERNEL_GRID),
-    dict(kernel=B.CLOTH_KERNEL_GRID, hit_slots=4, xcd_runs=2),
+    dict(kernel=B.CLOTH_KERNEL_GRID, block_threads=64),
+    dict(kernel=B.CLOTH_KERNEL_GRID, block_threads=64, hit_slots=4, xcd_runs=2),
+    dict(kernel=B.CLOTH_KERNEL_GRID, block_threads=128),
+    dict(kernel=B.CLOTH_KERNEL_GRID, block_threads=128, hit_slots=4, xcd_runs=2),
 ]
 
 

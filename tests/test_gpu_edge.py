@@ -130,24 +130,27 @@ def test_every_spring_with_its_own_parameters():
 
 @pytest.mark.parametrize("shape", [(1, 37), (37, 1), (2, 2), (3, 5), (9, 17), (65, 3), (20, 20)])
 def test_grid_kernel_on_ragged_shapes_equals_the_one_thread_kernel(shape):
-    """The stencil kernel on cloths whose sides are not multiples of the 8x8 tile (narrow
+    """The stencil kernel, with one and with two wavefronts per tile, on cloths whose sides are not multiples of the 8x8 tile (narrow
     last tile columns, short last tile rows, one-node-wide strips), over the floor triangle
     with a pinned corner: the same bits as the one-thread-per-node kernel after every frame,
     and its node order is the grid's tiles row by row."""
     nx, ny = shape
     inp = _scene(nx, ny, drop=0.012, spacing=0.008, pins=[(0, 0)], n_steps=30)
     outs = []
-    for kernel in (B.CLOTH_KERNEL_DIRECT, B.CLOTH_KERNEL_GRID):
+    for cfg in (dict(kernel=B.CLOTH_KERNEL_DIRECT, block_threads=64),
+                dict(kernel=B.CLOTH_KERNEL_GRID, block_threads=64),
+                dict(kernel=B.CLOTH_KERNEL_GRID, block_threads=128)):
         with B.Cloth(inp) as sim:
-            sim.set_launch(kernel=kernel)
+            sim.set_launch(**cfg)
             states = []
             for _ in range(inp.n_steps):
                 sim.step(n_steps=1)
                 states.append(sim.read_state())
             order = sim.node_order()
         outs.append(states)
-    for (xa, va), (xb, vb) in zip(*outs):
-        assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+    for other in outs[1:]:
+        for (xa, va), (xb, vb) in zip(outs[0], other):
+            assert np.array_equal(xa, xb) and np.array_equal(va, vb)
     want = [i * nx + j for tj in range(0, ny, 8) for ti in range(0, nx, 8)
             for i in range(tj, min(ny, tj + 8)) for j in range(ti, min(nx, ti + 8))]
     assert np.array_equal(order, want)

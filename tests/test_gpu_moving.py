@@ -113,7 +113,8 @@ LAUNCHES = [
     dict(kernel=B.CLOTH_KERNEL_DIRECT, use_graph=1, hit_slots=0),
     dict(kernel=B.CLOTH_KERNEL_DIRECT, use_graph=1, hit_slots=16),
     dict(kernel=B.CLOTH_KERNEL_LANES4, use_graph=1, hit_slots=8, block_threads=64),
-    dict(kernel=B.CLOTH_KERNEL_GRID, use_graph=1),
+    dict(kernel=B.CLOTH_KERNEL_GRID, use_graph=1, block_threads=64),
+    dict(kernel=B.CLOTH_KERNEL_GRID, use_graph=1, block_threads=128),
 ]
 
 

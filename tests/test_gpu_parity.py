@@ -266,9 +266,13 @@ LAUNCHES = [
     dict(kernel=B.CLOTH_KERNEL_LANES4, block_threads=64, use_graph=1, hit_slots=8),
     dict(kernel=B.CLOTH_KERNEL_LANES4, block_threads=128, use_graph=1, hit_slots=1),
     dict(kernel=B.CLOTH_KERNEL_LANES4, block_threads=256, use_graph=0, hit_slots=0, xcd_runs=1),
-    dict(kernel=B.CLOTH_KERNEL_GRID, use_graph=1),
-    dict(kernel=B.CLOTH_KERNEL_GRID, use_graph=0, hit_slots=0),
-    dict(kernel=B.CLOTH_KERNEL_GRID, use_graph=1, hit_slots=4, xcd_runs=3),
+    dict(kernel=B.CLOTH_KERNEL_GRID, block_threads=64, use_graph=1),
+    dict(kernel=B.CLOTH_KERNEL_GRID, block_threads=64, use_graph=0, hit_slots=0),
+    dict(kernel=B.CLOTH_KERNEL_GRID, block_threads=64, use_graph=1, hit_slots=4, xcd_runs=3),
+    dict(kernel=B.CLOTH_KERNEL_GRID, block_threads=128, use_graph=1),
+    dict(kernel=B.CLOTH_KERNEL_GRID, block_threads=128, use_graph=0, hit_slots=0),
+    dict(kernel=B.CLOTH_KERNEL_GRID, block_threads=128, use_graph=1, hit_slots=4, xcd_runs=3),
+    dict(kernel=B.CLOTH_KERNEL_GRID, block_threads=256, use_graph=1, hit_slots=64, xcd_runs=16),
 ]
 
 
@@ -300,7 +304,9 @@ def test_default_and_tile_kernels_match_oracle_one_substep(kernel):
     model = oracle.Model.from_inputs(inp)
     with B.Cloth(inp) as sim:
         if kernel == B.CLOTH_KERNEL_GRID:
-            assert sim.get_launch()["kernel"] == B.CLOTH_KERNEL_GRID  # the default
+            # the default for one grid cloth with a surface: two wavefronts per tile
+            assert sim.get_launch()["kernel"] == B.CLOTH_KERNEL_GRID
+            assert sim.get_launch()["block_threads"] == 128
         else:
             sim.set_launch(kernel=kernel, block_threads=256 if kernel == B.CLOTH_KERNEL_TILE else 64)
         sim.step(n_steps=120)
@@ -346,8 +352,10 @@ def test_sliver_triangles_listed_and_unlisted_queries_agree():
                 dict(kernel=B.CLOTH_KERNEL_LANES4, hit_slots=8, block_threads=64),
                 dict(kernel=B.CLOTH_KERNEL_LANES2, hit_slots=2, block_threads=128),
                 dict(kernel=B.CLOTH_KERNEL_LANES4, hit_slots=0, block_threads=64),
-                dict(kernel=B.CLOTH_KERNEL_GRID, hit_slots=64),
-                dict(kernel=B.CLOTH_KERNEL_GRID, hit_slots=2)):
+                dict(kernel=B.CLOTH_KERNEL_GRID, hit_slots=64, block_threads=64),
+                dict(kernel=B.CLOTH_KERNEL_GRID, hit_slots=2, block_threads=64),
+                dict(kernel=B.CLOTH_KERNEL_GRID, hit_slots=64, block_threads=128),
+                dict(kernel=B.CLOTH_KERNEL_GRID, hit_slots=2, block_threads=128)):
         with B.Cloth(inp) as sim:
             if cfg:
                 sim.set_launch(**cfg)
