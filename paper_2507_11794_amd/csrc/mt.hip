@@ -86,30 +86,48 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? l
 // reference boxes tested per round of loads.
 constexpr int kMtSlots = 24;
 constexpr int kMtRefRound = 8;
+constexpr int kMtLanes = 4;  // lanes per node of the stepping kernel
 
-template <bool DEBUG>
+// LANES lanes per node, in LANES consecutive wavefronts of a 256-thread workgroup: lane j
+// takes the cells of the node's query box whose ordinal is j modulo LANES, and lanes 1 ..
+// LANES - 1 add their contact sums to lane 0's through LDS, in that order (the debug form
+// keeps one lane per node, so each node's ids are written by one thread in test order).
+template <int LANES>
+constexpr int mt_nodes_per_block() { return 256 / LANES; }
+
+template <bool DEBUG, int LANES>
 __global__ void __launch_bounds__(256)
     k_mt_collide(const ClothView cv, const StepParams sp, const int* __restrict__ order,
                  const int* __restrict__ slot, const int* __restrict__ node_group,
                  const int4* __restrict__ groups, const SurfaceView* __restrict__ svs,
                  const float* __restrict__ xs, const float* __restrict__ P, float* __restrict__ xd,
                  float* __restrict__ vd, int* __restrict__ counts, int* __restrict__ ids, int cap) {
-    __shared__ uint32_t lists[4 * 64 * kMtSlots];  // each lane's list: every 64th word
+    static_assert(LANES == 1 || LANES == 2 || LANES == 4, "1, 2 or 4 lanes per node");
+    static_assert(!(DEBUG && LANES > 1), "the debug form runs one lane per node");
+    constexpr bool SPLIT = LANES > 1;
+    constexpr int kNodes = mt_nodes_per_block<LANES>();
+    __shared__ uint32_t lists[4 * 64 * kMtSlots];   // each lane's list: every 64th word
+    __shared__ float4 part[SPLIT ? LANES - 1 : 1][SPLIT ? kNodes : 1];  // lanes 1..: sums, counts
     uint32_t* list = lists + (threadIdx.x >> 6) * 64 * kMtSlots + (threadIdx.x & 63);
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= cv.n) return;
+    const int lane = threadIdx.x & 63;
+    const int half = SPLIT ? (threadIdx.x >> 6) % LANES : 0;  // this lane's share of the cells
+    const int pair = SPLIT ? (threadIdx.x >> 6) / LANES * 64 + lane : 0;  // the node in part
+    const int p = SPLIT ? blockIdx.x * kNodes + pair : blockIdx.x * blockDim.x + threadIdx.x;
+    if (!SPLIT && p >= cv.n) return;
+    const bool node = p < cv.n;  // (with SPLIT every thread reaches the barrier below)
     const int ld = cv.ld;
+    const int pn = node ? p : 0;
     const float* Pv = P + 3 * (size_t)ld;
-    float3 xp = make_float3(P[p], P[ld + p], P[2 * ld + p]);
-    float3 vp = make_float3(Pv[p], Pv[ld + p], Pv[2 * ld + p]);
-    const float w = cv.w[p];
-    const int g = node_group ? node_group[p] : 0;
+    float3 xp = make_float3(P[pn], P[ld + pn], P[2 * ld + pn]);
+    float3 vp = make_float3(Pv[pn], Pv[ld + pn], Pv[2 * ld + pn]);
+    const float w = cv.w[pn];
+    const int g = node_group ? node_group[pn] : 0;
     const SurfaceView sv = svs[g];
     int cnt = 0;
     float3 acc = make_float3(0.0f, 0.0f, 0.0f);
-    if (w != 0.0f && sv.n_tris > 0) {
+    if (node && w != 0.0f && sv.n_tris > 0) {
         const int4 G = groups[g];  // node_off, nx, ny
-        const int id = order[p], loc = id - G.x, nx = G.y, ny = G.z;
+        const int id = order[pn], loc = id - G.x, nx = G.y, ny = G.z;
         const int row = loc / nx, col = loc - row * nx;
         // cloth-edge neighbours in the order (0,+1) (0,-1) (+1,0) (-1,0) (+1,+1) (-1,-1);
         // absent ones have ok = false
@@ -122,10 +140,10 @@ __global__ void __launch_bounds__(256)
             const int r2 = row + dr[k], c2 = col + dc[k];
             ok[k] = r2 >= 0 && c2 >= 0 && r2 < ny && c2 < nx;
             nid[k] = id + dr[k] * nx + dc[k];
-            const int sk = ok[k] ? slot[nid[k]] : p;
+            const int sk = ok[k] ? slot[nid[k]] : pn;
             q[k] = make_float3(P[sk], P[ld + sk], P[2 * ld + sk]);
         }
-        const float3 x0 = make_float3(xs[p], xs[ld + p], xs[2 * ld + p]);
+        const float3 x0 = make_float3(xs[pn], xs[ld + pn], xs[2 * ld + pn]);
         // query box: path and neighbours (every cloth triangle at i is spanned by them)
         float3 lo = make_float3(fminf(x0.x, xp.x), fminf(x0.y, xp.y), fminf(x0.z, xp.z));
         float3 hi = make_float3(fmaxf(x0.x, xp.x), fmaxf(x0.y, xp.y), fmaxf(x0.z, xp.z));
@@ -235,14 +253,18 @@ __global__ void __launch_bounds__(256)
             // lanes of the wavefront test their listed candidates together, in listing order,
             // each triangle's box and vertices loaded one candidate ahead.  A triangle whose
             // box meets the query box is listed in the first query cell that lists it, so
-            // each candidate is listed once.
-            int cx = q0x, cy = q0y, cz = q0z;
-            uint32_t r = gmem(sv.cell_start)[(cz * sv.dim[1] + cy) * sv.dim[0] + cx];
-            uint32_t e = gmem(sv.cell_start)[(cz * sv.dim[1] + cy) * sv.dim[0] + cx + 1];
+            // each candidate is listed once.  A lane takes the query cells whose ordinal (x
+            // fastest, then y, then z) is its share modulo LANES.
+            int cx = q0x, cy = q0y, cz = q0z, ci = 0;
+            uint32_t r = 0, e = 0;
+            if (half == 0) {
+                r = gmem(sv.cell_start)[(cz * sv.dim[1] + cy) * sv.dim[0] + cx];
+                e = gmem(sv.cell_start)[(cz * sv.dim[1] + cy) * sv.dim[0] + cx + 1];
+            }
             bool done = false;
             int nl = 0;
             for (;;) {
-                while (!done && r >= e) {  // the next query cell
+                while (!done && r >= e) {  // the next query cell (of this lane's half)
                     if (++cx > q1x) {
                         cx = q0x;
                         if (++cy > q1y) {
@@ -250,7 +272,8 @@ __global__ void __launch_bounds__(256)
                             if (++cz > q1z) done = true;
                         }
                     }
-                    if (!done) {
+                    ++ci;
+                    if (!done && ci % LANES == half) {
                         const int cell = (cz * sv.dim[1] + cy) * sv.dim[0] + cx;
                         r = gmem(sv.cell_start)[cell];
                         e = gmem(sv.cell_start)[cell + 1];
@@ -310,6 +333,20 @@ __global__ void __launch_bounds__(256)
         counts[p] = cnt;
         return;
     }
+    if constexpr (SPLIT) {
+        // the other lanes' sums and counts, added to the first's in lane order
+        if (half > 0) part[half - 1][pair] = make_float4(acc.x, acc.y, acc.z, __int_as_float(cnt));
+        __syncthreads();
+        if (half > 0 || !node) return;
+#pragma unroll
+        for (int j = 0; j < LANES - 1; ++j) {
+            const float4 o = part[j][pair];
+            acc.x += o.x;
+            acc.y += o.y;
+            acc.z += o.z;
+            cnt += __float_as_int(o.w);
+        }
+    }
     if (cnt > 0) {
         const float inv = 1.0f / (float)cnt;
         xp.x += acc.x * inv;
@@ -340,9 +377,10 @@ hipError_t launch_mt_substep(const ClothView& cv, const StepParams& sp, const Mt
     // prediction without collision into P, then the contact search and response
     hipError_t e = launch_substep(cv, 0, sp, xs, vs, P, P + 3 * (size_t)cv.ld, block, st, svs);
     if (e != hipSuccess) return e;
-    k_mt_collide<false><<<(cv.n + 255) / 256, 256, 0, st>>>(cv, sp, tp.order, tp.slot,
-                                                            tp.node_group, tp.groups, svs, xs, P,
-                                                            xd, vd, nullptr, nullptr, 0);
+    constexpr int per = mt_nodes_per_block<kMtLanes>();
+    k_mt_collide<false, kMtLanes><<<(cv.n + per - 1) / per, 256, 0, st>>>(
+        cv, sp, tp.order, tp.slot, tp.node_group, tp.groups, svs, xs, P, xd, vd, nullptr, nullptr,
+        0);
     return hipGetLastError();
 }
 
@@ -353,9 +391,10 @@ hipError_t launch_mt_debug_contacts(const ClothView& cv, const StepParams& sp,
     if (cv.n <= 0) return hipSuccess;
     hipError_t e = launch_substep(cv, 0, sp, xs, vs, P, P + 3 * (size_t)cv.ld, 256, st, svs);
     if (e != hipSuccess) return e;
-    k_mt_collide<true><<<(cv.n + 255) / 256, 256, 0, st>>>(cv, sp, tp.order, tp.slot,
-                                                           tp.node_group, tp.groups, svs, xs, P,
-                                                           nullptr, nullptr, counts, ids, cap);
+    constexpr int per = mt_nodes_per_block<1>();
+    k_mt_collide<true, 1><<<(cv.n + per - 1) / per, 256, 0, st>>>(
+        cv, sp, tp.order, tp.slot, tp.node_group, tp.groups, svs, xs, P, nullptr, nullptr, counts,
+        ids, cap);
     return hipGetLastError();
 }
 
