@@ -1,8 +1,9 @@
 // Triangle-triangle narrow phase (the extended Moller-Trumbore process of Sec. 3) as an
 // alternative to the point-triangle proximity test.  A substep is two launches: the
 // collision-free prediction of every node (forces and integration, into a scratch state),
-// then one thread per node that finds the node's contact set from the predictions of its
-// cloth neighbours and responds.  Surface triangle t is a contact of node i when
+// then four lanes per node (each scanning a quarter of the node's query cells) that find the
+// node's contact set from the predictions of its cloth neighbours, and the response.
+// Surface triangle t is a contact of node i when
 //   (A) a cloth edge at i crosses t (oriented from the lower node id),
 //   (B) an edge of t (oriented from the lower vertex id) crosses a cloth triangle at i, or
 //   (C) i's path from its start position to its prediction crosses t.
