@@ -558,14 +558,16 @@ __device__ __forceinline__ bool cell_refs(const SurfaceView& sv, float px, float
     return true;
 }
 
-// listed_range over the whole cell of p (no candidates outside the grid).
+// listed_range over the whole cell of p (no candidates outside the grid).  Short rounds of
+// box hits (HR <= 4) go with short rounds of references as well: fewer registers, for
+// collision work spread over many wavefronts.
 template <bool NARROW = true, int HR = kHitRound, class Visit>
 __device__ __forceinline__ int contacts_listed(const SurfaceView& sv, uint32_t* list, int slots,
                                                float px, float py, float pz, Visit&& visit) {
+    constexpr int RR = HR <= 4 ? 4 : kRefRound;
     uint32_t cx, cy, cz, b, e;
     if (!cell_refs(sv, px, py, pz, cx, cy, cz, b, e)) return 0;
-    return listed_range<NARROW, kRefRound, HR>(sv, list, slots, cx, cy, cz, b, e, px, py, pz,
-                                               visit);
+    return listed_range<NARROW, RR, HR>(sv, list, slots, cx, cy, cz, b, e, px, py, pz, visit);
 }
 
 // collide_listed: contacts_listed with the averaged response (HR box hits per round of

@@ -321,8 +321,8 @@ hipError_t launch_grid_substep(const ClothView& cv, const GridView& gv, int coll
     if (waves != 1 && waves != 2) return hipErrorInvalidValue;
     const int grid = xcd_grid(gv.n_tiles, xcd_runs);
     const size_t lds = collide ? grid_lds_bytes(hit_slots) : 0;
-    // short hit lists go with short rounds of geometry loads: fewer registers, more
-    // wavefronts per SIMD for workloads whose collision work is spread over many of them;
+    // short hit lists go with short rounds of geometry and reference loads: fewer registers,
+    // more wavefronts per SIMD for workloads whose collision work is spread over many of them;
     // the two-wavefront form always takes short rounds (at about 100 registers every tile of
     // a 100K-node cloth is resident at once; rounds of eight need 166)
     const bool short_round = hit_slots <= kShortListSlots;
