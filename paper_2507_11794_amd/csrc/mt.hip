@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(256)
     __shared__ float4 part[SPLIT ? LANES - 1 : 1][SPLIT ? kNodes : 1];  // lanes 1..: sums, counts
     uint32_t* list = lists + (threadIdx.x >> 6) * 64 * kMtSlots + (threadIdx.x & 63);
     const int lane = threadIdx.x & 63;
-    const int half = SPLIT ? (threadIdx.x >> 6) % LANES : 0;  // this lane's share of the cells
+    const int share = SPLIT ? (threadIdx.x >> 6) % LANES : 0;  // this lane's share of the cells
     const int pair = SPLIT ? (threadIdx.x >> 6) / LANES * 64 + lane : 0;  // the node in part
     const int p = SPLIT ? blockIdx.x * kNodes + pair : blockIdx.x * blockDim.x + threadIdx.x;
     if (!SPLIT && p >= cv.n) return;
@@ -258,14 +258,14 @@ __global__ void __launch_bounds__(256)
             // fastest, then y, then z) is its share modulo LANES.
             int cx = q0x, cy = q0y, cz = q0z, ci = 0;
             uint32_t r = 0, e = 0;
-            if (half == 0) {
+            if (share == 0) {
                 r = gmem(sv.cell_start)[(cz * sv.dim[1] + cy) * sv.dim[0] + cx];
                 e = gmem(sv.cell_start)[(cz * sv.dim[1] + cy) * sv.dim[0] + cx + 1];
             }
             bool done = false;
             int nl = 0;
             for (;;) {
-                while (!done && r >= e) {  // the next query cell (of this lane's half)
+                while (!done && r >= e) {  // the next query cell (of this lane's share)
                     if (++cx > q1x) {
                         cx = q0x;
                         if (++cy > q1y) {
@@ -274,7 +274,7 @@ __global__ void __launch_bounds__(256)
                         }
                     }
                     ++ci;
-                    if (!done && ci % LANES == half) {
+                    if (!done && ci % LANES == share) {
                         const int cell = (cz * sv.dim[1] + cy) * sv.dim[0] + cx;
                         r = gmem(sv.cell_start)[cell];
                         e = gmem(sv.cell_start)[cell + 1];
@@ -336,9 +336,9 @@ __global__ void __launch_bounds__(256)
     }
     if constexpr (SPLIT) {
         // the other lanes' sums and counts, added to the first's in lane order
-        if (half > 0) part[half - 1][pair] = make_float4(acc.x, acc.y, acc.z, __int_as_float(cnt));
+        if (share > 0) part[share - 1][pair] = make_float4(acc.x, acc.y, acc.z, __int_as_float(cnt));
         __syncthreads();
-        if (half > 0 || !node) return;
+        if (share > 0 || !node) return;
 #pragma unroll
         for (int j = 0; j < LANES - 1; ++j) {
             const float4 o = part[j][pair];
