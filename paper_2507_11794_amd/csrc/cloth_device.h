@@ -382,6 +382,20 @@ __device__ __forceinline__ int contacts_visit(const SurfaceView& sv, float px, f
     return visit_range<NARROW>(sv, cs[cell], cs[cell + 1], px, py, pz, visit);
 }
 
+// The sum that the averaged response divides by the contact count: (th - s) n over the
+// contacts, in the order they are visited (a visitor for the contact searches).
+struct PushSum {
+    float th;
+    float x = 0.0f, y = 0.0f, z = 0.0f;
+    __device__ explicit PushSum(float thickness) : th(thickness) {}
+    __device__ __forceinline__ void operator()(const float4& n, float s, uint32_t) {
+        const float push = th - s;
+        x += push * n.x;
+        y += push * n.y;
+        z += push * n.z;
+    }
+};
+
 // Response of Alg. 2 with the averaged direction: with at least one contact, p moves by the
 // mean of (th - s_t) n_t over the contacts and q becomes -restitution q.
 __device__ __forceinline__ void respond(int cnt, float sx, float sy, float sz, float restitution,
@@ -400,15 +414,9 @@ __device__ __forceinline__ void respond(int cnt, float sx, float sy, float sz, f
 
 __device__ __forceinline__ int collide(const SurfaceView& sv, float restitution, float& px,
                                        float& py, float& pz, float& qx, float& qy, float& qz) {
-    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
-    const float th = sv.thickness;
-    const int cnt = contacts_visit(sv, px, py, pz, [&](const float4& n, float s, uint32_t) {
-        const float push = th - s;
-        sx += push * n.x;
-        sy += push * n.y;
-        sz += push * n.z;
-    });
-    respond(cnt, sx, sy, sz, restitution, px, py, pz, qx, qy, qz);
+    PushSum sum(sv.thickness);
+    const int cnt = contacts_visit(sv, px, py, pz, sum);
+    respond(cnt, sum.x, sum.y, sum.z, restitution, px, py, pz, qx, qy, qz);
     return cnt;
 }
 
@@ -576,16 +584,9 @@ template <int HR = kHitRound>
 __device__ __forceinline__ int collide_listed(const SurfaceView& sv, uint32_t* list, int slots,
                                               float restitution, float& px, float& py,
                                               float& pz, float& qx, float& qy, float& qz) {
-    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
-    const float th = sv.thickness;
-    auto accumulate = [&](const float4& n, float s, uint32_t) {
-        const float push = th - s;
-        sx += push * n.x;
-        sy += push * n.y;
-        sz += push * n.z;
-    };
-    const int contacts = contacts_listed<true, HR>(sv, list, slots, px, py, pz, accumulate);
-    respond(contacts, sx, sy, sz, restitution, px, py, pz, qx, qy, qz);
+    PushSum sum(sv.thickness);
+    const int contacts = contacts_listed<true, HR>(sv, list, slots, px, py, pz, sum);
+    respond(contacts, sum.x, sum.y, sum.z, restitution, px, py, pz, qx, qy, qz);
     return contacts;
 }
 

@@ -227,17 +227,10 @@ __global__ void __launch_bounds__(64 * NW, 2)
             if (hit_slots == 0) {
                 collide(sv, sp.restitution, px, py, pz, qx, qy, qz);
             } else {
-                float sx = 0.0f, sy = 0.0f, sz = 0.0f;
-                const float th = sv.thickness;
-                auto accumulate = [&](const float4& n, float s, uint32_t) {
-                    const float push = th - s;
-                    sx += push * n.x;
-                    sy += push * n.y;
-                    sz += push * n.z;
-                };
+                PushSum sum(sv.thickness);
                 int cnt = 0;
                 if (nh > hit_slots) {
-                    cnt = visit_range<true, kRefRound>(sv, rb, re, px, py, pz, accumulate);
+                    cnt = visit_range<true, kRefRound>(sv, rb, re, px, py, pz, sum);
                 } else if (nh > 0) {
                     for (unsigned long long m = bits | bits_lds[lane]; m; m &= m - 1ull) {
                         const uint32_t id = hit_lds[lane + 64 * __builtin_ctzll(m)] & 0x7fffffffu;
@@ -247,11 +240,11 @@ __global__ void __launch_bounds__(64 * NW, 2)
                                                      ldg4(sv.geo, 3 * (size_t)id + 1),
                                                      ldg4(sv.geo, 3 * (size_t)id + 2), px, py,
                                                      pz, n, ax, ay, az);
-                        accumulate(n, s, id);
+                        sum(n, s, id);
                         ++cnt;
                     }
                 }
-                respond(cnt, sx, sy, sz, sp.restitution, px, py, pz, qx, qy, qz);
+                respond(cnt, sum.x, sum.y, sum.z, sp.restitution, px, py, pz, qx, qy, qz);
             }
         }
     }

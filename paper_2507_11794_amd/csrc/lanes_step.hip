@@ -192,19 +192,13 @@ __global__ void __launch_bounds__(256)
             const int most = max(max(n0, n1), max(n2, n3));
             if (most > kLaneContacts) {
                 // a lane kept too few: the one-lane query over the whole cell
-                float sx = 0.0f, sy = 0.0f, sz = 0.0f;
-                auto accumulate = [&](const float4& n, float s, uint32_t) {
-                    const float push = th - s;
-                    sx += push * n.x;
-                    sy += push * n.y;
-                    sz += push * n.z;
-                };
+                PushSum sum(th);
                 const int cnt =
                     hit_slots > 0
                         ? listed_range<true, kLaneRefRound, kLaneHitRound>(
-                              sv, list, hit_slots, cx, cy, cz, b, e, px, py, pz, accumulate)
-                        : visit_range<true, kLaneRefRound>(sv, b, e, px, py, pz, accumulate);
-                respond(cnt, sx, sy, sz, sp.restitution, px, py, pz, qx, qy, qz);
+                              sv, list, hit_slots, cx, cy, cz, b, e, px, py, pz, sum)
+                        : visit_range<true, kLaneRefRound>(sv, b, e, px, py, pz, sum);
+                respond(cnt, sum.x, sum.y, sum.z, sp.restitution, px, py, pz, qx, qy, qz);
             } else {
                 // the group's records, in lane order (LDS operations of a wavefront complete
                 // in order, so the other lanes' records are in place)
