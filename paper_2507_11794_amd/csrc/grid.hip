@@ -243,11 +243,19 @@ __device__ void finish_cell(int c, int lane, const Dims& g, const uint32_t* __re
     if (n <= 128) {
         const uint32_t v0 = lane < (int)n ? refs[b + lane] : 0xffffffffu;
         const uint32_t v1 = lane + 64 < (int)n ? refs[b + 64 + lane] : 0xffffffffu;
+        // (entries past n hold 0xffffffff, which is smaller than no entry: the broadcasts
+        // stop at the cell's count, which is the same for every lane)
         uint32_t r0 = 0, r1 = 0;
-        for (int k = 0; k < 64; ++k) {
-            const uint32_t w0 = __shfl(v0, k), w1 = __shfl(v1, k);
-            r0 += (w0 < v0) + (w1 < v0);
-            r1 += (w0 < v1) + (w1 < v1);
+        const int n0 = min((int)n, 64), n1 = (int)n - n0;
+        for (int k = 0; k < n0; ++k) {
+            const uint32_t w0 = __shfl(v0, k);
+            r0 += w0 < v0;
+            r1 += w0 < v1;
+        }
+        for (int k = 0; k < n1; ++k) {
+            const uint32_t w1 = __shfl(v1, k);
+            r0 += w1 < v0;
+            r1 += w1 < v1;
         }
         if (lane < (int)n) {
             refs[b + r0] = v0;
