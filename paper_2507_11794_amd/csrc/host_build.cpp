@@ -625,14 +625,18 @@ int rebuild_surface(SurfaceDevice* sd, const float* verts, DeviceArena& arena,
             (e = arena.alloc(&sd->ref_hi, cap)) || (e = arena.alloc(&sd->ref_q, cap)))
             return hip_fail(e, "hipMalloc grid");
         sd->cap_refs = cap;
+        // kRefPad entries after the last reference let the query loops load a round of
+        // references without a bounds test (the loaded values past a cell's end are never
+        // used, but a reference's triangle id may be followed): zeroed once here, every entry
+        // past a later build's last reference holds zero or an earlier build's reference, so
+        // always a valid triangle id
+        if ((e = hipMemsetAsync(sd->refs, 0, 4 * cap, stream)) ||
+            (e = hipMemsetAsync(sd->ref_lo, 0, sizeof(float4) * cap, stream)) ||
+            (e = hipMemsetAsync(sd->ref_hi, 0, sizeof(float4) * cap, stream)) ||
+            (e = hipMemsetAsync(sd->ref_q, 0, sizeof(uint4) * cap, stream)))
+            return hip_fail(e, "grid build");
     }
-    // kRefPad zero entries after the last reference let the query loops load a round of
-    // references without a bounds test (the loaded values past a cell's end are never used)
-    if ((e = hipMemsetAsync(sd->refs + total, 0, 4 * kRefPad, stream)) ||
-        (e = hipMemsetAsync(sd->ref_lo + total, 0, sizeof(float4) * kRefPad, stream)) ||
-        (e = hipMemsetAsync(sd->ref_hi + total, 0, sizeof(float4) * kRefPad, stream)) ||
-        (e = hipMemsetAsync(sd->ref_q + total, 0, sizeof(uint4) * kRefPad, stream)) ||
-        (e = hipMemsetAsync(sd->counts, 0, 4 * C, stream)) ||
+    if ((e = hipMemsetAsync(sd->counts, 0, 4 * C, stream)) ||
         (e = launch_grid_count(T, sd->box_lo, sd->box_hi, sv.org, sv.inv_cell, sv.dim, sd->counts,
                                stream)) ||
         (e = scan_exclusive_u32(sd->counts, sd->cell_start, C, sd->tmp, stream)) ||
